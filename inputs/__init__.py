@@ -1,0 +1,266 @@
+"""Seeded synthetic inputs shared by the oracle and the HIP path.
+
+This module holds problem descriptions (grid, time axis, line geometry),
+seeded earth models (a Gaussian low-velocity lens and a layered model with
+sinusoidal interfaces and a smooth random perturbation), the Ricker wavelet
+and seeded random vectors.  It contains none of the method's arithmetic: no
+stencil, no absorbing layer, no injection or sampling rule, no solver step.
+
+Units are SI throughout: metres, seconds, pascals, kg/m^3.
+
+The workloads stand in for the paper's synthetic crosswell examples
+(Numerical Examples section: smooth models, 20 m cells, sub-12 Hz wavelets);
+the paper uses no public dataset.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+RHO_WATERLIKE = 1000.0  # 1 g/cm^3, the paper's constant density
+BASE_SEED = 20220331
+
+
+@dataclass(frozen=True)
+class Problem:
+    """Geometry and discretisation of one surface-source subproblem family.
+
+    The physical grid has ``nz`` rows (depth, slow axis) and ``nx`` columns
+    (lateral, fast axis) with spacing ``h`` in both directions; node (i, j)
+    sits at depth ``i*h`` and lateral position ``j*h``.  An absorbing layer of
+    ``npml`` cells is added outside this grid on all four sides.
+
+    The extended source lives on the horizontal line at depth ``z_src``,
+    sampled at ``ns`` positions ``x_src0 + k*h``; receivers sit at depth
+    ``z_rec`` at ``nr`` positions ``x_rec0 + k*h``.  ``slab_dz`` is the signed
+    datum offset (in cells, positive = deeper) of the thin slab that carries
+    the preconditioner.  ``xs`` lists the lateral position of the physical
+    point source of each shot (one shot = one subproblem sharing the model).
+    """
+
+    nz: int
+    nx: int
+    h: float
+    dt: float
+    nt: int
+    order: int = 8
+    npml: int = 20
+    pml_R: float = 1e-3
+    z_src: float = 0.0
+    x_src0: float = 0.0
+    ns: int = 0
+    z_rec: float = 0.0
+    x_rec0: float = 0.0
+    nr: int = 0
+    slab_dz: int = 5
+    xs: tuple = (0.0,)
+
+    @property
+    def nshots(self) -> int:
+        return len(self.xs)
+
+    def replace(self, **kw) -> "Problem":
+        return dataclasses.replace(self, **kw)
+
+
+@dataclass
+class Workload:
+    """A problem plus its model, wavelet and solver settings."""
+
+    name: str
+    prob: Problem
+    kappa: np.ndarray  # [nz][nx] bulk modulus, Pa
+    rho: float
+    freq: float  # Ricker peak frequency, Hz
+    K: int  # fixed PCG iteration count
+    alpha_rel: float
+    dtype: str
+    extras: dict = field(default_factory=dict)
+
+
+# ----------------------------------------------------------------------------
+# wavelet
+
+def ricker(t: np.ndarray, f: float, t0: float | None = None) -> np.ndarray:
+    """Ricker wavelet (1 - 2 pi^2 f^2 tau^2) exp(-pi^2 f^2 tau^2), tau = t - t0,
+    with the default delay t0 = 1.5/f."""
+    if t0 is None:
+        t0 = 1.5 / f
+    a = (math.pi * f * (np.asarray(t, dtype=np.float64) - t0)) ** 2
+    return (1.0 - 2.0 * a) * np.exp(-a)
+
+
+def ricker_deriv(t: np.ndarray, f: float, t0: float | None = None) -> np.ndarray:
+    """Time derivative of :func:`ricker`."""
+    if t0 is None:
+        t0 = 1.5 / f
+    tau = np.asarray(t, dtype=np.float64) - t0
+    b = (math.pi * f) ** 2
+    return (-6.0 * b * tau + 4.0 * b * b * tau ** 3) * np.exp(-b * tau * tau)
+
+
+# ----------------------------------------------------------------------------
+# models
+
+def lens_velocity(nz: int, nx: int, h: float, rng: np.random.Generator,
+                  c0: float = 2500.0, dip: float = 500.0, radius: float = 300.0,
+                  xc_range=(600.0, 3400.0), zc_range=(600.0, 1400.0)) -> np.ndarray:
+    """Background c0 with a Gaussian low-velocity lens of depth ``dip`` and
+    radius ``radius``; the centre is drawn uniformly from the given ranges."""
+    xc = rng.uniform(*xc_range)
+    zc = rng.uniform(*zc_range)
+    z = np.arange(nz)[:, None] * h
+    x = np.arange(nx)[None, :] * h
+    r2 = (x - xc) ** 2 + (z - zc) ** 2
+    return c0 - dip * np.exp(-r2 / radius ** 2)
+
+
+def layered_velocity(nz: int, nx: int, h: float, rng: np.random.Generator,
+                     nlayers: int = 12, vmin: float = 1500.0, vmax: float = 4500.0,
+                     zrange=(100.0, 3900.0), min_gap: float = 100.0,
+                     amp: float = 20.0, pert: float = 0.03,
+                     smooth: float = 50.0) -> np.ndarray:
+    """Layered model: ``nlayers - 1`` interfaces with depths drawn uniformly
+    (sorted, redrawn until separated by ``min_gap``), each bent by a sinusoid
+    of amplitude ``amp`` and random wavelength/phase; layer k has velocity
+    vmin + (vmax - vmin) k / (nlayers - 1).  The result is multiplied by
+    1 + pert * delta with delta a Gaussian-smoothed white field (std 1,
+    clipped to +-3)."""
+    from scipy.ndimage import gaussian_filter
+
+    nif = nlayers - 1
+    for _ in range(1000):
+        depths = np.sort(rng.uniform(zrange[0], zrange[1], size=nif))
+        if np.all(np.diff(depths) >= min_gap):
+            break
+    lam = rng.uniform(500.0, 4000.0, size=nif)
+    phi = rng.uniform(0.0, 2.0 * math.pi, size=nif)
+    z = np.arange(nz)[:, None] * h
+    x = np.arange(nx)[None, :] * h
+    layer = np.zeros((nz, nx), dtype=np.int64)
+    for k in range(nif):
+        zk = depths[k] + amp * np.sin(2.0 * math.pi * x / lam[k] + phi[k])
+        layer += (z >= zk).astype(np.int64)
+    vel = vmin + (vmax - vmin) * layer / (nlayers - 1)
+    white = rng.standard_normal((nz, nx))
+    sm = gaussian_filter(white, sigma=smooth / h, mode="reflect")
+    sm = (sm - sm.mean()) / sm.std()
+    sm = np.clip(sm, -3.0, 3.0)
+    return vel * (1.0 + pert * sm)
+
+
+def kappa_from_velocity(vel: np.ndarray, rho: float = RHO_WATERLIKE) -> np.ndarray:
+    """Bulk modulus of a constant-density model with the given velocity."""
+    return rho * np.asarray(vel, dtype=np.float64) ** 2
+
+
+def homogeneous_kappa(nz: int, nx: int, c: float = 2000.0,
+                      rho: float = RHO_WATERLIKE) -> np.ndarray:
+    return np.full((nz, nx), rho * c * c)
+
+
+# ----------------------------------------------------------------------------
+# workloads (the five benchmark configurations)
+
+def _shot_positions(nshots: int, width: float) -> tuple:
+    return tuple((k + 0.5) * width / nshots for k in range(nshots))
+
+
+def workload(c: int, **over) -> Workload:
+    """Configuration ``c`` in 1..4 (5 is a request generator, see
+    :func:`serving_requests`).  Keyword overrides replace Problem fields."""
+    rng = np.random.default_rng(BASE_SEED + c)
+    if c == 1:
+        nz, nx, h = 101, 201, 20.0
+        vel = lens_velocity(nz, nx, h, rng)
+        prob = Problem(nz=nz, nx=nx, h=h, dt=2e-3, nt=1000, order=4, npml=20,
+                       z_src=100.0, x_src0=0.0, ns=nx, z_rec=40.0, x_rec0=0.0,
+                       nr=nx, slab_dz=5, xs=(2000.0,))
+        wl = Workload("c1", prob, kappa_from_velocity(vel), RHO_WATERLIKE,
+                      8.0, 10, 1e-3, "f64")
+    elif c in (2, 4):
+        nz, nx, h = 801, 1601, 5.0
+        rng = np.random.default_rng(BASE_SEED + 2)
+        vel = layered_velocity(nz, nx, h, rng)
+        prob = Problem(nz=nz, nx=nx, h=h, dt=0.5e-3, nt=4000, order=8, npml=20,
+                       z_src=20.0, x_src0=0.0, ns=nx, z_rec=10.0, x_rec0=0.0,
+                       nr=nx, slab_dz=5, xs=(4000.0,))
+        wl = Workload("c2" if c == 2 else "c4", prob, kappa_from_velocity(vel),
+                      RHO_WATERLIKE, 15.0, 30, 1e-3,
+                      "f32" if c == 2 else "f16")
+    elif c == 3:
+        nz, nx, h = 401, 801, 10.0
+        vel = layered_velocity(nz, nx, h, rng)
+        prob = Problem(nz=nz, nx=nx, h=h, dt=1e-3, nt=2000, order=8, npml=20,
+                       z_src=20.0, x_src0=0.0, ns=nx, z_rec=10.0, x_rec0=0.0,
+                       nr=nx, slab_dz=5, xs=_shot_positions(64, (nx - 1) * h))
+        wl = Workload("c3", prob, kappa_from_velocity(vel), RHO_WATERLIKE,
+                      15.0, 20, 1e-3, "f32")
+    else:
+        raise ValueError(f"unknown configuration {c}")
+    if over:
+        wl.prob = wl.prob.replace(**over)
+    return wl
+
+
+SERVING_GRIDS = ((201, 401, 20.0), (401, 801, 10.0), (801, 1601, 5.0))
+
+
+def serving_request(req_id: int, rng: np.random.Generator, max_shots: int = 64,
+                    nt_range=(500, 4000)) -> Workload:
+    """One request of the serving stream: a grid drawn from SERVING_GRIDS, a
+    record length from nt_range in steps of 100, 1..max_shots shots spaced as
+    in the batched configuration, and a layered model seeded by the request
+    id.  dt = h/10 ms per metre of cell size (2, 1, 0.5 ms)."""
+    gi = int(rng.integers(0, len(SERVING_GRIDS)))
+    nz, nx, h = SERVING_GRIDS[gi]
+    nt = int(rng.integers(nt_range[0] // 100, nt_range[1] // 100 + 1)) * 100
+    nshots = int(rng.integers(1, max_shots + 1))
+    mrng = np.random.default_rng(BASE_SEED + 1000 + req_id)
+    vel = layered_velocity(nz, nx, h, mrng)
+    dt = h / 10.0 * 1e-3
+    prob = Problem(nz=nz, nx=nx, h=h, dt=dt, nt=nt, order=8, npml=20,
+                   z_src=4 * h, x_src0=0.0, ns=nx, z_rec=2 * h, x_rec0=0.0,
+                   nr=nx, slab_dz=5, xs=_shot_positions(nshots, (nx - 1) * h))
+    return Workload(f"req{req_id}", prob, kappa_from_velocity(vel),
+                    RHO_WATERLIKE, 15.0 * 5.0 / h if h > 5.0 else 15.0, 20,
+                    1e-3, "f16")
+
+
+def serving_requests(n: int = 200, seed: int = BASE_SEED + 5, **kw):
+    """Seeded request stream: (arrival offset in units of the mean gap, Workload)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0.0
+    for i in range(n):
+        t += rng.exponential(1.0)
+        out.append((t, serving_request(i, rng, **kw)))
+    return out
+
+
+# ----------------------------------------------------------------------------
+# source gathers and random vectors
+
+def spike_gather(prob: Problem, wavelet: np.ndarray, shot: int = 0) -> np.ndarray:
+    """Source gather [nt][ns] that is zero except for the trace nearest the
+    shot's physical position, which carries ``wavelet`` divided by the cell
+    size (a point source on the source line expressed as a line density)."""
+    g = np.zeros((prob.nt, prob.ns))
+    k = int(round((prob.xs[shot] - prob.x_src0) / prob.h))
+    k = min(max(k, 0), prob.ns - 1)
+    g[:, k] = wavelet / prob.h
+    return g
+
+
+def source_wavelet(prob: Problem, freq: float) -> np.ndarray:
+    """Ricker samples at the half-step times (n + 1/2) dt, the times at
+    which the source term enters the leapfrog update n -> n+1."""
+    t = (np.arange(prob.nt) + 0.5) * prob.dt
+    return ricker(t, freq)
+
+
+def random_traces(shape, seed: int) -> np.ndarray:
+    return np.random.default_rng(seed).standard_normal(shape)

@@ -1,0 +1,29 @@
+"""Plain FP64 CPU oracle for the surface-source subproblem.
+
+TEST INFRASTRUCTURE: only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this package.  The product path (the HIP library
+and its Python binding) never calls it, and it shares no code with that path:
+the only common module is ``inputs`` (seeded problem descriptions, models and
+wavelets), which holds none of the method's arithmetic.
+
+Modules, each citing the passage of W. W. Symes, "Efficient Computation of
+Extended Surface Sources" (arXiv 2203.16573) that it follows:
+
+* ``fd``     staggered first-derivative operators (Numerical Examples:
+             staggered scheme of order 2 in time, 2k in space);
+* ``grid``   padded grid, PML profiles, line sampling (same passage);
+* ``prop``   forward time stepping and its exact transpose (Operators
+             section; Appendix A);
+* ``ops``    F, F^T, the penalty A, the thin-slab preconditioner, the normal
+             operator and Algorithm 1 (Introduction; Accelerated Iterative
+             Inversion; Computing and Symmetrizing Lambda);
+* ``greens`` the closed-form 2D point-source response used as a pin.
+
+Every function is pinned by the CPU tests against facts that do not come
+from this code: the dot-product adjoint test, brute-force dense transposes,
+discrete energy conservation, reciprocity, the closed-form Green's function at
+second-order convergence, the 1D plane-wave amplitudes, polynomial exactness
+of the stencils, dense normal-equation solves and Krylov-subspace optimality.
+"""
+from . import fd, grid, prop, ops, greens  # noqa: F401
+from .ops import Model, pcg, pcg_solve, precond, penalty, dscale, normal  # noqa: F401

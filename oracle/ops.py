@@ -1,0 +1,211 @@
+"""The surface-source subproblem operators and PCG (oracle).
+
+TEST INFRASTRUCTURE ONLY -- see the package header.
+
+* F   = S^+_{z_s,z_r}: pressure source on the line z = z_s to pressure trace
+        on z = z_r (Operators section, definition of S as the (0,0) block of
+        the vector modelling operator).
+* F^T: its exact discrete transpose (adjoint-state identity of the Operators
+        section; Appendix A).
+* A:   multiplication by the lateral distance |x - x_s| to the physical
+        source (Introduction, the penalty operator).
+* M^-1 = D W^-1 D with D = (I + a^2 A^T A)^(-1/2) (Accelerated Iterative
+        Inversion, the preconditioner) and W^-1 the symmetrised
+        pressure-to-source operator computed on a thin slab by one forward
+        and one adjoint simulation with the pressure/velocity exchange in
+        between (Computing and Symmetrizing Lambda, the W_m^-1 formula and
+        the thin-slab datum of the lamnear approximation).
+* N   = F^T F + alpha^2 A^T A, the Euclidean normal operator of the penalised
+        least-squares problem (Operators section, the esisp problem).
+* pcg: Algorithm 1 (standard preconditioned CG, h_0 = 0).
+
+Readings where the paper is silent or inconsistent are listed with the
+design notes; the ones that change results here are: the Euclidean normal
+equations, alpha = alpha_rel ||F^T d|| / ||d|| with alpha_rel itself inside
+D, and the slab scale s = 4 sign(dz) (the paper's -4 on its own datum side).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import fd
+from .grid import Grid
+from .prop import adjoint, forward
+
+
+class Model:
+    """The full-grid and thin-slab discretisations of one problem."""
+
+    def __init__(self, prob, kappa, rho):
+        self.prob = prob
+        self.rho = float(rho)
+        kappa = np.asarray(kappa, dtype=np.float64)
+        if kappa.shape != (prob.nz, prob.nx):
+            raise ValueError("kappa must be [nz][nx]")
+        self.kappa = kappa
+        self.full = Grid(kappa, rho, prob.h, prob.dt, prob.npml, prob.pml_R,
+                         prob.order)
+        g = self.full
+        self.h_line = g.p_line(prob.z_src, prob.x_src0, prob.ns)
+        self.r_line = g.p_line(prob.z_rec, prob.x_rec0, prob.nr)
+        self._slab = None
+
+    # -- thin slab -----------------------------------------------------------
+    def slab(self):
+        """Slab grid: physical rows from min(z_s, z_s + dz) - k cells to
+        max(...) + k cells (k = order/2), full width, model rows copied from
+        the full model (clamped at its top and bottom), plus the absorbing
+        layer.  Returns (grid, source line on v_z nodes at z_s, datum line on
+        p nodes, datum line on v_z nodes)."""
+        if self._slab is None:
+            prob = self.prob
+            k = prob.order // 2
+            dz = int(prob.slab_dz)
+            if dz == 0:
+                raise ValueError("slab datum offset must be nonzero")
+            i_s = int(math.floor(prob.z_src / prob.h + 1e-12))
+            i_lo = min(i_s, i_s + dz) - k
+            i_hi = max(i_s, i_s + dz) + k + (1 if prob.z_src / prob.h - i_s > 1e-12 else 0)
+            rows = np.clip(np.arange(i_lo, i_hi + 1), 0, prob.nz - 1)
+            kap = self.kappa[rows, :]
+            g = Grid(kap, self.rho, prob.h, prob.dt, prob.npml, prob.pml_R,
+                     prob.order)
+            zs = prob.z_src - i_lo * prob.h
+            zd = zs + dz * prob.h
+            f_line = g.vz_line(zs, prob.x_src0, prob.ns)
+            d_p = g.p_line(zd, prob.x_src0, prob.ns)
+            d_v = g.vz_line(zd, prob.x_src0, prob.ns)
+            self._slab = (g, f_line, d_p, d_v)
+        return self._slab
+
+    # -- F and F^T -----------------------------------------------------------
+    def fwd(self, h):
+        """d = F h, h [nt][ns] -> d [nt][nr]."""
+        P, _ = forward(self.full, self.prob.nt, h_src=(self.h_line, h),
+                       rec_p=self.r_line)
+        return P
+
+    def adj(self, r):
+        """g = F^T r, r [nt][nr] -> g [nt][ns]."""
+        hb, _ = adjoint(self.full, self.prob.nt, h_line=self.h_line,
+                        rec_p=(self.r_line, r))
+        return hb
+
+    # -- thin-slab vector operator X = Pi-projected S on the slab -------------
+    def slab_fwd(self, f):
+        """X f = (P, V): normal-load source f on z_s, pressure and normal
+        velocity recorded on the datum."""
+        g, f_line, d_p, d_v = self.slab()
+        return forward(g, self.prob.nt, f_src=(f_line, f), rec_p=d_p, rec_v=d_v)
+
+    def slab_adj(self, a, b):
+        """X^T (a, b): a enters the pressure-trace slot, b the v_z slot; the
+        result is read from the normal-load source slot."""
+        g, f_line, d_p, d_v = self.slab()
+        _, fb = adjoint(g, self.prob.nt, f_line=f_line, rec_p=(d_p, a),
+                        rec_v=(d_v, b))
+        return fb
+
+    def slab_scale(self) -> float:
+        return 4.0 * math.copysign(1.0, self.prob.slab_dz)
+
+    def winv(self, g):
+        """Symmetrised thin-slab pressure-to-source operator:
+        s X^T J X g with J (P, V) = (V, P)."""
+        P, V = self.slab_fwd(g)
+        return self.slab_scale() * self.slab_adj(V, P)
+
+
+# ----------------------------------------------------------------------------
+# penalty and diagonal scalings
+
+def lateral_distance(prob, shot: int = 0) -> np.ndarray:
+    """|x_k - x_s| for the source-line samples x_k = x_src0 + k h."""
+    x = prob.x_src0 + prob.h * np.arange(prob.ns)
+    return np.abs(x - prob.xs[shot])
+
+
+def penalty(prob, x, shot: int = 0):
+    """(A x)[n][k] = |x_k - x_s| x[n][k]."""
+    return lateral_distance(prob, shot)[None, :] * x
+
+
+def dscale(prob, alpha_hat: float, shot: int = 0) -> np.ndarray:
+    """Diagonal of D = (1 + alpha_hat^2 |x_k - x_s|^2)^(-1/2)."""
+    a = lateral_distance(prob, shot)
+    return 1.0 / np.sqrt(1.0 + (alpha_hat * a) ** 2)
+
+
+def precond(model: Model, alpha_hat: float, r, shot: int = 0):
+    """M^-1 r = D W^-1 (D r)."""
+    d = dscale(model.prob, alpha_hat, shot)[None, :]
+    return d * model.winv(d * r)
+
+
+def normal(model: Model, alpha: float, p, shot: int = 0):
+    """N p = F^T F p + alpha^2 A^T A p; also returns F p."""
+    Fp = model.fwd(p)
+    Ap = penalty(model.prob, p, shot)
+    return model.adj(Fp) + alpha * alpha * penalty(model.prob, Ap, shot), Fp
+
+
+def dot(x, y) -> float:
+    return float(np.sum(np.asarray(x, dtype=np.float64) * np.asarray(y, dtype=np.float64)))
+
+
+def pcg(apply_N, apply_Minv, b, K: int, d_misfit=None):
+    """Algorithm 1 (standard PCG), fixed K iterations, h_0 = 0.
+
+    apply_N(p) -> (N p, F p or None); apply_Minv(r) -> M^-1 r.
+    Returns (h_K, history) where history[k] = (||r_k||, ||g_k||, <g_k, r_k>,
+    ||F h_k - d||) for k = 0..K; the misfit column is NaN unless d_misfit
+    (the data d) is given, in which case F h_k - d is updated alongside h
+    from the F p_k produced by apply_N."""
+    h = np.zeros_like(b)
+    r = b.copy()
+    g = apply_Minv(r)
+    p = g.copy()
+    q, Fp = apply_N(p)
+    gr = dot(g, r)
+    e = -np.asarray(d_misfit, dtype=np.float64) if d_misfit is not None else None
+    hist = [(math.sqrt(dot(r, r)), math.sqrt(dot(g, g)), gr,
+             math.sqrt(dot(e, e)) if e is not None else math.nan)]
+    for k in range(K):
+        a = gr / dot(p, q)
+        h = h + a * p
+        r = r - a * q
+        if e is not None:
+            e = e + a * Fp
+        g = apply_Minv(r)
+        gr_new = dot(g, r)
+        beta = gr_new / gr
+        p = g + beta * p
+        gr = gr_new
+        hist.append((math.sqrt(dot(r, r)), math.sqrt(dot(g, g)), gr,
+                     math.sqrt(dot(e, e)) if e is not None else math.nan))
+        if k < K - 1:
+            q, Fp = apply_N(p)
+    return h, np.array(hist)
+
+
+def pcg_solve(model: Model, d, alpha_rel: float, K: int, use_precond: bool = True,
+              shot: int = 0):
+    """The surface-source subproblem solve for one shot: b = F^T d,
+    alpha = alpha_rel ||b|| / ||d||, K iterations of Algorithm 1 on
+    N h = b with M^-1 = D W^-1 D (alpha_hat = alpha_rel) or M = I."""
+    b = model.adj(d)
+    alpha = alpha_rel * math.sqrt(dot(b, b)) / math.sqrt(dot(d, d))
+
+    def apply_N(p):
+        return normal(model, alpha, p, shot)
+
+    if use_precond:
+        def apply_Minv(r):
+            return precond(model, alpha_rel, r, shot)
+    else:
+        def apply_Minv(r):
+            return r.copy()
+    h, hist = pcg(apply_N, apply_Minv, b, K, d_misfit=d)
+    return h, hist, alpha

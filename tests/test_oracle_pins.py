@@ -1,0 +1,448 @@
+"""Pins of the FP64 oracle against facts that do not come from its own code.
+
+Each test names the passage of the paper (or the mathematical fact) it
+relies on.  Together they are meant to catch a plausible slip anywhere in
+the oracle: a dropped term or factor, a wrong sign, index or time level, a
+transposed operand.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+from oracle import fd, greens
+from oracle.grid import Grid
+from oracle.prop import adjoint, forward
+
+RHO = 1000.0
+
+
+def tiny_problem(order=4, nz=12, nx=16, L=4, nt=24, h=10.0, dt=1e-3,
+                 z_src=35.0, z_rec=80.0, ns=8, nr=10, slab_dz=3, xs=(52.0,)):
+    return inputs.Problem(nz=nz, nx=nx, h=h, dt=dt, nt=nt, order=order, npml=L,
+                          z_src=z_src, x_src0=2 * h, ns=ns, z_rec=z_rec,
+                          x_rec0=h, nr=nr, slab_dz=slab_dz, xs=xs)
+
+
+def tiny_kappa(prob, seed=0):
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(1800.0, 2200.0, size=(prob.nz, prob.nx))
+    return RHO * c * c
+
+
+def dense(apply, n_in, shape_in):
+    cols = []
+    for i in range(n_in):
+        e = np.zeros(n_in)
+        e[i] = 1.0
+        cols.append(np.asarray(apply(e.reshape(shape_in))).ravel())
+    return np.array(cols).T
+
+
+# ---------------------------------------------------------------------------
+# stencils (Numerical Examples: staggered scheme, order 2k in space)
+
+@pytest.mark.parametrize("order,expected", [
+    (2, (1.0,)),
+    (4, (9 / 8, -1 / 24)),
+    (8, (1225 / 1024, -245 / 3072, 49 / 5120, -5 / 7168)),
+])
+def test_stencil_matches_textbook_values(order, expected):
+    # the classical staggered Taylor coefficients (Fornberg 1988)
+    c = fd.stencil(order)
+    assert np.allclose(c, expected, rtol=1e-14, atol=0)
+    assert abs(sum((2 * m - 1) * cm for m, cm in enumerate(c, 1)) - 1) < 1e-14
+
+
+@pytest.mark.parametrize("order", [4, 8])
+def test_stencil_polynomial_exactness(order):
+    # D+ of x^q sampled on nodes equals q x^(q-1) at half nodes for
+    # q <= order (interior points); D- likewise from half nodes to nodes.
+    c = fd.stencil(order)
+    k = order // 2
+    x = np.arange(40, dtype=np.float64) * 0.1 - 2.0
+    for q in range(0, order + 1):
+        p = x ** q
+        dp = fd.dplus(p, c, axis=0) / 0.1
+        xh = x + 0.05
+        exact = q * xh ** (q - 1) if q > 0 else 0 * xh
+        assert np.allclose(dp[k:-k], exact[k:-k], rtol=1e-9, atol=1e-9), q
+        v = xh ** q
+        dv = fd.dminus(v, c, axis=0) / 0.1
+        exact = q * x ** (q - 1) if q > 0 else 0 * x
+        assert np.allclose(dv[k:-k], exact[k:-k], rtol=1e-9, atol=1e-9), q
+
+
+@pytest.mark.parametrize("order", [2, 4, 8])
+def test_difference_operators_transpose(order):
+    # D- = -(D+)^T exactly with zero extension, and the *_T functions are
+    # the dense transposes.
+    c = fd.stencil(order)
+    n = 13
+    Dp = dense(lambda e: fd.dplus(e, c, 0), n, (n,))
+    Dm = dense(lambda e: fd.dminus(e, c, 0), n, (n,))
+    DpT = dense(lambda e: fd.dplus_T(e, c, 0), n, (n,))
+    DmT = dense(lambda e: fd.dminus_T(e, c, 0), n, (n,))
+    assert np.array_equal(Dm, -Dp.T)
+    assert np.array_equal(DpT, Dp.T)
+    assert np.array_equal(DmT, Dm.T)
+    # along axis 1 of a 2D array as well
+    u = np.random.default_rng(1).standard_normal((5, 11))
+    w = np.random.default_rng(2).standard_normal((5, 11))
+    assert abs(np.sum(fd.dplus(u, c, 1) * w) + np.sum(u * fd.dminus(w, c, 1))) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# sampling and injection (linear interpolation and its adjoint)
+
+@pytest.mark.parametrize("z", [30.0, 35.0, 47.5, 80.0])
+def test_line_interpolation_exact_on_linear_fields(z):
+    prob = tiny_problem()
+    g = Grid(tiny_kappa(prob), RHO, prob.h, prob.dt, prob.npml, prob.pml_R, 4)
+    I = np.arange(g.NZ)[:, None] * np.ones((1, g.NX))
+    # p node row i is at depth (i - L) h, v_z row i at (i - L + 1/2) h
+    fp = 3.0 + 0.7 * (I - g.L) * g.h
+    fv = 3.0 + 0.7 * (I - g.L + 0.5) * g.h
+    lp = g.p_line(z, 20.0, 5)
+    lv = g.vz_line(z, 20.0, 5)
+    assert np.allclose(lp.gather(fp), 3.0 + 0.7 * z, rtol=1e-14)
+    assert np.allclose(lv.gather(fv), 3.0 + 0.7 * z, rtol=1e-14)
+    assert abs(sum(w for _, w in lp.rows) - 1) < 1e-15
+    # spread is the transpose of gather
+    a = np.random.default_rng(0).standard_normal(5)
+    F = np.random.default_rng(1).standard_normal((g.NZ, g.NX))
+    assert abs(np.sum(lp.spread(a, F.shape) * F) - np.sum(a * lp.gather(F))) < 1e-12
+
+
+def test_pml_profile_values():
+    prob = tiny_problem(L=6)
+    g = Grid(tiny_kappa(prob), RHO, prob.h, prob.dt, prob.npml, prob.pml_R, 4)
+    L, nx = g.L, g.nx
+    # no damping on physical nodes and on half nodes between them
+    assert np.all(g.ax_n[L:L + nx] == 1) and np.all(g.bx_n[L:L + nx] == 1)
+    assert np.all(g.ax_h[L:L + nx - 1] == 1)
+    # outermost node: sigma = sigma_max; a, b from the trapezoidal rule
+    q = 0.5 * g.sigma_max * prob.dt
+    assert abs(g.ax_n[0] - (1 - q) / (1 + q)) < 1e-15
+    assert abs(g.bx_n[0] - 1 / (1 + q)) < 1e-15
+    # half node at depth 1/2 cell into the layer: sigma_max (1/(2L))^2
+    q = 0.5 * g.sigma_max * (0.5 / L) ** 2 * prob.dt
+    assert abs(g.ax_h[L - 1] - (1 - q) / (1 + q)) < 1e-15
+    assert abs(g.ax_h[L + nx - 1] - (1 - q) / (1 + q)) < 1e-15
+    cmax = math.sqrt(tiny_kappa(prob).max() / RHO)
+    assert abs(g.sigma_max - 3 * cmax * math.log(1e3) / (2 * L * prob.h)) < 1e-9
+
+
+def test_pml_absorbs():
+    # A pulse started in the middle of the box: with the absorbing layer the
+    # energy left after the wave has crossed the layer is a small fraction of
+    # the same run with a rigid box and no layer.
+    kap = inputs.homogeneous_kappa(40, 40, 2000.0)
+    nt = 600
+    w = inputs.ricker((np.arange(nt) + 0.5) * 1e-3, 25.0)
+    res = {}
+    for L in (0, 20):
+        g = Grid(kap, RHO, 10.0, 1e-3, L, 1e-3, 4)
+        line = g.p_line(200.0, 200.0, 1)
+        _, _, E = forward(g, nt, h_src=(line, (w / 10.0)[:, None]), energy=True)
+        res[L] = E
+    peak = max(res[0])
+    assert res[0][-1] > 0.5 * peak          # rigid box keeps its energy
+    assert res[20][-1] < 1e-4 * peak        # layer takes it out
+
+
+# ---------------------------------------------------------------------------
+# P1/P2: adjoint (Operators section, adjoint identity; Appendix A; the
+# paper's own pseudorandom dot-product test in Numerical Examples)
+
+@pytest.mark.parametrize("order", [4, 8])
+def test_dot_product_full_and_slab(order):
+    prob = tiny_problem(order=order, nz=20, nx=24, L=6, nt=60, ns=18, nr=20,
+                        z_src=55.0, z_rec=140.0, slab_dz=-4)
+    m = oracle.Model(prob, tiny_kappa(prob, 3), RHO)
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal((prob.nt, prob.ns))
+    y = rng.standard_normal((prob.nt, prob.nr))
+    Fx = m.fwd(x)
+    Fty = m.adj(y)
+    err = abs(np.sum(Fx * y) - np.sum(x * Fty)) / (np.linalg.norm(Fx) * np.linalg.norm(y))
+    assert err < 1e-14
+    P, V = m.slab_fwd(x)
+    a = rng.standard_normal(P.shape)
+    b = rng.standard_normal(V.shape)
+    Xt = m.slab_adj(a, b)
+    lhs = np.sum(P * a) + np.sum(V * b)
+    err = abs(lhs - np.sum(x * Xt)) / (math.hypot(np.linalg.norm(P), np.linalg.norm(V))
+                                       * math.hypot(np.linalg.norm(a), np.linalg.norm(b)))
+    assert err < 1e-14
+
+
+def test_dense_transpose_brute_force():
+    prob = tiny_problem()
+    m = oracle.Model(prob, tiny_kappa(prob, 5), RHO)
+    nin, nout = prob.nt * prob.ns, prob.nt * prob.nr
+    F = dense(m.fwd, nin, (prob.nt, prob.ns))
+    Ft = dense(m.adj, nout, (prob.nt, prob.nr))
+    scale = np.abs(F).max()
+    assert np.abs(F.T - Ft).max() <= 1e-14 * scale
+    # causality: output sample n depends only on inputs up to n
+    Fb = F.reshape(prob.nt, prob.nr, prob.nt, prob.ns)
+    for n in range(prob.nt):
+        assert np.all(Fb[n, :, n + 1:, :] == 0)
+
+
+# ---------------------------------------------------------------------------
+# P3: discrete energy (the acoustic energy of the Pressure-to-Source
+# section; Appendix A's energy argument), rigid box, no absorbing layer
+
+@pytest.mark.parametrize("order", [4, 8])
+def test_energy_conserved_without_absorption(order):
+    prob = tiny_problem(order=order, nz=30, nx=34, L=0, nt=200, ns=1, z_src=145.0,
+                        xs=(0.0,))
+    kap = tiny_kappa(prob, 11)
+    g = Grid(kap, RHO, prob.h, prob.dt, 0, prob.pml_R, order)
+    src = np.zeros((prob.nt, 1))
+    src[:20, 0] = np.random.default_rng(3).standard_normal(20)
+    line = g.p_line(145.0, 150.0, 1)
+    _, _, E = forward(g, prob.nt, h_src=(line, src), energy=True)
+    E = np.array(E[21:])
+    assert E.max() > 0
+    assert (E.max() - E.min()) / E.max() < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# P4: reciprocity (the time-reversal / transpose relations of the Operators
+# section applied to a point-to-point pressure response), rigid box
+
+def test_reciprocity_point_sources():
+    prob = tiny_problem(nz=26, nx=30, L=0, nt=120)
+    kap = tiny_kappa(prob, 13)
+    g = Grid(kap, RHO, prob.h, prob.dt, 0, prob.pml_R, 4)
+    a = g.p_line(60.0, 70.0, 1)
+    b = g.p_line(190.0, 220.0, 1)
+    w = np.random.default_rng(4).standard_normal((prob.nt, 1))
+    Pab, _ = forward(g, prob.nt, h_src=(a, w), rec_p=b)
+    Pba, _ = forward(g, prob.nt, h_src=(b, w), rec_p=a)
+    assert np.abs(Pab).max() > 0
+    assert np.abs(Pab - Pba).max() <= 1e-13 * np.abs(Pab).max()
+
+
+# ---------------------------------------------------------------------------
+# P5: closed-form 2D Green's function, second-order convergence at fixed
+# Courant number (scheme of order 2 in time)
+
+def _green_error(h, order=8, courant=0.4, c=2000.0, f=10.0, r=300.0, W=800.0):
+    dt = courant * h / c
+    n = int(round(2 * W / h)) + 1
+    kap = inputs.homogeneous_kappa(n, n, c)
+    g = Grid(kap, RHO, h, dt, 0, 1e-3, order)
+    tmax = 1.5 / f + r / c + 2.0 / f
+    nt = int(math.ceil(tmax / dt))
+    w = inputs.ricker((np.arange(nt) + 0.5) * dt, f)
+    src = g.p_line(W, W, 1)            # node at the centre
+    rec = g.p_line(W + r, W, 1)        # r below it
+    P, _ = forward(g, nt, h_src=(src, (w / h)[:, None]), rec_p=rec)
+    t = (np.arange(nt) + 1) * dt
+    ref = greens.point_source_pressure(r, t, c, RHO,
+                                       lambda s: np.where(s > 0, inputs.ricker_deriv(s, f), 0.0))
+    return np.abs(P[:, 0] - ref).max() / np.abs(ref).max()
+
+
+@pytest.mark.slow
+def test_greens_function_second_order():
+    e = [_green_error(h) for h in (20.0, 10.0, 5.0)]
+    orders = [math.log2(e[0] / e[1]), math.log2(e[1] / e[2])]
+    assert e[2] < 5e-3, e
+    for o in orders:
+        assert 1.8 <= o <= 2.2, (e, orders)
+
+
+def test_greens_function_amplitude_coarse():
+    # a single cheap resolution: right scale, sign and arrival time
+    assert _green_error(10.0) < 3e-2
+
+
+# ---------------------------------------------------------------------------
+# P6: 1D special case -- a laterally uniform line source makes plane waves:
+# p = (rho c / 2) h(t - tau) below a pressure source (jump of v_z equals h,
+# Pressure-to-Source section), and the thin-slab operator s X^T J X acts as
+# 2/(rho c) on laterally uniform input for either datum side.
+
+def _plane_setup(slab_dz=5, order=4):
+    c, h = 2000.0, 10.0
+    prob = inputs.Problem(nz=60, nx=201, h=h, dt=1e-3, nt=400, order=order,
+                          npml=20, z_src=200.0, x_src0=0.0, ns=201,
+                          z_rec=300.0, x_rec0=0.0, nr=201, slab_dz=slab_dz,
+                          xs=(1000.0,))
+    return prob, oracle.Model(prob, inputs.homogeneous_kappa(60, 201, c), RHO), c
+
+
+def test_plane_wave_amplitude_pressure_source():
+    prob, m, c = _plane_setup()
+    f = 10.0
+    w = inputs.ricker((np.arange(prob.nt) + 0.5) * prob.dt, f)
+    d = m.fwd(np.repeat(w[:, None], prob.ns, axis=1))
+    tau = (prob.z_rec - prob.z_src) / c
+    expect = 0.5 * RHO * c * inputs.ricker((np.arange(prob.nt) + 1) * prob.dt - tau, f)
+    got = d[:, prob.nr // 2]
+    assert np.abs(got - expect).max() < 1e-2 * np.abs(expect).max()
+
+
+def _slab_plane_error(h, dz, order=4, f=10.0, c=2000.0):
+    nz, nx = int(600 / h), int(2000 / h) + 1
+    dt = 0.2 * h / c
+    nt = int(0.4 / dt)
+    prob = inputs.Problem(nz=nz, nx=nx, h=h, dt=dt, nt=nt, order=order, npml=20,
+                          z_src=200.0, x_src0=0.0, ns=nx, z_rec=300.0, x_rec0=0.0,
+                          nr=nx, slab_dz=dz, xs=(1000.0,))
+    m = oracle.Model(prob, inputs.homogeneous_kappa(nz, nx, c), RHO)
+    w = inputs.ricker((np.arange(nt) + 0.5) * dt, f)
+    out = m.winv(np.repeat(w[:, None], nx, axis=1))[:, nx // 2]
+    expect = 2.0 / (RHO * c) * w
+    return np.abs(out - expect).max() / np.abs(expect).max()
+
+
+@pytest.mark.parametrize("dz", [5, -5])
+def test_plane_wave_slab_operator_scale(dz):
+    # The half-row injection of the normal load and the interpolated v_z
+    # sampling each average a plane wave over one cell, so the discrete
+    # operator approaches 2/(rho c) at second order in h (about 5% low at
+    # 20 points per wavelength, 1.4% at 40).  Both datum sides give the
+    # same positive scale with s = 4 sign(dz).
+    e10 = _slab_plane_error(10.0, dz)
+    e5 = _slab_plane_error(5.0, dz)
+    assert e5 < 0.02
+    assert math.log2(e10 / e5) > 1.7
+
+
+# ---------------------------------------------------------------------------
+# P7: symmetry of the preconditioner by construction (the W_m^-1 formula of
+# Computing and Symmetrizing Lambda); spectrum reported, not asserted
+
+def test_preconditioner_symmetric():
+    prob = tiny_problem(nz=14, nx=20, L=5, nt=30, ns=16, slab_dz=3, z_src=50.0)
+    m = oracle.Model(prob, tiny_kappa(prob, 17), RHO)
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal((prob.nt, prob.ns))
+    y = rng.standard_normal((prob.nt, prob.ns))
+    Wx, Wy = m.winv(x), m.winv(y)
+    err = abs(np.sum(x * Wy) - np.sum(Wx * y)) / (np.linalg.norm(Wx) * np.linalg.norm(y))
+    assert err < 1e-13
+    Mx = oracle.precond(m, 1e-3, x)
+    My = oracle.precond(m, 1e-3, y)
+    assert abs(np.sum(x * My) - np.sum(Mx * y)) <= 1e-13 * np.linalg.norm(Mx) * np.linalg.norm(y)
+
+
+# ---------------------------------------------------------------------------
+# P8/P9: Algorithm 1 against dense linear algebra
+
+def _dense_system(alpha_scale=0.05):
+    prob = tiny_problem(nt=20, ns=8, nr=10, xs=(47.0,))  # x_s between nodes
+    m = oracle.Model(prob, tiny_kappa(prob, 21), RHO)
+    n = prob.nt * prob.ns
+    F = dense(m.fwd, n, (prob.nt, prob.ns))
+    A = np.tile(oracle.ops.lateral_distance(prob), prob.nt)
+    smax = np.linalg.norm(F, 2)
+    alpha = alpha_scale * smax / A.max()
+    N = F.T @ F + alpha ** 2 * np.diag(A * A)
+    d = np.random.default_rng(5).standard_normal(prob.nt * prob.nr)
+    b = F.T @ d
+    return prob, m, F, N, b, alpha
+
+
+def test_pcg_converges_to_dense_solution():
+    prob, m, F, N, b, alpha = _dense_system(alpha_scale=0.3)
+    assert np.abs(N - N.T).max() <= 1e-13 * np.abs(N).max()
+    Lc = np.linalg.cholesky(N)
+    hstar = np.linalg.solve(Lc.T, np.linalg.solve(Lc, b))
+    shp = (prob.nt, prob.ns)
+
+    def apply_N(p):
+        return (N @ p.ravel()).reshape(shp), None
+
+    h, hist = oracle.pcg(apply_N, lambda r: r.copy(), b.reshape(shp), 400)
+    assert np.linalg.norm(h.ravel() - hstar) <= 1e-9 * np.linalg.norm(hstar)
+    # and through the operators themselves (not the dense matrix)
+    hop, _ = oracle.pcg(lambda p: oracle.normal(m, alpha, p), lambda r: r.copy(),
+                        b.reshape(shp), 400)
+    assert np.linalg.norm(hop.ravel() - hstar) <= 1e-9 * np.linalg.norm(hstar)
+
+
+def _krylov_minimiser(N, Minv, b, k):
+    # argmin ||h - h*||_N over K_k(Minv N, Minv b) = Galerkin solution on the
+    # span (Golub & Van Loan, Matrix Computations, CG as a projection
+    # method).  The span is built by Arnoldi with two Gram-Schmidt passes,
+    # which keeps the basis well conditioned when Minv is nearly singular.
+    q = Minv @ b
+    Q = [q / np.linalg.norm(q)]
+    for _ in range(k - 1):
+        w = Minv @ (N @ Q[-1])
+        for _ in range(2):
+            for u in Q:
+                w = w - (u @ w) * u
+        Q.append(w / np.linalg.norm(w))
+    Q = np.array(Q).T
+    y = np.linalg.solve(Q.T @ N @ Q, Q.T @ b)
+    return Q @ y
+
+
+def test_pcg_iterates_are_krylov_minimisers():
+    prob, m, F, N, b, alpha = _dense_system(alpha_scale=0.3)
+    shp = (prob.nt, prob.ns)
+    n = prob.nt * prob.ns
+    Minv = dense(lambda r: oracle.precond(m, 1e-3, r), n, shp)
+    assert np.abs(Minv - Minv.T).max() <= 1e-12 * np.abs(Minv).max()
+    ev = np.linalg.eigvalsh(0.5 * (Minv + Minv.T))
+    print(f"slab M^-1 spectrum: min {ev.min():.3e} max {ev.max():.3e} "
+          f"negative fraction {np.mean(ev < 0):.3f}")
+
+    def apply_N(p):
+        return (N @ p.ravel()).reshape(shp), None
+
+    # (beyond k ~ 6 this nearly singular, indefinite M^-1 amplifies rounding
+    # by ~50x per iteration, so the comparison stops at k = 5)
+    for scale in (1.0, -1.0, 10.0):
+        for k in (1, 2, 3, 5):
+            hk, _ = oracle.pcg(apply_N, lambda r: scale * (Minv @ r.ravel()).reshape(shp),
+                               b.reshape(shp), k)
+            ref = _krylov_minimiser(N, Minv, b, k)
+            assert np.linalg.norm(hk.ravel() - ref) <= 1e-9 * np.linalg.norm(ref), (scale, k)
+    # plain CG is PCG with M = I
+    for k in (1, 3, 5):
+        hk, _ = oracle.pcg(apply_N, lambda r: r.copy(), b.reshape(shp), k)
+        ref = _krylov_minimiser(N, np.eye(n), b, k)
+        assert np.linalg.norm(hk.ravel() - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+def test_pcg_solve_misfit_history():
+    # the misfit column tracked by the recurrence e_{k+1} = e_k + a_k F p_k
+    # equals ||F h_k - d|| recomputed from scratch
+    prob = tiny_problem(nt=20, xs=(47.0,))
+    m = oracle.Model(prob, tiny_kappa(prob, 23), RHO)
+    d = np.random.default_rng(6).standard_normal((prob.nt, prob.nr))
+    for K in (1, 3):
+        h, hist, alpha = oracle.pcg_solve(m, d, 1e-3, K)
+        assert abs(hist[-1, 3] - np.linalg.norm(m.fwd(h) - d)) <= 1e-12 * np.linalg.norm(d)
+        b = m.adj(d)
+        assert abs(alpha - 1e-3 * np.linalg.norm(b) / np.linalg.norm(d)) < 1e-18
+        assert abs(hist[0, 0] - np.linalg.norm(b)) <= 1e-12 * np.linalg.norm(b)
+
+
+# ---------------------------------------------------------------------------
+# P10: penalty and diagonal scaling (Introduction, the penalty operator;
+# Accelerated Iterative Inversion, the preconditioner's outer factors)
+
+def test_penalty_and_dscale_closed_form():
+    prob = tiny_problem(xs=(47.0,))
+    x = np.random.default_rng(8).standard_normal((prob.nt, prob.ns))
+    Ax = oracle.penalty(prob, x)
+    D = oracle.dscale(prob, 0.01)
+    for n in range(prob.nt):
+        for k in range(prob.ns):
+            xk = prob.x_src0 + k * prob.h
+            assert Ax[n, k] == abs(xk - 47.0) * x[n, k]
+    for k in range(prob.ns):
+        xk = prob.x_src0 + k * prob.h
+        assert abs(D[k] - (1 + (0.01 * (xk - 47.0)) ** 2) ** -0.5) < 1e-15
