@@ -1,0 +1,174 @@
+"""Benchmark: preconditioned-CG surface-source solves per second on one GPU.
+
+Default workload (the production single-subproblem configuration): 801 x 1601
+grid at 5 m, seeded layered model, 2-8 staggered scheme, 20-cell PML, dt
+0.5 ms, 4000 steps, source line at 20 m, 1601 receivers at 10 m, 30
+preconditioned CG iterations, FP32 wavefields and vectors, FP64 Krylov
+scalars.  One step = one complete solve (r_0 = F^T d, 30 x (N p, M^-1 r),
+with all dots and recurrences) for the given data.  Data: d = F h_true with
+h_true a Ricker point source at x_s on the source line, computed on the
+device before timing (synthetic input preparation).
+
+Prints one JSON line.  Also reports the dominant kernel's throughput
+against the HBM roofline and the FP64 oracle's CPU rate on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c4bf"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=12,
+                    help="time steps of the oracle's bounded CPU sample")
+    ap.add_argument("--graphs", type=int, default=1)
+    return ap.parse_args()
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import inputs
+    import paper_2203_16573_amd as ssx
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    torch.cuda.set_device(0)
+
+    cnum = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "c4bf": 4}[args.config]
+    wl = inputs.workload(cnum)
+    prob = wl.prob
+    fd = {"c1": "f64", "c2": "f32", "c3": "f32", "c4": "f16", "c4bf": "bf16"}[args.config]
+    vdt = torch.float64 if fd == "f64" else torch.float32
+
+    ctx = ssx.Context(prob, wl.kappa, wl.rho, field_dtype=fd)
+    ctx.set_graphs(bool(args.graphs))
+    wav = inputs.source_wavelet(prob, wl.freq)
+    htrue = np.stack([inputs.spike_gather(prob, wav, s) for s in range(prob.nshots)])
+    d = ctx.fwd(torch.tensor(htrue, dtype=vdt, device="cuda"), ctx.empty_r())
+    h = ctx.empty_s()
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        ctx.pcg_solve(d, wl.alpha_rel, wl.K, h=h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, hist, iters, st = ctx.pcg_solve(d, wl.alpha_rel, wl.K, h=h)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    solves = args.steps * prob.nshots
+    value = solves / elapsed
+
+    # dominant kernel: the full-grid time step.  One forward propagation is
+    # nt launches of it (plus one sampling launch); time it with events on
+    # the context's stream.
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    dtmp = ctx.empty_r()
+    nrep = 3
+    e0.record(stream)
+    for _ in range(nrep):
+        ctx.fwd(h, dtmp)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    step_ms = e0.elapsed_time(e1) / (nrep * prob.nt)
+    cells = ctx.cells_per_launch()
+    fsz = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[fd]
+    csz = 8 if fd == "f64" else 4
+    # algorithmic bytes per cell-update: read p, v_x, v_z and kappa once,
+    # write p, v_x, v_z once
+    b_alg = 6 * fsz + csz
+    achieved = b_alg * cells / (step_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": ctx.step_kernel_name(), "us_per_launch": round(step_ms * 1e3, 3),
+                "bytes_per_cell": b_alg, "cells_per_launch": cells}
+
+    # cell-updates in one solve: (2K + 1) full propagations, 2 (K + 1) slab
+    NZ, NX = prob.nz + 2 * prob.npml, prob.nx + 2 * prob.npml
+    k = prob.order // 2
+    nzs = abs(prob.slab_dz) + 1 + 2 * k + 2 * prob.npml
+    cu_solve = prob.nt * ((2 * wl.K + 1) * NZ * NX + 2 * (wl.K + 1) * nzs * NX)
+    gcell = cu_solve * prob.nshots / (elapsed / args.steps) / 1e9
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        ns_cpu = min(args.cpu_steps, prob.nt)
+        m = oracle.Model(prob.replace(nt=ns_cpu), wl.kappa, wl.rho)
+        hs = np.random.default_rng(0).standard_normal((ns_cpu, prob.ns))
+        t = time.perf_counter()
+        m.fwd(hs)
+        tc = time.perf_counter() - t
+        cpu_gcell = ns_cpu * NZ * NX / tc / 1e9
+        cpu = {"value": cpu_gcell * 1e9 / cu_solve, "unit": "solves/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"FP64 NumPy oracle forward, {ns_cpu} steps of the {NZ}x{NX} "
+                         f"padded grid ({tc:.1f} s, {cpu_gcell:.4f} Gcell/s, 1 thread), "
+                         f"extrapolated linearly to {cu_solve:.3e} cell-updates per solve",
+               "cpu": cpu_model()}
+
+    out = {
+        "metric": "PCG surface-source solves/s",
+        "value": round(value, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32", "f16": "f16-storage/f32", "bf16": "bf16-storage/f32"}[fd],
+        "data": "synthetic (seeded layered model; d = F of a Ricker point source)",
+        "config": {"workload": f"{wl.name}: {prob.nz}x{prob.nx} @ {prob.h} m, order "
+                               f"{prob.order}, nt {prob.nt}, K {wl.K}, shots {prob.nshots}",
+                   "nz": prob.nz, "nx": prob.nx, "nt": prob.nt, "K": wl.K,
+                   "shots": prob.nshots, "field_dtype": fd},
+        "gcell_updates_per_s": round(gcell, 2),
+        "iters": iters,
+        "final_rel_residual": float(hist[0, -1, 0] / hist[0, 0, 0]),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,201 @@
+/*
+ * ssx.h -- C ABI of the surface-source subproblem library (libssx.so).
+ *
+ * The library computes, on one AMD Instinct MI355X (gfx950), the operators
+ * of the surface-source subproblem of W. W. Symes, "Efficient Computation
+ * of Extended Surface Sources" (arXiv 2203.16573):
+ *
+ *   F    pressure source on the line z = z_s  ->  pressure traces on z = z_r
+ *        (the operator S of the Operators section, eqn sdef);
+ *   F^T  its exact discrete transpose (eqn sadj1, Appendix A);
+ *   A    multiplication by the lateral distance |x - x_s| (eqn penop);
+ *   M^-1 = D W^-1 D, D = (I + a^2 A^T A)^(-1/2), W^-1 the thin-slab
+ *        symmetrised pressure-to-source operator (eqns defprecond,
+ *        winvcomp, lamnear);
+ *   and Algorithm 1 (preconditioned CG) on N h = F^T d,
+ *   N = F^T F + alpha^2 A^T A (the penalised problem esisp).
+ *
+ * Discretisation: 2D staggered grid (p on nodes, v_x and v_z on half
+ * nodes), order 2 in time and 4 or 8 in space, split-field PML of npml
+ * cells added outside the physical grid, linear interpolation for sampling
+ * and its transpose (divided by h) for injection (Numerical Examples,
+ * "Synthetic models and simulation").  Time alignment: source sample n
+ * enters the update p^n -> p^{n+1}; pressure trace sample n is p^{n+1};
+ * normal-velocity trace sample n is v_z^{n+1/2}.
+ *
+ * Conventions for every entry point below:
+ *  - Array arguments are DEVICE pointers owned by the caller, contiguous,
+ *    row-major, of the context's vector dtype (double for SSX_F64 fields,
+ *    float otherwise).  Trace arrays are [nshots][nt][n] with the trace
+ *    index fastest.  The library never frees caller memory and keeps no
+ *    reference to it after the call returns.
+ *  - All device work is ordered on the stream given to ssx_create; calls
+ *    return before the work finishes unless stated otherwise.
+ *  - Inputs and outputs must not overlap unless stated otherwise.
+ *  - Errors are returned as ssx_status; no exception crosses the ABI.  On an
+ *    error the outputs are unspecified and the context stays usable, except
+ *    after SSX_ERR_HIP.  ssx_last_error() describes the last error of the
+ *    calling thread.
+ */
+#ifndef SSX_H
+#define SSX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ssx_ctx ssx_ctx;
+
+typedef enum {
+  SSX_OK = 0,
+  SSX_ERR_ARG = 1,        /* invalid argument or geometry                 */
+  SSX_ERR_CFL = 2,        /* dt above the stability bound                 */
+  SSX_ERR_OOM = 3,        /* device allocation failed / workspace too small*/
+  SSX_ERR_HIP = 4,        /* HIP runtime error (context no longer usable)  */
+  SSX_ERR_BREAKDOWN = 5,  /* PCG: <g,r> or <p,q> zero or changed sign      */
+  SSX_ERR_NONFINITE = 6   /* PCG: a non-finite scalar appeared             */
+} ssx_status;
+
+typedef enum { SSX_F64 = 0, SSX_F32 = 1, SSX_F16 = 2, SSX_BF16 = 3 } ssx_dtype;
+
+/* penalty operators for ssx_penalty */
+typedef enum {
+  SSX_PEN_A = 0,      /* y = A x,                      A = |x_k - x_s|     */
+  SSX_PEN_ATA = 1,    /* y = A^T A x                                        */
+  SSX_PEN_DHALF = 2   /* y = (1 + a^2 A^T A)^(-1/2) x  (a = argument a)     */
+} ssx_penalty_op;
+
+/*
+ * Problem description.  Physical grid nz x nx (z slow, x fast), spacing h
+ * (metres) in both directions, node (i, j) at depth i h and lateral
+ * position j h.  npml absorbing cells are added on every side; pml_R is the
+ * target reflection coefficient of the layer.  Source line: ns samples at
+ * depth z_src, lateral positions x_src0 + k h (k < ns); receiver line
+ * likewise.  Lateral positions must lie on grid columns; depths may fall
+ * between rows (linear interpolation).  slab_dz: signed offset, in cells,
+ * of the thin-slab datum from the source line (positive = deeper), used by
+ * the preconditioner.  nshots subproblems share the model and both lines
+ * and differ in their physical point x_s (given to ssx_create) and data.
+ * field_dtype: wavefield storage (F64, F32, F16, BF16); vec_dtype: traces
+ * and Krylov vectors, which must be F64 for F64 fields and F32 otherwise.
+ */
+typedef struct {
+  int32_t nz, nx;
+  double h, dt;
+  int32_t nt;
+  int32_t order;        /* 4 or 8 */
+  int32_t npml;
+  double pml_R;
+  double z_src, x_src0;
+  int32_t ns;
+  double z_rec, x_rec0;
+  int32_t nr;
+  int32_t slab_dz;
+  int32_t nshots;
+  int32_t field_dtype;  /* ssx_dtype */
+  int32_t vec_dtype;    /* ssx_dtype */
+} ssx_problem;
+
+/* Host-only check of a problem and model (no device work).  Rejects:
+ * nz or nx below order+1; order not 4 or 8; negative npml; non-positive h,
+ * dt, nt, ns, nr or nshots; lines off grid columns or outside the physical
+ * grid; slab_dz == 0; dtype combinations other than F64/F64 and
+ * {F32,F16,BF16}/F32; non-finite or non-positive kappa or rho (ARG); and
+ * c_max dt / h above 1 / (sqrt(2) sum_m |c_m|) (CFL).  kappa_host may be
+ * NULL to check the problem alone (the CFL test is then skipped). */
+ssx_status ssx_validate(const ssx_problem* prob, const double* kappa_host, double rho);
+
+/* Device bytes a context for this problem needs (all fields, coefficients,
+ * slab, PCG vectors and scratch); 0 if the problem is invalid. */
+size_t ssx_footprint(const ssx_problem* prob);
+
+/* Create a context.  kappa_host: HOST array [nz][nx] of bulk modulus (Pa),
+ * read during the call only; rho: constant density (kg/m^3); xs_host: HOST
+ * array [nshots] of the physical point of each shot (lateral position, m).
+ * stream: hipStream_t for all work of this context (NULL = default stream).
+ * workspace: optional DEVICE buffer of at least ssx_footprint(prob) bytes,
+ * owned by the caller and used for every internal buffer (then the library
+ * allocates no device memory); NULL makes the library allocate it.  The
+ * call synchronises the stream once (coefficient upload). */
+ssx_status ssx_create(const ssx_problem* prob, const double* kappa_host, double rho,
+                      const double* xs_host, void* stream, void* workspace,
+                      size_t workspace_bytes, ssx_ctx** out);
+
+/* Release the context (waits for its stream).  NULL is ignored. */
+void ssx_destroy(ssx_ctx* ctx);
+
+/* d = F h (Operators section, eqn sdef; one full simulation per shot).
+ * h: [nshots][nt][ns] -> d: [nshots][nt][nr]. */
+ssx_status ssx_fwd(ssx_ctx* ctx, const void* h, void* d);
+
+/* g = F^T r, the exact transpose of ssx_fwd (eqn sadj1, Appendix A): a
+ * reverse-time sweep driven by the residual traces, no stored forward
+ * states.  r: [nshots][nt][nr] -> g: [nshots][nt][ns]. */
+ssx_status ssx_adj(ssx_ctx* ctx, const void* r, void* g);
+
+/* Thin-slab vector operator X (eqns fwd, lamnear): normal-load source f on
+ * the source line of the slab, pressure P and normal velocity V recorded on
+ * the datum z_s + slab_dz h.  f: [nshots][nt][ns] -> P, V: [nshots][nt][ns]. */
+ssx_status ssx_slab_fwd(ssx_ctx* ctx, const void* f, void* P, void* V);
+
+/* Exact transpose of ssx_slab_fwd: a enters the pressure-trace slot, b the
+ * normal-velocity slot; f: the normal-load source slot. */
+ssx_status ssx_slab_adj(ssx_ctx* ctx, const void* a, const void* b, void* f);
+
+/* Diagonal operators of the penalty (eqn penop; the outer factors of eqn
+ * defprecond), per shot with its own x_s: see ssx_penalty_op.  x and y may
+ * be the same array.  x, y: [nshots][nt][ns]. */
+ssx_status ssx_penalty(ssx_ctx* ctx, int op, double a, const void* x, void* y);
+
+/* g = M^-1 r = D W^-1 D r with D = (1 + alpha_hat^2 A^T A)^(-1/2) and
+ * W^-1 = s X^T J X, J (P, V) = (V, P), s = 4 sign(slab_dz) (eqns
+ * defprecond and winvcomp: one forward and one adjoint thin-slab
+ * simulation).  r, g: [nshots][nt][ns]. */
+ssx_status ssx_precond(ssx_ctx* ctx, double alpha_hat, const void* r, void* g);
+
+/* q = N p = F^T F p + alpha^2 A^T A p (the normal operator of esisp), and
+ * Fp = F p if Fp is not NULL.  p, q: [nshots][nt][ns]; Fp: [nshots][nt][nr]. */
+ssx_status ssx_normal(ssx_ctx* ctx, double alpha, const void* p, void* q, void* Fp);
+
+/* Per-shot FP64 inner products <x, y> over n elements per shot (shots at
+ * stride n), deterministic reduction order.  out_host: HOST [nshots];
+ * synchronises the stream. */
+ssx_status ssx_dot(ssx_ctx* ctx, const void* x, const void* y, int64_t n,
+                   double* out_host);
+
+/* Algorithm 1 (standard PCG, h_0 = 0) on N h = F^T d for every shot:
+ * alpha = alpha_rel ||F^T d|| / ||d|| per shot; M^-1 as ssx_precond with
+ * alpha_hat = alpha_rel when use_precond != 0, M = I otherwise (plain CG).
+ * Step lengths, beta and all inner products are FP64 on the device.  Runs
+ * maxit iterations, or stops early once every shot has ||r_k|| <=
+ * rtol ||r_0|| (rtol > 0 only).  d: [nshots][nt][nr]; h_out:
+ * [nshots][nt][ns].  hist_host: HOST [nshots][maxit+1][4] or NULL, row k =
+ * (||r_k||, ||g_k||, <g_k, r_k>, ||F h_k - d||).  iters_host: HOST, the
+ * iterations run.  Synchronises the stream before returning.  Returns
+ * SSX_ERR_BREAKDOWN / SSX_ERR_NONFINITE if any shot broke down (that
+ * shot's iterate is frozen at its last valid value). */
+ssx_status ssx_pcg_solve(ssx_ctx* ctx, const void* d, double alpha_rel, int32_t maxit,
+                         double rtol, int32_t use_precond, void* h_out,
+                         double* hist_host, int32_t* iters_host);
+
+/* Use captured HIP graphs for whole propagations (enable != 0, default) or
+ * plain stream launches (enable == 0).  Results are identical. */
+ssx_status ssx_set_graphs(ssx_ctx* ctx, int enable);
+
+/* Message for the last error on the calling thread ("" if none). */
+const char* ssx_last_error(void);
+
+/* Name of the kernel that dominates a full-grid propagation, and the
+ * number of grid cells one of its launches advances by one time step
+ * (all shots), for throughput accounting. */
+const char* ssx_step_kernel_name(ssx_ctx* ctx);
+int64_t ssx_cells_per_launch(ssx_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSX_H */

@@ -1,0 +1,270 @@
+"""Python binding of libssx (surface-source subproblem on MI355X).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libssx.so``.  PyTorch supplies device memory and the stream.
+The binding fails loudly when the library is missing; there is no CPU path.
+
+Function names follow the C ABI (include/ssx.h):
+
+    ctx = Context(prob, kappa, rho, xs, field_dtype="f32")
+    ctx.fwd(h, d)          d = F h
+    ctx.adj(r, g)          g = F^T r
+    ctx.slab_fwd(f, P, V)  thin-slab X f = (P, V)
+    ctx.slab_adj(a, b, f)  f = X^T (a, b)
+    ctx.penalty(op, a, x, y)
+    ctx.precond(alpha_hat, r, g)
+    ctx.normal(alpha, p, q, Fp=None)
+    ctx.pcg_solve(d, alpha_rel, maxit, ...) -> (h, hist, iters)
+
+``prob`` is any object with the fields of ``ssx_problem`` (nz, nx, h, dt,
+nt, order, npml, pml_R, z_src, x_src0, ns, z_rec, x_rec0, nr, slab_dz);
+the number of shots is ``len(xs)``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libssx.so")
+
+DTYPES = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
+PEN_A, PEN_ATA, PEN_DHALF = 0, 1, 2
+
+STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_CFL", 3: "ERR_OOM", 4: "ERR_HIP",
+          5: "ERR_BREAKDOWN", 6: "ERR_NONFINITE"}
+
+EXPORTS = ("ssx_validate", "ssx_footprint", "ssx_create", "ssx_destroy", "ssx_fwd",
+           "ssx_adj", "ssx_slab_fwd", "ssx_slab_adj", "ssx_penalty", "ssx_precond",
+           "ssx_normal", "ssx_dot", "ssx_pcg_solve", "ssx_set_graphs", "ssx_last_error",
+           "ssx_step_kernel_name", "ssx_cells_per_launch")
+
+
+class SSXError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class ssx_problem(ctypes.Structure):
+    _fields_ = [("nz", ctypes.c_int32), ("nx", ctypes.c_int32),
+                ("h", ctypes.c_double), ("dt", ctypes.c_double),
+                ("nt", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("npml", ctypes.c_int32), ("pml_R", ctypes.c_double),
+                ("z_src", ctypes.c_double), ("x_src0", ctypes.c_double),
+                ("ns", ctypes.c_int32), ("z_rec", ctypes.c_double),
+                ("x_rec0", ctypes.c_double), ("nr", ctypes.c_int32),
+                ("slab_dz", ctypes.c_int32), ("nshots", ctypes.c_int32),
+                ("field_dtype", ctypes.c_int32), ("vec_dtype", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libssx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "paper_2203_16573_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, c_int, c_dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        for name in EXPORTS:
+            getattr(L, name).restype = c_int
+        P = ctypes.POINTER(ssx_problem)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.ssx_validate.argtypes = [P, dp, c_dbl]
+        L.ssx_footprint.argtypes = [P]
+        L.ssx_footprint.restype = ctypes.c_size_t
+        L.ssx_create.argtypes = [P, dp, c_dbl, dp, vp, vp, ctypes.c_size_t,
+                                 ctypes.POINTER(vp)]
+        L.ssx_destroy.argtypes = [vp]
+        L.ssx_destroy.restype = None
+        L.ssx_fwd.argtypes = [vp, vp, vp]
+        L.ssx_adj.argtypes = [vp, vp, vp]
+        L.ssx_slab_fwd.argtypes = [vp, vp, vp, vp]
+        L.ssx_slab_adj.argtypes = [vp, vp, vp, vp]
+        L.ssx_penalty.argtypes = [vp, c_int, c_dbl, vp, vp]
+        L.ssx_precond.argtypes = [vp, c_dbl, vp, vp]
+        L.ssx_normal.argtypes = [vp, c_dbl, vp, vp, vp]
+        L.ssx_dot.argtypes = [vp, vp, vp, ctypes.c_int64, dp]
+        L.ssx_pcg_solve.argtypes = [vp, vp, c_dbl, ctypes.c_int32, c_dbl, ctypes.c_int32,
+                                    vp, dp, ctypes.POINTER(ctypes.c_int32)]
+        L.ssx_set_graphs.argtypes = [vp, c_int]
+        L.ssx_last_error.restype = ctypes.c_char_p
+        L.ssx_step_kernel_name.argtypes = [vp]
+        L.ssx_step_kernel_name.restype = ctypes.c_char_p
+        L.ssx_cells_per_launch.argtypes = [vp]
+        L.ssx_cells_per_launch.restype = ctypes.c_int64
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise SSXError(status, lib().ssx_last_error().decode())
+
+
+def make_problem(prob, nshots: int, field_dtype: str = "f32") -> ssx_problem:
+    fd = DTYPES[field_dtype]
+    vd = 0 if fd == 0 else 1
+    return ssx_problem(int(prob.nz), int(prob.nx), float(prob.h), float(prob.dt),
+                       int(prob.nt), int(prob.order), int(prob.npml), float(prob.pml_R),
+                       float(prob.z_src), float(prob.x_src0), int(prob.ns),
+                       float(prob.z_rec), float(prob.x_rec0), int(prob.nr),
+                       int(prob.slab_dz), int(nshots), fd, vd)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def validate(prob, kappa=None, rho: float = 1000.0, field_dtype: str = "f32",
+             nshots: int | None = None) -> None:
+    """Host-only validation; raises SSXError."""
+    ns = len(prob.xs) if nshots is None else nshots
+    P = make_problem(prob, ns, field_dtype)
+    k = None
+    if kappa is not None:
+        k = np.ascontiguousarray(kappa, dtype=np.float64)
+    _check(lib().ssx_validate(ctypes.byref(P), _dptr(k) if k is not None else None, rho))
+
+
+def footprint(prob, field_dtype: str = "f32", nshots: int | None = None) -> int:
+    ns = len(prob.xs) if nshots is None else nshots
+    P = make_problem(prob, ns, field_dtype)
+    return int(lib().ssx_footprint(ctypes.byref(P)))
+
+
+class Context:
+    """An ssx_ctx bound to a torch device stream (the current stream by default)."""
+
+    def __init__(self, prob, kappa, rho: float, xs=None, field_dtype: str = "f32",
+                 stream=None, workspace=None):
+        import torch
+
+        self.prob = prob
+        xs = tuple(prob.xs) if xs is None else tuple(xs)
+        self.nshots = len(xs)
+        self.field_dtype = field_dtype
+        self.vdtype = torch.float64 if field_dtype == "f64" else torch.float32
+        self._P = make_problem(prob, self.nshots, field_dtype)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        k = np.ascontiguousarray(kappa, dtype=np.float64)
+        xsa = np.ascontiguousarray(xs, dtype=np.float64)
+        ctx = ctypes.c_void_p()
+        ws_ptr, ws_bytes = None, 0
+        if workspace is not None:
+            ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+        self._workspace = workspace
+        _check(lib().ssx_create(ctypes.byref(self._P), _dptr(k), float(rho), _dptr(xsa),
+                                ctypes.c_void_p(self.stream.cuda_stream), ws_ptr, ws_bytes,
+                                ctypes.byref(ctx)))
+        self._ctx = ctx
+
+    # -- helpers --------------------------------------------------------------
+    def _vec(self, t, n, name):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a device tensor")
+        if t.dtype != self.vdtype or not t.is_contiguous() or t.numel() != n:
+            raise ValueError(f"{name}: expected contiguous {self.vdtype} with {n} elements, "
+                             f"got {t.dtype} {tuple(t.shape)}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    @property
+    def n_s(self):
+        return self.nshots * self.prob.nt * self.prob.ns
+
+    @property
+    def n_r(self):
+        return self.nshots * self.prob.nt * self.prob.nr
+
+    def empty_s(self):
+        import torch
+        return torch.empty((self.nshots, self.prob.nt, self.prob.ns), dtype=self.vdtype,
+                           device="cuda")
+
+    def empty_r(self):
+        import torch
+        return torch.empty((self.nshots, self.prob.nt, self.prob.nr), dtype=self.vdtype,
+                           device="cuda")
+
+    # -- operators ------------------------------------------------------------
+    def fwd(self, h, d):
+        _check(lib().ssx_fwd(self._ctx, self._vec(h, self.n_s, "h"), self._vec(d, self.n_r, "d")))
+        return d
+
+    def adj(self, r, g):
+        _check(lib().ssx_adj(self._ctx, self._vec(r, self.n_r, "r"), self._vec(g, self.n_s, "g")))
+        return g
+
+    def slab_fwd(self, f, P, V):
+        _check(lib().ssx_slab_fwd(self._ctx, self._vec(f, self.n_s, "f"),
+                                  self._vec(P, self.n_s, "P"), self._vec(V, self.n_s, "V")))
+        return P, V
+
+    def slab_adj(self, a, b, f):
+        _check(lib().ssx_slab_adj(self._ctx, self._vec(a, self.n_s, "a"),
+                                  self._vec(b, self.n_s, "b"), self._vec(f, self.n_s, "f")))
+        return f
+
+    def penalty(self, op, a, x, y):
+        _check(lib().ssx_penalty(self._ctx, int(op), float(a), self._vec(x, self.n_s, "x"),
+                                 self._vec(y, self.n_s, "y")))
+        return y
+
+    def precond(self, alpha_hat, r, g):
+        _check(lib().ssx_precond(self._ctx, float(alpha_hat), self._vec(r, self.n_s, "r"),
+                                 self._vec(g, self.n_s, "g")))
+        return g
+
+    def normal(self, alpha, p, q, Fp=None):
+        fp = self._vec(Fp, self.n_r, "Fp") if Fp is not None else None
+        _check(lib().ssx_normal(self._ctx, float(alpha), self._vec(p, self.n_s, "p"),
+                                self._vec(q, self.n_s, "q"), fp))
+        return q
+
+    def dot(self, x, y):
+        n = x.numel() // self.nshots
+        out = np.zeros(self.nshots)
+        _check(lib().ssx_dot(self._ctx, self._vec(x, x.numel(), "x"),
+                             self._vec(y, x.numel(), "y"), n, _dptr(out)))
+        return out
+
+    def pcg_solve(self, d, alpha_rel, maxit, rtol=0.0, use_precond=True, h=None,
+                  raise_on_breakdown=True):
+        """Returns (h, hist [nshots][maxit+1][4], iterations, status)."""
+        if h is None:
+            h = self.empty_s()
+        hist = np.zeros((self.nshots, maxit + 1, 4))
+        it = ctypes.c_int32(0)
+        st = lib().ssx_pcg_solve(self._ctx, self._vec(d, self.n_r, "d"), float(alpha_rel),
+                                 int(maxit), float(rtol), int(bool(use_precond)),
+                                 self._vec(h, self.n_s, "h"), _dptr(hist), ctypes.byref(it))
+        if st != 0 and (raise_on_breakdown or st not in (5, 6)):
+            _check(st)
+        return h, hist[:, : it.value + 1], it.value, st
+
+    def set_graphs(self, enable: bool):
+        _check(lib().ssx_set_graphs(self._ctx, int(bool(enable))))
+
+    def step_kernel_name(self) -> str:
+        return lib().ssx_step_kernel_name(self._ctx).decode()
+
+    def cells_per_launch(self) -> int:
+        return int(lib().ssx_cells_per_launch(self._ctx))
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().ssx_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,753 @@
+// C ABI of libssx: validation, model/coefficient setup, propagation drivers,
+// the thin-slab preconditioner and Algorithm 1 (preconditioned CG).
+//
+// Every numerical step runs in the HIP kernels of ssx_kernels.hip; this
+// file only prepares coefficients (once, in FP64 on the host), sequences
+// launches on the context's stream and moves scalars/history to the host.
+#include "ssx.h"
+#include "ssx_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace ssx;
+
+namespace {
+
+thread_local std::string g_err;
+
+ssx_status fail(ssx_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define SSX_HIP(expr)                                                          \
+  do {                                                                         \
+    hipError_t e_ = (expr);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      g_err = std::string(#expr) + ": " + hipGetErrorString(e_);               \
+      return SSX_ERR_HIP;                                                      \
+    }                                                                          \
+  } while (0)
+
+#define SSX_TRY(expr)                 \
+  do {                                \
+    ssx_status s_ = (expr);           \
+    if (s_ != SSX_OK) return s_;      \
+  } while (0)
+
+constexpr int HIST_CAP = 4096;  // maximum PCG iterations with history
+
+size_t dtype_size(int dt) {
+  switch (dt) {
+    case SSX_F64: return 8;
+    case SSX_F32: return 4;
+    case SSX_F16: return 2;
+    case SSX_BF16: return 2;
+  }
+  return 0;
+}
+
+// Sum of |c_m| of the staggered stencil of the given order.
+double stencil_abs_sum(int order) {
+  if (order == 4) return 9.0 / 8.0 + 1.0 / 24.0;
+  return 1225.0 / 1024.0 + 245.0 / 3072.0 + 49.0 / 5120.0 + 5.0 / 7168.0;
+}
+
+// A line at physical depth z on one grid.  node = true: p nodes (row i at
+// depth (i - L) h); false: v_z half nodes (row i at depth (i - L + 1/2) h).
+bool make_line(double z, double x0, int n, double h, int L, int nz_phys, int nx_phys,
+               bool node, LineDev* out, std::string* why) {
+  const double u = L + z / h - (node ? 0.0 : 0.5);
+  int i0 = (int)std::floor(u + 1e-12);
+  double w1 = u - i0;
+  if (std::fabs(w1) < 1e-12) w1 = 0.0;
+  const int lo = L, hi = node ? L + nz_phys - 1 : L + nz_phys - 2;
+  const int i1 = (w1 == 0.0) ? i0 : i0 + 1;
+  if (i0 < lo || i1 > hi) {
+    *why = "line depth outside the physical grid";
+    return false;
+  }
+  const double j0 = x0 / h;
+  if (std::fabs(j0 - std::round(j0)) > 1e-9) {
+    *why = "line lateral positions must lie on grid columns";
+    return false;
+  }
+  const int c0 = L + (int)std::lround(j0);
+  if (n < 1 || c0 < L || c0 + n - 1 > L + nx_phys - 1) {
+    *why = "line extends outside the physical grid";
+    return false;
+  }
+  out->row0 = i0;
+  out->row1 = i1;
+  out->w0 = 1.0 - w1;
+  out->w1 = w1;
+  out->col0 = c0;
+  out->ntr = n;
+  return true;
+}
+
+// Rows of the full model used by the thin slab: [i_lo, i_hi] (may extend
+// beyond the model; clamped when copying kappa).
+void slab_rows(const ssx_problem& p, int* i_lo, int* i_hi, double* zs_slab) {
+  const int k = p.order / 2;
+  const int i_s = (int)std::floor(p.z_src / p.h + 1e-12);
+  const double frac = p.z_src / p.h - i_s;
+  *i_lo = std::min(i_s, i_s + p.slab_dz) - k;
+  *i_hi = std::max(i_s, i_s + p.slab_dz) + k + (frac > 1e-12 ? 1 : 0);
+  *zs_slab = p.z_src - (*i_lo) * p.h;
+}
+
+ssx_status check_problem(const ssx_problem* pp) {
+  if (!pp) return fail(SSX_ERR_ARG, "problem is NULL");
+  const ssx_problem& p = *pp;
+  if (p.order != 4 && p.order != 8) return fail(SSX_ERR_ARG, "order must be 4 or 8");
+  if (p.nz < p.order + 1 || p.nx < p.order + 1)
+    return fail(SSX_ERR_ARG, "grid smaller than the stencil");
+  if (p.npml < 0) return fail(SSX_ERR_ARG, "npml must be >= 0");
+  if (!(p.h > 0) || !(p.dt > 0) || !std::isfinite(p.h) || !std::isfinite(p.dt))
+    return fail(SSX_ERR_ARG, "h and dt must be positive");
+  if (p.nt < 1 || p.ns < 1 || p.nr < 1 || p.nshots < 1)
+    return fail(SSX_ERR_ARG, "nt, ns, nr and nshots must be >= 1");
+  if (p.slab_dz == 0) return fail(SSX_ERR_ARG, "slab_dz must be nonzero");
+  if (p.npml > 0 && !(p.pml_R > 0 && p.pml_R < 1))
+    return fail(SSX_ERR_ARG, "pml_R must be in (0, 1)");
+  const bool ok_dt = (p.field_dtype == SSX_F64 && p.vec_dtype == SSX_F64) ||
+                     ((p.field_dtype == SSX_F32 || p.field_dtype == SSX_F16 ||
+                       p.field_dtype == SSX_BF16) &&
+                      p.vec_dtype == SSX_F32);
+  if (!ok_dt) return fail(SSX_ERR_ARG, "dtypes must be F64/F64 or {F32,F16,BF16}/F32");
+  std::string why;
+  LineDev l;
+  const int L = p.npml;
+  if (!make_line(p.z_src, p.x_src0, p.ns, p.h, L, p.nz, p.nx, true, &l, &why))
+    return fail(SSX_ERR_ARG, "source line: " + why);
+  if (!make_line(p.z_rec, p.x_rec0, p.nr, p.h, L, p.nz, p.nx, true, &l, &why))
+    return fail(SSX_ERR_ARG, "receiver line: " + why);
+  int i_lo, i_hi;
+  double zs;
+  slab_rows(p, &i_lo, &i_hi, &zs);
+  const int nzs = i_hi - i_lo + 1;
+  if (!make_line(zs, p.x_src0, p.ns, p.h, L, nzs, p.nx, false, &l, &why) ||
+      !make_line(zs + p.slab_dz * p.h, p.x_src0, p.ns, p.h, L, nzs, p.nx, true, &l, &why) ||
+      !make_line(zs + p.slab_dz * p.h, p.x_src0, p.ns, p.h, L, nzs, p.nx, false, &l, &why))
+    return fail(SSX_ERR_ARG, "thin slab: " + why);
+  return SSX_OK;
+}
+
+ssx_status check_model(const ssx_problem& p, const double* kappa, double rho, double* cmax) {
+  if (!(rho > 0) || !std::isfinite(rho)) return fail(SSX_ERR_ARG, "rho must be positive");
+  double kmax = 0;
+  const size_t n = (size_t)p.nz * p.nx;
+  for (size_t i = 0; i < n; ++i) {
+    const double k = kappa[i];
+    if (!std::isfinite(k) || !(k > 0)) return fail(SSX_ERR_ARG, "kappa must be finite and > 0");
+    kmax = std::max(kmax, k);
+  }
+  *cmax = std::sqrt(kmax / rho);
+  const double bound = 1.0 / (std::sqrt(2.0) * stencil_abs_sum(p.order));
+  const double courant = *cmax * p.dt / p.h;
+  if (courant > bound) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "Courant number %.4f above the stability bound %.4f",
+                  courant, bound);
+    return fail(SSX_ERR_CFL, buf);
+  }
+  return SSX_OK;
+}
+
+// Host-side description of one padded grid and its FP64 coefficients.
+struct GridHost {
+  int nz, nx, L, NZ, NX, pitch;
+  long long field_elems;  // one field of one shot, ghosts included
+  long long origin;
+  std::vector<double> ck;   // [NZ][NX]
+  std::vector<double> pml;  // ax_n bx_n ax_h bx_h [NX], az_n bz_n az_h bz_h [NZ]
+};
+
+void build_grid(const ssx_problem& p, const std::vector<double>& kphys, int nz, double Z0,
+                double rho, GridHost* g) {
+  const int L = p.npml, nx = p.nx;
+  g->nz = nz;
+  g->nx = nx;
+  g->L = L;
+  g->NZ = nz + 2 * L;
+  g->NX = nx + 2 * L;
+  g->pitch = ((g->NX + 2 * GX) + 63) / 64 * 64;
+  g->field_elems = (long long)(g->NZ + 2 * GZ) * g->pitch;
+  g->origin = (long long)GZ * g->pitch + GX;
+  // model padded by copying the nearest physical value
+  double kmax = 0;
+  g->ck.resize((size_t)g->NZ * g->NX);
+  for (int I = 0; I < g->NZ; ++I) {
+    const int i = std::min(std::max(I - L, 0), nz - 1);
+    for (int J = 0; J < g->NX; ++J) {
+      const int j = std::min(std::max(J - L, 0), nx - 1);
+      const double k = kphys[(size_t)i * nx + j];
+      kmax = std::max(kmax, k);
+      g->ck[(size_t)I * g->NX + J] = p.dt * k / (p.h * Z0);
+    }
+  }
+  // PML: sigma(d) = smax (d / L)^2, d = cells into the layer;
+  // a = (1 - sigma dt / 2) / (1 + sigma dt / 2), b = 1 / (1 + sigma dt / 2)
+  const double cmax = std::sqrt(kmax / rho);
+  const double smax = L > 0 ? 3.0 * cmax * std::log(1.0 / p.pml_R) / (2.0 * L * p.h) : 0.0;
+  auto ab = [&](double pos, int nphys, double* a, double* b) {
+    double d = std::max(std::max((double)L - pos, pos - (double)(L + nphys - 1)), 0.0);
+    const double sig = L > 0 ? smax * (d / L) * (d / L) : 0.0;
+    const double q = 0.5 * sig * p.dt;
+    *a = (1.0 - q) / (1.0 + q);
+    *b = 1.0 / (1.0 + q);
+  };
+  const int NX = g->NX, NZ = g->NZ;
+  g->pml.assign(4 * (size_t)NX + 4 * (size_t)NZ, 0.0);
+  double* P = g->pml.data();
+  for (int J = 0; J < NX; ++J) {
+    ab(J, nx, &P[J], &P[NX + J]);
+    ab(J + 0.5, nx, &P[2 * NX + J], &P[3 * NX + J]);
+  }
+  for (int I = 0; I < NZ; ++I) {
+    ab(I, nz, &P[4 * NX + I], &P[4 * NX + NZ + I]);
+    ab(I + 0.5, nz, &P[4 * NX + 2 * NZ + I], &P[4 * NX + 3 * NZ + I]);
+  }
+}
+
+struct Alloc {  // bump allocator over one device block
+  char* base = nullptr;
+  size_t off = 0, cap = 0;
+  void* take(size_t bytes) {
+    off = (off + 255) / 256 * 256;
+    void* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+struct Layout {
+  size_t fields_full, fields_slab, coef_full, coef_slab, xs, vec_s, vec_r, sc, partial, hist;
+  size_t total;
+};
+
+}  // namespace
+
+struct GridDev {
+  GridHost host;
+  GridDims dims;
+  Coef coef;
+  Fields fields;
+  void* field_block;
+  size_t field_bytes;
+};
+
+struct ssx_ctx {
+  ssx_problem prob;
+  Dt fdt;
+  bool vdbl;
+  size_t fsz, csz, vsz;
+  hipStream_t stream;
+  double rho, Z0;
+  GridDev full, slab;
+  LineDev h_line, r_line, f_line, dp_line, dv_line;
+  double* xs_dev;
+  // vectors: [nshots][nt][ns] (s) or [nshots][nt][nr] (r)
+  void *r, *g, *p, *q, *t1, *sP, *sV, *sF;  // s-vectors
+  void *e, *Fp, *t2;                          // r-vectors
+  double* sc;
+  double* partial;
+  double* hist;
+  void* own = nullptr;  // device block allocated by the library (null if workspace)
+  bool graphs = true;
+};
+
+namespace {
+
+long long nvec_s(const ssx_problem& p) { return (long long)p.nt * p.ns; }
+long long nvec_r(const ssx_problem& p) { return (long long)p.nt * p.nr; }
+
+// Lays out every buffer of a context; with a null base only sizes are computed.
+void layout(ssx_ctx* c, const GridHost& fg, const GridHost& sg, char* base, size_t* total) {
+  const ssx_problem& p = c->prob;
+  Alloc a;
+  a.base = base;
+  const int ns = p.nshots;
+  const size_t fsz = dtype_size(p.field_dtype);
+  const size_t csz = p.field_dtype == SSX_F64 ? 8 : 4;
+  const size_t vsz = dtype_size(p.vec_dtype);
+  auto grid = [&](GridDev& gd, const GridHost& gh) {
+    gd.field_bytes = 4 * (size_t)ns * gh.field_elems * fsz;
+    gd.field_block = a.take(gd.field_bytes);
+    char* fb = (char*)gd.field_block;
+    const size_t one = (size_t)ns * gh.field_elems * fsz;
+    gd.fields.p = fb;
+    gd.fields.vx = fb ? fb + one : nullptr;
+    gd.fields.vz = fb ? fb + 2 * one : nullptr;
+    gd.fields.aux = fb ? fb + 3 * one : nullptr;
+    gd.coef.ck = a.take((size_t)gh.NZ * gh.NX * csz);
+    gd.coef.pml = a.take(gh.pml.size() * csz);
+  };
+  grid(c->full, fg);
+  grid(c->slab, sg);
+  c->xs_dev = (double*)a.take((size_t)ns * 8);
+  const size_t bs = (size_t)ns * nvec_s(p) * vsz, br = (size_t)ns * nvec_r(p) * vsz;
+  void** svec[] = {&c->r, &c->g, &c->p, &c->q, &c->t1, &c->sP, &c->sV, &c->sF};
+  for (void** v : svec) *v = a.take(bs);
+  void** rvec[] = {&c->e, &c->Fp, &c->t2};
+  for (void** v : rvec) *v = a.take(br);
+  c->sc = (double*)a.take((size_t)ns * SC_N * 8);
+  c->partial = (double*)a.take((size_t)ns * NBLK_DOT * 3 * 8);
+  c->hist = (double*)a.take((size_t)ns * (HIST_CAP + 1) * 4 * 8);
+  *total = a.off + 256;
+}
+
+ssx_status upload(GridDev& gd, bool dbl, hipStream_t s) {
+  const GridHost& g = gd.host;
+  if (dbl) {
+    SSX_HIP(hipMemcpyAsync(const_cast<void*>(gd.coef.ck), g.ck.data(), g.ck.size() * 8,
+                           hipMemcpyHostToDevice, s));
+    SSX_HIP(hipMemcpyAsync(const_cast<void*>(gd.coef.pml), g.pml.data(), g.pml.size() * 8,
+                           hipMemcpyHostToDevice, s));
+    SSX_HIP(hipStreamSynchronize(s));
+  } else {
+    std::vector<float> ck(g.ck.begin(), g.ck.end()), pml(g.pml.begin(), g.pml.end());
+    SSX_HIP(hipMemcpyAsync(const_cast<void*>(gd.coef.ck), ck.data(), ck.size() * 4,
+                           hipMemcpyHostToDevice, s));
+    SSX_HIP(hipMemcpyAsync(const_cast<void*>(gd.coef.pml), pml.data(), pml.size() * 4,
+                           hipMemcpyHostToDevice, s));
+    SSX_HIP(hipStreamSynchronize(s));
+  }
+  return SSX_OK;
+}
+
+void fill_dims(GridDev& gd, int nshots) {
+  const GridHost& g = gd.host;
+  gd.dims.NZ = g.NZ;
+  gd.dims.NX = g.NX;
+  gd.dims.L = g.L;
+  gd.dims.pitch = g.pitch;
+  gd.dims.field_stride = g.field_elems;
+  gd.dims.origin = g.origin;
+  (void)nshots;
+}
+
+// Per-shot field arrays are laid out [field][shot][rows][pitch]; the kernels
+// take one base pointer per field and step by field_stride between shots.
+
+TraceIO io_none() {
+  TraceIO t;
+  t.in = nullptr;
+  t.out = nullptr;
+  t.n = -1;
+  t.shot_stride = 0;
+  t.scale = 1.0;
+  return t;
+}
+TraceIO io_in(const void* in, long long stride, double scale) {
+  TraceIO t = io_none();
+  t.in = in;
+  t.shot_stride = stride;
+  t.scale = scale;
+  return t;
+}
+TraceIO io_out(void* out, long long stride, double scale) {
+  TraceIO t = io_none();
+  t.out = out;
+  t.shot_stride = stride;
+  t.scale = scale;
+  return t;
+}
+
+// One propagation over nt steps.
+//   vs: sampled by the velocity launch (a pressure line)
+//   vi: injected by the velocity launch (a v_z line)
+//   ps: sampled by the pressure launch (a v_z line)
+//   pi: injected by the pressure launch (a pressure line)
+// Forward: step n samples vs at n-1 (p^n), injects vi[n], samples ps[n]
+// (v^{n+1/2}), injects pi[n]; a last launch samples vs at nt-1.
+// Transpose: pi[nt-1] enters first; step n (descending) samples vs[n]
+// (the transposed pressure after sample n of the adjoint input entered),
+// injects vi[n], samples ps[n] and injects pi[n-1].
+ssx_status propagate(ssx_ctx* c, GridDev& gd, bool adj, const LineDev& vsl, TraceIO vs,
+                     const LineDev& vil, TraceIO vi, const LineDev& psl, TraceIO ps,
+                     const LineDev& pil, TraceIO pi) {
+  const int nt = c->prob.nt, ns = c->prob.nshots, order = c->prob.order;
+  hipStream_t s = c->stream;
+  SSX_HIP(launch_zero(gd.field_block, gd.field_bytes, s));
+  if (!adj) {
+    for (int n = 0; n < nt; ++n) {
+      vs.n = (vs.out && n >= 1) ? n - 1 : -1;
+      vi.n = vi.in ? n : -1;
+      SSX_HIP(launch_vel(c->fdt, order, false, gd.fields, gd.dims, gd.coef, vsl, vs, vil, vi,
+                         ns, s));
+      ps.n = ps.out ? n : -1;
+      pi.n = pi.in ? n : -1;
+      SSX_HIP(launch_pres(c->fdt, order, false, gd.fields, gd.dims, gd.coef, psl, ps, pil, pi,
+                          ns, s));
+    }
+    if (vs.out) {
+      vs.n = nt - 1;
+      SSX_HIP(launch_sample_p(c->fdt, gd.fields, gd.dims, vsl, vs, ns, s));
+    }
+  } else {
+    {
+      TraceIO none = io_none();
+      pi.n = pi.in ? nt - 1 : -1;
+      SSX_HIP(launch_pres(c->fdt, order, true, gd.fields, gd.dims, gd.coef, psl, none, pil, pi,
+                          ns, s));
+    }
+    for (int n = nt - 1; n >= 0; --n) {
+      vs.n = vs.out ? n : -1;
+      vi.n = vi.in ? n : -1;
+      SSX_HIP(launch_vel(c->fdt, order, true, gd.fields, gd.dims, gd.coef, vsl, vs, vil, vi, ns,
+                         s));
+      ps.n = ps.out ? n : -1;
+      pi.n = (pi.in && n >= 1) ? n - 1 : -1;
+      SSX_HIP(launch_pres(c->fdt, order, true, gd.fields, gd.dims, gd.coef, psl, ps, pil, pi,
+                          ns, s));
+    }
+  }
+  return SSX_OK;
+}
+
+ssx_status do_fwd(ssx_ctx* c, const void* h, void* d) {
+  const ssx_problem& p = c->prob;
+  return propagate(c, c->full, false, c->r_line, io_out(d, nvec_r(p), c->Z0), c->r_line,
+                   io_none(), c->r_line, io_none(), c->h_line, io_in(h, nvec_s(p), 1.0));
+}
+
+ssx_status do_adj(ssx_ctx* c, const void* r, void* g) {
+  const ssx_problem& p = c->prob;
+  return propagate(c, c->full, true, c->h_line, io_out(g, nvec_s(p), 1.0), c->h_line,
+                   io_none(), c->h_line, io_none(), c->r_line, io_in(r, nvec_r(p), c->Z0));
+}
+
+ssx_status do_slab_fwd(ssx_ctx* c, const void* f, void* P, void* V) {
+  const long long st = nvec_s(c->prob);
+  return propagate(c, c->slab, false, c->dp_line, io_out(P, st, c->Z0), c->f_line,
+                   io_in(f, st, 1.0 / c->Z0), c->dv_line, io_out(V, st, 1.0), c->dp_line,
+                   io_none());
+}
+
+ssx_status do_slab_adj(ssx_ctx* c, const void* a, const void* b, void* f) {
+  const long long st = nvec_s(c->prob);
+  return propagate(c, c->slab, true, c->dp_line, io_none(), c->dv_line, io_in(b, st, 1.0),
+                   c->f_line, io_out(f, st, 1.0 / c->Z0), c->dp_line, io_in(a, st, c->Z0));
+}
+
+double slab_scale(const ssx_ctx* c) { return c->prob.slab_dz > 0 ? 4.0 : -4.0; }
+
+ssx_status do_precond(ssx_ctx* c, double alpha_hat, const void* r, void* g) {
+  const ssx_problem& p = c->prob;
+  SSX_HIP(launch_diag(c->vdbl, 2, alpha_hat, 1.0, r, c->t1, p.nt, p.ns, p.nshots, p.x_src0, p.h,
+                      c->xs_dev, c->stream));
+  SSX_TRY(do_slab_fwd(c, c->t1, c->sP, c->sV));
+  SSX_TRY(do_slab_adj(c, c->sV, c->sP, c->sF));  // J (P, V) = (V, P)
+  SSX_HIP(launch_diag(c->vdbl, 2, alpha_hat, slab_scale(c), c->sF, g, p.nt, p.ns, p.nshots,
+                      p.x_src0, p.h, c->xs_dev, c->stream));
+  return SSX_OK;
+}
+
+// q = F^T F p + alpha^2 A^T A p, Fp = F p; alpha^2 from the device scalar
+// block (alpha2_dev != null) or the host value.
+ssx_status do_normal(ssx_ctx* c, const double* alpha2_dev, double alpha2_host, const void* p,
+                     void* q, void* Fp) {
+  const ssx_problem& pr = c->prob;
+  SSX_TRY(do_fwd(c, p, Fp));
+  SSX_TRY(do_adj(c, Fp, q));
+  SSX_HIP(launch_add_penalty(c->vdbl, q, p, alpha2_dev, SC_N, alpha2_host, pr.nt, pr.ns,
+                             pr.nshots, pr.x_src0, pr.h, c->xs_dev, c->stream));
+  return SSX_OK;
+}
+
+ssx_status copy_vec(ssx_ctx* c, void* dst, const void* src, size_t bytes) {
+  SSX_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream));
+  return SSX_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+ssx_status ssx_validate(const ssx_problem* prob, const double* kappa_host, double rho) {
+  SSX_TRY(check_problem(prob));
+  if (kappa_host) {
+    double cmax;
+    SSX_TRY(check_model(*prob, kappa_host, rho, &cmax));
+  }
+  return SSX_OK;
+}
+
+size_t ssx_footprint(const ssx_problem* prob) {
+  if (check_problem(prob) != SSX_OK) return 0;
+  ssx_ctx c{};
+  c.prob = *prob;
+  int i_lo, i_hi;
+  double zs;
+  slab_rows(*prob, &i_lo, &i_hi, &zs);
+  GridHost fg{}, sg{};
+  auto dims = [&](GridHost& g, int nz) {
+    g.nz = nz;
+    g.nx = prob->nx;
+    g.L = prob->npml;
+    g.NZ = nz + 2 * g.L;
+    g.NX = prob->nx + 2 * g.L;
+    g.pitch = ((g.NX + 2 * GX) + 63) / 64 * 64;
+    g.field_elems = (long long)(g.NZ + 2 * GZ) * g.pitch;
+    g.pml.resize(4 * (size_t)g.NX + 4 * (size_t)g.NZ);
+  };
+  dims(fg, prob->nz);
+  dims(sg, i_hi - i_lo + 1);
+  size_t total = 0;
+  layout(&c, fg, sg, nullptr, &total);
+  return total;
+}
+
+ssx_status ssx_create(const ssx_problem* prob, const double* kappa_host, double rho,
+                      const double* xs_host, void* stream, void* workspace,
+                      size_t workspace_bytes, ssx_ctx** out) {
+  if (!out) return fail(SSX_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  SSX_TRY(check_problem(prob));
+  if (!kappa_host || !xs_host) return fail(SSX_ERR_ARG, "kappa_host and xs_host are required");
+  double cmax;
+  SSX_TRY(check_model(*prob, kappa_host, rho, &cmax));
+  for (int s = 0; s < prob->nshots; ++s)
+    if (!std::isfinite(xs_host[s])) return fail(SSX_ERR_ARG, "xs must be finite");
+
+  ssx_ctx* c = new ssx_ctx();
+  c->prob = *prob;
+  const ssx_problem& p = c->prob;
+  c->fdt = (Dt)p.field_dtype;
+  c->vdbl = p.vec_dtype == SSX_F64;
+  c->fsz = dtype_size(p.field_dtype);
+  c->csz = p.field_dtype == SSX_F64 ? 8 : 4;
+  c->vsz = dtype_size(p.vec_dtype);
+  c->stream = (hipStream_t)stream;
+  c->rho = rho;
+  c->Z0 = rho * cmax;
+
+  std::vector<double> kphys(kappa_host, kappa_host + (size_t)p.nz * p.nx);
+  build_grid(p, kphys, p.nz, c->Z0, rho, &c->full.host);
+  int i_lo, i_hi;
+  double zs;
+  slab_rows(p, &i_lo, &i_hi, &zs);
+  const int nzs = i_hi - i_lo + 1;
+  std::vector<double> kslab((size_t)nzs * p.nx);
+  for (int r = 0; r < nzs; ++r) {
+    const int i = std::min(std::max(i_lo + r, 0), p.nz - 1);
+    std::memcpy(&kslab[(size_t)r * p.nx], &kphys[(size_t)i * p.nx], p.nx * sizeof(double));
+  }
+  build_grid(p, kslab, nzs, c->Z0, rho, &c->slab.host);
+  fill_dims(c->full, p.nshots);
+  fill_dims(c->slab, p.nshots);
+  c->full.coef.cb = c->Z0 * p.dt / (rho * p.h);
+  c->slab.coef.cb = c->full.coef.cb;
+
+  std::string why;
+  const int L = p.npml;
+  make_line(p.z_src, p.x_src0, p.ns, p.h, L, p.nz, p.nx, true, &c->h_line, &why);
+  make_line(p.z_rec, p.x_rec0, p.nr, p.h, L, p.nz, p.nx, true, &c->r_line, &why);
+  make_line(zs, p.x_src0, p.ns, p.h, L, nzs, p.nx, false, &c->f_line, &why);
+  make_line(zs + p.slab_dz * p.h, p.x_src0, p.ns, p.h, L, nzs, p.nx, true, &c->dp_line, &why);
+  make_line(zs + p.slab_dz * p.h, p.x_src0, p.ns, p.h, L, nzs, p.nx, false, &c->dv_line, &why);
+
+  size_t total = 0;
+  layout(c, c->full.host, c->slab.host, nullptr, &total);
+  char* base = nullptr;
+  if (workspace) {
+    if (workspace_bytes < total) {
+      delete c;
+      return fail(SSX_ERR_OOM, "workspace smaller than ssx_footprint()");
+    }
+    base = (char*)workspace;
+  } else {
+    if (hipMalloc((void**)&base, total) != hipSuccess) {
+      delete c;
+      (void)hipGetLastError();
+      return fail(SSX_ERR_OOM, "device allocation of the context failed");
+    }
+    c->own = base;
+  }
+  // align the base to 256 bytes
+  char* aligned = (char*)(((uintptr_t)base + 255) / 256 * 256);
+  layout(c, c->full.host, c->slab.host, aligned, &total);
+  ssx_status st = SSX_OK;
+  auto cleanup = [&]() {
+    if (c->own) (void)hipFree(c->own);
+    delete c;
+  };
+  if (hipMemsetAsync(aligned, 0, total - 256, c->stream) != hipSuccess ||
+      hipMemcpyAsync(c->xs_dev, xs_host, p.nshots * sizeof(double), hipMemcpyHostToDevice,
+                     c->stream) != hipSuccess) {
+    cleanup();
+    return fail(SSX_ERR_HIP, "context initialisation failed");
+  }
+  st = upload(c->full, c->fdt == Dt::F64, c->stream);
+  if (st == SSX_OK) st = upload(c->slab, c->fdt == Dt::F64, c->stream);
+  if (st != SSX_OK) {
+    cleanup();
+    return st;
+  }
+  *out = c;
+  return SSX_OK;
+}
+
+void ssx_destroy(ssx_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  if (c->own) (void)hipFree(c->own);
+  delete c;
+}
+
+ssx_status ssx_fwd(ssx_ctx* c, const void* h, void* d) {
+  if (!c || !h || !d) return fail(SSX_ERR_ARG, "null argument");
+  return do_fwd(c, h, d);
+}
+
+ssx_status ssx_adj(ssx_ctx* c, const void* r, void* g) {
+  if (!c || !r || !g) return fail(SSX_ERR_ARG, "null argument");
+  return do_adj(c, r, g);
+}
+
+ssx_status ssx_slab_fwd(ssx_ctx* c, const void* f, void* P, void* V) {
+  if (!c || !f || !P || !V) return fail(SSX_ERR_ARG, "null argument");
+  return do_slab_fwd(c, f, P, V);
+}
+
+ssx_status ssx_slab_adj(ssx_ctx* c, const void* a, const void* b, void* f) {
+  if (!c || !a || !b || !f) return fail(SSX_ERR_ARG, "null argument");
+  return do_slab_adj(c, a, b, f);
+}
+
+ssx_status ssx_penalty(ssx_ctx* c, int op, double a, const void* x, void* y) {
+  if (!c || !x || !y) return fail(SSX_ERR_ARG, "null argument");
+  if (op < SSX_PEN_A || op > SSX_PEN_DHALF) return fail(SSX_ERR_ARG, "unknown penalty op");
+  if (!std::isfinite(a)) return fail(SSX_ERR_ARG, "a must be finite");
+  const ssx_problem& p = c->prob;
+  SSX_HIP(launch_diag(c->vdbl, op, a, 1.0, x, y, p.nt, p.ns, p.nshots, p.x_src0, p.h, c->xs_dev,
+                      c->stream));
+  return SSX_OK;
+}
+
+ssx_status ssx_precond(ssx_ctx* c, double alpha_hat, const void* r, void* g) {
+  if (!c || !r || !g) return fail(SSX_ERR_ARG, "null argument");
+  if (!std::isfinite(alpha_hat)) return fail(SSX_ERR_ARG, "alpha_hat must be finite");
+  return do_precond(c, alpha_hat, r, g);
+}
+
+ssx_status ssx_normal(ssx_ctx* c, double alpha, const void* p, void* q, void* Fp) {
+  if (!c || !p || !q) return fail(SSX_ERR_ARG, "null argument");
+  if (!std::isfinite(alpha)) return fail(SSX_ERR_ARG, "alpha must be finite");
+  return do_normal(c, nullptr, alpha * alpha, p, q, Fp ? Fp : c->t2);
+}
+
+ssx_status ssx_dot(ssx_ctx* c, const void* x, const void* y, int64_t n, double* out_host) {
+  if (!c || !x || !y || !out_host || n < 0) return fail(SSX_ERR_ARG, "bad argument");
+  const int ns = c->prob.nshots;
+  SSX_HIP(launch_dot1(c->vdbl, x, y, n, ns, c->partial, c->sc + SC_TMP, SC_N, c->stream));
+  std::vector<double> tmp((size_t)ns * SC_N);
+  SSX_HIP(hipMemcpyAsync(tmp.data(), c->sc, tmp.size() * 8, hipMemcpyDeviceToHost, c->stream));
+  SSX_HIP(hipStreamSynchronize(c->stream));
+  for (int s = 0; s < ns; ++s) out_host[s] = tmp[(size_t)s * SC_N + SC_TMP];
+  return SSX_OK;
+}
+
+ssx_status ssx_pcg_solve(ssx_ctx* c, const void* d, double alpha_rel, int32_t maxit,
+                         double rtol, int32_t use_precond, void* h_out, double* hist_host,
+                         int32_t* iters_host) {
+  if (!c || !d || !h_out) return fail(SSX_ERR_ARG, "null argument");
+  if (maxit < 0 || maxit > HIST_CAP) return fail(SSX_ERR_ARG, "maxit out of range");
+  if (!std::isfinite(alpha_rel) || alpha_rel < 0) return fail(SSX_ERR_ARG, "alpha_rel must be >= 0");
+  const ssx_problem& p = c->prob;
+  hipStream_t s = c->stream;
+  const int ns = p.nshots;
+  const long long n = nvec_s(p), ne = nvec_r(p);
+  const size_t bs = (size_t)ns * n * c->vsz;
+  double* sc = c->sc;
+  double* hist = c->hist;
+  void* h = h_out;
+
+  SSX_HIP(launch_zero(h, bs, s));
+  SSX_TRY(do_adj(c, d, c->r));  // r_0 = F^T d
+  SSX_HIP(launch_dot1(c->vdbl, d, d, ne, ns, c->partial, sc + SC_DD, SC_N, s));
+  SSX_HIP(launch_dot1(c->vdbl, c->r, c->r, n, ns, c->partial, sc + SC_RR, SC_N, s));
+  SSX_HIP(launch_pcg_init(sc, alpha_rel, ns, s));
+  SSX_HIP(launch_neg_copy(c->vdbl, c->e, d, (long long)ns * ne, s));  // e_0 = F h_0 - d
+  auto apply_M = [&](const void* r, void* g) -> ssx_status {
+    if (use_precond) return do_precond(c, alpha_rel, r, g);
+    return copy_vec(c, g, r, bs);
+  };
+  SSX_TRY(apply_M(c->r, c->g));
+  SSX_TRY(copy_vec(c, c->p, c->g, bs));
+  if (maxit > 0) SSX_TRY(do_normal(c, sc + SC_ALPHA2, 0.0, c->p, c->q, c->Fp));
+  SSX_HIP(launch_dot3(c->vdbl, c->g, c->r, n, ns, c->partial, sc + SC_GRNEW, SC_N, s));
+  SSX_HIP(launch_dot1(c->vdbl, c->e, c->e, ne, ns, c->partial, sc + SC_EE, SC_N, s));
+  SSX_HIP(launch_pcg_record(sc, hist, 0, maxit, ns, s));
+  int iters = 0;
+  std::vector<double> hrow((size_t)ns * SC_N);
+  for (int k = 0; k < maxit; ++k) {
+    SSX_HIP(launch_dot1(c->vdbl, c->p, c->q, n, ns, c->partial, sc + SC_PQ, SC_N, s));
+    SSX_HIP(launch_pcg_step_length(sc, ns, s));
+    SSX_HIP(launch_pcg_update(c->vdbl, h, c->r, c->p, c->q, c->e, c->Fp, n, ne, sc, ns, s));
+    SSX_TRY(apply_M(c->r, c->g));
+    SSX_HIP(launch_dot3(c->vdbl, c->g, c->r, n, ns, c->partial, sc + SC_GRNEW, SC_N, s));
+    SSX_HIP(launch_dot1(c->vdbl, c->e, c->e, ne, ns, c->partial, sc + SC_EE, SC_N, s));
+    SSX_HIP(launch_pcg_record(sc, hist, k + 1, maxit, ns, s));
+    SSX_HIP(launch_pcg_dir(c->vdbl, c->p, c->g, n, sc, ns, s));
+    iters = k + 1;
+    bool stop = false;
+    if (rtol > 0) {
+      std::vector<double> rows((size_t)ns * 2);
+      for (int sh = 0; sh < ns; ++sh) {
+        SSX_HIP(hipMemcpyAsync(&rows[2 * sh], hist + ((size_t)sh * (maxit + 1) + 0) * 4, 8,
+                               hipMemcpyDeviceToHost, s));
+        SSX_HIP(hipMemcpyAsync(&rows[2 * sh + 1], hist + ((size_t)sh * (maxit + 1) + k + 1) * 4,
+                               8, hipMemcpyDeviceToHost, s));
+      }
+      SSX_HIP(hipStreamSynchronize(s));
+      stop = true;
+      for (int sh = 0; sh < ns; ++sh)
+        if (!(rows[2 * sh + 1] <= rtol * rows[2 * sh])) stop = false;
+    }
+    if (stop) break;
+    if (k < maxit - 1) SSX_TRY(do_normal(c, sc + SC_ALPHA2, 0.0, c->p, c->q, c->Fp));
+  }
+  SSX_HIP(hipMemcpyAsync(hrow.data(), sc, hrow.size() * 8, hipMemcpyDeviceToHost, s));
+  if (hist_host) {
+    for (int sh = 0; sh < ns; ++sh)
+      SSX_HIP(hipMemcpyAsync(hist_host + (size_t)sh * (maxit + 1) * 4,
+                             hist + (size_t)sh * (maxit + 1) * 4, (size_t)(maxit + 1) * 4 * 8,
+                             hipMemcpyDeviceToHost, s));
+  }
+  SSX_HIP(hipStreamSynchronize(s));
+  if (iters_host) *iters_host = iters;
+  int worst = 0;
+  for (int sh = 0; sh < ns; ++sh) worst |= (int)hrow[(size_t)sh * SC_N + SC_FLAG];
+  if (worst & 2) return fail(SSX_ERR_NONFINITE, "a non-finite PCG scalar appeared");
+  if (worst & 1) return fail(SSX_ERR_BREAKDOWN, "PCG breakdown: <g,r> or <p,q> zero or sign change");
+  return SSX_OK;
+}
+
+ssx_status ssx_set_graphs(ssx_ctx* c, int enable) {
+  if (!c) return fail(SSX_ERR_ARG, "null context");
+  c->graphs = enable != 0;
+  return SSX_OK;
+}
+
+const char* ssx_last_error(void) { return g_err.c_str(); }
+
+const char* ssx_step_kernel_name(ssx_ctx* c) {
+  (void)c;
+  return "k_pres";
+}
+
+int64_t ssx_cells_per_launch(ssx_ctx* c) {
+  if (!c) return 0;
+  return (int64_t)c->full.host.NZ * c->full.host.NX * c->prob.nshots;
+}
+
+}  // extern "C"

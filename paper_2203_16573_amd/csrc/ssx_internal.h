@@ -1,0 +1,130 @@
+// Internal declarations shared by the host API (ssx_api.cpp) and the HIP
+// kernels (ssx_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ssx {
+
+// Ghost cells around every stored field: always zero, never written, so the
+// stencils read "zero outside the grid" without bounds checks.  GX columns
+// (also keeps row starts 256-byte aligned for FP32) and GZ rows.
+constexpr int GX = 64;
+constexpr int GZ = 4;
+
+enum class Dt : int { F64 = 0, F32 = 1, F16 = 2, BF16 = 3 };
+
+// Geometry of one padded grid as the kernels see it.
+struct GridDims {
+  int NZ, NX;              // computational grid (physical + 2 L)
+  int L;                   // absorbing layer width (cells)
+  int pitch;               // row pitch of field arrays (elements)
+  long long field_stride;  // elements between consecutive shots of one field
+  long long origin;        // offset of element (0,0) from the array start
+};
+
+// A line that is sampled or injected: one or two grid rows with linear
+// interpolation weights, ntr consecutive columns.
+struct LineDev {
+  int row0, row1;   // row1 == row0 with w1 == 0 for a single row
+  double w0, w1;
+  int col0, ntr;
+};
+
+// Per-launch trace I/O: pointer to [shot][nt][ntr] traces, time index, and a
+// scale applied to the values (traces are V = double or float).
+struct TraceIO {
+  const void* in;   // injected traces (nullptr: none)
+  void* out;        // sampled traces (nullptr: none)
+  int n;            // time index (-1: nothing this launch)
+  long long shot_stride;  // nt * ntr
+  double scale;
+};
+
+struct Coef {
+  const void* ck;   // [NZ][NX] dt kappa / (h Z0), compute type
+  const void* pml;  // 8 arrays: ax_n bx_n ax_h bx_h [NX], az_n bz_n az_h bz_h [NZ]
+  double cb;        // Z0 dt / (rho h)
+};
+
+// Field pointers of one grid (all shots): main pressure, v_x, v_z and the
+// absorbing-layer auxiliary (forward: p_x; transpose: P~x - P~z).
+struct Fields {
+  void* p;
+  void* vx;
+  void* vz;
+  void* aux;
+};
+
+// ---- launchers (ssx_kernels.hip) -----------------------------------------
+// All return hipSuccess or the launch error.
+hipError_t launch_vel(Dt dt, int order, bool adj, const Fields& f, const GridDims& g,
+                      const Coef& c, const LineDev& samp_line, const TraceIO& samp,
+                      const LineDev& inj_line, const TraceIO& inj, int nshots,
+                      hipStream_t s);
+hipError_t launch_pres(Dt dt, int order, bool adj, const Fields& f, const GridDims& g,
+                       const Coef& c, const LineDev& samp_line, const TraceIO& samp,
+                       const LineDev& inj_line, const TraceIO& inj, int nshots,
+                       hipStream_t s);
+// sample a line of the main pressure field into traces (forward final step)
+hipError_t launch_sample_p(Dt dt, const Fields& f, const GridDims& g,
+                           const LineDev& line, const TraceIO& io, int nshots,
+                           hipStream_t s);
+// zero n bytes (multiple of 4) at ptr with a fill kernel (safe in graphs)
+hipError_t launch_zero(void* ptr, size_t bytes, hipStream_t s);
+
+// Vector kernels; V = double when vdbl, float otherwise.  n = elements per
+// shot; vectors of consecutive shots are n apart.
+// partial sums: grid (NBLK_DOT, nshots); then final reduction into out[shot*ostride + k].
+constexpr int NBLK_DOT = 256;
+hipError_t launch_dot3(bool vdbl, const void* x, const void* y, long long n, int nshots,
+                       double* partial /*[nshots][NBLK_DOT][3]*/, double* out,
+                       int ostride, hipStream_t s);
+// out[shot*ostride + 0] = sum x*y only (one product)
+hipError_t launch_dot1(bool vdbl, const void* x, const void* y, long long n, int nshots,
+                       double* partial, double* out, int ostride, hipStream_t s);
+
+// y[shot][t][k] = s * f(k, shot) * x   with f chosen by op:
+//   0: |xk - xs|, 1: |xk - xs|^2, 2: (1 + a^2 |xk-xs|^2)^(-1/2), 3: 1
+// xk = x0 + k h; xs per shot (device doubles).  scale_dev (optional) holds a
+// per-shot extra factor applied as well.
+hipError_t launch_diag(bool vdbl, int op, double a, double s, const void* x, void* y,
+                       long long nt, int ns, int nshots, double x0, double h,
+                       const double* xs_dev, hipStream_t st);
+// q += alpha2 * |xk - xs|^2 * p with alpha2 = alpha2_dev[shot*astride], or
+// alpha2_host when alpha2_dev is null
+hipError_t launch_add_penalty(bool vdbl, void* q, const void* p, const double* alpha2_dev,
+                              int astride, double alpha2_host, long long nt, int ns,
+                              int nshots, double x0, double h, const double* xs_dev,
+                              hipStream_t st);
+
+// PCG scalar block per shot (doubles), see ssx_api.cpp for the layout.
+constexpr int SC_N = 16;
+// SC_GRNEW, SC_GG, SC_RR are consecutive: they receive dot3(g, r) = (g.r, g.g, r.r).
+enum Sc { SC_GR = 0, SC_PQ = 1, SC_A = 2, SC_BETA = 3, SC_GRNEW = 4, SC_GG = 5, SC_RR = 6,
+          SC_EE = 7, SC_ALPHA2 = 8, SC_FLAG = 9, SC_GR0 = 10, SC_PQ0 = 11, SC_DD = 12,
+          SC_TMP = 15 };
+// SC_FLAG bits: 1 breakdown, 2 non-finite, 4 exact zero residual (converged)
+// a = gr / pq (with breakdown checks), per shot
+hipError_t launch_pcg_step_length(double* sc, int nshots, hipStream_t s);
+// h += a p; r -= a q (n per shot); e += a Fp (ne per shot, e may be null)
+hipError_t launch_pcg_update(bool vdbl, void* h, void* r, const void* p, const void* q,
+                             void* e, const void* Fp, long long n, long long ne,
+                             const double* sc, int nshots, hipStream_t s);
+// beta = grnew / gr; gr = grnew; record history row k (k = 0: start, sets gr0)
+hipError_t launch_pcg_record(double* sc, double* hist, int k, int maxit, int nshots,
+                             hipStream_t s);
+// p = g + beta p
+hipError_t launch_pcg_dir(bool vdbl, void* p, const void* g, long long n,
+                          const double* sc, int nshots, hipStream_t s);
+// alpha2 = (alpha_rel * sqrt(rr / dd))^2 from SC_RR = <r0,r0>, SC_DD = <d,d>;
+// clears flags and reference signs
+hipError_t launch_pcg_init(double* sc, double alpha_rel, int nshots, hipStream_t s);
+hipError_t launch_neg_copy(bool vdbl, void* y, const void* x, long long n, hipStream_t s);
+
+}  // namespace ssx

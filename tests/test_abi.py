@@ -1,0 +1,82 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry
+point declared in include/ssx.h, and validates problems without a GPU."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import inputs
+import paper_2203_16573_amd as ssx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "ssx.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ssx_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_declares_the_binding_exports():
+    assert set(declared_functions()) == set(ssx.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = ssx.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_validate_accepts_the_benchmark_configurations():
+    for c in (1, 2, 3):
+        wl = inputs.workload(c)
+        fd = "f64" if wl.dtype == "f64" else "f32"
+        ssx.validate(wl.prob, wl.kappa, wl.rho, field_dtype=fd)
+        assert ssx.footprint(wl.prob, field_dtype=fd) > 0
+
+
+@pytest.mark.parametrize("change,status", [
+    (dict(dt=6e-3), 2),                 # Courant number above the bound
+    (dict(order=6), 1),
+    (dict(z_src=-5.0), 1),              # line above the grid
+    (dict(z_rec=2010.0), 1),            # line below the grid
+    (dict(x_src0=15.0), 1),             # not on a grid column
+    (dict(ns=10_000), 1),
+    (dict(slab_dz=0), 1),
+    (dict(nt=0), 1),
+    (dict(npml=-1), 1),
+    (dict(nz=5), 1),
+])
+def test_validate_rejects(change, status):
+    wl = inputs.workload(1)
+    prob = wl.prob.replace(**change)
+    with pytest.raises(ssx.SSXError) as e:
+        kap = wl.kappa if prob.nz == wl.prob.nz else None
+        ssx.validate(prob, kap, wl.rho, field_dtype="f64")
+    assert e.value.status == status
+
+
+def test_validate_rejects_bad_models_and_dtypes():
+    wl = inputs.workload(1)
+    bad = wl.kappa.copy()
+    bad[3, 4] = np.nan
+    with pytest.raises(ssx.SSXError):
+        ssx.validate(wl.prob, bad, wl.rho, field_dtype="f64")
+    bad[3, 4] = -1.0
+    with pytest.raises(ssx.SSXError):
+        ssx.validate(wl.prob, bad, wl.rho, field_dtype="f64")
+    with pytest.raises(ssx.SSXError):
+        ssx.validate(wl.prob, wl.kappa, -1.0, field_dtype="f64")
+    P = ssx.make_problem(wl.prob, 1, "f32")
+    P.vec_dtype = 0  # F32 fields with F64 vectors is not a supported pair
+    import ctypes
+    assert ssx.lib().ssx_validate(ctypes.byref(P), None, 1000.0) == 1
+    assert ssx.lib().ssx_footprint(ctypes.byref(P)) == 0
+
+
+def test_footprint_scales_with_shots():
+    wl = inputs.workload(3)
+    one = ssx.footprint(wl.prob, nshots=1)
+    many = ssx.footprint(wl.prob, nshots=64)
+    assert 40 * one < many < 70 * one
