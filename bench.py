@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=12,
                     help="time steps of the oracle's bounded CPU sample")
     ap.add_argument("--graphs", type=int, default=1)
+    ap.add_argument("--prop-only", type=int, default=0,
+                    help="run this many forward+adjoint propagation pairs and exit "
+                         "(a short workload for kernel profiling)")
     return ap.parse_args()
 
 
@@ -82,6 +85,18 @@ def main():
     d = ctx.fwd(torch.tensor(htrue, dtype=vdt, device="cuda"), ctx.empty_r())
     h = ctx.empty_s()
     torch.cuda.synchronize()
+    if args.prop_only:
+        g = ctx.empty_s()
+        t0 = time.perf_counter()
+        for _ in range(args.prop_only):
+            ctx.adj(d, g)
+            ctx.fwd(g, d)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        print(json.dumps({"mode": "prop-only", "config": wl.name, "pairs": args.prop_only,
+                          "ms_per_propagation": 1e3 * el / (2 * args.prop_only)}), flush=True)
+        ctx.close()
+        return
 
     for _ in range(args.warmup):
         ctx.pcg_solve(d, wl.alpha_rel, wl.K, h=h)

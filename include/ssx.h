@@ -181,9 +181,23 @@ ssx_status ssx_pcg_solve(ssx_ctx* ctx, const void* d, double alpha_rel, int32_t 
                          double rtol, int32_t use_precond, void* h_out,
                          double* hist_host, int32_t* iters_host);
 
-/* Use captured HIP graphs for whole propagations (enable != 0, default) or
- * plain stream launches (enable == 0).  Results are identical. */
-ssx_status ssx_set_graphs(ssx_ctx* ctx, int enable);
+/* Execution options (results do not depend on them, see each value):
+ *   SSX_OPT_GRAPHS      1 (default): replay each whole propagation as a
+ *                       captured HIP graph; 0: plain stream launches.
+ *   SSX_OPT_STEP_KERNEL 1 (default): one fused launch per time step
+ *                       (velocity and pressure on an LDS-staged tile);
+ *                       0: one velocity and one pressure launch per step.
+ *   SSX_OPT_TILE_Z      tile height of the fused kernel: 8, 16 or 32 (32
+ *                       not for F64 fields); 0 picks a default.
+ *   SSX_OPT_STEPS_PER_LAUNCH  time steps fused per launch (1 or 2).
+ * Returns SSX_ERR_ARG for an unknown option or value. */
+typedef enum {
+  SSX_OPT_GRAPHS = 0,
+  SSX_OPT_STEP_KERNEL = 1,
+  SSX_OPT_TILE_Z = 2,
+  SSX_OPT_STEPS_PER_LAUNCH = 3
+} ssx_option;
+ssx_status ssx_set_option(ssx_ctx* ctx, int option, int value);
 
 /* Message for the last error on the calling thread ("" if none). */
 const char* ssx_last_error(void);

@@ -32,13 +32,14 @@ LIB_PATH = os.path.join(_HERE, "libssx.so")
 
 DTYPES = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 PEN_A, PEN_ATA, PEN_DHALF = 0, 1, 2
+OPT_GRAPHS, OPT_STEP_KERNEL, OPT_TILE_Z, OPT_STEPS_PER_LAUNCH = 0, 1, 2, 3
 
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_CFL", 3: "ERR_OOM", 4: "ERR_HIP",
           5: "ERR_BREAKDOWN", 6: "ERR_NONFINITE"}
 
 EXPORTS = ("ssx_validate", "ssx_footprint", "ssx_create", "ssx_destroy", "ssx_fwd",
            "ssx_adj", "ssx_slab_fwd", "ssx_slab_adj", "ssx_penalty", "ssx_precond",
-           "ssx_normal", "ssx_dot", "ssx_pcg_solve", "ssx_set_graphs", "ssx_last_error",
+           "ssx_normal", "ssx_dot", "ssx_pcg_solve", "ssx_set_option", "ssx_last_error",
            "ssx_step_kernel_name", "ssx_cells_per_launch")
 
 
@@ -93,7 +94,7 @@ def lib():
         L.ssx_dot.argtypes = [vp, vp, vp, ctypes.c_int64, dp]
         L.ssx_pcg_solve.argtypes = [vp, vp, c_dbl, ctypes.c_int32, c_dbl, ctypes.c_int32,
                                     vp, dp, ctypes.POINTER(ctypes.c_int32)]
-        L.ssx_set_graphs.argtypes = [vp, c_int]
+        L.ssx_set_option.argtypes = [vp, c_int, c_int]
         L.ssx_last_error.restype = ctypes.c_char_p
         L.ssx_step_kernel_name.argtypes = [vp]
         L.ssx_step_kernel_name.restype = ctypes.c_char_p
@@ -249,8 +250,11 @@ class Context:
             _check(st)
         return h, hist[:, : it.value + 1], it.value, st
 
+    def set_option(self, option: int, value: int):
+        _check(lib().ssx_set_option(self._ctx, int(option), int(value)))
+
     def set_graphs(self, enable: bool):
-        _check(lib().ssx_set_graphs(self._ctx, int(bool(enable))))
+        self.set_option(OPT_GRAPHS, int(bool(enable)))
 
     def step_kernel_name(self) -> str:
         return lib().ssx_step_kernel_name(self._ctx).decode()

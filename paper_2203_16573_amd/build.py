@@ -18,6 +18,9 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950",
     # packed FP32 instructions are disabled for all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit contraction: every kernel variant evaluates the same
+    # explicitly written fused multiply-adds
+    "-ffp-contract=off",
     "-Wall", "-Wno-unused-result",
 ]
 

@@ -238,9 +238,20 @@ struct GridDev {
   GridHost host;
   GridDims dims;
   Coef coef;
-  Fields fields;
+  Fields fields;   // buffer 0 (also the in-place buffer of the split kernels)
+  Fields fields1;  // buffer 1 (fused kernel writes step n+1 here, then swaps)
   void* field_block;
   size_t field_bytes;
+};
+
+// A captured propagation: keyed by the operation and every trace pointer it
+// reads or writes, so replays are exact re-runs of the captured launches.
+struct GraphEntry {
+  int op;
+  const void* ptr[4];
+  int tile_z, fused;
+  hipGraphExec_t exec;
+  unsigned long long last_use;
 };
 
 struct ssx_ctx {
@@ -259,8 +270,15 @@ struct ssx_ctx {
   double* sc;
   double* partial;
   double* hist;
+  float* dyn;          // [nshots] field scale of the current propagation (16-bit fields)
+  float* amax_part;    // [2][nshots][NBLK_DOT]
   void* own = nullptr;  // device block allocated by the library (null if workspace)
   bool graphs = true;
+  bool fused = true;
+  int tile_z_full = 0, tile_z_slab = 0;  // 0: default
+  hipStream_t cap_stream = nullptr;      // capture stream (graphs are launched on `stream`)
+  std::vector<GraphEntry> graphs_cache;
+  unsigned long long use_clock = 0;
 };
 
 namespace {
@@ -278,7 +296,7 @@ void layout(ssx_ctx* c, const GridHost& fg, const GridHost& sg, char* base, size
   const size_t csz = p.field_dtype == SSX_F64 ? 8 : 4;
   const size_t vsz = dtype_size(p.vec_dtype);
   auto grid = [&](GridDev& gd, const GridHost& gh) {
-    gd.field_bytes = 4 * (size_t)ns * gh.field_elems * fsz;
+    gd.field_bytes = 8 * (size_t)ns * gh.field_elems * fsz;
     gd.field_block = a.take(gd.field_bytes);
     char* fb = (char*)gd.field_block;
     const size_t one = (size_t)ns * gh.field_elems * fsz;
@@ -286,6 +304,10 @@ void layout(ssx_ctx* c, const GridHost& fg, const GridHost& sg, char* base, size
     gd.fields.vx = fb ? fb + one : nullptr;
     gd.fields.vz = fb ? fb + 2 * one : nullptr;
     gd.fields.aux = fb ? fb + 3 * one : nullptr;
+    gd.fields1.p = fb ? fb + 4 * one : nullptr;
+    gd.fields1.vx = fb ? fb + 5 * one : nullptr;
+    gd.fields1.vz = fb ? fb + 6 * one : nullptr;
+    gd.fields1.aux = fb ? fb + 7 * one : nullptr;
     gd.coef.ck = a.take((size_t)gh.NZ * gh.NX * csz);
     gd.coef.pml = a.take(gh.pml.size() * csz);
   };
@@ -300,6 +322,8 @@ void layout(ssx_ctx* c, const GridHost& fg, const GridHost& sg, char* base, size
   c->sc = (double*)a.take((size_t)ns * SC_N * 8);
   c->partial = (double*)a.take((size_t)ns * NBLK_DOT * 3 * 8);
   c->hist = (double*)a.take((size_t)ns * (HIST_CAP + 1) * 4 * 8);
+  c->dyn = (float*)a.take((size_t)ns * 4);
+  c->amax_part = (float*)a.take((size_t)2 * ns * NBLK_DOT * 4);
   *total = a.off + 256;
 }
 
@@ -343,6 +367,7 @@ TraceIO io_none() {
   t.n = -1;
   t.shot_stride = 0;
   t.scale = 1.0;
+  t.dyn = nullptr;
   return t;
 }
 TraceIO io_in(const void* in, long long stride, double scale) {
@@ -360,80 +385,215 @@ TraceIO io_out(void* out, long long stride, double scale) {
   return t;
 }
 
-// One propagation over nt steps.
-//   vs: sampled by the velocity launch (a pressure line)
-//   vi: injected by the velocity launch (a v_z line)
-//   ps: sampled by the pressure launch (a v_z line)
-//   pi: injected by the pressure launch (a pressure line)
+int default_tile_z(const ssx_ctx* c, const GridDev& gd) {
+  // enough tiles to fill 256 CUs several times over, else shorter tiles
+  const long long tiles32 = (long long)((gd.host.NX + 63) / 64) * ((gd.host.NZ + 31) / 32) *
+                            c->prob.nshots;
+  if (c->fdt == Dt::F64) return tiles32 >= 1024 ? 16 : 8;
+  if (tiles32 >= 1024) return 32;
+  return tiles32 >= 256 ? 16 : 8;
+}
+
+// One propagation over nt steps, issued on stream s.
+//   vs: sampled by the velocity phase (a pressure line)
+//   vi: injected by the velocity phase (a v_z line)
+//   ps: sampled by the pressure phase (a v_z line)
+//   pi: injected by the pressure phase (a pressure line)
 // Forward: step n samples vs at n-1 (p^n), injects vi[n], samples ps[n]
 // (v^{n+1/2}), injects pi[n]; a last launch samples vs at nt-1.
 // Transpose: pi[nt-1] enters first; step n (descending) samples vs[n]
 // (the transposed pressure after sample n of the adjoint input entered),
 // injects vi[n], samples ps[n] and injects pi[n-1].
-ssx_status propagate(ssx_ctx* c, GridDev& gd, bool adj, const LineDev& vsl, TraceIO vs,
-                     const LineDev& vil, TraceIO vi, const LineDev& psl, TraceIO ps,
-                     const LineDev& pil, TraceIO pi) {
+ssx_status issue_propagation(ssx_ctx* c, GridDev& gd, bool adj, const LineDev& vsl, TraceIO vs,
+                             const LineDev& vil, TraceIO vi, const LineDev& psl, TraceIO ps,
+                             const LineDev& pil, TraceIO pi, hipStream_t s) {
   const int nt = c->prob.nt, ns = c->prob.nshots, order = c->prob.order;
-  hipStream_t s = c->stream;
   SSX_HIP(launch_zero(gd.field_block, gd.field_bytes, s));
-  if (!adj) {
-    for (int n = 0; n < nt; ++n) {
-      vs.n = (vs.out && n >= 1) ? n - 1 : -1;
-      vi.n = vi.in ? n : -1;
-      SSX_HIP(launch_vel(c->fdt, order, false, gd.fields, gd.dims, gd.coef, vsl, vs, vil, vi,
-                         ns, s));
-      ps.n = ps.out ? n : -1;
-      pi.n = pi.in ? n : -1;
-      SSX_HIP(launch_pres(c->fdt, order, false, gd.fields, gd.dims, gd.coef, psl, ps, pil, pi,
-                          ns, s));
+  if (c->fsz == 2) {
+    // 16-bit fields: normalise the injected traces per shot by a power of two
+    const void* ia = pi.in ? pi.in : vi.in;
+    const double sa = pi.in ? pi.scale : vi.scale;
+    const void* ib = (pi.in && vi.in) ? vi.in : nullptr;
+    const long long nin = (pi.in ? pi.shot_stride : vi.shot_stride);
+    if (ia) {
+      if (ib && vi.shot_stride != nin) return fail(SSX_ERR_ARG, "mismatched trace inputs");
+      SSX_HIP(launch_field_scale(c->vdbl, ia, sa, ib, vi.scale, nin, ns, c->amax_part, c->dyn, s));
+      vs.dyn = vi.dyn = ps.dyn = pi.dyn = c->dyn;
     }
-    if (vs.out) {
-      vs.n = nt - 1;
-      SSX_HIP(launch_sample_p(c->fdt, gd.fields, gd.dims, vsl, vs, ns, s));
-    }
-  } else {
-    {
+  }
+  if (!c->fused) {
+    if (!adj) {
+      for (int n = 0; n < nt; ++n) {
+        vs.n = (vs.out && n >= 1) ? n - 1 : -1;
+        vi.n = vi.in ? n : -1;
+        SSX_HIP(launch_vel(c->fdt, order, false, gd.fields, gd.dims, gd.coef, vsl, vs, vil, vi,
+                           ns, s));
+        ps.n = ps.out ? n : -1;
+        pi.n = pi.in ? n : -1;
+        SSX_HIP(launch_pres(c->fdt, order, false, gd.fields, gd.dims, gd.coef, psl, ps, pil, pi,
+                            ns, s));
+      }
+      if (vs.out) {
+        vs.n = nt - 1;
+        SSX_HIP(launch_sample_p(c->fdt, gd.fields, gd.dims, vsl, vs, ns, s));
+      }
+    } else {
       TraceIO none = io_none();
       pi.n = pi.in ? nt - 1 : -1;
       SSX_HIP(launch_pres(c->fdt, order, true, gd.fields, gd.dims, gd.coef, psl, none, pil, pi,
                           ns, s));
+      for (int n = nt - 1; n >= 0; --n) {
+        vs.n = vs.out ? n : -1;
+        vi.n = vi.in ? n : -1;
+        SSX_HIP(launch_vel(c->fdt, order, true, gd.fields, gd.dims, gd.coef, vsl, vs, vil, vi,
+                           ns, s));
+        ps.n = ps.out ? n : -1;
+        pi.n = (pi.in && n >= 1) ? n - 1 : -1;
+        SSX_HIP(launch_pres(c->fdt, order, true, gd.fields, gd.dims, gd.coef, psl, ps, pil, pi,
+                            ns, s));
+      }
     }
+    return SSX_OK;
+  }
+  // fused: one launch per step, ping-pong between the two field buffers
+  const int tz_opt = (&gd == &c->full) ? c->tile_z_full : c->tile_z_slab;
+  const int tz = tz_opt ? tz_opt : default_tile_z(c, gd);
+  StepArgs a;
+  a.g = gd.dims;
+  a.c = gd.coef;
+  a.vsl = vsl;
+  a.vil = vil;
+  a.psl = psl;
+  a.pil = pil;
+  a.ntx = (gd.host.NX + step_tile_width() - 1) / step_tile_width();
+  a.ntz = (gd.host.NZ + tz - 1) / tz;
+  a.nshots = ns;
+  Fields buf[2] = {gd.fields, gd.fields1};
+  int cur = 0;
+  if (!adj) {
+    for (int n = 0; n < nt; ++n) {
+      a.in = buf[cur];
+      a.out = buf[1 - cur];
+      a.vs = vs;
+      a.vs.n = (vs.out && n >= 1) ? n - 1 : -1;
+      a.vi = vi;
+      a.vi.n = vi.in ? n : -1;
+      a.ps = ps;
+      a.ps.n = ps.out ? n : -1;
+      a.pi = pi;
+      a.pi.n = pi.in ? n : -1;
+      SSX_HIP(launch_step(c->fdt, order, false, tz, a, s));
+      cur = 1 - cur;
+    }
+    if (vs.out) {
+      vs.n = nt - 1;
+      SSX_HIP(launch_sample_p(c->fdt, buf[cur], gd.dims, vsl, vs, ns, s));
+    }
+  } else {
+    TraceIO none = io_none();
+    TraceIO p0 = pi;
+    p0.n = pi.in ? nt - 1 : -1;
+    SSX_HIP(launch_pres(c->fdt, order, true, buf[0], gd.dims, gd.coef, psl, none, pil, p0, ns, s));
     for (int n = nt - 1; n >= 0; --n) {
-      vs.n = vs.out ? n : -1;
-      vi.n = vi.in ? n : -1;
-      SSX_HIP(launch_vel(c->fdt, order, true, gd.fields, gd.dims, gd.coef, vsl, vs, vil, vi, ns,
-                         s));
-      ps.n = ps.out ? n : -1;
-      pi.n = (pi.in && n >= 1) ? n - 1 : -1;
-      SSX_HIP(launch_pres(c->fdt, order, true, gd.fields, gd.dims, gd.coef, psl, ps, pil, pi,
-                          ns, s));
+      a.in = buf[cur];
+      a.out = buf[1 - cur];
+      a.vs = vs;
+      a.vs.n = vs.out ? n : -1;
+      a.vi = vi;
+      a.vi.n = vi.in ? n : -1;
+      a.ps = ps;
+      a.ps.n = ps.out ? n : -1;
+      a.pi = pi;
+      a.pi.n = (pi.in && n >= 1) ? n - 1 : -1;
+      SSX_HIP(launch_step(c->fdt, order, true, tz, a, s));
+      cur = 1 - cur;
     }
   }
   return SSX_OK;
 }
 
+constexpr size_t GRAPH_CACHE_MAX = 12;
+
+// Runs a propagation: replays a cached graph for (op, pointers) when graphs
+// are enabled (capturing it on first use), else issues the launches.
+ssx_status propagate(ssx_ctx* c, int op, GridDev& gd, bool adj, const LineDev& vsl, TraceIO vs,
+                     const LineDev& vil, TraceIO vi, const LineDev& psl, TraceIO ps,
+                     const LineDev& pil, TraceIO pi) {
+  if (!c->graphs)
+    return issue_propagation(c, gd, adj, vsl, vs, vil, vi, psl, ps, pil, pi, c->stream);
+  const void* key[4] = {vs.out, vi.in, ps.out, pi.in};
+  const int tz = (&gd == &c->full) ? c->tile_z_full : c->tile_z_slab;
+  for (GraphEntry& e : c->graphs_cache) {
+    if (e.op == op && e.ptr[0] == key[0] && e.ptr[1] == key[1] && e.ptr[2] == key[2] &&
+        e.ptr[3] == key[3] && e.tile_z == tz && e.fused == (int)c->fused) {
+      e.last_use = ++c->use_clock;
+      SSX_HIP(hipGraphLaunch(e.exec, c->stream));
+      return SSX_OK;
+    }
+  }
+  if (!c->cap_stream) SSX_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  SSX_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  ssx_status st = issue_propagation(c, gd, adj, vsl, vs, vil, vi, psl, ps, pil, pi, c->cap_stream);
+  hipGraph_t graph = nullptr;
+  hipError_t e1 = hipStreamEndCapture(c->cap_stream, &graph);
+  if (st != SSX_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  SSX_HIP(e1);
+  hipGraphExec_t exec = nullptr;
+  hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  SSX_HIP(e2);
+  if (c->graphs_cache.size() >= GRAPH_CACHE_MAX) {
+    auto lru = std::min_element(c->graphs_cache.begin(), c->graphs_cache.end(),
+                                [](const GraphEntry& x, const GraphEntry& y) {
+                                  return x.last_use < y.last_use;
+                                });
+    (void)hipGraphExecDestroy(lru->exec);
+    c->graphs_cache.erase(lru);
+  }
+  GraphEntry ge;
+  ge.op = op;
+  for (int i = 0; i < 4; ++i) ge.ptr[i] = key[i];
+  ge.tile_z = tz;
+  ge.fused = (int)c->fused;
+  ge.exec = exec;
+  ge.last_use = ++c->use_clock;
+  c->graphs_cache.push_back(ge);
+  SSX_HIP(hipGraphLaunch(exec, c->stream));
+  return SSX_OK;
+}
+
+void drop_graphs(ssx_ctx* c) {
+  for (GraphEntry& e : c->graphs_cache) (void)hipGraphExecDestroy(e.exec);
+  c->graphs_cache.clear();
+}
+
+enum { OP_FWD = 0, OP_ADJ = 1, OP_SLAB_FWD = 2, OP_SLAB_ADJ = 3 };
+
 ssx_status do_fwd(ssx_ctx* c, const void* h, void* d) {
   const ssx_problem& p = c->prob;
-  return propagate(c, c->full, false, c->r_line, io_out(d, nvec_r(p), c->Z0), c->r_line,
+  return propagate(c, OP_FWD, c->full, false, c->r_line, io_out(d, nvec_r(p), c->Z0), c->r_line,
                    io_none(), c->r_line, io_none(), c->h_line, io_in(h, nvec_s(p), 1.0));
 }
 
 ssx_status do_adj(ssx_ctx* c, const void* r, void* g) {
   const ssx_problem& p = c->prob;
-  return propagate(c, c->full, true, c->h_line, io_out(g, nvec_s(p), 1.0), c->h_line,
+  return propagate(c, OP_ADJ, c->full, true, c->h_line, io_out(g, nvec_s(p), 1.0), c->h_line,
                    io_none(), c->h_line, io_none(), c->r_line, io_in(r, nvec_r(p), c->Z0));
 }
 
 ssx_status do_slab_fwd(ssx_ctx* c, const void* f, void* P, void* V) {
   const long long st = nvec_s(c->prob);
-  return propagate(c, c->slab, false, c->dp_line, io_out(P, st, c->Z0), c->f_line,
+  return propagate(c, OP_SLAB_FWD, c->slab, false, c->dp_line, io_out(P, st, c->Z0), c->f_line,
                    io_in(f, st, 1.0 / c->Z0), c->dv_line, io_out(V, st, 1.0), c->dp_line,
                    io_none());
 }
 
 ssx_status do_slab_adj(ssx_ctx* c, const void* a, const void* b, void* f) {
   const long long st = nvec_s(c->prob);
-  return propagate(c, c->slab, true, c->dp_line, io_none(), c->dv_line, io_in(b, st, 1.0),
+  return propagate(c, OP_SLAB_ADJ, c->slab, true, c->dp_line, io_none(), c->dv_line, io_in(b, st, 1.0),
                    c->f_line, io_out(f, st, 1.0 / c->Z0), c->dp_line, io_in(a, st, c->Z0));
 }
 
@@ -599,6 +759,8 @@ ssx_status ssx_create(const ssx_problem* prob, const double* kappa_host, double 
 void ssx_destroy(ssx_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  drop_graphs(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->own) (void)hipFree(c->own);
   delete c;
 }
@@ -732,17 +894,35 @@ ssx_status ssx_pcg_solve(ssx_ctx* c, const void* d, double alpha_rel, int32_t ma
   return SSX_OK;
 }
 
-ssx_status ssx_set_graphs(ssx_ctx* c, int enable) {
+ssx_status ssx_set_option(ssx_ctx* c, int option, int value) {
   if (!c) return fail(SSX_ERR_ARG, "null context");
-  c->graphs = enable != 0;
-  return SSX_OK;
+  switch (option) {
+    case SSX_OPT_GRAPHS:
+      c->graphs = value != 0;
+      return SSX_OK;
+    case SSX_OPT_STEP_KERNEL:
+      if (value != 0 && value != 1) return fail(SSX_ERR_ARG, "step kernel must be 0 or 1");
+      c->fused = value == 1;
+      return SSX_OK;
+    case SSX_OPT_TILE_Z:
+      if (value != 0 && value != 8 && value != 16 && value != 32)
+        return fail(SSX_ERR_ARG, "tile height must be 0, 8, 16 or 32");
+      if (value == 32 && c->fdt == Dt::F64)
+        return fail(SSX_ERR_ARG, "tile height 32 is not available for F64 fields");
+      c->tile_z_full = c->tile_z_slab = value;
+      return SSX_OK;
+    case SSX_OPT_STEPS_PER_LAUNCH:
+      if (value != 1) return fail(SSX_ERR_ARG, "steps per launch must be 1");
+      return SSX_OK;
+  }
+  return fail(SSX_ERR_ARG, "unknown option");
 }
 
 const char* ssx_last_error(void) { return g_err.c_str(); }
 
 const char* ssx_step_kernel_name(ssx_ctx* c) {
-  (void)c;
-  return "k_pres";
+  if (c && !c->fused) return "k_vel + k_pres";
+  return "k_step";
 }
 
 int64_t ssx_cells_per_launch(ssx_ctx* c) {

@@ -44,6 +44,9 @@ struct TraceIO {
   int n;            // time index (-1: nothing this launch)
   long long shot_stride;  // nt * ntr
   double scale;
+  // per-shot power-of-two field scale (nullptr: 1): injections are divided
+  // by dyn[shot], samples multiplied by it (keeps 16-bit fields in range)
+  const float* dyn;
 };
 
 struct Coef {
@@ -61,7 +64,22 @@ struct Fields {
   void* aux;
 };
 
+// Everything one fused time-step launch needs: fields at step n (in) and
+// n+1 (out), the grid, coefficients and the four line I/O slots.
+struct StepArgs {
+  Fields in, out;
+  GridDims g;
+  Coef c;
+  LineDev vsl, vil, psl, pil;  // velocity-phase sample/inject, pressure-phase sample/inject
+  TraceIO vs, vi, ps, pi;
+  int ntx, ntz, nshots;        // tiles across x, down z; shots
+};
+
 // ---- launchers (ssx_kernels.hip) -----------------------------------------
+// One fused time step (velocity then pressure, one launch).  tz: tile height
+// (8, 16 or 32; 32 is not available for FP64 fields).
+hipError_t launch_step(Dt dt, int order, bool adj, int tz, StepArgs a, hipStream_t s);
+int step_tile_width();
 // All return hipSuccess or the launch error.
 hipError_t launch_vel(Dt dt, int order, bool adj, const Fields& f, const GridDims& g,
                       const Coef& c, const LineDev& samp_line, const TraceIO& samp,
@@ -126,5 +144,11 @@ hipError_t launch_pcg_dir(bool vdbl, void* p, const void* g, long long n,
 // clears flags and reference signs
 hipError_t launch_pcg_init(double* sc, double alpha_rel, int nshots, hipStream_t s);
 hipError_t launch_neg_copy(bool vdbl, void* y, const void* x, long long n, hipStream_t s);
+
+// dyn[shot] = smallest power of two >= max(sa * max|a[shot]|, sb * max|b[shot]|)
+// (1 when both are zero); b may be null.  partial: [2][nshots][NBLK_DOT] floats.
+hipError_t launch_field_scale(bool vdbl, const void* a, double sa, const void* b, double sb,
+                              long long n, int nshots, float* partial, float* dyn,
+                              hipStream_t s);
 
 }  // namespace ssx

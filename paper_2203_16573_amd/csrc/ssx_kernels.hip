@@ -45,6 +45,16 @@ __device__ __forceinline__ void stc(double* p, double v) { *p = v; }
 __device__ __forceinline__ void stc(float* p, float v) { *p = v; }
 __device__ __forceinline__ void stc(__half* p, float v) { *p = __float2half(v); }
 __device__ __forceinline__ void stc(__hip_bfloat16* p, float v) { *p = __float2bfloat16(v); }
+// value as it will read back after a store to T
+template <typename T, typename C> __device__ __forceinline__ C rnd(C v) {
+  if constexpr (sizeof(T) == sizeof(C)) {
+    return v;
+  } else {
+    T t;
+    stc(&t, v);
+    return ldc<C>(&t);
+  }
+}
 
 // Staggered first-derivative weights c_1..c_K (Taylor / Fornberg).
 template <int K, typename C> __device__ __forceinline__ C wst(int m) {
@@ -58,7 +68,52 @@ template <int K, typename C> __device__ __forceinline__ C wst(int m) {
   }
 }
 
+// Per-cell update formulas, shared by every kernel variant so that all of
+// them evaluate exactly the same expression (the library is built with
+// -ffp-contract=off; fused multiply-adds are written out).
+__device__ __forceinline__ float fmac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmac(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// stencil difference accumulator: s + w * (hi - lo)
+template <typename C> __device__ __forceinline__ C acc(C s, C w, C hi, C lo) {
+  return fmac(w, hi - lo, s);
+}
+// velocity: a v + b cb (sgn * sum + src)
+template <bool ADJ, typename C>
+__device__ __forceinline__ C upd_v(C a, C b, C cb, C old, C sum, C src) {
+  const C r = ADJ ? (sum + src) : (src - sum);
+  return fmac(a, old, (b * cb) * r);
+}
+// pressure away from the absorbing frame
+template <bool ADJ, typename C>
+__device__ __forceinline__ C upd_p(C ck, C p, C dx, C dz, C src) {
+  const C r = ADJ ? ((dx + dz) + src) : (src - (dx + dz));
+  return fmac(ck, r, p);
+}
+// pressure in the frame; aux: forward p_x, transpose P~_x - P~_z
+template <bool ADJ, typename C>
+__device__ __forceinline__ C upd_p_frame(C ck, C p, C aux, C dx, C dz, C src, C axn, C bxn,
+                                         C azn, C bzn, C* aux_new) {
+  if constexpr (!ADJ) {
+    const C px = fmac(axn, aux, -((bxn * ck) * dx));
+    const C pz = fmac(azn, p - aux, (bzn * ck) * (src - dz));
+    *aux_new = px;
+    return px + pz;
+  } else {
+    const C t = (dx + dz) + src;
+    const C Px = fmac(axn, p + aux, (bxn * ck) * t);
+    const C Pz = fmac(azn, p, (bzn * ck) * t);
+    *aux_new = Px - Pz;
+    return Pz;
+  }
+}
+
 constexpr int TBX = 64;  // one wavefront across x
+
+template <typename C>
+__device__ __forceinline__ C dyn_of(const TraceIO& t, int shot) {
+  return t.dyn ? C(t.dyn[shot]) : C(1);
+}
 constexpr int TBY = 4;
 
 // ---------------------------------------------------------------------------
@@ -86,39 +141,42 @@ __global__ __launch_bounds__(TBX* TBY) void k_vel(Fields f, GridDims g, Coef cf,
     const C val = C(sl.w0) * ldc<C>(p + o) + C(sl.w1) * ldc<C>(p + (long long)sl.row1 * P + J);
     V* out = static_cast<V*>(so.out) + shot * so.shot_stride + (long long)so.n * sl.ntr +
              (J - sl.col0);
-    *out = V(C(so.scale) * val);
+    *out = V(C(so.scale) * val * dyn_of<C>(so, shot));
   }
 
   C sx = C(0);
+  bool split_x = false;
+  if constexpr (ADJ) split_x = I < g.L || I >= g.NZ - g.L || J < g.L + K || J >= g.NX - g.L - K;
+  if (!split_x) {
 #pragma unroll
-  for (int m = 1; m <= K; ++m) sx += wst<K, C>(m - 1) * (ldc<C>(p + o + m) - ldc<C>(p + o + 1 - m));
-  if constexpr (ADJ) {
-    // x-split part of the transposed pressure, nonzero only in the frame
-    if (I < g.L || I >= g.NZ - g.L || J < g.L + K || J >= g.NX - g.L - K) {
-      const T* __restrict__ ax = static_cast<const T*>(f.aux) + base;
+    for (int m = 1; m <= K; ++m)
+      sx = acc(sx, wst<K, C>(m - 1), ldc<C>(p + o + m), ldc<C>(p + o + 1 - m));
+  } else {
+    // transposed x-split pressure P~_x = P~_z + aux, nonzero aux only in the frame
+    const T* __restrict__ ax = static_cast<const T*>(f.aux) + base;
 #pragma unroll
-      for (int m = 1; m <= K; ++m)
-        sx += wst<K, C>(m - 1) * (ldc<C>(ax + o + m) - ldc<C>(ax + o + 1 - m));
-    }
+    for (int m = 1; m <= K; ++m)
+      sx = acc(sx, wst<K, C>(m - 1), ldc<C>(p + o + m) + ldc<C>(ax + o + m),
+               ldc<C>(p + o + 1 - m) + ldc<C>(ax + o + 1 - m));
   }
-  constexpr C sgn = ADJ ? C(1) : C(-1);
   const int NX = g.NX, NZ = g.NZ;
-  const C vxn = pml[2 * NX + J] * ldc<C>(vx + o) + pml[3 * NX + J] * cb * (sgn * sx);
+  const C vxn = upd_v<ADJ>(pml[2 * NX + J], pml[3 * NX + J], cb, ldc<C>(vx + o), sx, C(0));
   stc(vx + o, vxn);
 
   C sz = C(0);
 #pragma unroll
   for (int m = 1; m <= K; ++m)
-    sz += wst<K, C>(m - 1) * (ldc<C>(p + o + (long long)m * P) - ldc<C>(p + o + (long long)(1 - m) * P));
+    sz = acc(sz, wst<K, C>(m - 1), ldc<C>(p + o + (long long)m * P),
+             ldc<C>(p + o + (long long)(1 - m) * P));
   C src = C(0);
   if (io.n >= 0 && (I == il.row0 || I == il.row1) && J >= il.col0 && J < il.col0 + il.ntr) {
     const C w = (I == il.row0 ? C(il.w0) : C(0)) + (I == il.row1 ? C(il.w1) : C(0));
     const V* in = static_cast<const V*>(io.in) + shot * io.shot_stride + (long long)io.n * il.ntr +
                   (J - il.col0);
-    src = w * (C(io.scale) * C(*in));
+    src = w * (C(io.scale) * C(*in) / dyn_of<C>(io, shot));
   }
-  const C vzn = pml[4 * NX + 2 * NZ + I] * ldc<C>(vz + o) +
-                pml[4 * NX + 3 * NZ + I] * cb * (sgn * sz + src);
+  const C vzn = upd_v<ADJ>(pml[4 * NX + 2 * NZ + I], pml[4 * NX + 3 * NZ + I], cb,
+                          ldc<C>(vz + o), sz, src);
   stc(vz + o, vzn);
 }
 
@@ -147,22 +205,22 @@ __global__ __launch_bounds__(TBX* TBY) void k_pres(Fields f, GridDims g, Coef cf
         C(sl.w0) * ldc<C>(vz + o) + C(sl.w1) * ldc<C>(vz + (long long)sl.row1 * P + J);
     V* out = static_cast<V*>(so.out) + shot * so.shot_stride + (long long)so.n * sl.ntr +
              (J - sl.col0);
-    *out = V(C(so.scale) * val);
+    *out = V(C(so.scale) * val * dyn_of<C>(so, shot));
   }
 
   C dx = C(0), dz = C(0);
 #pragma unroll
   for (int m = 1; m <= K; ++m) {
-    dx += wst<K, C>(m - 1) * (ldc<C>(vx + o + m - 1) - ldc<C>(vx + o - m));
-    dz += wst<K, C>(m - 1) *
-          (ldc<C>(vz + o + (long long)(m - 1) * P) - ldc<C>(vz + o - (long long)m * P));
+    dx = acc(dx, wst<K, C>(m - 1), ldc<C>(vx + o + m - 1), ldc<C>(vx + o - m));
+    dz = acc(dz, wst<K, C>(m - 1), ldc<C>(vz + o + (long long)(m - 1) * P),
+             ldc<C>(vz + o - (long long)m * P));
   }
   C src = C(0);
   if (io.n >= 0 && (I == il.row0 || I == il.row1) && J >= il.col0 && J < il.col0 + il.ntr) {
     const C w = (I == il.row0 ? C(il.w0) : C(0)) + (I == il.row1 ? C(il.w1) : C(0));
     const V* in = static_cast<const V*>(io.in) + shot * io.shot_stride + (long long)io.n * il.ntr +
                   (J - il.col0);
-    src = w * (C(io.scale) * C(*in));
+    src = w * (C(io.scale) * C(*in) / dyn_of<C>(io, shot));
   }
   const int NX = g.NX, NZ = g.NZ;
   const C ck = static_cast<const C*>(cf.ck)[(long long)I * NX + J];
@@ -170,31 +228,332 @@ __global__ __launch_bounds__(TBX* TBY) void k_pres(Fields f, GridDims g, Coef cf
   const bool frame = I < g.L || I >= NZ - g.L || J < g.L || J >= NX - g.L;
   C pn;
   if (!frame) {
-    if constexpr (ADJ)
-      pn = pc + ck * ((dx + dz) + src);
-    else
-      pn = pc + ck * (src - (dx + dz));
+    pn = upd_p<ADJ>(ck, pc, dx, dz, src);
   } else {
     T* __restrict__ au = static_cast<T*>(f.aux) + base;
-    const C axn = pml[J], bxn = pml[NX + J];
-    const C azn = pml[4 * NX + I], bzn = pml[4 * NX + NZ + I];
-    if constexpr (!ADJ) {
-      C px = ldc<C>(au + o);
-      C pz = pc - px;
-      px = axn * px - bxn * ck * dx;
-      pz = azn * pz + bzn * ck * (src - dz);
-      pn = px + pz;
-      stc(au + o, px);
-    } else {
-      const C t = (dx + dz) + src;
-      const C Px = axn * (pc + ldc<C>(au + o)) + bxn * ck * t;
-      const C Pz = azn * pc + bzn * ck * t;
-      pn = Pz;
-      stc(au + o, Px - Pz);
-    }
+    C an;
+    pn = upd_p_frame<ADJ>(ck, pc, ldc<C>(au + o), dx, dz, src, pml[J], pml[NX + J],
+                          pml[4 * NX + I], pml[4 * NX + NZ + I], &an);
+    stc(au + o, an);
   }
   stc(p + o, pn);
 }
+
+// ---------------------------------------------------------------------------
+// Fused time step: one launch advances (p, v) by dt on a TX x TZ output tile.
+//
+// Phase 1 stages p^n over the tile plus a halo of R = 2K-1 cells (the
+// pressure dependency radius of one full step) in LDS; the transpose also
+// stages the x-split part P~_x = P~_z + aux on the tile rows when the tile
+// touches the absorbing frame.  Phase 2 computes v^{n+1/2} for the tile and
+// the K-cell halo the pressure stencil needs (v_x on the tile rows, v_z on
+// the tile columns), writes the owned part and keeps the rest in LDS.
+// Phase 3 computes p^{n+1} on the tile.  Fields are double-buffered (in ->
+// out), so neighbouring tiles never see a half-updated step.  Values
+// outside the grid are zero, as in the single-phase kernels.
+//
+// Tiles are assigned so that each XCD receives a contiguous band of tiles
+// (blocks are dispatched round-robin over the 8 XCDs), which keeps halo
+// re-reads inside one L2.
+constexpr int TX = 64;
+
+template <int K, bool ADJ, typename T, int TZ>
+__global__ __launch_bounds__(256) void k_step(StepArgs a) {
+  using C = typename Tr<T>::C;
+  using V = typename Tr<T>::V;
+  static_assert(TZ % 4 == 0, "tile height must be a multiple of 4");
+  constexpr int R = 2 * K - 1;
+  constexpr int WP = TX + 2 * R, HP = TZ + 2 * R;
+  constexpr int WVX = TX + 2 * K - 1, HVZ = TZ + 2 * K - 1;
+  constexpr int NP = (HP + 3) / 4;    // staging rows per thread (4 thread rows)
+  constexpr int NV = TZ / 4;          // tile rows per thread
+  constexpr int NVZ = (HVZ + 3) / 4;  // v_z rows per thread
+  static_assert(WP <= 2 * TX && WVX <= 2 * TX, "halo wider than one extra chunk");
+  __shared__ C sP[HP * WP];
+  __shared__ C sPX[ADJ ? TZ * WP : 1];
+  __shared__ C sVX[TZ * WVX];
+  __shared__ C sVZ[HVZ * TX];
+
+  // XCD-aware tile index
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int full = nb >> 3, rem = nb & 7, xcd = b & 7;
+  const int t = xcd * full + (xcd < rem ? xcd : rem) + (b >> 3);
+  const int per_shot = a.ntx * a.ntz;
+  const int shot = t / per_shot;
+  const int tt = t - shot * per_shot;
+  const int tzi = tt / a.ntx, txi = tt - tzi * a.ntx;
+  const int x0 = txi * TX, z0 = tzi * TZ;
+  const int x1 = x0 + TX, z1 = z0 + TZ;
+  const int NX = a.g.NX, NZ = a.g.NZ, P = a.g.pitch, L = a.g.L;
+  const long long base = a.g.origin + (long long)shot * a.g.field_stride;
+  const T* __restrict__ pA = static_cast<const T*>(a.in.p) + base;
+  const T* __restrict__ vxA = static_cast<const T*>(a.in.vx) + base;
+  const T* __restrict__ vzA = static_cast<const T*>(a.in.vz) + base;
+  const T* __restrict__ auA = static_cast<const T*>(a.in.aux) + base;
+  T* __restrict__ pB = static_cast<T*>(a.out.p) + base;
+  T* __restrict__ vxB = static_cast<T*>(a.out.vx) + base;
+  T* __restrict__ vzB = static_cast<T*>(a.out.vz) + base;
+  T* __restrict__ auB = static_cast<T*>(a.out.aux) + base;
+  const C* __restrict__ pml = static_cast<const C*>(a.c.pml);
+  const C* __restrict__ ckp = static_cast<const C*>(a.c.ck);
+  const C cb = C(a.c.cb);
+  const int lx = threadIdx.x & (TX - 1), ly = threadIdx.x >> 6;
+  const bool frame_tile = (z0 < L) || (z1 > NZ - L) || (x0 < L) || (x1 > NX - L);
+
+  // ---- issue every global load of the step before touching LDS --------
+  C rp[NP][2];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const int rr = ly + 4 * k, I = z0 - R + rr;
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+      const int cc = lx + TX * hh, J = x0 - R + cc;
+      const bool ok = rr < HP && cc < WP && I >= 0 && I < NZ && J >= 0 && J < NX;
+      rp[k][hh] = ok ? ldc<C>(pA + (long long)I * P + J) : C(0);
+    }
+  }
+  C rvx[NV][2];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int I = z0 + ly + 4 * k;
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+      const int cc = lx + TX * hh, J = x0 - K + cc;
+      const bool ok = cc < WVX && I < NZ && J >= 0 && J < NX;
+      rvx[k][hh] = ok ? ldc<C>(vxA + (long long)I * P + J) : C(0);
+    }
+  }
+  C rvz[NVZ];
+#pragma unroll
+  for (int k = 0; k < NVZ; ++k) {
+    const int rr = ly + 4 * k, I = z0 - K + rr, J = x0 + lx;
+    const bool ok = rr < HVZ && I >= 0 && I < NZ && J < NX;
+    rvz[k] = ok ? ldc<C>(vzA + (long long)I * P + J) : C(0);
+  }
+  C rck[NV], rau[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int I = z0 + ly + 4 * k, J = x0 + lx;
+    const bool ok = I < NZ && J < NX;
+    rck[k] = ok ? ckp[(long long)I * NX + J] : C(0);
+    const bool fr = ok && (I < L || I >= NZ - L || J < L || J >= NX - L);
+    rau[k] = fr ? ldc<C>(auA + (long long)I * P + J) : C(0);
+  }
+  // transposed x-split part P~_x - P~_z on the tile rows (frame tiles only)
+  bool use_px = false;
+  C rax[ADJ ? NV : 1][2];
+  if constexpr (ADJ) {
+    use_px = (z0 < L) || (z1 > NZ - L) || (x0 - R < L) || (x1 + R > NX - L);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const int I = z0 + ly + 4 * k;
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        const int cc = lx + TX * hh, J = x0 - R + cc;
+        const bool ok = use_px && cc < WP && I < NZ && J >= 0 && J < NX;
+        rax[k][hh] = ok ? ldc<C>(auA + (long long)I * P + J) : C(0);
+      }
+    }
+  }
+
+  // ---- phase 1: stage p^n (and P~_x) in LDS
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const int rr = ly + 4 * k;
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+      const int cc = lx + TX * hh;
+      if (rr < HP && cc < WP) sP[rr * WP + cc] = rp[k][hh];
+    }
+  }
+  if constexpr (ADJ) {
+    if (use_px) {
+      // P~_x = P~_z + aux: aux goes to LDS first (its rows live in other
+      // threads than the matching p rows), the sum is formed after the barrier
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        const int tr = ly + 4 * k;
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          const int cc = lx + TX * hh;
+          if (cc < WP) sPX[tr * WP + cc] = rax[k][hh];  // aux first; p added below
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if constexpr (ADJ) {
+    if (use_px) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        const int tr = ly + 4 * k;
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          const int cc = lx + TX * hh;
+          if (cc < WP) sPX[tr * WP + cc] = sP[(tr + R) * WP + cc] + sPX[tr * WP + cc];
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // pressure-line sampling (reads p^n)
+  if (a.vs.n >= 0 && a.vsl.row0 >= z0 && a.vsl.row0 < z1 && ly == 0) {
+    const int J = x0 + lx;
+    if (J >= a.vsl.col0 && J < a.vsl.col0 + a.vsl.ntr && J < NX) {
+      const int r0 = a.vsl.row0 - z0 + R, r1 = a.vsl.row1 - z0 + R;
+      const C val = C(a.vsl.w0) * sP[r0 * WP + lx + R] + C(a.vsl.w1) * sP[r1 * WP + lx + R];
+      V* out = static_cast<V*>(a.vs.out) + shot * a.vs.shot_stride +
+               (long long)a.vs.n * a.vsl.ntr + (J - a.vsl.col0);
+      *out = V(C(a.vs.scale) * val * dyn_of<C>(a.vs, shot));
+    }
+  }
+
+  // ---- phase 2a: v_x on tile rows, columns [x0 - K, x1 + K - 1)
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int rr = ly + 4 * k, I = z0 + rr;
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+      const int cc = lx + TX * hh;
+      if (cc >= WVX) continue;
+      const int J = x0 - K + cc;
+      C val = C(0);
+      if (I < NZ && J >= 0 && J < NX) {
+        const C* row = (ADJ && use_px) ? (sPX + rr * WP) : (sP + (rr + R) * WP);
+        const int c0 = cc - K + R;
+        C sx = C(0);
+#pragma unroll
+        for (int m = 1; m <= K; ++m) sx = acc(sx, wst<K, C>(m - 1), row[c0 + m], row[c0 + 1 - m]);
+        val = rnd<T>(upd_v<ADJ>(pml[2 * NX + J], pml[3 * NX + J], cb, rvx[k][hh], sx, C(0)));
+        if (J >= x0 && J < x1) stc(vxB + (long long)I * P + J, val);
+      }
+      sVX[rr * WVX + cc] = val;
+    }
+  }
+  // ---- phase 2b: v_z on tile columns, rows [z0 - K, z1 + K - 1)
+#pragma unroll
+  for (int k = 0; k < NVZ; ++k) {
+    const int rr = ly + 4 * k;
+    if (rr >= HVZ) continue;
+    const int I = z0 - K + rr, J = x0 + lx;
+    C val = C(0);
+    if (I >= 0 && I < NZ && J < NX) {
+      const int r0 = rr - K + R;
+      C sz = C(0);
+#pragma unroll
+      for (int m = 1; m <= K; ++m)
+        sz = acc(sz, wst<K, C>(m - 1), sP[(r0 + m) * WP + lx + R], sP[(r0 + 1 - m) * WP + lx + R]);
+      C src = C(0);
+      if (a.vi.n >= 0 && (I == a.vil.row0 || I == a.vil.row1) && J >= a.vil.col0 &&
+          J < a.vil.col0 + a.vil.ntr) {
+        const C w = (I == a.vil.row0 ? C(a.vil.w0) : C(0)) + (I == a.vil.row1 ? C(a.vil.w1) : C(0));
+        const V* in = static_cast<const V*>(a.vi.in) + shot * a.vi.shot_stride +
+                      (long long)a.vi.n * a.vil.ntr + (J - a.vil.col0);
+        src = w * (C(a.vi.scale) * C(*in) / dyn_of<C>(a.vi, shot));
+      }
+      val = rnd<T>(upd_v<ADJ>(pml[4 * NX + 2 * NZ + I], pml[4 * NX + 3 * NZ + I], cb, rvz[k], sz,
+                              src));
+      if (I >= z0 && I < z1) stc(vzB + (long long)I * P + J, val);
+    }
+    sVZ[rr * TX + lx] = val;
+  }
+  __syncthreads();
+
+  // v_z-line sampling (reads v^{n+1/2})
+  if (a.ps.n >= 0 && a.psl.row0 >= z0 && a.psl.row0 < z1 && ly == 0) {
+    const int J = x0 + lx;
+    if (J >= a.psl.col0 && J < a.psl.col0 + a.psl.ntr && J < NX) {
+      const int r0 = a.psl.row0 - z0 + K, r1 = a.psl.row1 - z0 + K;
+      const C val = C(a.psl.w0) * sVZ[r0 * TX + lx] + C(a.psl.w1) * sVZ[r1 * TX + lx];
+      V* out = static_cast<V*>(a.ps.out) + shot * a.ps.shot_stride +
+               (long long)a.ps.n * a.psl.ntr + (J - a.psl.col0);
+      *out = V(C(a.ps.scale) * val * dyn_of<C>(a.ps, shot));
+    }
+  }
+
+  // ---- phase 3: p^{n+1} on the tile
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int rr = ly + 4 * k, cc = lx;
+    const int I = z0 + rr, J = x0 + cc;
+    if (I >= NZ || J >= NX) continue;
+    C dx = C(0), dz = C(0);
+#pragma unroll
+    for (int m = 1; m <= K; ++m) {
+      dx = acc(dx, wst<K, C>(m - 1), sVX[rr * WVX + cc + K + m - 1], sVX[rr * WVX + cc + K - m]);
+      dz = acc(dz, wst<K, C>(m - 1), sVZ[(rr + K + m - 1) * TX + cc], sVZ[(rr + K - m) * TX + cc]);
+    }
+    C src = C(0);
+    if (a.pi.n >= 0 && (I == a.pil.row0 || I == a.pil.row1) && J >= a.pil.col0 &&
+        J < a.pil.col0 + a.pil.ntr) {
+      const C w = (I == a.pil.row0 ? C(a.pil.w0) : C(0)) + (I == a.pil.row1 ? C(a.pil.w1) : C(0));
+      const V* in = static_cast<const V*>(a.pi.in) + shot * a.pi.shot_stride +
+                    (long long)a.pi.n * a.pil.ntr + (J - a.pil.col0);
+      src = w * (C(a.pi.scale) * C(*in) / dyn_of<C>(a.pi, shot));
+    }
+    const long long o = (long long)I * P + J;
+    const C ck = rck[k];
+    const C pc = sP[(rr + R) * WP + cc + R];
+    const bool frame = frame_tile && (I < L || I >= NZ - L || J < L || J >= NX - L);
+    C pn;
+    if (!frame) {
+      pn = upd_p<ADJ>(ck, pc, dx, dz, src);
+    } else {
+      C an;
+      pn = upd_p_frame<ADJ>(ck, pc, rau[k], dx, dz, src, pml[J], pml[NX + J], pml[4 * NX + I],
+                            pml[4 * NX + NZ + I], &an);
+      stc(auB + o, an);
+    }
+    stc(pB + o, pn);
+  }
+}
+
+template <int K, bool ADJ, typename T>
+static hipError_t step_t(int tz, const StepArgs& a, hipStream_t s) {
+  const int nb = a.ntx * a.ntz * a.nshots;
+  switch (tz) {
+    case 8: hipLaunchKernelGGL((k_step<K, ADJ, T, 8>), dim3(nb), dim3(256), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_step<K, ADJ, T, 16>), dim3(nb), dim3(256), 0, s, a); break;
+    case 32:
+      if constexpr (sizeof(T) < 8) {
+        hipLaunchKernelGGL((k_step<K, ADJ, T, 32>), dim3(nb), dim3(256), 0, s, a);
+        break;
+      }
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+#define SSX_DISPATCH_STEP(...)                                                   \
+  do {                                                                           \
+    const bool o8 = (order == 8);                                                \
+    switch (dt) {                                                                \
+      case Dt::F64:                                                              \
+        if (o8) return adj ? step_t<4, true, double>(__VA_ARGS__) : step_t<4, false, double>(__VA_ARGS__); \
+        return adj ? step_t<2, true, double>(__VA_ARGS__) : step_t<2, false, double>(__VA_ARGS__);         \
+      case Dt::F32:                                                              \
+        if (o8) return adj ? step_t<4, true, float>(__VA_ARGS__) : step_t<4, false, float>(__VA_ARGS__);   \
+        return adj ? step_t<2, true, float>(__VA_ARGS__) : step_t<2, false, float>(__VA_ARGS__);           \
+      case Dt::F16:                                                              \
+        if (o8) return adj ? step_t<4, true, __half>(__VA_ARGS__) : step_t<4, false, __half>(__VA_ARGS__); \
+        return adj ? step_t<2, true, __half>(__VA_ARGS__) : step_t<2, false, __half>(__VA_ARGS__);         \
+      case Dt::BF16:                                                             \
+        if (o8)                                                                  \
+          return adj ? step_t<4, true, __hip_bfloat16>(__VA_ARGS__)             \
+                     : step_t<4, false, __hip_bfloat16>(__VA_ARGS__);           \
+        return adj ? step_t<2, true, __hip_bfloat16>(__VA_ARGS__)               \
+                   : step_t<2, false, __hip_bfloat16>(__VA_ARGS__);             \
+    }                                                                            \
+    return hipErrorInvalidValue;                                                 \
+  } while (0)
+
+hipError_t launch_step(Dt dt, int order, bool adj, int tz, StepArgs a, hipStream_t s) {
+  SSX_DISPATCH_STEP(tz, a, s);
+}
+
+int step_tile_width() { return TX; }
 
 template <typename T>
 __global__ void k_sample_p(Fields f, GridDims g, LineDev sl, TraceIO so) {
@@ -209,7 +568,7 @@ __global__ void k_sample_p(Fields f, GridDims g, LineDev sl, TraceIO so) {
   const C val = C(sl.w0) * ldc<C>(p + (long long)sl.row0 * g.pitch + J) +
                 C(sl.w1) * ldc<C>(p + (long long)sl.row1 * g.pitch + J);
   V* out = static_cast<V*>(so.out) + shot * so.shot_stride + (long long)so.n * sl.ntr + k;
-  *out = V(C(so.scale) * val);
+  *out = V(C(so.scale) * val * dyn_of<C>(so, shot));
 }
 
 __global__ void k_zero(uint32_t* p, size_t n) {
@@ -606,6 +965,73 @@ hipError_t launch_pcg_dir(bool vdbl, void* p, const void* g, long long n, const 
                        static_cast<const float*>(g), n, sc);
   return hipGetLastError();
 }
+// ---------------------------------------------------------------------------
+// per-shot power-of-two field scale from the propagation inputs (two-pass,
+// no atomics)
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_amax_partial(const V* __restrict__ x, double sc,
+                                                      long long n, float* partial) {
+  __shared__ float sh[256];
+  const int shot = blockIdx.y;
+  const V* xs = x + (long long)shot * n;
+  float m = 0.0f;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (long long)NBLK_DOT * 256)
+    m = fmaxf(m, float(fabs(double(xs[i]) * sc)));
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[(long long)shot * NBLK_DOT + blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_amax_final(const float* partial, int two, int nshots,
+                                                    float* dyn) {
+  __shared__ float sh[256];
+  const int shot = blockIdx.x;
+  float m = partial[(long long)shot * NBLK_DOT + threadIdx.x];
+  if (two) m = fmaxf(m, partial[((long long)nshots + shot) * NBLK_DOT + threadIdx.x]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] = fmaxf(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const float a = sh[0];
+    float s = 1.0f;
+    if (a > 0.0f && isfinite(a)) {
+      int e;
+      frexpf(a, &e);  // a = f 2^e, f in [0.5, 1)
+      s = ldexpf(1.0f, e);
+    }
+    dyn[shot] = s;
+  }
+}
+
+hipError_t launch_field_scale(bool vdbl, const void* a, double sa, const void* b, double sb,
+                              long long n, int nshots, float* partial, float* dyn,
+                              hipStream_t s) {
+  dim3 grid(NBLK_DOT, nshots);
+  const void* xs[2] = {a, b};
+  const double sc[2] = {sa, sb};
+  for (int k = 0; k < (b ? 2 : 1); ++k) {
+    float* part = partial + (long long)k * nshots * NBLK_DOT;
+    if (vdbl)
+      hipLaunchKernelGGL(k_amax_partial<double>, grid, dim3(256), 0, s,
+                         static_cast<const double*>(xs[k]), sc[k], n, part);
+    else
+      hipLaunchKernelGGL(k_amax_partial<float>, grid, dim3(256), 0, s,
+                         static_cast<const float*>(xs[k]), sc[k], n, part);
+  }
+  hipLaunchKernelGGL(k_amax_final, dim3(nshots), dim3(256), 0, s, partial, b ? 1 : 0, nshots,
+                     dyn);
+  return hipGetLastError();
+}
+
 hipError_t launch_neg_copy(bool vdbl, void* y, const void* x, long long n, hipStream_t s) {
   dim3 grid((unsigned)((n + 255) / 256));
   if (vdbl)

@@ -1,0 +1,123 @@
+"""Execution variants of the HIP path must not change results: the fused
+one-launch step equals the split velocity/pressure launches bitwise (FP32 and
+FP64), tile heights agree bitwise, and captured-graph replays equal eager
+launches on every replay."""
+import numpy as np
+import pytest
+
+import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2203_16573_amd as ssx  # noqa: E402
+
+RHO = 1000.0
+
+
+def problem(order, **kw):
+    base = dict(nz=37, nx=150, h=10.0, dt=1e-3, nt=120, order=order, npml=10,
+                z_src=45.0, x_src0=30.0, ns=100, z_rec=203.0, x_rec0=0.0, nr=150,
+                slab_dz=5, xs=(300.0, 717.0))
+    base.update(kw)
+    return inputs.Problem(**base)
+
+
+def kappa(prob, seed=1):
+    c = np.random.default_rng(seed).uniform(1800.0, 2400.0, size=(prob.nz, prob.nx))
+    return RHO * c * c
+
+
+def run_all(ctx, prob, fd, seed=0):
+    dt = torch.float64 if fd == "f64" else torch.float32
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    h = torch.randn((2, prob.nt, prob.ns), generator=g, dtype=torch.float64).to(dt).cuda()
+    r = torch.randn((2, prob.nt, prob.nr), generator=g, dtype=torch.float64).to(dt).cuda()
+    d = ctx.fwd(h, ctx.empty_r())
+    gg = ctx.adj(r, ctx.empty_s())
+    P, V = ctx.slab_fwd(h, ctx.empty_s(), ctx.empty_s())
+    f = ctx.slab_adj(h, r[:, :, :prob.ns].contiguous(), ctx.empty_s())
+    torch.cuda.synchronize()
+    return [t.cpu().numpy().copy() for t in (d, gg, P, V, f)]
+
+
+@pytest.mark.parametrize("fd", ["f64", "f32", "f16", "bf16"])
+@pytest.mark.parametrize("order", [4, 8])
+def test_fused_equals_split_bitwise(fd, order):
+    prob = problem(order)
+    print(f"case fused-vs-split order={order} dtype={fd}", flush=True)
+    ctx = ssx.Context(prob, kappa(prob), RHO, field_dtype=fd)
+    ctx.set_graphs(False)
+    ctx.set_option(ssx.OPT_STEP_KERNEL, 0)
+    split = run_all(ctx, prob, fd)
+    ctx.set_option(ssx.OPT_STEP_KERNEL, 1)
+    tiles = [8, 16] + ([32] if fd != "f64" else [])
+    for tz in tiles:
+        ctx.set_option(ssx.OPT_TILE_Z, tz)
+        fused = run_all(ctx, prob, fd)
+        for a, b in zip(split, fused):
+            assert np.array_equal(a, b), (fd, order, tz)
+    ctx.close()
+
+
+@pytest.mark.parametrize("fd", ["f64", "f32"])
+def test_graph_replays_equal_eager(fd):
+    prob = problem(8)
+    print(f"case graph replay dtype={fd}", flush=True)
+    ctx = ssx.Context(prob, kappa(prob), RHO, field_dtype=fd)
+    ctx.set_graphs(False)
+    eager = run_all(ctx, prob, fd, seed=3)
+    ctx.set_graphs(True)
+    dt = torch.float64 if fd == "f64" else torch.float32
+    g = torch.Generator(device="cpu").manual_seed(3)
+    h = torch.randn((2, prob.nt, prob.ns), generator=g, dtype=torch.float64).to(dt).cuda()
+    d = ctx.empty_r()
+    for rep in range(4):
+        d.fill_(float(rep))          # eager work between replays
+        x = torch.ones(1000, device="cuda").sum()
+        torch.cuda.synchronize()
+        ctx.fwd(h, d)
+        torch.cuda.synchronize()
+        assert np.array_equal(d.cpu().numpy(), eager[0]), rep
+        del x
+    for rep in range(2):
+        got = run_all(ctx, prob, fd, seed=3)
+        for a, b in zip(eager, got):
+            assert np.array_equal(a, b), rep
+    ctx.close()
+
+
+def test_options_rejected():
+    prob = problem(8)
+    ctx = ssx.Context(prob, kappa(prob), RHO, field_dtype="f64")
+    for opt, val in ((ssx.OPT_TILE_Z, 32), (ssx.OPT_TILE_Z, 12), (ssx.OPT_STEP_KERNEL, 2), (99, 1)):
+        with pytest.raises(ssx.SSXError):
+            ctx.set_option(opt, val)
+    ctx.close()
+
+
+@pytest.mark.parametrize("fd,tol", [("f16", 2e-2), ("bf16", 1e-1)])
+def test_half_precision_storage_error(fd, tol):
+    # 16-bit wavefield storage with FP32 arithmetic: error against the FP64
+    # oracle per propagation, stated and bounded
+    import oracle
+    prob = problem(8)
+    kap = kappa(prob)
+    m = oracle.Model(prob, kap, RHO)
+    ctx = ssx.Context(prob, kap, RHO, field_dtype=fd)
+    rng = np.random.default_rng(11)
+    h = rng.standard_normal((2, prob.nt, prob.ns)) * 1e-3   # arbitrary scale
+    r = rng.standard_normal((2, prob.nt, prob.nr)) * 1e5
+    d = ctx.fwd(torch.tensor(h, dtype=torch.float32, device="cuda"), ctx.empty_r())
+    g = ctx.adj(torch.tensor(r, dtype=torch.float32, device="cuda"), ctx.empty_s())
+    w = ctx.precond(1e-3, torch.tensor(h, dtype=torch.float32, device="cuda"), ctx.empty_s())
+    torch.cuda.synchronize()
+    errs = []
+    for s in range(2):
+        for got, ref in ((d[s], m.fwd(h[s])), (g[s], m.adj(r[s])),
+                         (w[s], oracle.precond(m, 1e-3, h[s], s))):
+            got = got.double().cpu().numpy()
+            errs.append(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    print(f"{fd} storage: relative L2 errors fwd/adj/precond {errs}")
+    assert max(errs) < tol
+    ctx.close()
