@@ -34,7 +34,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c4bf"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c4bf", "c5"])
+    ap.add_argument("--autotune", type=int, default=1)
+    ap.add_argument("--requests", type=int, default=12, help="c5: requests served")
+    ap.add_argument("--max-shots", type=int, default=8, help="c5: shots per request cap")
+    ap.add_argument("--max-nt", type=int, default=1500, help="c5: record length cap")
+    ap.add_argument("--slots", type=int, default=4, help="c5: concurrent requests")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=12,
                     help="time steps of the oracle's bounded CPU sample")
@@ -72,6 +77,8 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
 
+    if args.config == "c5":
+        return serve_bench(args)
     cnum = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "c4bf": 4}[args.config]
     wl = inputs.workload(cnum)
     prob = wl.prob
@@ -79,6 +86,11 @@ def main():
     vdt = torch.float64 if fd == "f64" else torch.float32
 
     ctx = ssx.Context(prob, wl.kappa, wl.rho, field_dtype=fd)
+    tuned = None
+    if args.autotune:
+        from paper_2203_16573_amd import autotune
+        tuned = autotune.choose(prob, wl.kappa, wl.rho, field_dtype=fd)
+        autotune.apply(ctx, tuned)
     ctx.set_graphs(bool(args.graphs))
     wav = inputs.source_wavelet(prob, wl.freq)
     htrue = np.stack([inputs.spike_gather(prob, wav, s) for s in range(prob.nshots)])
@@ -177,12 +189,82 @@ def main():
                    "shots": prob.nshots, "field_dtype": fd},
         "gcell_updates_per_s": round(gcell, 2),
         "iters": iters,
+        "kernel_choice": None if tuned is None else {k: tuned[k] for k in
+                                                     ("step_kernel", "tile_z", "tile_z_slab")},
         "final_rel_residual": float(hist[0, -1, 0] / hist[0, 0, 0]),
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def serve_bench(args):
+    """Serving workload: the first --requests requests of the seeded stream
+    (grids 201x401 / 401x801 / 801x1601, layered models, 1..--max-shots
+    shots, 500..--max-nt steps, K = 20, FP16 storage), data generated on the
+    device before timing.  A closed-loop pass (all queued at t = 0) measures
+    capacity; an open-loop pass with Poisson arrivals at 0.8x that rate
+    measures latency."""
+    import numpy as np
+    import torch
+
+    import inputs
+    import paper_2203_16573_amd as ssx
+    from paper_2203_16573_amd import autotune, serve
+
+    torch.cuda.set_device(0)
+    stream = inputs.serving_requests(args.requests, max_shots=args.max_shots,
+                                     nt_range=(500, args.max_nt))
+    reqs = []
+    for i, (t, wl) in enumerate(stream):
+        prob = wl.prob
+        gen = ssx.Context(prob, wl.kappa, wl.rho, field_dtype="f32")
+        wav = inputs.source_wavelet(prob, wl.freq)
+        htrue = np.stack([inputs.spike_gather(prob, wav, s) for s in range(prob.nshots)])
+        d = gen.fwd(torch.tensor(htrue, dtype=torch.float32, device="cuda"), gen.empty_r())
+        torch.cuda.synchronize()
+        gen.close()
+        reqs.append(serve.Request(i, prob, wl.kappa, wl.rho, d, alpha_rel=wl.alpha_rel, K=wl.K,
+                                  field_dtype="f16", arrival=t))
+    tuner = None
+    if args.autotune:
+        def tuner(ctx, req):
+            autotune.apply(ctx, autotune.choose(req.prob, req.kappa, req.rho, field_dtype="f16"))
+        for r in reqs:  # tune every shape before timing
+            autotune.choose(r.prob, r.kappa, r.rho, field_dtype="f16")
+    budget = int(0.8 * torch.cuda.mem_get_info()[0])
+    srv = serve.Server(budget, slots=args.slots, graphs=False, tuner=tuner)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    closed = srv.run(reqs, realtime=False)
+    wall_closed = time.perf_counter() - t0
+    cap = serve.summarize(closed, wall_closed)
+    rate = 0.8 * cap["requests_per_s"]
+    gaps = np.random.default_rng(inputs.BASE_SEED + 5).exponential(1.0 / rate, size=len(reqs))
+    for r, t in zip(reqs, np.cumsum(gaps)):
+        r.arrival = float(t)
+    t0 = time.perf_counter()
+    opened = srv.run(reqs, realtime=True)
+    wall_open = time.perf_counter() - t0
+    lat = serve.summarize(opened, wall_open)
+    same = all(torch.equal(a.h, b.h) for a, b in zip(closed, opened))
+    out = {
+        "metric": "served PCG surface-source solves/s (p50/p99 latency)",
+        "value": round(cap["solves_per_s"], 4), "unit": "solves/s", "n_gpus": 1,
+        "steps": len(reqs), "warmup": 0,
+        "ms_per_step": round(1e3 * wall_closed / len(reqs), 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f16-storage/f32", "data": "synthetic (seeded serving stream)",
+        "config": {"workload": f"c5: first {len(reqs)} requests of the seeded stream, "
+                               f"<= {args.max_shots} shots, nt <= {args.max_nt}, K 20, "
+                               f"{args.slots} slots"},
+        "closed_loop": cap, "open_loop_0p8": lat,
+        "p50_latency_s": round(lat["latency_p50_s"], 3),
+        "p99_latency_s": round(lat["latency_p99_s"], 3),
+        "results_identical_closed_vs_open": same,
+    }
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

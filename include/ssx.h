@@ -187,15 +187,16 @@ ssx_status ssx_pcg_solve(ssx_ctx* ctx, const void* d, double alpha_rel, int32_t 
  *   SSX_OPT_STEP_KERNEL 1 (default): one fused launch per time step
  *                       (velocity and pressure on an LDS-staged tile);
  *                       0: one velocity and one pressure launch per step.
- *   SSX_OPT_TILE_Z      tile height of the fused kernel: 8, 16 or 32 (32
- *                       not for F64 fields); 0 picks a default.
- *   SSX_OPT_STEPS_PER_LAUNCH  time steps fused per launch (1 or 2).
+ *   SSX_OPT_TILE_Z      tile height of the fused kernel on the full grid
+ *                       and the thin slab: 8, 16 or 32 (32 not for F64
+ *                       fields); 0 picks a default from the grid size.
+ *   SSX_OPT_TILE_Z_SLAB the same for the thin slab only.
  * Returns SSX_ERR_ARG for an unknown option or value. */
 typedef enum {
   SSX_OPT_GRAPHS = 0,
   SSX_OPT_STEP_KERNEL = 1,
   SSX_OPT_TILE_Z = 2,
-  SSX_OPT_STEPS_PER_LAUNCH = 3
+  SSX_OPT_TILE_Z_SLAB = 3
 } ssx_option;
 ssx_status ssx_set_option(ssx_ctx* ctx, int option, int value);
 

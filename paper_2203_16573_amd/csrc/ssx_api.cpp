@@ -165,9 +165,11 @@ struct GridHost {
   int nz, nx, L, NZ, NX, pitch;
   long long field_elems;  // one field of one shot, ghosts included
   long long origin;
-  std::vector<double> ck;   // [NZ][NX]
-  std::vector<double> pml;  // ax_n bx_n ax_h bx_h [NX], az_n bz_n az_h bz_h [NZ]
+  std::vector<double> ck;   // laid out like a field (zero ghosts)
+  std::vector<double> pml;  // x arrays of length pitch (origin GX), then z arrays
 };
+
+int grid_pitch(int NX) { return ((NX + 2 * GX + 8) + 63) / 64 * 64; }
 
 void build_grid(const ssx_problem& p, const std::vector<double>& kphys, int nz, double Z0,
                 double rho, GridHost* g) {
@@ -177,19 +179,19 @@ void build_grid(const ssx_problem& p, const std::vector<double>& kphys, int nz, 
   g->L = L;
   g->NZ = nz + 2 * L;
   g->NX = nx + 2 * L;
-  g->pitch = ((g->NX + 2 * GX) + 63) / 64 * 64;
+  g->pitch = grid_pitch(g->NX);
   g->field_elems = (long long)(g->NZ + 2 * GZ) * g->pitch;
   g->origin = (long long)GZ * g->pitch + GX;
   // model padded by copying the nearest physical value
   double kmax = 0;
-  g->ck.resize((size_t)g->NZ * g->NX);
+  g->ck.assign((size_t)g->field_elems, 0.0);
   for (int I = 0; I < g->NZ; ++I) {
     const int i = std::min(std::max(I - L, 0), nz - 1);
     for (int J = 0; J < g->NX; ++J) {
       const int j = std::min(std::max(J - L, 0), nx - 1);
       const double k = kphys[(size_t)i * nx + j];
       kmax = std::max(kmax, k);
-      g->ck[(size_t)I * g->NX + J] = p.dt * k / (p.h * Z0);
+      g->ck[(size_t)(g->origin + (long long)I * g->pitch + J)] = p.dt * k / (p.h * Z0);
     }
   }
   // PML: sigma(d) = smax (d / L)^2, d = cells into the layer;
@@ -203,16 +205,16 @@ void build_grid(const ssx_problem& p, const std::vector<double>& kphys, int nz, 
     *a = (1.0 - q) / (1.0 + q);
     *b = 1.0 / (1.0 + q);
   };
-  const int NX = g->NX, NZ = g->NZ;
-  g->pml.assign(4 * (size_t)NX + 4 * (size_t)NZ, 0.0);
-  double* P = g->pml.data();
+  const int NX = g->NX, NZ = g->NZ, PX = g->pitch;
+  g->pml.assign(4 * (size_t)PX + 4 * (size_t)NZ, 1.0);
+  double* Q = g->pml.data();
   for (int J = 0; J < NX; ++J) {
-    ab(J, nx, &P[J], &P[NX + J]);
-    ab(J + 0.5, nx, &P[2 * NX + J], &P[3 * NX + J]);
+    ab(J, nx, &Q[GX + J], &Q[PX + GX + J]);
+    ab(J + 0.5, nx, &Q[2 * PX + GX + J], &Q[3 * PX + GX + J]);
   }
   for (int I = 0; I < NZ; ++I) {
-    ab(I, nz, &P[4 * NX + I], &P[4 * NX + NZ + I]);
-    ab(I + 0.5, nz, &P[4 * NX + 2 * NZ + I], &P[4 * NX + 3 * NZ + I]);
+    ab(I, nz, &Q[4 * PX + I], &Q[4 * PX + NZ + I]);
+    ab(I + 0.5, nz, &Q[4 * PX + 2 * NZ + I], &Q[4 * PX + 3 * NZ + I]);
   }
 }
 
@@ -308,8 +310,8 @@ void layout(ssx_ctx* c, const GridHost& fg, const GridHost& sg, char* base, size
     gd.fields1.vx = fb ? fb + 5 * one : nullptr;
     gd.fields1.vz = fb ? fb + 6 * one : nullptr;
     gd.fields1.aux = fb ? fb + 7 * one : nullptr;
-    gd.coef.ck = a.take((size_t)gh.NZ * gh.NX * csz);
-    gd.coef.pml = a.take(gh.pml.size() * csz);
+    gd.coef.ck = a.take((size_t)gh.field_elems * csz);
+    gd.coef.pml = a.take((4 * (size_t)gh.pitch + 4 * (size_t)gh.NZ) * csz);
   };
   grid(c->full, fg);
   grid(c->slab, sg);
@@ -655,9 +657,8 @@ size_t ssx_footprint(const ssx_problem* prob) {
     g.L = prob->npml;
     g.NZ = nz + 2 * g.L;
     g.NX = prob->nx + 2 * g.L;
-    g.pitch = ((g.NX + 2 * GX) + 63) / 64 * 64;
+    g.pitch = grid_pitch(g.NX);
     g.field_elems = (long long)(g.NZ + 2 * GZ) * g.pitch;
-    g.pml.resize(4 * (size_t)g.NX + 4 * (size_t)g.NZ);
   };
   dims(fg, prob->nz);
   dims(sg, i_hi - i_lo + 1);
@@ -905,14 +906,13 @@ ssx_status ssx_set_option(ssx_ctx* c, int option, int value) {
       c->fused = value == 1;
       return SSX_OK;
     case SSX_OPT_TILE_Z:
+    case SSX_OPT_TILE_Z_SLAB:
       if (value != 0 && value != 8 && value != 16 && value != 32)
         return fail(SSX_ERR_ARG, "tile height must be 0, 8, 16 or 32");
       if (value == 32 && c->fdt == Dt::F64)
         return fail(SSX_ERR_ARG, "tile height 32 is not available for F64 fields");
-      c->tile_z_full = c->tile_z_slab = value;
-      return SSX_OK;
-    case SSX_OPT_STEPS_PER_LAUNCH:
-      if (value != 1) return fail(SSX_ERR_ARG, "steps per launch must be 1");
+      if (option == SSX_OPT_TILE_Z) c->tile_z_full = value;
+      c->tile_z_slab = value;
       return SSX_OK;
   }
   return fail(SSX_ERR_ARG, "unknown option");

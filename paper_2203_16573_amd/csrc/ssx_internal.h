@@ -13,7 +13,8 @@ namespace ssx {
 
 // Ghost cells around every stored field: always zero, never written, so the
 // stencils read "zero outside the grid" without bounds checks.  GX columns
-// (also keeps row starts 256-byte aligned for FP32) and GZ rows.
+// (also keeps row starts 256-byte aligned for FP32) and GZ rows.  The row
+// pitch is at least NX + 2 GX + 8, a multiple of 64.
 constexpr int GX = 64;
 constexpr int GZ = 4;
 
@@ -50,8 +51,12 @@ struct TraceIO {
 };
 
 struct Coef {
-  const void* ck;   // [NZ][NX] dt kappa / (h Z0), compute type
-  const void* pml;  // 8 arrays: ax_n bx_n ax_h bx_h [NX], az_n bz_n az_h bz_h [NZ]
+  // dt kappa / (h Z0), compute type, laid out like one shot of a field
+  // (element (I, J) at origin + I * pitch + J, zero ghosts)
+  const void* ck;
+  // absorbing-layer factors, compute type: ax_n bx_n ax_h bx_h, each pitch
+  // long with element J at GX + J; then az_n bz_n az_h bz_h, each NZ long
+  const void* pml;
   double cb;        // Z0 dt / (rho h)
 };
 

@@ -1,0 +1,667 @@
+// HIP stencil kernels for gfx950 (CDNA4): the staggered-grid acoustic time
+// step and its exact transpose, with line injection and sampling fused in.
+//
+// Scheme (Numerical Examples, "Synthetic models and simulation": staggered
+// grid, order 2 in time and 2K in space, PML on all sides, linear
+// interpolation for sampling, its transpose for injection).  Stored
+// variables are scaled, p^ = p / Z0 and v^ = v with Z0 a reference
+// impedance, so that both update coefficients are Courant-sized:
+//   cb = Z0 dt / (rho h),  ck = dt kappa / (h Z0).
+//
+// Forward step n:
+//   v_x <- a v_x - b cb Dx+ p ;  v_z <- a v_z + b cb (-Dz+ p + w f[n])
+//   p   <- p + ck (-(Dx- v_x + Dz- v_z) + w h[n])               (interior)
+//   in the absorbing frame p = p_x + p_z is split, with p_x stored.
+// Transposed step n (scaled adjoint variables P~ = ck b' pbar,
+// V~ = b cb vbar; interior P~_x = P~_z): the stencil terms change sign, the
+// x-stencil of the velocity update reads P~_x and the z-stencil P~_z, and
+// both split pressure parts receive the full divergence (transposition
+// exchanges which side of the update is split).
+//
+// Two implementations compute the same expressions (bitwise equal for every
+// storage type): k_vel + k_pres, one thread per cell and two launches per
+// step (the reference); and k_step, one launch per step on an LDS-staged
+// tile with each thread owning 1 x 4 cells.
+#include "ssx_device.h"
+
+#include <cmath>
+
+namespace ssx {
+
+// ---------------------------------------------------------------------------
+// per-cell formulas (the library is built with -ffp-contract=off; fused
+// multiply-adds are explicit so every variant rounds identically)
+
+__device__ __forceinline__ float fmac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmac(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Staggered first-derivative weights c_1..c_K (Taylor / Fornberg).
+template <int K, typename C> __device__ __forceinline__ C wst(int m) {
+  if constexpr (K == 2) {
+    return m == 0 ? C(9.0 / 8.0) : C(-1.0 / 24.0);
+  } else {
+    return m == 0   ? C(1225.0 / 1024.0)
+           : m == 1 ? C(-245.0 / 3072.0)
+           : m == 2 ? C(49.0 / 5120.0)
+                    : C(-5.0 / 7168.0);
+  }
+}
+
+// stencil accumulator: s + w (hi - lo)
+template <typename C> __device__ __forceinline__ C acc(C s, C w, C hi, C lo) {
+  return fmac(w, hi - lo, s);
+}
+// velocity: a v + b cb (sgn sum + src), sgn = -1 forward, +1 transposed
+template <bool ADJ, typename C>
+__device__ __forceinline__ C upd_v(C a, C b, C cb, C old, C sum, C src) {
+  const C r = ADJ ? (sum + src) : (src - sum);
+  return fmac(a, old, (b * cb) * r);
+}
+// pressure away from the absorbing frame
+template <bool ADJ, typename C>
+__device__ __forceinline__ C upd_p(C ck, C p, C dx, C dz, C src) {
+  const C r = ADJ ? ((dx + dz) + src) : (src - (dx + dz));
+  return fmac(ck, r, p);
+}
+// pressure in the frame; aux: forward p_x, transposed P~_x - P~_z
+template <bool ADJ, typename C>
+__device__ __forceinline__ C upd_p_frame(C ck, C p, C aux, C dx, C dz, C src, C axn, C bxn,
+                                         C azn, C bzn, C* aux_new) {
+  if constexpr (!ADJ) {
+    const C px = fmac(axn, aux, -((bxn * ck) * dx));
+    const C pz = fmac(azn, p - aux, (bzn * ck) * (src - dz));
+    *aux_new = px;
+    return px + pz;
+  } else {
+    const C t = (dx + dz) + src;
+    const C Px = fmac(axn, p + aux, (bxn * ck) * t);
+    const C Pz = fmac(azn, p, (bzn * ck) * t);
+    *aux_new = Px - Pz;
+    return Pz;
+  }
+}
+
+// absorbing-layer factors: x arrays of length pitch (origin GX), then z
+// arrays of length NZ
+template <typename C> struct Pml {
+  const C* p;
+  int P, NZ;
+  __device__ __forceinline__ const C* xa(int k, int J) const { return p + k * P + GX + J; }
+  __device__ __forceinline__ C axn(int J) const { return p[GX + J]; }
+  __device__ __forceinline__ C bxn(int J) const { return p[P + GX + J]; }
+  __device__ __forceinline__ C axh(int J) const { return p[2 * P + GX + J]; }
+  __device__ __forceinline__ C bxh(int J) const { return p[3 * P + GX + J]; }
+  __device__ __forceinline__ C azn(int I) const { return p[4 * P + I]; }
+  __device__ __forceinline__ C bzn(int I) const { return p[4 * P + NZ + I]; }
+  __device__ __forceinline__ C azh(int I) const { return p[4 * P + 2 * NZ + I]; }
+  __device__ __forceinline__ C bzh(int I) const { return p[4 * P + 3 * NZ + I]; }
+};
+
+template <typename C>
+__device__ __forceinline__ C dyn_of(const TraceIO& t, int shot) {
+  return t.dyn ? C(t.dyn[shot]) : C(1);
+}
+
+// injected value at (I, J) from a line (0 off the line)
+template <typename C, typename V>
+__device__ __forceinline__ C line_src(const LineDev& l, const TraceIO& io, int I, int J,
+                                      int shot) {
+  if (io.n < 0 || (I != l.row0 && I != l.row1) || J < l.col0 || J >= l.col0 + l.ntr) return C(0);
+  const C w = (I == l.row0 ? C(l.w0) : C(0)) + (I == l.row1 ? C(l.w1) : C(0));
+  const V* in = static_cast<const V*>(io.in) + shot * io.shot_stride + (long long)io.n * l.ntr +
+                (J - l.col0);
+  return w * (C(io.scale) * C(*in) / dyn_of<C>(io, shot));
+}
+
+template <typename C, typename V>
+__device__ __forceinline__ void line_out(const LineDev& l, const TraceIO& io, int J, int shot,
+                                         C val) {
+  V* out = static_cast<V*>(io.out) + shot * io.shot_stride + (long long)io.n * l.ntr + (J - l.col0);
+  *out = V(C(io.scale) * val * dyn_of<C>(io, shot));
+}
+
+constexpr int TBX = 64;  // split kernels: one wavefront across x
+constexpr int TBY = 4;
+
+// ---------------------------------------------------------------------------
+// split reference kernels: velocity update (+ pressure-line sampling, +
+// v_z injection), then pressure update (+ v_z-line sampling, + pressure
+// injection), one thread per cell, in place.
+template <int K, bool ADJ, typename T>
+__global__ __launch_bounds__(TBX* TBY) void k_vel(Fields f, GridDims g, Coef cf, LineDev sl,
+                                                  TraceIO so, LineDev il, TraceIO io) {
+  using C = typename Tr<T>::C;
+  using V = typename Tr<T>::V;
+  const int J = blockIdx.x * TBX + threadIdx.x;
+  const int I = blockIdx.y * TBY + threadIdx.y;
+  const int shot = blockIdx.z;
+  if (I >= g.NZ || J >= g.NX) return;
+  const long long base = g.origin + (long long)shot * g.field_stride;
+  const T* __restrict__ p = static_cast<const T*>(f.p) + base;
+  T* __restrict__ vx = static_cast<T*>(f.vx) + base;
+  T* __restrict__ vz = static_cast<T*>(f.vz) + base;
+  const int P = g.pitch;
+  const long long o = (long long)I * P + J;
+  const Pml<C> pm{static_cast<const C*>(cf.pml), P, g.NZ};
+  const C cb = C(cf.cb);
+
+  if (so.n >= 0 && I == sl.row0 && J >= sl.col0 && J < sl.col0 + sl.ntr) {
+    const C val = C(sl.w0) * ldc<C>(p + o) + C(sl.w1) * ldc<C>(p + (long long)sl.row1 * P + J);
+    line_out<C, V>(sl, so, J, shot, val);
+  }
+
+  C sx = C(0);
+  bool split_x = false;
+  if constexpr (ADJ) split_x = I < g.L || I >= g.NZ - g.L || J < g.L + K || J >= g.NX - g.L - K;
+  if (!split_x) {
+#pragma unroll
+    for (int m = 1; m <= K; ++m)
+      sx = acc(sx, wst<K, C>(m - 1), ldc<C>(p + o + m), ldc<C>(p + o + 1 - m));
+  } else {
+    // transposed x-split pressure P~_x = P~_z + aux (aux is zero off the frame)
+    const T* __restrict__ ax = static_cast<const T*>(f.aux) + base;
+#pragma unroll
+    for (int m = 1; m <= K; ++m)
+      sx = acc(sx, wst<K, C>(m - 1), ldc<C>(p + o + m) + ldc<C>(ax + o + m),
+               ldc<C>(p + o + 1 - m) + ldc<C>(ax + o + 1 - m));
+  }
+  stc(vx + o, upd_v<ADJ>(pm.axh(J), pm.bxh(J), cb, ldc<C>(vx + o), sx, C(0)));
+
+  C sz = C(0);
+#pragma unroll
+  for (int m = 1; m <= K; ++m)
+    sz = acc(sz, wst<K, C>(m - 1), ldc<C>(p + o + (long long)m * P),
+             ldc<C>(p + o + (long long)(1 - m) * P));
+  const C src = line_src<C, V>(il, io, I, J, shot);
+  stc(vz + o, upd_v<ADJ>(pm.azh(I), pm.bzh(I), cb, ldc<C>(vz + o), sz, src));
+}
+
+template <int K, bool ADJ, typename T>
+__global__ __launch_bounds__(TBX* TBY) void k_pres(Fields f, GridDims g, Coef cf, LineDev sl,
+                                                   TraceIO so, LineDev il, TraceIO io) {
+  using C = typename Tr<T>::C;
+  using V = typename Tr<T>::V;
+  const int J = blockIdx.x * TBX + threadIdx.x;
+  const int I = blockIdx.y * TBY + threadIdx.y;
+  const int shot = blockIdx.z;
+  if (I >= g.NZ || J >= g.NX) return;
+  const long long base = g.origin + (long long)shot * g.field_stride;
+  T* __restrict__ p = static_cast<T*>(f.p) + base;
+  const T* __restrict__ vx = static_cast<const T*>(f.vx) + base;
+  const T* __restrict__ vz = static_cast<const T*>(f.vz) + base;
+  const int P = g.pitch;
+  const long long o = (long long)I * P + J;
+  const Pml<C> pm{static_cast<const C*>(cf.pml), P, g.NZ};
+
+  if (so.n >= 0 && I == sl.row0 && J >= sl.col0 && J < sl.col0 + sl.ntr) {
+    const C val =
+        C(sl.w0) * ldc<C>(vz + o) + C(sl.w1) * ldc<C>(vz + (long long)sl.row1 * P + J);
+    line_out<C, V>(sl, so, J, shot, val);
+  }
+
+  C dx = C(0), dz = C(0);
+#pragma unroll
+  for (int m = 1; m <= K; ++m) {
+    dx = acc(dx, wst<K, C>(m - 1), ldc<C>(vx + o + m - 1), ldc<C>(vx + o - m));
+    dz = acc(dz, wst<K, C>(m - 1), ldc<C>(vz + o + (long long)(m - 1) * P),
+             ldc<C>(vz + o - (long long)m * P));
+  }
+  const C src = line_src<C, V>(il, io, I, J, shot);
+  const C ck = static_cast<const C*>(cf.ck)[g.origin + o];
+  const C pc = ldc<C>(p + o);
+  const bool frame = I < g.L || I >= g.NZ - g.L || J < g.L || J >= g.NX - g.L;
+  C pn;
+  if (!frame) {
+    pn = upd_p<ADJ>(ck, pc, dx, dz, src);
+  } else {
+    T* __restrict__ au = static_cast<T*>(f.aux) + base;
+    C an;
+    pn = upd_p_frame<ADJ>(ck, pc, ldc<C>(au + o), dx, dz, src, pm.axn(J), pm.bxn(J), pm.azn(I),
+                          pm.bzn(I), &an);
+    stc(au + o, an);
+  }
+  stc(p + o, pn);
+}
+
+// ---------------------------------------------------------------------------
+// Fused time step: one launch advances (p, v) by dt on a TX x TZ output tile
+// (all shots in one grid).
+//
+// Every global load of the step (p^n with a halo, the old velocities, ck,
+// the frame auxiliaries) is issued up front into registers.  Then p^n over
+// the tile plus R = 2K-1 rows and 8 columns is staged in LDS; v^{n+1/2} is
+// computed for the tile and the halo the pressure stencil needs (v_x on the
+// tile rows over columns x0-4 .. x1+3, v_z on the tile columns over rows
+// z0-K .. z1+K-2), the owned part is stored and the rest kept in LDS; last,
+// p^{n+1} on the tile.  Each thread handles groups of 4 adjacent cells with
+// 128-bit accesses.  Fields are double-buffered (in -> out), so neighbouring
+// tiles never see a half-updated step.  Values outside the grid are zero
+// (zero ghost cells around every field, rows outside [0, NZ) skipped).
+//
+// Tiles are ordered so that each XCD receives a contiguous band of tiles
+// (workgroups are dispatched round-robin over the 8 XCDs), which keeps halo
+// re-reads inside one L2.
+constexpr int TX = 64;
+constexpr int HXS = 8;  // staged x halo (>= 2K - 1, multiple of 4)
+
+template <int K, bool ADJ, typename T, int TZ>
+__global__ __launch_bounds__(256) void k_step(StepArgs a) {
+  using C = typename Tr<T>::C;
+  using V = typename Tr<T>::V;
+  constexpr int R = 2 * K - 1;
+  constexpr int WP = TX + 2 * HXS;     // staged p columns: x0-8 .. x1+7
+  constexpr int GP = WP / 4;
+  constexpr int HP = TZ + 2 * R;       // staged p rows: z0-R .. z1+R-1
+  constexpr int GVX = TX / 4 + 2;      // v_x groups: x0-4 .. x1+3
+  constexpr int WVX = 4 * GVX;
+  constexpr int HVZ = TZ + 2 * K - 1;  // v_z rows: z0-K .. z1+K-2
+  constexpr int GT = TX / 4;           // groups per tile row
+  constexpr int NQP = (HP * GP + 255) / 256;
+  constexpr int NQX = (TZ * GVX + 255) / 256;
+  constexpr int NQZ = (HVZ * GT + 255) / 256;
+  constexpr int NQT = (TZ * GT + 255) / 256;
+  constexpr int NQA = (TZ * GP + 255) / 256;
+  static_assert(2 * K - 1 <= HXS && K <= 4, "halo wider than the staged columns");
+  __shared__ __align__(16) C sP[HP * WP];
+  __shared__ __align__(16) C sPX[ADJ ? TZ * WP : 4];
+  __shared__ __align__(16) C sVX[TZ * WVX];
+  __shared__ __align__(16) C sVZ[HVZ * TX];
+
+  // XCD-aware tile index
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int full = nb >> 3, rem = nb & 7, xcd = b & 7;
+  const int t = xcd * full + (xcd < rem ? xcd : rem) + (b >> 3);
+  const int per_shot = a.ntx * a.ntz;
+  const int shot = t / per_shot;
+  const int tt = t - shot * per_shot;
+  const int tzi = tt / a.ntx, txi = tt - tzi * a.ntx;
+  const int x0 = txi * TX, z0 = tzi * TZ;
+  const int x1 = x0 + TX, z1 = z0 + TZ;
+  const int NX = a.g.NX, NZ = a.g.NZ, P = a.g.pitch, L = a.g.L;
+  const long long base = a.g.origin + (long long)shot * a.g.field_stride;
+  const T* __restrict__ pA = static_cast<const T*>(a.in.p) + base;
+  const T* __restrict__ vxA = static_cast<const T*>(a.in.vx) + base;
+  const T* __restrict__ vzA = static_cast<const T*>(a.in.vz) + base;
+  const T* __restrict__ auA = static_cast<const T*>(a.in.aux) + base;
+  T* __restrict__ pB = static_cast<T*>(a.out.p) + base;
+  T* __restrict__ vxB = static_cast<T*>(a.out.vx) + base;
+  T* __restrict__ vzB = static_cast<T*>(a.out.vz) + base;
+  T* __restrict__ auB = static_cast<T*>(a.out.aux) + base;
+  const C* __restrict__ ckp = static_cast<const C*>(a.c.ck) + a.g.origin;
+  const Pml<C> pm{static_cast<const C*>(a.c.pml), P, NZ};
+  const C cb = C(a.c.cb);
+  const int tid = threadIdx.x;
+  const bool frame_tile = (z0 < L) || (z1 > NZ - L) || (x0 < L) || (x1 > NX - L);
+
+  // ---- every global load of the step, before touching LDS ---------------
+  C rp[NQP][4];
+#pragma unroll
+  for (int k = 0; k < NQP; ++k) {
+    const int q = tid + 256 * k;
+    const int rr = q / GP, g = q - rr * GP;
+    const int I = z0 - R + rr, J = x0 - HXS + 4 * g;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) rp[k][e] = C(0);
+    if (q < HP * GP && I >= 0 && I < NZ && J < NX) ld4(rp[k], pA + (long long)I * P + J);
+  }
+  C rvx[NQX][4];
+#pragma unroll
+  for (int k = 0; k < NQX; ++k) {
+    const int q = tid + 256 * k;
+    const int rr = q / GVX, g = q - rr * GVX;
+    const int I = z0 + rr, J = x0 - 4 + 4 * g;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) rvx[k][e] = C(0);
+    if (q < TZ * GVX && I < NZ && J < NX) ld4(rvx[k], vxA + (long long)I * P + J);
+  }
+  C rvz[NQZ][4];
+#pragma unroll
+  for (int k = 0; k < NQZ; ++k) {
+    const int q = tid + 256 * k;
+    const int rr = q >> 4, g = q & 15;
+    const int I = z0 - K + rr, J = x0 + 4 * g;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) rvz[k][e] = C(0);
+    if (q < HVZ * GT && I >= 0 && I < NZ && J < NX) ld4(rvz[k], vzA + (long long)I * P + J);
+  }
+  C rck[NQT][4], rau[NQT][4];
+#pragma unroll
+  for (int k = 0; k < NQT; ++k) {
+    const int q = tid + 256 * k;
+    const int rr = q >> 4, g = q & 15;
+    const int I = z0 + rr, J = x0 + 4 * g;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) rck[k][e] = rau[k][e] = C(0);
+    if (q < TZ * GT && I < NZ && J < NX) {
+      ld4(rck[k], ckp + (long long)I * P + J);
+      if (frame_tile) ld4(rau[k], auA + (long long)I * P + J);
+    }
+  }
+  bool use_px = false;
+  C rax[ADJ ? NQA : 1][4];
+  if constexpr (ADJ) {
+    // the transposed x-stencil reads P~_x = P~_z + aux where the frame is near
+    use_px = (z0 < L) || (z1 > NZ - L) || (x0 - HXS < L) || (x1 + HXS > NX - L);
+#pragma unroll
+    for (int k = 0; k < NQA; ++k) {
+      const int q = tid + 256 * k;
+      const int rr = q / GP, g = q - rr * GP;
+      const int I = z0 + rr, J = x0 - HXS + 4 * g;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) rax[k][e] = C(0);
+      if (use_px && q < TZ * GP && I < NZ && J < NX) ld4(rax[k], auA + (long long)I * P + J);
+    }
+  }
+
+  // ---- stage p^n (and P~_x) in LDS --------------------------------------
+#pragma unroll
+  for (int k = 0; k < NQP; ++k) {
+    const int q = tid + 256 * k;
+    if (q < HP * GP) st4(sP + 4 * q, rp[k]);
+  }
+  if constexpr (ADJ) {
+    if (use_px) {
+#pragma unroll
+      for (int k = 0; k < NQA; ++k) {
+        const int q = tid + 256 * k;
+        if (q < TZ * GP) st4(sPX + 4 * q, rax[k]);
+      }
+    }
+  }
+  __syncthreads();
+  if constexpr (ADJ) {
+    if (use_px) {
+      // P~_x = P~_z + aux (tile row rr of sPX is row rr + R of sP)
+#pragma unroll
+      for (int k = 0; k < NQA; ++k) {
+        const int q = tid + 256 * k;
+        if (q < TZ * GP) {
+          C pz[4], ax[4], s[4];
+          ld4(pz, sP + 4 * q + R * WP);
+          ld4(ax, sPX + 4 * q);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) s[e] = pz[e] + ax[e];
+          st4(sPX + 4 * q, s);
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // pressure-line sampling (p^n)
+  if (a.vs.n >= 0 && a.vsl.row0 >= z0 && a.vsl.row0 < z1 && tid < TX) {
+    const int J = x0 + tid;
+    if (J >= a.vsl.col0 && J < a.vsl.col0 + a.vsl.ntr && J < NX) {
+      const int r0 = a.vsl.row0 - z0 + R, r1 = a.vsl.row1 - z0 + R;
+      const C val =
+          C(a.vsl.w0) * sP[r0 * WP + tid + HXS] + C(a.vsl.w1) * sP[r1 * WP + tid + HXS];
+      line_out<C, V>(a.vsl, a.vs, J, shot, val);
+    }
+  }
+
+  // ---- v_x on the tile rows, columns x0-4 .. x1+3 ------------------------
+#pragma unroll
+  for (int k = 0; k < NQX; ++k) {
+    const int q = tid + 256 * k;
+    if (q >= TZ * GVX) continue;
+    const int rr = q / GVX, g = q - rr * GVX;
+    const int I = z0 + rr, J = x0 - 4 + 4 * g;
+    C val[4] = {C(0), C(0), C(0), C(0)};
+    if (I < NZ) {
+      const C* row = (ADJ && use_px) ? (sPX + rr * WP) : (sP + (rr + R) * WP);
+      C w[12];  // staged p at columns J-4 .. J+7
+      ld4(*reinterpret_cast<C(*)[4]>(w), row + 4 * g);
+      ld4(*reinterpret_cast<C(*)[4]>(w + 4), row + 4 * g + 4);
+      ld4(*reinterpret_cast<C(*)[4]>(w + 8), row + 4 * g + 8);
+      C ax[4], bx[4];
+      ld4(ax, pm.xa(2, J));
+      ld4(bx, pm.xa(3, J));
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (J + e >= 0 && J + e < NX) {
+          C sx = C(0);
+#pragma unroll
+          for (int m = 1; m <= K; ++m) sx = acc(sx, wst<K, C>(m - 1), w[e + 4 + m], w[e + 5 - m]);
+          val[e] = rnd<T>(upd_v<ADJ>(ax[e], bx[e], cb, rvx[k][e], sx, C(0)));
+        }
+      }
+      if (g >= 1 && g <= GT && J < NX) {
+        T* dst = vxB + (long long)I * P + J;
+        if (J + 3 < NX) {
+          st4(dst, val);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (J + e < NX) stc(dst + e, val[e]);
+        }
+      }
+    }
+    st4(sVX + 4 * q, val);
+  }
+  // ---- v_z on the tile columns, rows z0-K .. z1+K-2 ----------------------
+#pragma unroll
+  for (int k = 0; k < NQZ; ++k) {
+    const int q = tid + 256 * k;
+    if (q >= HVZ * GT) continue;
+    const int rr = q >> 4, g = q & 15;
+    const int I = z0 - K + rr, J = x0 + 4 * g;
+    C val[4] = {C(0), C(0), C(0), C(0)};
+    if (I >= 0 && I < NZ) {
+      const int r0 = rr - K + R;  // staged row of I
+      C sz[4] = {C(0), C(0), C(0), C(0)};
+#pragma unroll
+      for (int m = 1; m <= K; ++m) {
+        C hi[4], lo[4];
+        ld4(hi, sP + (r0 + m) * WP + 4 * g + HXS);
+        ld4(lo, sP + (r0 + 1 - m) * WP + 4 * g + HXS);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sz[e] = acc(sz[e], wst<K, C>(m - 1), hi[e], lo[e]);
+      }
+      const C az = pm.azh(I), bz = pm.bzh(I);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (J + e < NX) {
+          const C src = line_src<C, V>(a.vil, a.vi, I, J + e, shot);
+          val[e] = rnd<T>(upd_v<ADJ>(az, bz, cb, rvz[k][e], sz[e], src));
+        }
+      }
+      if (I >= z0 && I < z1 && J < NX) {
+        T* dst = vzB + (long long)I * P + J;
+        if (J + 3 < NX) {
+          st4(dst, val);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (J + e < NX) stc(dst + e, val[e]);
+        }
+      }
+    }
+    st4(sVZ + 4 * q, val);
+  }
+  __syncthreads();
+
+  // v_z-line sampling (v^{n+1/2})
+  if (a.ps.n >= 0 && a.psl.row0 >= z0 && a.psl.row0 < z1 && tid < TX) {
+    const int J = x0 + tid;
+    if (J >= a.psl.col0 && J < a.psl.col0 + a.psl.ntr && J < NX) {
+      const int r0 = a.psl.row0 - z0 + K, r1 = a.psl.row1 - z0 + K;
+      const C val = C(a.psl.w0) * sVZ[r0 * TX + tid] + C(a.psl.w1) * sVZ[r1 * TX + tid];
+      line_out<C, V>(a.psl, a.ps, J, shot, val);
+    }
+  }
+
+  // ---- p^{n+1} on the tile ----------------------------------------------
+#pragma unroll
+  for (int k = 0; k < NQT; ++k) {
+    const int q = tid + 256 * k;
+    if (q >= TZ * GT) continue;
+    const int rr = q >> 4, g = q & 15;
+    const int I = z0 + rr, J = x0 + 4 * g;
+    if (I >= NZ || J >= NX) continue;
+    C w[12];  // v_x at columns J-4 .. J+7
+    ld4(*reinterpret_cast<C(*)[4]>(w), sVX + rr * WVX + 4 * g);
+    ld4(*reinterpret_cast<C(*)[4]>(w + 4), sVX + rr * WVX + 4 * g + 4);
+    ld4(*reinterpret_cast<C(*)[4]>(w + 8), sVX + rr * WVX + 4 * g + 8);
+    C dx[4] = {C(0), C(0), C(0), C(0)}, dz[4] = {C(0), C(0), C(0), C(0)};
+#pragma unroll
+    for (int m = 1; m <= K; ++m) {
+      C hi[4], lo[4];
+      ld4(hi, sVZ + (rr + K + m - 1) * TX + 4 * g);
+      ld4(lo, sVZ + (rr + K - m) * TX + 4 * g);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        dx[e] = acc(dx[e], wst<K, C>(m - 1), w[e + m + 3], w[e + 4 - m]);
+        dz[e] = acc(dz[e], wst<K, C>(m - 1), hi[e], lo[e]);
+      }
+    }
+    C pc[4];
+    ld4(pc, sP + (rr + R) * WP + 4 * g + HXS);
+    C pn[4];
+    const long long o = (long long)I * P + J;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int Je = J + e;
+      const C src = line_src<C, V>(a.pil, a.pi, I, Je, shot);
+      const bool frame = frame_tile && (I < L || I >= NZ - L || Je < L || Je >= NX - L);
+      if (!frame) {
+        pn[e] = upd_p<ADJ>(rck[k][e], pc[e], dx[e], dz[e], src);
+      } else {
+        C an;
+        pn[e] = upd_p_frame<ADJ>(rck[k][e], pc[e], rau[k][e], dx[e], dz[e], src, pm.axn(Je),
+                                 pm.bxn(Je), pm.azn(I), pm.bzn(I), &an);
+        if (Je < NX) stc(auB + o + e, an);
+      }
+    }
+    if (J + 3 < NX) {
+      st4(pB + o, pn);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (J + e < NX) stc(pB + o + e, pn[e]);
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_sample_p(Fields f, GridDims g, LineDev sl, TraceIO so) {
+  using C = typename Tr<T>::C;
+  using V = typename Tr<T>::V;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int shot = blockIdx.y;
+  if (k >= sl.ntr) return;
+  const long long base = g.origin + (long long)shot * g.field_stride;
+  const T* p = static_cast<const T*>(f.p) + base;
+  const int J = sl.col0 + k;
+  const C val = C(sl.w0) * ldc<C>(p + (long long)sl.row0 * g.pitch + J) +
+                C(sl.w1) * ldc<C>(p + (long long)sl.row1 * g.pitch + J);
+  line_out<C, V>(sl, so, J, shot, val);
+}
+
+__global__ void k_zero(uint32_t* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+template <int K, bool ADJ, typename T>
+static hipError_t vel_t(const Fields& f, const GridDims& g, const Coef& c, const LineDev& sl,
+                        const TraceIO& so, const LineDev& il, const TraceIO& io, int ns,
+                        hipStream_t s) {
+  dim3 grid((g.NX + TBX - 1) / TBX, (g.NZ + TBY - 1) / TBY, ns);
+  hipLaunchKernelGGL((k_vel<K, ADJ, T>), grid, dim3(TBX, TBY), 0, s, f, g, c, sl, so, il, io);
+  return hipGetLastError();
+}
+template <int K, bool ADJ, typename T>
+static hipError_t pres_t(const Fields& f, const GridDims& g, const Coef& c, const LineDev& sl,
+                         const TraceIO& so, const LineDev& il, const TraceIO& io, int ns,
+                         hipStream_t s) {
+  dim3 grid((g.NX + TBX - 1) / TBX, (g.NZ + TBY - 1) / TBY, ns);
+  hipLaunchKernelGGL((k_pres<K, ADJ, T>), grid, dim3(TBX, TBY), 0, s, f, g, c, sl, so, il, io);
+  return hipGetLastError();
+}
+template <int K, bool ADJ, typename T>
+static hipError_t step_t(int tz, const StepArgs& a, hipStream_t s) {
+  const int nb = a.ntx * a.ntz * a.nshots;
+  switch (tz) {
+    case 8: hipLaunchKernelGGL((k_step<K, ADJ, T, 8>), dim3(nb), dim3(256), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_step<K, ADJ, T, 16>), dim3(nb), dim3(256), 0, s, a); break;
+    case 32:
+      if constexpr (sizeof(T) < 8) {
+        hipLaunchKernelGGL((k_step<K, ADJ, T, 32>), dim3(nb), dim3(256), 0, s, a);
+        break;
+      }
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+#define SSX_DISPATCH(FN, ...)                                                        \
+  do {                                                                               \
+    const bool o8 = (order == 8);                                                    \
+    switch (dt) {                                                                    \
+      case Dt::F64:                                                                  \
+        if (o8) return adj ? FN<4, true, double>(__VA_ARGS__) : FN<4, false, double>(__VA_ARGS__); \
+        return adj ? FN<2, true, double>(__VA_ARGS__) : FN<2, false, double>(__VA_ARGS__);         \
+      case Dt::F32:                                                                  \
+        if (o8) return adj ? FN<4, true, float>(__VA_ARGS__) : FN<4, false, float>(__VA_ARGS__);   \
+        return adj ? FN<2, true, float>(__VA_ARGS__) : FN<2, false, float>(__VA_ARGS__);           \
+      case Dt::F16:                                                                  \
+        if (o8) return adj ? FN<4, true, __half>(__VA_ARGS__) : FN<4, false, __half>(__VA_ARGS__); \
+        return adj ? FN<2, true, __half>(__VA_ARGS__) : FN<2, false, __half>(__VA_ARGS__);         \
+      case Dt::BF16:                                                                 \
+        if (o8)                                                                      \
+          return adj ? FN<4, true, __hip_bfloat16>(__VA_ARGS__)                     \
+                     : FN<4, false, __hip_bfloat16>(__VA_ARGS__);                   \
+        return adj ? FN<2, true, __hip_bfloat16>(__VA_ARGS__)                       \
+                   : FN<2, false, __hip_bfloat16>(__VA_ARGS__);                     \
+    }                                                                                \
+    return hipErrorInvalidValue;                                                     \
+  } while (0)
+
+hipError_t launch_vel(Dt dt, int order, bool adj, const Fields& f, const GridDims& g,
+                      const Coef& c, const LineDev& sl, const TraceIO& so, const LineDev& il,
+                      const TraceIO& io, int nshots, hipStream_t s) {
+  SSX_DISPATCH(vel_t, f, g, c, sl, so, il, io, nshots, s);
+}
+
+hipError_t launch_pres(Dt dt, int order, bool adj, const Fields& f, const GridDims& g,
+                       const Coef& c, const LineDev& sl, const TraceIO& so, const LineDev& il,
+                       const TraceIO& io, int nshots, hipStream_t s) {
+  SSX_DISPATCH(pres_t, f, g, c, sl, so, il, io, nshots, s);
+}
+
+hipError_t launch_step(Dt dt, int order, bool adj, int tz, StepArgs a, hipStream_t s) {
+  SSX_DISPATCH(step_t, tz, a, s);
+}
+
+int step_tile_width() { return TX; }
+
+hipError_t launch_sample_p(Dt dt, const Fields& f, const GridDims& g, const LineDev& line,
+                           const TraceIO& io, int nshots, hipStream_t s) {
+  dim3 grid((line.ntr + 255) / 256, nshots);
+  switch (dt) {
+    case Dt::F64: hipLaunchKernelGGL(k_sample_p<double>, grid, dim3(256), 0, s, f, g, line, io); break;
+    case Dt::F32: hipLaunchKernelGGL(k_sample_p<float>, grid, dim3(256), 0, s, f, g, line, io); break;
+    case Dt::F16: hipLaunchKernelGGL(k_sample_p<__half>, grid, dim3(256), 0, s, f, g, line, io); break;
+    case Dt::BF16:
+      hipLaunchKernelGGL(k_sample_p<__hip_bfloat16>, grid, dim3(256), 0, s, f, g, line, io);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(void* ptr, size_t bytes, hipStream_t s) {
+  const size_t n = bytes / 4;
+  if (n == 0) return hipSuccess;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s,
+                     static_cast<uint32_t*>(ptr), n);
+  return hipGetLastError();
+}
+
+}  // namespace ssx

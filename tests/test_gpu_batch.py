@@ -1,0 +1,78 @@
+"""Batched shots (several subproblems in one launch per time step) against
+the same subproblems run one at a time, and the batched configuration at
+full size against the oracle."""
+import numpy as np
+import pytest
+
+import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2203_16573_amd as ssx  # noqa: E402
+
+RHO = 1000.0
+
+
+def problem(xs, **kw):
+    base = dict(nz=41, nx=130, h=10.0, dt=1e-3, nt=150, order=8, npml=12,
+                z_src=20.0, x_src0=0.0, ns=130, z_rec=10.0, x_rec0=0.0, nr=130,
+                slab_dz=5, xs=tuple(xs))
+    base.update(kw)
+    return inputs.Problem(**base)
+
+
+@pytest.mark.parametrize("fd", ["f64", "f32", "f16"])
+def test_batched_equals_looped_bitwise(fd):
+    xs = (105.0, 431.0, 777.0, 1212.0)
+    prob = problem(xs)
+    print(f"case batched-vs-looped dtype={fd}", flush=True)
+    kap = inputs.kappa_from_velocity(
+        inputs.layered_velocity(prob.nz, prob.nx, prob.h, np.random.default_rng(3)))
+    vdt = torch.float64 if fd == "f64" else torch.float32
+    rng = np.random.default_rng(4)
+    d = torch.tensor(rng.standard_normal((len(xs), prob.nt, prob.nr)), dtype=vdt, device="cuda")
+    h = torch.tensor(rng.standard_normal((len(xs), prob.nt, prob.ns)), dtype=vdt, device="cuda")
+    batch = ssx.Context(prob, kap, RHO, field_dtype=fd)
+    outs_b = [batch.fwd(h, batch.empty_r()), batch.adj(d, batch.empty_s()),
+              batch.precond(1e-3, h, batch.empty_s())]
+    hb, histb, _, _ = batch.pcg_solve(d, 1e-3, 4)
+    torch.cuda.synchronize()
+    for s, x in enumerate(xs):
+        one = ssx.Context(prob.replace(xs=(x,)), kap, RHO, field_dtype=fd)
+        hs, ds = h[s:s + 1].contiguous(), d[s:s + 1].contiguous()
+        outs_1 = [one.fwd(hs, one.empty_r()), one.adj(ds, one.empty_s()),
+                  one.precond(1e-3, hs, one.empty_s())]
+        h1, hist1, _, _ = one.pcg_solve(ds, 1e-3, 4)
+        torch.cuda.synchronize()
+        for ob, o1 in zip(outs_b, outs_1):
+            assert torch.equal(ob[s], o1[0]), s
+        assert torch.equal(hb[s], h1[0])
+        assert np.array_equal(histb[s], hist1[0])
+        one.close()
+    batch.close()
+
+
+def test_c3_full_size_truncated_parity():
+    # 64 shots on the 401 x 801 layered model in one launch per step
+    # (nt = 2000): first / last N samples of two shots against the oracle
+    import oracle
+    wl = inputs.workload(3)
+    prob = wl.prob
+    N = 30
+    print("case c3 truncated parity", flush=True)
+    rng = np.random.default_rng(9)
+    h = np.zeros((prob.nshots, prob.nt, prob.ns), dtype=np.float32)
+    h[:, :N] = rng.standard_normal((prob.nshots, N, prob.ns))
+    r = np.zeros((prob.nshots, prob.nt, prob.nr), dtype=np.float32)
+    r[:, -N:] = rng.standard_normal((prob.nshots, N, prob.nr))
+    ctx = ssx.Context(prob, wl.kappa, wl.rho, field_dtype="f32")
+    d = ctx.fwd(torch.tensor(h, device="cuda"), ctx.empty_r()).cpu().numpy()
+    g = ctx.adj(torch.tensor(r, device="cuda"), ctx.empty_s()).cpu().numpy()
+    ctx.close()
+    m = oracle.Model(prob.replace(nt=N), wl.kappa, wl.rho)
+    for s in (0, 63):
+        dr = m.fwd(h[s, :N].astype(np.float64))
+        gr = m.adj(r[s, -N:].astype(np.float64))
+        assert np.linalg.norm(d[s, :N] - dr) / np.linalg.norm(dr) < 1e-5
+        assert np.linalg.norm(g[s, -N:] - gr) / np.linalg.norm(gr) < 1e-5

@@ -1,0 +1,87 @@
+"""Serving: requests of different sizes admitted as memory and slots free
+up, overlapping on the device; every result equals the same request solved
+alone, and the mixed-precision solutions stay close to the FP64 oracle."""
+import numpy as np
+import pytest
+
+import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2203_16573_amd as ssx  # noqa: E402
+from paper_2203_16573_amd import serve  # noqa: E402
+
+RHO = 1000.0
+SHAPES = ((31, 61, 20.0), (41, 81, 15.0), (25, 101, 20.0))
+
+
+def make_requests(n=6, K=3, fd="f16"):
+    reqs = []
+    for i in range(n):
+        nz, nx, h = SHAPES[i % len(SHAPES)]
+        nshots = 1 + (i % 3)
+        nt = 120 + 20 * (i % 4)
+        rng = np.random.default_rng(100 + i)
+        vel = inputs.layered_velocity(nz, nx, h, rng, zrange=(2 * h, (nz - 2) * h),
+                                      min_gap=2 * h)
+        dt = 0.25 * h / vel.max() * 2.0
+        prob = inputs.Problem(nz=nz, nx=nx, h=h, dt=dt, nt=nt, order=8, npml=10,
+                              z_src=4 * h, x_src0=0.0, ns=nx, z_rec=2 * h, x_rec0=0.0,
+                              nr=nx, slab_dz=5,
+                              xs=tuple((k + 0.5) * (nx - 1) * h / nshots for k in range(nshots)))
+        kap = inputs.kappa_from_velocity(vel)
+        # data of a Ricker point source at each shot's x_s (d = F h_true)
+        gen = ssx.Context(prob, kap, RHO, field_dtype="f32")
+        wav = inputs.source_wavelet(prob, 0.5 / (4 * dt * 5))
+        ht = np.stack([inputs.spike_gather(prob, wav, s) for s in range(nshots)])
+        d = gen.fwd(torch.tensor(ht, dtype=torch.float32, device="cuda"), gen.empty_r())
+        torch.cuda.synchronize()
+        gen.close()
+        reqs.append(serve.Request(i, prob, kap, RHO, d, K=K, field_dtype=fd,
+                                  arrival=0.004 * i))
+    torch.cuda.synchronize()
+    return reqs
+
+
+def test_mix_equals_alone():
+    print("case serving mix vs alone", flush=True)
+    reqs = make_requests()
+    mixed = serve.Server(budget_bytes=8 << 30, slots=3).run(reqs, realtime=True)
+    assert [r.rid for r in mixed] == list(range(len(reqs)))
+    # overlap actually happened: some request was admitted before another finished
+    spans = sorted((r.t_admit, r.t_done) for r in mixed)
+    assert any(spans[i + 1][0] < spans[i][1] for i in range(len(spans) - 1))
+    for req, res in zip(reqs, mixed):
+        alone = serve.Server(budget_bytes=8 << 30, slots=1).run([req], realtime=False)[0]
+        assert alone.status == res.status and alone.iters == res.iters
+        assert torch.equal(alone.h, res.h), req.rid
+        assert np.array_equal(alone.hist, res.hist)
+
+
+def test_budget_limits_residency():
+    print("case serving budget", flush=True)
+    reqs = make_requests(n=4)
+    need = max(serve.request_bytes(r) for r in reqs)
+    res = serve.Server(budget_bytes=need, slots=4).run(reqs, realtime=False)
+    spans = sorted((r.t_admit, r.t_done) for r in res)
+    # each request needs more than half of the budget: never two at once
+    if all(2 * serve.request_bytes(r) > need for r in reqs):
+        for a, b in zip(spans, spans[1:]):
+            assert b[0] >= a[1] - 1e-3
+
+
+@pytest.mark.parametrize("fd,tol", [("f16", 3e-2), ("bf16", 1e-1), ("f32", 1e-4)])
+def test_served_solution_against_oracle(fd, tol):
+    import oracle
+    print(f"case serving vs oracle {fd}", flush=True)
+    req = make_requests(n=1, K=3, fd=fd)[0]
+    res = serve.Server(budget_bytes=8 << 30, slots=1).run([req], realtime=False)[0]
+    m = oracle.Model(req.prob, req.kappa, RHO)
+    d = req.d.double().cpu().numpy()
+    h_ref, hist_ref, _ = oracle.pcg_solve(m, d[0], req.alpha_rel, req.K)
+    h = res.h.double().cpu().numpy()[0]
+    err = np.linalg.norm(h - h_ref) / np.linalg.norm(h_ref)
+    herr = np.abs(res.hist[0][:, 0] - hist_ref[:, 0]) / hist_ref[:, 0]
+    print(f"{fd}: solution rel err {err:.3e}; per-iteration ||r|| rel err {herr}")
+    assert err < tol
