@@ -47,6 +47,11 @@ def parse():
     ap.add_argument("--prop-only", type=int, default=0,
                     help="run this many forward+adjoint propagation pairs and exit "
                          "(a short workload for kernel profiling)")
+    ap.add_argument("--nt", type=int, default=0,
+                    help="with --prop-only: override the record length")
+    ap.add_argument("--calib-copy", type=float, default=0.0,
+                    help="with --prop-only: also run 10 plain device copies of this many "
+                         "MB (reference for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -81,6 +86,8 @@ def main():
         return serve_bench(args)
     cnum = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "c4bf": 4}[args.config]
     wl = inputs.workload(cnum)
+    if args.prop_only and args.nt:
+        wl.prob = wl.prob.replace(nt=args.nt)
     prob = wl.prob
     fd = {"c1": "f64", "c2": "f32", "c3": "f32", "c4": "f16", "c4bf": "bf16"}[args.config]
     vdt = torch.float64 if fd == "f64" else torch.float32
@@ -98,6 +105,13 @@ def main():
     h = ctx.empty_s()
     torch.cuda.synchronize()
     if args.prop_only:
+        if args.calib_copy:
+            n = int(args.calib_copy * 1e6 / 4)
+            src = torch.ones(n, device="cuda")
+            dst = torch.empty_like(src)
+            for _ in range(10):
+                dst.copy_(src)
+            torch.cuda.synchronize()
         g = ctx.empty_s()
         t0 = time.perf_counter()
         for _ in range(args.prop_only):
