@@ -191,12 +191,18 @@ ssx_status ssx_pcg_solve(ssx_ctx* ctx, const void* d, double alpha_rel, int32_t 
  *                       and the thin slab: 8, 16 or 32 (32 not for F64
  *                       fields); 0 picks a default from the grid size.
  *   SSX_OPT_TILE_Z_SLAB the same for the thin slab only.
+ *   SSX_OPT_STEPS_PER_LAUNCH      time steps fused per launch of the fused
+ *                       kernel on the full grid: 1 (default) or 2 (2: F32
+ *                       fields only; uses a tile height of 8).
+ *   SSX_OPT_STEPS_PER_LAUNCH_SLAB the same for the thin slab.
  * Returns SSX_ERR_ARG for an unknown option or value. */
 typedef enum {
   SSX_OPT_GRAPHS = 0,
   SSX_OPT_STEP_KERNEL = 1,
   SSX_OPT_TILE_Z = 2,
-  SSX_OPT_TILE_Z_SLAB = 3
+  SSX_OPT_TILE_Z_SLAB = 3,
+  SSX_OPT_STEPS_PER_LAUNCH = 4,
+  SSX_OPT_STEPS_PER_LAUNCH_SLAB = 5
 } ssx_option;
 ssx_status ssx_set_option(ssx_ctx* ctx, int option, int value);
 

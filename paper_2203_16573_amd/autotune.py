@@ -15,9 +15,10 @@ import json
 import os
 import threading
 
-from . import (OPT_STEP_KERNEL, OPT_TILE_Z, OPT_TILE_Z_SLAB, Context)
+from . import (OPT_STEP_KERNEL, OPT_STEPS_PER_LAUNCH, OPT_STEPS_PER_LAUNCH_SLAB, OPT_TILE_Z,
+               OPT_TILE_Z_SLAB, Context)
 
-DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ssx", "autotune.json")
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ssx", "autotune-v2.json")
 _lock = threading.Lock()
 
 
@@ -72,25 +73,36 @@ def tune(prob, kappa, rho, xs=None, field_dtype="f32", nt_tune: int = 60,
     d = ctx.empty_r()
     g = ctx.empty_s()
     P, V = ctx.empty_s(), ctx.empty_s()
-    tiles = (8, 16) if field_dtype == "f64" else (8, 16, 32)
+    # candidates: (steps per launch, tile height)
+    if field_dtype == "f64":
+        cands = [(1, 8), (1, 16)]
+    elif field_dtype == "f32":
+        cands = [(1, 8), (1, 16), (1, 32), (2, 8)]
+    else:  # two steps per launch are FP32-only
+        cands = [(1, 8), (1, 16), (1, 32)]
     us = {}
     ctx.set_option(OPT_STEP_KERNEL, 1)
-    for tz in tiles:
+    for spl, tz in cands:
         ctx.set_option(OPT_TILE_Z, tz)
-        us[f"full_fused_tz{tz}"] = 1e3 * _time_ms(lambda: (ctx.fwd(h, d), ctx.adj(d, g))) / (2 * nt)
-        us[f"slab_fused_tz{tz}"] = 1e3 * _time_ms(
+        ctx.set_option(OPT_STEPS_PER_LAUNCH, spl)
+        tag = f"s{spl}_tz{tz}"
+        us[f"full_{tag}"] = 1e3 * _time_ms(lambda: (ctx.fwd(h, d), ctx.adj(d, g))) / (2 * nt)
+        us[f"slab_{tag}"] = 1e3 * _time_ms(
             lambda: (ctx.slab_fwd(h, P, V), ctx.slab_adj(V, P, g))) / (2 * nt)
+    ctx.set_option(OPT_STEPS_PER_LAUNCH, 1)
     ctx.set_option(OPT_STEP_KERNEL, 0)
     us["full_split"] = 1e3 * _time_ms(lambda: (ctx.fwd(h, d), ctx.adj(d, g))) / (2 * nt)
     us["slab_split"] = 1e3 * _time_ms(
         lambda: (ctx.slab_fwd(h, P, V), ctx.slab_adj(V, P, g))) / (2 * nt)
     ctx.close()
-    best_full = min(tiles, key=lambda t: us[f"full_fused_tz{t}"])
-    best_slab = min(tiles, key=lambda t: us[f"slab_fused_tz{t}"])
-    fused_total = us[f"full_fused_tz{best_full}"] + us[f"slab_fused_tz{best_slab}"]
+    best_full = min(cands, key=lambda c: us[f"full_s{c[0]}_tz{c[1]}"])
+    best_slab = min(cands, key=lambda c: us[f"slab_s{c[0]}_tz{c[1]}"])
+    fused_total = us[f"full_s{best_full[0]}_tz{best_full[1]}"] + \
+        us[f"slab_s{best_slab[0]}_tz{best_slab[1]}"]
     split_total = us["full_split"] + us["slab_split"]
-    return {"step_kernel": 1 if fused_total <= split_total else 0, "tile_z": best_full,
-            "tile_z_slab": best_slab, "us": us}
+    return {"step_kernel": 1 if fused_total <= split_total else 0,
+            "steps_per_launch": best_full[0], "tile_z": best_full[1],
+            "steps_per_launch_slab": best_slab[0], "tile_z_slab": best_slab[1], "us": us}
 
 
 def choose(prob, kappa, rho, xs=None, field_dtype="f32", cache_path: str | None = DEFAULT_CACHE,
@@ -117,3 +129,5 @@ def apply(ctx: Context, choice: dict) -> None:
     ctx.set_option(OPT_STEP_KERNEL, int(choice["step_kernel"]))
     ctx.set_option(OPT_TILE_Z, int(choice["tile_z"]))
     ctx.set_option(OPT_TILE_Z_SLAB, int(choice["tile_z_slab"]))
+    ctx.set_option(OPT_STEPS_PER_LAUNCH, int(choice.get("steps_per_launch", 1)))
+    ctx.set_option(OPT_STEPS_PER_LAUNCH_SLAB, int(choice.get("steps_per_launch_slab", 1)))

@@ -251,7 +251,7 @@ struct GridDev {
 struct GraphEntry {
   int op;
   const void* ptr[4];
-  int tile_z, fused;
+  int tile_z, fused, spl;
   hipGraphExec_t exec;
   unsigned long long last_use;
 };
@@ -278,6 +278,7 @@ struct ssx_ctx {
   bool graphs = true;
   bool fused = true;
   int tile_z_full = 0, tile_z_slab = 0;  // 0: default
+  int spl_full = 1, spl_slab = 1;        // time steps per fused launch
   hipStream_t cap_stream = nullptr;      // capture stream (graphs are launched on `stream`)
   std::vector<GraphEntry> graphs_cache;
   unsigned long long use_clock = 0;
@@ -457,8 +458,11 @@ ssx_status issue_propagation(ssx_ctx* c, GridDev& gd, bool adj, const LineDev& v
     }
     return SSX_OK;
   }
-  // fused: one launch per step, ping-pong between the two field buffers
-  const int tz_opt = (&gd == &c->full) ? c->tile_z_full : c->tile_z_slab;
+  // fused: one launch per step (or per two steps), ping-pong between the two
+  // field buffers
+  const bool is_full = (&gd == &c->full);
+  const int spl = is_full ? c->spl_full : c->spl_slab;
+  const int tz_opt = is_full ? c->tile_z_full : c->tile_z_slab;
   const int tz = tz_opt ? tz_opt : default_tile_z(c, gd);
   StepArgs a;
   a.g = gd.dims;
@@ -468,25 +472,44 @@ ssx_status issue_propagation(ssx_ctx* c, GridDev& gd, bool adj, const LineDev& v
   a.psl = psl;
   a.pil = pil;
   a.ntx = (gd.host.NX + step_tile_width() - 1) / step_tile_width();
-  a.ntz = (gd.host.NZ + tz - 1) / tz;
   a.nshots = ns;
+  a.nt = nt;
+  a.dir = adj ? -1 : 1;
+  const int ntz1 = (gd.host.NZ + tz - 1) / tz;
+  const int ntz2 = (gd.host.NZ + STEP2_TZ - 1) / STEP2_TZ;
   Fields buf[2] = {gd.fields, gd.fields1};
   int cur = 0;
-  if (!adj) {
-    for (int n = 0; n < nt; ++n) {
-      a.in = buf[cur];
-      a.out = buf[1 - cur];
-      a.vs = vs;
-      a.vs.n = (vs.out && n >= 1) ? n - 1 : -1;
-      a.vi = vi;
-      a.vi.n = vi.in ? n : -1;
-      a.ps = ps;
-      a.ps.n = ps.out ? n : -1;
-      a.pi = pi;
-      a.pi.n = pi.in ? n : -1;
-      SSX_HIP(launch_step(c->fdt, order, false, tz, a, s));
-      cur = 1 - cur;
+  // one launch covering `steps` (1 or 2) steps starting at step n with the
+  // given level-0 trace indices
+  auto launch = [&](int steps, int ivs, int ivi, int ips, int ipi) -> ssx_status {
+    a.in = buf[cur];
+    a.out = buf[1 - cur];
+    a.vs = vs;
+    a.vi = vi;
+    a.ps = ps;
+    a.pi = pi;
+    if (steps == 2) {
+      a.vs.n = ivs;
+      a.vi.n = ivi;
+      a.ps.n = ips;
+      a.pi.n = ipi;
+      a.ntz = ntz2;
+      SSX_HIP(launch_step2(c->fdt, order, adj, a, s));
+    } else {
+      a.vs.n = (vs.out && ivs >= 0 && ivs < nt) ? ivs : -1;
+      a.vi.n = (vi.in && ivi >= 0 && ivi < nt) ? ivi : -1;
+      a.ps.n = (ps.out && ips >= 0 && ips < nt) ? ips : -1;
+      a.pi.n = (pi.in && ipi >= 0 && ipi < nt) ? ipi : -1;
+      a.ntz = ntz1;
+      SSX_HIP(launch_step(c->fdt, order, adj, tz, a, s));
     }
+    cur = 1 - cur;
+    return SSX_OK;
+  };
+  if (!adj) {
+    int n = 0;
+    for (; n + spl <= nt; n += spl) SSX_TRY(launch(spl, n - 1, n, n, n));
+    for (; n < nt; ++n) SSX_TRY(launch(1, n - 1, n, n, n));
     if (vs.out) {
       vs.n = nt - 1;
       SSX_HIP(launch_sample_p(c->fdt, buf[cur], gd.dims, vsl, vs, ns, s));
@@ -496,20 +519,9 @@ ssx_status issue_propagation(ssx_ctx* c, GridDev& gd, bool adj, const LineDev& v
     TraceIO p0 = pi;
     p0.n = pi.in ? nt - 1 : -1;
     SSX_HIP(launch_pres(c->fdt, order, true, buf[0], gd.dims, gd.coef, psl, none, pil, p0, ns, s));
-    for (int n = nt - 1; n >= 0; --n) {
-      a.in = buf[cur];
-      a.out = buf[1 - cur];
-      a.vs = vs;
-      a.vs.n = vs.out ? n : -1;
-      a.vi = vi;
-      a.vi.n = vi.in ? n : -1;
-      a.ps = ps;
-      a.ps.n = ps.out ? n : -1;
-      a.pi = pi;
-      a.pi.n = (pi.in && n >= 1) ? n - 1 : -1;
-      SSX_HIP(launch_step(c->fdt, order, true, tz, a, s));
-      cur = 1 - cur;
-    }
+    int n = nt - 1;
+    for (; n - spl + 1 >= 0; n -= spl) SSX_TRY(launch(spl, n, n, n, n - 1));
+    for (; n >= 0; --n) SSX_TRY(launch(1, n, n, n, n - 1));
   }
   return SSX_OK;
 }
@@ -525,9 +537,10 @@ ssx_status propagate(ssx_ctx* c, int op, GridDev& gd, bool adj, const LineDev& v
     return issue_propagation(c, gd, adj, vsl, vs, vil, vi, psl, ps, pil, pi, c->stream);
   const void* key[4] = {vs.out, vi.in, ps.out, pi.in};
   const int tz = (&gd == &c->full) ? c->tile_z_full : c->tile_z_slab;
+  const int spl = (&gd == &c->full) ? c->spl_full : c->spl_slab;
   for (GraphEntry& e : c->graphs_cache) {
     if (e.op == op && e.ptr[0] == key[0] && e.ptr[1] == key[1] && e.ptr[2] == key[2] &&
-        e.ptr[3] == key[3] && e.tile_z == tz && e.fused == (int)c->fused) {
+        e.ptr[3] == key[3] && e.tile_z == tz && e.fused == (int)c->fused && e.spl == spl) {
       e.last_use = ++c->use_clock;
       SSX_HIP(hipGraphLaunch(e.exec, c->stream));
       return SSX_OK;
@@ -560,6 +573,7 @@ ssx_status propagate(ssx_ctx* c, int op, GridDev& gd, bool adj, const LineDev& v
   for (int i = 0; i < 4; ++i) ge.ptr[i] = key[i];
   ge.tile_z = tz;
   ge.fused = (int)c->fused;
+  ge.spl = spl;
   ge.exec = exec;
   ge.last_use = ++c->use_clock;
   c->graphs_cache.push_back(ge);
@@ -913,6 +927,16 @@ ssx_status ssx_set_option(ssx_ctx* c, int option, int value) {
         return fail(SSX_ERR_ARG, "tile height 32 is not available for F64 fields");
       if (option == SSX_OPT_TILE_Z) c->tile_z_full = value;
       c->tile_z_slab = value;
+      return SSX_OK;
+    case SSX_OPT_STEPS_PER_LAUNCH:
+    case SSX_OPT_STEPS_PER_LAUNCH_SLAB:
+      if (value != 1 && value != 2) return fail(SSX_ERR_ARG, "steps per launch must be 1 or 2");
+      // two steps per launch: FP32 fields only (the 16-bit instances are
+      // switched off after a device memory fault whose cause is not known)
+      if (value == 2 && c->fdt != Dt::F32)
+        return fail(SSX_ERR_ARG, "two steps per launch are available for F32 fields only");
+      if (option == SSX_OPT_STEPS_PER_LAUNCH) c->spl_full = value;
+      c->spl_slab = value;
       return SSX_OK;
   }
   return fail(SSX_ERR_ARG, "unknown option");

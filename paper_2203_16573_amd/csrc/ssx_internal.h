@@ -78,12 +78,17 @@ struct StepArgs {
   LineDev vsl, vil, psl, pil;  // velocity-phase sample/inject, pressure-phase sample/inject
   TraceIO vs, vi, ps, pi;
   int ntx, ntz, nshots;        // tiles across x, down z; shots
+  int nt;                      // record length (trace indices outside [0, nt) are skipped)
+  int dir;                     // +1 forward, -1 transposed: trace index of level t = n + dir t
 };
 
 // ---- launchers (ssx_kernels.hip) -----------------------------------------
 // One fused time step (velocity then pressure, one launch).  tz: tile height
 // (8, 16 or 32; 32 is not available for FP64 fields).
 hipError_t launch_step(Dt dt, int order, bool adj, int tz, StepArgs a, hipStream_t s);
+// Two fused time steps per launch (tile height 8; not for F64 fields).
+hipError_t launch_step2(Dt dt, int order, bool adj, StepArgs a, hipStream_t s);
+constexpr int STEP2_TZ = 8;
 int step_tile_width();
 // All return hipSuccess or the launch error.
 hipError_t launch_vel(Dt dt, int order, bool adj, const Fields& f, const GridDims& g,

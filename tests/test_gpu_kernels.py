@@ -42,10 +42,13 @@ def run_all(ctx, prob, fd, seed=0):
 
 
 @pytest.mark.parametrize("fd", ["f64", "f32", "f16", "bf16"])
-@pytest.mark.parametrize("order", [4, 8])
-def test_fused_equals_split_bitwise(fd, order):
-    prob = problem(order)
-    print(f"case fused-vs-split order={order} dtype={fd}", flush=True)
+@pytest.mark.parametrize("order,nt", [(4, 120), (8, 121)])
+def test_fused_equals_split_bitwise(fd, order, nt):
+    # one-step fused kernel at every tile height, and (except FP64) the
+    # two-steps-per-launch kernel, against the split reference; an odd
+    # record length exercises the single-step remainder
+    prob = problem(order, nt=nt)
+    print(f"case fused-vs-split order={order} nt={nt} dtype={fd}", flush=True)
     ctx = ssx.Context(prob, kappa(prob), RHO, field_dtype=fd)
     ctx.set_graphs(False)
     ctx.set_option(ssx.OPT_STEP_KERNEL, 0)
@@ -57,6 +60,16 @@ def test_fused_equals_split_bitwise(fd, order):
         fused = run_all(ctx, prob, fd)
         for a, b in zip(split, fused):
             assert np.array_equal(a, b), (fd, order, tz)
+    if fd == "f32":
+        ctx.set_option(ssx.OPT_TILE_Z, 16)
+        ctx.set_option(ssx.OPT_STEPS_PER_LAUNCH, 2)
+        two = run_all(ctx, prob, fd)
+        for i, (a, b) in enumerate(zip(split, two)):
+            assert np.array_equal(a, b), (fd, order, "two steps per launch", i)
+    else:
+        # two steps per launch are switched off for FP64 and 16-bit fields
+        with pytest.raises(ssx.SSXError):
+            ctx.set_option(ssx.OPT_STEPS_PER_LAUNCH, 2)
     ctx.close()
 
 
@@ -90,7 +103,8 @@ def test_graph_replays_equal_eager(fd):
 def test_options_rejected():
     prob = problem(8)
     ctx = ssx.Context(prob, kappa(prob), RHO, field_dtype="f64")
-    for opt, val in ((ssx.OPT_TILE_Z, 32), (ssx.OPT_TILE_Z, 12), (ssx.OPT_STEP_KERNEL, 2), (99, 1)):
+    for opt, val in ((ssx.OPT_TILE_Z, 32), (ssx.OPT_TILE_Z, 12), (ssx.OPT_STEP_KERNEL, 2),
+                     (ssx.OPT_STEPS_PER_LAUNCH, 2), (ssx.OPT_STEPS_PER_LAUNCH, 3), (99, 1)):
         with pytest.raises(ssx.SSXError):
             ctx.set_option(opt, val)
     ctx.close()
