@@ -55,7 +55,7 @@ typedef enum {
   SSX_ERR_CFL = 2,        /* dt above the stability bound                 */
   SSX_ERR_OOM = 3,        /* device allocation failed / workspace too small*/
   SSX_ERR_HIP = 4,        /* HIP runtime error (context no longer usable)  */
-  SSX_ERR_BREAKDOWN = 5,  /* PCG: <g,r> or <p,q> zero or changed sign      */
+  SSX_ERR_BREAKDOWN = 5,  /* PCG: <g,r> or <p,q> became zero               */
   SSX_ERR_NONFINITE = 6   /* PCG: a non-finite scalar appeared             */
 } ssx_status;
 
@@ -174,9 +174,12 @@ ssx_status ssx_dot(ssx_ctx* ctx, const void* x, const void* y, int64_t n,
  * rtol ||r_0|| (rtol > 0 only).  d: [nshots][nt][nr]; h_out:
  * [nshots][nt][ns].  hist_host: HOST [nshots][maxit+1][4] or NULL, row k =
  * (||r_k||, ||g_k||, <g_k, r_k>, ||F h_k - d||).  iters_host: HOST, the
- * iterations run.  Synchronises the stream before returning.  Returns
- * SSX_ERR_BREAKDOWN / SSX_ERR_NONFINITE if any shot broke down (that
- * shot's iterate is frozen at its last valid value). */
+ * iterations run.  Synchronises the stream before returning.  Algorithm 1
+ * is run as stated: a change of sign of <g,r> (M^-1 indefinite on that
+ * residual) does not stop it (hist records <g,r>).  Returns
+ * SSX_ERR_BREAKDOWN / SSX_ERR_NONFINITE if <g,r> or <p,q> became zero or
+ * non-finite for any shot (that shot's iterate is frozen at its last valid
+ * value). */
 ssx_status ssx_pcg_solve(ssx_ctx* ctx, const void* d, double alpha_rel, int32_t maxit,
                          double rtol, int32_t use_precond, void* h_out,
                          double* hist_host, int32_t* iters_host);

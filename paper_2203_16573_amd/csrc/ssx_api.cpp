@@ -905,7 +905,7 @@ ssx_status ssx_pcg_solve(ssx_ctx* c, const void* d, double alpha_rel, int32_t ma
   int worst = 0;
   for (int sh = 0; sh < ns; ++sh) worst |= (int)hrow[(size_t)sh * SC_N + SC_FLAG];
   if (worst & 2) return fail(SSX_ERR_NONFINITE, "a non-finite PCG scalar appeared");
-  if (worst & 1) return fail(SSX_ERR_BREAKDOWN, "PCG breakdown: <g,r> or <p,q> zero or sign change");
+  if (worst & 1) return fail(SSX_ERR_BREAKDOWN, "PCG breakdown: <g,r> or <p,q> became zero");
   return SSX_OK;
 }
 

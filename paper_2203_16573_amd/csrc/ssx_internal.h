@@ -137,7 +137,8 @@ constexpr int SC_N = 16;
 enum Sc { SC_GR = 0, SC_PQ = 1, SC_A = 2, SC_BETA = 3, SC_GRNEW = 4, SC_GG = 5, SC_RR = 6,
           SC_EE = 7, SC_ALPHA2 = 8, SC_FLAG = 9, SC_GR0 = 10, SC_PQ0 = 11, SC_DD = 12,
           SC_TMP = 15 };
-// SC_FLAG bits: 1 breakdown, 2 non-finite, 4 exact zero residual (converged)
+// SC_FLAG bits: 1 breakdown (zero <g,r> or <p,q>), 2 non-finite, 4 exact zero
+// residual (converged), 8 a sign change of <g,r> or <p,q> was seen (not fatal)
 // a = gr / pq (with breakdown checks), per shot
 hipError_t launch_pcg_step_length(double* sc, int nshots, hipStream_t s);
 // h += a p; r -= a q (n per shot); e += a Fp (ne per shot, e may be null)

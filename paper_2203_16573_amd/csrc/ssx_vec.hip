@@ -183,6 +183,10 @@ __global__ void k_pcg_init(double* sc, double alpha_rel, int nshots) {
 }
 
 // k == 0: start of the iteration (g_0, r_0 known); k >= 1: after iteration k-1.
+// Algorithm 1 is followed as stated: a change of sign of <g, r> or <p, q>
+// (possible when M^-1 is indefinite) is recorded (flag 8) and the iteration
+// goes on; only a zero or non-finite value stops a shot (its iterate is
+// frozen at the last valid value).
 __global__ void k_pcg_record(double* sc, double* hist, int k, int maxit, int nshots) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nshots) return;
@@ -195,15 +199,15 @@ __global__ void k_pcg_record(double* sc, double* hist, int k, int maxit, int nsh
     if (!isfinite(grn)) flag |= 2;
     else if (grn == 0.0) flag |= (c[SC_RR] == 0.0 ? 4 : 1);
     c[SC_BETA] = 0.0;
-  } else if (flag == 0) {
+  } else if ((flag & 7) == 0) {
     if (!isfinite(grn)) {
       flag |= 2;
     } else if (grn == 0.0) {
       flag |= (c[SC_RR] == 0.0 ? 4 : 1);
     } else if (!same_sign(grn, c[SC_GR0])) {
-      flag |= 1;
+      flag |= 8;
     }
-    if (flag == 0) {
+    if ((flag & 7) == 0) {
       c[SC_BETA] = grn / c[SC_GR];
       c[SC_GR] = grn;
     } else {
@@ -228,13 +232,13 @@ __global__ void k_pcg_step_length(double* sc, int nshots) {
   double* c = sc + (long long)s * SC_N;
   int flag = int(c[SC_FLAG]);
   const double pq = c[SC_PQ];
-  if (flag == 0) {
+  if ((flag & 7) == 0) {
     if (!isfinite(pq)) flag |= 2;
     else if (pq == 0.0) flag |= 1;
     else if (c[SC_PQ0] == 0.0) c[SC_PQ0] = pq;
-    else if (!same_sign(pq, c[SC_PQ0])) flag |= 1;
+    else if (!same_sign(pq, c[SC_PQ0])) flag |= 8;
   }
-  c[SC_A] = (flag == 0) ? c[SC_GR] / pq : 0.0;
+  c[SC_A] = ((flag & 7) == 0) ? c[SC_GR] / pq : 0.0;
   c[SC_FLAG] = double(flag);
 }
 
