@@ -48,7 +48,8 @@ def parse():
                     help="run this many forward+adjoint propagation pairs and exit "
                          "(a short workload for kernel profiling)")
     ap.add_argument("--nt", type=int, default=0,
-                    help="with --prop-only: override the record length")
+                    help="override the record length (for short profiling runs; the "
+                         "result line then describes that shortened workload)")
     ap.add_argument("--calib-copy", type=float, default=0.0,
                     help="with --prop-only: also run 10 plain device copies of this many "
                          "MB (reference for hardware byte counters)")
@@ -86,7 +87,7 @@ def main():
         return serve_bench(args)
     cnum = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "c4bf": 4}[args.config]
     wl = inputs.workload(cnum)
-    if args.prop_only and args.nt:
+    if args.nt:
         wl.prob = wl.prob.replace(nt=args.nt)
     prob = wl.prob
     fd = {"c1": "f64", "c2": "f32", "c3": "f32", "c4": "f16", "c4bf": "bf16"}[args.config]
