@@ -245,6 +245,188 @@ __global__ __launch_bounds__(TBX* TBY) void k_pres(Fields f, GridDims g, Coef cf
 constexpr int TX = 64;
 constexpr int HXS = 8;  // staged x halo (>= 2K - 1, multiple of 4)
 
+// element i of an array, addressed as a 32-bit byte offset from a base that
+// is uniform over the workgroup (one scalar base + one vector offset)
+template <typename T> __device__ __forceinline__ const T* at(const T* b, unsigned i) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(b) + i * (unsigned)sizeof(T));
+}
+template <typename T> __device__ __forceinline__ T* at(T* b, unsigned i) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(b) + i * (unsigned)sizeof(T));
+}
+
+// no row of the line is active in rows [lo, hi)
+__device__ __forceinline__ bool line_clear(const LineDev& l, const TraceIO& io, int lo, int hi) {
+  return io.n < 0 || ((l.row0 < lo || l.row0 >= hi) && (l.row1 < lo || l.row1 >= hi));
+}
+
+// A tile is interior when everything it computes (v_x on columns x0-4 ..
+// x1+3, v_z on rows z0-K .. z1+K-2, p on the tile) and everything it stages
+// lies inside the absorbing frame's inner edge, where the layer factors a
+// and b are exactly 1 at nodes and half nodes and the pressure is not split,
+// and no line is sampled or injected in its rows.  Interior tiles take a
+// path without per-cell tests; it evaluates the same expressions as the
+// general path with a = b = 1 and zero sources, so results are bitwise
+// equal.
+template <int K, int TZ>
+__device__ __forceinline__ bool interior_tile(const StepArgs& a, int x0, int z0) {
+  constexpr int R = 2 * K - 1;
+  const int L = a.g.L, NZ = a.g.NZ, NX = a.g.NX;
+  return z0 - R >= L && z0 + TZ + R <= NZ - L - 1 && x0 - HXS >= L &&
+         x0 + TX + HXS <= NX - L - 1 && line_clear(a.vsl, a.vs, z0 - R, z0 + TZ + R) &&
+         line_clear(a.vil, a.vi, z0 - R, z0 + TZ + R) &&
+         line_clear(a.psl, a.ps, z0 - R, z0 + TZ + R) &&
+         line_clear(a.pil, a.pi, z0 - R, z0 + TZ + R);
+}
+
+template <int K, bool ADJ, typename T, int TZ, typename C>
+__device__ __forceinline__ void step_interior(const StepArgs& a, long long base, int x0, int z0,
+                                              C* __restrict__ sP, C* __restrict__ sVX,
+                                              C* __restrict__ sVZ) {
+  constexpr int R = 2 * K - 1;
+  constexpr int WP = TX + 2 * HXS;
+  constexpr int GP = WP / 4;
+  constexpr int HP = TZ + 2 * R;
+  constexpr int GVX = TX / 4 + 2;
+  constexpr int WVX = 4 * GVX;
+  constexpr int HVZ = TZ + 2 * K - 1;
+  constexpr int GT = TX / 4;
+  constexpr int NQP = (HP * GP + 255) / 256;
+  constexpr int NQX = (TZ * GVX + 255) / 256;
+  constexpr int NQZ = (HVZ * GT + 255) / 256;
+  constexpr int NQT = (TZ * GT + 255) / 256;
+  const int P = a.g.pitch;
+  const int tid = threadIdx.x;
+  const long long o0 = base + (long long)z0 * P + x0;  // element (z0, x0) of this shot
+  const T* pA = static_cast<const T*>(a.in.p) + (o0 - (long long)R * P - HXS);
+  const T* vxA = static_cast<const T*>(a.in.vx) + (o0 - 4);
+  const T* vzA = static_cast<const T*>(a.in.vz) + (o0 - (long long)K * P);
+  const C* ckA = static_cast<const C*>(a.c.ck) + (a.g.origin + (long long)z0 * P + x0);
+  T* pB = static_cast<T*>(a.out.p) + o0;
+  T* vxB = static_cast<T*>(a.out.vx) + (o0 - 4);
+  T* vzB = static_cast<T*>(a.out.vz) + (o0 - (long long)K * P);
+  const C cb = C(a.c.cb);
+  const C one = C(1), zero = C(0);
+
+  // ---- loads ---------------------------------------------------------------
+  C rp[NQP][4];
+#pragma unroll
+  for (int k = 0; k < NQP; ++k) {
+    const int q = tid + 256 * k;
+    if (256 * k + 255 < HP * GP || q < HP * GP) {
+      const int rr = q / GP, g = q - rr * GP;
+      ld4(rp[k], at(pA, rr * P + 4 * g));
+    }
+  }
+  C rvx[NQX][4];
+#pragma unroll
+  for (int k = 0; k < NQX; ++k) {
+    const int q = tid + 256 * k;
+    if (256 * k + 255 < TZ * GVX || q < TZ * GVX) {
+      const int rr = q / GVX, g = q - rr * GVX;
+      ld4(rvx[k], at(vxA, rr * P + 4 * g));
+    }
+  }
+  C rvz[NQZ][4];
+#pragma unroll
+  for (int k = 0; k < NQZ; ++k) {
+    const int q = tid + 256 * k;
+    if (256 * k + 255 < HVZ * GT || q < HVZ * GT) ld4(rvz[k], at(vzA, (q >> 4) * P + 4 * (q & 15)));
+  }
+  C rck[NQT][4];
+#pragma unroll
+  for (int k = 0; k < NQT; ++k) {
+    const int q = tid + 256 * k;
+    if (256 * k + 255 < TZ * GT || q < TZ * GT) ld4(rck[k], at(ckA, (q >> 4) * P + 4 * (q & 15)));
+  }
+
+  // ---- stage p^n -------------------------------------------------------------
+#pragma unroll
+  for (int k = 0; k < NQP; ++k) {
+    const int q = tid + 256 * k;
+    if (256 * k + 255 < HP * GP || q < HP * GP) st4(sP + 4 * q, rp[k]);
+  }
+  __syncthreads();
+
+  // ---- v_x on the tile rows, columns x0-4 .. x1+3 ------------------------------
+#pragma unroll
+  for (int k = 0; k < NQX; ++k) {
+    const int q = tid + 256 * k;
+    if (256 * k + 255 < TZ * GVX || q < TZ * GVX) {
+      const int rr = q / GVX, g = q - rr * GVX;
+      const C* row = sP + (rr + R) * WP + 4 * g;
+      C w[12];
+      ld4(*reinterpret_cast<C(*)[4]>(w), row);
+      ld4(*reinterpret_cast<C(*)[4]>(w + 4), row + 4);
+      ld4(*reinterpret_cast<C(*)[4]>(w + 8), row + 8);
+      C val[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        C sx = zero;
+#pragma unroll
+        for (int m = 1; m <= K; ++m) sx = acc(sx, wst<K, C>(m - 1), w[e + 4 + m], w[e + 5 - m]);
+        val[e] = rnd<T>(upd_v<ADJ>(one, one, cb, rvx[k][e], sx, zero));
+      }
+      if (g >= 1 && g <= GT) st4(at(vxB, rr * P + 4 * g), val);
+      st4(sVX + 4 * q, val);
+    }
+  }
+  // ---- v_z on the tile columns, rows z0-K .. z1+K-2 ----------------------------
+#pragma unroll
+  for (int k = 0; k < NQZ; ++k) {
+    const int q = tid + 256 * k;
+    if (256 * k + 255 < HVZ * GT || q < HVZ * GT) {
+      const int rr = q >> 4, g = q & 15;
+      const C* col = sP + (rr - K + R) * WP + 4 * g + HXS;
+      C sz[4] = {zero, zero, zero, zero};
+#pragma unroll
+      for (int m = 1; m <= K; ++m) {
+        C hi[4], lo[4];
+        ld4(hi, col + m * WP);
+        ld4(lo, col + (1 - m) * WP);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sz[e] = acc(sz[e], wst<K, C>(m - 1), hi[e], lo[e]);
+      }
+      C val[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) val[e] = rnd<T>(upd_v<ADJ>(one, one, cb, rvz[k][e], sz[e], zero));
+      if (rr >= K && rr < K + TZ) st4(at(vzB, rr * P + 4 * g), val);
+      st4(sVZ + 4 * q, val);
+    }
+  }
+  __syncthreads();
+
+  // ---- p^{n+1} on the tile -------------------------------------------------------
+#pragma unroll
+  for (int k = 0; k < NQT; ++k) {
+    const int q = tid + 256 * k;
+    if (256 * k + 255 < TZ * GT || q < TZ * GT) {
+      const int rr = q >> 4, g = q & 15;
+      C w[12];
+      const C* vrow = sVX + rr * WVX + 4 * g;
+      ld4(*reinterpret_cast<C(*)[4]>(w), vrow);
+      ld4(*reinterpret_cast<C(*)[4]>(w + 4), vrow + 4);
+      ld4(*reinterpret_cast<C(*)[4]>(w + 8), vrow + 8);
+      C dx[4] = {zero, zero, zero, zero}, dz[4] = {zero, zero, zero, zero};
+#pragma unroll
+      for (int m = 1; m <= K; ++m) {
+        C hi[4], lo[4];
+        ld4(hi, sVZ + (rr + K + m - 1) * TX + 4 * g);
+        ld4(lo, sVZ + (rr + K - m) * TX + 4 * g);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          dx[e] = acc(dx[e], wst<K, C>(m - 1), w[e + m + 3], w[e + 4 - m]);
+          dz[e] = acc(dz[e], wst<K, C>(m - 1), hi[e], lo[e]);
+        }
+      }
+      C pc[4], pn[4];
+      ld4(pc, sP + (rr + R) * WP + 4 * g + HXS);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) pn[e] = upd_p<ADJ>(rck[k][e], pc[e], dx[e], dz[e], zero);
+      st4(at(pB, rr * P + 4 * g), pn);
+    }
+  }
+}
+
 template <int K, bool ADJ, typename T, int TZ>
 __global__ __launch_bounds__(256) void k_step(StepArgs a) {
   using C = typename Tr<T>::C;
@@ -280,6 +462,10 @@ __global__ __launch_bounds__(256) void k_step(StepArgs a) {
   const int x1 = x0 + TX, z1 = z0 + TZ;
   const int NX = a.g.NX, NZ = a.g.NZ, P = a.g.pitch, L = a.g.L;
   const long long base = a.g.origin + (long long)shot * a.g.field_stride;
+  if (interior_tile<K, TZ>(a, x0, z0)) {
+    step_interior<K, ADJ, T, TZ, C>(a, base, x0, z0, sP, sVX, sVZ);
+    return;
+  }
   const T* __restrict__ pA = static_cast<const T*>(a.in.p) + base;
   const T* __restrict__ vxA = static_cast<const T*>(a.in.vx) + base;
   const T* __restrict__ vzA = static_cast<const T*>(a.in.vz) + base;

@@ -15,10 +15,22 @@ import paper_2203_16573_amd as ssx  # noqa: E402
 RHO = 1000.0
 
 
-def problem(order, **kw):
-    base = dict(nz=37, nx=150, h=10.0, dt=1e-3, nt=120, order=order, npml=10,
-                z_src=45.0, x_src0=30.0, ns=100, z_rec=203.0, x_rec0=0.0, nr=150,
-                slab_dz=5, xs=(300.0, 717.0))
+GEOMS = {
+    # every tile touches the absorbing frame or a line
+    "small": dict(nz=37, nx=150, z_src=45.0, x_src0=30.0, ns=100, z_rec=203.0, x_rec0=0.0,
+                  nr=150),
+    # interior tiles (no per-cell tests) beside frame and line tiles
+    "wide": dict(nz=100, nx=300, z_src=45.0, x_src0=30.0, ns=200, z_rec=203.0, x_rec0=0.0,
+                 nr=300),
+    # lines deep inside, part width: interior tiles above, between and below
+    "deep": dict(nz=130, nx=300, z_src=603.0, x_src0=450.0, ns=150, z_rec=455.0,
+                 x_rec0=1000.0, nr=170),
+}
+
+
+def problem(order, geom="small", **kw):
+    base = dict(h=10.0, dt=1e-3, nt=120, order=order, npml=10, slab_dz=5, xs=(300.0, 717.0))
+    base.update(GEOMS[geom])
     base.update(kw)
     return inputs.Problem(**base)
 
@@ -41,14 +53,15 @@ def run_all(ctx, prob, fd, seed=0):
     return [t.cpu().numpy().copy() for t in (d, gg, P, V, f)]
 
 
+@pytest.mark.parametrize("geom", ["small", "wide", "deep"])
 @pytest.mark.parametrize("fd", ["f64", "f32", "f16", "bf16"])
 @pytest.mark.parametrize("order,nt", [(4, 120), (8, 121)])
-def test_fused_equals_split_bitwise(fd, order, nt):
+def test_fused_equals_split_bitwise(fd, order, nt, geom):
     # one-step fused kernel at every tile height, and (except FP64) the
     # two-steps-per-launch kernel, against the split reference; an odd
     # record length exercises the single-step remainder
-    prob = problem(order, nt=nt)
-    print(f"case fused-vs-split order={order} nt={nt} dtype={fd}", flush=True)
+    prob = problem(order, geom, nt=nt)
+    print(f"case fused-vs-split order={order} nt={nt} dtype={fd} geom={geom}", flush=True)
     ctx = ssx.Context(prob, kappa(prob), RHO, field_dtype=fd)
     ctx.set_graphs(False)
     ctx.set_option(ssx.OPT_STEP_KERNEL, 0)
