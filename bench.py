@@ -149,20 +149,24 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     step_ms = e0.elapsed_time(e1) / (nrep * prob.nt)
-    cells = ctx.cells_per_launch()
+    NZ, NX = prob.nz + 2 * prob.npml, prob.nx + 2 * prob.npml
+    cells = ctx.cells_per_launch()          # one launch: the shots of one group
+    group = cells // (NZ * NX)
+    launches = -(-prob.nshots // group)      # launches per time step
     fsz = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[fd]
     csz = 8 if fd == "f64" else 4
     # algorithmic bytes per cell-update: read p, v_x, v_z and kappa once,
     # write p, v_x, v_z once
     b_alg = 6 * fsz + csz
-    achieved = b_alg * cells / (step_ms * 1e-3) / 1e9
+    achieved = b_alg * NZ * NX * prob.nshots / (step_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": ctx.step_kernel_name(), "us_per_launch": round(step_ms * 1e3, 3),
-                "bytes_per_cell": b_alg, "cells_per_launch": cells}
+                "kernel": ctx.step_kernel_name(),
+                "us_per_launch": round(step_ms * 1e3 / launches, 3),
+                "launches_per_step": launches, "bytes_per_cell": b_alg,
+                "cells_per_launch": cells}
 
     # cell-updates in one solve: (2K + 1) full propagations, 2 (K + 1) slab
-    NZ, NX = prob.nz + 2 * prob.npml, prob.nx + 2 * prob.npml
     k = prob.order // 2
     nzs = abs(prob.slab_dz) + 1 + 2 * k + 2 * prob.npml
     cu_solve = prob.nt * ((2 * wl.K + 1) * NZ * NX + 2 * (wl.K + 1) * nzs * NX)

@@ -198,6 +198,14 @@ ssx_status ssx_pcg_solve(ssx_ctx* ctx, const void* d, double alpha_rel, int32_t 
  *                       kernel on the full grid: 1 (default) or 2 (2: F32
  *                       fields only; uses a tile height of 8).
  *   SSX_OPT_STEPS_PER_LAUNCH_SLAB the same for the thin slab.
+ *   SSX_OPT_SHOT_GROUP  shots advanced together by one launch on the full
+ *                       grid and the thin slab: the shots are split into
+ *                       balanced groups of at most this many, and each
+ *                       group runs its whole record before the next one;
+ *                       0 (default) picks the largest group whose per-step
+ *                       traffic fits the last-level cache (176 MiB at 6
+ *                       field values and one coefficient per cell).
+ *   SSX_OPT_SHOT_GROUP_SLAB the same for the thin slab only.
  * Returns SSX_ERR_ARG for an unknown option or value. */
 typedef enum {
   SSX_OPT_GRAPHS = 0,
@@ -205,7 +213,9 @@ typedef enum {
   SSX_OPT_TILE_Z = 2,
   SSX_OPT_TILE_Z_SLAB = 3,
   SSX_OPT_STEPS_PER_LAUNCH = 4,
-  SSX_OPT_STEPS_PER_LAUNCH_SLAB = 5
+  SSX_OPT_STEPS_PER_LAUNCH_SLAB = 5,
+  SSX_OPT_SHOT_GROUP = 6,
+  SSX_OPT_SHOT_GROUP_SLAB = 7
 } ssx_option;
 ssx_status ssx_set_option(ssx_ctx* ctx, int option, int value);
 
@@ -214,7 +224,8 @@ const char* ssx_last_error(void);
 
 /* Name of the kernel that dominates a full-grid propagation, and the
  * number of grid cells one of its launches advances by one time step
- * (all shots), for throughput accounting. */
+ * (the shots of one group, see SSX_OPT_SHOT_GROUP), for throughput
+ * accounting. */
 const char* ssx_step_kernel_name(ssx_ctx* ctx);
 int64_t ssx_cells_per_launch(ssx_ctx* ctx);
 

@@ -1,13 +1,15 @@
-"""Tile-shape autotuner for the fused time-step kernel.
+"""Execution-shape autotuner for the fused time-step kernel.
 
 For a problem shape (padded grid, stencil order, storage type, shots) it
-times the candidate tile heights of the fused step on a short copy of the
-problem (same grid, same shots, few time steps) for the full grid and for
-the thin slab separately, also times the split two-launch step on the full
-grid, and applies the fastest choice to a context.  Results are cached in a
-JSON file keyed by shape, never by the data or the mix of other work, so a
-given shape always runs the same kernels (results do not depend on the
-choice: every variant evaluates the same expressions).
+times, on a short copy of the problem (same grid, same shots, few time
+steps) and under captured graphs as the solver runs them, first the
+candidate (steps per launch, tile height) pairs of the fused step and the
+split two-launch step, then the number of shots advanced per launch, for
+the full grid and the thin slab separately, and applies the fastest choice
+to a context.  Results are cached in a JSON file keyed by shape, never by
+the data or the mix of other work, so a given shape always runs the same
+kernels (results do not depend on the choice: every variant evaluates the
+same expressions).
 """
 from __future__ import annotations
 
@@ -15,10 +17,10 @@ import json
 import os
 import threading
 
-from . import (OPT_STEP_KERNEL, OPT_STEPS_PER_LAUNCH, OPT_STEPS_PER_LAUNCH_SLAB, OPT_TILE_Z,
-               OPT_TILE_Z_SLAB, Context)
+from . import (OPT_SHOT_GROUP, OPT_SHOT_GROUP_SLAB, OPT_STEP_KERNEL, OPT_STEPS_PER_LAUNCH,
+               OPT_STEPS_PER_LAUNCH_SLAB, OPT_TILE_Z, OPT_TILE_Z_SLAB, Context)
 
-DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ssx", "autotune-v2.json")
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ssx", "autotune-v3.json")
 _lock = threading.Lock()
 
 
@@ -45,9 +47,9 @@ def _store(path, table):
     os.replace(tmp, path)
 
 
-def _time_ms(fn, reps=2):
+def _time_ms(fn, reps=3):
     import torch
-    fn()
+    fn()  # first call captures the graph
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -58,21 +60,30 @@ def _time_ms(fn, reps=2):
     return e0.elapsed_time(e1) / reps
 
 
+def _group_candidates(auto: int, nshots: int) -> list:
+    c = {auto, nshots, max(1, auto // 2), min(nshots, 2 * auto)}
+    return sorted(c)
+
+
 def tune(prob, kappa, rho, xs=None, field_dtype="f32", nt_tune: int = 60,
          stream=None) -> dict:
-    """Measure the candidates and return {"step_kernel", "tile_z", "tile_z_slab",
-    "us": {...}} (per-step times in microseconds)."""
+    """Measure the candidates and return {"step_kernel", "steps_per_launch",
+    "tile_z", "shot_group", "steps_per_launch_slab", "tile_z_slab",
+    "shot_group_slab", "us": {...}} (per-step times in microseconds)."""
     import torch
     xs = tuple(prob.xs) if xs is None else tuple(xs)
     short = prob.replace(nt=min(int(nt_tune), int(prob.nt))) if hasattr(prob, "replace") else prob
     ctx = Context(short, kappa, rho, xs=xs, field_dtype=field_dtype, stream=stream)
-    ctx.set_graphs(False)
-    nt = short.nt
+    ctx.set_graphs(True)
+    nt, ns = short.nt, len(xs)
+    NZ, NX = short.nz + 2 * short.npml, short.nx + 2 * short.npml
     vdt = ctx.vdtype
-    h = torch.randn((len(xs), nt, short.ns), dtype=vdt, device="cuda")
+    h = torch.randn((ns, nt, short.ns), dtype=vdt, device="cuda")
     d = ctx.empty_r()
     g = ctx.empty_s()
     P, V = ctx.empty_s(), ctx.empty_s()
+    full = lambda: (ctx.fwd(h, d), ctx.adj(d, g))          # noqa: E731
+    slab = lambda: (ctx.slab_fwd(h, P, V), ctx.slab_adj(V, P, g))  # noqa: E731
     # candidates: (steps per launch, tile height)
     if field_dtype == "f64":
         cands = [(1, 8), (1, 16)]
@@ -82,27 +93,41 @@ def tune(prob, kappa, rho, xs=None, field_dtype="f32", nt_tune: int = 60,
         cands = [(1, 8), (1, 16), (1, 32)]
     us = {}
     ctx.set_option(OPT_STEP_KERNEL, 1)
+    ctx.set_option(OPT_SHOT_GROUP, 0)
+    auto_group = max(1, ctx.cells_per_launch() // (NZ * NX))
     for spl, tz in cands:
         ctx.set_option(OPT_TILE_Z, tz)
         ctx.set_option(OPT_STEPS_PER_LAUNCH, spl)
         tag = f"s{spl}_tz{tz}"
-        us[f"full_{tag}"] = 1e3 * _time_ms(lambda: (ctx.fwd(h, d), ctx.adj(d, g))) / (2 * nt)
-        us[f"slab_{tag}"] = 1e3 * _time_ms(
-            lambda: (ctx.slab_fwd(h, P, V), ctx.slab_adj(V, P, g))) / (2 * nt)
+        us[f"full_{tag}"] = 1e3 * _time_ms(full) / (2 * nt)
+        us[f"slab_{tag}"] = 1e3 * _time_ms(slab) / (2 * nt)
     ctx.set_option(OPT_STEPS_PER_LAUNCH, 1)
     ctx.set_option(OPT_STEP_KERNEL, 0)
-    us["full_split"] = 1e3 * _time_ms(lambda: (ctx.fwd(h, d), ctx.adj(d, g))) / (2 * nt)
-    us["slab_split"] = 1e3 * _time_ms(
-        lambda: (ctx.slab_fwd(h, P, V), ctx.slab_adj(V, P, g))) / (2 * nt)
-    ctx.close()
+    us["full_split"] = 1e3 * _time_ms(full) / (2 * nt)
+    us["slab_split"] = 1e3 * _time_ms(slab) / (2 * nt)
     best_full = min(cands, key=lambda c: us[f"full_s{c[0]}_tz{c[1]}"])
     best_slab = min(cands, key=lambda c: us[f"slab_s{c[0]}_tz{c[1]}"])
     fused_total = us[f"full_s{best_full[0]}_tz{best_full[1]}"] + \
         us[f"slab_s{best_slab[0]}_tz{best_slab[1]}"]
     split_total = us["full_split"] + us["slab_split"]
-    return {"step_kernel": 1 if fused_total <= split_total else 0,
-            "steps_per_launch": best_full[0], "tile_z": best_full[1],
-            "steps_per_launch_slab": best_slab[0], "tile_z_slab": best_slab[1], "us": us}
+    step_kernel = 1 if fused_total <= split_total else 0
+    ctx.set_option(OPT_STEP_KERNEL, step_kernel)
+    ctx.set_option(OPT_TILE_Z, best_full[1])
+    ctx.set_option(OPT_TILE_Z_SLAB, best_slab[1])
+    ctx.set_option(OPT_STEPS_PER_LAUNCH, best_full[0])
+    ctx.set_option(OPT_STEPS_PER_LAUNCH_SLAB, best_slab[0])
+    group, group_slab = auto_group, 0
+    if ns > 1:
+        for gsz in _group_candidates(auto_group, ns):
+            ctx.set_option(OPT_SHOT_GROUP, gsz)
+            ctx.set_option(OPT_SHOT_GROUP_SLAB, 0)
+            us[f"full_group{gsz}"] = 1e3 * _time_ms(full) / (2 * nt)
+        group = min(_group_candidates(auto_group, ns), key=lambda x: us[f"full_group{x}"])
+    ctx.close()
+    return {"step_kernel": step_kernel,
+            "steps_per_launch": best_full[0], "tile_z": best_full[1], "shot_group": group,
+            "steps_per_launch_slab": best_slab[0], "tile_z_slab": best_slab[1],
+            "shot_group_slab": group_slab, "us": us}
 
 
 def choose(prob, kappa, rho, xs=None, field_dtype="f32", cache_path: str | None = DEFAULT_CACHE,
@@ -125,9 +150,12 @@ def choose(prob, kappa, rho, xs=None, field_dtype="f32", cache_path: str | None 
 
 
 def apply(ctx: Context, choice: dict) -> None:
-    """Set a context's step kernel and tile heights from a tuning result."""
+    """Set a context's step kernel, tile heights, steps per launch and shot
+    groups from a tuning result."""
     ctx.set_option(OPT_STEP_KERNEL, int(choice["step_kernel"]))
     ctx.set_option(OPT_TILE_Z, int(choice["tile_z"]))
     ctx.set_option(OPT_TILE_Z_SLAB, int(choice["tile_z_slab"]))
     ctx.set_option(OPT_STEPS_PER_LAUNCH, int(choice.get("steps_per_launch", 1)))
     ctx.set_option(OPT_STEPS_PER_LAUNCH_SLAB, int(choice.get("steps_per_launch_slab", 1)))
+    ctx.set_option(OPT_SHOT_GROUP, int(choice.get("shot_group", 0)))
+    ctx.set_option(OPT_SHOT_GROUP_SLAB, int(choice.get("shot_group_slab", 0)))

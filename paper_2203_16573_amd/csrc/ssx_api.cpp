@@ -251,7 +251,7 @@ struct GridDev {
 struct GraphEntry {
   int op;
   const void* ptr[4];
-  int tile_z, fused, spl;
+  int tile_z, fused, spl, group;
   hipGraphExec_t exec;
   unsigned long long last_use;
 };
@@ -279,6 +279,7 @@ struct ssx_ctx {
   bool fused = true;
   int tile_z_full = 0, tile_z_slab = 0;  // 0: default
   int spl_full = 1, spl_slab = 1;        // time steps per fused launch
+  int group_full = 0, group_slab = 0;    // shots per launch (0: from the cache budget)
   hipStream_t cap_stream = nullptr;      // capture stream (graphs are launched on `stream`)
   std::vector<GraphEntry> graphs_cache;
   unsigned long long use_clock = 0;
@@ -388,10 +389,12 @@ TraceIO io_out(void* out, long long stride, double scale) {
   return t;
 }
 
+int shot_group(const ssx_ctx* c, const GridDev& gd);
+
 int default_tile_z(const ssx_ctx* c, const GridDev& gd) {
   // enough tiles to fill 256 CUs several times over, else shorter tiles
   const long long tiles32 = (long long)((gd.host.NX + 63) / 64) * ((gd.host.NZ + 31) / 32) *
-                            c->prob.nshots;
+                            shot_group(c, gd);
   if (c->fdt == Dt::F64) return tiles32 >= 1024 ? 16 : 8;
   if (tiles32 >= 1024) return 32;
   return tiles32 >= 256 ? 16 : 8;
@@ -407,52 +410,42 @@ int default_tile_z(const ssx_ctx* c, const GridDev& gd) {
 // Transpose: pi[nt-1] enters first; step n (descending) samples vs[n]
 // (the transposed pressure after sample n of the adjoint input entered),
 // injects vi[n], samples ps[n] and injects pi[n-1].
-ssx_status issue_propagation(ssx_ctx* c, GridDev& gd, bool adj, const LineDev& vsl, TraceIO vs,
-                             const LineDev& vil, TraceIO vi, const LineDev& psl, TraceIO ps,
-                             const LineDev& pil, TraceIO pi, hipStream_t s) {
-  const int nt = c->prob.nt, ns = c->prob.nshots, order = c->prob.order;
-  SSX_HIP(launch_zero(gd.field_block, gd.field_bytes, s));
-  if (c->fsz == 2) {
-    // 16-bit fields: normalise the injected traces per shot by a power of two
-    const void* ia = pi.in ? pi.in : vi.in;
-    const double sa = pi.in ? pi.scale : vi.scale;
-    const void* ib = (pi.in && vi.in) ? vi.in : nullptr;
-    const long long nin = (pi.in ? pi.shot_stride : vi.shot_stride);
-    if (ia) {
-      if (ib && vi.shot_stride != nin) return fail(SSX_ERR_ARG, "mismatched trace inputs");
-      SSX_HIP(launch_field_scale(c->vdbl, ia, sa, ib, vi.scale, nin, ns, c->amax_part, c->dyn, s));
-      vs.dyn = vi.dyn = ps.dyn = pi.dyn = c->dyn;
-    }
-  }
+// One propagation of ns shots (a group of the context's shots) whose
+// fields start at f0 (step n) and f1 (the second buffer).
+ssx_status issue_group(ssx_ctx* c, GridDev& gd, bool adj, const Fields& f0, const Fields& f1,
+                       int ns, const LineDev& vsl, TraceIO vs, const LineDev& vil, TraceIO vi,
+                       const LineDev& psl, TraceIO ps, const LineDev& pil, TraceIO pi,
+                       hipStream_t s) {
+  const int nt = c->prob.nt, order = c->prob.order;
   if (!c->fused) {
     if (!adj) {
       for (int n = 0; n < nt; ++n) {
         vs.n = (vs.out && n >= 1) ? n - 1 : -1;
         vi.n = vi.in ? n : -1;
-        SSX_HIP(launch_vel(c->fdt, order, false, gd.fields, gd.dims, gd.coef, vsl, vs, vil, vi,
+        SSX_HIP(launch_vel(c->fdt, order, false, f0, gd.dims, gd.coef, vsl, vs, vil, vi,
                            ns, s));
         ps.n = ps.out ? n : -1;
         pi.n = pi.in ? n : -1;
-        SSX_HIP(launch_pres(c->fdt, order, false, gd.fields, gd.dims, gd.coef, psl, ps, pil, pi,
+        SSX_HIP(launch_pres(c->fdt, order, false, f0, gd.dims, gd.coef, psl, ps, pil, pi,
                             ns, s));
       }
       if (vs.out) {
         vs.n = nt - 1;
-        SSX_HIP(launch_sample_p(c->fdt, gd.fields, gd.dims, vsl, vs, ns, s));
+        SSX_HIP(launch_sample_p(c->fdt, f0, gd.dims, vsl, vs, ns, s));
       }
     } else {
       TraceIO none = io_none();
       pi.n = pi.in ? nt - 1 : -1;
-      SSX_HIP(launch_pres(c->fdt, order, true, gd.fields, gd.dims, gd.coef, psl, none, pil, pi,
+      SSX_HIP(launch_pres(c->fdt, order, true, f0, gd.dims, gd.coef, psl, none, pil, pi,
                           ns, s));
       for (int n = nt - 1; n >= 0; --n) {
         vs.n = vs.out ? n : -1;
         vi.n = vi.in ? n : -1;
-        SSX_HIP(launch_vel(c->fdt, order, true, gd.fields, gd.dims, gd.coef, vsl, vs, vil, vi,
+        SSX_HIP(launch_vel(c->fdt, order, true, f0, gd.dims, gd.coef, vsl, vs, vil, vi,
                            ns, s));
         ps.n = ps.out ? n : -1;
         pi.n = (pi.in && n >= 1) ? n - 1 : -1;
-        SSX_HIP(launch_pres(c->fdt, order, true, gd.fields, gd.dims, gd.coef, psl, ps, pil, pi,
+        SSX_HIP(launch_pres(c->fdt, order, true, f0, gd.dims, gd.coef, psl, ps, pil, pi,
                             ns, s));
       }
     }
@@ -477,7 +470,7 @@ ssx_status issue_propagation(ssx_ctx* c, GridDev& gd, bool adj, const LineDev& v
   a.dir = adj ? -1 : 1;
   const int ntz1 = (gd.host.NZ + tz - 1) / tz;
   const int ntz2 = (gd.host.NZ + STEP2_TZ - 1) / STEP2_TZ;
-  Fields buf[2] = {gd.fields, gd.fields1};
+  Fields buf[2] = {f0, f1};
   int cur = 0;
   // one launch covering `steps` (1 or 2) steps starting at step n with the
   // given level-0 trace indices
@@ -526,6 +519,74 @@ ssx_status issue_propagation(ssx_ctx* c, GridDev& gd, bool adj, const LineDev& v
   return SSX_OK;
 }
 
+
+// Shots advanced by one launch on grid gd: the option value, else as many
+// as keep one step's algorithmic traffic (6 field values and one
+// coefficient per cell and shot) within STEP_SET_BYTES, so that a group's
+// fields stay in the 256 MB last-level cache from one step to the next.
+constexpr double STEP_SET_BYTES = 176.0 * 1024 * 1024;
+int shot_group(const ssx_ctx* c, const GridDev& gd) {
+  const int ns = c->prob.nshots;
+  const int opt = (&gd == &c->full) ? c->group_full : c->group_slab;
+  int g;
+  if (opt > 0) {
+    g = opt;
+  } else {
+    const double per_shot = (6.0 * c->fsz + c->csz) * gd.host.NZ * gd.host.NX;
+    g = std::max(1, (int)(STEP_SET_BYTES / per_shot));
+  }
+  if (g >= ns) return ns;
+  const int ngroups = (ns + g - 1) / g;  // balanced groups
+  return (ns + ngroups - 1) / ngroups;
+}
+
+Fields shift_fields(const Fields& f, long long elems, size_t fsz) {
+  Fields o;
+  o.p = (char*)f.p + elems * fsz;
+  o.vx = (char*)f.vx + elems * fsz;
+  o.vz = (char*)f.vz + elems * fsz;
+  o.aux = (char*)f.aux + elems * fsz;
+  return o;
+}
+
+TraceIO shift_io(TraceIO t, int s0, size_t vsz) {
+  if (t.in) t.in = (const char*)t.in + (long long)s0 * t.shot_stride * vsz;
+  if (t.out) t.out = (char*)t.out + (long long)s0 * t.shot_stride * vsz;
+  if (t.dyn) t.dyn += s0;
+  return t;
+}
+
+// One propagation of all shots over nt steps, issued on stream s, group by
+// group (each group runs its whole record before the next starts).
+ssx_status issue_propagation(ssx_ctx* c, GridDev& gd, bool adj, const LineDev& vsl, TraceIO vs,
+                             const LineDev& vil, TraceIO vi, const LineDev& psl, TraceIO ps,
+                             const LineDev& pil, TraceIO pi, hipStream_t s) {
+  const int ns = c->prob.nshots;
+  SSX_HIP(launch_zero(gd.field_block, gd.field_bytes, s));
+  if (c->fsz == 2) {
+    // 16-bit fields: normalise the injected traces per shot by a power of two
+    const void* ia = pi.in ? pi.in : vi.in;
+    const double sa = pi.in ? pi.scale : vi.scale;
+    const void* ib = (pi.in && vi.in) ? vi.in : nullptr;
+    const long long nin = (pi.in ? pi.shot_stride : vi.shot_stride);
+    if (ia) {
+      if (ib && vi.shot_stride != nin) return fail(SSX_ERR_ARG, "mismatched trace inputs");
+      SSX_HIP(launch_field_scale(c->vdbl, ia, sa, ib, vi.scale, nin, ns, c->amax_part, c->dyn, s));
+      vs.dyn = vi.dyn = ps.dyn = pi.dyn = c->dyn;
+    }
+  }
+  const int G = shot_group(c, gd);
+  for (int s0 = 0; s0 < ns; s0 += G) {
+    const int gs = std::min(G, ns - s0);
+    const long long off = (long long)s0 * gd.dims.field_stride;
+    SSX_TRY(issue_group(c, gd, adj, shift_fields(gd.fields, off, c->fsz),
+                        shift_fields(gd.fields1, off, c->fsz), gs, vsl,
+                        shift_io(vs, s0, c->vsz), vil, shift_io(vi, s0, c->vsz), psl,
+                        shift_io(ps, s0, c->vsz), pil, shift_io(pi, s0, c->vsz), s));
+  }
+  return SSX_OK;
+}
+
 constexpr size_t GRAPH_CACHE_MAX = 12;
 
 // Runs a propagation: replays a cached graph for (op, pointers) when graphs
@@ -538,9 +599,11 @@ ssx_status propagate(ssx_ctx* c, int op, GridDev& gd, bool adj, const LineDev& v
   const void* key[4] = {vs.out, vi.in, ps.out, pi.in};
   const int tz = (&gd == &c->full) ? c->tile_z_full : c->tile_z_slab;
   const int spl = (&gd == &c->full) ? c->spl_full : c->spl_slab;
+  const int group = (&gd == &c->full) ? c->group_full : c->group_slab;
   for (GraphEntry& e : c->graphs_cache) {
     if (e.op == op && e.ptr[0] == key[0] && e.ptr[1] == key[1] && e.ptr[2] == key[2] &&
-        e.ptr[3] == key[3] && e.tile_z == tz && e.fused == (int)c->fused && e.spl == spl) {
+        e.ptr[3] == key[3] && e.tile_z == tz && e.fused == (int)c->fused && e.spl == spl &&
+        e.group == group) {
       e.last_use = ++c->use_clock;
       SSX_HIP(hipGraphLaunch(e.exec, c->stream));
       return SSX_OK;
@@ -574,6 +637,7 @@ ssx_status propagate(ssx_ctx* c, int op, GridDev& gd, bool adj, const LineDev& v
   ge.tile_z = tz;
   ge.fused = (int)c->fused;
   ge.spl = spl;
+  ge.group = group;
   ge.exec = exec;
   ge.last_use = ++c->use_clock;
   c->graphs_cache.push_back(ge);
@@ -938,6 +1002,12 @@ ssx_status ssx_set_option(ssx_ctx* c, int option, int value) {
       if (option == SSX_OPT_STEPS_PER_LAUNCH) c->spl_full = value;
       c->spl_slab = value;
       return SSX_OK;
+    case SSX_OPT_SHOT_GROUP:
+    case SSX_OPT_SHOT_GROUP_SLAB:
+      if (value < 0) return fail(SSX_ERR_ARG, "shots per launch must be >= 0");
+      if (option == SSX_OPT_SHOT_GROUP) c->group_full = value;
+      c->group_slab = value;
+      return SSX_OK;
   }
   return fail(SSX_ERR_ARG, "unknown option");
 }
@@ -951,7 +1021,7 @@ const char* ssx_step_kernel_name(ssx_ctx* c) {
 
 int64_t ssx_cells_per_launch(ssx_ctx* c) {
   if (!c) return 0;
-  return (int64_t)c->full.host.NZ * c->full.host.NX * c->prob.nshots;
+  return (int64_t)c->full.host.NZ * c->full.host.NX * shot_group(c, c->full);
 }
 
 }  // extern "C"

@@ -53,6 +53,45 @@ def test_batched_equals_looped_bitwise(fd):
     batch.close()
 
 
+@pytest.mark.parametrize("fd", ["f32", "f16"])
+def test_shot_groups_bitwise(fd):
+    # five shots advanced one at a time, in balanced groups (3 + 2 and
+    # 2 + 2 + 1), all at once and in the default grouping, with the full grid
+    # and the slab grouped differently, with and without graphs: every output
+    # bitwise equal
+    xs = (105.0, 431.0, 777.0, 1010.0, 1212.0)
+    prob = problem(xs)
+    print(f"case shot groups dtype={fd}", flush=True)
+    kap = inputs.kappa_from_velocity(
+        inputs.layered_velocity(prob.nz, prob.nx, prob.h, np.random.default_rng(3)))
+    rng = np.random.default_rng(5)
+    d = torch.tensor(rng.standard_normal((len(xs), prob.nt, prob.nr)), dtype=torch.float32,
+                     device="cuda")
+    h = torch.tensor(rng.standard_normal((len(xs), prob.nt, prob.ns)), dtype=torch.float32,
+                     device="cuda")
+    ctx = ssx.Context(prob, kap, RHO, field_dtype=fd)
+
+    def run():
+        out = [ctx.fwd(h, ctx.empty_r()), ctx.adj(d, ctx.empty_s()),
+               ctx.precond(1e-3, h, ctx.empty_s())]
+        hk, hist, _, _ = ctx.pcg_solve(d, 1e-3, 3)
+        torch.cuda.synchronize()
+        return [t.cpu() for t in out] + [hk.cpu(), torch.tensor(hist)]
+
+    ctx.set_option(ssx.OPT_SHOT_GROUP, len(xs))
+    ref = run()
+    for graphs in (True, False):
+        ctx.set_graphs(graphs)
+        for full, slab in ((1, 1), (3, 3), (2, 5), (5, 2), (0, 0)):
+            ctx.set_option(ssx.OPT_SHOT_GROUP, full)
+            ctx.set_option(ssx.OPT_SHOT_GROUP_SLAB, slab)
+            for i, (a, b) in enumerate(zip(ref, run())):
+                assert torch.equal(a, b), (fd, graphs, full, slab, i)
+    with pytest.raises(ssx.SSXError):
+        ctx.set_option(ssx.OPT_SHOT_GROUP, -1)
+    ctx.close()
+
+
 def test_c3_full_size_truncated_parity():
     # 64 shots on the 401 x 801 layered model in one launch per step
     # (nt = 2000): first / last N samples of two shots against the oracle

@@ -43,8 +43,9 @@ def kappa(prob, seed=1):
 def run_all(ctx, prob, fd, seed=0):
     dt = torch.float64 if fd == "f64" else torch.float32
     g = torch.Generator(device="cpu").manual_seed(seed)
-    h = torch.randn((2, prob.nt, prob.ns), generator=g, dtype=torch.float64).to(dt).cuda()
-    r = torch.randn((2, prob.nt, prob.nr), generator=g, dtype=torch.float64).to(dt).cuda()
+    S = len(prob.xs)
+    h = torch.randn((S, prob.nt, prob.ns), generator=g, dtype=torch.float64).to(dt).cuda()
+    r = torch.randn((S, prob.nt, prob.nr), generator=g, dtype=torch.float64).to(dt).cuda()
     d = ctx.fwd(h, ctx.empty_r())
     gg = ctx.adj(r, ctx.empty_s())
     P, V = ctx.slab_fwd(h, ctx.empty_s(), ctx.empty_s())
@@ -147,4 +148,24 @@ def test_half_precision_storage_error(fd, tol):
             errs.append(np.linalg.norm(got - ref) / np.linalg.norm(ref))
     print(f"{fd} storage: relative L2 errors fwd/adj/precond {errs}")
     assert max(errs) < tol
+    ctx.close()
+
+
+def test_autotune_choice_applies_and_keeps_results():
+    # the tuner's choice is a valid option set, and results under it equal
+    # the defaults bitwise
+    from paper_2203_16573_amd import autotune
+    prob = problem(8, "wide", nt=40, xs=(300.0, 717.0, 1500.0))
+    print("case autotune wide f32", flush=True)
+    kap = kappa(prob)
+    choice = autotune.choose(prob, kap, RHO, field_dtype="f32", cache_path=None, nt_tune=20)
+    for key in ("step_kernel", "steps_per_launch", "tile_z", "shot_group",
+                "steps_per_launch_slab", "tile_z_slab", "shot_group_slab"):
+        assert key in choice, key
+    assert 1 <= choice["shot_group"] <= 3
+    ctx = ssx.Context(prob, kap, RHO, field_dtype="f32")
+    ref = run_all(ctx, prob, "f32")
+    autotune.apply(ctx, choice)
+    for a, b in zip(ref, run_all(ctx, prob, "f32")):
+        assert np.array_equal(a, b)
     ctx.close()
