@@ -197,7 +197,15 @@ ssx_status ssx_pcg_solve(ssx_ctx* ctx, const void* d, double alpha_rel, int32_t 
  *   SSX_OPT_STEPS_PER_LAUNCH      time steps fused per launch of the fused
  *                       kernel on the full grid: 1 (default) or 2 (2: F32
  *                       fields only; uses a tile height of 8).
- *   SSX_OPT_STEPS_PER_LAUNCH_SLAB the same for the thin slab.
+ *   SSX_OPT_STEPS_PER_LAUNCH_SLAB the same for the thin slab, and also 4
+ *                       or 8 (not for F64 fields, slabs of at most 56
+ *                       rows): each workgroup holds the whole slab height
+ *                       of a strip of columns in LDS and advances it 4 or
+ *                       8 steps, recomputing an x halo of that many
+ *                       stencil reaches on each side.
+ *   SSX_OPT_SLAB_STRIP  strip width in columns of the 4/8-step slab kernel,
+ *                       halo included: 64 or 128 (0, the default: 128;
+ *                       8 steps always use 128).
  *   SSX_OPT_SHOT_GROUP  shots advanced together by one launch on the full
  *                       grid and the thin slab: the shots are split into
  *                       balanced groups of at most this many, and each
@@ -215,7 +223,8 @@ typedef enum {
   SSX_OPT_STEPS_PER_LAUNCH = 4,
   SSX_OPT_STEPS_PER_LAUNCH_SLAB = 5,
   SSX_OPT_SHOT_GROUP = 6,
-  SSX_OPT_SHOT_GROUP_SLAB = 7
+  SSX_OPT_SHOT_GROUP_SLAB = 7,
+  SSX_OPT_SLAB_STRIP = 8
 } ssx_option;
 ssx_status ssx_set_option(ssx_ctx* ctx, int option, int value);
 
@@ -228,6 +237,12 @@ const char* ssx_last_error(void);
  * accounting. */
 const char* ssx_step_kernel_name(ssx_ctx* ctx);
 int64_t ssx_cells_per_launch(ssx_ctx* ctx);
+
+/* Launch shape of the full-grid step as the next propagation will run it:
+ * shape[0] tile height, shape[1] time steps per launch, shape[2] shots per
+ * launch (options resolved, defaults included).  shape is a host array of
+ * three; SSX_ERR_ARG for a null argument. */
+ssx_status ssx_launch_shape(ssx_ctx* ctx, int32_t* shape);
 
 #ifdef __cplusplus
 }

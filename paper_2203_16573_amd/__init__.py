@@ -34,7 +34,7 @@ DTYPES = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 PEN_A, PEN_ATA, PEN_DHALF = 0, 1, 2
 OPT_GRAPHS, OPT_STEP_KERNEL, OPT_TILE_Z, OPT_TILE_Z_SLAB = 0, 1, 2, 3
 OPT_STEPS_PER_LAUNCH, OPT_STEPS_PER_LAUNCH_SLAB = 4, 5
-OPT_SHOT_GROUP, OPT_SHOT_GROUP_SLAB = 6, 7
+OPT_SHOT_GROUP, OPT_SHOT_GROUP_SLAB, OPT_SLAB_STRIP = 6, 7, 8
 
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_CFL", 3: "ERR_OOM", 4: "ERR_HIP",
           5: "ERR_BREAKDOWN", 6: "ERR_NONFINITE"}
@@ -42,7 +42,7 @@ STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_CFL", 3: "ERR_OOM", 4: "ERR_HIP",
 EXPORTS = ("ssx_validate", "ssx_footprint", "ssx_create", "ssx_destroy", "ssx_fwd",
            "ssx_adj", "ssx_slab_fwd", "ssx_slab_adj", "ssx_penalty", "ssx_precond",
            "ssx_normal", "ssx_dot", "ssx_pcg_solve", "ssx_set_option", "ssx_last_error",
-           "ssx_step_kernel_name", "ssx_cells_per_launch")
+           "ssx_step_kernel_name", "ssx_cells_per_launch", "ssx_launch_shape")
 
 
 class SSXError(RuntimeError):
@@ -102,6 +102,8 @@ def lib():
         L.ssx_step_kernel_name.restype = ctypes.c_char_p
         L.ssx_cells_per_launch.argtypes = [vp]
         L.ssx_cells_per_launch.restype = ctypes.c_int64
+        L.ssx_launch_shape.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+        L.ssx_launch_shape.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -263,6 +265,15 @@ class Context:
 
     def cells_per_launch(self) -> int:
         return int(lib().ssx_cells_per_launch(self._ctx))
+
+    def launch_shape(self) -> tuple:
+        """(tile height, steps per launch, shots per launch) of the full-grid step."""
+        shape = (ctypes.c_int32 * 3)()
+        _check(lib().ssx_launch_shape(self._ctx, shape))
+        return tuple(int(v) for v in shape)
+
+    def tile_z(self) -> int:
+        return self.launch_shape()[0]
 
     def close(self):
         if getattr(self, "_ctx", None):

@@ -17,10 +17,12 @@ import json
 import os
 import threading
 
-from . import (OPT_SHOT_GROUP, OPT_SHOT_GROUP_SLAB, OPT_STEP_KERNEL, OPT_STEPS_PER_LAUNCH,
-               OPT_STEPS_PER_LAUNCH_SLAB, OPT_TILE_Z, OPT_TILE_Z_SLAB, Context)
+from . import (OPT_SHOT_GROUP, OPT_SHOT_GROUP_SLAB, OPT_SLAB_STRIP, OPT_STEP_KERNEL,
+               OPT_STEPS_PER_LAUNCH, OPT_STEPS_PER_LAUNCH_SLAB, OPT_TILE_Z, OPT_TILE_Z_SLAB,
+               Context)
 
-DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ssx", "autotune-v3.json")
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ssx", "autotune-v4.json")
+SLAB_MAXZ = 56  # tallest slab the 4/8-step slab kernel holds
 _lock = threading.Lock()
 
 
@@ -69,7 +71,8 @@ def tune(prob, kappa, rho, xs=None, field_dtype="f32", nt_tune: int = 60,
          stream=None) -> dict:
     """Measure the candidates and return {"step_kernel", "steps_per_launch",
     "tile_z", "shot_group", "steps_per_launch_slab", "tile_z_slab",
-    "shot_group_slab", "us": {...}} (per-step times in microseconds)."""
+    "slab_strip", "shot_group_slab", "us": {...}} (per-step times in
+    microseconds)."""
     import torch
     xs = tuple(prob.xs) if xs is None else tuple(xs)
     short = prob.replace(nt=min(int(nt_tune), int(prob.nt))) if hasattr(prob, "replace") else prob
@@ -91,6 +94,12 @@ def tune(prob, kappa, rho, xs=None, field_dtype="f32", nt_tune: int = 60,
         cands = [(1, 8), (1, 16), (1, 32), (2, 8)]
     else:  # two steps per launch are FP32-only
         cands = [(1, 8), (1, 16), (1, 32)]
+    # slab candidates: the same, plus the multi-step slab kernel
+    # (steps, strip width) with the tile height of its one-step remainder
+    slab_cands = [(spl, tz, 0) for spl, tz in cands]
+    nzs = abs(short.slab_dz) + 1 + short.order + 2 * short.npml + 1
+    if field_dtype != "f64" and nzs <= SLAB_MAXZ:
+        slab_cands += [(4, 8, 64), (4, 8, 128), (8, 8, 128)]
     us = {}
     ctx.set_option(OPT_STEP_KERNEL, 1)
     ctx.set_option(OPT_SHOT_GROUP, 0)
@@ -98,17 +107,23 @@ def tune(prob, kappa, rho, xs=None, field_dtype="f32", nt_tune: int = 60,
     for spl, tz in cands:
         ctx.set_option(OPT_TILE_Z, tz)
         ctx.set_option(OPT_STEPS_PER_LAUNCH, spl)
-        tag = f"s{spl}_tz{tz}"
-        us[f"full_{tag}"] = 1e3 * _time_ms(full) / (2 * nt)
-        us[f"slab_{tag}"] = 1e3 * _time_ms(slab) / (2 * nt)
+        us[f"full_s{spl}_tz{tz}"] = 1e3 * _time_ms(full) / (2 * nt)
+    ctx.set_option(OPT_STEPS_PER_LAUNCH, 1)
+    for spl, tz, strip in slab_cands:
+        ctx.set_option(OPT_TILE_Z_SLAB, tz)
+        ctx.set_option(OPT_STEPS_PER_LAUNCH_SLAB, spl)
+        ctx.set_option(OPT_SLAB_STRIP, strip)
+        us[f"slab_s{spl}_tz{tz}_w{strip}"] = 1e3 * _time_ms(slab) / (2 * nt)
+    ctx.set_option(OPT_STEPS_PER_LAUNCH_SLAB, 1)
+    ctx.set_option(OPT_SLAB_STRIP, 0)
     ctx.set_option(OPT_STEPS_PER_LAUNCH, 1)
     ctx.set_option(OPT_STEP_KERNEL, 0)
     us["full_split"] = 1e3 * _time_ms(full) / (2 * nt)
     us["slab_split"] = 1e3 * _time_ms(slab) / (2 * nt)
     best_full = min(cands, key=lambda c: us[f"full_s{c[0]}_tz{c[1]}"])
-    best_slab = min(cands, key=lambda c: us[f"slab_s{c[0]}_tz{c[1]}"])
+    best_slab = min(slab_cands, key=lambda c: us[f"slab_s{c[0]}_tz{c[1]}_w{c[2]}"])
     fused_total = us[f"full_s{best_full[0]}_tz{best_full[1]}"] + \
-        us[f"slab_s{best_slab[0]}_tz{best_slab[1]}"]
+        us[f"slab_s{best_slab[0]}_tz{best_slab[1]}_w{best_slab[2]}"]
     split_total = us["full_split"] + us["slab_split"]
     step_kernel = 1 if fused_total <= split_total else 0
     ctx.set_option(OPT_STEP_KERNEL, step_kernel)
@@ -116,6 +131,7 @@ def tune(prob, kappa, rho, xs=None, field_dtype="f32", nt_tune: int = 60,
     ctx.set_option(OPT_TILE_Z_SLAB, best_slab[1])
     ctx.set_option(OPT_STEPS_PER_LAUNCH, best_full[0])
     ctx.set_option(OPT_STEPS_PER_LAUNCH_SLAB, best_slab[0])
+    ctx.set_option(OPT_SLAB_STRIP, best_slab[2])
     group, group_slab = auto_group, 0
     if ns > 1:
         for gsz in _group_candidates(auto_group, ns):
@@ -127,7 +143,7 @@ def tune(prob, kappa, rho, xs=None, field_dtype="f32", nt_tune: int = 60,
     return {"step_kernel": step_kernel,
             "steps_per_launch": best_full[0], "tile_z": best_full[1], "shot_group": group,
             "steps_per_launch_slab": best_slab[0], "tile_z_slab": best_slab[1],
-            "shot_group_slab": group_slab, "us": us}
+            "slab_strip": best_slab[2], "shot_group_slab": group_slab, "us": us}
 
 
 def choose(prob, kappa, rho, xs=None, field_dtype="f32", cache_path: str | None = DEFAULT_CACHE,
@@ -159,3 +175,4 @@ def apply(ctx: Context, choice: dict) -> None:
     ctx.set_option(OPT_STEPS_PER_LAUNCH_SLAB, int(choice.get("steps_per_launch_slab", 1)))
     ctx.set_option(OPT_SHOT_GROUP, int(choice.get("shot_group", 0)))
     ctx.set_option(OPT_SHOT_GROUP_SLAB, int(choice.get("shot_group_slab", 0)))
+    ctx.set_option(OPT_SLAB_STRIP, int(choice.get("slab_strip", 0)))

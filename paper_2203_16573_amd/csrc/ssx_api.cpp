@@ -251,7 +251,7 @@ struct GridDev {
 struct GraphEntry {
   int op;
   const void* ptr[4];
-  int tile_z, fused, spl, group;
+  int tile_z, fused, spl, group, strip;
   hipGraphExec_t exec;
   unsigned long long last_use;
 };
@@ -280,6 +280,7 @@ struct ssx_ctx {
   int tile_z_full = 0, tile_z_slab = 0;  // 0: default
   int spl_full = 1, spl_slab = 1;        // time steps per fused launch
   int group_full = 0, group_slab = 0;    // shots per launch (0: from the cache budget)
+  int slab_strip = 0;                    // strip width of the multi-step slab kernel (0: 128)
   hipStream_t cap_stream = nullptr;      // capture stream (graphs are launched on `stream`)
   std::vector<GraphEntry> graphs_cache;
   unsigned long long use_clock = 0;
@@ -470,6 +471,9 @@ ssx_status issue_group(ssx_ctx* c, GridDev& gd, bool adj, const Fields& f0, cons
   a.dir = adj ? -1 : 1;
   const int ntz1 = (gd.host.NZ + tz - 1) / tz;
   const int ntz2 = (gd.host.NZ + STEP2_TZ - 1) / STEP2_TZ;
+  // multi-step slab kernel: strip width (ns = 8 needs 128 columns)
+  const int wr = (spl == 8 || c->slab_strip == 0) ? 128 : c->slab_strip;
+  const int wown = spl >= 4 ? slab_strip_width(order, spl, wr) : 0;
   Fields buf[2] = {f0, f1};
   int cur = 0;
   // one launch covering `steps` (1 or 2) steps starting at step n with the
@@ -488,6 +492,15 @@ ssx_status issue_group(ssx_ctx* c, GridDev& gd, bool adj, const Fields& f0, cons
       a.pi.n = ipi;
       a.ntz = ntz2;
       SSX_HIP(launch_step2(c->fdt, order, adj, a, s));
+    } else if (steps >= 4) {
+      a.vs.n = ivs;
+      a.vi.n = ivi;
+      a.ps.n = ips;
+      a.pi.n = ipi;
+      a.ntz = 1;
+      a.ntx = (gd.host.NX + wown - 1) / wown;
+      SSX_HIP(launch_slab(c->fdt, order, adj, steps, wr, a, s));
+      a.ntx = (gd.host.NX + step_tile_width() - 1) / step_tile_width();
     } else {
       a.vs.n = (vs.out && ivs >= 0 && ivs < nt) ? ivs : -1;
       a.vi.n = (vi.in && ivi >= 0 && ivi < nt) ? ivi : -1;
@@ -600,10 +613,11 @@ ssx_status propagate(ssx_ctx* c, int op, GridDev& gd, bool adj, const LineDev& v
   const int tz = (&gd == &c->full) ? c->tile_z_full : c->tile_z_slab;
   const int spl = (&gd == &c->full) ? c->spl_full : c->spl_slab;
   const int group = (&gd == &c->full) ? c->group_full : c->group_slab;
+  const int strip = (&gd == &c->full) ? 0 : c->slab_strip;
   for (GraphEntry& e : c->graphs_cache) {
     if (e.op == op && e.ptr[0] == key[0] && e.ptr[1] == key[1] && e.ptr[2] == key[2] &&
         e.ptr[3] == key[3] && e.tile_z == tz && e.fused == (int)c->fused && e.spl == spl &&
-        e.group == group) {
+        e.group == group && e.strip == strip) {
       e.last_use = ++c->use_clock;
       SSX_HIP(hipGraphLaunch(e.exec, c->stream));
       return SSX_OK;
@@ -638,6 +652,7 @@ ssx_status propagate(ssx_ctx* c, int op, GridDev& gd, bool adj, const LineDev& v
   ge.fused = (int)c->fused;
   ge.spl = spl;
   ge.group = group;
+  ge.strip = strip;
   ge.exec = exec;
   ge.last_use = ++c->use_clock;
   c->graphs_cache.push_back(ge);
@@ -992,8 +1007,17 @@ ssx_status ssx_set_option(ssx_ctx* c, int option, int value) {
       if (option == SSX_OPT_TILE_Z) c->tile_z_full = value;
       c->tile_z_slab = value;
       return SSX_OK;
-    case SSX_OPT_STEPS_PER_LAUNCH:
     case SSX_OPT_STEPS_PER_LAUNCH_SLAB:
+      if (value == 4 || value == 8) {
+        if (c->fdt == Dt::F64)
+          return fail(SSX_ERR_ARG, "4 or 8 slab steps per launch are not available for F64 fields");
+        if (c->slab.host.NZ > SLAB_MAXZ)
+          return fail(SSX_ERR_ARG, "the slab is too tall for 4 or 8 steps per launch");
+        c->spl_slab = value;
+        return SSX_OK;
+      }
+      [[fallthrough]];
+    case SSX_OPT_STEPS_PER_LAUNCH:
       if (value != 1 && value != 2) return fail(SSX_ERR_ARG, "steps per launch must be 1 or 2");
       // two steps per launch: FP32 fields only (the 16-bit instances are
       // switched off after a device memory fault whose cause is not known)
@@ -1001,6 +1025,11 @@ ssx_status ssx_set_option(ssx_ctx* c, int option, int value) {
         return fail(SSX_ERR_ARG, "two steps per launch are available for F32 fields only");
       if (option == SSX_OPT_STEPS_PER_LAUNCH) c->spl_full = value;
       c->spl_slab = value;
+      return SSX_OK;
+    case SSX_OPT_SLAB_STRIP:
+      if (value != 0 && value != 64 && value != 128)
+        return fail(SSX_ERR_ARG, "slab strip width must be 0, 64 or 128");
+      c->slab_strip = value;
       return SSX_OK;
     case SSX_OPT_SHOT_GROUP:
     case SSX_OPT_SHOT_GROUP_SLAB:
@@ -1017,6 +1046,17 @@ const char* ssx_last_error(void) { return g_err.c_str(); }
 const char* ssx_step_kernel_name(ssx_ctx* c) {
   if (c && !c->fused) return "k_vel + k_pres";
   return "k_step";
+}
+
+ssx_status ssx_launch_shape(ssx_ctx* c, int32_t* shape) {
+  if (!c || !shape) return fail(SSX_ERR_ARG, "null argument");
+  shape[0] = c->fused ? (c->spl_full == 2 ? STEP2_TZ
+                                           : (c->tile_z_full ? c->tile_z_full
+                                                             : default_tile_z(c, c->full)))
+                      : 0;
+  shape[1] = c->fused ? c->spl_full : 1;
+  shape[2] = shot_group(c, c->full);
+  return SSX_OK;
 }
 
 int64_t ssx_cells_per_launch(ssx_ctx* c) {

@@ -90,6 +90,14 @@ hipError_t launch_step(Dt dt, int order, bool adj, int tz, StepArgs a, hipStream
 hipError_t launch_step2(Dt dt, int order, bool adj, StepArgs a, hipStream_t s);
 constexpr int STEP2_TZ = 8;
 int step_tile_width();
+// Several time steps per launch on a slab grid of at most SLAB_MAXZ rows
+// (FP32, FP16 or BF16 fields): ns steps (4 or 8) on strips of wr columns
+// (64 or 128; ns = 8 needs 128) held whole in LDS.  a.ntx must be the strip
+// count ceil(NX / slab_strip_width(order, ns, wr)) and a.ntz 1.
+constexpr int SLAB_MAXZ = 56;
+hipError_t launch_slab(Dt dt, int order, bool adj, int ns, int wr, StepArgs a, hipStream_t s);
+// owned columns per strip (0 for an unsupported combination)
+int slab_strip_width(int order, int ns, int wr);
 // All return hipSuccess or the launch error.
 hipError_t launch_vel(Dt dt, int order, bool adj, const Fields& f, const GridDims& g,
                       const Coef& c, const LineDev& samp_line, const TraceIO& samp,

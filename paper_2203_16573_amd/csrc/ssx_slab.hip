@@ -1,0 +1,363 @@
+// Several time steps per launch on the thin slab.
+//
+// The slab grid is short (2 L + |dz| + 1 + 2K rows, under SLAB_MAXZ), so one
+// workgroup holds its whole height for a strip of WR columns in LDS and
+// advances it NS steps before writing back.  Only x needs a halo: one step
+// of the staggered scheme reads 2K-1 columns to either side (K-1 and K for
+// the velocity, K and K-1 for the pressure), so after NS steps the columns
+// at least NS (2K-1) from the strip's edges are exact; those H columns on
+// each side are recomputed by both neighbours, the W = WR - 2H in the middle
+// are owned and written back.  Strips touching the grid's left or right
+// edge keep the columns outside the grid at zero, as the stored ghost
+// columns are.  Rows outside the slab read zero from padding rows.
+//
+// Every cell update uses the same expressions, in the same order, as the
+// split and fused step kernels (values are rounded to the storage type
+// wherever those kernels store them), so results are bitwise equal.  The
+// transposed step reads P~_x = P~_z + aux in the x-stencil everywhere (aux is
+// zero off the absorbing frame), like the fused kernel.
+//
+// Trace slots use level-0 indices from the host and step t uses n + dir t;
+// indices outside [0, nt) are skipped.
+#include "ssx_cell.h"
+
+#include <type_traits>
+
+namespace ssx {
+
+constexpr int SLAB_THREADS = 1024;
+
+template <int K, int NS, int WR>
+struct SlabShape {
+  static constexpr int R = 2 * K - 1;                 // per-step reach in x
+  static constexpr int H = (NS * R + 3) / 4 * 4;      // halo columns each side
+  static constexpr int W = WR - 2 * H;                // owned columns
+  static constexpr int RP = WR + 8;                   // LDS pitch, x-stencil arrays
+  static constexpr int ZR = SLAB_MAXZ + 2 * K;        // LDS rows, z-stencil arrays
+  static constexpr int G = WR / 4;                    // 4-column groups per row
+  static constexpr int NQ = (SLAB_MAXZ * G + SLAB_THREADS - 1) / SLAB_THREADS;
+  static_assert(W > 0 && W % 4 == 0, "strip too narrow for the step count");
+  static_assert(H <= GX, "halo wider than the ghost columns");
+};
+
+template <int K, int NS, int WR>
+int slab_owned_width() {
+  return SlabShape<K, NS, WR>::W;
+}
+
+template <int K, bool ADJ, typename T, int NS, int WR>
+__global__ __launch_bounds__(SLAB_THREADS) void k_slab(StepArgs a) {
+  using C = typename Tr<T>::C;
+  using V = typename Tr<T>::V;
+  using S = SlabShape<K, NS, WR>;
+  static_assert(std::is_same<C, float>::value, "FP32 compute only");
+  constexpr int H = S::H, W = S::W, RP = S::RP, G = S::G, NQ = S::NQ;
+  // p: rows -K .. SLAB_MAXZ+K-1, columns -4 .. WR+3
+  __shared__ __align__(16) C sp[S::ZR * RP];
+  // v_x and the absorbing-layer auxiliary: rows 0 .. SLAB_MAXZ-1, columns
+  // -4 .. WR+3
+  __shared__ __align__(16) C svx[SLAB_MAXZ * RP];
+  __shared__ __align__(16) C sau[SLAB_MAXZ * RP];
+  // v_z: rows -K .. SLAB_MAXZ+K-1, columns 0 .. WR-1
+  __shared__ __align__(16) C svz[S::ZR * WR];
+  // absorbing-layer factors: a_n b_n a_h b_h over the region's columns, then
+  // over the slab's rows
+  __shared__ __align__(16) C spx[4 * WR];
+  __shared__ __align__(16) C spz[4 * SLAB_MAXZ];
+  // injected values of the current step on the two rows of the v_z line and
+  // of the pressure line, over the region's columns
+  __shared__ __align__(16) C ssv[2 * WR];
+  __shared__ __align__(16) C ssp[2 * WR];
+  // ck: rows 0 .. SLAB_MAXZ-1, columns 0 .. WR-1
+  __shared__ __align__(16) C sck[SLAB_MAXZ * WR];
+  auto P_ = [](int I, int c) { return (I + K) * RP + c + 4; };
+  auto X_ = [](int I, int c) { return I * RP + c + 4; };
+  auto Z_ = [](int I, int c) { return (I + K) * WR + c; };
+
+  const int NZ = a.g.NZ, NX = a.g.NX, Pt = a.g.pitch, L = a.g.L;
+  const int shot = blockIdx.x / a.ntx;
+  const int strip = blockIdx.x - shot * a.ntx;
+  const int x0 = strip * W;      // first owned column
+  const int xr = x0 - H;         // grid column of region column 0
+  const long long base = a.g.origin + (long long)shot * a.g.field_stride;
+  const T* pA = static_cast<const T*>(a.in.p) + base;
+  const T* vxA = static_cast<const T*>(a.in.vx) + base;
+  const T* vzA = static_cast<const T*>(a.in.vz) + base;
+  const T* auA = static_cast<const T*>(a.in.aux) + base;
+  const C* ckp = static_cast<const C*>(a.c.ck) + a.g.origin;
+  const C* pml = static_cast<const C*>(a.c.pml);
+  const C cb = C(a.c.cb);
+  const int tid = threadIdx.x;
+  // values a line injects at step index idx on its rows row0 (buf[0..WR))
+  // and row1 (buf[WR..2WR)), computed once per step by the first 2 WR threads
+  auto fill_src = [&](const LineDev& l, const TraceIO& io, int idx, C* buf) {
+    if (tid < 2 * WR) {
+      const int j = tid / WR, c = tid - j * WR;
+      buf[tid] = line_src_at<C, V>(l, io, idx, a.nt, j ? l.row1 : l.row0, xr + c, shot);
+    }
+  };
+
+  // ---- zero LDS (padding rows and columns stay zero) ----------------------
+  for (int i = tid; i < S::ZR * RP; i += SLAB_THREADS) sp[i] = C(0);
+  for (int i = tid; i < SLAB_MAXZ * RP; i += SLAB_THREADS) svx[i] = C(0);
+  for (int i = tid; i < SLAB_MAXZ * RP; i += SLAB_THREADS) sau[i] = C(0);
+  for (int i = tid; i < S::ZR * WR; i += SLAB_THREADS) svz[i] = C(0);
+  for (int i = tid; i < 4 * WR; i += SLAB_THREADS) {
+    const int f = i / WR, J = xr + (i - f * WR);
+    spx[i] = (J >= 0 && J < NX) ? pml[f * Pt + GX + J] : C(1);
+  }
+  for (int i = tid; i < 4 * SLAB_MAXZ; i += SLAB_THREADS) {
+    const int f = i / SLAB_MAXZ, I = i - f * SLAB_MAXZ;
+    spz[i] = I < NZ ? pml[4 * Pt + f * NZ + I] : C(1);
+  }
+  __syncthreads();
+
+  // ---- load the strip ----------------------------------------------------
+  // task q: row q / G, columns 4 (q % G) .. +3 of the region
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    const int q = tid + SLAB_THREADS * k;
+    const int I = q / G, c = 4 * (q - (q / G) * G), J = xr + c;
+    if (I < NZ && J < NX) {
+      // columns J .. J+3 lie in [-GX, NX + 3) (ghost columns read zero)
+      const long long o = (long long)I * Pt + J;
+      C v[4];
+      ld4(v, pA + o);
+      st4(sp + P_(I, c), v);
+      ld4(v, vxA + o);
+      st4(svx + X_(I, c), v);
+      ld4(v, vzA + o);
+      st4(svz + Z_(I, c), v);
+      ld4(v, auA + o);
+      st4(sau + X_(I, c), v);
+      ld4(v, ckp + o);
+      st4(sck + I * WR + c, v);
+    }
+  }
+  fill_src(a.vil, a.vi, a.vi.n, ssv);
+  __syncthreads();
+
+  for (int t = 0; t < NS; ++t) {
+    const int ivs = a.vs.n + a.dir * t, ivi = a.vi.n + a.dir * t;
+    const int ips = a.ps.n + a.dir * t, ipi = a.pi.n + a.dir * t;
+
+    // pressure-line sampling (p^n), owned columns
+    if (a.vs.out && ivs >= 0 && ivs < a.nt && tid < W) {
+      const int c = H + tid, J = xr + c;
+      if (J < NX && J >= a.vsl.col0 && J < a.vsl.col0 + a.vsl.ntr) {
+        const C val = C(a.vsl.w0) * sp[P_(a.vsl.row0, c)] + C(a.vsl.w1) * sp[P_(a.vsl.row1, c)];
+        line_out_at<C, V>(a.vsl, a.vs, ivs, J, shot, val);
+      }
+    }
+
+    fill_src(a.pil, a.pi, ipi, ssp);  // read after the next barrier
+
+    // ---- velocities ----------------------------------------------------------
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+      const int q = tid + SLAB_THREADS * k;
+      const int I = q / G, c = 4 * (q - (q / G) * G), J = xr + c;
+      if (I >= NZ) continue;
+      C w[12];  // p (transposed: P~_z + aux) at region columns c-4 .. c+7
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        C pv[4];
+        ld4(pv, sp + P_(I, c - 4 + 4 * j));
+        if constexpr (ADJ) {
+          C av[4];
+          ld4(av, sau + X_(I, c - 4 + 4 * j));
+#pragma unroll
+          for (int e = 0; e < 4; ++e) pv[e] = pv[e] + av[e];
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w[4 * j + e] = pv[e];
+      }
+      C ovx[4], ovz[4], nvx[4], nvz[4];
+      ld4(ovx, svx + X_(I, c));
+      ld4(ovz, svz + Z_(I, c));
+      C sz[4] = {C(0), C(0), C(0), C(0)};
+#pragma unroll
+      for (int m = 1; m <= K; ++m) {
+        C hi[4], lo[4];
+        ld4(hi, sp + P_(I + m, c));
+        ld4(lo, sp + P_(I + 1 - m, c));
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sz[e] = acc(sz[e], wst<K, C>(m - 1), hi[e], lo[e]);
+      }
+      C axh[4], bxh[4];
+      ld4(axh, spx + 2 * WR + c);
+      ld4(bxh, spx + 3 * WR + c);
+      const C azh = spz[2 * SLAB_MAXZ + I], bzh = spz[3 * SLAB_MAXZ + I];
+      const C* src_row = I == a.vil.row0 ? ssv : (I == a.vil.row1 ? ssv + WR : nullptr);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int Je = J + e;
+        nvx[e] = ovx[e];
+        nvz[e] = ovz[e];
+        if (Je >= 0 && Je < NX) {
+          C sx = C(0);
+#pragma unroll
+          for (int m = 1; m <= K; ++m) sx = acc(sx, wst<K, C>(m - 1), w[e + 4 + m], w[e + 5 - m]);
+          nvx[e] = rnd<T>(upd_v<ADJ>(axh[e], bxh[e], cb, ovx[e], sx, C(0)));
+          const C src = src_row ? src_row[c + e] : C(0);
+          nvz[e] = rnd<T>(upd_v<ADJ>(azh, bzh, cb, ovz[e], sz[e], src));
+        }
+      }
+      st4(svx + X_(I, c), nvx);
+      st4(svz + Z_(I, c), nvz);
+      // one task at a time: interleaving two tasks' loads spills registers
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+
+    // v_z-line sampling (v^{n+1/2}), owned columns
+    if (a.ps.out && ips >= 0 && ips < a.nt && tid < W) {
+      const int c = H + tid, J = xr + c;
+      if (J < NX && J >= a.psl.col0 && J < a.psl.col0 + a.psl.ntr) {
+        const C val = C(a.psl.w0) * svz[Z_(a.psl.row0, c)] + C(a.psl.w1) * svz[Z_(a.psl.row1, c)];
+        line_out_at<C, V>(a.psl, a.ps, ips, J, shot, val);
+      }
+    }
+
+    if (t + 1 < NS) fill_src(a.vil, a.vi, ivi + a.dir, ssv);  // read after the next barrier
+
+    // ---- pressure --------------------------------------------------------------
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+      const int q = tid + SLAB_THREADS * k;
+      const int I = q / G, c = 4 * (q - (q / G) * G), J = xr + c;
+      if (I >= NZ) continue;
+      C w[12];  // v_x at region columns c-4 .. c+7
+      ld4(*reinterpret_cast<C(*)[4]>(w), svx + X_(I, c - 4));
+      ld4(*reinterpret_cast<C(*)[4]>(w + 4), svx + X_(I, c));
+      ld4(*reinterpret_cast<C(*)[4]>(w + 8), svx + X_(I, c + 4));
+      C dx[4] = {C(0), C(0), C(0), C(0)}, dz[4] = {C(0), C(0), C(0), C(0)};
+#pragma unroll
+      for (int m = 1; m <= K; ++m) {
+        C hi[4], lo[4];
+        ld4(hi, svz + Z_(I + m - 1, c));
+        ld4(lo, svz + Z_(I - m, c));
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          dx[e] = acc(dx[e], wst<K, C>(m - 1), w[e + m + 3], w[e + 4 - m]);
+          dz[e] = acc(dz[e], wst<K, C>(m - 1), hi[e], lo[e]);
+        }
+      }
+      C pc[4], pn[4], au[4], an[4], ck[4], axn[4], bxn[4];
+      ld4(pc, sp + P_(I, c));
+      ld4(ck, sck + I * WR + c);
+      ld4(au, sau + X_(I, c));
+      ld4(axn, spx + c);
+      ld4(bxn, spx + WR + c);
+      const C azn = spz[I], bzn = spz[SLAB_MAXZ + I];
+      const C* src_row = I == a.pil.row0 ? ssp : (I == a.pil.row1 ? ssp + WR : nullptr);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int Je = J + e;
+        pn[e] = pc[e];
+        an[e] = au[e];
+        if (Je >= 0 && Je < NX) {
+          const C src = src_row ? src_row[c + e] : C(0);
+          const bool frame = I < L || I >= NZ - L || Je < L || Je >= NX - L;
+          if (!frame) {
+            pn[e] = rnd<T>(upd_p<ADJ>(ck[e], pc[e], dx[e], dz[e], src));
+          } else {
+            C anew;
+            pn[e] = rnd<T>(upd_p_frame<ADJ>(ck[e], pc[e], au[e], dx[e], dz[e], src,
+                                            axn[e], bxn[e], azn, bzn, &anew));
+            an[e] = rnd<T>(anew);
+          }
+        }
+      }
+      st4(sp + P_(I, c), pn);
+      st4(sau + X_(I, c), an);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+  }
+
+  // ---- write the owned columns ------------------------------------------------
+  T* pB = static_cast<T*>(a.out.p) + base;
+  T* vxB = static_cast<T*>(a.out.vx) + base;
+  T* vzB = static_cast<T*>(a.out.vz) + base;
+  T* auB = static_cast<T*>(a.out.aux) + base;
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    const int q = tid + SLAB_THREADS * k;
+    const int I = q / G, c = 4 * (q - (q / G) * G), J = xr + c;
+    if (I >= NZ || c < H || c >= H + W || J >= NX) continue;
+    const long long o = (long long)I * Pt + J;
+    C v[4];
+    if (J + 3 < NX) {
+      ld4(v, sp + P_(I, c));
+      st4(pB + o, v);
+      ld4(v, svx + X_(I, c));
+      st4(vxB + o, v);
+      ld4(v, svz + Z_(I, c));
+      st4(vzB + o, v);
+      ld4(v, sau + X_(I, c));
+      st4(auB + o, v);
+    } else {
+      for (int e = 0; e < 4 && J + e < NX; ++e) {
+        stc(pB + o + e, sp[P_(I, c + e)]);
+        stc(vxB + o + e, svx[X_(I, c + e)]);
+        stc(vzB + o + e, svz[Z_(I, c + e)]);
+        stc(auB + o + e, sau[X_(I, c + e)]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+
+template <int K, bool ADJ, typename T>
+static hipError_t slab_t(int ns, int wr, const StepArgs& a, hipStream_t s) {
+  if constexpr (!std::is_same<typename Tr<T>::C, float>::value) {
+    return hipErrorInvalidValue;
+  } else {
+    const int blocks = a.ntx * a.nshots;
+    if (a.g.NZ > SLAB_MAXZ || a.ntz != 1) return hipErrorInvalidValue;
+    if (ns == 4 && wr == 64) {
+      hipLaunchKernelGGL((k_slab<K, ADJ, T, 4, 64>), dim3(blocks), dim3(SLAB_THREADS), 0, s, a);
+    } else if (ns == 4 && wr == 128) {
+      hipLaunchKernelGGL((k_slab<K, ADJ, T, 4, 128>), dim3(blocks), dim3(SLAB_THREADS), 0, s, a);
+    } else if (ns == 8 && wr == 128) {
+      hipLaunchKernelGGL((k_slab<K, ADJ, T, 8, 128>), dim3(blocks), dim3(SLAB_THREADS), 0, s, a);
+    } else {
+      return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
+}
+
+int slab_strip_width(int order, int ns, int wr) {
+  const bool o8 = order == 8;
+  if (ns == 4 && wr == 64) return o8 ? slab_owned_width<4, 4, 64>() : slab_owned_width<2, 4, 64>();
+  if (ns == 4 && wr == 128)
+    return o8 ? slab_owned_width<4, 4, 128>() : slab_owned_width<2, 4, 128>();
+  if (ns == 8 && wr == 128)
+    return o8 ? slab_owned_width<4, 8, 128>() : slab_owned_width<2, 8, 128>();
+  return 0;
+}
+
+hipError_t launch_slab(Dt dt, int order, bool adj, int ns, int wr, StepArgs a, hipStream_t s) {
+  const bool o8 = (order == 8);
+  switch (dt) {
+    case Dt::F64: return hipErrorInvalidValue;
+    case Dt::F32:
+      if (o8) return adj ? slab_t<4, true, float>(ns, wr, a, s) : slab_t<4, false, float>(ns, wr, a, s);
+      return adj ? slab_t<2, true, float>(ns, wr, a, s) : slab_t<2, false, float>(ns, wr, a, s);
+    case Dt::F16:
+      if (o8) return adj ? slab_t<4, true, __half>(ns, wr, a, s) : slab_t<4, false, __half>(ns, wr, a, s);
+      return adj ? slab_t<2, true, __half>(ns, wr, a, s) : slab_t<2, false, __half>(ns, wr, a, s);
+    case Dt::BF16:
+      if (o8)
+        return adj ? slab_t<4, true, __hip_bfloat16>(ns, wr, a, s)
+                   : slab_t<4, false, __hip_bfloat16>(ns, wr, a, s);
+      return adj ? slab_t<2, true, __hip_bfloat16>(ns, wr, a, s)
+                 : slab_t<2, false, __hip_bfloat16>(ns, wr, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace ssx

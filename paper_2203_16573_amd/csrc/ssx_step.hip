@@ -22,104 +22,12 @@
 // storage type): k_vel + k_pres, one thread per cell and two launches per
 // step (the reference); and k_step, one launch per step on an LDS-staged
 // tile with each thread owning 1 x 4 cells.
-#include "ssx_device.h"
+#include "ssx_cell.h"
 
 #include <cmath>
 #include <type_traits>
 
 namespace ssx {
-
-// ---------------------------------------------------------------------------
-// per-cell formulas (the library is built with -ffp-contract=off; fused
-// multiply-adds are explicit so every variant rounds identically)
-
-__device__ __forceinline__ float fmac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fmac(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-// Staggered first-derivative weights c_1..c_K (Taylor / Fornberg).
-template <int K, typename C> __device__ __forceinline__ C wst(int m) {
-  if constexpr (K == 2) {
-    return m == 0 ? C(9.0 / 8.0) : C(-1.0 / 24.0);
-  } else {
-    return m == 0   ? C(1225.0 / 1024.0)
-           : m == 1 ? C(-245.0 / 3072.0)
-           : m == 2 ? C(49.0 / 5120.0)
-                    : C(-5.0 / 7168.0);
-  }
-}
-
-// stencil accumulator: s + w (hi - lo)
-template <typename C> __device__ __forceinline__ C acc(C s, C w, C hi, C lo) {
-  return fmac(w, hi - lo, s);
-}
-// velocity: a v + b cb (sgn sum + src), sgn = -1 forward, +1 transposed
-template <bool ADJ, typename C>
-__device__ __forceinline__ C upd_v(C a, C b, C cb, C old, C sum, C src) {
-  const C r = ADJ ? (sum + src) : (src - sum);
-  return fmac(a, old, (b * cb) * r);
-}
-// pressure away from the absorbing frame
-template <bool ADJ, typename C>
-__device__ __forceinline__ C upd_p(C ck, C p, C dx, C dz, C src) {
-  const C r = ADJ ? ((dx + dz) + src) : (src - (dx + dz));
-  return fmac(ck, r, p);
-}
-// pressure in the frame; aux: forward p_x, transposed P~_x - P~_z
-template <bool ADJ, typename C>
-__device__ __forceinline__ C upd_p_frame(C ck, C p, C aux, C dx, C dz, C src, C axn, C bxn,
-                                         C azn, C bzn, C* aux_new) {
-  if constexpr (!ADJ) {
-    const C px = fmac(axn, aux, -((bxn * ck) * dx));
-    const C pz = fmac(azn, p - aux, (bzn * ck) * (src - dz));
-    *aux_new = px;
-    return px + pz;
-  } else {
-    const C t = (dx + dz) + src;
-    const C Px = fmac(axn, p + aux, (bxn * ck) * t);
-    const C Pz = fmac(azn, p, (bzn * ck) * t);
-    *aux_new = Px - Pz;
-    return Pz;
-  }
-}
-
-// absorbing-layer factors: x arrays of length pitch (origin GX), then z
-// arrays of length NZ
-template <typename C> struct Pml {
-  const C* p;
-  int P, NZ;
-  __device__ __forceinline__ const C* xa(int k, int J) const { return p + k * P + GX + J; }
-  __device__ __forceinline__ C axn(int J) const { return p[GX + J]; }
-  __device__ __forceinline__ C bxn(int J) const { return p[P + GX + J]; }
-  __device__ __forceinline__ C axh(int J) const { return p[2 * P + GX + J]; }
-  __device__ __forceinline__ C bxh(int J) const { return p[3 * P + GX + J]; }
-  __device__ __forceinline__ C azn(int I) const { return p[4 * P + I]; }
-  __device__ __forceinline__ C bzn(int I) const { return p[4 * P + NZ + I]; }
-  __device__ __forceinline__ C azh(int I) const { return p[4 * P + 2 * NZ + I]; }
-  __device__ __forceinline__ C bzh(int I) const { return p[4 * P + 3 * NZ + I]; }
-};
-
-template <typename C>
-__device__ __forceinline__ C dyn_of(const TraceIO& t, int shot) {
-  return t.dyn ? C(t.dyn[shot]) : C(1);
-}
-
-// injected value at (I, J) from a line (0 off the line)
-template <typename C, typename V>
-__device__ __forceinline__ C line_src(const LineDev& l, const TraceIO& io, int I, int J,
-                                      int shot) {
-  if (io.n < 0 || (I != l.row0 && I != l.row1) || J < l.col0 || J >= l.col0 + l.ntr) return C(0);
-  const C w = (I == l.row0 ? C(l.w0) : C(0)) + (I == l.row1 ? C(l.w1) : C(0));
-  const V* in = static_cast<const V*>(io.in) + shot * io.shot_stride + (long long)io.n * l.ntr +
-                (J - l.col0);
-  return w * (C(io.scale) * C(*in) / dyn_of<C>(io, shot));
-}
-
-template <typename C, typename V>
-__device__ __forceinline__ void line_out(const LineDev& l, const TraceIO& io, int J, int shot,
-                                         C val) {
-  V* out = static_cast<V*>(io.out) + shot * io.shot_stride + (long long)io.n * l.ntr + (J - l.col0);
-  *out = V(C(io.scale) * val * dyn_of<C>(io, shot));
-}
 
 constexpr int TBX = 64;  // split kernels: one wavefront across x
 constexpr int TBY = 4;
@@ -244,15 +152,6 @@ __global__ __launch_bounds__(TBX* TBY) void k_pres(Fields f, GridDims g, Coef cf
 // re-reads inside one L2.
 constexpr int TX = 64;
 constexpr int HXS = 8;  // staged x halo (>= 2K - 1, multiple of 4)
-
-// element i of an array, addressed as a 32-bit byte offset from a base that
-// is uniform over the workgroup (one scalar base + one vector offset)
-template <typename T> __device__ __forceinline__ const T* at(const T* b, unsigned i) {
-  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(b) + i * (unsigned)sizeof(T));
-}
-template <typename T> __device__ __forceinline__ T* at(T* b, unsigned i) {
-  return reinterpret_cast<T*>(reinterpret_cast<char*>(b) + i * (unsigned)sizeof(T));
-}
 
 // no row of the line is active in rows [lo, hi)
 __device__ __forceinline__ bool line_clear(const LineDev& l, const TraceIO& io, int lo, int hi) {
@@ -740,25 +639,6 @@ __global__ __launch_bounds__(256) void k_step(StepArgs a) {
 // tile grown by (1 - t) R, so level 1 produces p^{n+2}, v^{n+3/2} on the
 // tile exactly as two single steps would (same expressions, same order).
 // Trace samples and injections of level t use time index n + dir t.
-
-template <typename C, typename V>
-__device__ __forceinline__ C line_src_at(const LineDev& l, const TraceIO& io, int idx, int nt,
-                                         int I, int J, int shot) {
-  if (!io.in || idx < 0 || idx >= nt || (I != l.row0 && I != l.row1) || J < l.col0 ||
-      J >= l.col0 + l.ntr)
-    return C(0);
-  const C w = (I == l.row0 ? C(l.w0) : C(0)) + (I == l.row1 ? C(l.w1) : C(0));
-  const V* in = static_cast<const V*>(io.in) + shot * io.shot_stride + (long long)idx * l.ntr +
-                (J - l.col0);
-  return w * (C(io.scale) * C(*in) / dyn_of<C>(io, shot));
-}
-
-template <typename C, typename V>
-__device__ __forceinline__ void line_out_at(const LineDev& l, const TraceIO& io, int idx, int J,
-                                            int shot, C val) {
-  V* out = static_cast<V*>(io.out) + shot * io.shot_stride + (long long)idx * l.ntr + (J - l.col0);
-  *out = V(C(io.scale) * val * dyn_of<C>(io, shot));
-}
 
 constexpr int r4(int v) { return (v + 3) / 4 * 4; }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }

@@ -80,10 +80,24 @@ def test_fused_equals_split_bitwise(fd, order, nt, geom):
         two = run_all(ctx, prob, fd)
         for i, (a, b) in enumerate(zip(split, two)):
             assert np.array_equal(a, b), (fd, order, "two steps per launch", i)
+        ctx.set_option(ssx.OPT_STEPS_PER_LAUNCH, 1)
     else:
         # two steps per launch are switched off for FP64 and 16-bit fields
         with pytest.raises(ssx.SSXError):
             ctx.set_option(ssx.OPT_STEPS_PER_LAUNCH, 2)
+    if fd != "f64":
+        # slab strips held in LDS over 4 or 8 steps (the odd record leaves a
+        # one-step remainder)
+        for spl, strip in ((4, 64), (4, 128), (8, 128)):
+            ctx.set_option(ssx.OPT_STEPS_PER_LAUNCH_SLAB, spl)
+            ctx.set_option(ssx.OPT_SLAB_STRIP, strip)
+            multi = run_all(ctx, prob, fd)
+            for i, (a, b) in enumerate(zip(split, multi)):
+                assert np.array_equal(a, b), (fd, order, "slab", spl, strip, i)
+        ctx.set_option(ssx.OPT_STEPS_PER_LAUNCH_SLAB, 1)
+    else:
+        with pytest.raises(ssx.SSXError):
+            ctx.set_option(ssx.OPT_STEPS_PER_LAUNCH_SLAB, 4)
     ctx.close()
 
 
@@ -160,12 +174,18 @@ def test_autotune_choice_applies_and_keeps_results():
     kap = kappa(prob)
     choice = autotune.choose(prob, kap, RHO, field_dtype="f32", cache_path=None, nt_tune=20)
     for key in ("step_kernel", "steps_per_launch", "tile_z", "shot_group",
-                "steps_per_launch_slab", "tile_z_slab", "shot_group_slab"):
+                "steps_per_launch_slab", "tile_z_slab", "slab_strip", "shot_group_slab"):
         assert key in choice, key
     assert 1 <= choice["shot_group"] <= 3
     ctx = ssx.Context(prob, kap, RHO, field_dtype="f32")
     ref = run_all(ctx, prob, "f32")
     autotune.apply(ctx, choice)
+    tz, spl, grp = ctx.launch_shape()
+    if choice["step_kernel"] == 1:
+        assert (tz, spl) == ((8 if choice["steps_per_launch"] == 2 else choice["tile_z"]),
+                             choice["steps_per_launch"])
+    assert grp == choice["shot_group"]
+    assert ctx.cells_per_launch() == (prob.nz + 20) * (prob.nx + 20) * grp
     for a, b in zip(ref, run_all(ctx, prob, "f32")):
         assert np.array_equal(a, b)
     ctx.close()
