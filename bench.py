@@ -27,6 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# sources of the full-grid step kernel (their hash keys the counter profile)
+KERNEL_SOURCES = ("ssx_step.hip", "ssx_cell.h", "ssx_device.h", "ssx_internal.h")
 
 
 def parse():
@@ -41,8 +43,17 @@ def parse():
     ap.add_argument("--max-nt", type=int, default=1500, help="c5: record length cap")
     ap.add_argument("--slots", type=int, default=4, help="c5: concurrent requests")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=12,
-                    help="time steps of the oracle's bounded CPU sample")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target length of the oracle's bounded CPU sample")
+    ap.add_argument("--shots", type=int, default=0,
+                    help="override the number of shots (spread across the surface as in "
+                         "the batched configuration)")
+    ap.add_argument("--dtype", default="", choices=["", "f64", "f32", "f16", "bf16"],
+                    help="override the wavefield storage type")
+    ap.add_argument("--tile-z", type=int, default=-1,
+                    help="force the full-grid tile height after tuning (profiling runs)")
+    ap.add_argument("--shot-group", type=int, default=-1,
+                    help="force the full-grid shots per launch after tuning (profiling runs)")
     ap.add_argument("--graphs", type=int, default=1)
     ap.add_argument("--prop-only", type=int, default=0,
                     help="run this many forward+adjoint propagation pairs and exit "
@@ -89,8 +100,13 @@ def main():
     wl = inputs.workload(cnum)
     if args.nt:
         wl.prob = wl.prob.replace(nt=args.nt)
+    if args.shots:
+        width = (wl.prob.nx - 1) * wl.prob.h
+        wl.prob = wl.prob.replace(xs=inputs.shot_positions(args.shots, width))
     prob = wl.prob
     fd = {"c1": "f64", "c2": "f32", "c3": "f32", "c4": "f16", "c4bf": "bf16"}[args.config]
+    if args.dtype:
+        fd = args.dtype
     vdt = torch.float64 if fd == "f64" else torch.float32
 
     ctx = ssx.Context(prob, wl.kappa, wl.rho, field_dtype=fd)
@@ -99,6 +115,10 @@ def main():
         from paper_2203_16573_amd import autotune
         tuned = autotune.choose(prob, wl.kappa, wl.rho, field_dtype=fd)
         autotune.apply(ctx, tuned)
+    if args.tile_z >= 0:
+        ctx.set_option(ssx.OPT_TILE_Z, args.tile_z)
+    if args.shot_group >= 0:
+        ctx.set_option(ssx.OPT_SHOT_GROUP, args.shot_group)
     ctx.set_graphs(bool(args.graphs))
     wav = inputs.source_wavelet(prob, wl.freq)
     htrue = np.stack([inputs.spike_gather(prob, wav, s) for s in range(prob.nshots)])
@@ -159,9 +179,14 @@ def main():
     # write p, v_x, v_z once
     b_alg = 6 * fsz + csz
     achieved = b_alg * NZ * NX * prob.nshots / (step_ms * 1e-3) / 1e9
+    tz_used = ctx.tile_z()
+    traffic = measured_traffic(args.config, fd, prob.nshots, tz_used, group,
+                               ctx.step_kernel_name())
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": ctx.step_kernel_name(),
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else traffic["bytes_per_launch"],
+                "traffic_detail": traffic,
+                "kernel": ctx.step_kernel_name(), "tile_z": tz_used,
                 "us_per_launch": round(step_ms * 1e3 / launches, 3),
                 "launches_per_step": launches, "bytes_per_cell": b_alg,
                 "cells_per_launch": cells}
@@ -175,12 +200,19 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        ns_cpu = min(args.cpu_steps, prob.nt)
-        m = oracle.Model(prob.replace(nt=ns_cpu), wl.kappa, wl.rho)
-        hs = np.random.default_rng(0).standard_normal((ns_cpu, prob.ns))
-        t = time.perf_counter()
-        m.fwd(hs)
-        tc = time.perf_counter() - t
+
+        def oracle_fwd_seconds(steps):
+            m = oracle.Model(prob.replace(nt=steps, xs=prob.xs[:1]), wl.kappa, wl.rho)
+            hs = np.random.default_rng(0).standard_normal((steps, prob.ns))
+            t = time.perf_counter()
+            m.fwd(hs)
+            return time.perf_counter() - t
+
+        # size the sample from a 4-step probe so that it takes about
+        # --cpu-seconds of one core
+        probe = oracle_fwd_seconds(4)
+        ns_cpu = int(max(4, min(prob.nt, round(4 * args.cpu_seconds / max(probe, 1e-6)))))
+        tc = oracle_fwd_seconds(ns_cpu)
         cpu_gcell = ns_cpu * NZ * NX / tc / 1e9
         cpu = {"value": cpu_gcell * 1e9 / cu_solve, "unit": "solves/s", "cores": 1,
                "kind": "oracle",
@@ -218,6 +250,37 @@ def main():
     }
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def measured_traffic(config, fd, nshots, tile_z, group, kernel):
+    """HBM bytes per launch of the full-grid step kernel from the committed
+    counter profile, when it was taken on the current kernel source with the
+    same workload and launch shape; None otherwise."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "k_step_hbm_traffic.md")
+    csrc = os.path.join(ROOT, "paper_2203_16573_amd", "csrc")
+    h = hashlib.sha256()
+    try:
+        text = open(path).read()
+        for name in KERNEL_SOURCES:
+            h.update(open(os.path.join(csrc, name), "rb").read())
+    except OSError:
+        return None
+    digest = h.hexdigest()
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    if not m:
+        return None
+    table = json.loads(m.group(1))
+    if table.get("kernel_source_sha256") != digest or kernel != "k_step":
+        return None
+    e = table["launches"].get(f"{config}|{fd}|shots{nshots}|tz{tile_z}|group{group}")
+    if e is None:
+        return None
+    fetch = e["fetch_kib"] * 1024 * table["fetch_scale"]
+    write = e["write_kib"] * 1024 * table["write_scale"]
+    return {"bytes_per_launch": round(fetch + write), "fetch_bytes": round(fetch),
+            "write_bytes": round(write), "source": "profiles/k_step_hbm_traffic.md"}
 
 
 def serve_bench(args):

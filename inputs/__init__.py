@@ -165,8 +165,12 @@ def homogeneous_kappa(nz: int, nx: int, c: float = 2000.0,
 # ----------------------------------------------------------------------------
 # workloads (the five benchmark configurations)
 
-def _shot_positions(nshots: int, width: float) -> tuple:
+def shot_positions(nshots: int, width: float) -> tuple:
+    """nshots source positions evenly spread over [0, width] (cell centres)."""
     return tuple((k + 0.5) * width / nshots for k in range(nshots))
+
+
+_shot_positions = shot_positions
 
 
 def workload(c: int, **over) -> Workload:
