@@ -93,25 +93,10 @@ def test_shot_groups_bitwise(fd):
 
 
 def test_c3_full_size_truncated_parity():
-    # 64 shots on the 401 x 801 layered model in one launch per step
-    # (nt = 2000): first / last N samples of two shots against the oracle
-    import oracle
-    wl = inputs.workload(3)
-    prob = wl.prob
-    N = 30
+    # 64 shots on the 401 x 801 layered model (nt = 2000) in bench's launch
+    # configuration (autotuned shot groups, tiles, slab kernel): first / last
+    # N samples of F, F^T, X, X^T for two shots in different groups against
+    # the oracle
+    from test_gpu_parity import truncated_parity
     print("case c3 truncated parity", flush=True)
-    rng = np.random.default_rng(9)
-    h = np.zeros((prob.nshots, prob.nt, prob.ns), dtype=np.float32)
-    h[:, :N] = rng.standard_normal((prob.nshots, N, prob.ns))
-    r = np.zeros((prob.nshots, prob.nt, prob.nr), dtype=np.float32)
-    r[:, -N:] = rng.standard_normal((prob.nshots, N, prob.nr))
-    ctx = ssx.Context(prob, wl.kappa, wl.rho, field_dtype="f32")
-    d = ctx.fwd(torch.tensor(h, device="cuda"), ctx.empty_r()).cpu().numpy()
-    g = ctx.adj(torch.tensor(r, device="cuda"), ctx.empty_s()).cpu().numpy()
-    ctx.close()
-    m = oracle.Model(prob.replace(nt=N), wl.kappa, wl.rho)
-    for s in (0, 63):
-        dr = m.fwd(h[s, :N].astype(np.float64))
-        gr = m.adj(r[s, -N:].astype(np.float64))
-        assert np.linalg.norm(d[s, :N] - dr) / np.linalg.norm(dr) < 1e-5
-        assert np.linalg.norm(g[s, -N:] - gr) / np.linalg.norm(gr) < 1e-5
+    truncated_parity(inputs.workload(3), "f32", 30, (0, 63), 1e-5, 9)

@@ -198,27 +198,88 @@ def test_pcg_parity_c1_fp64(c1_reference):
     ctx.close()
 
 
-def test_c2_full_size_truncated_parity():
-    # 801 x 1601 at 5 m, 2-8, FP32, the benchmark's launch configuration
-    # (nt = 4000): F is causal and time-invariant, so the first N output
-    # samples equal an N-step oracle run on the first N inputs; F^T likewise
-    # for the last N samples.
-    wl = inputs.workload(2)
-    prob = wl.prob
-    N = 40
-    print("case c2 truncated parity", flush=True)
-    rng = np.random.default_rng(7)
-    h = np.zeros((1, prob.nt, prob.ns))
-    h[0, :N] = rng.standard_normal((N, prob.ns))
-    r = np.zeros((1, prob.nt, prob.nr))
-    r[0, -N:] = rng.standard_normal((N, prob.nr))
-    ctx = ssx.Context(prob, wl.kappa, wl.rho, field_dtype="f32")
-    d = host(ctx.fwd(dev(h, "f32"), ctx.empty_r()))
-    g = host(ctx.adj(dev(r, "f32"), ctx.empty_s()))
+@pytest.mark.parametrize("fd", ["f64", "f32"])
+@pytest.mark.parametrize("order", [4, 8])
+def test_parity_with_interior_tiles(fd, order):
+    # a grid with interior tiles (no per-cell tests) beside frame and line
+    # tiles, lines deep inside and part width: F, F^T, X, X^T
+    prob = small_problem(order, 1, nz=100, nx=300, nt=150, z_src=603.0, x_src0=450.0,
+                         ns=150, z_rec=455.0, x_rec0=1000.0, nr=170, xs=(1700.0,))
+    print(f"case interior parity order={order} dtype={fd}", flush=True)
+    kap = small_kappa(prob, seed=2)
+    m = oracle.Model(prob, kap, RHO)
+    ctx = ssx.Context(prob, kap, RHO, field_dtype=fd)
+    rng = np.random.default_rng(11)
+    h = rng.standard_normal((1, prob.nt, prob.ns))
+    r = rng.standard_normal((1, prob.nt, prob.nr))
+    d = host(ctx.fwd(dev(h, fd), ctx.empty_r()))
+    g = host(ctx.adj(dev(r, fd), ctx.empty_s()))
+    P, V = ctx.slab_fwd(dev(h, fd), ctx.empty_s(), ctx.empty_s())
+    f = host(ctx.slab_adj(dev(h, fd), dev(r[:, :, :prob.ns], fd), ctx.empty_s()))
+    Pr, Vr = m.slab_fwd(h[0])
+    assert rel(d[0], m.fwd(h[0])) < TOL[fd]
+    assert rel(g[0], m.adj(r[0])) < TOL[fd]
+    assert rel(host(P)[0], Pr) < TOL[fd] and rel(host(V)[0], Vr) < TOL[fd]
+    assert rel(f[0], m.slab_adj(h[0], r[0, :, :prob.ns])) < TOL[fd]
     ctx.close()
-    m = oracle.Model(prob.replace(nt=N), wl.kappa, wl.rho)
-    assert rel(d[0, :N], m.fwd(h[0, :N])) < 1e-5
-    assert rel(g[0, -N:], m.adj(r[0, -N:])) < 1e-5
+
+
+def bench_context(wl, fd):
+    """A context in the launch configuration bench.py times (autotuned)."""
+    from paper_2203_16573_amd import autotune
+    ctx = ssx.Context(wl.prob, wl.kappa, wl.rho, field_dtype=fd)
+    choice = autotune.choose(wl.prob, wl.kappa, wl.rho, field_dtype=fd)
+    autotune.apply(ctx, choice)
+    print(f"  launch shape {ctx.launch_shape()} choice "
+          f"{ {k: v for k, v in choice.items() if k != 'us'} }", flush=True)
+    return ctx
+
+
+def truncated_parity(wl, fd, N, shots, tol, seed):
+    # F and the slab X are causal and time-invariant: the first N output
+    # samples equal an N-step oracle run on the first N inputs; F^T and X^T
+    # likewise for the last N samples.
+    prob = wl.prob
+    S = prob.nshots
+    rng = np.random.default_rng(seed)
+    h = np.zeros((S, prob.nt, prob.ns))
+    h[:, :N] = rng.standard_normal((S, N, prob.ns))
+    r = np.zeros((S, prob.nt, prob.nr))
+    r[:, -N:] = rng.standard_normal((S, N, prob.nr))
+    a = np.zeros((S, prob.nt, prob.ns))
+    a[:, -N:] = rng.standard_normal((S, N, prob.ns))
+    b = np.zeros((S, prob.nt, prob.ns))
+    b[:, -N:] = rng.standard_normal((S, N, prob.ns))
+    vf = "f64" if fd == "f64" else "f32"
+    ctx = bench_context(wl, fd)
+    d = host(ctx.fwd(dev(h, vf), ctx.empty_r()))
+    g = host(ctx.adj(dev(r, vf), ctx.empty_s()))
+    P, V = ctx.slab_fwd(dev(h, vf), ctx.empty_s(), ctx.empty_s())
+    P, V = host(P), host(V)
+    f = host(ctx.slab_adj(dev(a, vf), dev(b, vf), ctx.empty_s()))
+    ctx.close()
+    errs = []
+    for s in shots:
+        m = oracle.Model(prob.replace(nt=N, xs=(prob.xs[s],)), wl.kappa, wl.rho)
+        Pr, Vr = m.slab_fwd(h[s, :N])
+        errs += [rel(d[s, :N], m.fwd(h[s, :N])), rel(g[s, -N:], m.adj(r[s, -N:])),
+                 rel(P[s, :N], Pr), rel(V[s, :N], Vr),
+                 rel(f[s, -N:], m.slab_adj(a[s, -N:], b[s, -N:]))]
+    print(f"  relative errors {['%.2e' % e for e in errs]}", flush=True)
+    assert max(errs) < tol, errs
+
+
+def test_c2_full_size_truncated_parity():
+    # 801 x 1601 at 5 m, 2-8, FP32, nt = 4000, bench's launch configuration
+    print("case c2 truncated parity", flush=True)
+    truncated_parity(inputs.workload(2), "f32", 40, (0,), 1e-5, 7)
+
+
+@pytest.mark.parametrize("fd,tol", [("f16", 1e-2), ("bf16", 5e-2)])
+def test_c4_full_size_truncated_parity(fd, tol):
+    # the c2 grid with 16-bit wavefield storage (FP32 arithmetic)
+    print(f"case c4 truncated parity {fd}", flush=True)
+    truncated_parity(inputs.workload(4), fd, 40, (0,), tol, 17)
 
 
 def test_c2_full_size_dot_product():
