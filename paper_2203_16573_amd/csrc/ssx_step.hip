@@ -327,7 +327,7 @@ __device__ __forceinline__ void step_interior(const StepArgs& a, long long base,
 }
 
 template <int K, bool ADJ, typename T, int TZ>
-__global__ __launch_bounds__(256) void k_step(StepArgs a) {
+__global__ __launch_bounds__(256, 6) void k_step(StepArgs a) {
   using C = typename Tr<T>::C;
   using V = typename Tr<T>::V;
   constexpr int R = 2 * K - 1;
@@ -348,6 +348,9 @@ __global__ __launch_bounds__(256) void k_step(StepArgs a) {
   __shared__ __align__(16) C sPX[ADJ ? TZ * WP : 4];
   __shared__ __align__(16) C sVX[TZ * WVX];
   __shared__ __align__(16) C sVZ[HVZ * TX];
+  // layer factors of frame tiles: a_n, b_n over the tile's columns; a_h,
+  // b_h over the v_z rows; a_n, b_n over the tile's rows
+  __shared__ __align__(16) C sF[2 * TX + 2 * HVZ + 2 * TZ];
 
   // XCD-aware tile index
   const int nb = gridDim.x, b = blockIdx.x;
@@ -378,6 +381,11 @@ __global__ __launch_bounds__(256) void k_step(StepArgs a) {
   const C cb = C(a.c.cb);
   const int tid = threadIdx.x;
   const bool frame_tile = (z0 < L) || (z1 > NZ - L) || (x0 < L) || (x1 > NX - L);
+  // tile-uniform tests: columns outside the grid among those computed
+  // (x0-4 .. x1+3), and lines injected in the rows computed
+  const bool edge_x = x0 == 0 || x1 + 4 > NX;
+  const bool vil_here = !line_clear(a.vil, a.vi, z0 - K, z1 + K - 1);
+  const bool pil_here = !line_clear(a.pil, a.pi, z0, z1);
 
   // ---- every global load of the step, before touching LDS ---------------
   C rp[NQP][4];
@@ -422,6 +430,22 @@ __global__ __launch_bounds__(256) void k_step(StepArgs a) {
       ld4(rck[k], ckp + (long long)I * P + J);
       if (frame_tile) ld4(rau[k], auA + (long long)I * P + J);
     }
+  }
+  // layer factors (1 outside the grid; the x arrays are pitch long, the z
+  // arrays NZ long)
+  for (int i = tid; i < 2 * TX + 2 * HVZ + 2 * TZ; i += 256) {
+    C f = C(1);
+    if (i < 2 * TX) {
+      const int J = x0 + (i & (TX - 1));
+      if (frame_tile && J < NX) f = i < TX ? pm.axn(J) : pm.bxn(J);
+    } else if (i < 2 * TX + 2 * HVZ) {
+      const int j = i - 2 * TX, I = z0 - K + (j < HVZ ? j : j - HVZ);
+      if (I >= 0 && I < NZ) f = j < HVZ ? pm.azh(I) : pm.bzh(I);
+    } else {
+      const int j = i - 2 * TX - 2 * HVZ, I = z0 + (j < TZ ? j : j - TZ);
+      if (frame_tile && I < NZ) f = j < TZ ? pm.azn(I) : pm.bzn(I);
+    }
+    sF[i] = f;
   }
   bool use_px = false;
   C rax[ADJ ? NQA : 1][4];
@@ -500,16 +524,16 @@ __global__ __launch_bounds__(256) void k_step(StepArgs a) {
       ld4(*reinterpret_cast<C(*)[4]>(w + 4), row + 4 * g + 4);
       ld4(*reinterpret_cast<C(*)[4]>(w + 8), row + 4 * g + 8);
       C ax[4], bx[4];
-      ld4(ax, pm.xa(2, J));
+      ld4(ax, pm.xa(2, J));  // columns -4 .. NX+66 lie inside the x arrays
       ld4(bx, pm.xa(3, J));
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        if (J + e >= 0 && J + e < NX) {
-          C sx = C(0);
+        C sx = C(0);
 #pragma unroll
-          for (int m = 1; m <= K; ++m) sx = acc(sx, wst<K, C>(m - 1), w[e + 4 + m], w[e + 5 - m]);
-          val[e] = rnd<T>(upd_v<ADJ>(ax[e], bx[e], cb, rvx[k][e], sx, C(0)));
-        }
+        for (int m = 1; m <= K; ++m) sx = acc(sx, wst<K, C>(m - 1), w[e + 4 + m], w[e + 5 - m]);
+        val[e] = rnd<T>(upd_v<ADJ>(ax[e], bx[e], cb, rvx[k][e], sx, C(0)));
+        // columns outside the grid hold zero
+        if (edge_x && (J + e < 0 || J + e >= NX)) val[e] = C(0);
       }
       if (g >= 1 && g <= GT && J < NX) {
         T* dst = vxB + (long long)I * P + J;
@@ -543,13 +567,12 @@ __global__ __launch_bounds__(256) void k_step(StepArgs a) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) sz[e] = acc(sz[e], wst<K, C>(m - 1), hi[e], lo[e]);
       }
-      const C az = pm.azh(I), bz = pm.bzh(I);
+      const C az = sF[2 * TX + rr], bz = sF[2 * TX + HVZ + rr];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        if (J + e < NX) {
-          const C src = line_src<C, V>(a.vil, a.vi, I, J + e, shot);
-          val[e] = rnd<T>(upd_v<ADJ>(az, bz, cb, rvz[k][e], sz[e], src));
-        }
+        const C src = vil_here ? line_src<C, V>(a.vil, a.vi, I, J + e, shot) : C(0);
+        val[e] = rnd<T>(upd_v<ADJ>(az, bz, cb, rvz[k][e], sz[e], src));
+        if (edge_x && J + e >= NX) val[e] = C(0);
       }
       if (I >= z0 && I < z1 && J < NX) {
         T* dst = vzB + (long long)I * P + J;
@@ -607,14 +630,15 @@ __global__ __launch_bounds__(256) void k_step(StepArgs a) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int Je = J + e;
-      const C src = line_src<C, V>(a.pil, a.pi, I, Je, shot);
+      const C src = pil_here ? line_src<C, V>(a.pil, a.pi, I, Je, shot) : C(0);
       const bool frame = frame_tile && (I < L || I >= NZ - L || Je < L || Je >= NX - L);
       if (!frame) {
         pn[e] = upd_p<ADJ>(rck[k][e], pc[e], dx[e], dz[e], src);
       } else {
         C an;
-        pn[e] = upd_p_frame<ADJ>(rck[k][e], pc[e], rau[k][e], dx[e], dz[e], src, pm.axn(Je),
-                                 pm.bxn(Je), pm.azn(I), pm.bzn(I), &an);
+        pn[e] = upd_p_frame<ADJ>(rck[k][e], pc[e], rau[k][e], dx[e], dz[e], src,
+                                 sF[4 * g + e], sF[TX + 4 * g + e],
+                                 sF[2 * TX + 2 * HVZ + rr], sF[2 * TX + 2 * HVZ + TZ + rr], &an);
         if (Je < NX) stc(auB + o + e, an);
       }
     }
