@@ -16,7 +16,7 @@ namespace ssx {
 // (also keeps row starts 256-byte aligned for FP32) and GZ rows.  The row
 // pitch is at least NX + 2 GX + 8, a multiple of 64.
 constexpr int GX = 64;
-constexpr int GZ = 4;
+constexpr int GZ = 8;
 
 enum class Dt : int { F64 = 0, F32 = 1, F16 = 2, BF16 = 3 };
 

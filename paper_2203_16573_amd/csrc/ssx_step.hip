@@ -153,6 +153,10 @@ __global__ __launch_bounds__(TBX* TBY) void k_pres(Fields f, GridDims g, Coef cf
 constexpr int TX = 64;
 constexpr int HXS = 8;  // staged x halo (>= 2K - 1, multiple of 4)
 
+// threads of a fused-step workgroup: 256 for 64 x 8 and 64 x 16 tiles, 512
+// for 64 x 32 (each thread owns the same 1 x 4 cells at every height)
+constexpr int step_threads(int tz) { return tz == 32 ? 512 : 256; }
+
 // no row of the line is active in rows [lo, hi)
 __device__ __forceinline__ bool line_clear(const LineDev& l, const TraceIO& io, int lo, int hi) {
   return io.n < 0 || ((l.row0 < lo || l.row0 >= hi) && (l.row1 < lo || l.row1 >= hi));
@@ -181,6 +185,7 @@ template <int K, bool ADJ, typename T, int TZ, typename C>
 __device__ __forceinline__ void step_interior(const StepArgs& a, long long base, int x0, int z0,
                                               C* __restrict__ sP, C* __restrict__ sVX,
                                               C* __restrict__ sVZ) {
+  constexpr int NT = step_threads(TZ);
   constexpr int R = 2 * K - 1;
   constexpr int WP = TX + 2 * HXS;
   constexpr int GP = WP / 4;
@@ -189,10 +194,10 @@ __device__ __forceinline__ void step_interior(const StepArgs& a, long long base,
   constexpr int WVX = 4 * GVX;
   constexpr int HVZ = TZ + 2 * K - 1;
   constexpr int GT = TX / 4;
-  constexpr int NQP = (HP * GP + 255) / 256;
-  constexpr int NQX = (TZ * GVX + 255) / 256;
-  constexpr int NQZ = (HVZ * GT + 255) / 256;
-  constexpr int NQT = (TZ * GT + 255) / 256;
+  constexpr int NQP = (HP * GP + NT - 1) / NT;
+  constexpr int NQX = (TZ * GVX + NT - 1) / NT;
+  constexpr int NQZ = (HVZ * GT + NT - 1) / NT;
+  constexpr int NQT = (TZ * GT + NT - 1) / NT;
   const int P = a.g.pitch;
   const int tid = threadIdx.x;
   const long long o0 = base + (long long)z0 * P + x0;  // element (z0, x0) of this shot
@@ -210,8 +215,8 @@ __device__ __forceinline__ void step_interior(const StepArgs& a, long long base,
   C rp[NQP][4];
 #pragma unroll
   for (int k = 0; k < NQP; ++k) {
-    const int q = tid + 256 * k;
-    if (256 * k + 255 < HP * GP || q < HP * GP) {
+    const int q = tid + NT * k;
+    if (NT * k + NT - 1 < HP * GP || q < HP * GP) {
       const int rr = q / GP, g = q - rr * GP;
       ld4(rp[k], at(pA, rr * P + 4 * g));
     }
@@ -219,8 +224,8 @@ __device__ __forceinline__ void step_interior(const StepArgs& a, long long base,
   C rvx[NQX][4];
 #pragma unroll
   for (int k = 0; k < NQX; ++k) {
-    const int q = tid + 256 * k;
-    if (256 * k + 255 < TZ * GVX || q < TZ * GVX) {
+    const int q = tid + NT * k;
+    if (NT * k + NT - 1 < TZ * GVX || q < TZ * GVX) {
       const int rr = q / GVX, g = q - rr * GVX;
       ld4(rvx[k], at(vxA, rr * P + 4 * g));
     }
@@ -228,29 +233,29 @@ __device__ __forceinline__ void step_interior(const StepArgs& a, long long base,
   C rvz[NQZ][4];
 #pragma unroll
   for (int k = 0; k < NQZ; ++k) {
-    const int q = tid + 256 * k;
-    if (256 * k + 255 < HVZ * GT || q < HVZ * GT) ld4(rvz[k], at(vzA, (q >> 4) * P + 4 * (q & 15)));
+    const int q = tid + NT * k;
+    if (NT * k + NT - 1 < HVZ * GT || q < HVZ * GT) ld4(rvz[k], at(vzA, (q >> 4) * P + 4 * (q & 15)));
   }
   C rck[NQT][4];
 #pragma unroll
   for (int k = 0; k < NQT; ++k) {
-    const int q = tid + 256 * k;
-    if (256 * k + 255 < TZ * GT || q < TZ * GT) ld4(rck[k], at(ckA, (q >> 4) * P + 4 * (q & 15)));
+    const int q = tid + NT * k;
+    if (NT * k + NT - 1 < TZ * GT || q < TZ * GT) ld4(rck[k], at(ckA, (q >> 4) * P + 4 * (q & 15)));
   }
 
   // ---- stage p^n -------------------------------------------------------------
 #pragma unroll
   for (int k = 0; k < NQP; ++k) {
-    const int q = tid + 256 * k;
-    if (256 * k + 255 < HP * GP || q < HP * GP) st4(sP + 4 * q, rp[k]);
+    const int q = tid + NT * k;
+    if (NT * k + NT - 1 < HP * GP || q < HP * GP) st4(sP + 4 * q, rp[k]);
   }
   __syncthreads();
 
   // ---- v_x on the tile rows, columns x0-4 .. x1+3 ------------------------------
 #pragma unroll
   for (int k = 0; k < NQX; ++k) {
-    const int q = tid + 256 * k;
-    if (256 * k + 255 < TZ * GVX || q < TZ * GVX) {
+    const int q = tid + NT * k;
+    if (NT * k + NT - 1 < TZ * GVX || q < TZ * GVX) {
       const int rr = q / GVX, g = q - rr * GVX;
       const C* row = sP + (rr + R) * WP + 4 * g;
       C w[12];
@@ -272,8 +277,8 @@ __device__ __forceinline__ void step_interior(const StepArgs& a, long long base,
   // ---- v_z on the tile columns, rows z0-K .. z1+K-2 ----------------------------
 #pragma unroll
   for (int k = 0; k < NQZ; ++k) {
-    const int q = tid + 256 * k;
-    if (256 * k + 255 < HVZ * GT || q < HVZ * GT) {
+    const int q = tid + NT * k;
+    if (NT * k + NT - 1 < HVZ * GT || q < HVZ * GT) {
       const int rr = q >> 4, g = q & 15;
       const C* col = sP + (rr - K + R) * WP + 4 * g + HXS;
       C sz[4] = {zero, zero, zero, zero};
@@ -297,8 +302,8 @@ __device__ __forceinline__ void step_interior(const StepArgs& a, long long base,
   // ---- p^{n+1} on the tile -------------------------------------------------------
 #pragma unroll
   for (int k = 0; k < NQT; ++k) {
-    const int q = tid + 256 * k;
-    if (256 * k + 255 < TZ * GT || q < TZ * GT) {
+    const int q = tid + NT * k;
+    if (NT * k + NT - 1 < TZ * GT || q < TZ * GT) {
       const int rr = q >> 4, g = q & 15;
       C w[12];
       const C* vrow = sVX + rr * WVX + 4 * g;
@@ -327,9 +332,10 @@ __device__ __forceinline__ void step_interior(const StepArgs& a, long long base,
 }
 
 template <int K, bool ADJ, typename T, int TZ>
-__global__ __launch_bounds__(256, 6) void k_step(StepArgs a) {
+__global__ __launch_bounds__(step_threads(TZ), 6) void k_step(StepArgs a) {
   using C = typename Tr<T>::C;
   using V = typename Tr<T>::V;
+  constexpr int NT = step_threads(TZ);
   constexpr int R = 2 * K - 1;
   constexpr int WP = TX + 2 * HXS;     // staged p columns: x0-8 .. x1+7
   constexpr int GP = WP / 4;
@@ -338,19 +344,27 @@ __global__ __launch_bounds__(256, 6) void k_step(StepArgs a) {
   constexpr int WVX = 4 * GVX;
   constexpr int HVZ = TZ + 2 * K - 1;  // v_z rows: z0-K .. z1+K-2
   constexpr int GT = TX / 4;           // groups per tile row
-  constexpr int NQP = (HP * GP + 255) / 256;
-  constexpr int NQX = (TZ * GVX + 255) / 256;
-  constexpr int NQZ = (HVZ * GT + 255) / 256;
-  constexpr int NQT = (TZ * GT + 255) / 256;
-  constexpr int NQA = (TZ * GP + 255) / 256;
+  constexpr int NQP = (HP * GP + NT - 1) / NT;
+  constexpr int NQX = (TZ * GVX + NT - 1) / NT;
+  constexpr int NQZ = (HVZ * GT + NT - 1) / NT;
+  constexpr int NQT = (TZ * GT + NT - 1) / NT;
+  constexpr int NQA = (TZ * GP + NT - 1) / NT;
   static_assert(2 * K - 1 <= HXS && K <= 4, "halo wider than the staged columns");
   __shared__ __align__(16) C sP[HP * WP];
   __shared__ __align__(16) C sPX[ADJ ? TZ * WP : 4];
   __shared__ __align__(16) C sVX[TZ * WVX];
   __shared__ __align__(16) C sVZ[HVZ * TX];
-  // layer factors of frame tiles: a_n, b_n over the tile's columns; a_h,
-  // b_h over the v_z rows; a_n, b_n over the tile's rows
-  __shared__ __align__(16) C sF[2 * TX + 2 * HVZ + 2 * TZ];
+  // general tiles: layer factors and line injections, staged with the
+  // loads so that no global access waits inside the compute phases
+  //   sF: a_h, b_h over the v_x columns x0-4 .. x1+3; a_n, b_n over the
+  //       tile's columns; a_h, b_h over the v_z rows; a_n, b_n over the
+  //       tile's rows
+  //   sL: injected values of the v_z line (rows row0, row1) and of the
+  //       pressure line (rows row0, row1) over the tile's columns
+  constexpr int FXH = 0, FXN = 2 * WVX, FZH = FXN + 2 * TX, FZN = FZH + 2 * HVZ;
+  constexpr int NF = FZN + 2 * TZ;
+  __shared__ __align__(16) C sF[NF];
+  __shared__ __align__(16) C sL[4 * TX];
 
   // XCD-aware tile index
   const int nb = gridDim.x, b = blockIdx.x;
@@ -368,113 +382,133 @@ __global__ __launch_bounds__(256, 6) void k_step(StepArgs a) {
     step_interior<K, ADJ, T, TZ, C>(a, base, x0, z0, sP, sVX, sVZ);
     return;
   }
-  const T* __restrict__ pA = static_cast<const T*>(a.in.p) + base;
-  const T* __restrict__ vxA = static_cast<const T*>(a.in.vx) + base;
-  const T* __restrict__ vzA = static_cast<const T*>(a.in.vz) + base;
-  const T* __restrict__ auA = static_cast<const T*>(a.in.aux) + base;
-  T* __restrict__ pB = static_cast<T*>(a.out.p) + base;
-  T* __restrict__ vxB = static_cast<T*>(a.out.vx) + base;
-  T* __restrict__ vzB = static_cast<T*>(a.out.vz) + base;
-  T* __restrict__ auB = static_cast<T*>(a.out.aux) + base;
-  const C* __restrict__ ckp = static_cast<const C*>(a.c.ck) + a.g.origin;
-  const Pml<C> pm{static_cast<const C*>(a.c.pml), P, NZ};
+  // ---- general tiles: absorbing frame, lines, grid edges -----------------
+  // Same expressions as the interior path, with the layer factors, the
+  // frame split and the line terms, and with tile-uniform tests selecting
+  // the per-cell work: columns or rows outside the grid hold zero, nothing
+  // outside the grid is stored.  Ghost rows (GZ >= R) and columns (GX >= 8)
+  // make every staged access of a tile above the last tile row land in
+  // zeroed padding, so only that row predicates its loads.
   const C cb = C(a.c.cb);
   const int tid = threadIdx.x;
+  const Pml<C> pm{static_cast<const C*>(a.c.pml), P, NZ};
   const bool frame_tile = (z0 < L) || (z1 > NZ - L) || (x0 < L) || (x1 > NX - L);
-  // tile-uniform tests: columns outside the grid among those computed
-  // (x0-4 .. x1+3), and lines injected in the rows computed
-  const bool edge_x = x0 == 0 || x1 + 4 > NX;
+  const bool edge_x = x0 == 0 || x1 + 4 > NX;   // computed columns outside the grid
+  const bool edge_z = z0 - K < 0 || z1 + K - 1 > NZ;  // computed rows outside the grid
+  const bool rows_ok = z0 - R >= -GZ && z1 + R <= NZ + GZ;  // no load needs a row test
   const bool vil_here = !line_clear(a.vil, a.vi, z0 - K, z1 + K - 1);
   const bool pil_here = !line_clear(a.pil, a.pi, z0, z1);
+  // the transposed x-stencil reads P~_x = P~_z + aux where the frame is near
+  const bool use_px = ADJ && ((z0 < L) || (z1 > NZ - L) || (x0 - HXS < L) || (x1 + HXS > NX - L));
+  static_assert(GZ >= R && GX >= HXS, "ghost padding narrower than the staged halo");
 
-  // ---- every global load of the step, before touching LDS ---------------
+  const long long o0 = base + (long long)z0 * P + x0;  // element (z0, x0) of this shot
+  const T* pA = static_cast<const T*>(a.in.p) + (o0 - (long long)R * P - HXS);
+  const T* vxA = static_cast<const T*>(a.in.vx) + (o0 - 4);
+  const T* vzA = static_cast<const T*>(a.in.vz) + (o0 - (long long)K * P);
+  const T* auA = static_cast<const T*>(a.in.aux) + o0;
+  const T* axA = static_cast<const T*>(a.in.aux) + (o0 - HXS);
+  const C* ckA = static_cast<const C*>(a.c.ck) + (a.g.origin + (long long)z0 * P + x0);
+  T* pB = static_cast<T*>(a.out.p) + o0;
+  T* vxB = static_cast<T*>(a.out.vx) + (o0 - 4);
+  T* vzB = static_cast<T*>(a.out.vz) + (o0 - (long long)K * P);
+  T* auB = static_cast<T*>(a.out.aux) + o0;
+  auto row_in = [&](int I) { return rows_ok || (I >= 0 && I < NZ); };
+
+  // ---- loads ---------------------------------------------------------------
   C rp[NQP][4];
 #pragma unroll
   for (int k = 0; k < NQP; ++k) {
-    const int q = tid + 256 * k;
-    const int rr = q / GP, g = q - rr * GP;
-    const int I = z0 - R + rr, J = x0 - HXS + 4 * g;
+    const int q = tid + NT * k;
 #pragma unroll
     for (int e = 0; e < 4; ++e) rp[k][e] = C(0);
-    if (q < HP * GP && I >= 0 && I < NZ && J < NX) ld4(rp[k], pA + (long long)I * P + J);
+    if (NT * k + NT - 1 < HP * GP || q < HP * GP) {
+      const int rr = q / GP, g = q - rr * GP;
+      if (row_in(z0 - R + rr)) ld4(rp[k], at(pA, rr * P + 4 * g));
+    }
   }
   C rvx[NQX][4];
 #pragma unroll
   for (int k = 0; k < NQX; ++k) {
-    const int q = tid + 256 * k;
-    const int rr = q / GVX, g = q - rr * GVX;
-    const int I = z0 + rr, J = x0 - 4 + 4 * g;
+    const int q = tid + NT * k;
 #pragma unroll
     for (int e = 0; e < 4; ++e) rvx[k][e] = C(0);
-    if (q < TZ * GVX && I < NZ && J < NX) ld4(rvx[k], vxA + (long long)I * P + J);
+    if (NT * k + NT - 1 < TZ * GVX || q < TZ * GVX) {
+      const int rr = q / GVX, g = q - rr * GVX;
+      if (row_in(z0 + rr)) ld4(rvx[k], at(vxA, rr * P + 4 * g));
+    }
   }
   C rvz[NQZ][4];
 #pragma unroll
   for (int k = 0; k < NQZ; ++k) {
-    const int q = tid + 256 * k;
-    const int rr = q >> 4, g = q & 15;
-    const int I = z0 - K + rr, J = x0 + 4 * g;
+    const int q = tid + NT * k;
 #pragma unroll
     for (int e = 0; e < 4; ++e) rvz[k][e] = C(0);
-    if (q < HVZ * GT && I >= 0 && I < NZ && J < NX) ld4(rvz[k], vzA + (long long)I * P + J);
+    if ((NT * k + NT - 1 < HVZ * GT || q < HVZ * GT) && row_in(z0 - K + (q >> 4)))
+      ld4(rvz[k], at(vzA, (q >> 4) * P + 4 * (q & 15)));
   }
   C rck[NQT][4], rau[NQT][4];
 #pragma unroll
   for (int k = 0; k < NQT; ++k) {
-    const int q = tid + 256 * k;
-    const int rr = q >> 4, g = q & 15;
-    const int I = z0 + rr, J = x0 + 4 * g;
+    const int q = tid + NT * k;
 #pragma unroll
     for (int e = 0; e < 4; ++e) rck[k][e] = rau[k][e] = C(0);
-    if (q < TZ * GT && I < NZ && J < NX) {
-      ld4(rck[k], ckp + (long long)I * P + J);
-      if (frame_tile) ld4(rau[k], auA + (long long)I * P + J);
+    if ((NT * k + NT - 1 < TZ * GT || q < TZ * GT) && row_in(z0 + (q >> 4))) {
+      const unsigned off = (q >> 4) * P + 4 * (q & 15);
+      ld4(rck[k], at(ckA, off));
+      if (frame_tile) ld4(rau[k], at(auA, off));
     }
   }
-  // layer factors (1 outside the grid; the x arrays are pitch long, the z
-  // arrays NZ long)
-  for (int i = tid; i < 2 * TX + 2 * HVZ + 2 * TZ; i += 256) {
+  C rax[ADJ ? NQA : 1][4];
+  if constexpr (ADJ) {
+#pragma unroll
+    for (int k = 0; k < NQA; ++k) {
+      const int q = tid + NT * k;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) rax[k][e] = C(0);
+      if (use_px && (NT * k + NT - 1 < TZ * GP || q < TZ * GP)) {
+        const int rr = q / GP, g = q - rr * GP;
+        if (row_in(z0 + rr)) ld4(rax[k], at(axA, rr * P + 4 * g));
+      }
+    }
+  }
+  // layer factors (1 outside the grid) and line injections (0 off the line)
+  for (int i = tid; i < NF; i += NT) {
     C f = C(1);
-    if (i < 2 * TX) {
-      const int J = x0 + (i & (TX - 1));
-      if (frame_tile && J < NX) f = i < TX ? pm.axn(J) : pm.bxn(J);
-    } else if (i < 2 * TX + 2 * HVZ) {
-      const int j = i - 2 * TX, I = z0 - K + (j < HVZ ? j : j - HVZ);
+    if (i < FXN) {
+      const int j = i < WVX ? i : i - WVX, J = x0 - 4 + j;
+      if (J >= 0 && J < NX) f = i < WVX ? pm.axh(J) : pm.bxh(J);
+    } else if (i < FZH) {
+      const int j = i - FXN, J = x0 + (j & (TX - 1));
+      if (frame_tile && J < NX) f = j < TX ? pm.axn(J) : pm.bxn(J);
+    } else if (i < FZN) {
+      const int j = i - FZH, I = z0 - K + (j < HVZ ? j : j - HVZ);
       if (I >= 0 && I < NZ) f = j < HVZ ? pm.azh(I) : pm.bzh(I);
     } else {
-      const int j = i - 2 * TX - 2 * HVZ, I = z0 + (j < TZ ? j : j - TZ);
+      const int j = i - FZN, I = z0 + (j < TZ ? j : j - TZ);
       if (frame_tile && I < NZ) f = j < TZ ? pm.azn(I) : pm.bzn(I);
     }
     sF[i] = f;
   }
-  bool use_px = false;
-  C rax[ADJ ? NQA : 1][4];
-  if constexpr (ADJ) {
-    // the transposed x-stencil reads P~_x = P~_z + aux where the frame is near
-    use_px = (z0 < L) || (z1 > NZ - L) || (x0 - HXS < L) || (x1 + HXS > NX - L);
-#pragma unroll
-    for (int k = 0; k < NQA; ++k) {
-      const int q = tid + 256 * k;
-      const int rr = q / GP, g = q - rr * GP;
-      const int I = z0 + rr, J = x0 - HXS + 4 * g;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) rax[k][e] = C(0);
-      if (use_px && q < TZ * GP && I < NZ && J < NX) ld4(rax[k], auA + (long long)I * P + J);
-    }
+  if ((vil_here || pil_here) && tid < 4 * TX) {
+    const int j = tid >> 6, c = tid & (TX - 1);  // 4 rows of TX values
+    const LineDev& l = j < 2 ? a.vil : a.pil;
+    const TraceIO& io = j < 2 ? a.vi : a.pi;
+    sL[tid] = line_src<C, V>(l, io, (j & 1) ? l.row1 : l.row0, x0 + c, shot);
   }
 
-  // ---- stage p^n (and P~_x) in LDS --------------------------------------
+  // ---- stage p^n (and P~_x) ----------------------------------------------------
 #pragma unroll
   for (int k = 0; k < NQP; ++k) {
-    const int q = tid + 256 * k;
-    if (q < HP * GP) st4(sP + 4 * q, rp[k]);
+    const int q = tid + NT * k;
+    if (NT * k + NT - 1 < HP * GP || q < HP * GP) st4(sP + 4 * q, rp[k]);
   }
   if constexpr (ADJ) {
     if (use_px) {
 #pragma unroll
       for (int k = 0; k < NQA; ++k) {
-        const int q = tid + 256 * k;
-        if (q < TZ * GP) st4(sPX + 4 * q, rax[k]);
+        const int q = tid + NT * k;
+        if (NT * k + NT - 1 < TZ * GP || q < TZ * GP) st4(sPX + 4 * q, rax[k]);
       }
     }
   }
@@ -484,14 +518,14 @@ __global__ __launch_bounds__(256, 6) void k_step(StepArgs a) {
       // P~_x = P~_z + aux (tile row rr of sPX is row rr + R of sP)
 #pragma unroll
       for (int k = 0; k < NQA; ++k) {
-        const int q = tid + 256 * k;
-        if (q < TZ * GP) {
-          C pz[4], ax[4], s[4];
+        const int q = tid + NT * k;
+        if (NT * k + NT - 1 < TZ * GP || q < TZ * GP) {
+          C pz[4], ax[4], sum[4];
           ld4(pz, sP + 4 * q + R * WP);
           ld4(ax, sPX + 4 * q);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) s[e] = pz[e] + ax[e];
-          st4(sPX + 4 * q, s);
+          for (int e = 0; e < 4; ++e) sum[e] = pz[e] + ax[e];
+          st4(sPX + 4 * q, sum);
         }
       }
       __syncthreads();
@@ -509,83 +543,81 @@ __global__ __launch_bounds__(256, 6) void k_step(StepArgs a) {
     }
   }
 
-  // ---- v_x on the tile rows, columns x0-4 .. x1+3 ------------------------
+  // ---- v_x on the tile rows, columns x0-4 .. x1+3 ------------------------------
 #pragma unroll
   for (int k = 0; k < NQX; ++k) {
-    const int q = tid + 256 * k;
-    if (q >= TZ * GVX) continue;
-    const int rr = q / GVX, g = q - rr * GVX;
-    const int I = z0 + rr, J = x0 - 4 + 4 * g;
-    C val[4] = {C(0), C(0), C(0), C(0)};
-    if (I < NZ) {
-      const C* row = (ADJ && use_px) ? (sPX + rr * WP) : (sP + (rr + R) * WP);
-      C w[12];  // staged p at columns J-4 .. J+7
-      ld4(*reinterpret_cast<C(*)[4]>(w), row + 4 * g);
-      ld4(*reinterpret_cast<C(*)[4]>(w + 4), row + 4 * g + 4);
-      ld4(*reinterpret_cast<C(*)[4]>(w + 8), row + 4 * g + 8);
+    const int q = tid + NT * k;
+    if (NT * k + NT - 1 < TZ * GVX || q < TZ * GVX) {
+      const int rr = q / GVX, g = q - rr * GVX;
+      const int I = z0 + rr, J = x0 - 4 + 4 * g;
+      const C* row = (ADJ && use_px) ? (sPX + rr * WP + 4 * g) : (sP + (rr + R) * WP + 4 * g);
+      C w[12];  // staged p (transposed: P~_x) at columns J-4 .. J+7
+      ld4(*reinterpret_cast<C(*)[4]>(w), row);
+      ld4(*reinterpret_cast<C(*)[4]>(w + 4), row + 4);
+      ld4(*reinterpret_cast<C(*)[4]>(w + 8), row + 8);
       C ax[4], bx[4];
-      ld4(ax, pm.xa(2, J));  // columns -4 .. NX+66 lie inside the x arrays
-      ld4(bx, pm.xa(3, J));
+      ld4(ax, sF + FXH + 4 * g);
+      ld4(bx, sF + FXH + WVX + 4 * g);
+      C val[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         C sx = C(0);
 #pragma unroll
         for (int m = 1; m <= K; ++m) sx = acc(sx, wst<K, C>(m - 1), w[e + 4 + m], w[e + 5 - m]);
         val[e] = rnd<T>(upd_v<ADJ>(ax[e], bx[e], cb, rvx[k][e], sx, C(0)));
-        // columns outside the grid hold zero
-        if (edge_x && (J + e < 0 || J + e >= NX)) val[e] = C(0);
+        if (edge_x && (J + e < 0 || J + e >= NX)) val[e] = C(0);  // outside the grid
       }
-      if (g >= 1 && g <= GT && J < NX) {
-        T* dst = vxB + (long long)I * P + J;
-        if (J + 3 < NX) {
-          st4(dst, val);
+      if (g >= 1 && g <= GT && I < NZ) {
+        if (!edge_x || J + 3 < NX) {
+          st4(at(vxB, rr * P + 4 * g), val);
         } else {
 #pragma unroll
           for (int e = 0; e < 4; ++e)
-            if (J + e < NX) stc(dst + e, val[e]);
+            if (J + e < NX) stc(at(vxB, rr * P + 4 * g + e), val[e]);
         }
       }
+      st4(sVX + 4 * q, val);
     }
-    st4(sVX + 4 * q, val);
   }
-  // ---- v_z on the tile columns, rows z0-K .. z1+K-2 ----------------------
+  // ---- v_z on the tile columns, rows z0-K .. z1+K-2 ----------------------------
 #pragma unroll
   for (int k = 0; k < NQZ; ++k) {
-    const int q = tid + 256 * k;
-    if (q >= HVZ * GT) continue;
-    const int rr = q >> 4, g = q & 15;
-    const int I = z0 - K + rr, J = x0 + 4 * g;
-    C val[4] = {C(0), C(0), C(0), C(0)};
-    if (I >= 0 && I < NZ) {
-      const int r0 = rr - K + R;  // staged row of I
+    const int q = tid + NT * k;
+    if (NT * k + NT - 1 < HVZ * GT || q < HVZ * GT) {
+      const int rr = q >> 4, g = q & 15;
+      const int I = z0 - K + rr, J = x0 + 4 * g;
+      const C* col = sP + (rr - K + R) * WP + 4 * g + HXS;
       C sz[4] = {C(0), C(0), C(0), C(0)};
 #pragma unroll
       for (int m = 1; m <= K; ++m) {
         C hi[4], lo[4];
-        ld4(hi, sP + (r0 + m) * WP + 4 * g + HXS);
-        ld4(lo, sP + (r0 + 1 - m) * WP + 4 * g + HXS);
+        ld4(hi, col + m * WP);
+        ld4(lo, col + (1 - m) * WP);
 #pragma unroll
         for (int e = 0; e < 4; ++e) sz[e] = acc(sz[e], wst<K, C>(m - 1), hi[e], lo[e]);
       }
-      const C az = sF[2 * TX + rr], bz = sF[2 * TX + HVZ + rr];
+      const C az = sF[FZH + rr], bz = sF[FZH + HVZ + rr];
+      const bool row_ok = !edge_z || (I >= 0 && I < NZ);
+      const C* lrow = !vil_here ? nullptr
+                      : I == a.vil.row0 ? sL : (I == a.vil.row1 ? sL + TX : nullptr);
+      C val[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const C src = vil_here ? line_src<C, V>(a.vil, a.vi, I, J + e, shot) : C(0);
+        const C src = lrow ? lrow[4 * g + e] : C(0);
         val[e] = rnd<T>(upd_v<ADJ>(az, bz, cb, rvz[k][e], sz[e], src));
-        if (edge_x && J + e >= NX) val[e] = C(0);
+        if (!row_ok || (edge_x && J + e >= NX)) val[e] = C(0);  // outside the grid
       }
-      if (I >= z0 && I < z1 && J < NX) {
-        T* dst = vzB + (long long)I * P + J;
-        if (J + 3 < NX) {
-          st4(dst, val);
+      if (rr >= K && rr < K + TZ && I < NZ) {
+        if (!edge_x || J + 3 < NX) {
+          st4(at(vzB, rr * P + 4 * g), val);
         } else {
 #pragma unroll
           for (int e = 0; e < 4; ++e)
-            if (J + e < NX) stc(dst + e, val[e]);
+            if (J + e < NX) stc(at(vzB, rr * P + 4 * g + e), val[e]);
         }
       }
+      st4(sVZ + 4 * q, val);
     }
-    st4(sVZ + 4 * q, val);
   }
   __syncthreads();
 
@@ -599,55 +631,62 @@ __global__ __launch_bounds__(256, 6) void k_step(StepArgs a) {
     }
   }
 
-  // ---- p^{n+1} on the tile ----------------------------------------------
+  // ---- p^{n+1} on the tile -------------------------------------------------------
 #pragma unroll
   for (int k = 0; k < NQT; ++k) {
-    const int q = tid + 256 * k;
-    if (q >= TZ * GT) continue;
-    const int rr = q >> 4, g = q & 15;
-    const int I = z0 + rr, J = x0 + 4 * g;
-    if (I >= NZ || J >= NX) continue;
-    C w[12];  // v_x at columns J-4 .. J+7
-    ld4(*reinterpret_cast<C(*)[4]>(w), sVX + rr * WVX + 4 * g);
-    ld4(*reinterpret_cast<C(*)[4]>(w + 4), sVX + rr * WVX + 4 * g + 4);
-    ld4(*reinterpret_cast<C(*)[4]>(w + 8), sVX + rr * WVX + 4 * g + 8);
-    C dx[4] = {C(0), C(0), C(0), C(0)}, dz[4] = {C(0), C(0), C(0), C(0)};
+    const int q = tid + NT * k;
+    if (NT * k + NT - 1 < TZ * GT || q < TZ * GT) {
+      const int rr = q >> 4, g = q & 15;
+      const int I = z0 + rr, J = x0 + 4 * g;
+      if (I >= NZ || J >= NX) continue;
+      C w[12];  // v_x at columns J-4 .. J+7
+      const C* vrow = sVX + rr * WVX + 4 * g;
+      ld4(*reinterpret_cast<C(*)[4]>(w), vrow);
+      ld4(*reinterpret_cast<C(*)[4]>(w + 4), vrow + 4);
+      ld4(*reinterpret_cast<C(*)[4]>(w + 8), vrow + 8);
+      C dx[4] = {C(0), C(0), C(0), C(0)}, dz[4] = {C(0), C(0), C(0), C(0)};
 #pragma unroll
-    for (int m = 1; m <= K; ++m) {
-      C hi[4], lo[4];
-      ld4(hi, sVZ + (rr + K + m - 1) * TX + 4 * g);
-      ld4(lo, sVZ + (rr + K - m) * TX + 4 * g);
+      for (int m = 1; m <= K; ++m) {
+        C hi[4], lo[4];
+        ld4(hi, sVZ + (rr + K + m - 1) * TX + 4 * g);
+        ld4(lo, sVZ + (rr + K - m) * TX + 4 * g);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          dx[e] = acc(dx[e], wst<K, C>(m - 1), w[e + m + 3], w[e + 4 - m]);
+          dz[e] = acc(dz[e], wst<K, C>(m - 1), hi[e], lo[e]);
+        }
+      }
+      C pc[4], pn[4], an[4];
+      ld4(pc, sP + (rr + R) * WP + 4 * g + HXS);
+      const C* lrow = !pil_here ? nullptr
+                      : I == a.pil.row0 ? sL + 2 * TX : (I == a.pil.row1 ? sL + 3 * TX : nullptr);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        dx[e] = acc(dx[e], wst<K, C>(m - 1), w[e + m + 3], w[e + 4 - m]);
-        dz[e] = acc(dz[e], wst<K, C>(m - 1), hi[e], lo[e]);
+        const int Je = J + e;
+        const C src = lrow ? lrow[4 * g + e] : C(0);
+        const bool frame = frame_tile && (I < L || I >= NZ - L || Je < L || Je >= NX - L);
+        an[e] = rau[k][e];
+        if (!frame) {
+          pn[e] = upd_p<ADJ>(rck[k][e], pc[e], dx[e], dz[e], src);
+        } else {
+          pn[e] = upd_p_frame<ADJ>(rck[k][e], pc[e], rau[k][e], dx[e], dz[e], src,
+                                   sF[FXN + 4 * g + e], sF[FXN + TX + 4 * g + e],
+                                   sF[FZN + rr], sF[FZN + TZ + rr], &an[e]);
+        }
       }
-    }
-    C pc[4];
-    ld4(pc, sP + (rr + R) * WP + 4 * g + HXS);
-    C pn[4];
-    const long long o = (long long)I * P + J;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int Je = J + e;
-      const C src = pil_here ? line_src<C, V>(a.pil, a.pi, I, Je, shot) : C(0);
-      const bool frame = frame_tile && (I < L || I >= NZ - L || Je < L || Je >= NX - L);
-      if (!frame) {
-        pn[e] = upd_p<ADJ>(rck[k][e], pc[e], dx[e], dz[e], src);
+      const unsigned off = rr * P + 4 * g;
+      if (!edge_x || J + 3 < NX) {
+        st4(at(pB, off), pn);
+        if (frame_tile) st4(at(auB, off), an);
       } else {
-        C an;
-        pn[e] = upd_p_frame<ADJ>(rck[k][e], pc[e], rau[k][e], dx[e], dz[e], src,
-                                 sF[4 * g + e], sF[TX + 4 * g + e],
-                                 sF[2 * TX + 2 * HVZ + rr], sF[2 * TX + 2 * HVZ + TZ + rr], &an);
-        if (Je < NX) stc(auB + o + e, an);
-      }
-    }
-    if (J + 3 < NX) {
-      st4(pB + o, pn);
-    } else {
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (J + e < NX) stc(pB + o + e, pn[e]);
+        for (int e = 0; e < 4; ++e) {
+          if (J + e < NX) {
+            stc(at(pB, off + e), pn[e]);
+            if (frame_tile) stc(at(auB, off + e), an[e]);
+          }
+        }
+      }
     }
   }
 }
@@ -977,11 +1016,11 @@ template <int K, bool ADJ, typename T>
 static hipError_t step_t(int tz, const StepArgs& a, hipStream_t s) {
   const int nb = a.ntx * a.ntz * a.nshots;
   switch (tz) {
-    case 8: hipLaunchKernelGGL((k_step<K, ADJ, T, 8>), dim3(nb), dim3(256), 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_step<K, ADJ, T, 16>), dim3(nb), dim3(256), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_step<K, ADJ, T, 8>), dim3(nb), dim3(step_threads(8)), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_step<K, ADJ, T, 16>), dim3(nb), dim3(step_threads(16)), 0, s, a); break;
     case 32:
       if constexpr (sizeof(T) < 8) {
-        hipLaunchKernelGGL((k_step<K, ADJ, T, 32>), dim3(nb), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_step<K, ADJ, T, 32>), dim3(nb), dim3(step_threads(32)), 0, s, a);
         break;
       }
       return hipErrorInvalidValue;
