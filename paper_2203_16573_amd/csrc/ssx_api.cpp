@@ -205,16 +205,17 @@ void build_grid(const ssx_problem& p, const std::vector<double>& kphys, int nz, 
     *a = (1.0 - q) / (1.0 + q);
     *b = 1.0 / (1.0 + q);
   };
-  const int NX = g->NX, NZ = g->NZ, PX = g->pitch;
-  g->pml.assign(4 * (size_t)PX + 4 * (size_t)NZ, 1.0);
+  const int NX = g->NX, NZ = g->NZ, PX = g->pitch, ZL = NZ + 2 * PZ;
+  g->pml.assign(4 * (size_t)PX + 4 * (size_t)ZL, 1.0);
   double* Q = g->pml.data();
   for (int J = 0; J < NX; ++J) {
     ab(J, nx, &Q[GX + J], &Q[PX + GX + J]);
     ab(J + 0.5, nx, &Q[2 * PX + GX + J], &Q[3 * PX + GX + J]);
   }
+  double* Z = Q + 4 * (size_t)PX + PZ;
   for (int I = 0; I < NZ; ++I) {
-    ab(I, nz, &Q[4 * PX + I], &Q[4 * PX + NZ + I]);
-    ab(I + 0.5, nz, &Q[4 * PX + 2 * NZ + I], &Q[4 * PX + 3 * NZ + I]);
+    ab(I, nz, &Z[I], &Z[ZL + I]);
+    ab(I + 0.5, nz, &Z[2 * ZL + I], &Z[3 * ZL + I]);
   }
 }
 
@@ -314,7 +315,7 @@ void layout(ssx_ctx* c, const GridHost& fg, const GridHost& sg, char* base, size
     gd.fields1.vz = fb ? fb + 6 * one : nullptr;
     gd.fields1.aux = fb ? fb + 7 * one : nullptr;
     gd.coef.ck = a.take((size_t)gh.field_elems * csz);
-    gd.coef.pml = a.take((4 * (size_t)gh.pitch + 4 * (size_t)gh.NZ) * csz);
+    gd.coef.pml = a.take((4 * (size_t)gh.pitch + 4 * (size_t)(gh.NZ + 2 * PZ)) * csz);
   };
   grid(c->full, fg);
   grid(c->slab, sg);

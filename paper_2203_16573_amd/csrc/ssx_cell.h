@@ -62,19 +62,23 @@ __device__ __forceinline__ C upd_p_frame(C ck, C p, C aux, C dx, C dz, C src, C 
 }
 
 // absorbing-layer factors: x arrays of length pitch (origin GX), then z
-// arrays of length NZ
+// arrays of length NZ + 2 PZ (origin PZ); 1 outside the grid
 template <typename C> struct Pml {
   const C* p;
   int P, NZ;
+  __device__ __forceinline__ int zl() const { return NZ + 2 * PZ; }
   __device__ __forceinline__ const C* xa(int k, int J) const { return p + k * P + GX + J; }
+  __device__ __forceinline__ const C* za(int k, int I) const {
+    return p + 4 * P + k * zl() + PZ + I;
+  }
   __device__ __forceinline__ C axn(int J) const { return p[GX + J]; }
   __device__ __forceinline__ C bxn(int J) const { return p[P + GX + J]; }
   __device__ __forceinline__ C axh(int J) const { return p[2 * P + GX + J]; }
   __device__ __forceinline__ C bxh(int J) const { return p[3 * P + GX + J]; }
-  __device__ __forceinline__ C azn(int I) const { return p[4 * P + I]; }
-  __device__ __forceinline__ C bzn(int I) const { return p[4 * P + NZ + I]; }
-  __device__ __forceinline__ C azh(int I) const { return p[4 * P + 2 * NZ + I]; }
-  __device__ __forceinline__ C bzh(int I) const { return p[4 * P + 3 * NZ + I]; }
+  __device__ __forceinline__ C azn(int I) const { return *za(0, I); }
+  __device__ __forceinline__ C bzn(int I) const { return *za(1, I); }
+  __device__ __forceinline__ C azh(int I) const { return *za(2, I); }
+  __device__ __forceinline__ C bzh(int I) const { return *za(3, I); }
 };
 
 template <typename C>

@@ -17,6 +17,10 @@ namespace ssx {
 // pitch is at least NX + 2 GX + 8, a multiple of 64.
 constexpr int GX = 64;
 constexpr int GZ = 8;
+// The absorbing-layer factor arrays along z are padded by PZ entries of 1 on
+// both sides (the arrays along x are pitch long, origin GX, 1 outside the
+// grid), so any tile row or staged halo row reads a factor without a test.
+constexpr int PZ = 64;
 
 enum class Dt : int { F64 = 0, F32 = 1, F16 = 2, BF16 = 3 };
 
@@ -55,7 +59,8 @@ struct Coef {
   // (element (I, J) at origin + I * pitch + J, zero ghosts)
   const void* ck;
   // absorbing-layer factors, compute type: ax_n bx_n ax_h bx_h, each pitch
-  // long with element J at GX + J; then az_n bz_n az_h bz_h, each NZ long
+  // long with element J at GX + J; then az_n bz_n az_h bz_h, each NZ + 2 PZ
+  // long with element I at PZ + I (1 outside the grid)
   const void* pml;
   double cb;        // Z0 dt / (rho h)
 };

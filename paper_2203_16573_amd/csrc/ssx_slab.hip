@@ -108,7 +108,7 @@ __global__ __launch_bounds__(SLAB_THREADS) void k_slab(StepArgs a) {
   }
   for (int i = tid; i < 4 * SLAB_MAXZ; i += SLAB_THREADS) {
     const int f = i / SLAB_MAXZ, I = i - f * SLAB_MAXZ;
-    spz[i] = I < NZ ? pml[4 * Pt + f * NZ + I] : C(1);
+    spz[i] = I < NZ ? pml[4 * Pt + f * (NZ + 2 * PZ) + PZ + I] : C(1);
   }
   __syncthreads();
 

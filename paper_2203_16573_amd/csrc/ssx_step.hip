@@ -472,24 +472,30 @@ __global__ __launch_bounds__(step_threads(TZ), 6) void k_step(StepArgs a) {
       }
     }
   }
-  // layer factors (1 outside the grid) and line injections (0 off the line)
-  for (int i = tid; i < NF; i += NT) {
-    C f = C(1);
-    if (i < FXN) {
-      const int j = i < WVX ? i : i - WVX, J = x0 - 4 + j;
-      if (J >= 0 && J < NX) f = i < WVX ? pm.axh(J) : pm.bxh(J);
-    } else if (i < FZH) {
-      const int j = i - FXN, J = x0 + (j & (TX - 1));
-      if (frame_tile && J < NX) f = j < TX ? pm.axn(J) : pm.bxn(J);
-    } else if (i < FZN) {
-      const int j = i - FZH, I = z0 - K + (j < HVZ ? j : j - HVZ);
-      if (I >= 0 && I < NZ) f = j < HVZ ? pm.azh(I) : pm.bzh(I);
-    } else {
-      const int j = i - FZN, I = z0 + (j < TZ ? j : j - TZ);
-      if (frame_tile && I < NZ) f = j < TZ ? pm.azn(I) : pm.bzn(I);
-    }
-    sF[i] = f;
+  // layer factors (the padded arrays hold 1 outside the grid): the x
+  // factors as 128-bit groups, the z factors one per thread
+  // factors, only in a direction in which the tile reaches the layer
+  // (half nodes are 1 on [L, N-L-1), nodes on [L, N-L))
+  static_assert(NT >= 2 * GVX + 2 * GT + 2 * HVZ + 2 * TZ, "too few threads for the factors");
+  const bool lay_x = x0 - 4 < L || x1 + 4 > NX - L - 1;
+  const bool lay_z = z0 - K < L || z1 + K - 1 > NZ - L - 1;
+  if (tid < 2 * GVX) {
+    C f[4] = {C(1), C(1), C(1), C(1)};
+    if (lay_x) ld4(f, pm.xa(tid < GVX ? 2 : 3, x0 - 4 + 4 * (tid < GVX ? tid : tid - GVX)));
+    st4(sF + FXH + 4 * tid, f);
+  } else if (tid < 2 * GVX + 2 * GT) {
+    const int j = tid - 2 * GVX;
+    C f[4] = {C(1), C(1), C(1), C(1)};
+    if (lay_x) ld4(f, pm.xa(j < GT ? 0 : 1, x0 + 4 * (j < GT ? j : j - GT)));
+    st4(sF + FXN + 4 * j, f);
+  } else if (tid < 2 * GVX + 2 * GT + 2 * HVZ) {
+    const int j = tid - 2 * GVX - 2 * GT;
+    sF[FZH + j] = !lay_z ? C(1) : j < HVZ ? *pm.za(2, z0 - K + j) : *pm.za(3, z0 - K + j - HVZ);
+  } else if (tid < 2 * GVX + 2 * GT + 2 * HVZ + 2 * TZ) {
+    const int j = tid - 2 * GVX - 2 * GT - 2 * HVZ;
+    sF[FZN + j] = !lay_z ? C(1) : j < TZ ? *pm.za(0, z0 + j) : *pm.za(1, z0 + j - TZ);
   }
+  // line injections (0 off the line)
   if ((vil_here || pil_here) && tid < 4 * TX) {
     const int j = tid >> 6, c = tid & (TX - 1);  // 4 rows of TX values
     const LineDev& l = j < 2 ? a.vil : a.pil;
