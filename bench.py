@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--max-shots", type=int, default=8, help="c5: shots per request cap")
     ap.add_argument("--max-nt", type=int, default=1500, help="c5: record length cap")
     ap.add_argument("--slots", type=int, default=4, help="c5: concurrent requests")
+    ap.add_argument("--rate-sweep", action="store_true",
+                    help="c5: also serve open-loop streams at 0.5, 1.0 and 1.2x the measured "
+                         "capacity (0.8x is always run)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target length of the oracle's bounded CPU sample")
@@ -289,7 +292,9 @@ def serve_bench(args):
     shots, 500..--max-nt steps, K = 20, FP16 storage), data generated on the
     device before timing.  A closed-loop pass (all queued at t = 0) measures
     capacity; an open-loop pass with Poisson arrivals at 0.8x that rate
-    measures latency."""
+    measures latency (with --rate-sweep also 0.5x, 1.0x and 1.2x).  Each
+    request runs on its own stream with its propagations replayed as
+    captured graphs (--graphs 0: plain launches)."""
     import numpy as np
     import torch
 
@@ -318,21 +323,30 @@ def serve_bench(args):
         for r in reqs:  # tune every shape before timing
             autotune.choose(r.prob, r.kappa, r.rho, field_dtype="f16")
     budget = int(0.8 * torch.cuda.mem_get_info()[0])
-    srv = serve.Server(budget, slots=args.slots, graphs=False, tuner=tuner)
+    srv = serve.Server(budget, slots=args.slots, graphs=bool(args.graphs), tuner=tuner)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     closed = srv.run(reqs, realtime=False)
     wall_closed = time.perf_counter() - t0
     cap = serve.summarize(closed, wall_closed)
-    rate = 0.8 * cap["requests_per_s"]
-    gaps = np.random.default_rng(inputs.BASE_SEED + 5).exponential(1.0 / rate, size=len(reqs))
-    for r, t in zip(reqs, np.cumsum(gaps)):
-        r.arrival = float(t)
-    t0 = time.perf_counter()
-    opened = srv.run(reqs, realtime=True)
-    wall_open = time.perf_counter() - t0
-    lat = serve.summarize(opened, wall_open)
+    unit_gaps = np.random.default_rng(inputs.BASE_SEED + 5).exponential(1.0, size=len(reqs))
+
+    def open_loop(factor):
+        rate = factor * cap["requests_per_s"]
+        for r, t in zip(reqs, np.cumsum(unit_gaps / rate)):
+            r.arrival = float(t)
+        t0 = time.perf_counter()
+        res = srv.run(reqs, realtime=True)
+        return res, serve.summarize(res, time.perf_counter() - t0)
+
+    opened, lat = open_loop(0.8)
     same = all(torch.equal(a.h, b.h) for a, b in zip(closed, opened))
+    sweep = {}
+    if args.rate_sweep:
+        for factor in (0.5, 1.0, 1.2):
+            res, summ = open_loop(factor)
+            same = same and all(torch.equal(a.h, b.h) for a, b in zip(closed, res))
+            sweep[f"open_loop_{factor:g}x"] = summ
     out = {
         "metric": "served PCG surface-source solves/s (p50/p99 latency)",
         "value": round(cap["solves_per_s"], 4), "unit": "solves/s", "n_gpus": 1,
@@ -342,8 +356,8 @@ def serve_bench(args):
         "dtype": "f16-storage/f32", "data": "synthetic (seeded serving stream)",
         "config": {"workload": f"c5: first {len(reqs)} requests of the seeded stream, "
                                f"<= {args.max_shots} shots, nt <= {args.max_nt}, K 20, "
-                               f"{args.slots} slots"},
-        "closed_loop": cap, "open_loop_0p8": lat,
+                               f"{args.slots} slots, graphs {int(bool(args.graphs))}"},
+        "closed_loop": cap, "open_loop_0p8": lat, **sweep,
         "p50_latency_s": round(lat["latency_p50_s"], 3),
         "p99_latency_s": round(lat["latency_p99_s"], 3),
         "results_identical_closed_vs_open": same,

@@ -152,6 +152,9 @@ __global__ __launch_bounds__(TBX* TBY) void k_pres(Fields f, GridDims g, Coef cf
 // re-reads inside one L2.
 constexpr int TX = 64;
 constexpr int HXS = 8;  // staged x halo (>= 2K - 1, multiple of 4)
+// padding (floats) added to the LDS row pitch of the staged pressure, v_x
+// and v_z tiles (multiples of 4: rows stay 16-byte aligned)
+constexpr int LDS_PAD_P = 0, LDS_PAD_X = 0, LDS_PAD_Z = 0;
 
 // threads of a fused-step workgroup: 256 for 64 x 8 and 64 x 16 tiles, 512
 // for 64 x 32 (each thread owns the same 1 x 4 cells at every height)
@@ -194,6 +197,7 @@ __device__ __forceinline__ void step_interior(const StepArgs& a, long long base,
   constexpr int WVX = 4 * GVX;
   constexpr int HVZ = TZ + 2 * K - 1;
   constexpr int GT = TX / 4;
+  constexpr int SPP = WP + LDS_PAD_P, SPX = WVX + LDS_PAD_X, SPZ = TX + LDS_PAD_Z;  // LDS pitches
   constexpr int NQP = (HP * GP + NT - 1) / NT;
   constexpr int NQX = (TZ * GVX + NT - 1) / NT;
   constexpr int NQZ = (HVZ * GT + NT - 1) / NT;
@@ -247,7 +251,7 @@ __device__ __forceinline__ void step_interior(const StepArgs& a, long long base,
 #pragma unroll
   for (int k = 0; k < NQP; ++k) {
     const int q = tid + NT * k;
-    if (NT * k + NT - 1 < HP * GP || q < HP * GP) st4(sP + 4 * q, rp[k]);
+    if (NT * k + NT - 1 < HP * GP || q < HP * GP) { const int rr = q / GP, g = q - rr * GP; st4(sP + rr * SPP + 4 * g, rp[k]); }
   }
   __syncthreads();
 
@@ -257,7 +261,7 @@ __device__ __forceinline__ void step_interior(const StepArgs& a, long long base,
     const int q = tid + NT * k;
     if (NT * k + NT - 1 < TZ * GVX || q < TZ * GVX) {
       const int rr = q / GVX, g = q - rr * GVX;
-      const C* row = sP + (rr + R) * WP + 4 * g;
+      const C* row = sP + (rr + R) * SPP + 4 * g;
       C w[12];
       ld4(*reinterpret_cast<C(*)[4]>(w), row);
       ld4(*reinterpret_cast<C(*)[4]>(w + 4), row + 4);
@@ -271,7 +275,7 @@ __device__ __forceinline__ void step_interior(const StepArgs& a, long long base,
         val[e] = rnd<T>(upd_v<ADJ>(one, one, cb, rvx[k][e], sx, zero));
       }
       if (g >= 1 && g <= GT) st4(at(vxB, rr * P + 4 * g), val);
-      st4(sVX + 4 * q, val);
+      st4(sVX + rr * SPX + 4 * g, val);
     }
   }
   // ---- v_z on the tile columns, rows z0-K .. z1+K-2 ----------------------------
@@ -280,13 +284,13 @@ __device__ __forceinline__ void step_interior(const StepArgs& a, long long base,
     const int q = tid + NT * k;
     if (NT * k + NT - 1 < HVZ * GT || q < HVZ * GT) {
       const int rr = q >> 4, g = q & 15;
-      const C* col = sP + (rr - K + R) * WP + 4 * g + HXS;
+      const C* col = sP + (rr - K + R) * SPP + 4 * g + HXS;
       C sz[4] = {zero, zero, zero, zero};
 #pragma unroll
       for (int m = 1; m <= K; ++m) {
         C hi[4], lo[4];
-        ld4(hi, col + m * WP);
-        ld4(lo, col + (1 - m) * WP);
+        ld4(hi, col + m * SPP);
+        ld4(lo, col + (1 - m) * SPP);
 #pragma unroll
         for (int e = 0; e < 4; ++e) sz[e] = acc(sz[e], wst<K, C>(m - 1), hi[e], lo[e]);
       }
@@ -294,7 +298,7 @@ __device__ __forceinline__ void step_interior(const StepArgs& a, long long base,
 #pragma unroll
       for (int e = 0; e < 4; ++e) val[e] = rnd<T>(upd_v<ADJ>(one, one, cb, rvz[k][e], sz[e], zero));
       if (rr >= K && rr < K + TZ) st4(at(vzB, rr * P + 4 * g), val);
-      st4(sVZ + 4 * q, val);
+      st4(sVZ + rr * SPZ + 4 * g, val);
     }
   }
   __syncthreads();
@@ -306,7 +310,7 @@ __device__ __forceinline__ void step_interior(const StepArgs& a, long long base,
     if (NT * k + NT - 1 < TZ * GT || q < TZ * GT) {
       const int rr = q >> 4, g = q & 15;
       C w[12];
-      const C* vrow = sVX + rr * WVX + 4 * g;
+      const C* vrow = sVX + rr * SPX + 4 * g;
       ld4(*reinterpret_cast<C(*)[4]>(w), vrow);
       ld4(*reinterpret_cast<C(*)[4]>(w + 4), vrow + 4);
       ld4(*reinterpret_cast<C(*)[4]>(w + 8), vrow + 8);
@@ -314,8 +318,8 @@ __device__ __forceinline__ void step_interior(const StepArgs& a, long long base,
 #pragma unroll
       for (int m = 1; m <= K; ++m) {
         C hi[4], lo[4];
-        ld4(hi, sVZ + (rr + K + m - 1) * TX + 4 * g);
-        ld4(lo, sVZ + (rr + K - m) * TX + 4 * g);
+        ld4(hi, sVZ + (rr + K + m - 1) * SPZ + 4 * g);
+        ld4(lo, sVZ + (rr + K - m) * SPZ + 4 * g);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           dx[e] = acc(dx[e], wst<K, C>(m - 1), w[e + m + 3], w[e + 4 - m]);
@@ -323,7 +327,7 @@ __device__ __forceinline__ void step_interior(const StepArgs& a, long long base,
         }
       }
       C pc[4], pn[4];
-      ld4(pc, sP + (rr + R) * WP + 4 * g + HXS);
+      ld4(pc, sP + (rr + R) * SPP + 4 * g + HXS);
 #pragma unroll
       for (int e = 0; e < 4; ++e) pn[e] = upd_p<ADJ>(rck[k][e], pc[e], dx[e], dz[e], zero);
       st4(at(pB, rr * P + 4 * g), pn);
@@ -344,16 +348,17 @@ __global__ __launch_bounds__(step_threads(TZ), 6) void k_step(StepArgs a) {
   constexpr int WVX = 4 * GVX;
   constexpr int HVZ = TZ + 2 * K - 1;  // v_z rows: z0-K .. z1+K-2
   constexpr int GT = TX / 4;           // groups per tile row
+  constexpr int SPP = WP + LDS_PAD_P, SPX = WVX + LDS_PAD_X, SPZ = TX + LDS_PAD_Z;  // LDS pitches
   constexpr int NQP = (HP * GP + NT - 1) / NT;
   constexpr int NQX = (TZ * GVX + NT - 1) / NT;
   constexpr int NQZ = (HVZ * GT + NT - 1) / NT;
   constexpr int NQT = (TZ * GT + NT - 1) / NT;
   constexpr int NQA = (TZ * GP + NT - 1) / NT;
   static_assert(2 * K - 1 <= HXS && K <= 4, "halo wider than the staged columns");
-  __shared__ __align__(16) C sP[HP * WP];
-  __shared__ __align__(16) C sPX[ADJ ? TZ * WP : 4];
-  __shared__ __align__(16) C sVX[TZ * WVX];
-  __shared__ __align__(16) C sVZ[HVZ * TX];
+  __shared__ __align__(16) C sP[HP * SPP];
+  __shared__ __align__(16) C sPX[ADJ ? TZ * SPP : 4];
+  __shared__ __align__(16) C sVX[TZ * SPX];
+  __shared__ __align__(16) C sVZ[HVZ * SPZ];
   // general tiles: layer factors and line injections, staged with the
   // loads so that no global access waits inside the compute phases
   //   sF: a_h, b_h over the v_x columns x0-4 .. x1+3; a_n, b_n over the
@@ -507,14 +512,14 @@ __global__ __launch_bounds__(step_threads(TZ), 6) void k_step(StepArgs a) {
 #pragma unroll
   for (int k = 0; k < NQP; ++k) {
     const int q = tid + NT * k;
-    if (NT * k + NT - 1 < HP * GP || q < HP * GP) st4(sP + 4 * q, rp[k]);
+    if (NT * k + NT - 1 < HP * GP || q < HP * GP) { const int rr = q / GP, g = q - rr * GP; st4(sP + rr * SPP + 4 * g, rp[k]); }
   }
   if constexpr (ADJ) {
     if (use_px) {
 #pragma unroll
       for (int k = 0; k < NQA; ++k) {
         const int q = tid + NT * k;
-        if (NT * k + NT - 1 < TZ * GP || q < TZ * GP) st4(sPX + 4 * q, rax[k]);
+        if (NT * k + NT - 1 < TZ * GP || q < TZ * GP) { const int rr = q / GP, g = q - rr * GP; st4(sPX + rr * SPP + 4 * g, rax[k]); }
       }
     }
   }
@@ -526,12 +531,13 @@ __global__ __launch_bounds__(step_threads(TZ), 6) void k_step(StepArgs a) {
       for (int k = 0; k < NQA; ++k) {
         const int q = tid + NT * k;
         if (NT * k + NT - 1 < TZ * GP || q < TZ * GP) {
+          const int rr = q / GP, g = q - rr * GP;
           C pz[4], ax[4], sum[4];
-          ld4(pz, sP + 4 * q + R * WP);
-          ld4(ax, sPX + 4 * q);
+          ld4(pz, sP + (rr + R) * SPP + 4 * g);
+          ld4(ax, sPX + rr * SPP + 4 * g);
 #pragma unroll
           for (int e = 0; e < 4; ++e) sum[e] = pz[e] + ax[e];
-          st4(sPX + 4 * q, sum);
+          st4(sPX + rr * SPP + 4 * g, sum);
         }
       }
       __syncthreads();
@@ -544,7 +550,7 @@ __global__ __launch_bounds__(step_threads(TZ), 6) void k_step(StepArgs a) {
     if (J >= a.vsl.col0 && J < a.vsl.col0 + a.vsl.ntr && J < NX) {
       const int r0 = a.vsl.row0 - z0 + R, r1 = a.vsl.row1 - z0 + R;
       const C val =
-          C(a.vsl.w0) * sP[r0 * WP + tid + HXS] + C(a.vsl.w1) * sP[r1 * WP + tid + HXS];
+          C(a.vsl.w0) * sP[r0 * SPP + tid + HXS] + C(a.vsl.w1) * sP[r1 * SPP + tid + HXS];
       line_out<C, V>(a.vsl, a.vs, J, shot, val);
     }
   }
@@ -556,7 +562,7 @@ __global__ __launch_bounds__(step_threads(TZ), 6) void k_step(StepArgs a) {
     if (NT * k + NT - 1 < TZ * GVX || q < TZ * GVX) {
       const int rr = q / GVX, g = q - rr * GVX;
       const int I = z0 + rr, J = x0 - 4 + 4 * g;
-      const C* row = (ADJ && use_px) ? (sPX + rr * WP + 4 * g) : (sP + (rr + R) * WP + 4 * g);
+      const C* row = (ADJ && use_px) ? (sPX + rr * SPP + 4 * g) : (sP + (rr + R) * SPP + 4 * g);
       C w[12];  // staged p (transposed: P~_x) at columns J-4 .. J+7
       ld4(*reinterpret_cast<C(*)[4]>(w), row);
       ld4(*reinterpret_cast<C(*)[4]>(w + 4), row + 4);
@@ -582,7 +588,7 @@ __global__ __launch_bounds__(step_threads(TZ), 6) void k_step(StepArgs a) {
             if (J + e < NX) stc(at(vxB, rr * P + 4 * g + e), val[e]);
         }
       }
-      st4(sVX + 4 * q, val);
+      st4(sVX + rr * SPX + 4 * g, val);
     }
   }
   // ---- v_z on the tile columns, rows z0-K .. z1+K-2 ----------------------------
@@ -592,13 +598,13 @@ __global__ __launch_bounds__(step_threads(TZ), 6) void k_step(StepArgs a) {
     if (NT * k + NT - 1 < HVZ * GT || q < HVZ * GT) {
       const int rr = q >> 4, g = q & 15;
       const int I = z0 - K + rr, J = x0 + 4 * g;
-      const C* col = sP + (rr - K + R) * WP + 4 * g + HXS;
+      const C* col = sP + (rr - K + R) * SPP + 4 * g + HXS;
       C sz[4] = {C(0), C(0), C(0), C(0)};
 #pragma unroll
       for (int m = 1; m <= K; ++m) {
         C hi[4], lo[4];
-        ld4(hi, col + m * WP);
-        ld4(lo, col + (1 - m) * WP);
+        ld4(hi, col + m * SPP);
+        ld4(lo, col + (1 - m) * SPP);
 #pragma unroll
         for (int e = 0; e < 4; ++e) sz[e] = acc(sz[e], wst<K, C>(m - 1), hi[e], lo[e]);
       }
@@ -622,7 +628,7 @@ __global__ __launch_bounds__(step_threads(TZ), 6) void k_step(StepArgs a) {
             if (J + e < NX) stc(at(vzB, rr * P + 4 * g + e), val[e]);
         }
       }
-      st4(sVZ + 4 * q, val);
+      st4(sVZ + rr * SPZ + 4 * g, val);
     }
   }
   __syncthreads();
@@ -632,7 +638,7 @@ __global__ __launch_bounds__(step_threads(TZ), 6) void k_step(StepArgs a) {
     const int J = x0 + tid;
     if (J >= a.psl.col0 && J < a.psl.col0 + a.psl.ntr && J < NX) {
       const int r0 = a.psl.row0 - z0 + K, r1 = a.psl.row1 - z0 + K;
-      const C val = C(a.psl.w0) * sVZ[r0 * TX + tid] + C(a.psl.w1) * sVZ[r1 * TX + tid];
+      const C val = C(a.psl.w0) * sVZ[r0 * SPZ + tid] + C(a.psl.w1) * sVZ[r1 * SPZ + tid];
       line_out<C, V>(a.psl, a.ps, J, shot, val);
     }
   }
@@ -646,7 +652,7 @@ __global__ __launch_bounds__(step_threads(TZ), 6) void k_step(StepArgs a) {
       const int I = z0 + rr, J = x0 + 4 * g;
       if (I >= NZ || J >= NX) continue;
       C w[12];  // v_x at columns J-4 .. J+7
-      const C* vrow = sVX + rr * WVX + 4 * g;
+      const C* vrow = sVX + rr * SPX + 4 * g;
       ld4(*reinterpret_cast<C(*)[4]>(w), vrow);
       ld4(*reinterpret_cast<C(*)[4]>(w + 4), vrow + 4);
       ld4(*reinterpret_cast<C(*)[4]>(w + 8), vrow + 8);
@@ -654,8 +660,8 @@ __global__ __launch_bounds__(step_threads(TZ), 6) void k_step(StepArgs a) {
 #pragma unroll
       for (int m = 1; m <= K; ++m) {
         C hi[4], lo[4];
-        ld4(hi, sVZ + (rr + K + m - 1) * TX + 4 * g);
-        ld4(lo, sVZ + (rr + K - m) * TX + 4 * g);
+        ld4(hi, sVZ + (rr + K + m - 1) * SPZ + 4 * g);
+        ld4(lo, sVZ + (rr + K - m) * SPZ + 4 * g);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           dx[e] = acc(dx[e], wst<K, C>(m - 1), w[e + m + 3], w[e + 4 - m]);
@@ -663,7 +669,7 @@ __global__ __launch_bounds__(step_threads(TZ), 6) void k_step(StepArgs a) {
         }
       }
       C pc[4], pn[4], an[4];
-      ld4(pc, sP + (rr + R) * WP + 4 * g + HXS);
+      ld4(pc, sP + (rr + R) * SPP + 4 * g + HXS);
       const C* lrow = !pil_here ? nullptr
                       : I == a.pil.row0 ? sL + 2 * TX : (I == a.pil.row1 ? sL + 3 * TX : nullptr);
 #pragma unroll

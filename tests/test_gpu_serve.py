@@ -44,10 +44,13 @@ def make_requests(n=6, K=3, fd="f16"):
     return reqs
 
 
-def test_mix_equals_alone():
-    print("case serving mix vs alone", flush=True)
+@pytest.mark.parametrize("graphs", [False, True])
+def test_mix_equals_alone(graphs):
+    # each request's result is the same served alone and in an overlapping
+    # mix, with plain launches and with per-request captured graphs
+    print(f"case serving mix vs alone graphs={graphs}", flush=True)
     reqs = make_requests()
-    mixed = serve.Server(budget_bytes=8 << 30, slots=3).run(reqs, realtime=True)
+    mixed = serve.Server(budget_bytes=8 << 30, slots=3, graphs=graphs).run(reqs, realtime=True)
     assert [r.rid for r in mixed] == list(range(len(reqs)))
     # overlap actually happened: some request was admitted before another finished
     spans = sorted((r.t_admit, r.t_done) for r in mixed)
