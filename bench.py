@@ -55,6 +55,10 @@ def parse():
                     help="override the wavefield storage type")
     ap.add_argument("--tile-z", type=int, default=-1,
                     help="force the full-grid tile height after tuning (profiling runs)")
+    ap.add_argument("--ref-f64", type=int, default=0,
+                    help="after timing, solve the same problem with FP64 fields and vectors "
+                         "(the FP64 path matches the FP64 oracle to 1e-9) and report the "
+                         "timed solution's error against it")
     ap.add_argument("--shot-group", type=int, default=-1,
                     help="force the full-grid shots per launch after tuning (profiling runs)")
     ap.add_argument("--graphs", type=int, default=1)
@@ -224,6 +228,21 @@ def main():
                          f"extrapolated linearly to {cu_solve:.3e} cell-updates per solve",
                "cpu": cpu_model()}
 
+    ref = None
+    if args.ref_f64:
+        rctx = ssx.Context(prob, wl.kappa, wl.rho, field_dtype="f64")
+        h64, hist64, _, _ = rctx.pcg_solve(d.double(), wl.alpha_rel, wl.K, h=rctx.empty_s(),
+                                           raise_on_breakdown=False)
+        torch.cuda.synchronize()
+        rctx.close()
+        hh, hr = h.double().cpu().numpy(), h64.cpu().numpy()
+        errs = [float(np.linalg.norm(hh[s] - hr[s]) / np.linalg.norm(hr[s]))
+                for s in range(prob.nshots)]
+        rr = hist[:, :, 0] / hist64[:, :, 0]
+        ref = {"reference": "same solve with FP64 fields and vectors on the GPU",
+               "h_rel_l2_median": float(np.median(errs)), "h_rel_l2_max": float(np.max(errs)),
+               "residual_history_max_rel_diff": float(np.max(np.abs(rr - 1.0)))}
+
     out = {
         "metric": "PCG surface-source solves/s",
         "value": round(value, 4),
@@ -251,6 +270,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if ref is not None:
+        out["error_vs_f64_solve"] = ref
     print(json.dumps(out), flush=True)
     ctx.close()
 

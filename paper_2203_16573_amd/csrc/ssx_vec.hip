@@ -8,25 +8,28 @@
 namespace ssx {
 
 // ---------------------------------------------------------------------------
-// FP64 reductions: fixed grid and fixed tree, hence bitwise deterministic.
+// FP64 reductions: fixed grid, fixed per-thread order, fixed wavefront
+// shuffle tree, hence bitwise deterministic.
 
+// Sums of the 256 threads of a block, written to dst[0..NV): each wavefront
+// folds its 64 lanes with a fixed shuffle tree, then one thread adds the 4
+// wavefront sums in a fixed order.
 template <int NV>
 __device__ __forceinline__ void block_reduce_store(double (&acc)[NV], double* dst) {
-  __shared__ double sh[NV][256];
-  const int t = threadIdx.x;
+  static_assert(NV <= 3, "at most three sums");
+  __shared__ double sh[NV][4];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
 #pragma unroll
-  for (int v = 0; v < NV; ++v) sh[v][t] = acc[v];
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w) {
+  for (int v = 0; v < NV; ++v) {
+    double x = acc[v];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) sh[v][t] += sh[v][t + w];
-    }
-    __syncthreads();
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+    if (lane == 0) sh[v][wave] = x;
   }
+  __syncthreads();
   if (t == 0) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) dst[v] = sh[v][0];
+    for (int v = 0; v < NV; ++v) dst[v] = (sh[v][0] + sh[v][1]) + (sh[v][2] + sh[v][3]);
   }
 }
 
