@@ -26,6 +26,8 @@
 namespace ssx {
 
 constexpr int SLAB_THREADS = 1024;
+// s_waitcnt operand: vector memory count 0, the other counters unconstrained
+constexpr int VMCNT0 = 0x0F70;
 
 template <int K, int NS, int WR>
 struct SlabShape {
@@ -39,6 +41,13 @@ struct SlabShape {
   static_assert(W > 0 && W % 4 == 0, "strip too narrow for the step count");
   static_assert(H <= GX, "halo wider than the ghost columns");
 };
+
+// four values of a storage vector in the compute type
+template <typename T, typename C>
+__device__ __forceinline__ void cvt4(C (&o)[4], const V4<T>& v) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) o[i] = ldc<C>(&v.e[i]);
+}
 
 template <int K, int NS, int WR>
 int slab_owned_width() {
@@ -65,9 +74,10 @@ __global__ __launch_bounds__(SLAB_THREADS) void k_slab(StepArgs a) {
   __shared__ __align__(16) C spx[4 * WR];
   __shared__ __align__(16) C spz[4 * SLAB_MAXZ];
   // injected values of the current step on the two rows of the v_z line and
-  // of the pressure line, over the region's columns
-  __shared__ __align__(16) C ssv[2 * WR];
-  __shared__ __align__(16) C ssp[2 * WR];
+  // of the pressure line, over the region's columns (element 2 WR: a slot
+  // that threads without a column write to and nobody reads)
+  __shared__ __align__(16) C ssv[2 * WR + 4];
+  __shared__ __align__(16) C ssp[2 * WR + 4];
   // ck: rows 0 .. SLAB_MAXZ-1, columns 0 .. WR-1
   __shared__ __align__(16) C sck[SLAB_MAXZ * WR];
   auto P_ = [](int I, int c) { return (I + K) * RP + c + 4; };
@@ -88,32 +98,51 @@ __global__ __launch_bounds__(SLAB_THREADS) void k_slab(StepArgs a) {
   const C* pml = static_cast<const C*>(a.c.pml);
   const C cb = C(a.c.cb);
   const int tid = threadIdx.x;
-  // values a line injects at step index idx on its rows row0 (buf[0..WR))
-  // and row1 (buf[WR..2WR)), computed once per step by the first 2 WR threads
-  auto fill_src = [&](const LineDev& l, const TraceIO& io, int idx, C* buf) {
-    if (tid < 2 * WR) {
-      const int j = tid / WR, c = tid - j * WR;
-      buf[tid] = line_src_at<C, V>(l, io, idx, a.nt, j ? l.row1 : l.row0, xr + c, shot);
-    }
+  // Line injections: the first 2 WR threads own one region column of a
+  // line's row0 (tid < WR) or row1, and compute the value the line injects
+  // there at a step into buf[tid].  The trace load is issued a phase or more
+  // before the value is needed (fetch), the value formed and stored when it
+  // is (finish), with the arithmetic of line_src_at, so that the memory
+  // latency overlaps a stencil phase instead of stalling the step.
+  const bool filler = tid < 2 * WR;
+  const int fj = tid / WR, fcol = xr + (tid - (tid / WR) * WR);
+  auto fetch = [&](const LineDev& l, const TraceIO& io, int idx, bool& on) -> C {
+    on = filler && io.in && idx >= 0 && idx < a.nt && fcol >= l.col0 && fcol < l.col0 + l.ntr;
+    if (!on) return C(0);
+    const V* in = static_cast<const V*>(io.in) + shot * io.shot_stride + (long long)idx * l.ntr +
+                  (fcol - l.col0);
+    return C(*in);
+  };
+  // finish() begins by waiting for every vector memory operation issued so
+  // far (vmcnt 0): the trace loads it consumes were issued a phase earlier,
+  // and the wait, taken on every path, keeps the compiler from assuming a
+  // load still in flight on paths that do not read its register and from
+  // waiting on it, and on every later memory operation, at an unrelated LDS
+  // read.  Every thread stores, to its column or to the unread slot.
+  auto finish = [&](const LineDev& l, const TraceIO& io, C raw, bool on, C dyn, C* buf) {
+    __builtin_amdgcn_s_waitcnt(VMCNT0);
+    const int I = fj ? l.row1 : l.row0;
+    const C w = (I == l.row0 ? C(l.w0) : C(0)) + (I == l.row1 ? C(l.w1) : C(0));
+    buf[filler ? tid : 2 * WR] = on ? w * (C(io.scale) * raw / dyn) : C(0);
   };
 
-  // ---- zero LDS (padding rows and columns stay zero) ----------------------
-  for (int i = tid; i < S::ZR * RP; i += SLAB_THREADS) sp[i] = C(0);
-  for (int i = tid; i < SLAB_MAXZ * RP; i += SLAB_THREADS) svx[i] = C(0);
-  for (int i = tid; i < SLAB_MAXZ * RP; i += SLAB_THREADS) sau[i] = C(0);
-  for (int i = tid; i < S::ZR * WR; i += SLAB_THREADS) svz[i] = C(0);
-  for (int i = tid; i < 4 * WR; i += SLAB_THREADS) {
-    const int f = i / WR, J = xr + (i - f * WR);
-    spx[i] = (J >= 0 && J < NX) ? pml[f * Pt + GX + J] : C(1);
+  // ---- issue every load of the launch's start, then zero LDS ----------------
+  // absorbing-layer factors: one x entry and one z entry per thread
+  static_assert(4 * WR <= SLAB_THREADS && 4 * SLAB_MAXZ <= SLAB_THREADS, "one factor per thread");
+  C fx = C(1), fz = C(1);
+  if (tid < 4 * WR) {
+    const int f = tid / WR, J = xr + (tid - f * WR);
+    if (J >= 0 && J < NX) fx = pml[f * Pt + GX + J];
   }
-  for (int i = tid; i < 4 * SLAB_MAXZ; i += SLAB_THREADS) {
-    const int f = i / SLAB_MAXZ, I = i - f * SLAB_MAXZ;
-    spz[i] = I < NZ ? pml[4 * Pt + f * (NZ + 2 * PZ) + PZ + I] : C(1);
+  if (tid < 4 * SLAB_MAXZ) {
+    const int f = tid / SLAB_MAXZ, I = tid - f * SLAB_MAXZ;
+    if (I < NZ) fz = pml[4 * Pt + f * (NZ + 2 * PZ) + PZ + I];
   }
-  __syncthreads();
-
-  // ---- load the strip ----------------------------------------------------
-  // task q: row q / G, columns 4 (q % G) .. +3 of the region
+  // the strip: task q: row q / G, columns 4 (q % G) .. +3 of the region; all loads are
+  // in flight together and land in registers, in the storage type, until LDS
+  // is cleared
+  V4<T> lp[NQ], lvx[NQ], lvz[NQ], lau[NQ];
+  V4<C> lck[NQ];
 #pragma unroll
   for (int k = 0; k < NQ; ++k) {
     const int q = tid + SLAB_THREADS * k;
@@ -121,36 +150,76 @@ __global__ __launch_bounds__(SLAB_THREADS) void k_slab(StepArgs a) {
     if (I < NZ && J < NX) {
       // columns J .. J+3 lie in [-GX, NX + 3) (ghost columns read zero)
       const long long o = (long long)I * Pt + J;
+      lp[k] = *reinterpret_cast<const V4<T>*>(pA + o);
+      lvx[k] = *reinterpret_cast<const V4<T>*>(vxA + o);
+      lvz[k] = *reinterpret_cast<const V4<T>*>(vzA + o);
+      lau[k] = *reinterpret_cast<const V4<T>*>(auA + o);
+      lck[k] = *reinterpret_cast<const V4<C>*>(ckp + o);
+    }
+  }
+  const C dynv = a.vi.in ? dyn_of<C>(a.vi, shot) : C(1);
+  const C dynp = a.pi.in ? dyn_of<C>(a.pi, shot) : C(1);
+  const C dynvs = a.vs.out ? dyn_of<C>(a.vs, shot) : C(1);
+  const C dynps = a.ps.out ? dyn_of<C>(a.ps, shot) : C(1);
+  // a sampled value written to a line's trace (the arithmetic of
+  // line_out_at, with the field scale read once)
+  auto emit = [&](const LineDev& l, const TraceIO& io, int idx, int J, C val, C dyn) {
+    V* out = static_cast<V*>(io.out) + shot * io.shot_stride + (long long)idx * l.ntr + (J - l.col0);
+    *out = V(C(io.scale) * val * dyn);
+  };
+  bool onv, onp;
+  C rv = fetch(a.vil, a.vi, a.vi.n, onv);
+  C rp = fetch(a.pil, a.pi, a.pi.n, onp);
+  // padding rows and columns stay zero
+  for (int i = tid; i < S::ZR * RP; i += SLAB_THREADS) sp[i] = C(0);
+  for (int i = tid; i < SLAB_MAXZ * RP; i += SLAB_THREADS) svx[i] = C(0);
+  for (int i = tid; i < SLAB_MAXZ * RP; i += SLAB_THREADS) sau[i] = C(0);
+  for (int i = tid; i < S::ZR * WR; i += SLAB_THREADS) svz[i] = C(0);
+  if (tid < 4 * WR) spx[tid] = fx;
+  if (tid < 4 * SLAB_MAXZ) spz[tid] = fz;
+  __syncthreads();
+
+  // ---- store the strip ---------------------------------------------------
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    const int q = tid + SLAB_THREADS * k;
+    const int I = q / G, c = 4 * (q - (q / G) * G), J = xr + c;
+    if (I < NZ && J < NX) {
       C v[4];
-      ld4(v, pA + o);
+      cvt4(v, lp[k]);
       st4(sp + P_(I, c), v);
-      ld4(v, vxA + o);
+      cvt4(v, lvx[k]);
       st4(svx + X_(I, c), v);
-      ld4(v, vzA + o);
+      cvt4(v, lvz[k]);
       st4(svz + Z_(I, c), v);
-      ld4(v, auA + o);
+      cvt4(v, lau[k]);
       st4(sau + X_(I, c), v);
-      ld4(v, ckp + o);
+      cvt4(v, lck[k]);
       st4(sck + I * WR + c, v);
     }
   }
-  fill_src(a.vil, a.vi, a.vi.n, ssv);
+  finish(a.vil, a.vi, rv, onv, dynv, ssv);  // step 0
+  finish(a.pil, a.pi, rp, onp, dynp, ssp);
   __syncthreads();
 
   for (int t = 0; t < NS; ++t) {
-    const int ivs = a.vs.n + a.dir * t, ivi = a.vi.n + a.dir * t;
-    const int ips = a.ps.n + a.dir * t, ipi = a.pi.n + a.dir * t;
+    const int ivs = a.vs.n + a.dir * t, ips = a.ps.n + a.dir * t;
+    // pressure injections of step t (the readers of step t - 1 are past the
+    // last barrier), then the trace loads of step t + 1
+    if (t > 0) finish(a.pil, a.pi, rp, onp, dynp, ssp);
+    if (t + 1 < NS) {
+      rv = fetch(a.vil, a.vi, a.vi.n + a.dir * (t + 1), onv);
+      rp = fetch(a.pil, a.pi, a.pi.n + a.dir * (t + 1), onp);
+    }
 
     // pressure-line sampling (p^n), owned columns
     if (a.vs.out && ivs >= 0 && ivs < a.nt && tid < W) {
       const int c = H + tid, J = xr + c;
       if (J < NX && J >= a.vsl.col0 && J < a.vsl.col0 + a.vsl.ntr) {
         const C val = C(a.vsl.w0) * sp[P_(a.vsl.row0, c)] + C(a.vsl.w1) * sp[P_(a.vsl.row1, c)];
-        line_out_at<C, V>(a.vsl, a.vs, ivs, J, shot, val);
+        emit(a.vsl, a.vs, ivs, J, val, dynvs);
       }
     }
-
-    fill_src(a.pil, a.pi, ipi, ssp);  // read after the next barrier
 
     // ---- velocities ----------------------------------------------------------
 #pragma unroll
@@ -210,16 +279,19 @@ __global__ __launch_bounds__(SLAB_THREADS) void k_slab(StepArgs a) {
     }
     __syncthreads();
 
+    // velocity injections of step t + 1 (read after the next barrier); before
+    // the sampling store below, so that waiting for the trace loads does not
+    // also wait for that store
+    if (t + 1 < NS) finish(a.vil, a.vi, rv, onv, dynv, ssv);
+
     // v_z-line sampling (v^{n+1/2}), owned columns
     if (a.ps.out && ips >= 0 && ips < a.nt && tid < W) {
       const int c = H + tid, J = xr + c;
       if (J < NX && J >= a.psl.col0 && J < a.psl.col0 + a.psl.ntr) {
         const C val = C(a.psl.w0) * svz[Z_(a.psl.row0, c)] + C(a.psl.w1) * svz[Z_(a.psl.row1, c)];
-        line_out_at<C, V>(a.psl, a.ps, ips, J, shot, val);
+        emit(a.psl, a.ps, ips, J, val, dynps);
       }
     }
-
-    if (t + 1 < NS) fill_src(a.vil, a.vi, ivi + a.dir, ssv);  // read after the next barrier
 
     // ---- pressure --------------------------------------------------------------
 #pragma unroll
