@@ -61,6 +61,9 @@ def parse():
                          "timed solution's error against it")
     ap.add_argument("--shot-group", type=int, default=-1,
                     help="force the full-grid shots per launch after tuning (profiling runs)")
+    ap.add_argument("--tile-loop", type=int, default=-1,
+                    help="force the full-grid tile-loop setting after tuning (0 off, 1 on; "
+                         "profiling runs)")
     ap.add_argument("--graphs", type=int, default=1)
     ap.add_argument("--prop-only", type=int, default=0,
                     help="run this many forward+adjoint propagation pairs and exit "
@@ -126,6 +129,8 @@ def main():
         ctx.set_option(ssx.OPT_TILE_Z, args.tile_z)
     if args.shot_group >= 0:
         ctx.set_option(ssx.OPT_SHOT_GROUP, args.shot_group)
+    if args.tile_loop >= 0:
+        ctx.set_option(ssx.OPT_TILE_LOOP, args.tile_loop)
     ctx.set_graphs(bool(args.graphs))
     wav = inputs.source_wavelet(prob, wl.freq)
     htrue = np.stack([inputs.spike_gather(prob, wav, s) for s in range(prob.nshots)])
@@ -186,14 +191,14 @@ def main():
     # write p, v_x, v_z once
     b_alg = 6 * fsz + csz
     achieved = b_alg * NZ * NX * prob.nshots / (step_ms * 1e-3) / 1e9
-    tz_used = ctx.tile_z()
-    traffic = measured_traffic(args.config, fd, prob.nshots, tz_used, group,
+    tz_used, _, _, loop_used = ctx.launch_shape()
+    traffic = measured_traffic(args.config, fd, prob.nshots, tz_used, group, loop_used,
                                ctx.step_kernel_name())
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else traffic["bytes_per_launch"],
                 "traffic_detail": traffic,
-                "kernel": ctx.step_kernel_name(), "tile_z": tz_used,
+                "kernel": ctx.step_kernel_name(), "tile_z": tz_used, "tile_loop": loop_used,
                 "us_per_launch": round(step_ms * 1e3 / launches, 3),
                 "launches_per_step": launches, "bytes_per_cell": b_alg,
                 "cells_per_launch": cells}
@@ -276,7 +281,7 @@ def main():
     ctx.close()
 
 
-def measured_traffic(config, fd, nshots, tile_z, group, kernel):
+def measured_traffic(config, fd, nshots, tile_z, group, loop, kernel):
     """HBM bytes per launch of the full-grid step kernel from the committed
     counter profile, when it was taken on the current kernel source with the
     same workload and launch shape; None otherwise."""
@@ -298,7 +303,7 @@ def measured_traffic(config, fd, nshots, tile_z, group, kernel):
     table = json.loads(m.group(1))
     if table.get("kernel_source_sha256") != digest or kernel != "k_step":
         return None
-    e = table["launches"].get(f"{config}|{fd}|shots{nshots}|tz{tile_z}|group{group}")
+    e = table["launches"].get(f"{config}|{fd}|shots{nshots}|tz{tile_z}|group{group}|loop{loop}")
     if e is None:
         return None
     fetch = e["fetch_kib"] * 1024 * table["fetch_scale"]

@@ -214,6 +214,15 @@ ssx_status ssx_pcg_solve(ssx_ctx* ctx, const void* d, double alpha_rel, int32_t 
  *                       traffic fits the last-level cache (176 MiB at 6
  *                       field values and one coefficient per cell).
  *   SSX_OPT_SHOT_GROUP_SLAB the same for the thin slab only.
+ *   SSX_OPT_TILE_LOOP   one-step fused kernel on the full grid: 0
+ *                       (default) one tile per workgroup; 1 one workgroup
+ *                       per tile of the absorbing frame, line rows and grid
+ *                       edges, and for the interior tiles a set of
+ *                       workgroups the device holds at once, each taking
+ *                       tiles in turn and loading the next one while it
+ *                       computes the current one; a value of 8 or more
+ *                       also caps that set at the value rounded down to a
+ *                       multiple of 8.
  * Returns SSX_ERR_ARG for an unknown option or value. */
 typedef enum {
   SSX_OPT_GRAPHS = 0,
@@ -224,7 +233,8 @@ typedef enum {
   SSX_OPT_STEPS_PER_LAUNCH_SLAB = 5,
   SSX_OPT_SHOT_GROUP = 6,
   SSX_OPT_SHOT_GROUP_SLAB = 7,
-  SSX_OPT_SLAB_STRIP = 8
+  SSX_OPT_SLAB_STRIP = 8,
+  SSX_OPT_TILE_LOOP = 9
 } ssx_option;
 ssx_status ssx_set_option(ssx_ctx* ctx, int option, int value);
 
@@ -240,8 +250,9 @@ int64_t ssx_cells_per_launch(ssx_ctx* ctx);
 
 /* Launch shape of the full-grid step as the next propagation will run it:
  * shape[0] tile height, shape[1] time steps per launch, shape[2] shots per
- * launch (options resolved, defaults included).  shape is a host array of
- * three; SSX_ERR_ARG for a null argument. */
+ * launch, shape[3] the tile-loop setting (options resolved, defaults
+ * included).  shape is a host array of four; SSX_ERR_ARG for a null
+ * argument. */
 ssx_status ssx_launch_shape(ssx_ctx* ctx, int32_t* shape);
 
 #ifdef __cplusplus

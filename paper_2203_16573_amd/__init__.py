@@ -35,6 +35,7 @@ PEN_A, PEN_ATA, PEN_DHALF = 0, 1, 2
 OPT_GRAPHS, OPT_STEP_KERNEL, OPT_TILE_Z, OPT_TILE_Z_SLAB = 0, 1, 2, 3
 OPT_STEPS_PER_LAUNCH, OPT_STEPS_PER_LAUNCH_SLAB = 4, 5
 OPT_SHOT_GROUP, OPT_SHOT_GROUP_SLAB, OPT_SLAB_STRIP = 6, 7, 8
+OPT_TILE_LOOP = 9
 
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_CFL", 3: "ERR_OOM", 4: "ERR_HIP",
           5: "ERR_BREAKDOWN", 6: "ERR_NONFINITE"}
@@ -267,8 +268,9 @@ class Context:
         return int(lib().ssx_cells_per_launch(self._ctx))
 
     def launch_shape(self) -> tuple:
-        """(tile height, steps per launch, shots per launch) of the full-grid step."""
-        shape = (ctypes.c_int32 * 3)()
+        """(tile height, steps per launch, shots per launch, tile-loop setting)
+        of the full-grid step."""
+        shape = (ctypes.c_int32 * 4)()
         _check(lib().ssx_launch_shape(self._ctx, shape))
         return tuple(int(v) for v in shape)
 

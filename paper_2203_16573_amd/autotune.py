@@ -18,10 +18,11 @@ import os
 import threading
 
 from . import (OPT_SHOT_GROUP, OPT_SHOT_GROUP_SLAB, OPT_SLAB_STRIP, OPT_STEP_KERNEL,
-               OPT_STEPS_PER_LAUNCH, OPT_STEPS_PER_LAUNCH_SLAB, OPT_TILE_Z, OPT_TILE_Z_SLAB,
+               OPT_STEPS_PER_LAUNCH, OPT_STEPS_PER_LAUNCH_SLAB, OPT_TILE_LOOP, OPT_TILE_Z,
+               OPT_TILE_Z_SLAB,
                Context)
 
-DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ssx", "autotune-v4.json")
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ssx", "autotune-v5.json")
 SLAB_MAXZ = 56  # tallest slab the 4/8-step slab kernel holds
 _lock = threading.Lock()
 
@@ -97,6 +98,9 @@ def tune(prob, kappa, rho, xs=None, field_dtype="f32", nt_tune: int = 60,
     # slab candidates: the same, plus the multi-step slab kernel
     # (steps, strip width) with the tile height of its one-step remainder
     slab_cands = [(spl, tz, 0) for spl, tz in cands]
+    # full-grid candidates: one-step launches also with workgroups looping
+    # over the interior tiles
+    full_cands = [(spl, tz, 0) for spl, tz in cands] + [(1, tz, 1) for spl, tz in cands if spl == 1]
     nzs = abs(short.slab_dz) + 1 + short.order + 2 * short.npml + 1
     if field_dtype != "f64" and nzs <= SLAB_MAXZ:
         slab_cands += [(4, 8, 64), (4, 8, 128), (8, 8, 128)]
@@ -104,11 +108,13 @@ def tune(prob, kappa, rho, xs=None, field_dtype="f32", nt_tune: int = 60,
     ctx.set_option(OPT_STEP_KERNEL, 1)
     ctx.set_option(OPT_SHOT_GROUP, 0)
     auto_group = max(1, ctx.cells_per_launch() // (NZ * NX))
-    for spl, tz in cands:
+    for spl, tz, loop in full_cands:
         ctx.set_option(OPT_TILE_Z, tz)
         ctx.set_option(OPT_STEPS_PER_LAUNCH, spl)
-        us[f"full_s{spl}_tz{tz}"] = 1e3 * _time_ms(full) / (2 * nt)
+        ctx.set_option(OPT_TILE_LOOP, loop)
+        us[f"full_s{spl}_tz{tz}_l{loop}"] = 1e3 * _time_ms(full) / (2 * nt)
     ctx.set_option(OPT_STEPS_PER_LAUNCH, 1)
+    ctx.set_option(OPT_TILE_LOOP, 0)
     for spl, tz, strip in slab_cands:
         ctx.set_option(OPT_TILE_Z_SLAB, tz)
         ctx.set_option(OPT_STEPS_PER_LAUNCH_SLAB, spl)
@@ -120,9 +126,9 @@ def tune(prob, kappa, rho, xs=None, field_dtype="f32", nt_tune: int = 60,
     ctx.set_option(OPT_STEP_KERNEL, 0)
     us["full_split"] = 1e3 * _time_ms(full) / (2 * nt)
     us["slab_split"] = 1e3 * _time_ms(slab) / (2 * nt)
-    best_full = min(cands, key=lambda c: us[f"full_s{c[0]}_tz{c[1]}"])
+    best_full = min(full_cands, key=lambda c: us[f"full_s{c[0]}_tz{c[1]}_l{c[2]}"])
     best_slab = min(slab_cands, key=lambda c: us[f"slab_s{c[0]}_tz{c[1]}_w{c[2]}"])
-    fused_total = us[f"full_s{best_full[0]}_tz{best_full[1]}"] + \
+    fused_total = us[f"full_s{best_full[0]}_tz{best_full[1]}_l{best_full[2]}"] + \
         us[f"slab_s{best_slab[0]}_tz{best_slab[1]}_w{best_slab[2]}"]
     split_total = us["full_split"] + us["slab_split"]
     step_kernel = 1 if fused_total <= split_total else 0
@@ -130,6 +136,7 @@ def tune(prob, kappa, rho, xs=None, field_dtype="f32", nt_tune: int = 60,
     ctx.set_option(OPT_TILE_Z, best_full[1])
     ctx.set_option(OPT_TILE_Z_SLAB, best_slab[1])
     ctx.set_option(OPT_STEPS_PER_LAUNCH, best_full[0])
+    ctx.set_option(OPT_TILE_LOOP, best_full[2])
     ctx.set_option(OPT_STEPS_PER_LAUNCH_SLAB, best_slab[0])
     ctx.set_option(OPT_SLAB_STRIP, best_slab[2])
     group, group_slab = auto_group, 0
@@ -141,7 +148,8 @@ def tune(prob, kappa, rho, xs=None, field_dtype="f32", nt_tune: int = 60,
         group = min(_group_candidates(auto_group, ns), key=lambda x: us[f"full_group{x}"])
     ctx.close()
     return {"step_kernel": step_kernel,
-            "steps_per_launch": best_full[0], "tile_z": best_full[1], "shot_group": group,
+            "steps_per_launch": best_full[0], "tile_z": best_full[1], "tile_loop": best_full[2],
+            "shot_group": group,
             "steps_per_launch_slab": best_slab[0], "tile_z_slab": best_slab[1],
             "slab_strip": best_slab[2], "shot_group_slab": group_slab, "us": us}
 
@@ -176,3 +184,4 @@ def apply(ctx: Context, choice: dict) -> None:
     ctx.set_option(OPT_SHOT_GROUP, int(choice.get("shot_group", 0)))
     ctx.set_option(OPT_SHOT_GROUP_SLAB, int(choice.get("shot_group_slab", 0)))
     ctx.set_option(OPT_SLAB_STRIP, int(choice.get("slab_strip", 0)))
+    ctx.set_option(OPT_TILE_LOOP, int(choice.get("tile_loop", 0)))

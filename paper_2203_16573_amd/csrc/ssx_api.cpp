@@ -245,6 +245,11 @@ struct GridDev {
   Fields fields1;  // buffer 1 (fused kernel writes step n+1 here, then swaps)
   void* field_block;
   size_t field_bytes;
+  // tile lists of the one-step kernel's tile-loop launches, per tile height
+  // 8, 16, 32 (index tz / 16): general tiles, then interior ones
+  std::vector<int> tiles_host[3];
+  int ngen[3] = {0, 0, 0}, nint[3] = {0, 0, 0};
+  int* tiles_dev[3] = {nullptr, nullptr, nullptr};
 };
 
 // A captured propagation: keyed by the operation and every trace pointer it
@@ -252,7 +257,7 @@ struct GridDev {
 struct GraphEntry {
   int op;
   const void* ptr[4];
-  int tile_z, fused, spl, group, strip;
+  int tile_z, fused, spl, group, strip, loop;
   hipGraphExec_t exec;
   unsigned long long last_use;
 };
@@ -282,6 +287,7 @@ struct ssx_ctx {
   int spl_full = 1, spl_slab = 1;        // time steps per fused launch
   int group_full = 0, group_slab = 0;    // shots per launch (0: from the cache budget)
   int slab_strip = 0;                    // strip width of the multi-step slab kernel (0: 128)
+  int loop_full = 0;                     // full-grid one-step kernel: tile loop (0 off)
   hipStream_t cap_stream = nullptr;      // capture stream (graphs are launched on `stream`)
   std::vector<GraphEntry> graphs_cache;
   unsigned long long use_clock = 0;
@@ -316,6 +322,12 @@ void layout(ssx_ctx* c, const GridHost& fg, const GridHost& sg, char* base, size
     gd.fields1.aux = fb ? fb + 7 * one : nullptr;
     gd.coef.ck = a.take((size_t)gh.field_elems * csz);
     gd.coef.pml = a.take((4 * (size_t)gh.pitch + 4 * (size_t)(gh.NZ + 2 * PZ)) * csz);
+    for (int i = 0; i < 3; ++i) {
+      const int tz = 8 << i;
+      const size_t n = (size_t)((gh.NX + step_tile_width() - 1) / step_tile_width()) *
+                       ((gh.NZ + tz - 1) / tz);
+      gd.tiles_dev[i] = (int*)a.take(n * sizeof(int));
+    }
   };
   grid(c->full, fg);
   grid(c->slab, sg);
@@ -349,6 +361,12 @@ ssx_status upload(GridDev& gd, bool dbl, hipStream_t s) {
                            hipMemcpyHostToDevice, s));
     SSX_HIP(hipStreamSynchronize(s));
   }
+  for (int i = 0; i < 3; ++i) {
+    if (gd.tiles_host[i].empty()) continue;
+    SSX_HIP(hipMemcpyAsync(gd.tiles_dev[i], gd.tiles_host[i].data(),
+                           gd.tiles_host[i].size() * sizeof(int), hipMemcpyHostToDevice, s));
+  }
+  SSX_HIP(hipStreamSynchronize(s));
   return SSX_OK;
 }
 
@@ -470,6 +488,13 @@ ssx_status issue_group(ssx_ctx* c, GridDev& gd, bool adj, const Fields& f0, cons
   a.nshots = ns;
   a.nt = nt;
   a.dir = adj ? -1 : 1;
+  // one-step launches on the full grid may loop over tiles (lists built at
+  // context creation for tile heights 8, 16, 32)
+  const int loop = is_full ? c->loop_full : 0;
+  const int li = tz == 8 ? 0 : (tz == 16 ? 1 : 2);
+  a.tiles = loop ? gd.tiles_dev[li] : nullptr;
+  a.ngen = loop ? gd.ngen[li] : 0;
+  a.nint = loop ? gd.nint[li] : 0;
   const int ntz1 = (gd.host.NZ + tz - 1) / tz;
   const int ntz2 = (gd.host.NZ + STEP2_TZ - 1) / STEP2_TZ;
   // multi-step slab kernel: strip width (ns = 8 needs 128 columns)
@@ -508,7 +533,7 @@ ssx_status issue_group(ssx_ctx* c, GridDev& gd, bool adj, const Fields& f0, cons
       a.ps.n = (ps.out && ips >= 0 && ips < nt) ? ips : -1;
       a.pi.n = (pi.in && ipi >= 0 && ipi < nt) ? ipi : -1;
       a.ntz = ntz1;
-      SSX_HIP(launch_step(c->fdt, order, adj, tz, a, s));
+      SSX_HIP(launch_step(c->fdt, order, adj, tz, loop, a, s));
     }
     cur = 1 - cur;
     return SSX_OK;
@@ -615,10 +640,11 @@ ssx_status propagate(ssx_ctx* c, int op, GridDev& gd, bool adj, const LineDev& v
   const int spl = (&gd == &c->full) ? c->spl_full : c->spl_slab;
   const int group = (&gd == &c->full) ? c->group_full : c->group_slab;
   const int strip = (&gd == &c->full) ? 0 : c->slab_strip;
+  const int loop = (&gd == &c->full) ? c->loop_full : 0;
   for (GraphEntry& e : c->graphs_cache) {
     if (e.op == op && e.ptr[0] == key[0] && e.ptr[1] == key[1] && e.ptr[2] == key[2] &&
         e.ptr[3] == key[3] && e.tile_z == tz && e.fused == (int)c->fused && e.spl == spl &&
-        e.group == group && e.strip == strip) {
+        e.group == group && e.strip == strip && e.loop == loop) {
       e.last_use = ++c->use_clock;
       SSX_HIP(hipGraphLaunch(e.exec, c->stream));
       return SSX_OK;
@@ -654,6 +680,7 @@ ssx_status propagate(ssx_ctx* c, int op, GridDev& gd, bool adj, const LineDev& v
   ge.spl = spl;
   ge.group = group;
   ge.strip = strip;
+  ge.loop = loop;
   ge.exec = exec;
   ge.last_use = ++c->use_clock;
   c->graphs_cache.push_back(ge);
@@ -809,6 +836,18 @@ ssx_status ssx_create(const ssx_problem* prob, const double* kappa_host, double 
   make_line(zs, p.x_src0, p.ns, p.h, L, nzs, p.nx, false, &c->f_line, &why);
   make_line(zs + p.slab_dz * p.h, p.x_src0, p.ns, p.h, L, nzs, p.nx, true, &c->dp_line, &why);
   make_line(zs + p.slab_dz * p.h, p.x_src0, p.ns, p.h, L, nzs, p.nx, false, &c->dv_line, &why);
+  // full-grid tile lists for tile-loop launches (its lines: source, receivers)
+  {
+    const LineDev* lines[2] = {&c->h_line, &c->r_line};
+    for (int i = 0; i < 3; ++i) {
+      std::vector<int> gen, inter;
+      step_tile_lists(p.order, 8 << i, c->full.dims, lines, 2, &gen, &inter);
+      c->full.ngen[i] = (int)gen.size();
+      c->full.nint[i] = (int)inter.size();
+      c->full.tiles_host[i] = gen;
+      c->full.tiles_host[i].insert(c->full.tiles_host[i].end(), inter.begin(), inter.end());
+    }
+  }
 
   size_t total = 0;
   layout(c, c->full.host, c->slab.host, nullptr, &total);
@@ -1038,6 +1077,11 @@ ssx_status ssx_set_option(ssx_ctx* c, int option, int value) {
       if (option == SSX_OPT_SHOT_GROUP) c->group_full = value;
       c->group_slab = value;
       return SSX_OK;
+    case SSX_OPT_TILE_LOOP:
+      if (value != 0 && value != 1 && value < 8)
+        return fail(SSX_ERR_ARG, "tile loop must be 0, 1 or at least 8");
+      c->loop_full = value;
+      return SSX_OK;
   }
   return fail(SSX_ERR_ARG, "unknown option");
 }
@@ -1057,6 +1101,7 @@ ssx_status ssx_launch_shape(ssx_ctx* c, int32_t* shape) {
                       : 0;
   shape[1] = c->fused ? c->spl_full : 1;
   shape[2] = shot_group(c, c->full);
+  shape[3] = (c->fused && c->spl_full == 1) ? c->loop_full : 0;
   return SSX_OK;
 }
 

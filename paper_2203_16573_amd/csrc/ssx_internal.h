@@ -8,6 +8,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 namespace ssx {
 
@@ -85,12 +86,28 @@ struct StepArgs {
   int ntx, ntz, nshots;        // tiles across x, down z; shots
   int nt;                      // record length (trace indices outside [0, nt) are skipped)
   int dir;                     // +1 forward, -1 transposed: trace index of level t = n + dir t
+  // tile-loop launches of the one-step kernel: per-shot tile indices
+  // (tz-row * ntx + tx-column), the ngen general tiles first, then the nint
+  // interior ones (see step_tile_lists)
+  const int* tiles;
+  int ngen, nint;
 };
 
 // ---- launchers (ssx_kernels.hip) -----------------------------------------
 // One fused time step (velocity then pressure, one launch).  tz: tile height
-// (8, 16 or 32; 32 is not available for FP64 fields).
-hipError_t launch_step(Dt dt, int order, bool adj, int tz, StepArgs a, hipStream_t s);
+// (8, 16 or 32; 32 is not available for FP64 fields).  loop: 0, one tile
+// per workgroup; else one workgroup per general tile and, for the interior
+// tiles (a.tiles lists), a set of workgroups taking several tiles in turn:
+// as many as the device holds at once (loop = 1), or at most loop rounded
+// down to a multiple of 8 (loop >= 8).
+hipError_t launch_step(Dt dt, int order, bool adj, int tz, int loop, StepArgs a, hipStream_t s);
+// The tiles of one shot of a grid for the one-step kernel with tile height
+// tz, split into those that take the general path (absorbing frame, grid
+// edges, rows of any of the given lines) and the interior ones, each list in
+// row-major tile order.  Lines count as active at every step, so every
+// listed interior tile is interior at every step.
+void step_tile_lists(int order, int tz, const GridDims& g, const LineDev* const* lines,
+                     int nlines, std::vector<int>* gen, std::vector<int>* inter);
 // Two fused time steps per launch (tile height 8; not for F64 fields).
 hipError_t launch_step2(Dt dt, int order, bool adj, StepArgs a, hipStream_t s);
 constexpr int STEP2_TZ = 8;

@@ -24,6 +24,7 @@
 // tile with each thread owning 1 x 4 cells.
 #include "ssx_cell.h"
 
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -160,6 +161,42 @@ constexpr int LDS_PAD_P = 0, LDS_PAD_X = 0, LDS_PAD_Z = 0;
 // for 64 x 32 (each thread owns the same 1 x 4 cells at every height)
 constexpr int step_threads(int tz) { return tz == 32 ? 512 : 256; }
 
+// s_waitcnt operand: vector memory count 0, the other counters unconstrained
+constexpr int VMCNT0 = 0x0F70;
+
+// shape of the fused step's TX x TZ tile and of what it stages
+template <int K, int TZ>
+struct TileShape {
+  static constexpr int NT = step_threads(TZ);
+  static constexpr int R = 2 * K - 1;
+  static constexpr int WP = TX + 2 * HXS;     // staged p columns: x0-8 .. x1+7
+  static constexpr int GP = WP / 4;
+  static constexpr int HP = TZ + 2 * R;       // staged p rows: z0-R .. z1+R-1
+  static constexpr int GVX = TX / 4 + 2;      // v_x groups: x0-4 .. x1+3
+  static constexpr int WVX = 4 * GVX;
+  static constexpr int HVZ = TZ + 2 * K - 1;  // v_z rows: z0-K .. z1+K-2
+  static constexpr int GT = TX / 4;           // groups per tile row
+  // LDS pitches
+  static constexpr int SPP = WP + LDS_PAD_P, SPX = WVX + LDS_PAD_X, SPZ = TX + LDS_PAD_Z;
+  // 4-cell tasks per thread of each phase
+  static constexpr int NQP = (HP * GP + NT - 1) / NT;
+  static constexpr int NQX = (TZ * GVX + NT - 1) / NT;
+  static constexpr int NQZ = (HVZ * GT + NT - 1) / NT;
+  static constexpr int NQT = (TZ * GT + NT - 1) / NT;
+  static constexpr int NQA = (TZ * GP + NT - 1) / NT;
+  // general tiles' staged layer factors (offsets into sF, see step_general)
+  static constexpr int FXH = 0, FXN = 2 * WVX, FZH = FXN + 2 * TX, FZN = FZH + 2 * HVZ;
+  static constexpr int NF = FZN + 2 * TZ;
+};
+
+// an interior tile's loads, held in registers from their issue to the
+// tile's compute phases
+template <int K, int TZ, typename C>
+struct InteriorRegs {
+  using S = TileShape<K, TZ>;
+  C rp[S::NQP][4], rvx[S::NQX][4], rvz[S::NQZ][4], rck[S::NQT][4];
+};
+
 // no row of the line is active in rows [lo, hi)
 __device__ __forceinline__ bool line_clear(const LineDev& l, const TraceIO& io, int lo, int hi) {
   return io.n < 0 || ((l.row0 < lo || l.row0 >= hi) && (l.row1 < lo || l.row1 >= hi));
@@ -173,35 +210,33 @@ __device__ __forceinline__ bool line_clear(const LineDev& l, const TraceIO& io, 
 // path without per-cell tests; it evaluates the same expressions as the
 // general path with a = b = 1 and zero sources, so results are bitwise
 // equal.
-template <int K, int TZ>
-__device__ __forceinline__ bool interior_tile(const StepArgs& a, int x0, int z0) {
-  constexpr int R = 2 * K - 1;
-  const int L = a.g.L, NZ = a.g.NZ, NX = a.g.NX;
-  return z0 - R >= L && z0 + TZ + R <= NZ - L - 1 && x0 - HXS >= L &&
-         x0 + TX + HXS <= NX - L - 1 && line_clear(a.vsl, a.vs, z0 - R, z0 + TZ + R) &&
-         line_clear(a.vil, a.vi, z0 - R, z0 + TZ + R) &&
-         line_clear(a.psl, a.ps, z0 - R, z0 + TZ + R) &&
-         line_clear(a.pil, a.pi, z0 - R, z0 + TZ + R);
+// the absorbing-frame part of the test, and the rows a line must avoid
+__host__ __device__ __forceinline__ bool interior_box(int K, int tz, int L, int NZ, int NX,
+                                                      int x0, int z0) {
+  const int R = 2 * K - 1;
+  return z0 - R >= L && z0 + tz + R <= NZ - L - 1 && x0 - HXS >= L && x0 + TX + HXS <= NX - L - 1;
+}
+__host__ __device__ __forceinline__ int interior_rows_lo(int K, int z0) { return z0 - (2 * K - 1); }
+__host__ __device__ __forceinline__ int interior_rows_hi(int K, int tz, int z0) {
+  return z0 + tz + 2 * K - 1;
 }
 
-template <int K, bool ADJ, typename T, int TZ, typename C>
-__device__ __forceinline__ void step_interior(const StepArgs& a, long long base, int x0, int z0,
-                                              C* __restrict__ sP, C* __restrict__ sVX,
-                                              C* __restrict__ sVZ) {
-  constexpr int NT = step_threads(TZ);
-  constexpr int R = 2 * K - 1;
-  constexpr int WP = TX + 2 * HXS;
-  constexpr int GP = WP / 4;
-  constexpr int HP = TZ + 2 * R;
-  constexpr int GVX = TX / 4 + 2;
-  constexpr int WVX = 4 * GVX;
-  constexpr int HVZ = TZ + 2 * K - 1;
-  constexpr int GT = TX / 4;
-  constexpr int SPP = WP + LDS_PAD_P, SPX = WVX + LDS_PAD_X, SPZ = TX + LDS_PAD_Z;  // LDS pitches
-  constexpr int NQP = (HP * GP + NT - 1) / NT;
-  constexpr int NQX = (TZ * GVX + NT - 1) / NT;
-  constexpr int NQZ = (HVZ * GT + NT - 1) / NT;
-  constexpr int NQT = (TZ * GT + NT - 1) / NT;
+template <int K, int TZ>
+__device__ __forceinline__ bool interior_tile(const StepArgs& a, int x0, int z0) {
+  const int lo = interior_rows_lo(K, z0), hi = interior_rows_hi(K, TZ, z0);
+  return interior_box(K, TZ, a.g.L, a.g.NZ, a.g.NX, x0, z0) && line_clear(a.vsl, a.vs, lo, hi) &&
+         line_clear(a.vil, a.vi, lo, hi) && line_clear(a.psl, a.ps, lo, hi) &&
+         line_clear(a.pil, a.pi, lo, hi);
+}
+
+// An interior tile's global loads (p^n with its halo, the old velocities,
+// ck), issued into registers.
+template <int K, typename T, int TZ, typename C>
+__device__ __forceinline__ void interior_load(const StepArgs& a, long long base, int x0, int z0,
+                                              InteriorRegs<K, TZ, C>& r) {
+  using S = TileShape<K, TZ>;
+  constexpr int NT = S::NT, R = S::R, GP = S::GP, HP = S::HP, GVX = S::GVX, HVZ = S::HVZ;
+  constexpr int GT = S::GT, NQP = S::NQP, NQX = S::NQX, NQZ = S::NQZ, NQT = S::NQT;
   const int P = a.g.pitch;
   const int tid = threadIdx.x;
   const long long o0 = base + (long long)z0 * P + x0;  // element (z0, x0) of this shot
@@ -209,51 +244,66 @@ __device__ __forceinline__ void step_interior(const StepArgs& a, long long base,
   const T* vxA = static_cast<const T*>(a.in.vx) + (o0 - 4);
   const T* vzA = static_cast<const T*>(a.in.vz) + (o0 - (long long)K * P);
   const C* ckA = static_cast<const C*>(a.c.ck) + (a.g.origin + (long long)z0 * P + x0);
-  T* pB = static_cast<T*>(a.out.p) + o0;
-  T* vxB = static_cast<T*>(a.out.vx) + (o0 - 4);
-  T* vzB = static_cast<T*>(a.out.vz) + (o0 - (long long)K * P);
-  const C cb = C(a.c.cb);
-  const C one = C(1), zero = C(0);
-
-  // ---- loads ---------------------------------------------------------------
-  C rp[NQP][4];
 #pragma unroll
   for (int k = 0; k < NQP; ++k) {
     const int q = tid + NT * k;
     if (NT * k + NT - 1 < HP * GP || q < HP * GP) {
       const int rr = q / GP, g = q - rr * GP;
-      ld4(rp[k], at(pA, rr * P + 4 * g));
+      ld4(r.rp[k], at(pA, rr * P + 4 * g));
     }
   }
-  C rvx[NQX][4];
 #pragma unroll
   for (int k = 0; k < NQX; ++k) {
     const int q = tid + NT * k;
     if (NT * k + NT - 1 < TZ * GVX || q < TZ * GVX) {
       const int rr = q / GVX, g = q - rr * GVX;
-      ld4(rvx[k], at(vxA, rr * P + 4 * g));
+      ld4(r.rvx[k], at(vxA, rr * P + 4 * g));
     }
   }
-  C rvz[NQZ][4];
 #pragma unroll
   for (int k = 0; k < NQZ; ++k) {
     const int q = tid + NT * k;
-    if (NT * k + NT - 1 < HVZ * GT || q < HVZ * GT) ld4(rvz[k], at(vzA, (q >> 4) * P + 4 * (q & 15)));
+    if (NT * k + NT - 1 < HVZ * GT || q < HVZ * GT) ld4(r.rvz[k], at(vzA, (q >> 4) * P + 4 * (q & 15)));
   }
-  C rck[NQT][4];
 #pragma unroll
   for (int k = 0; k < NQT; ++k) {
     const int q = tid + NT * k;
-    if (NT * k + NT - 1 < TZ * GT || q < TZ * GT) ld4(rck[k], at(ckA, (q >> 4) * P + 4 * (q & 15)));
+    if (NT * k + NT - 1 < TZ * GT || q < TZ * GT) ld4(r.rck[k], at(ckA, (q >> 4) * P + 4 * (q & 15)));
   }
+}
+
+// An interior tile's compute phases from its loaded registers: stage p^n,
+// then (after the barrier, where after_stage() may issue the next tile's
+// loads) v^{n+1/2} and p^{n+1}.
+template <int K, bool ADJ, typename T, int TZ, typename C, typename F>
+__device__ __forceinline__ void interior_compute(const StepArgs& a, long long base, int x0, int z0,
+                                                 const InteriorRegs<K, TZ, C>& r,
+                                                 C* __restrict__ sP, C* __restrict__ sVX,
+                                                 C* __restrict__ sVZ, F&& after_stage) {
+  using S = TileShape<K, TZ>;
+  constexpr int NT = S::NT, R = S::R, GP = S::GP, HP = S::HP, GVX = S::GVX, HVZ = S::HVZ;
+  constexpr int GT = S::GT, SPP = S::SPP, SPX = S::SPX, SPZ = S::SPZ;
+  constexpr int NQP = S::NQP, NQX = S::NQX, NQZ = S::NQZ, NQT = S::NQT;
+  const int P = a.g.pitch;
+  const int tid = threadIdx.x;
+  const long long o0 = base + (long long)z0 * P + x0;  // element (z0, x0) of this shot
+  T* pB = static_cast<T*>(a.out.p) + o0;
+  T* vxB = static_cast<T*>(a.out.vx) + (o0 - 4);
+  T* vzB = static_cast<T*>(a.out.vz) + (o0 - (long long)K * P);
+  const C cb = C(a.c.cb);
+  const C one = C(1), zero = C(0);
+  const auto& rvx = r.rvx;
+  const auto& rvz = r.rvz;
+  const auto& rck = r.rck;
 
   // ---- stage p^n -------------------------------------------------------------
 #pragma unroll
   for (int k = 0; k < NQP; ++k) {
     const int q = tid + NT * k;
-    if (NT * k + NT - 1 < HP * GP || q < HP * GP) { const int rr = q / GP, g = q - rr * GP; st4(sP + rr * SPP + 4 * g, rp[k]); }
+    if (NT * k + NT - 1 < HP * GP || q < HP * GP) { const int rr = q / GP, g = q - rr * GP; st4(sP + rr * SPP + 4 * g, r.rp[k]); }
   }
   __syncthreads();
+  after_stage();
 
   // ---- v_x on the tile rows, columns x0-4 .. x1+3 ------------------------------
 #pragma unroll
@@ -335,58 +385,21 @@ __device__ __forceinline__ void step_interior(const StepArgs& a, long long base,
   }
 }
 
-template <int K, bool ADJ, typename T, int TZ>
-__global__ __launch_bounds__(step_threads(TZ), 6) void k_step(StepArgs a) {
-  using C = typename Tr<T>::C;
+// A general tile (absorbing frame, lines, grid edges), loads included.
+template <int K, bool ADJ, typename T, int TZ, typename C>
+__device__ __forceinline__ void step_general(const StepArgs& a, int shot, int x0, int z0,
+                                             C* __restrict__ sP, C* __restrict__ sPX,
+                                             C* __restrict__ sVX, C* __restrict__ sVZ,
+                                             C* __restrict__ sF, C* __restrict__ sL) {
   using V = typename Tr<T>::V;
-  constexpr int NT = step_threads(TZ);
-  constexpr int R = 2 * K - 1;
-  constexpr int WP = TX + 2 * HXS;     // staged p columns: x0-8 .. x1+7
-  constexpr int GP = WP / 4;
-  constexpr int HP = TZ + 2 * R;       // staged p rows: z0-R .. z1+R-1
-  constexpr int GVX = TX / 4 + 2;      // v_x groups: x0-4 .. x1+3
-  constexpr int WVX = 4 * GVX;
-  constexpr int HVZ = TZ + 2 * K - 1;  // v_z rows: z0-K .. z1+K-2
-  constexpr int GT = TX / 4;           // groups per tile row
-  constexpr int SPP = WP + LDS_PAD_P, SPX = WVX + LDS_PAD_X, SPZ = TX + LDS_PAD_Z;  // LDS pitches
-  constexpr int NQP = (HP * GP + NT - 1) / NT;
-  constexpr int NQX = (TZ * GVX + NT - 1) / NT;
-  constexpr int NQZ = (HVZ * GT + NT - 1) / NT;
-  constexpr int NQT = (TZ * GT + NT - 1) / NT;
-  constexpr int NQA = (TZ * GP + NT - 1) / NT;
-  static_assert(2 * K - 1 <= HXS && K <= 4, "halo wider than the staged columns");
-  __shared__ __align__(16) C sP[HP * SPP];
-  __shared__ __align__(16) C sPX[ADJ ? TZ * SPP : 4];
-  __shared__ __align__(16) C sVX[TZ * SPX];
-  __shared__ __align__(16) C sVZ[HVZ * SPZ];
-  // general tiles: layer factors and line injections, staged with the
-  // loads so that no global access waits inside the compute phases
-  //   sF: a_h, b_h over the v_x columns x0-4 .. x1+3; a_n, b_n over the
-  //       tile's columns; a_h, b_h over the v_z rows; a_n, b_n over the
-  //       tile's rows
-  //   sL: injected values of the v_z line (rows row0, row1) and of the
-  //       pressure line (rows row0, row1) over the tile's columns
-  constexpr int FXH = 0, FXN = 2 * WVX, FZH = FXN + 2 * TX, FZN = FZH + 2 * HVZ;
-  constexpr int NF = FZN + 2 * TZ;
-  __shared__ __align__(16) C sF[NF];
-  __shared__ __align__(16) C sL[4 * TX];
-
-  // XCD-aware tile index
-  const int nb = gridDim.x, b = blockIdx.x;
-  const int full = nb >> 3, rem = nb & 7, xcd = b & 7;
-  const int t = xcd * full + (xcd < rem ? xcd : rem) + (b >> 3);
-  const int per_shot = a.ntx * a.ntz;
-  const int shot = t / per_shot;
-  const int tt = t - shot * per_shot;
-  const int tzi = tt / a.ntx, txi = tt - tzi * a.ntx;
-  const int x0 = txi * TX, z0 = tzi * TZ;
+  using S = TileShape<K, TZ>;
+  constexpr int NT = S::NT, R = S::R, GP = S::GP, HP = S::HP, GVX = S::GVX, WVX = S::WVX;
+  constexpr int HVZ = S::HVZ, GT = S::GT, SPP = S::SPP, SPX = S::SPX, SPZ = S::SPZ;
+  constexpr int NQP = S::NQP, NQX = S::NQX, NQZ = S::NQZ, NQT = S::NQT, NQA = S::NQA;
+  constexpr int FXH = S::FXH, FXN = S::FXN, FZH = S::FZH, FZN = S::FZN;
   const int x1 = x0 + TX, z1 = z0 + TZ;
   const int NX = a.g.NX, NZ = a.g.NZ, P = a.g.pitch, L = a.g.L;
   const long long base = a.g.origin + (long long)shot * a.g.field_stride;
-  if (interior_tile<K, TZ>(a, x0, z0)) {
-    step_interior<K, ADJ, T, TZ, C>(a, base, x0, z0, sP, sVX, sVZ);
-    return;
-  }
   // ---- general tiles: absorbing frame, lines, grid edges -----------------
   // Same expressions as the interior path, with the layer factors, the
   // frame split and the line terms, and with tile-uniform tests selecting
@@ -699,6 +712,115 @@ __global__ __launch_bounds__(step_threads(TZ), 6) void k_step(StepArgs a) {
           }
         }
       }
+    }
+  }
+}
+
+// XCD-aware tile order: logical index Lg -> tile.  Workgroups are
+// dispatched round-robin over the 8 XCDs and workgroup b takes logical
+// indices congruent to b mod 8, so each XCD receives a contiguous band of
+// tiles, which keeps halo re-reads inside one L2.
+__device__ __forceinline__ int xcd_tile(int Lg, int ntiles) {
+  const int full = ntiles >> 3, rem = ntiles & 7, xcd = Lg & 7;
+  return xcd * full + (xcd < rem ? xcd : rem) + (Lg >> 3);
+}
+
+// Fused one-step kernel.
+//   LOOP = false: one tile per workgroup, the grid covers every tile.
+//   LOOP = true (tile lists in a.tiles): the first nshots * ngen workgroups
+//   take one general tile each; the others, a multiple of 8 no larger than
+//   what the device holds at once, loop over the interior tiles (logical
+//   indices b, b + G, b + 2G, ...) and issue the next tile's loads right
+//   after staging the current one, so that its memory traffic overlaps the
+//   current tile's compute instead of every workgroup loading, computing and
+//   storing in step.  (General tiles stay outside the loop: inside it, their
+//   long path raises register use past the point of spilling.)
+template <int K, bool ADJ, typename T, int TZ, bool LOOP>
+__global__ __launch_bounds__(step_threads(TZ), LOOP ? 4 : 6) void k_step(StepArgs a) {
+  using C = typename Tr<T>::C;
+  using S = TileShape<K, TZ>;
+  static_assert(2 * K - 1 <= HXS && K <= 4, "halo wider than the staged columns");
+  __shared__ __align__(16) C sP[S::HP * S::SPP];
+  __shared__ __align__(16) C sPX[ADJ ? TZ * S::SPP : 4];
+  __shared__ __align__(16) C sVX[TZ * S::SPX];
+  __shared__ __align__(16) C sVZ[S::HVZ * S::SPZ];
+  // general tiles: layer factors and line injections, staged with the
+  // loads so that no global access waits inside the compute phases
+  //   sF: a_h, b_h over the v_x columns x0-4 .. x1+3; a_n, b_n over the
+  //       tile's columns; a_h, b_h over the v_z rows; a_n, b_n over the
+  //       tile's rows
+  //   sL: injected values of the v_z line (rows row0, row1) and of the
+  //       pressure line (rows row0, row1) over the tile's columns
+  __shared__ __align__(16) C sF[S::NF];
+  __shared__ __align__(16) C sL[4 * TX];
+
+  auto base_of = [&](int shot) { return a.g.origin + (long long)shot * a.g.field_stride; };
+  if constexpr (!LOOP) {
+    const int per_shot = a.ntx * a.ntz;
+    const int t = xcd_tile(blockIdx.x, per_shot * a.nshots);
+    const int shot = t / per_shot;
+    const int tt = t - shot * per_shot;
+    const int tzi = tt / a.ntx;
+    const int x0 = (tt - tzi * a.ntx) * TX, z0 = tzi * TZ;
+    if (interior_tile<K, TZ>(a, x0, z0)) {
+      InteriorRegs<K, TZ, C> r;
+      interior_load<K, T, TZ, C>(a, base_of(shot), x0, z0, r);
+      interior_compute<K, ADJ, T, TZ, C>(a, base_of(shot), x0, z0, r, sP, sVX, sVZ, [] {});
+    } else {
+      step_general<K, ADJ, T, TZ, C>(a, shot, x0, z0, sP, sPX, sVX, sVZ, sF, sL);
+    }
+  } else {
+    const int ngen_all = a.nshots * a.ngen, nint_all = a.nshots * a.nint;
+    if ((int)blockIdx.x < ngen_all) {
+      const int idx = xcd_tile(blockIdx.x, ngen_all);
+      const int shot = idx / a.ngen;
+      const int tt = a.tiles[idx - shot * a.ngen];
+      const int tzi = tt / a.ntx;
+      step_general<K, ADJ, T, TZ, C>(a, shot, (tt - tzi * a.ntx) * TX, tzi * TZ, sP, sPX, sVX, sVZ,
+                                     sF, sL);
+      return;
+    }
+    // interior tiles: logical index Li -> (shot, x0, z0); the list entry is
+    // read as constant memory with a uniform index, i.e. by a scalar load (a
+    // vector load here would be waited for right away, and that wait would
+    // also wait for every load in flight)
+    auto locate = [&](int Li, int& shot, int& x0, int& z0) {
+      const int idx = xcd_tile(Li, nint_all);
+      shot = idx / a.nint;
+      const int e = __builtin_amdgcn_readfirstlane(a.ngen + idx - shot * a.nint);
+      const int tt = ((const __attribute__((address_space(4))) int*)a.tiles)[e];
+      const int tzi = tt / a.ntx;
+      x0 = (tt - tzi * a.ntx) * TX;
+      z0 = tzi * TZ;
+    };
+    const int G = (int)gridDim.x - ngen_all;
+    int Li = (int)blockIdx.x - ngen_all, shot, x0, z0;
+    locate(Li, shot, x0, z0);
+    // two register sets: the current tile's loads (staged, then read by its
+    // compute phases) and the next tile's, issued once the current tile is
+    // staged and in flight through its compute.  The first tile's loads are
+    // waited for before the loop (its staging needs them anyway): with them
+    // still in flight on entry, the compiler, merging entry and loop end,
+    // would wait in every iteration as if they were, on the next tile's
+    // loads too.
+    InteriorRegs<K, TZ, C> cur, nxt;
+    interior_load<K, T, TZ, C>(a, base_of(shot), x0, z0, nxt);
+    __builtin_amdgcn_s_waitcnt(VMCNT0);
+    for (;;) {
+      cur = nxt;
+      const int Ln = Li + G;
+      const bool more = Ln < nint_all;
+      int shotn = 0, x0n = 0, z0n = 0;
+      if (more) locate(Ln, shotn, x0n, z0n);
+      interior_compute<K, ADJ, T, TZ, C>(a, base_of(shot), x0, z0, cur, sP, sVX, sVZ, [&] {
+        if (more) interior_load<K, T, TZ, C>(a, base_of(shotn), x0n, z0n, nxt);
+      });
+      if (!more) break;
+      __syncthreads();  // every read of this tile's LDS precedes the next staging
+      Li = Ln;
+      shot = shotn;
+      x0 = x0n;
+      z0 = z0n;
     }
   }
 }
@@ -1024,21 +1146,48 @@ static hipError_t pres_t(const Fields& f, const GridDims& g, const Coef& c, cons
   hipLaunchKernelGGL((k_pres<K, ADJ, T>), grid, dim3(TBX, TBY), 0, s, f, g, c, sl, so, il, io);
   return hipGetLastError();
 }
+#define SSX_HIP_RET(x)                 \
+  do {                                 \
+    const hipError_t e_ = (x);         \
+    if (e_ != hipSuccess) return e_;   \
+  } while (0)
+
 template <int K, bool ADJ, typename T>
-static hipError_t step_t(int tz, const StepArgs& a, hipStream_t s) {
-  const int nb = a.ntx * a.ntz * a.nshots;
+static hipError_t step_t(int tz, int loop, const StepArgs& a, hipStream_t s) {
+  const int ntiles = a.ntx * a.ntz * a.nshots;
+  if (ntiles <= 0) return hipSuccess;
+  // one tile per workgroup; or (loop) one workgroup per general tile plus
+  // a looping set, a multiple of 8 no larger than what the device holds
+  auto go = [&](auto kernel, int threads) -> hipError_t {
+    int nb = ntiles;
+    if (loop) {
+      if (!a.tiles || a.ngen + a.nint != a.ntx * a.ntz) return hipErrorInvalidValue;
+      int dev = 0, cus = 0, occ = 0;
+      SSX_HIP_RET(hipGetDevice(&dev));
+      SSX_HIP_RET(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+      SSX_HIP_RET(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, threads, 0));
+      int cap = std::max(8, cus * std::max(occ, 1) / 8 * 8);
+      if (loop >= 8) cap = std::min(cap, loop / 8 * 8);
+      nb = a.nshots * a.ngen + std::min(a.nshots * a.nint, cap);
+    }
+    hipLaunchKernelGGL(kernel, dim3(nb), dim3(threads), 0, s, a);
+    return hipGetLastError();
+  };
   switch (tz) {
-    case 8: hipLaunchKernelGGL((k_step<K, ADJ, T, 8>), dim3(nb), dim3(step_threads(8)), 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_step<K, ADJ, T, 16>), dim3(nb), dim3(step_threads(16)), 0, s, a); break;
+    case 8:
+      return loop ? go(k_step<K, ADJ, T, 8, true>, step_threads(8))
+                  : go(k_step<K, ADJ, T, 8, false>, step_threads(8));
+    case 16:
+      return loop ? go(k_step<K, ADJ, T, 16, true>, step_threads(16))
+                  : go(k_step<K, ADJ, T, 16, false>, step_threads(16));
     case 32:
       if constexpr (sizeof(T) < 8) {
-        hipLaunchKernelGGL((k_step<K, ADJ, T, 32>), dim3(nb), dim3(step_threads(32)), 0, s, a);
-        break;
+        return loop ? go(k_step<K, ADJ, T, 32, true>, step_threads(32))
+                    : go(k_step<K, ADJ, T, 32, false>, step_threads(32));
       }
       return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 #define SSX_DISPATCH(FN, ...)                                                        \
@@ -1076,8 +1225,28 @@ hipError_t launch_pres(Dt dt, int order, bool adj, const Fields& f, const GridDi
   SSX_DISPATCH(pres_t, f, g, c, sl, so, il, io, nshots, s);
 }
 
-hipError_t launch_step(Dt dt, int order, bool adj, int tz, StepArgs a, hipStream_t s) {
-  SSX_DISPATCH(step_t, tz, a, s);
+void step_tile_lists(int order, int tz, const GridDims& g, const LineDev* const* lines,
+                     int nlines, std::vector<int>* gen, std::vector<int>* inter) {
+  const int K = order / 2;
+  const int ntx = (g.NX + TX - 1) / TX, ntz = (g.NZ + tz - 1) / tz;
+  gen->clear();
+  inter->clear();
+  for (int tzi = 0; tzi < ntz; ++tzi) {
+    const int z0 = tzi * tz, lo = interior_rows_lo(K, z0), hi = interior_rows_hi(K, tz, z0);
+    bool rows_ok = true;
+    for (int i = 0; i < nlines; ++i) {
+      const LineDev& l = *lines[i];
+      if ((l.row0 >= lo && l.row0 < hi) || (l.row1 >= lo && l.row1 < hi)) rows_ok = false;
+    }
+    for (int txi = 0; txi < ntx; ++txi) {
+      const bool in = rows_ok && interior_box(K, tz, g.L, g.NZ, g.NX, txi * TX, z0);
+      (in ? inter : gen)->push_back(tzi * ntx + txi);
+    }
+  }
+}
+
+hipError_t launch_step(Dt dt, int order, bool adj, int tz, int loop, StepArgs a, hipStream_t s) {
+  SSX_DISPATCH(step_t, tz, loop, a, s);
 }
 
 template <int K, bool ADJ, typename T>

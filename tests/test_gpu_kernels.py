@@ -74,6 +74,14 @@ def test_fused_equals_split_bitwise(fd, order, nt, geom):
         fused = run_all(ctx, prob, fd)
         for a, b in zip(split, fused):
             assert np.array_equal(a, b), (fd, order, tz)
+        # workgroups looping over the interior tiles with the next tile's
+        # loads in flight (8 looping workgroups: several tiles each)
+        for loop in (1, 8):
+            ctx.set_option(ssx.OPT_TILE_LOOP, loop)
+            looped = run_all(ctx, prob, fd)
+            for a, b in zip(split, looped):
+                assert np.array_equal(a, b), (fd, order, tz, "tile loop", loop)
+        ctx.set_option(ssx.OPT_TILE_LOOP, 0)
     if fd == "f32":
         ctx.set_option(ssx.OPT_TILE_Z, 16)
         ctx.set_option(ssx.OPT_STEPS_PER_LAUNCH, 2)
@@ -173,17 +181,18 @@ def test_autotune_choice_applies_and_keeps_results():
     print("case autotune wide f32", flush=True)
     kap = kappa(prob)
     choice = autotune.choose(prob, kap, RHO, field_dtype="f32", cache_path=None, nt_tune=20)
-    for key in ("step_kernel", "steps_per_launch", "tile_z", "shot_group",
+    for key in ("step_kernel", "steps_per_launch", "tile_z", "tile_loop", "shot_group",
                 "steps_per_launch_slab", "tile_z_slab", "slab_strip", "shot_group_slab"):
         assert key in choice, key
     assert 1 <= choice["shot_group"] <= 3
     ctx = ssx.Context(prob, kap, RHO, field_dtype="f32")
     ref = run_all(ctx, prob, "f32")
     autotune.apply(ctx, choice)
-    tz, spl, grp = ctx.launch_shape()
+    tz, spl, grp, loop = ctx.launch_shape()
     if choice["step_kernel"] == 1:
         assert (tz, spl) == ((8 if choice["steps_per_launch"] == 2 else choice["tile_z"]),
                              choice["steps_per_launch"])
+        assert loop == (choice["tile_loop"] if spl == 1 else 0)
     assert grp == choice["shot_group"]
     assert ctx.cells_per_launch() == (prob.nz + 20) * (prob.nx + 20) * grp
     for a, b in zip(ref, run_all(ctx, prob, "f32")):
