@@ -37,7 +37,27 @@ struct SlabShape {
   static constexpr int RP = WR + 8;                   // LDS pitch, x-stencil arrays
   static constexpr int ZR = SLAB_MAXZ + 2 * K;        // LDS rows, z-stencil arrays
   static constexpr int G = WR / 4;                    // 4-column groups per row
+  // loads, stores: task q = row q / G, group q % G (consecutive lanes on
+  // consecutive columns), NQ tasks per thread
   static constexpr int NQ = (SLAB_MAXZ * G + SLAB_THREADS - 1) / SLAB_THREADS;
+  // stencil phases.  CONE (64-column strips): wavefront w takes column
+  // group w + NWV k, its lanes the rows, so that a whole wavefront skips a
+  // group outside the columns the remaining steps still need (the cone
+  // that narrows by the step's reach on each side per step).  Otherwise
+  // the load mapping.  CONE pads the v_z and ck rows by 8 columns so that
+  // lanes on consecutive rows hit different LDS banks (there is no room
+  // for that padding in LDS at 128 columns).
+  static constexpr bool CONE = WR == 64;
+  static constexpr int NWV = SLAB_THREADS / 64;
+  static constexpr int NQS = CONE ? (G + NWV - 1) / NWV : NQ;
+  static constexpr int ZP = CONE ? WR + 8 : WR;   // LDS pitch, v_z
+  static constexpr int CKP = CONE ? WR + 8 : WR;  // LDS pitch, ck
+  // CONE: the values sampled on the two lines at each step are kept in LDS
+  // and written after the last step (no global store in flight during the
+  // steps, whose waits for trace loads would otherwise also wait for it:
+  // vector memory operations complete in issue order)
+  static constexpr int NOUT = CONE ? 2 * NS * W : 1;
+  static_assert(!CONE || SLAB_MAXZ <= 64, "one lane per row");
   static_assert(W > 0 && W % 4 == 0, "strip too narrow for the step count");
   static_assert(H <= GX, "halo wider than the ghost columns");
 };
@@ -60,7 +80,8 @@ __global__ __launch_bounds__(SLAB_THREADS) void k_slab(StepArgs a) {
   using V = typename Tr<T>::V;
   using S = SlabShape<K, NS, WR>;
   static_assert(std::is_same<C, float>::value, "FP32 compute only");
-  constexpr int H = S::H, W = S::W, RP = S::RP, G = S::G, NQ = S::NQ;
+  constexpr int H = S::H, W = S::W, RP = S::RP, G = S::G, NQ = S::NQ, NQS = S::NQS;
+  constexpr int ZP = S::ZP, CKP = S::CKP, R = S::R;
   // p: rows -K .. SLAB_MAXZ+K-1, columns -4 .. WR+3
   __shared__ __align__(16) C sp[S::ZR * RP];
   // v_x and the absorbing-layer auxiliary: rows 0 .. SLAB_MAXZ-1, columns
@@ -68,7 +89,7 @@ __global__ __launch_bounds__(SLAB_THREADS) void k_slab(StepArgs a) {
   __shared__ __align__(16) C svx[SLAB_MAXZ * RP];
   __shared__ __align__(16) C sau[SLAB_MAXZ * RP];
   // v_z: rows -K .. SLAB_MAXZ+K-1, columns 0 .. WR-1
-  __shared__ __align__(16) C svz[S::ZR * WR];
+  __shared__ __align__(16) C svz[S::ZR * ZP];
   // absorbing-layer factors: a_n b_n a_h b_h over the region's columns, then
   // over the slab's rows
   __shared__ __align__(16) C spx[4 * WR];
@@ -79,10 +100,12 @@ __global__ __launch_bounds__(SLAB_THREADS) void k_slab(StepArgs a) {
   __shared__ __align__(16) C ssv[2 * WR + 4];
   __shared__ __align__(16) C ssp[2 * WR + 4];
   // ck: rows 0 .. SLAB_MAXZ-1, columns 0 .. WR-1
-  __shared__ __align__(16) C sck[SLAB_MAXZ * WR];
+  __shared__ __align__(16) C sck[SLAB_MAXZ * CKP];
+  // CONE: sampled values, [line (p line, v_z line)][step][owned column]
+  __shared__ C sout[S::NOUT];
   auto P_ = [](int I, int c) { return (I + K) * RP + c + 4; };
   auto X_ = [](int I, int c) { return I * RP + c + 4; };
-  auto Z_ = [](int I, int c) { return (I + K) * WR + c; };
+  auto Z_ = [](int I, int c) { return (I + K) * ZP + c; };
 
   const int NZ = a.g.NZ, NX = a.g.NX, Pt = a.g.pitch, L = a.g.L;
   const int shot = blockIdx.x / a.ntx;
@@ -167,14 +190,25 @@ __global__ __launch_bounds__(SLAB_THREADS) void k_slab(StepArgs a) {
     V* out = static_cast<V*>(io.out) + shot * io.shot_stride + (long long)idx * l.ntr + (J - l.col0);
     *out = V(C(io.scale) * val * dyn);
   };
-  bool onv, onp;
+  // trace values of the injections: CONE issues every step's loads here,
+  // with the strip's (one memory latency per launch); otherwise step 0's
+  // here and step t + 1's at the start of step t
+  bool onv, onp, onvA[NS], onpA[NS];
   C rv = fetch(a.vil, a.vi, a.vi.n, onv);
   C rp = fetch(a.pil, a.pi, a.pi.n, onp);
+  C rvA[NS], rpA[NS];
+  if constexpr (S::CONE) {
+#pragma unroll
+    for (int t = 1; t < NS; ++t) {
+      rvA[t] = fetch(a.vil, a.vi, a.vi.n + a.dir * t, onvA[t]);
+      rpA[t] = fetch(a.pil, a.pi, a.pi.n + a.dir * t, onpA[t]);
+    }
+  }
   // padding rows and columns stay zero
   for (int i = tid; i < S::ZR * RP; i += SLAB_THREADS) sp[i] = C(0);
   for (int i = tid; i < SLAB_MAXZ * RP; i += SLAB_THREADS) svx[i] = C(0);
   for (int i = tid; i < SLAB_MAXZ * RP; i += SLAB_THREADS) sau[i] = C(0);
-  for (int i = tid; i < S::ZR * WR; i += SLAB_THREADS) svz[i] = C(0);
+  for (int i = tid; i < S::ZR * ZP; i += SLAB_THREADS) svz[i] = C(0);
   if (tid < 4 * WR) spx[tid] = fx;
   if (tid < 4 * SLAB_MAXZ) spz[tid] = fz;
   __syncthreads();
@@ -195,21 +229,29 @@ __global__ __launch_bounds__(SLAB_THREADS) void k_slab(StepArgs a) {
       cvt4(v, lau[k]);
       st4(sau + X_(I, c), v);
       cvt4(v, lck[k]);
-      st4(sck + I * WR + c, v);
+      st4(sck + I * CKP + c, v);
     }
   }
   finish(a.vil, a.vi, rv, onv, dynv, ssv);  // step 0
   finish(a.pil, a.pi, rp, onp, dynp, ssp);
   __syncthreads();
 
+  // (CONE: unrolled, so that the per-step trace registers are indexed by
+  // constants)
+  constexpr int TUNROLL = S::CONE ? NS : 1;
+#pragma unroll TUNROLL
   for (int t = 0; t < NS; ++t) {
     const int ivs = a.vs.n + a.dir * t, ips = a.ps.n + a.dir * t;
     // pressure injections of step t (the readers of step t - 1 are past the
     // last barrier), then the trace loads of step t + 1
-    if (t > 0) finish(a.pil, a.pi, rp, onp, dynp, ssp);
-    if (t + 1 < NS) {
-      rv = fetch(a.vil, a.vi, a.vi.n + a.dir * (t + 1), onv);
-      rp = fetch(a.pil, a.pi, a.pi.n + a.dir * (t + 1), onp);
+    if constexpr (S::CONE) {
+      if (t > 0) finish(a.pil, a.pi, rpA[t], onpA[t], dynp, ssp);
+    } else {
+      if (t > 0) finish(a.pil, a.pi, rp, onp, dynp, ssp);
+      if (t + 1 < NS) {
+        rv = fetch(a.vil, a.vi, a.vi.n + a.dir * (t + 1), onv);
+        rp = fetch(a.pil, a.pi, a.pi.n + a.dir * (t + 1), onp);
+      }
     }
 
     // pressure-line sampling (p^n), owned columns
@@ -217,15 +259,32 @@ __global__ __launch_bounds__(SLAB_THREADS) void k_slab(StepArgs a) {
       const int c = H + tid, J = xr + c;
       if (J < NX && J >= a.vsl.col0 && J < a.vsl.col0 + a.vsl.ntr) {
         const C val = C(a.vsl.w0) * sp[P_(a.vsl.row0, c)] + C(a.vsl.w1) * sp[P_(a.vsl.row1, c)];
-        emit(a.vsl, a.vs, ivs, J, val, dynvs);
+        if constexpr (S::CONE)
+          sout[t * W + tid] = val;
+        else
+          emit(a.vsl, a.vs, ivs, J, val, dynvs);
       }
     }
 
+    // columns the remaining steps need: p of this step on [plo, phi), the
+    // velocities on [plo - K, phi + K - 1) (region columns)
+    const int plo = H - (NS - 1 - t) * R, phi = H + W + (NS - 1 - t) * R;
+
     // ---- velocities ----------------------------------------------------------
 #pragma unroll
-    for (int k = 0; k < NQ; ++k) {
-      const int q = tid + SLAB_THREADS * k;
-      const int I = q / G, c = 4 * (q - (q / G) * G), J = xr + c;
+    for (int k = 0; k < NQS; ++k) {
+      int I, c;
+      if constexpr (S::CONE) {
+        const int g = __builtin_amdgcn_readfirstlane((tid >> 6) + S::NWV * k);
+        if (g >= G || 4 * g + 4 <= plo - K || 4 * g >= phi + K - 1) continue;
+        I = tid & 63;
+        c = 4 * g;
+      } else {
+        const int q = tid + SLAB_THREADS * k;
+        I = q / G;
+        c = 4 * (q - (q / G) * G);
+      }
+      const int J = xr + c;
       if (I >= NZ) continue;
       C w[12];  // p (transposed: P~_z + aux) at region columns c-4 .. c+7
 #pragma unroll
@@ -282,22 +341,39 @@ __global__ __launch_bounds__(SLAB_THREADS) void k_slab(StepArgs a) {
     // velocity injections of step t + 1 (read after the next barrier); before
     // the sampling store below, so that waiting for the trace loads does not
     // also wait for that store
-    if (t + 1 < NS) finish(a.vil, a.vi, rv, onv, dynv, ssv);
+    if constexpr (S::CONE) {
+      if (t + 1 < NS) finish(a.vil, a.vi, rvA[t + 1], onvA[t + 1], dynv, ssv);
+    } else {
+      if (t + 1 < NS) finish(a.vil, a.vi, rv, onv, dynv, ssv);
+    }
 
     // v_z-line sampling (v^{n+1/2}), owned columns
     if (a.ps.out && ips >= 0 && ips < a.nt && tid < W) {
       const int c = H + tid, J = xr + c;
       if (J < NX && J >= a.psl.col0 && J < a.psl.col0 + a.psl.ntr) {
         const C val = C(a.psl.w0) * svz[Z_(a.psl.row0, c)] + C(a.psl.w1) * svz[Z_(a.psl.row1, c)];
-        emit(a.psl, a.ps, ips, J, val, dynps);
+        if constexpr (S::CONE)
+          sout[(NS + t) * W + tid] = val;
+        else
+          emit(a.psl, a.ps, ips, J, val, dynps);
       }
     }
 
     // ---- pressure --------------------------------------------------------------
 #pragma unroll
-    for (int k = 0; k < NQ; ++k) {
-      const int q = tid + SLAB_THREADS * k;
-      const int I = q / G, c = 4 * (q - (q / G) * G), J = xr + c;
+    for (int k = 0; k < NQS; ++k) {
+      int I, c;
+      if constexpr (S::CONE) {
+        const int g = __builtin_amdgcn_readfirstlane((tid >> 6) + S::NWV * k);
+        if (g >= G || 4 * g + 4 <= plo || 4 * g >= phi) continue;
+        I = tid & 63;
+        c = 4 * g;
+      } else {
+        const int q = tid + SLAB_THREADS * k;
+        I = q / G;
+        c = 4 * (q - (q / G) * G);
+      }
+      const int J = xr + c;
       if (I >= NZ) continue;
       C w[12];  // v_x at region columns c-4 .. c+7
       ld4(*reinterpret_cast<C(*)[4]>(w), svx + X_(I, c - 4));
@@ -317,7 +393,7 @@ __global__ __launch_bounds__(SLAB_THREADS) void k_slab(StepArgs a) {
       }
       C pc[4], pn[4], au[4], an[4], ck[4], axn[4], bxn[4];
       ld4(pc, sp + P_(I, c));
-      ld4(ck, sck + I * WR + c);
+      ld4(ck, sck + I * CKP + c);
       ld4(au, sau + X_(I, c));
       ld4(axn, spx + c);
       ld4(bxn, spx + WR + c);
@@ -346,6 +422,18 @@ __global__ __launch_bounds__(SLAB_THREADS) void k_slab(StepArgs a) {
       __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
+  }
+
+  // ---- CONE: the sampled values (the same tests as at sampling time) ----------
+  if constexpr (S::CONE) {
+    for (int i = tid; i < 2 * NS * W; i += SLAB_THREADS) {
+      const int line = i / (NS * W), t = (i / W) % NS, col = i % W;
+      const LineDev& l = line ? a.psl : a.vsl;
+      const TraceIO& io = line ? a.ps : a.vs;
+      const int idx = io.n + a.dir * t, J = xr + H + col;
+      if (io.out && idx >= 0 && idx < a.nt && J < NX && J >= l.col0 && J < l.col0 + l.ntr)
+        emit(l, io, idx, J, sout[i], line ? dynps : dynvs);
+    }
   }
 
   // ---- write the owned columns ------------------------------------------------
