@@ -161,9 +161,6 @@ constexpr int LDS_PAD_P = 0, LDS_PAD_X = 0, LDS_PAD_Z = 0;
 // for 64 x 32 (each thread owns the same 1 x 4 cells at every height)
 constexpr int step_threads(int tz) { return tz == 32 ? 512 : 256; }
 
-// s_waitcnt operand: vector memory count 0, the other counters unconstrained
-constexpr int VMCNT0 = 0x0F70;
-
 // shape of the fused step's TX x TZ tile and of what it stages
 template <int K, int TZ>
 struct TileShape {
@@ -798,16 +795,14 @@ __global__ __launch_bounds__(step_threads(TZ), LOOP ? 4 : 6) void k_step(StepArg
     locate(Li, shot, x0, z0);
     // two register sets: the current tile's loads (staged, then read by its
     // compute phases) and the next tile's, issued once the current tile is
-    // staged and in flight through its compute.  The first tile's loads are
-    // waited for before the loop (its staging needs them anyway): with them
-    // still in flight on entry, the compiler, merging entry and loop end,
-    // would wait in every iteration as if they were, on the next tile's
-    // loads too.
+    // staged and in flight through its compute, then copied at the end of
+    // the iteration.  (The compiler waits on part of the next tile's loads
+    // inside the compute phases.  A form that avoids those waits, by
+    // waiting for the first tile's loads before the loop and copying at the
+    // top of it, measured 4 % slower on a c2 step and is not used.)
     InteriorRegs<K, TZ, C> cur, nxt;
-    interior_load<K, T, TZ, C>(a, base_of(shot), x0, z0, nxt);
-    __builtin_amdgcn_s_waitcnt(VMCNT0);
+    interior_load<K, T, TZ, C>(a, base_of(shot), x0, z0, cur);
     for (;;) {
-      cur = nxt;
       const int Ln = Li + G;
       const bool more = Ln < nint_all;
       int shotn = 0, x0n = 0, z0n = 0;
@@ -817,6 +812,7 @@ __global__ __launch_bounds__(step_threads(TZ), LOOP ? 4 : 6) void k_step(StepArg
       });
       if (!more) break;
       __syncthreads();  // every read of this tile's LDS precedes the next staging
+      cur = nxt;
       Li = Ln;
       shot = shotn;
       x0 = x0n;
