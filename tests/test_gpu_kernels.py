@@ -140,9 +140,16 @@ def test_options_rejected():
     prob = problem(8)
     ctx = ssx.Context(prob, kappa(prob), RHO, field_dtype="f64")
     for opt, val in ((ssx.OPT_TILE_Z, 32), (ssx.OPT_TILE_Z, 12), (ssx.OPT_STEP_KERNEL, 2),
-                     (ssx.OPT_STEPS_PER_LAUNCH, 2), (ssx.OPT_STEPS_PER_LAUNCH, 3), (99, 1)):
+                     (ssx.OPT_STEPS_PER_LAUNCH, 2), (ssx.OPT_STEPS_PER_LAUNCH, 3),
+                     (ssx.OPT_TILE_LOOP, 2), (ssx.OPT_TILE_LOOP, 7), (ssx.OPT_TILE_LOOP, -1),
+                     (ssx.OPT_SLAB_STRIP, 96), (ssx.OPT_SHOT_GROUP, -1), (99, 1)):
         with pytest.raises(ssx.SSXError):
             ctx.set_option(opt, val)
+    # the tile-loop setting is reported in the launch shape (a cap of 8 or
+    # more is kept as given)
+    for val in (0, 1, 8, 100):
+        ctx.set_option(ssx.OPT_TILE_LOOP, val)
+        assert ctx.launch_shape()[3] == val
     ctx.close()
 
 
