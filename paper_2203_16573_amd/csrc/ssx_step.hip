@@ -491,38 +491,74 @@ __device__ __forceinline__ void step_general(const StepArgs& a, int shot, int x0
   // factors as 128-bit groups, the z factors one per thread
   // factors, only in a direction in which the tile reaches the layer
   // (half nodes are 1 on [L, N-L-1), nodes on [L, N-L))
+  // Their values are loaded into registers here, together with the fields
+  // (one memory round trip for every load of the tile), and stored to LDS
+  // with the staged p below.
   static_assert(NT >= 2 * GVX + 2 * GT + 2 * HVZ + 2 * TZ, "too few threads for the factors");
   const bool lay_x = x0 - 4 < L || x1 + 4 > NX - L - 1;
   const bool lay_z = z0 - K < L || z1 + K - 1 > NZ - L - 1;
-  if (tid < 2 * GVX) {
-    C f[4] = {C(1), C(1), C(1), C(1)};
-    if (lay_x) ld4(f, pm.xa(tid < GVX ? 2 : 3, x0 - 4 + 4 * (tid < GVX ? tid : tid - GVX)));
-    st4(sF + FXH + 4 * tid, f);
-  } else if (tid < 2 * GVX + 2 * GT) {
-    const int j = tid - 2 * GVX;
-    C f[4] = {C(1), C(1), C(1), C(1)};
-    if (lay_x) ld4(f, pm.xa(j < GT ? 0 : 1, x0 + 4 * (j < GT ? j : j - GT)));
-    st4(sF + FXN + 4 * j, f);
-  } else if (tid < 2 * GVX + 2 * GT + 2 * HVZ) {
-    const int j = tid - 2 * GVX - 2 * GT;
-    sF[FZH + j] = !lay_z ? C(1) : j < HVZ ? *pm.za(2, z0 - K + j) : *pm.za(3, z0 - K + j - HVZ);
-  } else if (tid < 2 * GVX + 2 * GT + 2 * HVZ + 2 * TZ) {
-    const int j = tid - 2 * GVX - 2 * GT - 2 * HVZ;
-    sF[FZN + j] = !lay_z ? C(1) : j < TZ ? *pm.za(0, z0 + j) : *pm.za(1, z0 + j - TZ);
+  // One load per kind and thread, into registers of its own (loads of
+  // different branches into the same registers would each wait for the
+  // last): four x factors (a_h, b_h over the v_x groups, then a_n, b_n over
+  // the tile's groups) or one z factor (a_h, b_h over the v_z rows, then
+  // a_n, b_n over the tile's rows).
+  C fx[4] = {C(1), C(1), C(1), C(1)};
+  C fz = C(1);
+  constexpr int NFX = 2 * GVX + 2 * GT, NFZ = 2 * HVZ + 2 * TZ;
+  // (two independent tests, both values set before either load: written
+  // inside the other branch, a default would wait for the load in flight)
+  const bool fxt = tid < NFX, fzt = tid >= NFX && tid < NFX + NFZ;
+  int fslot;  // sF slot of this thread's x group (fx) or z entry (fz)
+  {
+    const bool h = tid < 2 * GVX;
+    const int j = h ? tid : tid - 2 * GVX;
+    const int n = h ? GVX : GT;  // groups per factor
+    const int which = (h ? 2 : 0) + (j < n ? 0 : 1);
+    const int col = (h ? x0 - 4 : x0) + 4 * (j < n ? j : j - n);
+    if (fxt && lay_x) ld4(fx, pm.xa(which, col));
+    fslot = (h ? FXH : FXN) + 4 * j;
   }
-  // line injections (0 off the line)
-  if ((vil_here || pil_here) && tid < 4 * TX) {
-    const int j = tid >> 6, c = tid & (TX - 1);  // 4 rows of TX values
-    const LineDev& l = j < 2 ? a.vil : a.pil;
-    const TraceIO& io = j < 2 ? a.vi : a.pi;
-    sL[tid] = line_src<C, V>(l, io, (j & 1) ? l.row1 : l.row0, x0 + c, shot);
+  {
+    const int i = tid - NFX;
+    const bool h = i < 2 * HVZ;
+    const int j = h ? i : i - 2 * HVZ;
+    const int n = h ? HVZ : TZ;  // rows per factor
+    const int which = (h ? 2 : 0) + (j < n ? 0 : 1);
+    const int row = (h ? z0 - K : z0) + (j < n ? j : j - n);
+    if (fzt && lay_z) fz = *pm.za(which, row);
+    if (fzt) fslot = (h ? FZH : FZN) + j;
   }
+  // line injections (0 off the line), with the arithmetic of line_src: the
+  // trace value and the field scales are loaded here, the value formed
+  // when it is stored
+  const bool lthread = (vil_here || pil_here) && tid < 4 * TX;
+  const int lj = tid >> 6, lc = tid & (TX - 1);  // 4 rows of TX values
+  const LineDev& ll = lj < 2 ? a.vil : a.pil;
+  const TraceIO& lio = lj < 2 ? a.vi : a.pi;
+  const int lrow = (lj & 1) ? ll.row1 : ll.row0, lcol = x0 + lc;
+  const bool lon = lthread && lio.n >= 0 && (lrow == ll.row0 || lrow == ll.row1) &&
+                   lcol >= ll.col0 && lcol < ll.col0 + ll.ntr;
+  C lraw = C(0), ldyn = C(1);
+  if (lon) {
+    lraw = C(*(static_cast<const V*>(lio.in) + shot * lio.shot_stride + (long long)lio.n * ll.ntr +
+               (lcol - ll.col0)));
+    ldyn = dyn_of<C>(lio, shot);
+  }
+  // field scales of the sampled lines
+  const C dyn_vs = a.vs.n >= 0 ? dyn_of<C>(a.vs, shot) : C(1);
+  const C dyn_ps = a.ps.n >= 0 ? dyn_of<C>(a.ps, shot) : C(1);
 
-  // ---- stage p^n (and P~_x) ----------------------------------------------------
+  // ---- stage p^n (and P~_x), the layer factors and the line values ---------
 #pragma unroll
   for (int k = 0; k < NQP; ++k) {
     const int q = tid + NT * k;
     if (NT * k + NT - 1 < HP * GP || q < HP * GP) { const int rr = q / GP, g = q - rr * GP; st4(sP + rr * SPP + 4 * g, rp[k]); }
+  }
+  if (fxt) st4(sF + fslot, fx);
+  if (fzt) sF[fslot] = fz;
+  if (lthread) {
+    const C w = (lrow == ll.row0 ? C(ll.w0) : C(0)) + (lrow == ll.row1 ? C(ll.w1) : C(0));
+    sL[tid] = lon ? w * (C(lio.scale) * lraw / ldyn) : C(0);
   }
   if constexpr (ADJ) {
     if (use_px) {
@@ -561,7 +597,9 @@ __device__ __forceinline__ void step_general(const StepArgs& a, int shot, int x0
       const int r0 = a.vsl.row0 - z0 + R, r1 = a.vsl.row1 - z0 + R;
       const C val =
           C(a.vsl.w0) * sP[r0 * SPP + tid + HXS] + C(a.vsl.w1) * sP[r1 * SPP + tid + HXS];
-      line_out<C, V>(a.vsl, a.vs, J, shot, val);
+      V* out = static_cast<V*>(a.vs.out) + shot * a.vs.shot_stride + (long long)a.vs.n * a.vsl.ntr +
+               (J - a.vsl.col0);
+      *out = V(C(a.vs.scale) * val * dyn_vs);  // the arithmetic of line_out
     }
   }
 
@@ -649,7 +687,9 @@ __device__ __forceinline__ void step_general(const StepArgs& a, int shot, int x0
     if (J >= a.psl.col0 && J < a.psl.col0 + a.psl.ntr && J < NX) {
       const int r0 = a.psl.row0 - z0 + K, r1 = a.psl.row1 - z0 + K;
       const C val = C(a.psl.w0) * sVZ[r0 * SPZ + tid] + C(a.psl.w1) * sVZ[r1 * SPZ + tid];
-      line_out<C, V>(a.psl, a.ps, J, shot, val);
+      V* out = static_cast<V*>(a.ps.out) + shot * a.ps.shot_stride + (long long)a.ps.n * a.psl.ntr +
+               (J - a.psl.col0);
+      *out = V(C(a.ps.scale) * val * dyn_ps);  // the arithmetic of line_out
     }
   }
 
@@ -771,7 +811,8 @@ __global__ __launch_bounds__(step_threads(TZ), LOOP ? 4 : 6) void k_step(StepArg
     if ((int)blockIdx.x < ngen_all) {
       const int idx = xcd_tile(blockIdx.x, ngen_all);
       const int shot = idx / a.ngen;
-      const int tt = a.tiles[idx - shot * a.ngen];
+      const int e = __builtin_amdgcn_readfirstlane(idx - shot * a.ngen);
+      const int tt = ((const __attribute__((address_space(4))) int*)a.tiles)[e];  // scalar load
       const int tzi = tt / a.ntx;
       step_general<K, ADJ, T, TZ, C>(a, shot, (tt - tzi * a.ntx) * TX, tzi * TZ, sP, sPX, sVX, sVZ,
                                      sF, sL);
