@@ -19,6 +19,10 @@
 //
 // Trace slots use level-0 indices from the host and step t uses n + dir t;
 // indices outside [0, nt) are skipped.
+//
+// Only the columns the remaining steps still need are exact after each step
+// (a cone narrowing by the step's reach on each side); on 64-column strips
+// the stencil phases skip, per wavefront, column groups outside that cone.
 #include "ssx_cell.h"
 
 #include <type_traits>

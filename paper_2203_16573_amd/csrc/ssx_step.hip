@@ -137,8 +137,10 @@ __global__ __launch_bounds__(TBX* TBY) void k_pres(Fields f, GridDims g, Coef cf
 // Fused time step: one launch advances (p, v) by dt on a TX x TZ output tile
 // (all shots in one grid).
 //
-// Every global load of the step (p^n with a halo, the old velocities, ck,
-// the frame auxiliaries) is issued up front into registers.  Then p^n over
+// Every global load of a tile (p^n with a halo, the old velocities, ck, the
+// frame auxiliaries; on general tiles also the layer factors, line trace
+// values and field scales) is issued up front into registers, before the
+// first wait, so that a tile pays one memory round trip.  Then p^n over
 // the tile plus R = 2K-1 rows and 8 columns is staged in LDS; v^{n+1/2} is
 // computed for the tile and the halo the pressure stencil needs (v_x on the
 // tile rows over columns x0-4 .. x1+3, v_z on the tile columns over rows
@@ -150,7 +152,9 @@ __global__ __launch_bounds__(TBX* TBY) void k_pres(Fields f, GridDims g, Coef cf
 //
 // Tiles are ordered so that each XCD receives a contiguous band of tiles
 // (workgroups are dispatched round-robin over the 8 XCDs), which keeps halo
-// re-reads inside one L2.
+// re-reads inside one L2.  A tile-loop form (k_step with LOOP = true) lets
+// each workgroup take several interior tiles in turn, loading the next
+// while computing the current one.
 constexpr int TX = 64;
 constexpr int HXS = 8;  // staged x halo (>= 2K - 1, multiple of 4)
 // padding (floats) added to the LDS row pitch of the staged pressure, v_x
