@@ -26,7 +26,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <type_traits>
+#include <utility>
 
 namespace ssx {
 
@@ -1187,6 +1190,27 @@ static hipError_t pres_t(const Fields& f, const GridDims& g, const Coef& c, cons
   hipLaunchKernelGGL((k_pres<K, ADJ, T>), grid, dim3(TBX, TBY), 0, s, f, g, c, sl, so, il, io);
   return hipGetLastError();
 }
+// Compute units of device dev and workgroups of `threads` threads of
+// `kernel` that one of them holds at once, queried once per kernel and
+// device and then cached (launches in eager mode would otherwise query at
+// every step).
+static hipError_t resident_blocks(const void* kernel, int threads, int dev, int* cus, int* occ) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, std::pair<int, int>> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find({kernel, dev});
+  if (it == cache.end()) {
+    int c = 0, o = 0;
+    hipError_t e = hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, kernel, threads, 0);
+    if (e != hipSuccess) return e;
+    it = cache.emplace(std::make_pair(kernel, dev), std::make_pair(c, o)).first;
+  }
+  *cus = it->second.first;
+  *occ = it->second.second;
+  return hipSuccess;
+}
+
 #define SSX_HIP_RET(x)                 \
   do {                                 \
     const hipError_t e_ = (x);         \
@@ -1205,8 +1229,7 @@ static hipError_t step_t(int tz, int loop, const StepArgs& a, hipStream_t s) {
       if (!a.tiles || a.ngen + a.nint != a.ntx * a.ntz) return hipErrorInvalidValue;
       int dev = 0, cus = 0, occ = 0;
       SSX_HIP_RET(hipGetDevice(&dev));
-      SSX_HIP_RET(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-      SSX_HIP_RET(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, threads, 0));
+      SSX_HIP_RET(resident_blocks(reinterpret_cast<const void*>(kernel), threads, dev, &cus, &occ));
       int cap = std::max(8, cus * std::max(occ, 1) / 8 * 8);
       if (loop >= 8) cap = std::min(cap, loop / 8 * 8);
       nb = a.nshots * a.ngen + std::min(a.nshots * a.nint, cap);
