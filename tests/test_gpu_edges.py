@@ -62,6 +62,18 @@ def test_edge_geometries(case, fd):
         assert rel(d[s], m.fwd(h[s])) < tol
         assert rel(g[s], m.adj(r[s])) < tol
         assert rel(w[s], oracle.precond(m, 1e-3, h[s], s)) < tol
+    # the tile-loop launch (tile lists built for these geometries) gives the
+    # same bits at every tile height
+    for tz in (8, 16) + ((32,) if fd != "f64" else ()):
+        ctx.set_option(ssx.OPT_TILE_Z, tz)
+        ctx.set_option(ssx.OPT_TILE_LOOP, 0)
+        d0 = ctx.fwd(torch.tensor(h, dtype=vdt, device="cuda"), ctx.empty_r()).cpu()
+        g0 = ctx.adj(torch.tensor(r, dtype=vdt, device="cuda"), ctx.empty_s()).cpu()
+        for loop in (1, 8):
+            ctx.set_option(ssx.OPT_TILE_LOOP, loop)
+            d1 = ctx.fwd(torch.tensor(h, dtype=vdt, device="cuda"), ctx.empty_r()).cpu()
+            g1 = ctx.adj(torch.tensor(r, dtype=vdt, device="cuda"), ctx.empty_s()).cpu()
+            assert torch.equal(d0, d1) and torch.equal(g0, g1), (case, fd, tz, loop)
     ctx.close()
 
 
