@@ -37,7 +37,9 @@ class Problem:
     sampled at ``ns`` positions ``x_src0 + k*h``; receivers sit at depth
     ``z_rec`` at ``nr`` positions ``x_rec0 + k*h``.  ``slab_dz`` is the signed
     datum offset (in cells, positive = deeper) of the thin slab that carries
-    the preconditioner.  ``xs`` lists the lateral position of the physical
+    the preconditioner; ``rslab_dz`` the same for the thin slab around the
+    receiver line that carries the data-space weight of the weighted normal
+    equations (0: none).  ``xs`` lists the lateral position of the physical
     point source of each shot (one shot = one subproblem sharing the model).
     """
 
@@ -57,6 +59,7 @@ class Problem:
     nr: int = 0
     slab_dz: int = 5
     xs: tuple = (0.0,)
+    rslab_dz: int = 0
 
     @property
     def nshots(self) -> int:

@@ -15,15 +15,20 @@ Extended Surface Sources" (arXiv 2203.16573) that it follows:
 * ``prop``   forward time stepping and its exact transpose (Operators
              section; Appendix A);
 * ``ops``    F, F^T, the penalty A, the thin-slab preconditioner, the normal
-             operator and Algorithm 1 (Introduction; Accelerated Iterative
-             Inversion; Computing and Symmetrizing Lambda);
+             operator and Algorithm 1, and the weighted normal equations
+             with their data- and model-space weights (Introduction;
+             Accelerated Iterative Inversion; Computing and Symmetrizing
+             Lambda);
 * ``greens`` the closed-form 2D point-source response used as a pin.
 
 Every function is pinned by the CPU tests against facts that do not come
 from this code: the dot-product adjoint test, brute-force dense transposes,
 discrete energy conservation, reciprocity, the closed-form Green's function at
-second-order convergence, the 1D plane-wave amplitudes, polynomial exactness
-of the stencils, dense normal-equation solves and Krylov-subspace optimality.
+second-order convergence, the 1D plane-wave amplitudes (including the
+energy transmission coefficient that the weighted composition reduces to),
+polynomial exactness of the stencils, dense normal-equation solves, the
+gradient of the weighted objective and Krylov-subspace optimality.
 """
 from . import fd, grid, prop, ops, greens  # noqa: F401
-from .ops import Model, pcg, pcg_solve, precond, penalty, dscale, normal  # noqa: F401
+from .ops import (Model, pcg, pcg_solve, precond, penalty, dscale, normal,  # noqa: F401
+                  normal_w, pcg_solve_w)

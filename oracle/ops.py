@@ -18,11 +18,19 @@ TEST INFRASTRUCTURE ONLY -- see the package header.
 * N   = F^T F + alpha^2 A^T A, the Euclidean normal operator of the penalised
         least-squares problem (Operators section, the esisp problem).
 * pcg: Algorithm 1 (standard preconditioned CG, h_0 = 0).
+* N_w = F^T W_d F + alpha^2 A^T W_m A with b = F^T W_d d, the normal
+        equations in the weighted norms (Accelerated Iterative Inversion,
+        the normpart system), W_d the receiver-surface counterpart of W^-1
+        and W_m the symmetrised inverse pressure-to-source operator (the
+        wcomp formula), both on thin slabs.
 
 Readings where the paper is silent or inconsistent are listed with the
 design notes; the ones that change results here are: the Euclidean normal
 equations, alpha = alpha_rel ||F^T d|| / ||d|| with alpha_rel itself inside
-D, and the slab scale s = 4 sign(dz) (the paper's -4 on its own datum side).
+D, and the slab scale s = 4 sign(dz) (the paper's -4 on its own datum side);
+for the weighted system, W_m on the source-side slab with scale sign(dz)
+(positive, and inverse to W^-1 on plane waves) and alpha taken per unit
+length in both the penalty and D.
 """
 from __future__ import annotations
 
@@ -51,34 +59,49 @@ class Model:
         self.h_line = g.p_line(prob.z_src, prob.x_src0, prob.ns)
         self.r_line = g.p_line(prob.z_rec, prob.x_rec0, prob.nr)
         self._slab = None
+        self._rslab = None
 
-    # -- thin slab -----------------------------------------------------------
+    # -- thin slabs ----------------------------------------------------------
+    def _thin_slab(self, z, x0, n, dz):
+        """A thin slab around the line at depth z: physical rows from
+        min(i, i + dz) - k to max(i, i + dz) + k (i the row at or above z,
+        one more row below when z falls between rows, k = order/2), full
+        width, model rows copied from the full model (clamped at its top and
+        bottom), plus the absorbing layer.  Returns (grid, v_z line at z,
+        datum p line at z + dz h, datum v_z line, p line at z); every line
+        has n samples from x0."""
+        prob = self.prob
+        k = prob.order // 2
+        dz = int(dz)
+        if dz == 0:
+            raise ValueError("slab datum offset must be nonzero")
+        i_s = int(math.floor(z / prob.h + 1e-12))
+        i_lo = min(i_s, i_s + dz) - k
+        i_hi = max(i_s, i_s + dz) + k + (1 if z / prob.h - i_s > 1e-12 else 0)
+        rows = np.clip(np.arange(i_lo, i_hi + 1), 0, prob.nz - 1)
+        g = Grid(self.kappa[rows, :], self.rho, prob.h, prob.dt, prob.npml, prob.pml_R,
+                 prob.order)
+        zl = z - i_lo * prob.h
+        zd = zl + dz * prob.h
+        return (g, g.vz_line(zl, x0, n), g.p_line(zd, x0, n), g.vz_line(zd, x0, n),
+                g.p_line(zl, x0, n))
+
     def slab(self):
-        """Slab grid: physical rows from min(z_s, z_s + dz) - k cells to
-        max(...) + k cells (k = order/2), full width, model rows copied from
-        the full model (clamped at its top and bottom), plus the absorbing
-        layer.  Returns (grid, source line on v_z nodes at z_s, datum line on
-        p nodes, datum line on v_z nodes)."""
+        """Source-side slab (datum slab_dz cells from z_s): (grid, source
+        line on v_z nodes at z_s, datum line on p nodes, datum line on v_z
+        nodes)."""
         if self._slab is None:
-            prob = self.prob
-            k = prob.order // 2
-            dz = int(prob.slab_dz)
-            if dz == 0:
-                raise ValueError("slab datum offset must be nonzero")
-            i_s = int(math.floor(prob.z_src / prob.h + 1e-12))
-            i_lo = min(i_s, i_s + dz) - k
-            i_hi = max(i_s, i_s + dz) + k + (1 if prob.z_src / prob.h - i_s > 1e-12 else 0)
-            rows = np.clip(np.arange(i_lo, i_hi + 1), 0, prob.nz - 1)
-            kap = self.kappa[rows, :]
-            g = Grid(kap, self.rho, prob.h, prob.dt, prob.npml, prob.pml_R,
-                     prob.order)
-            zs = prob.z_src - i_lo * prob.h
-            zd = zs + dz * prob.h
-            f_line = g.vz_line(zs, prob.x_src0, prob.ns)
-            d_p = g.p_line(zd, prob.x_src0, prob.ns)
-            d_v = g.vz_line(zd, prob.x_src0, prob.ns)
-            self._slab = (g, f_line, d_p, d_v)
-        return self._slab
+            p = self.prob
+            self._slab = self._thin_slab(p.z_src, p.x_src0, p.ns, p.slab_dz)
+        return self._slab[:4]
+
+    def rslab(self):
+        """Receiver-side slab (datum rslab_dz cells from z_r), the same four
+        items for the receiver positions."""
+        if self._rslab is None:
+            p = self.prob
+            self._rslab = self._thin_slab(p.z_rec, p.x_rec0, p.nr, p.rslab_dz)
+        return self._rslab[:4]
 
     # -- F and F^T -----------------------------------------------------------
     def fwd(self, h):
@@ -116,6 +139,32 @@ class Model:
         s X^T J X g with J (P, V) = (V, P)."""
         P, V = self.slab_fwd(g)
         return self.slab_scale() * self.slab_adj(V, P)
+
+    # -- weights of the weighted normal equations -----------------------------
+    def wd(self, r):
+        """Data-space weight W_d~ = s_r X_r^T J X_r r: the symmetrised
+        pressure-to-source operator of the receiver surface, computed like
+        W^-1 on the receiver-side slab (normal load on z_r, datum rslab_dz
+        cells away), s_r = 4 sign(rslab_dz).  r [nt][nr] -> [nt][nr]."""
+        g, f_line, d_p, d_v = self.rslab()
+        nt = self.prob.nt
+        P, V = forward(g, nt, f_src=(f_line, r), rec_p=d_p, rec_v=d_v)
+        _, fb = adjoint(g, nt, f_line=f_line, rec_p=(d_p, V), rec_v=(d_v, P))
+        return 4.0 * math.copysign(1.0, self.prob.rslab_dz) * fb
+
+    def wm(self, x):
+        """Model-space weight W_m~, the symmetrised source-to-pressure
+        operator: the source-side slab driven by a pressure source on z_s
+        instead of a normal load, with the same exchange J of datum
+        pressure and velocity, read back from the pressure-source slot;
+        scaled by sign(slab_dz) so that it is positive and inverse to W^-1
+        on laterally uniform input.  x [nt][ns] -> [nt][ns]."""
+        self.slab()
+        g, _, d_p, d_v, p_line = self._slab
+        nt = self.prob.nt
+        P, V = forward(g, nt, h_src=(p_line, x), rec_p=d_p, rec_v=d_v)
+        hb, _ = adjoint(g, nt, h_line=p_line, rec_p=(d_p, V), rec_v=(d_v, P))
+        return math.copysign(1.0, self.prob.slab_dz) * hb
 
 
 # ----------------------------------------------------------------------------
@@ -209,3 +258,40 @@ def pcg_solve(model: Model, d, alpha_rel: float, K: int, use_precond: bool = Tru
             return r.copy()
     h, hist = pcg(apply_N, apply_Minv, b, K, d_misfit=d)
     return h, hist, alpha
+
+
+# ----------------------------------------------------------------------------
+# the weighted normal equations (Accelerated Iterative Inversion: the
+# normpart system with S* = S^T W_d and A* = A^T W_m; the weights replaced by
+# their thin-slab approximations of Computing and Symmetrizing Lambda)
+
+def normal_w(model: Model, alpha: float, p, shot: int = 0):
+    """N_w p = F^T W_d~ F p + alpha^2 A^T W_m~ A p; also returns F p.  The
+    model-space term is left out when alpha is zero."""
+    prob = model.prob
+    Fp = model.fwd(p)
+    q = model.adj(model.wd(Fp))
+    if alpha != 0.0:
+        q = q + alpha * alpha * penalty(prob, model.wm(penalty(prob, p, shot)), shot)
+    return q, Fp
+
+
+def pcg_solve_w(model: Model, d, alpha: float, K: int, use_precond: bool = True,
+                shot: int = 0):
+    """The weighted subproblem solve for one shot: b = F^T W_d~ d, K
+    iterations of Algorithm 1 on N_w h = b with M^-1 = D W^-1 D, where the
+    same alpha (per unit length, the weighted norms making F nearly unitary)
+    sets both the penalty and D; M = I when use_precond is false."""
+    b = model.adj(model.wd(d))
+
+    def apply_N(p):
+        return normal_w(model, alpha, p, shot)
+
+    if use_precond:
+        def apply_Minv(r):
+            return precond(model, alpha, r, shot)
+    else:
+        def apply_Minv(r):
+            return r.copy()
+    h, hist = pcg(apply_N, apply_Minv, b, K, d_misfit=d)
+    return h, hist

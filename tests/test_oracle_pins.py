@@ -20,10 +20,10 @@ RHO = 1000.0
 
 
 def tiny_problem(order=4, nz=12, nx=16, L=4, nt=24, h=10.0, dt=1e-3,
-                 z_src=35.0, z_rec=80.0, ns=8, nr=10, slab_dz=3, xs=(52.0,)):
+                 z_src=35.0, z_rec=80.0, ns=8, nr=10, slab_dz=3, xs=(52.0,), rslab_dz=2):
     return inputs.Problem(nz=nz, nx=nx, h=h, dt=dt, nt=nt, order=order, npml=L,
                           z_src=z_src, x_src0=2 * h, ns=ns, z_rec=z_rec,
-                          x_rec0=h, nr=nr, slab_dz=slab_dz, xs=xs)
+                          x_rec0=h, nr=nr, slab_dz=slab_dz, xs=xs, rslab_dz=rslab_dz)
 
 
 def tiny_kappa(prob, seed=0):
@@ -446,3 +446,145 @@ def test_penalty_and_dscale_closed_form():
     for k in range(prob.ns):
         xk = prob.x_src0 + k * prob.h
         assert abs(D[k] - (1 + (0.01 * (xk - 47.0)) ** 2) ** -0.5) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# P11: the weighted normal equations (Accelerated Iterative Inversion: the
+# normpart system, S* = S^T W_d, A* = A^T W_m; Computing and Symmetrizing
+# Lambda: W_m^-1 by the winvcomp formula, "a similar definition" for W_d, and
+# W_m by the wcomp formula, all on thin slabs)
+
+def _two_layer(h, dz=5, rdz=-5, c1=2000.0, c2=2500.0, order=4):
+    # source line at 150 m in c1, receiver line at 400 m in c2 (interface at
+    # 250 m), the receiver line 50 m short of either edge
+    nz, nx = int(600 / h), int(2000 / h) + 1
+    dt = 0.2 * h / c2
+    vel = np.full((nz, nx), c1)
+    vel[int(250 / h):, :] = c2
+    prob = inputs.Problem(nz=nz, nx=nx, h=h, dt=dt, nt=int(0.5 / dt), order=order,
+                          npml=20, z_src=150.0, x_src0=0.0, ns=nx, z_rec=400.0,
+                          x_rec0=50.0, nr=nx - int(100 / h), slab_dz=dz, xs=(1000.0,),
+                          rslab_dz=rdz)
+    return prob, oracle.Model(prob, inputs.kappa_from_velocity(vel, RHO), RHO)
+
+
+def _weight_plane_errors(h, dz, rdz, f=10.0, c1=2000.0, c2=2500.0):
+    prob, m = _two_layer(h, dz, rdz, c1, c2)
+    w = inputs.ricker((np.arange(prob.nt) + 0.5) * prob.dt, f)
+    jr = int(round((1000.0 - prob.x_rec0) / prob.h))
+    wd = m.wd(np.repeat(w[:, None], prob.nr, axis=1))[:, jr]
+    wm = m.wm(np.repeat(w[:, None], prob.ns, axis=1))[:, prob.ns // 2]
+    ed = np.abs(wd - 2.0 / (RHO * c2) * w).max() / (2.0 / (RHO * c2) * np.abs(w).max())
+    em = np.abs(wm - 0.5 * RHO * c1 * w).max() / (0.5 * RHO * c1 * np.abs(w).max())
+    return ed, em
+
+
+@pytest.mark.parametrize("dz,rdz", [(5, -5), (-5, 5)])
+def test_plane_wave_weights(dz, rdz):
+    # On laterally uniform input a downgoing plane wave has p = rho c v_z, so
+    # the pressure-to-source operator of a surface is 2/(rho c) at that
+    # surface and its inverse rho c/2.  W_d must take the impedance at the
+    # receiver depth, W_m the one at the source depth (the model has a
+    # different velocity at each), at second order in h, for either datum side.
+    ed10, em10 = _weight_plane_errors(10.0, dz, rdz)
+    ed5, em5 = _weight_plane_errors(5.0, dz, rdz)
+    assert ed5 < 0.01 and em5 < 0.01
+    assert math.log2(ed10 / ed5) > 1.7
+    assert math.log2(em10 / em5) > 1.7
+
+
+@pytest.mark.slow
+def test_weighted_composition_is_energy_transmission():
+    # Approximate unitarity (the wunitary relation): W_m^-1 F^T W_d F ~ I.  For
+    # a plane wave crossing one interface between the source and receiver
+    # surfaces it is exactly the energy transmission coefficient
+    # 4 Z1 Z2 / (Z1 + Z2)^2 (F scales by Z1 Z2 / (Z1 + Z2), the weights by
+    # 2 / Z2 and 2 / Z1), approached at second order in h.
+    c1, c2, f = 2000.0, 2500.0, 10.0
+    Z1, Z2 = RHO * c1, RHO * c2
+    T = 4.0 * Z1 * Z2 / (Z1 + Z2) ** 2
+    errs = []
+    for h in (10.0, 5.0):
+        prob, m = _two_layer(h, 5, -5, c1, c2)
+        w = inputs.ricker((np.arange(prob.nt) + 0.5) * prob.dt, f)
+        x = np.repeat(w[:, None], prob.ns, axis=1)
+        y = m.winv(m.adj(m.wd(m.fwd(x))))[:, prob.ns // 2]
+        errs.append(np.abs(y - T * w).max() / (T * np.abs(w).max()))
+    assert errs[1] < 0.03
+    assert math.log2(errs[0] / errs[1]) > 1.7
+
+
+def test_weights_symmetric():
+    # both weights are symmetric by construction (the exchange J is symmetric
+    # and the adjoint sweep is the exact transpose)
+    prob = tiny_problem(nz=16, nx=20, L=5, nt=30, ns=16, nr=14, slab_dz=3, rslab_dz=-2,
+                        z_src=50.0, z_rec=120.0)
+    m = oracle.Model(prob, tiny_kappa(prob, 31), RHO)
+    rng = np.random.default_rng(12)
+    for op, n in ((m.wd, prob.nr), (m.wm, prob.ns)):
+        x = rng.standard_normal((prob.nt, n))
+        y = rng.standard_normal((prob.nt, n))
+        Wx, Wy = op(x), op(y)
+        assert Wx.shape == x.shape
+        err = abs(np.sum(x * Wy) - np.sum(Wx * y)) / (np.linalg.norm(Wx) * np.linalg.norm(y))
+        assert err < 1e-13
+
+
+def _weighted_system():
+    prob = tiny_problem(nt=20, ns=8, nr=10, xs=(47.0,), rslab_dz=-2)
+    m = oracle.Model(prob, tiny_kappa(prob, 29), RHO)
+    d = np.random.default_rng(15).standard_normal((prob.nt, prob.nr))
+    # an alpha that makes the two terms of N_w comparable on this grid, whose
+    # short record lets little of F reach the receivers
+    alpha = 2e-4
+    return prob, m, d, alpha
+
+
+def test_weighted_normal_is_gradient_of_weighted_objective():
+    # N_w h - b_w is the gradient of
+    #   J(h) = 1/2 <F h - d, W_d (F h - d)> + alpha^2/2 <A h, W_m A h>
+    # (the einv objective in the weighted norms), checked by central
+    # differences, which are exact for a quadratic up to rounding.
+    prob, m, d, alpha = _weighted_system()
+
+    def J(h):
+        e = m.fwd(h) - d
+        Ah = oracle.penalty(prob, h)
+        return 0.5 * np.sum(e * m.wd(e)) + 0.5 * alpha ** 2 * np.sum(Ah * m.wm(Ah))
+
+    rng = np.random.default_rng(16)
+    b = m.adj(m.wd(d))
+    for h in (np.zeros((prob.nt, prob.ns)), rng.standard_normal((prob.nt, prob.ns))):
+        Nh, Fh = oracle.normal_w(m, alpha, h)
+        assert np.array_equal(Fh, m.fwd(h))
+        for _ in range(2):
+            u = rng.standard_normal(h.shape)
+            fd_dir = 0.5 * (J(h + u) - J(h - u))
+            an_dir = np.sum((Nh - b) * u)
+            assert abs(fd_dir - an_dir) <= 1e-9 * (abs(fd_dir) + abs(J(h)) + abs(J(u)))
+    # both terms matter at this alpha
+    h = rng.standard_normal((prob.nt, prob.ns))
+    q0, _ = oracle.normal_w(m, 0.0, h)
+    q1, _ = oracle.normal_w(m, alpha, h)
+    assert 0.1 < np.linalg.norm(q1 - q0) / np.linalg.norm(q0) < 10.0
+
+
+def test_weighted_pcg_iterates_are_krylov_projections():
+    # pcg_solve_w runs Algorithm 1 on N_w h = F^T W_d d with M^-1 = D W^-1 D
+    # at alpha_hat = alpha: its iterates are the Galerkin solutions on the
+    # Krylov spaces of the dense operators (plain CG with M = I likewise)
+    prob, m, d, alpha = _weighted_system()
+    shp = (prob.nt, prob.ns)
+    n = prob.nt * prob.ns
+    Nw = dense(lambda p: oracle.normal_w(m, alpha, p)[0], n, shp)
+    assert np.abs(Nw - Nw.T).max() <= 1e-12 * np.abs(Nw).max()
+    Minv = dense(lambda r: oracle.precond(m, alpha, r), n, shp)
+    b = m.adj(m.wd(d)).ravel()
+    for k in (1, 2, 3):
+        hk, hist = oracle.pcg_solve_w(m, d, alpha, k)
+        ref = _krylov_minimiser(Nw, Minv, b, k)
+        assert np.linalg.norm(hk.ravel() - ref) <= 1e-9 * np.linalg.norm(ref), k
+        assert abs(hist[-1, 3] - np.linalg.norm(m.fwd(hk) - d)) <= 1e-12 * np.linalg.norm(d)
+        hk, _ = oracle.pcg_solve_w(m, d, alpha, k, use_precond=False)
+        ref = _krylov_minimiser(Nw, np.eye(n), b, k)
+        assert np.linalg.norm(hk.ravel() - ref) <= 1e-9 * np.linalg.norm(ref), k
