@@ -13,7 +13,10 @@
  *        symmetrised pressure-to-source operator (eqns defprecond,
  *        winvcomp, lamnear);
  *   and Algorithm 1 (preconditioned CG) on N h = F^T d,
- *   N = F^T F + alpha^2 A^T A (the penalised problem esisp).
+ *   N = F^T F + alpha^2 A^T A (the penalised problem esisp);
+ *   and the same in the weighted norms of the Accelerated Iterative
+ *   Inversion section: N_w h = F^T W_d d, N_w = F^T W_d F + alpha^2 A^T W_m A
+ *   (the normpart system), W_d and W_m thin-slab weights.
  *
  * Discretisation: 2D staggered grid (p on nodes, v_x and v_z on half
  * nodes), order 2 in time and 4 or 8 in space, split-field PML of npml
@@ -81,6 +84,10 @@ typedef enum {
  * and differ in their physical point x_s (given to ssx_create) and data.
  * field_dtype: wavefield storage (F64, F32, F16, BF16); vec_dtype: traces
  * and Krylov vectors, which must be F64 for F64 fields and F32 otherwise.
+ * rslab_dz: signed offset, in cells, of the datum of a second thin slab
+ * around the receiver line (positive = deeper), which carries the
+ * data-space weight W_d of the weighted entry points; 0 leaves that slab
+ * out (the weighted entry points then return SSX_ERR_ARG).
  */
 typedef struct {
   int32_t nz, nx;
@@ -97,6 +104,7 @@ typedef struct {
   int32_t nshots;
   int32_t field_dtype;  /* ssx_dtype */
   int32_t vec_dtype;    /* ssx_dtype */
+  int32_t rslab_dz;     /* 0: no receiver-side slab */
 } ssx_problem;
 
 /* Host-only check of a problem and model (no device work).  Rejects:
@@ -183,6 +191,42 @@ ssx_status ssx_dot(ssx_ctx* ctx, const void* x, const void* y, int64_t n,
 ssx_status ssx_pcg_solve(ssx_ctx* ctx, const void* d, double alpha_rel, int32_t maxit,
                          double rtol, int32_t use_precond, void* h_out,
                          double* hist_host, int32_t* iters_host);
+
+/* ---- weighted normal equations (Accelerated Iterative Inversion, the
+ * normpart system S* = S^T W_d, A* = A^T W_m; weights of Computing and
+ * Symmetrizing Lambda).  All return SSX_ERR_ARG when the context was
+ * created with rslab_dz == 0. */
+
+/* y = W_d r: the symmetrised pressure-to-source operator of the receiver
+ * surface (the "similar definition" beside eqn winvcomp), computed like
+ * W^-1 on the receiver-side slab: normal load on z_rec, pressure and normal
+ * velocity recorded on the datum z_rec + rslab_dz h, exchanged, and the
+ * transposed sweep read from the normal-load slot, scaled by
+ * 4 sign(rslab_dz).  Two slab simulations.  r, y: [nshots][nt][nr]. */
+ssx_status ssx_weight_d(ssx_ctx* ctx, const void* r, void* y);
+
+/* y = W_m x: the symmetrised inverse pressure-to-source operator (eqn wcomp)
+ * on the source-side slab: a pressure source on z_src instead of a normal
+ * load, the same exchange on the datum, read back from the pressure-source
+ * slot and scaled by sign(slab_dz), so that W_m is positive and inverse to
+ * W^-1 on laterally uniform input.  Two slab simulations.
+ * x, y: [nshots][nt][ns]. */
+ssx_status ssx_weight_m(ssx_ctx* ctx, const void* x, void* y);
+
+/* q = N_w p = F^T W_d F p + alpha^2 A^T W_m A p, and Fp = F p if Fp is not
+ * NULL (the W_m term is skipped when alpha == 0).  p, q: [nshots][nt][ns];
+ * Fp: [nshots][nt][nr]. */
+ssx_status ssx_normal_w(ssx_ctx* ctx, double alpha, const void* p, void* q, void* Fp);
+
+/* Algorithm 1 on N_w h = F^T W_d d for every shot, as ssx_pcg_solve except
+ * that alpha (per metre, the weighted norms making F nearly unitary) is
+ * used as given, both in N_w and as alpha_hat of M^-1 = D W^-1 D (eqn
+ * defprecond); use_precond == 0 runs M = I.  hist rows as in ssx_pcg_solve
+ * (||r_k||, ||g_k||, <g_k, r_k>, ||F h_k - d||); ||g_k|| with M^-1 applied
+ * is the normal residual of the norm1 form.  Same return codes. */
+ssx_status ssx_pcg_solve_w(ssx_ctx* ctx, const void* d, double alpha, int32_t maxit,
+                           double rtol, int32_t use_precond, void* h_out,
+                           double* hist_host, int32_t* iters_host);
 
 /* Execution options (results do not depend on them, see each value):
  *   SSX_OPT_GRAPHS      1 (default): replay each whole propagation as a

@@ -14,11 +14,15 @@ Function names follow the C ABI (include/ssx.h):
     ctx.penalty(op, a, x, y)
     ctx.precond(alpha_hat, r, g)
     ctx.normal(alpha, p, q, Fp=None)
-    ctx.pcg_solve(d, alpha_rel, maxit, ...) -> (h, hist, iters)
+    ctx.pcg_solve(d, alpha_rel, maxit, ...) -> (h, hist, iters, status)
+    ctx.weight_d(r, y)     y = W_d r   (receiver-side slab)
+    ctx.weight_m(x, y)     y = W_m x   (source-side slab)
+    ctx.normal_w(alpha, p, q, Fp=None)
+    ctx.pcg_solve_w(d, alpha, maxit, ...) -> (h, hist, iters, status)
 
 ``prob`` is any object with the fields of ``ssx_problem`` (nz, nx, h, dt,
-nt, order, npml, pml_R, z_src, x_src0, ns, z_rec, x_rec0, nr, slab_dz);
-the number of shots is ``len(xs)``.
+nt, order, npml, pml_R, z_src, x_src0, ns, z_rec, x_rec0, nr, slab_dz and,
+optionally, rslab_dz); the number of shots is ``len(xs)``.
 """
 from __future__ import annotations
 
@@ -43,7 +47,8 @@ STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_CFL", 3: "ERR_OOM", 4: "ERR_HIP",
 EXPORTS = ("ssx_validate", "ssx_footprint", "ssx_create", "ssx_destroy", "ssx_fwd",
            "ssx_adj", "ssx_slab_fwd", "ssx_slab_adj", "ssx_penalty", "ssx_precond",
            "ssx_normal", "ssx_dot", "ssx_pcg_solve", "ssx_set_option", "ssx_last_error",
-           "ssx_step_kernel_name", "ssx_cells_per_launch", "ssx_launch_shape")
+           "ssx_step_kernel_name", "ssx_cells_per_launch", "ssx_launch_shape",
+           "ssx_weight_d", "ssx_weight_m", "ssx_normal_w", "ssx_pcg_solve_w")
 
 
 class SSXError(RuntimeError):
@@ -61,7 +66,8 @@ class ssx_problem(ctypes.Structure):
                 ("ns", ctypes.c_int32), ("z_rec", ctypes.c_double),
                 ("x_rec0", ctypes.c_double), ("nr", ctypes.c_int32),
                 ("slab_dz", ctypes.c_int32), ("nshots", ctypes.c_int32),
-                ("field_dtype", ctypes.c_int32), ("vec_dtype", ctypes.c_int32)]
+                ("field_dtype", ctypes.c_int32), ("vec_dtype", ctypes.c_int32),
+                ("rslab_dz", ctypes.c_int32)]
 
 
 _lib = None
@@ -97,6 +103,10 @@ def lib():
         L.ssx_dot.argtypes = [vp, vp, vp, ctypes.c_int64, dp]
         L.ssx_pcg_solve.argtypes = [vp, vp, c_dbl, ctypes.c_int32, c_dbl, ctypes.c_int32,
                                     vp, dp, ctypes.POINTER(ctypes.c_int32)]
+        L.ssx_weight_d.argtypes = [vp, vp, vp]
+        L.ssx_weight_m.argtypes = [vp, vp, vp]
+        L.ssx_normal_w.argtypes = [vp, c_dbl, vp, vp, vp]
+        L.ssx_pcg_solve_w.argtypes = L.ssx_pcg_solve.argtypes
         L.ssx_set_option.argtypes = [vp, c_int, c_int]
         L.ssx_last_error.restype = ctypes.c_char_p
         L.ssx_step_kernel_name.argtypes = [vp]
@@ -121,7 +131,8 @@ def make_problem(prob, nshots: int, field_dtype: str = "f32") -> ssx_problem:
                        int(prob.nt), int(prob.order), int(prob.npml), float(prob.pml_R),
                        float(prob.z_src), float(prob.x_src0), int(prob.ns),
                        float(prob.z_rec), float(prob.x_rec0), int(prob.nr),
-                       int(prob.slab_dz), int(nshots), fd, vd)
+                       int(prob.slab_dz), int(nshots), fd, vd,
+                       int(getattr(prob, "rslab_dz", 0)))
 
 
 def _dptr(a: np.ndarray):
@@ -241,19 +252,47 @@ class Context:
                              self._vec(y, x.numel(), "y"), n, _dptr(out)))
         return out
 
-    def pcg_solve(self, d, alpha_rel, maxit, rtol=0.0, use_precond=True, h=None,
-                  raise_on_breakdown=True):
-        """Returns (h, hist [nshots][maxit+1][4], iterations, status)."""
+    def _pcg(self, fn, d, alpha, maxit, rtol, use_precond, h, raise_on_breakdown):
         if h is None:
             h = self.empty_s()
         hist = np.zeros((self.nshots, maxit + 1, 4))
         it = ctypes.c_int32(0)
-        st = lib().ssx_pcg_solve(self._ctx, self._vec(d, self.n_r, "d"), float(alpha_rel),
-                                 int(maxit), float(rtol), int(bool(use_precond)),
-                                 self._vec(h, self.n_s, "h"), _dptr(hist), ctypes.byref(it))
+        st = fn(self._ctx, self._vec(d, self.n_r, "d"), float(alpha), int(maxit), float(rtol),
+                int(bool(use_precond)), self._vec(h, self.n_s, "h"), _dptr(hist),
+                ctypes.byref(it))
         if st != 0 and (raise_on_breakdown or st not in (5, 6)):
             _check(st)
         return h, hist[:, : it.value + 1], it.value, st
+
+    def pcg_solve(self, d, alpha_rel, maxit, rtol=0.0, use_precond=True, h=None,
+                  raise_on_breakdown=True):
+        """Returns (h, hist [nshots][maxit+1][4], iterations, status)."""
+        return self._pcg(lib().ssx_pcg_solve, d, alpha_rel, maxit, rtol, use_precond, h,
+                         raise_on_breakdown)
+
+    # -- weighted normal equations (context created with rslab_dz != 0) ------
+    def weight_d(self, r, y):
+        _check(lib().ssx_weight_d(self._ctx, self._vec(r, self.n_r, "r"),
+                                  self._vec(y, self.n_r, "y")))
+        return y
+
+    def weight_m(self, x, y):
+        _check(lib().ssx_weight_m(self._ctx, self._vec(x, self.n_s, "x"),
+                                  self._vec(y, self.n_s, "y")))
+        return y
+
+    def normal_w(self, alpha, p, q, Fp=None):
+        fp = self._vec(Fp, self.n_r, "Fp") if Fp is not None else None
+        _check(lib().ssx_normal_w(self._ctx, float(alpha), self._vec(p, self.n_s, "p"),
+                                  self._vec(q, self.n_s, "q"), fp))
+        return q
+
+    def pcg_solve_w(self, d, alpha, maxit, rtol=0.0, use_precond=True, h=None,
+                    raise_on_breakdown=True):
+        """Algorithm 1 on the weighted normal equations, alpha per metre.
+        Returns (h, hist [nshots][maxit+1][4], iterations, status)."""
+        return self._pcg(lib().ssx_pcg_solve_w, d, alpha, maxit, rtol, use_precond, h,
+                         raise_on_breakdown)
 
     def set_option(self, option: int, value: int):
         _check(lib().ssx_set_option(self._ctx, int(option), int(value)))

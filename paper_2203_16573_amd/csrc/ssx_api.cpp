@@ -91,15 +91,23 @@ bool make_line(double z, double x0, int n, double h, int L, int nz_phys, int nx_
   return true;
 }
 
-// Rows of the full model used by the thin slab: [i_lo, i_hi] (may extend
-// beyond the model; clamped when copying kappa).
-void slab_rows(const ssx_problem& p, int* i_lo, int* i_hi, double* zs_slab) {
+// Rows of the full model used by a thin slab around the line at depth z
+// with its datum dz cells away: [i_lo, i_hi] (may extend beyond the model;
+// clamped when copying kappa); *z_slab is the line's depth in the slab.
+void thin_rows(const ssx_problem& p, double z, int dz, int* i_lo, int* i_hi, double* z_slab) {
   const int k = p.order / 2;
-  const int i_s = (int)std::floor(p.z_src / p.h + 1e-12);
-  const double frac = p.z_src / p.h - i_s;
-  *i_lo = std::min(i_s, i_s + p.slab_dz) - k;
-  *i_hi = std::max(i_s, i_s + p.slab_dz) + k + (frac > 1e-12 ? 1 : 0);
-  *zs_slab = p.z_src - (*i_lo) * p.h;
+  const int i_s = (int)std::floor(z / p.h + 1e-12);
+  const double frac = z / p.h - i_s;
+  *i_lo = std::min(i_s, i_s + dz) - k;
+  *i_hi = std::max(i_s, i_s + dz) + k + (frac > 1e-12 ? 1 : 0);
+  *z_slab = z - (*i_lo) * p.h;
+}
+// the source-side slab (preconditioner, W_m) and the receiver-side one (W_d)
+void slab_rows(const ssx_problem& p, int* i_lo, int* i_hi, double* zs_slab) {
+  thin_rows(p, p.z_src, p.slab_dz, i_lo, i_hi, zs_slab);
+}
+void rslab_rows(const ssx_problem& p, int* i_lo, int* i_hi, double* zr_slab) {
+  thin_rows(p, p.z_rec, p.rslab_dz, i_lo, i_hi, zr_slab);
 }
 
 ssx_status check_problem(const ssx_problem* pp) {
@@ -133,9 +141,19 @@ ssx_status check_problem(const ssx_problem* pp) {
   slab_rows(p, &i_lo, &i_hi, &zs);
   const int nzs = i_hi - i_lo + 1;
   if (!make_line(zs, p.x_src0, p.ns, p.h, L, nzs, p.nx, false, &l, &why) ||
+      !make_line(zs, p.x_src0, p.ns, p.h, L, nzs, p.nx, true, &l, &why) ||
       !make_line(zs + p.slab_dz * p.h, p.x_src0, p.ns, p.h, L, nzs, p.nx, true, &l, &why) ||
       !make_line(zs + p.slab_dz * p.h, p.x_src0, p.ns, p.h, L, nzs, p.nx, false, &l, &why))
     return fail(SSX_ERR_ARG, "thin slab: " + why);
+  if (p.rslab_dz != 0) {
+    double zr;
+    rslab_rows(p, &i_lo, &i_hi, &zr);
+    const int nzr = i_hi - i_lo + 1;
+    if (!make_line(zr, p.x_rec0, p.nr, p.h, L, nzr, p.nx, false, &l, &why) ||
+        !make_line(zr + p.rslab_dz * p.h, p.x_rec0, p.nr, p.h, L, nzr, p.nx, true, &l, &why) ||
+        !make_line(zr + p.rslab_dz * p.h, p.x_rec0, p.nr, p.h, L, nzr, p.nx, false, &l, &why))
+      return fail(SSX_ERR_ARG, "receiver-side slab: " + why);
+  }
   return SSX_OK;
 }
 
@@ -271,10 +289,17 @@ struct ssx_ctx {
   double rho, Z0;
   GridDev full, slab;
   LineDev h_line, r_line, f_line, dp_line, dv_line;
+  // source-side slab: pressure line at z_s (W_m); receiver-side slab (W_d,
+  // present when rslab_dz != 0): normal-load line at z_r, datum lines
+  LineDev hp_line;
+  bool has_rslab = false;
+  GridDev rslab;
+  LineDev rf_line, rdp_line, rdv_line;
   double* xs_dev;
   // vectors: [nshots][nt][ns] (s) or [nshots][nt][nr] (r)
   void *r, *g, *p, *q, *t1, *sP, *sV, *sF;  // s-vectors
   void *e, *Fp, *t2;                          // r-vectors
+  void *rP, *rV, *rW;  // r-vectors of the weighted entry points (null without rslab)
   double* sc;
   double* partial;
   double* hist;
@@ -299,7 +324,8 @@ long long nvec_s(const ssx_problem& p) { return (long long)p.nt * p.ns; }
 long long nvec_r(const ssx_problem& p) { return (long long)p.nt * p.nr; }
 
 // Lays out every buffer of a context; with a null base only sizes are computed.
-void layout(ssx_ctx* c, const GridHost& fg, const GridHost& sg, char* base, size_t* total) {
+void layout(ssx_ctx* c, const GridHost& fg, const GridHost& sg, const GridHost* rg, char* base,
+            size_t* total) {
   const ssx_problem& p = c->prob;
   Alloc a;
   a.base = base;
@@ -331,12 +357,15 @@ void layout(ssx_ctx* c, const GridHost& fg, const GridHost& sg, char* base, size
   };
   grid(c->full, fg);
   grid(c->slab, sg);
+  if (rg) grid(c->rslab, *rg);
   c->xs_dev = (double*)a.take((size_t)ns * 8);
   const size_t bs = (size_t)ns * nvec_s(p) * vsz, br = (size_t)ns * nvec_r(p) * vsz;
   void** svec[] = {&c->r, &c->g, &c->p, &c->q, &c->t1, &c->sP, &c->sV, &c->sF};
   for (void** v : svec) *v = a.take(bs);
   void** rvec[] = {&c->e, &c->Fp, &c->t2};
   for (void** v : rvec) *v = a.take(br);
+  void** wvec[] = {&c->rP, &c->rV, &c->rW};
+  for (void** v : wvec) *v = rg ? a.take(br) : nullptr;
   c->sc = (double*)a.take((size_t)ns * SC_N * 8);
   c->partial = (double*)a.take((size_t)ns * NBLK_DOT * 3 * 8);
   c->hist = (double*)a.take((size_t)ns * (HIST_CAP + 1) * 4 * 8);
@@ -693,7 +722,10 @@ void drop_graphs(ssx_ctx* c) {
   c->graphs_cache.clear();
 }
 
-enum { OP_FWD = 0, OP_ADJ = 1, OP_SLAB_FWD = 2, OP_SLAB_ADJ = 3 };
+enum {
+  OP_FWD = 0, OP_ADJ = 1, OP_SLAB_FWD = 2, OP_SLAB_ADJ = 3,
+  OP_RSLAB_FWD = 4, OP_RSLAB_ADJ = 5, OP_SLABP_FWD = 6, OP_SLABP_ADJ = 7
+};
 
 ssx_status do_fwd(ssx_ctx* c, const void* h, void* d) {
   const ssx_problem& p = c->prob;
@@ -740,8 +772,54 @@ ssx_status do_normal(ssx_ctx* c, const double* alpha2_dev, double alpha2_host, c
   const ssx_problem& pr = c->prob;
   SSX_TRY(do_fwd(c, p, Fp));
   SSX_TRY(do_adj(c, Fp, q));
-  SSX_HIP(launch_add_penalty(c->vdbl, q, p, alpha2_dev, SC_N, alpha2_host, pr.nt, pr.ns,
+  SSX_HIP(launch_add_penalty(c->vdbl, q, p, 2, alpha2_dev, SC_N, alpha2_host, pr.nt, pr.ns,
                              pr.nshots, pr.x_src0, pr.h, c->xs_dev, c->stream));
+  return SSX_OK;
+}
+
+// y = W_d r on the receiver-side slab: X_r r = (P, V) with the normal load
+// on z_r, then s_r X_r^T (V, P), s_r = 4 sign(rslab_dz) folded into the
+// output scale.
+ssx_status do_wd(ssx_ctx* c, const void* r, void* y) {
+  const long long st = nvec_r(c->prob);
+  const double sr = c->prob.rslab_dz > 0 ? 4.0 : -4.0;
+  SSX_TRY(propagate(c, OP_RSLAB_FWD, c->rslab, false, c->rdp_line, io_out(c->rP, st, c->Z0),
+                    c->rf_line, io_in(r, st, 1.0 / c->Z0), c->rdv_line, io_out(c->rV, st, 1.0),
+                    c->rdp_line, io_none()));
+  return propagate(c, OP_RSLAB_ADJ, c->rslab, true, c->rdp_line, io_none(), c->rdv_line,
+                   io_in(c->rP, st, 1.0), c->rf_line, io_out(y, st, sr / c->Z0), c->rdp_line,
+                   io_in(c->rV, st, c->Z0));
+}
+
+// y = W_m x on the source-side slab: a pressure source on z_s, datum
+// (P, V) exchanged, the transposed sweep read from the pressure-source slot,
+// scaled by sign(slab_dz).  Uses sP and sV.
+ssx_status do_wm(ssx_ctx* c, const void* x, void* y) {
+  const long long st = nvec_s(c->prob);
+  const double sm = c->prob.slab_dz > 0 ? 1.0 : -1.0;
+  SSX_TRY(propagate(c, OP_SLABP_FWD, c->slab, false, c->dp_line, io_out(c->sP, st, c->Z0),
+                    c->dv_line, io_none(), c->dv_line, io_out(c->sV, st, 1.0), c->hp_line,
+                    io_in(x, st, 1.0)));
+  return propagate(c, OP_SLABP_ADJ, c->slab, true, c->hp_line, io_out(y, st, sm), c->dv_line,
+                   io_in(c->sP, st, 1.0), c->dv_line, io_none(), c->dp_line,
+                   io_in(c->sV, st, c->Z0));
+}
+
+// q = F^T W_d F p + alpha^2 A^T W_m A p, Fp = F p (the W_m term only when
+// with_m); alpha^2 as in do_normal.  Uses rW, rP, rV, t1, sF, sP, sV.
+ssx_status do_normal_w(ssx_ctx* c, const double* alpha2_dev, double alpha2_host, bool with_m,
+                       const void* p, void* q, void* Fp) {
+  const ssx_problem& pr = c->prob;
+  SSX_TRY(do_fwd(c, p, Fp));
+  SSX_TRY(do_wd(c, Fp, c->rW));
+  SSX_TRY(do_adj(c, c->rW, q));
+  if (with_m) {
+    SSX_HIP(launch_diag(c->vdbl, 0, 0.0, 1.0, p, c->t1, pr.nt, pr.ns, pr.nshots, pr.x_src0,
+                        pr.h, c->xs_dev, c->stream));
+    SSX_TRY(do_wm(c, c->t1, c->sF));
+    SSX_HIP(launch_add_penalty(c->vdbl, q, c->sF, 1, alpha2_dev, SC_N, alpha2_host, pr.nt,
+                               pr.ns, pr.nshots, pr.x_src0, pr.h, c->xs_dev, c->stream));
+  }
   return SSX_OK;
 }
 
@@ -783,8 +861,13 @@ size_t ssx_footprint(const ssx_problem* prob) {
   };
   dims(fg, prob->nz);
   dims(sg, i_hi - i_lo + 1);
+  GridHost rg{};
+  if (prob->rslab_dz != 0) {
+    rslab_rows(*prob, &i_lo, &i_hi, &zs);
+    dims(rg, i_hi - i_lo + 1);
+  }
   size_t total = 0;
-  layout(&c, fg, sg, nullptr, &total);
+  layout(&c, fg, sg, prob->rslab_dz != 0 ? &rg : nullptr, nullptr, &total);
   return total;
 }
 
@@ -828,6 +911,21 @@ ssx_status ssx_create(const ssx_problem* prob, const double* kappa_host, double 
   fill_dims(c->slab, p.nshots);
   c->full.coef.cb = c->Z0 * p.dt / (rho * p.h);
   c->slab.coef.cb = c->full.coef.cb;
+  c->has_rslab = p.rslab_dz != 0;
+  int r_lo = 0, r_hi = -1;
+  double zr = 0.0;
+  if (c->has_rslab) {
+    rslab_rows(p, &r_lo, &r_hi, &zr);
+    const int nzr = r_hi - r_lo + 1;
+    std::vector<double> krs((size_t)nzr * p.nx);
+    for (int r = 0; r < nzr; ++r) {
+      const int i = std::min(std::max(r_lo + r, 0), p.nz - 1);
+      std::memcpy(&krs[(size_t)r * p.nx], &kphys[(size_t)i * p.nx], p.nx * sizeof(double));
+    }
+    build_grid(p, krs, nzr, c->Z0, rho, &c->rslab.host);
+    fill_dims(c->rslab, p.nshots);
+    c->rslab.coef.cb = c->full.coef.cb;
+  }
 
   std::string why;
   const int L = p.npml;
@@ -836,6 +934,14 @@ ssx_status ssx_create(const ssx_problem* prob, const double* kappa_host, double 
   make_line(zs, p.x_src0, p.ns, p.h, L, nzs, p.nx, false, &c->f_line, &why);
   make_line(zs + p.slab_dz * p.h, p.x_src0, p.ns, p.h, L, nzs, p.nx, true, &c->dp_line, &why);
   make_line(zs + p.slab_dz * p.h, p.x_src0, p.ns, p.h, L, nzs, p.nx, false, &c->dv_line, &why);
+  make_line(zs, p.x_src0, p.ns, p.h, L, nzs, p.nx, true, &c->hp_line, &why);
+  if (c->has_rslab) {
+    const int nzr = r_hi - r_lo + 1;
+    make_line(zr, p.x_rec0, p.nr, p.h, L, nzr, p.nx, false, &c->rf_line, &why);
+    make_line(zr + p.rslab_dz * p.h, p.x_rec0, p.nr, p.h, L, nzr, p.nx, true, &c->rdp_line, &why);
+    make_line(zr + p.rslab_dz * p.h, p.x_rec0, p.nr, p.h, L, nzr, p.nx, false, &c->rdv_line,
+              &why);
+  }
   // full-grid tile lists for tile-loop launches (its lines: source, receivers)
   {
     const LineDev* lines[2] = {&c->h_line, &c->r_line};
@@ -850,7 +956,8 @@ ssx_status ssx_create(const ssx_problem* prob, const double* kappa_host, double 
   }
 
   size_t total = 0;
-  layout(c, c->full.host, c->slab.host, nullptr, &total);
+  const GridHost* rg = c->has_rslab ? &c->rslab.host : nullptr;
+  layout(c, c->full.host, c->slab.host, rg, nullptr, &total);
   char* base = nullptr;
   if (workspace) {
     if (workspace_bytes < total) {
@@ -868,7 +975,7 @@ ssx_status ssx_create(const ssx_problem* prob, const double* kappa_host, double 
   }
   // align the base to 256 bytes
   char* aligned = (char*)(((uintptr_t)base + 255) / 256 * 256);
-  layout(c, c->full.host, c->slab.host, aligned, &total);
+  layout(c, c->full.host, c->slab.host, rg, aligned, &total);
   ssx_status st = SSX_OK;
   auto cleanup = [&]() {
     if (c->own) (void)hipFree(c->own);
@@ -882,6 +989,7 @@ ssx_status ssx_create(const ssx_problem* prob, const double* kappa_host, double 
   }
   st = upload(c->full, c->fdt == Dt::F64, c->stream);
   if (st == SSX_OK) st = upload(c->slab, c->fdt == Dt::F64, c->stream);
+  if (st == SSX_OK && c->has_rslab) st = upload(c->rslab, c->fdt == Dt::F64, c->stream);
   if (st != SSX_OK) {
     cleanup();
     return st;
@@ -952,12 +1060,15 @@ ssx_status ssx_dot(ssx_ctx* c, const void* x, const void* y, int64_t n, double* 
   return SSX_OK;
 }
 
-ssx_status ssx_pcg_solve(ssx_ctx* c, const void* d, double alpha_rel, int32_t maxit,
-                         double rtol, int32_t use_precond, void* h_out, double* hist_host,
-                         int32_t* iters_host) {
-  if (!c || !d || !h_out) return fail(SSX_ERR_ARG, "null argument");
-  if (maxit < 0 || maxit > HIST_CAP) return fail(SSX_ERR_ARG, "maxit out of range");
-  if (!std::isfinite(alpha_rel) || alpha_rel < 0) return fail(SSX_ERR_ARG, "alpha_rel must be >= 0");
+}  // extern "C"
+
+namespace {
+
+// Algorithm 1 for ssx_pcg_solve (weighted = false: N h = F^T d, alpha =
+// a ||F^T d|| / ||d||, alpha_hat = a) and ssx_pcg_solve_w (weighted = true:
+// N_w h = F^T W_d d, alpha = alpha_hat = a).
+ssx_status run_pcg(ssx_ctx* c, bool weighted, const void* d, double a, int32_t maxit, double rtol,
+                   int32_t use_precond, void* h_out, double* hist_host, int32_t* iters_host) {
   const ssx_problem& p = c->prob;
   hipStream_t s = c->stream;
   const int ns = p.nshots;
@@ -968,18 +1079,27 @@ ssx_status ssx_pcg_solve(ssx_ctx* c, const void* d, double alpha_rel, int32_t ma
   void* h = h_out;
 
   SSX_HIP(launch_zero(h, bs, s));
-  SSX_TRY(do_adj(c, d, c->r));  // r_0 = F^T d
+  if (weighted) {  // r_0 = F^T W_d d
+    SSX_TRY(do_wd(c, d, c->rW));
+    SSX_TRY(do_adj(c, c->rW, c->r));
+  } else {  // r_0 = F^T d
+    SSX_TRY(do_adj(c, d, c->r));
+  }
   SSX_HIP(launch_dot1(c->vdbl, d, d, ne, ns, c->partial, sc + SC_DD, SC_N, s));
   SSX_HIP(launch_dot1(c->vdbl, c->r, c->r, n, ns, c->partial, sc + SC_RR, SC_N, s));
-  SSX_HIP(launch_pcg_init(sc, alpha_rel, ns, s));
+  SSX_HIP(launch_pcg_init(sc, a, weighted, ns, s));
   SSX_HIP(launch_neg_copy(c->vdbl, c->e, d, (long long)ns * ne, s));  // e_0 = F h_0 - d
   auto apply_M = [&](const void* r, void* g) -> ssx_status {
-    if (use_precond) return do_precond(c, alpha_rel, r, g);
+    if (use_precond) return do_precond(c, a, r, g);
     return copy_vec(c, g, r, bs);
+  };
+  auto apply_N = [&]() -> ssx_status {
+    if (weighted) return do_normal_w(c, sc + SC_ALPHA2, 0.0, a != 0.0, c->p, c->q, c->Fp);
+    return do_normal(c, sc + SC_ALPHA2, 0.0, c->p, c->q, c->Fp);
   };
   SSX_TRY(apply_M(c->r, c->g));
   SSX_TRY(copy_vec(c, c->p, c->g, bs));
-  if (maxit > 0) SSX_TRY(do_normal(c, sc + SC_ALPHA2, 0.0, c->p, c->q, c->Fp));
+  if (maxit > 0) SSX_TRY(apply_N());
   SSX_HIP(launch_dot3(c->vdbl, c->g, c->r, n, ns, c->partial, sc + SC_GRNEW, SC_N, s));
   SSX_HIP(launch_dot1(c->vdbl, c->e, c->e, ne, ns, c->partial, sc + SC_EE, SC_N, s));
   SSX_HIP(launch_pcg_record(sc, hist, 0, maxit, ns, s));
@@ -1010,7 +1130,7 @@ ssx_status ssx_pcg_solve(ssx_ctx* c, const void* d, double alpha_rel, int32_t ma
         if (!(rows[2 * sh + 1] <= rtol * rows[2 * sh])) stop = false;
     }
     if (stop) break;
-    if (k < maxit - 1) SSX_TRY(do_normal(c, sc + SC_ALPHA2, 0.0, c->p, c->q, c->Fp));
+    if (k < maxit - 1) SSX_TRY(apply_N());
   }
   SSX_HIP(hipMemcpyAsync(hrow.data(), sc, hrow.size() * 8, hipMemcpyDeviceToHost, s));
   if (hist_host) {
@@ -1026,6 +1146,48 @@ ssx_status ssx_pcg_solve(ssx_ctx* c, const void* d, double alpha_rel, int32_t ma
   if (worst & 2) return fail(SSX_ERR_NONFINITE, "a non-finite PCG scalar appeared");
   if (worst & 1) return fail(SSX_ERR_BREAKDOWN, "PCG breakdown: <g,r> or <p,q> became zero");
   return SSX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ssx_status ssx_pcg_solve(ssx_ctx* c, const void* d, double alpha_rel, int32_t maxit,
+                         double rtol, int32_t use_precond, void* h_out, double* hist_host,
+                         int32_t* iters_host) {
+  if (!c || !d || !h_out) return fail(SSX_ERR_ARG, "null argument");
+  if (maxit < 0 || maxit > HIST_CAP) return fail(SSX_ERR_ARG, "maxit out of range");
+  if (!std::isfinite(alpha_rel) || alpha_rel < 0) return fail(SSX_ERR_ARG, "alpha_rel must be >= 0");
+  return run_pcg(c, false, d, alpha_rel, maxit, rtol, use_precond, h_out, hist_host, iters_host);
+}
+
+ssx_status ssx_weight_d(ssx_ctx* c, const void* r, void* y) {
+  if (!c || !r || !y) return fail(SSX_ERR_ARG, "null argument");
+  if (!c->has_rslab) return fail(SSX_ERR_ARG, "context has no receiver-side slab (rslab_dz == 0)");
+  return do_wd(c, r, y);
+}
+
+ssx_status ssx_weight_m(ssx_ctx* c, const void* x, void* y) {
+  if (!c || !x || !y) return fail(SSX_ERR_ARG, "null argument");
+  if (!c->has_rslab) return fail(SSX_ERR_ARG, "context has no receiver-side slab (rslab_dz == 0)");
+  return do_wm(c, x, y);
+}
+
+ssx_status ssx_normal_w(ssx_ctx* c, double alpha, const void* p, void* q, void* Fp) {
+  if (!c || !p || !q) return fail(SSX_ERR_ARG, "null argument");
+  if (!c->has_rslab) return fail(SSX_ERR_ARG, "context has no receiver-side slab (rslab_dz == 0)");
+  if (!std::isfinite(alpha)) return fail(SSX_ERR_ARG, "alpha must be finite");
+  return do_normal_w(c, nullptr, alpha * alpha, alpha != 0.0, p, q, Fp ? Fp : c->t2);
+}
+
+ssx_status ssx_pcg_solve_w(ssx_ctx* c, const void* d, double alpha, int32_t maxit, double rtol,
+                           int32_t use_precond, void* h_out, double* hist_host,
+                           int32_t* iters_host) {
+  if (!c || !d || !h_out) return fail(SSX_ERR_ARG, "null argument");
+  if (!c->has_rslab) return fail(SSX_ERR_ARG, "context has no receiver-side slab (rslab_dz == 0)");
+  if (maxit < 0 || maxit > HIST_CAP) return fail(SSX_ERR_ARG, "maxit out of range");
+  if (!std::isfinite(alpha) || alpha < 0) return fail(SSX_ERR_ARG, "alpha must be >= 0");
+  return run_pcg(c, true, d, alpha, maxit, rtol, use_precond, h_out, hist_host, iters_host);
 }
 
 ssx_status ssx_set_option(ssx_ctx* c, int option, int value) {
@@ -1051,7 +1213,7 @@ ssx_status ssx_set_option(ssx_ctx* c, int option, int value) {
       if (value == 4 || value == 8) {
         if (c->fdt == Dt::F64)
           return fail(SSX_ERR_ARG, "4 or 8 slab steps per launch are not available for F64 fields");
-        if (c->slab.host.NZ > SLAB_MAXZ)
+        if (c->slab.host.NZ > SLAB_MAXZ || (c->has_rslab && c->rslab.host.NZ > SLAB_MAXZ))
           return fail(SSX_ERR_ARG, "the slab is too tall for 4 or 8 steps per launch");
         c->spl_slab = value;
         return SSX_OK;

@@ -154,9 +154,9 @@ hipError_t launch_dot1(bool vdbl, const void* x, const void* y, long long n, int
 hipError_t launch_diag(bool vdbl, int op, double a, double s, const void* x, void* y,
                        long long nt, int ns, int nshots, double x0, double h,
                        const double* xs_dev, hipStream_t st);
-// q += alpha2 * |xk - xs|^2 * p with alpha2 = alpha2_dev[shot*astride], or
-// alpha2_host when alpha2_dev is null
-hipError_t launch_add_penalty(bool vdbl, void* q, const void* p, const double* alpha2_dev,
+// q += alpha2 * |xk - xs|^pw * p (pw = 1 or 2) with alpha2 =
+// alpha2_dev[shot*astride], or alpha2_host when alpha2_dev is null
+hipError_t launch_add_penalty(bool vdbl, void* q, const void* p, int pw, const double* alpha2_dev,
                               int astride, double alpha2_host, long long nt, int ns,
                               int nshots, double x0, double h, const double* xs_dev,
                               hipStream_t st);
@@ -181,9 +181,9 @@ hipError_t launch_pcg_record(double* sc, double* hist, int k, int maxit, int nsh
 // p = g + beta p
 hipError_t launch_pcg_dir(bool vdbl, void* p, const void* g, long long n,
                           const double* sc, int nshots, hipStream_t s);
-// alpha2 = (alpha_rel * sqrt(rr / dd))^2 from SC_RR = <r0,r0>, SC_DD = <d,d>;
-// clears flags and reference signs
-hipError_t launch_pcg_init(double* sc, double alpha_rel, int nshots, hipStream_t s);
+// alpha2 = (alpha * sqrt(rr / dd))^2 from SC_RR = <r0,r0>, SC_DD = <d,d>, or
+// alpha^2 itself when absolute; clears flags and reference signs
+hipError_t launch_pcg_init(double* sc, double alpha, bool absolute, int nshots, hipStream_t s);
 hipError_t launch_neg_copy(bool vdbl, void* y, const void* x, long long n, hipStream_t s);
 
 // dyn[shot] = smallest power of two >= max(sa * max|a[shot]|, sb * max|b[shot]|)

@@ -118,9 +118,10 @@ __global__ void k_diag(int op, double a, double s, const V* __restrict__ x, V* y
 }
 
 template <typename V>
-__global__ void k_add_penalty(V* q, const V* __restrict__ p, const double* __restrict__ alpha2,
-                              int astride, double alpha2_host, long long nt, int ns, double x0,
-                              double h, const double* __restrict__ xs) {
+__global__ void k_add_penalty(V* q, const V* __restrict__ p, int pw,
+                              const double* __restrict__ alpha2, int astride, double alpha2_host,
+                              long long nt, int ns, double x0, double h,
+                              const double* __restrict__ xs) {
   const int shot = blockIdx.y;
   const long long n = nt * ns;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -128,7 +129,7 @@ __global__ void k_add_penalty(V* q, const V* __restrict__ p, const double* __res
   const int k = int(i % ns);
   const double dist = x0 + k * h - xs[shot];
   const double al2 = alpha2 ? alpha2[(long long)shot * astride] : alpha2_host;
-  const double fac = al2 * dist * dist;
+  const double fac = pw == 2 ? al2 * dist * dist : al2 * fabs(dist);
   const long long off = (long long)shot * n + i;
   q[off] = V(double(q[off]) + fac * double(p[off]));
 }
@@ -149,7 +150,7 @@ hipError_t launch_diag(bool vdbl, int op, double a, double s, const void* x, voi
   return hipGetLastError();
 }
 
-hipError_t launch_add_penalty(bool vdbl, void* q, const void* p, const double* alpha2,
+hipError_t launch_add_penalty(bool vdbl, void* q, const void* p, int pw, const double* alpha2,
                               int astride, double alpha2_host, long long nt, int ns,
                               int nshots, double x0, double h, const double* xs_dev,
                               hipStream_t st) {
@@ -157,12 +158,12 @@ hipError_t launch_add_penalty(bool vdbl, void* q, const void* p, const double* a
   dim3 grid((unsigned)((n + 255) / 256), nshots);
   if (vdbl)
     hipLaunchKernelGGL(k_add_penalty<double>, grid, dim3(256), 0, st, static_cast<double*>(q),
-                       static_cast<const double*>(p), alpha2, astride, alpha2_host, nt, ns, x0,
-                       h, xs_dev);
+                       static_cast<const double*>(p), pw, alpha2, astride, alpha2_host, nt, ns,
+                       x0, h, xs_dev);
   else
     hipLaunchKernelGGL(k_add_penalty<float>, grid, dim3(256), 0, st, static_cast<float*>(q),
-                       static_cast<const float*>(p), alpha2, astride, alpha2_host, nt, ns, x0,
-                       h, xs_dev);
+                       static_cast<const float*>(p), pw, alpha2, astride, alpha2_host, nt, ns,
+                       x0, h, xs_dev);
   return hipGetLastError();
 }
 
@@ -171,13 +172,13 @@ hipError_t launch_add_penalty(bool vdbl, void* q, const void* p, const double* a
 
 __device__ __forceinline__ bool same_sign(double a, double b) { return (a > 0) == (b > 0); }
 
-__global__ void k_pcg_init(double* sc, double alpha_rel, int nshots) {
+__global__ void k_pcg_init(double* sc, double alpha, int absolute, int nshots) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nshots) return;
   double* c = sc + (long long)s * SC_N;
   const double dd = c[SC_DD], rr = c[SC_RR];
-  const double sig = dd > 0.0 ? sqrt(rr / dd) : 0.0;
-  const double al = alpha_rel * sig;
+  const double sig = absolute ? 1.0 : (dd > 0.0 ? sqrt(rr / dd) : 0.0);
+  const double al = alpha * sig;
   c[SC_ALPHA2] = al * al;
   c[SC_FLAG] = 0.0;
   c[SC_PQ0] = 0.0;
@@ -280,9 +281,9 @@ __global__ void k_neg_copy(V* y, const V* __restrict__ x, long long n) {
   if (i < n) y[i] = -x[i];
 }
 
-hipError_t launch_pcg_init(double* sc, double alpha_rel, int nshots, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_init, dim3((nshots + 63) / 64), dim3(64), 0, s, sc, alpha_rel,
-                     nshots);
+hipError_t launch_pcg_init(double* sc, double alpha, bool absolute, int nshots, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_init, dim3((nshots + 63) / 64), dim3(64), 0, s, sc, alpha,
+                     (int)absolute, nshots);
   return hipGetLastError();
 }
 hipError_t launch_pcg_record(double* sc, double* hist, int k, int maxit, int nshots,

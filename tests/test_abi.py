@@ -80,3 +80,36 @@ def test_footprint_scales_with_shots():
     one = ssx.footprint(wl.prob, nshots=1)
     many = ssx.footprint(wl.prob, nshots=64)
     assert 40 * one < many < 70 * one
+
+
+def test_problem_struct_matches_header(tmp_path):
+    # the ctypes mirror of ssx_problem has the header's size and offsets
+    import ctypes
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    names = [f[0] for f in ssx.ssx_problem._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"ssx.h\"\n"
+                   "int main(void) {\n  printf(\"%zu\\n\", sizeof(ssx_problem));\n" +
+                   "".join(f"  printf(\"%zu\\n\", offsetof(ssx_problem, {n}));\n" for n in names) +
+                   "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    assert out[0] == ctypes.sizeof(ssx.ssx_problem)
+    for n, off in zip(names, out[1:]):
+        assert off == getattr(ssx.ssx_problem, n).offset, n
+
+
+def test_footprint_counts_the_receiver_side_slab():
+    wl = inputs.workload(1)
+    base = ssx.footprint(wl.prob, field_dtype="f64")
+    both = ssx.footprint(wl.prob.replace(rslab_dz=-5), field_dtype="f64")
+    # one more slab of fields and coefficients plus three trace vectors
+    assert base < both < 1.5 * base
+    ssx.validate(wl.prob.replace(rslab_dz=4), wl.kappa, wl.rho, field_dtype="f64")
