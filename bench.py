@@ -36,7 +36,17 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c4bf", "c5"])
+    ap.add_argument("--config", default="c2",
+                    choices=["c1", "c2", "c3", "c4", "c4bf", "c5", "xw"],
+                    help="c1..c5: the benchmark configurations; xw: the paper's crosswell "
+                         "example, CG against weighted PCG")
+    ap.add_argument("--solver", default="plain", choices=["plain", "weighted"],
+                    help="c1..c4: Algorithm 1 on the Euclidean normal equations (plain) or "
+                         "on the weighted ones N_w h = F^T W_d d (weighted)")
+    ap.add_argument("--alpha", type=float, default=1e-3,
+                    help="weighted solver: penalty weight per metre")
+    ap.add_argument("--iters", type=int, default=0,
+                    help="override the PCG iteration count (xw: default 60)")
     ap.add_argument("--autotune", type=int, default=1)
     ap.add_argument("--requests", type=int, default=12, help="c5: requests served")
     ap.add_argument("--max-shots", type=int, default=8, help="c5: shots per request cap")
@@ -106,6 +116,8 @@ def main():
 
     if args.config == "c5":
         return serve_bench(args)
+    if args.config == "xw":
+        return crosswell_bench(args)
     cnum = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "c4bf": 4}[args.config]
     wl = inputs.workload(cnum)
     if args.nt:
@@ -113,6 +125,12 @@ def main():
     if args.shots:
         width = (wl.prob.nx - 1) * wl.prob.h
         wl.prob = wl.prob.replace(xs=inputs.shot_positions(args.shots, width))
+    if args.iters:
+        wl.K = args.iters
+    weighted = args.solver == "weighted"
+    if weighted:
+        # receiver-side datum 5 cells beyond the receivers, away from the sources
+        wl.prob = wl.prob.replace(rslab_dz=-5 if wl.prob.z_rec < wl.prob.z_src else 5)
     prob = wl.prob
     fd = {"c1": "f64", "c2": "f32", "c3": "f32", "c4": "f16", "c4bf": "bf16"}[args.config]
     if args.dtype:
@@ -157,12 +175,17 @@ def main():
         ctx.close()
         return
 
+    def solve():
+        if weighted:
+            return ctx.pcg_solve_w(d, args.alpha, wl.K, h=h, raise_on_breakdown=False)
+        return ctx.pcg_solve(d, wl.alpha_rel, wl.K, h=h, raise_on_breakdown=False)
+
     for _ in range(args.warmup):
-        ctx.pcg_solve(d, wl.alpha_rel, wl.K, h=h, raise_on_breakdown=False)
+        solve()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        _, hist, iters, st = ctx.pcg_solve(d, wl.alpha_rel, wl.K, h=h, raise_on_breakdown=False)
+        _, hist, iters, st = solve()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     solves = args.steps * prob.nshots
@@ -207,10 +230,15 @@ def main():
                 "launches_per_step": launches, "bytes_per_cell": b_alg,
                 "cells_per_launch": cells}
 
-    # cell-updates in one solve: (2K + 1) full propagations, 2 (K + 1) slab
+    # cell-updates in one solve: (2K + 1) full propagations, 2 (K + 1) slab;
+    # weighted: also 2 (K + 1) on the receiver-side slab and, with a nonzero
+    # alpha, 2K more on the source-side one
     k = prob.order // 2
     nzs = abs(prob.slab_dz) + 1 + 2 * k + 2 * prob.npml
     cu_solve = prob.nt * ((2 * wl.K + 1) * NZ * NX + 2 * (wl.K + 1) * nzs * NX)
+    if weighted:
+        nzr = abs(prob.rslab_dz) + 1 + 2 * k + 2 * prob.npml
+        cu_solve += prob.nt * NX * (2 * (wl.K + 1) * nzr + (2 * wl.K * nzs if args.alpha else 0))
     gcell = cu_solve * prob.nshots / (elapsed / args.steps) / 1e9
 
     cpu = None
@@ -253,7 +281,8 @@ def main():
                "residual_history_max_rel_diff": float(np.max(np.abs(rr - 1.0)))}
 
     out = {
-        "metric": "PCG surface-source solves/s",
+        "metric": "weighted PCG surface-source solves/s" if weighted
+        else "PCG surface-source solves/s",
         "value": round(value, 4),
         "unit": "solves/s",
         "n_gpus": 1,
@@ -266,7 +295,8 @@ def main():
         "dtype": {"f64": "f64", "f32": "f32", "f16": "f16-storage/f32", "bf16": "bf16-storage/f32"}[fd],
         "data": "synthetic (seeded layered model; d = F of a Ricker point source)",
         "config": {"workload": f"{wl.name}: {prob.nz}x{prob.nx} @ {prob.h} m, order "
-                               f"{prob.order}, nt {prob.nt}, K {wl.K}, shots {prob.nshots}",
+                               f"{prob.order}, nt {prob.nt}, K {wl.K}, shots {prob.nshots}"
+                               + (f", weighted, alpha {args.alpha}/m" if weighted else ""),
                    "nz": prob.nz, "nx": prob.nx, "nt": prob.nt, "K": wl.K,
                    "shots": prob.nshots, "field_dtype": fd},
         "gcell_updates_per_s": round(gcell, 2),
@@ -281,6 +311,92 @@ def main():
     }
     if ref is not None:
         out["error_vs_f64_solve"] = ref
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def crosswell_bench(args):
+    """The paper's comparison of CG and preconditioned CG (Numerical
+    Examples, the last subsection) in its crosswell geometry: data from a
+    point source at (3500, 3500) m in the lens model, recorded at 1000 m
+    over x = 2000..6000 m and inverted for an extended source on 3000 m in
+    the homogeneous model.  CG runs Algorithm 1 with M = I on the Euclidean
+    normal equations (the same penalty relative to the operator scale,
+    alpha_rel = alpha); PCG runs it on the weighted normal equations with
+    M^-1 = D W^-1 D.  For each alpha in {0, --alpha} the line reports the
+    relative normal-residual curves (CG: ||r_k||; PCG: ||M^-1 r_k||, the
+    left side of the norm1 form), the iterations each needs to reduce it by
+    10x, 100x and 1000x, and the data misfit; then it times repeated weighted
+    solves (--steps, after --warmup)."""
+    import numpy as np
+    import torch
+
+    import inputs
+    import paper_2203_16573_amd as ssx
+
+    rho = inputs.RHO_WATERLIKE
+    prob = inputs.crosswell_problem()
+    if args.nt:
+        prob = prob.replace(nt=args.nt)
+    K = args.iters or 60
+    fd = args.dtype or "f32"
+    vdt = torch.float64 if fd == "f64" else torch.float32
+    # data: the point source in the lens model
+    pprob = inputs.crosswell_point_problem(prob)
+    pctx = ssx.Context(pprob, inputs.crosswell_kappa(lens=True), rho, field_dtype=fd)
+    w = inputs.bandpass_wavelet((np.arange(prob.nt) + 0.5) * prob.dt)
+    hpt = torch.tensor((w / prob.h)[None, :, None], dtype=vdt, device="cuda").contiguous()
+    d = pctx.fwd(hpt, pctx.empty_r())
+    torch.cuda.synchronize()
+    pctx.close()
+    ctx = ssx.Context(prob, inputs.crosswell_kappa(lens=False), rho, field_dtype=fd)
+    ctx.set_graphs(bool(args.graphs))
+    dn = float(torch.linalg.norm(d.double()))
+
+    def reached(curve, level):
+        idx = np.nonzero(curve <= level)[0]
+        return int(idx[0]) if idx.size else None
+
+    comparison = {}
+    for alpha in sorted({0.0, args.alpha}):
+        _, hc, _, stc = ctx.pcg_solve(d, alpha, K, use_precond=False, raise_on_breakdown=False)
+        _, hp, _, stp = ctx.pcg_solve_w(d, alpha, K, raise_on_breakdown=False)
+        cg = hc[0, :, 0] / hc[0, 0, 0]
+        pcg = hp[0, :, 1] / hp[0, 0, 1]
+        entry = {"cg_status": int(stc), "pcg_status": int(stp),
+                 "pcg_gr_sign_changes": int(np.sum(np.sign(hp[0, :, 2]) != np.sign(hp[0, 0, 2]))),
+                 "cg_curve": [round(float(v), 6) for v in cg],
+                 "pcg_curve": [round(float(v), 6) for v in pcg],
+                 "cg_misfit": round(float(hc[0, -1, 3] / dn), 5),
+                 "pcg_misfit": round(float(hp[0, -1, 3] / dn), 5)}
+        for tag, lev in (("10x", 1e-1), ("100x", 1e-2), ("1000x", 1e-3)):
+            a, b = reached(cg, lev), reached(pcg, lev)
+            entry[f"iters_to_{tag}"] = {"cg": a, "pcg": b,
+                                       "ratio": round(a / b, 2) if a and b else None}
+        comparison[f"alpha={alpha:g}"] = entry
+
+    h = ctx.empty_s()
+    for _ in range(args.warmup):
+        ctx.pcg_solve_w(d, args.alpha, K, h=h, raise_on_breakdown=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.pcg_solve_w(d, args.alpha, K, h=h, raise_on_breakdown=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out = {
+        "metric": "weighted PCG surface-source solves/s (crosswell example)",
+        "value": round(args.steps / el, 4), "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * el / args.steps, 2), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": fd,
+        "data": "synthetic (lens model of the paper's shape; bandpass point source)",
+        "config": {"workload": f"crosswell: {prob.nz}x{prob.nx} @ {prob.h} m, order "
+                               f"{prob.order}, nt {prob.nt}, K {K}, alpha {args.alpha}/m",
+                   "nz": prob.nz, "nx": prob.nx, "nt": prob.nt, "K": K, "field_dtype": fd},
+        "ms_per_iteration": round(1e3 * el / (args.steps * K), 3),
+        "cg_vs_pcg": comparison,
+    }
     print(json.dumps(out), flush=True)
     ctx.close()
 

@@ -271,3 +271,58 @@ def source_wavelet(prob: Problem, freq: float) -> np.ndarray:
 
 def random_traces(shape, seed: int) -> np.ndarray:
     return np.random.default_rng(seed).standard_normal(shape)
+
+
+# ----------------------------------------------------------------------------
+# the paper's crosswell example (Numerical Examples: 8 km x 4 km at 20 m,
+# kappa 4 GPa, rho 1 g/cm^3, a central low-velocity lens down to 1.6 GPa,
+# receivers at 1000 m and extended sources at 3000 m over x = 2000..6000 m,
+# point source at (3500, 3500) m with a 1 / 2.5 / 7.5 / 12.5 Hz bandpass
+# wavelet, auxiliary datums 100 m above both lines)
+
+def bandpass_wavelet(t: np.ndarray, corners=(1.0, 2.5, 7.5, 12.5), t0: float = 0.8,
+                     nfft: int = 1 << 16, dtf: float = 1e-3) -> np.ndarray:
+    """Zero-phase wavelet with a trapezoidal amplitude spectrum (0 below
+    corners[0], linear up to 1 at corners[1], flat to corners[2], linear
+    down to 0 at corners[3]), centred at t0 and sampled at times t by linear
+    interpolation of an nfft-point inverse FFT at spacing dtf; peak 1."""
+    f = np.fft.rfftfreq(nfft, dtf)
+    f1, f2, f3, f4 = corners
+    amp = np.clip(np.minimum((f - f1) / (f2 - f1), (f4 - f) / (f4 - f3)), 0.0, 1.0)
+    w = np.fft.irfft(amp, nfft)
+    w = np.roll(w, nfft // 2)
+    tw = (np.arange(nfft) - nfft // 2) * dtf + t0
+    out = np.interp(np.asarray(t, dtype=np.float64), tw, w, left=0.0, right=0.0)
+    return out / np.abs(w).max()
+
+
+def crosswell_kappa(nz: int = 201, nx: int = 401, h: float = 20.0, lens: bool = True,
+                    k0: float = 4.0e9, kmin: float = 1.6e9, radius: float = 500.0):
+    """Bulk modulus of the crosswell example: k0 everywhere, minus (when
+    lens) a Gaussian of standard deviation ``radius`` centred in the
+    rectangle that brings it to kmin at the centre."""
+    kap = np.full((nz, nx), k0)
+    if lens:
+        z = np.arange(nz)[:, None] * h - 0.5 * (nz - 1) * h
+        x = np.arange(nx)[None, :] * h - 0.5 * (nx - 1) * h
+        kap = kap - (k0 - kmin) * np.exp(-(x * x + z * z) / (2.0 * radius * radius))
+    return kap
+
+
+def crosswell_problem(h: float = 20.0, dt: float = 4e-3, nt: int = 1000, order: int = 8,
+                      npml: int = 20) -> Problem:
+    """The inversion geometry: extended sources on z = 3000 m and receivers
+    on z = 1000 m, both over x = 2000..6000 m; thin-slab datums 100 m above
+    each line; penalty centred on x_s = 3500 m."""
+    nz, nx = int(round(4000.0 / h)) + 1, int(round(8000.0 / h)) + 1
+    n = int(round(4000.0 / h)) + 1
+    dz = -int(round(100.0 / h))
+    return Problem(nz=nz, nx=nx, h=h, dt=dt, nt=nt, order=order, npml=npml,
+                   z_src=3000.0, x_src0=2000.0, ns=n, z_rec=1000.0, x_rec0=2000.0, nr=n,
+                   slab_dz=dz, xs=(3500.0,), rslab_dz=dz)
+
+
+def crosswell_point_problem(prob: Problem) -> Problem:
+    """The data geometry: the point source at (3500, 3500) m as a one-sample
+    source line, the same receivers."""
+    return prob.replace(z_src=3500.0, x_src0=3500.0, ns=1, slab_dz=-1, rslab_dz=0)
