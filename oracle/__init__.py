@@ -15,8 +15,9 @@ Extended Surface Sources" (arXiv 2203.16573) that it follows:
 * ``prop``   forward time stepping and its exact transpose (Operators
              section; Appendix A);
 * ``ops``    F, F^T, the penalty A, the thin-slab preconditioner, the normal
-             operator and Algorithm 1, and the weighted normal equations
-             with their data- and model-space weights (Introduction;
+             operator and Algorithm 1, the weighted normal equations with
+             their data- and model-space weights, V, the time-reversal
+             inverse and Lambda~ (Introduction; Time Reversal; Unitarity;
              Accelerated Iterative Inversion; Computing and Symmetrizing
              Lambda);
 * ``greens`` the closed-form 2D point-source response used as a pin.
@@ -25,7 +26,8 @@ Every function is pinned by the CPU tests against facts that do not come
 from this code: the dot-product adjoint test, brute-force dense transposes,
 discrete energy conservation, reciprocity, the closed-form Green's function at
 second-order convergence, the 1D plane-wave amplitudes (including the
-energy transmission coefficient that the weighted composition reduces to),
+energy transmission coefficient that the weighted composition and the
+time-reversal inverse reduce to, and the exact 1D form of the sv relation),
 polynomial exactness of the stencils, dense normal-equation solves, the
 gradient of the weighted objective and Krylov-subspace optimality.
 """

@@ -23,6 +23,10 @@ TEST INFRASTRUCTURE ONLY -- see the package header.
         the normpart system), W_d the receiver-surface counterpart of W^-1
         and W_m the symmetrised inverse pressure-to-source operator (the
         wcomp formula), both on thin slabs.
+* V   = normal load on z_s to normal velocity on z_r (the vdef operator),
+        its transpose, the time-reversal inverse 4 V^T of F (Time Reversal,
+        the approxinv relations), and Lambda~ with its transpose on either
+        thin slab (the lamtilde and lamtransp formulas).
 
 Readings where the paper is silent or inconsistent are listed with the
 design notes; the ones that change results here are: the Euclidean normal
@@ -115,6 +119,52 @@ class Model:
         hb, _ = adjoint(self.full, self.prob.nt, h_line=self.h_line,
                         rec_p=(self.r_line, r))
         return hb
+
+    # -- V and the time-reversal inverse ---------------------------------------
+    def _v_lines(self):
+        p, g = self.prob, self.full
+        return g.vz_line(p.z_src, p.x_src0, p.ns), g.vz_line(p.z_rec, p.x_rec0, p.nr)
+
+    def fwd_v(self, f):
+        """y = V f (the vdef operator): normal load f [nt][ns] on z_s, normal
+        velocity traces [nt][nr] recorded on z_r."""
+        fl, rl = self._v_lines()
+        _, V = forward(self.full, self.prob.nt, f_src=(fl, f), rec_v=rl)
+        return V
+
+    def adj_v(self, r):
+        """g = V^T r: r [nt][nr] enters the normal-velocity trace slot on
+        z_r; g [nt][ns] is read from the normal-load slot on z_s."""
+        fl, rl = self._v_lines()
+        _, fb = adjoint(self.full, self.prob.nt, f_line=fl, rec_v=(rl, r))
+        return fb
+
+    def tr_inverse(self, d):
+        """The time-reversal approximate inverse of F (the approxinv
+        relations, V^T F ~ I/4): h = 4 V^T d.  (The normal velocity radiated
+        by a normal load has the same sign on both sides of the load, so no
+        sign depends on whether the receivers lie above or below.)"""
+        return 4.0 * self.adj_v(d)
+
+    def lam(self, x, side: str = "s", transpose: bool = False):
+        """Lambda~ of the lamtilde formula on a thin slab (side "s": the
+        source-side slab; "r": the receiver-side one), or its transpose
+        (lamtransp): 2 s X^T (0, P) or 2 s X^T (V, 0) with (P, V) = X x and
+        s the slab's scale, so that half their sum is that slab's
+        symmetrised operator (W^-1 or W_d)."""
+        if side == "s":
+            g, f_line, d_p, d_v = self.slab()
+            dz = self.prob.slab_dz
+        else:
+            g, f_line, d_p, d_v = self.rslab()
+            dz = self.prob.rslab_dz
+        nt = self.prob.nt
+        P, V = forward(g, nt, f_src=(f_line, x), rec_p=d_p, rec_v=d_v)
+        if transpose:
+            _, fb = adjoint(g, nt, f_line=f_line, rec_p=(d_p, V))
+        else:
+            _, fb = adjoint(g, nt, f_line=f_line, rec_v=(d_v, P))
+        return 8.0 * math.copysign(1.0, dz) * fb
 
     # -- thin-slab vector operator X = Pi-projected S on the slab -------------
     def slab_fwd(self, f):

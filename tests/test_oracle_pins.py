@@ -588,3 +588,83 @@ def test_weighted_pcg_iterates_are_krylov_projections():
         hk, _ = oracle.pcg_solve_w(m, d, alpha, k, use_precond=False)
         ref = _krylov_minimiser(Nw, np.eye(n), b, k)
         assert np.linalg.norm(hk.ravel() - ref) <= 1e-9 * np.linalg.norm(ref), k
+
+
+# ---------------------------------------------------------------------------
+# P12: V, the time-reversal inverse and Lambda~ (Time Reversal: the
+# approxinv relations; Unitarity: the sv relation; Computing and
+# Symmetrizing Lambda: lamtilde, lamtransp, winvcomp)
+
+def test_v_and_lambda_transposes():
+    prob = tiny_problem(nz=16, nx=20, L=5, nt=30, ns=16, nr=14, slab_dz=3, rslab_dz=-2,
+                        z_src=50.0, z_rec=120.0)
+    m = oracle.Model(prob, tiny_kappa(prob, 41), RHO)
+    rng = np.random.default_rng(42)
+    f = rng.standard_normal((prob.nt, prob.ns))
+    r = rng.standard_normal((prob.nt, prob.nr))
+    Vf, Vtr = m.fwd_v(f), m.adj_v(r)
+    assert abs(np.sum(Vf * r) - np.sum(f * Vtr)) <= 1e-13 * np.linalg.norm(Vf) * np.linalg.norm(r)
+    for side, n in (("s", prob.ns), ("r", prob.nr)):
+        x = rng.standard_normal((prob.nt, n))
+        y = rng.standard_normal((prob.nt, n))
+        Lx, LTy = m.lam(x, side), m.lam(y, side, transpose=True)
+        assert abs(np.sum(Lx * y) - np.sum(x * LTy)) <= 1e-13 * np.linalg.norm(Lx) * np.linalg.norm(y)
+        # winvcomp: half the sum of Lambda~ and its transpose is the
+        # symmetrised operator computed with the datum exchange
+        sym = 0.5 * (m.lam(x, side) + m.lam(x, side, transpose=True))
+        ref = m.winv(x) if side == "s" else m.wd(x)
+        assert np.linalg.norm(sym - ref) <= 1e-13 * np.linalg.norm(ref)
+        # and Lambda~ itself is not symmetric on this grid
+        assert np.linalg.norm(Lx - m.lam(x, side, transpose=True)) > 1e-3 * np.linalg.norm(Lx)
+
+
+def _v_plane_errors(h, down, f=10.0, c1=2000.0, c2=2500.0):
+    # source line in c1, receivers in c2, the interface between them;
+    # down: receivers below the sources, else above (layers mirrored)
+    nz, nx = int(600 / h), int(2000 / h) + 1
+    dt = 0.2 * h / c2
+    vel = np.full((nz, nx), c1)
+    if down:
+        vel[int(250 / h):, :] = c2
+        zs, zr = 150.0, 400.0
+    else:
+        vel[:int(350 / h), :] = c2
+        zs, zr = 450.0, 200.0
+    prob = inputs.Problem(nz=nz, nx=nx, h=h, dt=dt, nt=int(0.5 / dt), order=4, npml=20,
+                          z_src=zs, x_src0=0.0, ns=nx, z_rec=zr, x_rec0=50.0,
+                          nr=nx - int(100 / h), slab_dz=5, xs=(1000.0,), rslab_dz=-5)
+    m = oracle.Model(prob, inputs.kappa_from_velocity(vel, RHO), RHO)
+    w = inputs.ricker((np.arange(prob.nt) + 0.5) * prob.dt, f)
+    x = np.repeat(w[:, None], prob.ns, axis=1)
+    jr, jc = int(round((1000.0 - prob.x_rec0) / h)), prob.ns // 2
+    Z1, Z2 = RHO * c1, RHO * c2
+    Vx = m.fwd_v(x)[:, jr]
+    Fx = m.fwd(x)
+    # peak values: the traces' timing conventions differ by fractions of a
+    # step (pressure at whole steps, velocity at half steps), so whole-trace
+    # differences would converge at first order only
+
+    def peak(y):
+        return y[np.argmax(np.abs(y))]
+
+    # V on a plane wave: the transmitted normal velocity f / (Z1 + Z2), of the
+    # same sign whichever way the wave travels (v_z is even across a normal
+    # load)
+    ev = peak(Vx) * (Z1 + Z2) / peak(w) - 1.0
+    # 4 V^T F: the energy transmission coefficient (approxinv, exact in 1D)
+    T = 4 * Z1 * Z2 / (Z1 + Z2) ** 2
+    et = peak(m.tr_inverse(Fx)[:, jc]) / (T * peak(w)) - 1.0
+    # sv: 1/4 Lambda_r F Lambda_s = V
+    es = peak(0.25 * m.lam(m.fwd(m.lam(x, "s")), "r")[:, jr]) / peak(Vx) - 1.0
+    return abs(ev), abs(et), abs(es)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("down", [True, False])
+def test_plane_wave_v_time_reversal_and_sv(down):
+    e10 = _v_plane_errors(10.0, down)
+    e5 = _v_plane_errors(5.0, down)
+    print(f"down={down}: V / 4V^T F / sv errors h=10 {e10}, h=5 {e5}")
+    for a, b in zip(e10, e5):
+        assert b < 0.025
+        assert math.log2(a / b) > 1.5
