@@ -228,6 +228,35 @@ ssx_status ssx_pcg_solve_w(ssx_ctx* ctx, const void* d, double alpha, int32_t ma
                            double rtol, int32_t use_precond, void* h_out,
                            double* hist_host, int32_t* iters_host);
 
+/* ---- V, the time-reversal inverse and Lambda~ (Time Reversal, Unitarity,
+ * Computing and Symmetrizing Lambda). */
+
+/* y = V f (eqn vdef): normal load f on the source line (normal-velocity
+ * rows at z_src), normal velocity sampled on the receiver line (rows at
+ * z_rec); one full simulation.  f: [nshots][nt][ns] -> y: [nshots][nt][nr].
+ * SSX_ERR_ARG when z_src or z_rec has no pair of normal-velocity rows
+ * inside the physical grid (a line on its last row). */
+ssx_status ssx_fwd_v(ssx_ctx* ctx, const void* f, void* y);
+
+/* g = V^T r, the exact transpose of ssx_fwd_v (reverse-time sweep).
+ * r: [nshots][nt][nr] -> g: [nshots][nt][ns]. */
+ssx_status ssx_adj_v(ssx_ctx* ctx, const void* r, void* g);
+
+/* h = 4 V^T d: the time-reversal approximate inverse of F (eqn approxinv,
+ * V^T F ~ I/4 for downgoing fields; the normal velocity of a normal load
+ * has the same sign on both of its sides, so the factor does not depend on
+ * whether the receivers lie above or below the sources).
+ * d: [nshots][nt][nr] -> h: [nshots][nt][ns]. */
+ssx_status ssx_tr_inverse(ssx_ctx* ctx, const void* d, void* h);
+
+/* y = Lambda~ x (eqn lamtilde) or, with transpose != 0, its transpose (eqn
+ * lamtransp), on the source-side slab (side 0, x and y [nshots][nt][ns]) or
+ * the receiver-side one (side 1, [nshots][nt][nr]; needs rslab_dz != 0):
+ * 2 s X^T (0, P) or 2 s X^T (V, 0) with (P, V) = X x and s = 4 sign(dz) of
+ * that slab, so that half the sum of the two is ssx_precond's W^-1 (side 0,
+ * alpha_hat = 0) or W_d (side 1), eqn winvcomp.  Two slab simulations. */
+ssx_status ssx_lambda(ssx_ctx* ctx, int32_t side, int32_t transpose, const void* x, void* y);
+
 /* Execution options (results do not depend on them, see each value):
  *   SSX_OPT_GRAPHS      1 (default): replay each whole propagation as a
  *                       captured HIP graph; 0: plain stream launches.

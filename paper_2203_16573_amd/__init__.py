@@ -19,6 +19,10 @@ Function names follow the C ABI (include/ssx.h):
     ctx.weight_m(x, y)     y = W_m x   (source-side slab)
     ctx.normal_w(alpha, p, q, Fp=None)
     ctx.pcg_solve_w(d, alpha, maxit, ...) -> (h, hist, iters, status)
+    ctx.fwd_v(f, y)        y = V f
+    ctx.adj_v(r, g)        g = V^T r
+    ctx.tr_inverse(d, h)   h = 4 V^T d (time-reversal inverse of F)
+    ctx.lam(side, transpose, x, y)   y = Lambda~ x or its transpose
 
 ``prob`` is any object with the fields of ``ssx_problem`` (nz, nx, h, dt,
 nt, order, npml, pml_R, z_src, x_src0, ns, z_rec, x_rec0, nr, slab_dz and,
@@ -48,7 +52,8 @@ EXPORTS = ("ssx_validate", "ssx_footprint", "ssx_create", "ssx_destroy", "ssx_fw
            "ssx_adj", "ssx_slab_fwd", "ssx_slab_adj", "ssx_penalty", "ssx_precond",
            "ssx_normal", "ssx_dot", "ssx_pcg_solve", "ssx_set_option", "ssx_last_error",
            "ssx_step_kernel_name", "ssx_cells_per_launch", "ssx_launch_shape",
-           "ssx_weight_d", "ssx_weight_m", "ssx_normal_w", "ssx_pcg_solve_w")
+           "ssx_weight_d", "ssx_weight_m", "ssx_normal_w", "ssx_pcg_solve_w",
+           "ssx_fwd_v", "ssx_adj_v", "ssx_tr_inverse", "ssx_lambda")
 
 
 class SSXError(RuntimeError):
@@ -107,6 +112,10 @@ def lib():
         L.ssx_weight_m.argtypes = [vp, vp, vp]
         L.ssx_normal_w.argtypes = [vp, c_dbl, vp, vp, vp]
         L.ssx_pcg_solve_w.argtypes = L.ssx_pcg_solve.argtypes
+        L.ssx_fwd_v.argtypes = [vp, vp, vp]
+        L.ssx_adj_v.argtypes = [vp, vp, vp]
+        L.ssx_tr_inverse.argtypes = [vp, vp, vp]
+        L.ssx_lambda.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp]
         L.ssx_set_option.argtypes = [vp, c_int, c_int]
         L.ssx_last_error.restype = ctypes.c_char_p
         L.ssx_step_kernel_name.argtypes = [vp]
@@ -293,6 +302,28 @@ class Context:
         Returns (h, hist [nshots][maxit+1][4], iterations, status)."""
         return self._pcg(lib().ssx_pcg_solve_w, d, alpha, maxit, rtol, use_precond, h,
                          raise_on_breakdown)
+
+    # -- V, time-reversal inverse, Lambda~ --------------------------------------
+    def fwd_v(self, f, y):
+        _check(lib().ssx_fwd_v(self._ctx, self._vec(f, self.n_s, "f"), self._vec(y, self.n_r, "y")))
+        return y
+
+    def adj_v(self, r, g):
+        _check(lib().ssx_adj_v(self._ctx, self._vec(r, self.n_r, "r"), self._vec(g, self.n_s, "g")))
+        return g
+
+    def tr_inverse(self, d, h):
+        _check(lib().ssx_tr_inverse(self._ctx, self._vec(d, self.n_r, "d"),
+                                    self._vec(h, self.n_s, "h")))
+        return h
+
+    def lam(self, side, transpose, x, y):
+        """side 0: source-side slab ([nshots][nt][ns]); 1: receiver-side
+        slab ([nshots][nt][nr])."""
+        n = self.n_s if int(side) == 0 else self.n_r
+        _check(lib().ssx_lambda(self._ctx, int(side), int(bool(transpose)), self._vec(x, n, "x"),
+                                self._vec(y, n, "y")))
+        return y
 
     def set_option(self, option: int, value: int):
         _check(lib().ssx_set_option(self._ctx, int(option), int(value)))

@@ -295,6 +295,10 @@ struct ssx_ctx {
   bool has_rslab = false;
   GridDev rslab;
   LineDev rf_line, rdp_line, rdv_line;
+  // full grid: normal-load line at z_s and normal-velocity line at z_r (V);
+  // absent when either depth leaves no v_z row pair inside the grid
+  bool has_v = false;
+  LineDev fv_line, rv_line;
   double* xs_dev;
   // vectors: [nshots][nt][ns] (s) or [nshots][nt][nr] (r)
   void *r, *g, *p, *q, *t1, *sP, *sV, *sF;  // s-vectors
@@ -724,7 +728,9 @@ void drop_graphs(ssx_ctx* c) {
 
 enum {
   OP_FWD = 0, OP_ADJ = 1, OP_SLAB_FWD = 2, OP_SLAB_ADJ = 3,
-  OP_RSLAB_FWD = 4, OP_RSLAB_ADJ = 5, OP_SLABP_FWD = 6, OP_SLABP_ADJ = 7
+  OP_RSLAB_FWD = 4, OP_RSLAB_ADJ = 5, OP_SLABP_FWD = 6, OP_SLABP_ADJ = 7,
+  OP_V_FWD = 8, OP_V_ADJ = 9, OP_LAM_ADJ = 10, OP_LAMT_ADJ = 11, OP_RLAM_ADJ = 12,
+  OP_RLAMT_ADJ = 13, OP_TR_INV = 14
 };
 
 ssx_status do_fwd(ssx_ctx* c, const void* h, void* d) {
@@ -803,6 +809,48 @@ ssx_status do_wm(ssx_ctx* c, const void* x, void* y) {
   return propagate(c, OP_SLABP_ADJ, c->slab, true, c->hp_line, io_out(y, st, sm), c->dv_line,
                    io_in(c->sP, st, 1.0), c->dv_line, io_none(), c->dp_line,
                    io_in(c->sV, st, c->Z0));
+}
+
+// y = V f: normal load on z_s, normal velocity sampled on z_r (full grid).
+ssx_status do_fwd_v(ssx_ctx* c, const void* f, void* y) {
+  const ssx_problem& p = c->prob;
+  return propagate(c, OP_V_FWD, c->full, false, c->r_line, io_none(), c->fv_line,
+                   io_in(f, nvec_s(p), 1.0 / c->Z0), c->rv_line, io_out(y, nvec_r(p), 1.0),
+                   c->h_line, io_none());
+}
+
+// g = V^T r (inverse = false) or 4 V^T r: r enters the normal-velocity slot
+// on z_r, g is read from the normal-load slot on z_s.  (A captured graph
+// holds its scales, so the two forms are distinct operations.)
+ssx_status do_adj_v(ssx_ctx* c, const void* r, void* g, bool inverse) {
+  const ssx_problem& p = c->prob;
+  const double scale = inverse ? 4.0 : 1.0;
+  return propagate(c, inverse ? OP_TR_INV : OP_V_ADJ, c->full, true, c->h_line, io_none(), c->rv_line,
+                   io_in(r, nvec_r(p), 1.0), c->fv_line, io_out(g, nvec_s(p), scale / c->Z0),
+                   c->r_line, io_none());
+}
+
+// y = Lambda~ x (transpose: its transpose) on the source-side slab (side 0)
+// or the receiver-side one (side 1): 2 s X^T (0, P) or 2 s X^T (V, 0) with
+// (P, V) = X x and s = 4 sign(dz) of that slab.
+ssx_status do_lambda(ssx_ctx* c, int side, bool transpose, const void* x, void* y) {
+  const ssx_problem& p = c->prob;
+  const bool src = side == 0;
+  GridDev& g = src ? c->slab : c->rslab;
+  const LineDev& fl = src ? c->f_line : c->rf_line;
+  const LineDev& dp = src ? c->dp_line : c->rdp_line;
+  const LineDev& dv = src ? c->dv_line : c->rdv_line;
+  void* P = src ? c->sP : c->rP;
+  void* V = src ? c->sV : c->rV;
+  const long long st = src ? nvec_s(p) : nvec_r(p);
+  const double s2 = ((src ? p.slab_dz : p.rslab_dz) > 0 ? 8.0 : -8.0) / c->Z0;
+  SSX_TRY(propagate(c, src ? OP_SLAB_FWD : OP_RSLAB_FWD, g, false, dp, io_out(P, st, c->Z0), fl,
+                    io_in(x, st, 1.0 / c->Z0), dv, io_out(V, st, 1.0), dp, io_none()));
+  if (!transpose)
+    return propagate(c, src ? OP_LAM_ADJ : OP_RLAM_ADJ, g, true, dp, io_none(), dv,
+                     io_in(P, st, 1.0), fl, io_out(y, st, s2), dp, io_none());
+  return propagate(c, src ? OP_LAMT_ADJ : OP_RLAMT_ADJ, g, true, dp, io_none(), dv, io_none(), fl,
+                   io_out(y, st, s2), dp, io_in(V, st, c->Z0));
 }
 
 // q = F^T W_d F p + alpha^2 A^T W_m A p, Fp = F p (the W_m term only when
@@ -935,6 +983,8 @@ ssx_status ssx_create(const ssx_problem* prob, const double* kappa_host, double 
   make_line(zs + p.slab_dz * p.h, p.x_src0, p.ns, p.h, L, nzs, p.nx, true, &c->dp_line, &why);
   make_line(zs + p.slab_dz * p.h, p.x_src0, p.ns, p.h, L, nzs, p.nx, false, &c->dv_line, &why);
   make_line(zs, p.x_src0, p.ns, p.h, L, nzs, p.nx, true, &c->hp_line, &why);
+  c->has_v = make_line(p.z_src, p.x_src0, p.ns, p.h, L, p.nz, p.nx, false, &c->fv_line, &why) &&
+             make_line(p.z_rec, p.x_rec0, p.nr, p.h, L, p.nz, p.nx, false, &c->rv_line, &why);
   if (c->has_rslab) {
     const int nzr = r_hi - r_lo + 1;
     make_line(zr, p.x_rec0, p.nr, p.h, L, nzr, p.nx, false, &c->rf_line, &why);
@@ -942,12 +992,14 @@ ssx_status ssx_create(const ssx_problem* prob, const double* kappa_host, double 
     make_line(zr + p.rslab_dz * p.h, p.x_rec0, p.nr, p.h, L, nzr, p.nx, false, &c->rdv_line,
               &why);
   }
-  // full-grid tile lists for tile-loop launches (its lines: source, receivers)
+  // full-grid tile lists for tile-loop launches (its lines: source and
+  // receivers on p nodes and, for V, on v_z nodes)
   {
-    const LineDev* lines[2] = {&c->h_line, &c->r_line};
+    const LineDev* lines[4] = {&c->h_line, &c->r_line, &c->fv_line, &c->rv_line};
+    const int nlines = c->has_v ? 4 : 2;
     for (int i = 0; i < 3; ++i) {
       std::vector<int> gen, inter;
-      step_tile_lists(p.order, 8 << i, c->full.dims, lines, 2, &gen, &inter);
+      step_tile_lists(p.order, 8 << i, c->full.dims, lines, nlines, &gen, &inter);
       c->full.ngen[i] = (int)gen.size();
       c->full.nint[i] = (int)inter.size();
       c->full.tiles_host[i] = gen;
@@ -1188,6 +1240,32 @@ ssx_status ssx_pcg_solve_w(ssx_ctx* c, const void* d, double alpha, int32_t maxi
   if (maxit < 0 || maxit > HIST_CAP) return fail(SSX_ERR_ARG, "maxit out of range");
   if (!std::isfinite(alpha) || alpha < 0) return fail(SSX_ERR_ARG, "alpha must be >= 0");
   return run_pcg(c, true, d, alpha, maxit, rtol, use_precond, h_out, hist_host, iters_host);
+}
+
+ssx_status ssx_fwd_v(ssx_ctx* c, const void* f, void* y) {
+  if (!c || !f || !y) return fail(SSX_ERR_ARG, "null argument");
+  if (!c->has_v) return fail(SSX_ERR_ARG, "no normal-velocity rows at the source or receiver depth");
+  return do_fwd_v(c, f, y);
+}
+
+ssx_status ssx_adj_v(ssx_ctx* c, const void* r, void* g) {
+  if (!c || !r || !g) return fail(SSX_ERR_ARG, "null argument");
+  if (!c->has_v) return fail(SSX_ERR_ARG, "no normal-velocity rows at the source or receiver depth");
+  return do_adj_v(c, r, g, false);
+}
+
+ssx_status ssx_tr_inverse(ssx_ctx* c, const void* d, void* h) {
+  if (!c || !d || !h) return fail(SSX_ERR_ARG, "null argument");
+  if (!c->has_v) return fail(SSX_ERR_ARG, "no normal-velocity rows at the source or receiver depth");
+  return do_adj_v(c, d, h, true);
+}
+
+ssx_status ssx_lambda(ssx_ctx* c, int32_t side, int32_t transpose, const void* x, void* y) {
+  if (!c || !x || !y) return fail(SSX_ERR_ARG, "null argument");
+  if (side != 0 && side != 1) return fail(SSX_ERR_ARG, "side must be 0 (source) or 1 (receiver)");
+  if (side == 1 && !c->has_rslab)
+    return fail(SSX_ERR_ARG, "context has no receiver-side slab (rslab_dz == 0)");
+  return do_lambda(c, side, transpose != 0, x, y);
 }
 
 ssx_status ssx_set_option(ssx_ctx* c, int option, int value) {
