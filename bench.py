@@ -326,8 +326,13 @@ def crosswell_bench(args):
     M^-1 = D W^-1 D.  For each alpha in {0, --alpha} the line reports the
     relative normal-residual curves (CG: ||r_k||; PCG: ||M^-1 r_k||, the
     left side of the norm1 form), the iterations each needs to reduce it by
-    10x, 100x and 1000x, and the data misfit; then it times repeated weighted
-    solves (--steps, after --warmup)."""
+    10x, 100x and 1000x, and the data misfit.  It also reports the paper's
+    operator checks as relative misfits: re-simulation of the time-reversal
+    inverse 4 V^T d and of the unitary-norm inverse W^-1 F^T W_d d, the
+    asymmetry of Lambda~ and the sv relation 1/4 Lambda_r F Lambda_s = V on
+    the pressure gather that the point source leaves on z = 3000 m (all in
+    the homogeneous model).  Then it times repeated weighted solves
+    (--steps, after --warmup)."""
     import numpy as np
     import torch
 
@@ -375,6 +380,32 @@ def crosswell_bench(args):
                                        "ratio": round(a / b, 2) if a and b else None}
         comparison[f"alpha={alpha:g}"] = entry
 
+    def nrm(t):
+        return float(torch.linalg.norm(t.double()))
+
+    # the point source's pressure gather on the source line, homogeneous model
+    gprob = pprob.replace(z_rec=prob.z_src, x_rec0=prob.x_src0, nr=prob.ns)
+    gctx = ssx.Context(gprob, inputs.crosswell_kappa(lens=False), rho, field_dtype=fd)
+    ps = gctx.fwd(hpt, gctx.empty_r()).clone()
+    torch.cuda.synchronize()
+    gctx.close()
+    Fh = ctx.empty_r()
+    h_tr = ctx.tr_inverse(d, ctx.empty_s())
+    mis_tr = nrm(ctx.fwd(h_tr, Fh) - d) / dn
+    h_u = ctx.precond(0.0, ctx.adj(ctx.weight_d(d, ctx.empty_r()), ctx.empty_s()), ctx.empty_s())
+    mis_u = nrm(ctx.fwd(h_u, Fh) - d) / dn
+    lam = ctx.lam(0, False, ps, ctx.empty_s()).clone()
+    lamt = ctx.lam(0, True, ps, ctx.empty_s())
+    asym = nrm(lam - lamt) / nrm(lam)
+    sv = 0.25 * ctx.lam(1, False, ctx.fwd(lam, ctx.empty_r()), ctx.empty_r())
+    vx = ctx.fwd_v(ps, ctx.empty_r())
+    sv_mis = nrm(sv - vx) / nrm(vx)
+    checks = {"time_reversal_resimulation_misfit": round(mis_tr, 4),
+              "unitary_inverse_resimulation_misfit": round(mis_u, 4),
+              "lambda_asymmetry": round(asym, 4),
+              "sv_relation_misfit": round(sv_mis, 4),
+              "input": "pressure gather of the point source on z = 3000 m (homogeneous model)"}
+
     h = ctx.empty_s()
     for _ in range(args.warmup):
         ctx.pcg_solve_w(d, args.alpha, K, h=h, raise_on_breakdown=False)
@@ -396,6 +427,7 @@ def crosswell_bench(args):
                    "nz": prob.nz, "nx": prob.nx, "nt": prob.nt, "K": K, "field_dtype": fd},
         "ms_per_iteration": round(1e3 * el / (args.steps * K), 3),
         "cg_vs_pcg": comparison,
+        "operator_checks": checks,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
