@@ -32,8 +32,10 @@
  *    float otherwise).  Trace arrays are [nshots][nt][n] with the trace
  *    index fastest.  The library never frees caller memory and keeps no
  *    reference to it after the call returns.
- *  - All device work is ordered on the stream given to ssx_create; calls
- *    return before the work finishes unless stated otherwise.
+ *  - All device work is ordered on the stream given to ssx_create (work
+ *    the library forks to a stream of its own is joined back into it
+ *    before the call returns, see SSX_OPT_OVERLAP); calls return before the
+ *    work finishes unless stated otherwise.
  *  - Inputs and outputs must not overlap unless stated otherwise.
  *  - Errors are returned as ssx_status; no exception crosses the ABI.  On an
  *    error the outputs are unspecified and the context stays usable, except
@@ -296,6 +298,12 @@ ssx_status ssx_lambda(ssx_ctx* ctx, int32_t side, int32_t transpose, const void*
  *                       computes the current one; a value of 8 or more
  *                       also caps that set at the value rounded down to a
  *                       multiple of 8.
+ *   SSX_OPT_OVERLAP     1 (default): the weighted normal operator runs its
+ *                       model-space term (W_m, two slab simulations) on a
+ *                       second stream of the library's, concurrently with
+ *                       F, W_d and F^T, and joins it into the context's
+ *                       stream before summing; 0: all on the context's
+ *                       stream.
  * Returns SSX_ERR_ARG for an unknown option or value. */
 typedef enum {
   SSX_OPT_GRAPHS = 0,
@@ -307,7 +315,8 @@ typedef enum {
   SSX_OPT_SHOT_GROUP = 6,
   SSX_OPT_SHOT_GROUP_SLAB = 7,
   SSX_OPT_SLAB_STRIP = 8,
-  SSX_OPT_TILE_LOOP = 9
+  SSX_OPT_TILE_LOOP = 9,
+  SSX_OPT_OVERLAP = 10
 } ssx_option;
 ssx_status ssx_set_option(ssx_ctx* ctx, int option, int value);
 

@@ -263,6 +263,11 @@ struct GridDev {
   Fields fields1;  // buffer 1 (fused kernel writes step n+1 here, then swaps)
   void* field_block;
   size_t field_bytes;
+  // 16-bit fields: per-shot field scale of the grid's current propagation
+  // and its partial maxima ([2][nshots][NBLK_DOT]); one set per grid, so
+  // propagations on different grids may run concurrently
+  float* dyn = nullptr;
+  float* amax_part = nullptr;
   // tile lists of the one-step kernel's tile-loop launches, per tile height
   // 8, 16, 32 (index tz / 16): general tiles, then interior ones
   std::vector<int> tiles_host[3];
@@ -307,8 +312,6 @@ struct ssx_ctx {
   double* sc;
   double* partial;
   double* hist;
-  float* dyn;          // [nshots] field scale of the current propagation (16-bit fields)
-  float* amax_part;    // [2][nshots][NBLK_DOT]
   void* own = nullptr;  // device block allocated by the library (null if workspace)
   bool graphs = true;
   bool fused = true;
@@ -317,7 +320,13 @@ struct ssx_ctx {
   int group_full = 0, group_slab = 0;    // shots per launch (0: from the cache budget)
   int slab_strip = 0;                    // strip width of the multi-step slab kernel (0: 128)
   int loop_full = 0;                     // full-grid one-step kernel: tile loop (0 off)
-  hipStream_t cap_stream = nullptr;      // capture stream (graphs are launched on `stream`)
+  hipStream_t cap_stream = nullptr;      // capture stream (graphs are launched on `run`)
+  // stream that propagate() issues on: `stream`, or `aux` while the weighted
+  // normal operator runs its model-space term beside the data-space chain
+  hipStream_t run = nullptr;
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool overlap = true;                   // SSX_OPT_OVERLAP
   std::vector<GraphEntry> graphs_cache;
   unsigned long long use_clock = 0;
 };
@@ -350,6 +359,8 @@ void layout(ssx_ctx* c, const GridHost& fg, const GridHost& sg, const GridHost* 
     gd.fields1.vx = fb ? fb + 5 * one : nullptr;
     gd.fields1.vz = fb ? fb + 6 * one : nullptr;
     gd.fields1.aux = fb ? fb + 7 * one : nullptr;
+    gd.dyn = (float*)a.take((size_t)ns * 4);
+    gd.amax_part = (float*)a.take((size_t)2 * ns * NBLK_DOT * 4);
     gd.coef.ck = a.take((size_t)gh.field_elems * csz);
     gd.coef.pml = a.take((4 * (size_t)gh.pitch + 4 * (size_t)(gh.NZ + 2 * PZ)) * csz);
     for (int i = 0; i < 3; ++i) {
@@ -373,8 +384,6 @@ void layout(ssx_ctx* c, const GridHost& fg, const GridHost& sg, const GridHost* 
   c->sc = (double*)a.take((size_t)ns * SC_N * 8);
   c->partial = (double*)a.take((size_t)ns * NBLK_DOT * 3 * 8);
   c->hist = (double*)a.take((size_t)ns * (HIST_CAP + 1) * 4 * 8);
-  c->dyn = (float*)a.take((size_t)ns * 4);
-  c->amax_part = (float*)a.take((size_t)2 * ns * NBLK_DOT * 4);
   *total = a.off + 256;
 }
 
@@ -643,8 +652,8 @@ ssx_status issue_propagation(ssx_ctx* c, GridDev& gd, bool adj, const LineDev& v
     const long long nin = (pi.in ? pi.shot_stride : vi.shot_stride);
     if (ia) {
       if (ib && vi.shot_stride != nin) return fail(SSX_ERR_ARG, "mismatched trace inputs");
-      SSX_HIP(launch_field_scale(c->vdbl, ia, sa, ib, vi.scale, nin, ns, c->amax_part, c->dyn, s));
-      vs.dyn = vi.dyn = ps.dyn = pi.dyn = c->dyn;
+      SSX_HIP(launch_field_scale(c->vdbl, ia, sa, ib, vi.scale, nin, ns, gd.amax_part, gd.dyn, s));
+      vs.dyn = vi.dyn = ps.dyn = pi.dyn = gd.dyn;
     }
   }
   const int G = shot_group(c, gd);
@@ -667,7 +676,7 @@ ssx_status propagate(ssx_ctx* c, int op, GridDev& gd, bool adj, const LineDev& v
                      const LineDev& vil, TraceIO vi, const LineDev& psl, TraceIO ps,
                      const LineDev& pil, TraceIO pi) {
   if (!c->graphs)
-    return issue_propagation(c, gd, adj, vsl, vs, vil, vi, psl, ps, pil, pi, c->stream);
+    return issue_propagation(c, gd, adj, vsl, vs, vil, vi, psl, ps, pil, pi, c->run);
   const void* key[4] = {vs.out, vi.in, ps.out, pi.in};
   const int tz = (&gd == &c->full) ? c->tile_z_full : c->tile_z_slab;
   const int spl = (&gd == &c->full) ? c->spl_full : c->spl_slab;
@@ -679,7 +688,7 @@ ssx_status propagate(ssx_ctx* c, int op, GridDev& gd, bool adj, const LineDev& v
         e.ptr[3] == key[3] && e.tile_z == tz && e.fused == (int)c->fused && e.spl == spl &&
         e.group == group && e.strip == strip && e.loop == loop) {
       e.last_use = ++c->use_clock;
-      SSX_HIP(hipGraphLaunch(e.exec, c->stream));
+      SSX_HIP(hipGraphLaunch(e.exec, c->run));
       return SSX_OK;
     }
   }
@@ -717,7 +726,7 @@ ssx_status propagate(ssx_ctx* c, int op, GridDev& gd, bool adj, const LineDev& v
   ge.exec = exec;
   ge.last_use = ++c->use_clock;
   c->graphs_cache.push_back(ge);
-  SSX_HIP(hipGraphLaunch(exec, c->stream));
+  SSX_HIP(hipGraphLaunch(exec, c->run));
   return SSX_OK;
 }
 
@@ -853,18 +862,46 @@ ssx_status do_lambda(ssx_ctx* c, int side, bool transpose, const void* x, void* 
                    io_out(y, st, s2), dp, io_in(V, st, c->Z0));
 }
 
+// The model-space term of do_normal_w, sF = W_m A p, issued on stream s.
+ssx_status wm_term(ssx_ctx* c, const void* p, hipStream_t s) {
+  const ssx_problem& pr = c->prob;
+  SSX_HIP(launch_diag(c->vdbl, 0, 0.0, 1.0, p, c->t1, pr.nt, pr.ns, pr.nshots, pr.x_src0, pr.h,
+                      c->xs_dev, s));
+  c->run = s;
+  const ssx_status st = do_wm(c, c->t1, c->sF);
+  c->run = c->stream;
+  return st;
+}
+
 // q = F^T W_d F p + alpha^2 A^T W_m A p, Fp = F p (the W_m term only when
-// with_m); alpha^2 as in do_normal.  Uses rW, rP, rV, t1, sF, sP, sV.
+// with_m); alpha^2 as in do_normal.  The W_m term (t1, sF, sP, sV and the
+// source-side slab) shares no buffer with the F, W_d, F^T chain (Fp, rW, rP,
+// rV, q, the full grid and the receiver-side slab), so with overlap on it
+// runs on a second stream, forked after p is ready and joined before the
+// two terms are summed; the results do not depend on it.
 ssx_status do_normal_w(ssx_ctx* c, const double* alpha2_dev, double alpha2_host, bool with_m,
                        const void* p, void* q, void* Fp) {
   const ssx_problem& pr = c->prob;
+  const bool fork = with_m && c->overlap;
+  if (fork) {
+    if (!c->aux) {
+      SSX_HIP(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+      SSX_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+      SSX_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    }
+    SSX_HIP(hipEventRecord(c->ev_fork, c->stream));
+    SSX_HIP(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
+    SSX_TRY(wm_term(c, p, c->aux));
+    SSX_HIP(hipEventRecord(c->ev_join, c->aux));
+  }
   SSX_TRY(do_fwd(c, p, Fp));
   SSX_TRY(do_wd(c, Fp, c->rW));
   SSX_TRY(do_adj(c, c->rW, q));
   if (with_m) {
-    SSX_HIP(launch_diag(c->vdbl, 0, 0.0, 1.0, p, c->t1, pr.nt, pr.ns, pr.nshots, pr.x_src0,
-                        pr.h, c->xs_dev, c->stream));
-    SSX_TRY(do_wm(c, c->t1, c->sF));
+    if (fork)
+      SSX_HIP(hipStreamWaitEvent(c->stream, c->ev_join, 0));
+    else
+      SSX_TRY(wm_term(c, p, c->stream));
     SSX_HIP(launch_add_penalty(c->vdbl, q, c->sF, 1, alpha2_dev, SC_N, alpha2_host, pr.nt,
                                pr.ns, pr.nshots, pr.x_src0, pr.h, c->xs_dev, c->stream));
   }
@@ -940,6 +977,7 @@ ssx_status ssx_create(const ssx_problem* prob, const double* kappa_host, double 
   c->csz = p.field_dtype == SSX_F64 ? 8 : 4;
   c->vsz = dtype_size(p.vec_dtype);
   c->stream = (hipStream_t)stream;
+  c->run = c->stream;
   c->rho = rho;
   c->Z0 = rho * cmax;
 
@@ -1053,8 +1091,12 @@ ssx_status ssx_create(const ssx_problem* prob, const double* kappa_host, double 
 void ssx_destroy(ssx_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  if (c->aux) (void)hipStreamSynchronize(c->aux);
   drop_graphs(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->aux) (void)hipStreamDestroy(c->aux);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   if (c->own) (void)hipFree(c->own);
   delete c;
 }
@@ -1321,6 +1363,10 @@ ssx_status ssx_set_option(ssx_ctx* c, int option, int value) {
       if (value != 0 && value != 1 && value < 8)
         return fail(SSX_ERR_ARG, "tile loop must be 0, 1 or at least 8");
       c->loop_full = value;
+      return SSX_OK;
+    case SSX_OPT_OVERLAP:
+      if (value != 0 && value != 1) return fail(SSX_ERR_ARG, "overlap must be 0 or 1");
+      c->overlap = value == 1;
       return SSX_OK;
   }
   return fail(SSX_ERR_ARG, "unknown option");

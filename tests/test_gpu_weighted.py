@@ -247,3 +247,32 @@ def test_weights_symmetric_at_production_size():
         print(f"  symmetry defect {abs(lhs - rhs) / nrm:.2e}")
         assert abs(lhs - rhs) <= 1e-5 * nrm
     ctx.close()
+
+
+@pytest.mark.parametrize("fd", ["f32", "f16"])
+def test_overlap_is_bitwise_neutral(setups, fd):
+    # the model-space term on the second stream gives the same bits as the
+    # same work on the context's stream (16-bit fields: each grid keeps its
+    # own field scales)
+    if fd == "f16":
+        prob = problem(8)
+        kap = kappa(prob)
+        ctx = ssx.Context(prob, kap, RHO, field_dtype="f16")
+    else:
+        prob, m, ctx = setups(8, fd)
+    print(f"case overlap dtype={fd}", flush=True)
+    rng = np.random.default_rng(17)
+    d = dev(rng.standard_normal((2, prob.nt, prob.nr)), "f32")
+    p = dev(rng.standard_normal((2, prob.nt, prob.ns)), "f32")
+    out = {}
+    for ov in (1, 0):
+        ctx.set_option(ssx.OPT_OVERLAP, ov)
+        q = ctx.normal_w(1e-3, p, ctx.empty_s()).clone()
+        h, hist, _, _ = ctx.pcg_solve_w(d, 1e-3, 4)
+        torch.cuda.synchronize()
+        out[ov] = (q.cpu(), h.clone().cpu(), hist)
+    ctx.set_option(ssx.OPT_OVERLAP, 1)
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+    assert np.array_equal(out[0][2], out[1][2])
+    if fd == "f16":
+        ctx.close()
