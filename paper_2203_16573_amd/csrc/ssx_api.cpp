@@ -891,17 +891,22 @@ ssx_status do_normal_w(ssx_ctx* c, const double* alpha2_dev, double alpha2_host,
     }
     SSX_HIP(hipEventRecord(c->ev_fork, c->stream));
     SSX_HIP(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
-    SSX_TRY(wm_term(c, p, c->aux));
+    ssx_status st = wm_term(c, p, c->aux);
     SSX_HIP(hipEventRecord(c->ev_join, c->aux));
+    // the context's stream waits for the second one on every path, so that
+    // no work reading p or writing the scratch vectors outlives the call
+    if (st == SSX_OK) st = do_fwd(c, p, Fp);
+    if (st == SSX_OK) st = do_wd(c, Fp, c->rW);
+    if (st == SSX_OK) st = do_adj(c, c->rW, q);
+    SSX_HIP(hipStreamWaitEvent(c->stream, c->ev_join, 0));
+    if (st != SSX_OK) return st;
+  } else {
+    SSX_TRY(do_fwd(c, p, Fp));
+    SSX_TRY(do_wd(c, Fp, c->rW));
+    SSX_TRY(do_adj(c, c->rW, q));
   }
-  SSX_TRY(do_fwd(c, p, Fp));
-  SSX_TRY(do_wd(c, Fp, c->rW));
-  SSX_TRY(do_adj(c, c->rW, q));
   if (with_m) {
-    if (fork)
-      SSX_HIP(hipStreamWaitEvent(c->stream, c->ev_join, 0));
-    else
-      SSX_TRY(wm_term(c, p, c->stream));
+    if (!fork) SSX_TRY(wm_term(c, p, c->stream));
     SSX_HIP(launch_add_penalty(c->vdbl, q, c->sF, 1, alpha2_dev, SC_N, alpha2_host, pr.nt,
                                pr.ns, pr.nshots, pr.x_src0, pr.h, c->xs_dev, c->stream));
   }
