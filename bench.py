@@ -34,7 +34,7 @@ KERNEL_SOURCES = ("ssx_step.hip", "ssx_cell.h", "ssx_device.h", "ssx_internal.h"
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2",
                     choices=["c1", "c2", "c3", "c4", "c4bf", "c5", "xw"],
@@ -184,10 +184,13 @@ def main():
         solve()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    marks = []
     for _ in range(args.steps):
-        _, hist, iters, st = solve()
+        _, hist, iters, st = solve()   # returns after synchronising the stream
+        marks.append(time.perf_counter())
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    per_step = np.diff([t0] + marks) * 1e3
     solves = args.steps * prob.nshots
     value = solves / elapsed
 
@@ -289,6 +292,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(1e3 * elapsed / args.steps, 2),
+        "ms_per_step_median": round(float(np.median(per_step)), 2),
+        "ms_per_step_range": [round(float(per_step.min()), 2), round(float(per_step.max()), 2)],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
