@@ -23,6 +23,9 @@ TEST INFRASTRUCTURE ONLY -- see the package header.
         the normpart system), W_d the receiver-surface counterpart of W^-1
         and W_m the symmetrised inverse pressure-to-source operator (the
         wcomp formula), both on thin slabs.
+* the four blocks of the vector modelling operator (pressure source or
+        normal load on z_s to pressure or normal velocity on z_r), F and
+        V among them;
 * V   = normal load on z_s to normal velocity on z_r (the vdef operator),
         its transpose, the time-reversal inverse 4 V^T of F (Time Reversal,
         the approxinv relations), and Lambda~ with its transpose on either
@@ -138,6 +141,28 @@ class Model:
         fl, rl = self._v_lines()
         _, fb = adjoint(self.full, self.prob.nt, f_line=fl, rec_v=(rl, r))
         return fb
+
+    def block(self, src: int, rec: int, x, transpose: bool = False):
+        """A block of the vector modelling operator (Operators section: the
+        source vector (h, f) on z = z_s to the traces (P_r p, P_r v_z) on
+        z = z_r): src 0 a pressure source, 1 a normal load on the source
+        line; rec 0 pressure, 1 normal velocity on the receiver line.
+        Block (0, 0) is F, block (1, 1) is V.  With transpose, the exact
+        transpose (x then holds receiver traces)."""
+        p, g = self.prob, self.full
+        s_line = self.h_line if src == 0 else g.vz_line(p.z_src, p.x_src0, p.ns)
+        r_line = self.r_line if rec == 0 else g.vz_line(p.z_rec, p.x_rec0, p.nr)
+        if not transpose:
+            P, V = forward(g, p.nt, h_src=(s_line, x) if src == 0 else None,
+                           f_src=(s_line, x) if src == 1 else None,
+                           rec_p=r_line if rec == 0 else None,
+                           rec_v=r_line if rec == 1 else None)
+            return P if rec == 0 else V
+        hb, fb = adjoint(g, p.nt, h_line=s_line if src == 0 else None,
+                         f_line=s_line if src == 1 else None,
+                         rec_p=(r_line, x) if rec == 0 else None,
+                         rec_v=(r_line, x) if rec == 1 else None)
+        return hb if src == 0 else fb
 
     def tr_inverse(self, d):
         """The time-reversal approximate inverse of F (the approxinv

@@ -668,3 +668,61 @@ def test_plane_wave_v_time_reversal_and_sv(down):
     for a, b in zip(e10, e5):
         assert b < 0.025
         assert math.log2(a / b) > 1.5
+
+
+def test_modelling_operator_blocks():
+    # the four blocks: (0,0) is F and (1,1) is V; every block's transpose
+    # passes the dot test
+    prob = tiny_problem(nz=16, nx=20, L=5, nt=30, ns=16, nr=14, z_src=50.0, z_rec=120.0)
+    m = oracle.Model(prob, tiny_kappa(prob, 43), RHO)
+    rng = np.random.default_rng(44)
+    x = rng.standard_normal((prob.nt, prob.ns))
+    y = rng.standard_normal((prob.nt, prob.nr))
+    assert np.array_equal(m.block(0, 0, x), m.fwd(x))
+    assert np.array_equal(m.block(1, 1, x), m.fwd_v(x))
+    for src in (0, 1):
+        for rec in (0, 1):
+            Bx = m.block(src, rec, x)
+            BTy = m.block(src, rec, y, transpose=True)
+            assert abs(np.sum(Bx * y) - np.sum(x * BTy)) <= 1e-13 * np.linalg.norm(Bx) * np.linalg.norm(y)
+
+
+@pytest.mark.parametrize("down", [True, False])
+def test_plane_wave_off_diagonal_blocks(down):
+    # A pressure source radiates pressure Z1 h / 2 to both sides and normal
+    # velocity of the sign of the direction of travel; a normal load the
+    # reverse (the jump conditions of the Pressure-to-Source section).
+    # Through the interface: pressure source -> v_z = s Z1 / (Z1 + Z2),
+    # normal load -> p = s Z2 / (Z1 + Z2), s = +1 for receivers below, -1
+    # above, at second order in h.
+    errs = []
+    for h in (10.0, 5.0):
+        c1, c2, f = 2000.0, 2500.0, 10.0
+        nz, nx = int(600 / h), int(2000 / h) + 1
+        dt = 0.2 * h / c2
+        vel = np.full((nz, nx), c1)
+        if down:
+            vel[int(250 / h):, :] = c2
+            zs, zr = 150.0, 400.0
+        else:
+            vel[:int(350 / h), :] = c2
+            zs, zr = 450.0, 200.0
+        prob = inputs.Problem(nz=nz, nx=nx, h=h, dt=dt, nt=int(0.5 / dt), order=4, npml=20,
+                              z_src=zs, x_src0=0.0, ns=nx, z_rec=zr, x_rec0=50.0,
+                              nr=nx - int(100 / h), slab_dz=5, xs=(1000.0,))
+        m = oracle.Model(prob, inputs.kappa_from_velocity(vel, RHO), RHO)
+        w = inputs.ricker((np.arange(prob.nt) + 0.5) * prob.dt, f)
+        x = np.repeat(w[:, None], prob.ns, axis=1)
+        jr = int(round((1000.0 - prob.x_rec0) / h))
+        Z1, Z2 = RHO * c1, RHO * c2
+        sgn = 1.0 if down else -1.0
+
+        def peak(y):
+            return y[np.argmax(np.abs(y))]
+
+        hv = peak(m.block(0, 1, x)[:, jr]) / (sgn * Z1 / (Z1 + Z2) * peak(w)) - 1.0
+        fp = peak(m.block(1, 0, x)[:, jr]) / (sgn * Z2 / (Z1 + Z2) * peak(w)) - 1.0
+        errs.append((abs(hv), abs(fp)))
+    for a, b in zip(errs[0], errs[1]):
+        assert b < 0.02
+        assert math.log2(a / b) > 1.5
