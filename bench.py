@@ -332,7 +332,9 @@ def crosswell_bench(args):
     relative normal-residual curves (CG: ||r_k||; PCG: ||M^-1 r_k||, the
     left side of the norm1 form), the iterations each needs to reduce it by
     10x, 100x and 1000x, and the data misfit.  It also reports the paper's
-    operator checks as relative misfits: re-simulation of the time-reversal
+    operator checks as relative misfits: the pressure source -2 P_s v_z and
+    the normal load -2 P_s p reproducing the point source's data, re-simulation
+    of the time-reversal
     inverse 4 V^T d and of the unitary-norm inverse W^-1 F^T W_d d, the
     asymmetry of Lambda~ and the sv relation 1/4 Lambda_r F Lambda_s = V on
     the pressure gather that the point source leaves on z = 3000 m (all in
@@ -405,7 +407,23 @@ def crosswell_bench(args):
     sv = 0.25 * ctx.lam(1, False, ctx.fwd(lam, ctx.empty_r()), ctx.empty_r())
     vx = ctx.fwd_v(ps, ctx.empty_r())
     sv_mis = nrm(sv - vx) / nrm(vx)
-    checks = {"time_reversal_resimulation_misfit": round(mis_tr, 4),
+    # equivalence of pressure and normal-load sources (snull, tracejump
+    # relations): h = -2 P_s v_z and f = -2 P_s p of the point source's field
+    # on the source line reproduce its data on the receiver line
+    gctx = ssx.Context(gprob, inputs.crosswell_kappa(lens=False), rho, field_dtype=fd)
+    vs = gctx.block(0, 1, False, hpt, gctx.empty_r()).clone()
+    torch.cuda.synchronize()
+    gctx.close()
+    hctx = ssx.Context(pprob, inputs.crosswell_kappa(lens=False), rho, field_dtype=fd)
+    d_h = hctx.fwd(hpt, hctx.empty_r()).clone()
+    torch.cuda.synchronize()
+    hctx.close()
+    dhn = nrm(d_h)
+    mis_hs = nrm(ctx.fwd(-2.0 * vs, ctx.empty_r()) - d_h) / dhn
+    mis_fs = nrm(ctx.block(1, 0, False, -2.0 * ps, ctx.empty_r()) - d_h) / dhn
+    checks = {"pressure_source_equivalence_misfit": round(mis_hs, 4),
+              "normal_load_equivalence_misfit": round(mis_fs, 4),
+              "time_reversal_resimulation_misfit": round(mis_tr, 4),
               "unitary_inverse_resimulation_misfit": round(mis_u, 4),
               "lambda_asymmetry": round(asym, 4),
               "sv_relation_misfit": round(sv_mis, 4),

@@ -251,6 +251,17 @@ ssx_status ssx_adj_v(ssx_ctx* ctx, const void* r, void* g);
  * d: [nshots][nt][nr] -> h: [nshots][nt][ns]. */
 ssx_status ssx_tr_inverse(ssx_ctx* ctx, const void* d, void* h);
 
+/* y = B x, B a block of the vector modelling operator (Operators section:
+ * the source vector (h, f) on z_src to the traces (P_r p, P_r v_z) on z_rec):
+ * src 0 a pressure source, 1 a normal load on the source line; rec 0
+ * pressure, 1 normal velocity on the receiver line; with transpose != 0,
+ * y = B^T x.  Block (0, 0) is ssx_fwd / ssx_adj, block (1, 1) ssx_fwd_v /
+ * ssx_adj_v.  x: [nshots][nt][ns] (or [nshots][nt][nr] transposed), y the
+ * other.  Blocks other than (0, 0) need the normal-velocity rows of
+ * ssx_fwd_v (SSX_ERR_ARG otherwise). */
+ssx_status ssx_block(ssx_ctx* ctx, int32_t src, int32_t rec, int32_t transpose, const void* x,
+                     void* y);
+
 /* y = Lambda~ x (eqn lamtilde) or, with transpose != 0, its transpose (eqn
  * lamtransp), on the source-side slab (side 0, x and y [nshots][nt][ns]) or
  * the receiver-side one (side 1, [nshots][nt][nr]; needs rslab_dz != 0):

@@ -23,6 +23,7 @@ Function names follow the C ABI (include/ssx.h):
     ctx.adj_v(r, g)        g = V^T r
     ctx.tr_inverse(d, h)   h = 4 V^T d (time-reversal inverse of F)
     ctx.lam(side, transpose, x, y)   y = Lambda~ x or its transpose
+    ctx.block(src, rec, transpose, x, y)   a block of the modelling operator
 
 ``prob`` is any object with the fields of ``ssx_problem`` (nz, nx, h, dt,
 nt, order, npml, pml_R, z_src, x_src0, ns, z_rec, x_rec0, nr, slab_dz and,
@@ -54,7 +55,7 @@ EXPORTS = ("ssx_validate", "ssx_footprint", "ssx_create", "ssx_destroy", "ssx_fw
            "ssx_normal", "ssx_dot", "ssx_pcg_solve", "ssx_set_option", "ssx_last_error",
            "ssx_step_kernel_name", "ssx_cells_per_launch", "ssx_launch_shape",
            "ssx_weight_d", "ssx_weight_m", "ssx_normal_w", "ssx_pcg_solve_w",
-           "ssx_fwd_v", "ssx_adj_v", "ssx_tr_inverse", "ssx_lambda")
+           "ssx_fwd_v", "ssx_adj_v", "ssx_tr_inverse", "ssx_lambda", "ssx_block")
 
 
 class SSXError(RuntimeError):
@@ -117,6 +118,7 @@ def lib():
         L.ssx_adj_v.argtypes = [vp, vp, vp]
         L.ssx_tr_inverse.argtypes = [vp, vp, vp]
         L.ssx_lambda.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp]
+        L.ssx_block.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp]
         L.ssx_set_option.argtypes = [vp, c_int, c_int]
         L.ssx_last_error.restype = ctypes.c_char_p
         L.ssx_step_kernel_name.argtypes = [vp]
@@ -324,6 +326,14 @@ class Context:
         n = self.n_s if int(side) == 0 else self.n_r
         _check(lib().ssx_lambda(self._ctx, int(side), int(bool(transpose)), self._vec(x, n, "x"),
                                 self._vec(y, n, "y")))
+        return y
+
+    def block(self, src, rec, transpose, x, y):
+        """src 0 pressure source / 1 normal load on the source line; rec 0
+        pressure / 1 normal velocity on the receiver line."""
+        nin, nout = (self.n_s, self.n_r) if not transpose else (self.n_r, self.n_s)
+        _check(lib().ssx_block(self._ctx, int(src), int(rec), int(bool(transpose)),
+                               self._vec(x, nin, "x"), self._vec(y, nout, "y")))
         return y
 
     def set_option(self, option: int, value: int):

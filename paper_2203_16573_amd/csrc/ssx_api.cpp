@@ -739,7 +739,8 @@ enum {
   OP_FWD = 0, OP_ADJ = 1, OP_SLAB_FWD = 2, OP_SLAB_ADJ = 3,
   OP_RSLAB_FWD = 4, OP_RSLAB_ADJ = 5, OP_SLABP_FWD = 6, OP_SLABP_ADJ = 7,
   OP_V_FWD = 8, OP_V_ADJ = 9, OP_LAM_ADJ = 10, OP_LAMT_ADJ = 11, OP_RLAM_ADJ = 12,
-  OP_RLAMT_ADJ = 13, OP_TR_INV = 14
+  OP_RLAMT_ADJ = 13, OP_TR_INV = 14,
+  OP_B01_FWD = 15, OP_B01_ADJ = 16, OP_B10_FWD = 17, OP_B10_ADJ = 18
 };
 
 ssx_status do_fwd(ssx_ctx* c, const void* h, void* d) {
@@ -837,6 +838,27 @@ ssx_status do_adj_v(ssx_ctx* c, const void* r, void* g, bool inverse) {
   return propagate(c, inverse ? OP_TR_INV : OP_V_ADJ, c->full, true, c->h_line, io_none(), c->rv_line,
                    io_in(r, nvec_r(p), 1.0), c->fv_line, io_out(g, nvec_s(p), scale / c->Z0),
                    c->r_line, io_none());
+}
+
+// An off-diagonal block of the vector modelling operator on the full grid:
+// src 0 pressure source / 1 normal load on z_s, rec 0 pressure / 1 normal
+// velocity on z_r (src != rec), or its transpose.
+ssx_status do_block(ssx_ctx* c, int src, int rec, bool transpose, const void* x, void* y) {
+  const ssx_problem& p = c->prob;
+  const long long ss = nvec_s(p), sr = nvec_r(p);
+  const int op = src == 0 ? (transpose ? OP_B01_ADJ : OP_B01_FWD)
+                          : (transpose ? OP_B10_ADJ : OP_B10_FWD);
+  if (!transpose)
+    return propagate(c, op, c->full, false, c->r_line,
+                     rec == 0 ? io_out(y, sr, c->Z0) : io_none(), c->fv_line,
+                     src == 1 ? io_in(x, ss, 1.0 / c->Z0) : io_none(), c->rv_line,
+                     rec == 1 ? io_out(y, sr, 1.0) : io_none(), c->h_line,
+                     src == 0 ? io_in(x, ss, 1.0) : io_none());
+  return propagate(c, op, c->full, true, c->h_line,
+                   src == 0 ? io_out(y, ss, 1.0) : io_none(), c->rv_line,
+                   rec == 1 ? io_in(x, sr, 1.0) : io_none(), c->fv_line,
+                   src == 1 ? io_out(y, ss, 1.0 / c->Z0) : io_none(), c->r_line,
+                   rec == 0 ? io_in(x, sr, c->Z0) : io_none());
 }
 
 // y = Lambda~ x (transpose: its transpose) on the source-side slab (side 0)
@@ -1305,6 +1327,17 @@ ssx_status ssx_tr_inverse(ssx_ctx* c, const void* d, void* h) {
   if (!c || !d || !h) return fail(SSX_ERR_ARG, "null argument");
   if (!c->has_v) return fail(SSX_ERR_ARG, "no normal-velocity rows at the source or receiver depth");
   return do_adj_v(c, d, h, true);
+}
+
+ssx_status ssx_block(ssx_ctx* c, int32_t src, int32_t rec, int32_t transpose, const void* x,
+                     void* y) {
+  if (!c || !x || !y) return fail(SSX_ERR_ARG, "null argument");
+  if ((src != 0 && src != 1) || (rec != 0 && rec != 1))
+    return fail(SSX_ERR_ARG, "src and rec must be 0 (pressure) or 1 (normal load / velocity)");
+  if (src == 0 && rec == 0) return transpose ? do_adj(c, x, y) : do_fwd(c, x, y);
+  if (!c->has_v) return fail(SSX_ERR_ARG, "no normal-velocity rows at the source or receiver depth");
+  if (src == 1 && rec == 1) return transpose ? do_adj_v(c, x, y, false) : do_fwd_v(c, x, y);
+  return do_block(c, src, rec, transpose != 0, x, y);
 }
 
 ssx_status ssx_lambda(ssx_ctx* c, int32_t side, int32_t transpose, const void* x, void* y) {

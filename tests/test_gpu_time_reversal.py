@@ -149,3 +149,23 @@ def test_v_transpose_at_production_size():
     print(f"  transpose defect {abs(lhs - rhs) / nrm:.2e}")
     assert abs(lhs - rhs) <= 1e-5 * nrm
     ctx.close()
+
+
+@pytest.mark.parametrize("fd", ["f64", "f32"])
+def test_modelling_operator_blocks_parity(fd):
+    prob = problem(8, z_src=45.0, z_rec=203.0)
+    print(f"case blocks dtype={fd}", flush=True)
+    kap = kappa(prob, 6)
+    m = oracle.Model(prob, kap, RHO)
+    ctx = ssx.Context(prob, kap, RHO, field_dtype=fd)
+    rng = np.random.default_rng(14)
+    x = rng.standard_normal((2, prob.nt, prob.ns))
+    r = rng.standard_normal((2, prob.nt, prob.nr))
+    for src in (0, 1):
+        for rec in (0, 1):
+            y = host(ctx.block(src, rec, False, dev(x, fd), ctx.empty_r()))
+            g = host(ctx.block(src, rec, True, dev(r, fd), ctx.empty_s()))
+            for s in range(2):
+                assert rel(y[s], m.block(src, rec, x[s])) < TOL[fd], (src, rec)
+                assert rel(g[s], m.block(src, rec, r[s], transpose=True)) < TOL[fd], (src, rec)
+    ctx.close()
