@@ -362,6 +362,11 @@ def crosswell_bench(args):
     torch.cuda.synchronize()
     pctx.close()
     ctx = ssx.Context(prob, inputs.crosswell_kappa(lens=False), rho, field_dtype=fd)
+    tuned = None
+    if args.autotune:
+        from paper_2203_16573_amd import autotune
+        tuned = autotune.choose(prob, inputs.crosswell_kappa(lens=False), rho, field_dtype=fd)
+        autotune.apply(ctx, tuned)
     ctx.set_graphs(bool(args.graphs))
     dn = float(torch.linalg.norm(d.double()))
 
@@ -449,6 +454,7 @@ def crosswell_bench(args):
                                f"{prob.order}, nt {prob.nt}, K {K}, alpha {args.alpha}/m",
                    "nz": prob.nz, "nx": prob.nx, "nt": prob.nt, "K": K, "field_dtype": fd},
         "ms_per_iteration": round(1e3 * el / (args.steps * K), 3),
+        "kernel_choice": None if tuned is None else {k: v for k, v in tuned.items() if k != "us"},
         "cg_vs_pcg": comparison,
         "operator_checks": checks,
     }
