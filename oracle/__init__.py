@@ -17,7 +17,8 @@ Extended Surface Sources" (arXiv 2203.16573) that it follows:
 * ``ops``    F, F^T, the penalty A, the thin-slab preconditioner, the normal
              operator and Algorithm 1, the weighted normal equations with
              their data- and model-space weights, V, the time-reversal
-             inverse and Lambda~ (Introduction; Time Reversal; Unitarity;
+             inverse, Lambda~ and the misfit gradient in kappa
+             (Introduction; Time Reversal; Unitarity;
              Accelerated Iterative Inversion; Computing and Symmetrizing
              Lambda);
 * ``greens`` the closed-form 2D point-source response used as a pin.
@@ -29,8 +30,9 @@ second-order convergence, the 1D plane-wave amplitudes (including the
 energy transmission coefficient that the weighted composition and the
 time-reversal inverse reduce to, and the exact 1D form of the sv relation),
 polynomial exactness of the stencils, dense normal-equation solves, the
-gradient of the weighted objective and Krylov-subspace optimality.
+gradient of the weighted objective, central differences of the misfit in
+kappa and Krylov-subspace optimality.
 """
 from . import fd, grid, prop, ops, greens  # noqa: F401
 from .ops import (Model, pcg, pcg_solve, precond, penalty, dscale, normal,  # noqa: F401
-                  normal_w, pcg_solve_w)
+                  normal_w, pcg_solve_w, misfit_gradient)

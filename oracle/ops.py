@@ -370,3 +370,35 @@ def pcg_solve_w(model: Model, d, alpha: float, K: int, use_precond: bool = True,
             return r.copy()
     h, hist = pcg(apply_N, apply_Minv, b, K, d_misfit=d)
     return h, hist
+
+
+# ----------------------------------------------------------------------------
+# the gradient of the data misfit with respect to the bulk modulus (the
+# derivative that the variable-projection outer problem needs: at the
+# subproblem's minimiser the reduced objective's gradient is the partial
+# gradient at fixed h, Introduction and Conclusion)
+
+def misfit_gradient(model: Model, h, d):
+    """g = dJ/dkappa of J = 1/2 ||F h - d||^2 at fixed h, for every physical
+    cell, by the adjoint state of the discrete scheme: kappa enters the
+    pressure update through Ck = dt kappa / h, so
+        g = -(dt / h) sum_n pbar^{n+1} (D^- v^{n+1/2} - E_h h^n)
+    with pbar the adjoint pressure (F^T of the residual).  The absorbing
+    layer's coefficients (its copies of the edge values and its damping
+    profile) are held fixed, so on the physical grid, where the layer's
+    split parts carry equal adjoints, this is the whole derivative.
+    Returns (g [nz][nx], J)."""
+    prob, g = model.prob, model.full
+    divs = []
+    P, _ = forward(g, prob.nt, h_src=(model.h_line, h), rec_p=model.r_line, div_out=divs)
+    res = P - d
+    acc = np.zeros_like(divs[0])
+
+    def on_p(n, pxb, pzb):
+        acc[...] += pzb * divs[n]
+
+    adjoint(g, prob.nt, h_line=model.h_line, rec_p=(model.r_line, res), on_p=on_p)
+    L = prob.npml
+    grad = -(prob.dt / prob.h) * acc[L:L + prob.nz, L:L + prob.nx]
+    return grad, 0.5 * float(np.sum(res * res))
+

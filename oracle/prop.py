@@ -45,12 +45,15 @@ def _coefs(g: Grid):
 
 
 def forward(g: Grid, nt: int, h_src=None, f_src=None, rec_p=None, rec_v=None,
-            energy: bool = False):
+            energy: bool = False, div_out: list = None):
     """Run nt steps from rest.
 
     h_src: (Line on p nodes, traces [nt][n]) constitutive-defect source.
     f_src: (Line on v_z nodes, traces [nt][n]) normal-load source.
     rec_p / rec_v: Lines where p^{n+1} / v_z^{n+1/2} are recorded.
+    div_out: if a list, receives for every step n the array that the
+    pressure update multiplies by Ck, D^- v^{n+1/2} - E_h h^n (the layer's
+    split parts summed).
     Returns (P [nt][n_p] or None, V [nt][n_v] or None[, energy list])."""
     c, Cb, Ck, (ax_n, bx_n, ax_h, bx_h, az_n, bz_n, az_h, bz_h) = _coefs(g)
     shp = (g.NZ, g.NX)
@@ -76,6 +79,8 @@ def forward(g: Grid, nt: int, h_src=None, f_src=None, rec_p=None, rec_v=None,
         if h_src is not None:
             h_src[0].spread_add(h_src[1][n], dz, -1.0)   # D_z^- v_z - E_h h
         pz = az_n * pz - bz_n * Ck * dz
+        if div_out is not None:
+            div_out.append(fd.dminus(vx, c, axis=1) + dz)
         if P is not None:
             P[n] = rec_p.gather(px + pz)
         if V is not None:
@@ -86,11 +91,14 @@ def forward(g: Grid, nt: int, h_src=None, f_src=None, rec_p=None, rec_v=None,
 
 
 def adjoint(g: Grid, nt: int, h_line: Line = None, f_line: Line = None,
-            rec_p=None, rec_v=None):
+            rec_p=None, rec_v=None, on_p=None):
     """Exact transpose of :func:`forward` as a map from the source traces
     (h, f) to the recorded traces (P, V).
 
     rec_p / rec_v: (Line, traces [nt][n]) adjoint inputs in the P / V slots.
+    on_p: if given, called as on_p(n, pxb, pzb) with the adjoint variables
+    of p_x^{n+1} and p_z^{n+1} (the recording of step n included), before
+    the transposed pressure update of step n.
     Returns (hbar [nt][n_h] or None, fbar [nt][n_f] or None)."""
     c, Cb, Ck, (ax_n, bx_n, ax_h, bx_h, az_n, bz_n, az_h, bz_h) = _coefs(g)
     shp = (g.NZ, g.NX)
@@ -104,6 +112,8 @@ def adjoint(g: Grid, nt: int, h_line: Line = None, f_line: Line = None,
             rec_p[0].spread_add(rec_p[1][n], pzb)
         if rec_v is not None:
             rec_v[0].spread_add(rec_v[1][n], vzb)
+        if on_p is not None:
+            on_p(n, pxb, pzb)
         # p_z update: pz' = az_n pz - bz_n Ck D_z^- vz + bz_n Ck E_h h
         if hb is not None:
             hb[n] = h_line.gather(bz_n * Ck * pzb)

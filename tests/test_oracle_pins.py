@@ -726,3 +726,43 @@ def test_plane_wave_off_diagonal_blocks(down):
     for a, b in zip(errs[0], errs[1]):
         assert b < 0.02
         assert math.log2(a / b) > 1.5
+
+
+# ---------------------------------------------------------------------------
+# P13: the misfit gradient in kappa (adjoint state of the discrete scheme)
+
+@pytest.mark.parametrize("order", [4, 8])
+def test_misfit_gradient_central_differences(order):
+    # <g, dk> against (J(k + e dk) - J(k - e dk)) / 2e, for dk on physical
+    # cells off the grid's edges (the absorbing layer copies only edge
+    # values) and off the fastest cell (whose value sets the layer's
+    # damping); the central difference of this smooth J is exact to O(e^2)
+    prob = tiny_problem(order=order, nz=16, nx=20, L=5, nt=40, ns=14, nr=16, z_src=50.0,
+                        z_rec=120.0)
+    kap = tiny_kappa(prob, 51)
+    m = oracle.Model(prob, kap, RHO)
+    rng = np.random.default_rng(52)
+    h = rng.standard_normal((prob.nt, prob.ns))
+    d = rng.standard_normal((prob.nt, prob.nr)) * np.abs(m.fwd(h)).max()
+    g, J0 = oracle.misfit_gradient(m, h, d)
+    assert g.shape == kap.shape
+    assert abs(J0 - 0.5 * np.sum((m.fwd(h) - d) ** 2)) <= 1e-12 * J0
+
+    def J(k):
+        mm = oracle.Model(prob, k, RHO)
+        return 0.5 * np.sum((mm.fwd(h) - d) ** 2)
+
+    for trial in range(2):
+        dk = np.zeros_like(kap)
+        dk[1:-1, 1:-1] = rng.standard_normal((prob.nz - 2, prob.nx - 2))
+        dk[np.unravel_index(np.argmax(kap), kap.shape)] = 0.0
+        eps = 1e-5 * kap.mean() / np.abs(dk).max()
+        fdiff = (J(kap + eps * dk) - J(kap - eps * dk)) / (2 * eps)
+        an = float(np.sum(g * dk))
+        assert abs(fdiff - an) <= 1e-6 * abs(an), (fdiff, an)
+    # a single interior cell, both ways round
+    dk = np.zeros_like(kap)
+    dk[8, 9] = 1.0
+    eps = 1e-5 * kap[8, 9]
+    fdiff = (J(kap + eps * dk) - J(kap - eps * dk)) / (2 * eps)
+    assert abs(fdiff - g[8, 9]) <= 1e-5 * abs(g).max()
