@@ -262,6 +262,24 @@ ssx_status ssx_tr_inverse(ssx_ctx* ctx, const void* d, void* h);
 ssx_status ssx_block(ssx_ctx* ctx, int32_t src, int32_t rec, int32_t transpose, const void* x,
                      void* y);
 
+/* Gradient of the data misfit J = 1/2 ||F h - d||^2 with respect to the
+ * bulk modulus at fixed h (the derivative that the variable-projection
+ * outer problem of the Introduction needs: at the subproblem's minimiser
+ * h the reduced objective's gradient is this partial gradient), by the
+ * adjoint state of the discrete scheme: g = (1/kappa) sum_n P~^{n+1} r^n,
+ * r^n = E_h h^n - D^- v^{n+1/2} stored by a forward sweep, P~ the
+ * transposed pressure of the sweep driven by F h - d.  g covers the
+ * physical grid, [nshots][nz][nx] (row-major, vector dtype); the absorbing
+ * layer's coefficients (copies of the edge values, damping profile) are
+ * held fixed.  J_host: HOST [nshots] or NULL (then the call does not
+ * synchronise).  h: [nshots][nt][ns]; d: [nshots][nt][nr].  F64 and F32
+ * fields only (SSX_ERR_ARG otherwise).  The first call allocates the step
+ * history, nt * nshots * nz * nx field values plus an FP64 accumulator,
+ * held until ssx_destroy (also for contexts made with a workspace);
+ * SSX_ERR_OOM if that fails.  Two full simulations, one launch per step. */
+ssx_status ssx_misfit_gradient(ssx_ctx* ctx, const void* h, const void* d, void* g,
+                               double* J_host);
+
 /* y = Lambda~ x (eqn lamtilde) or, with transpose != 0, its transpose (eqn
  * lamtransp), on the source-side slab (side 0, x and y [nshots][nt][ns]) or
  * the receiver-side one (side 1, [nshots][nt][nr]; needs rslab_dz != 0):

@@ -24,6 +24,7 @@ Function names follow the C ABI (include/ssx.h):
     ctx.tr_inverse(d, h)   h = 4 V^T d (time-reversal inverse of F)
     ctx.lam(side, transpose, x, y)   y = Lambda~ x or its transpose
     ctx.block(src, rec, transpose, x, y)   a block of the modelling operator
+    ctx.misfit_gradient(h, d, g) -> J   dJ/dkappa of 1/2 ||F h - d||^2
 
 ``prob`` is any object with the fields of ``ssx_problem`` (nz, nx, h, dt,
 nt, order, npml, pml_R, z_src, x_src0, ns, z_rec, x_rec0, nr, slab_dz and,
@@ -55,7 +56,8 @@ EXPORTS = ("ssx_validate", "ssx_footprint", "ssx_create", "ssx_destroy", "ssx_fw
            "ssx_normal", "ssx_dot", "ssx_pcg_solve", "ssx_set_option", "ssx_last_error",
            "ssx_step_kernel_name", "ssx_cells_per_launch", "ssx_launch_shape",
            "ssx_weight_d", "ssx_weight_m", "ssx_normal_w", "ssx_pcg_solve_w",
-           "ssx_fwd_v", "ssx_adj_v", "ssx_tr_inverse", "ssx_lambda", "ssx_block")
+           "ssx_fwd_v", "ssx_adj_v", "ssx_tr_inverse", "ssx_lambda", "ssx_block",
+           "ssx_misfit_gradient")
 
 
 class SSXError(RuntimeError):
@@ -119,6 +121,7 @@ def lib():
         L.ssx_tr_inverse.argtypes = [vp, vp, vp]
         L.ssx_lambda.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp]
         L.ssx_block.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp]
+        L.ssx_misfit_gradient.argtypes = [vp, vp, vp, vp, dp]
         L.ssx_set_option.argtypes = [vp, c_int, c_int]
         L.ssx_last_error.restype = ctypes.c_char_p
         L.ssx_step_kernel_name.argtypes = [vp]
@@ -335,6 +338,23 @@ class Context:
         _check(lib().ssx_block(self._ctx, int(src), int(rec), int(bool(transpose)),
                                self._vec(x, nin, "x"), self._vec(y, nout, "y")))
         return y
+
+    def empty_model(self):
+        import torch
+        return torch.empty((self.nshots, self.prob.nz, self.prob.nx), dtype=self.vdtype,
+                           device="cuda")
+
+    def misfit_gradient(self, h, d, g=None):
+        """g [nshots][nz][nx] = dJ/dkappa of J = 1/2 ||F h - d||^2 at fixed h
+        (physical cells); returns (g, J [nshots])."""
+        if g is None:
+            g = self.empty_model()
+        J = np.zeros(self.nshots)
+        _check(lib().ssx_misfit_gradient(self._ctx, self._vec(h, self.n_s, "h"),
+                                         self._vec(d, self.n_r, "d"),
+                                         self._vec(g, self.nshots * self.prob.nz * self.prob.nx,
+                                                   "g"), _dptr(J)))
+        return g, J
 
     def set_option(self, option: int, value: int):
         _check(lib().ssx_set_option(self._ctx, int(option), int(value)))

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libssx.so")
 
-SOURCES = ["ssx_step.hip", "ssx_slab.hip", "ssx_vec.hip", "ssx_api.cpp"]
+SOURCES = ["ssx_step.hip", "ssx_slab.hip", "ssx_vec.hip", "ssx_grad.hip", "ssx_api.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared",

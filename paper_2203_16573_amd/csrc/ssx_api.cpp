@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -327,6 +328,11 @@ struct ssx_ctx {
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool overlap = true;                   // SSX_OPT_OVERLAP
+  // misfit gradient (allocated on first use): r^n of every step and
+  // physical cell, [nt][nshots][nz][nx] in the field type; FP64
+  // accumulator [nshots][nz][nx]
+  void* ghist = nullptr;
+  double* gacc = nullptr;
   std::vector<GraphEntry> graphs_cache;
   unsigned long long use_clock = 0;
 };
@@ -472,12 +478,20 @@ int default_tile_z(const ssx_ctx* c, const GridDev& gd) {
 // Transpose: pi[nt-1] enters first; step n (descending) samples vs[n]
 // (the transposed pressure after sample n of the adjoint input entered),
 // injects vi[n], samples ps[n] and injects pi[n-1].
+// A per-step callback of a propagation: called with the step index and the
+// fields of the current group (forward: after step n, holding p^{n+1} and
+// v^{n+1/2}; transposed: before step n, holding the transposed state of
+// level n+1).  Steps then run one per launch.
+using StepHook = std::function<ssx_status(int n, const Fields& f)>;
+// the same with the first shot and the shot count of the group
+using GroupHook = std::function<ssx_status(int n, const Fields& f, int s0, int gs)>;
+
 // One propagation of ns shots (a group of the context's shots) whose
 // fields start at f0 (step n) and f1 (the second buffer).
 ssx_status issue_group(ssx_ctx* c, GridDev& gd, bool adj, const Fields& f0, const Fields& f1,
                        int ns, const LineDev& vsl, TraceIO vs, const LineDev& vil, TraceIO vi,
                        const LineDev& psl, TraceIO ps, const LineDev& pil, TraceIO pi,
-                       hipStream_t s) {
+                       hipStream_t s, const StepHook* hook = nullptr) {
   const int nt = c->prob.nt, order = c->prob.order;
   if (!c->fused) {
     if (!adj) {
@@ -490,6 +504,7 @@ ssx_status issue_group(ssx_ctx* c, GridDev& gd, bool adj, const Fields& f0, cons
         pi.n = pi.in ? n : -1;
         SSX_HIP(launch_pres(c->fdt, order, false, f0, gd.dims, gd.coef, psl, ps, pil, pi,
                             ns, s));
+        if (hook) SSX_TRY((*hook)(n, f0));
       }
       if (vs.out) {
         vs.n = nt - 1;
@@ -501,6 +516,7 @@ ssx_status issue_group(ssx_ctx* c, GridDev& gd, bool adj, const Fields& f0, cons
       SSX_HIP(launch_pres(c->fdt, order, true, f0, gd.dims, gd.coef, psl, none, pil, pi,
                           ns, s));
       for (int n = nt - 1; n >= 0; --n) {
+        if (hook) SSX_TRY((*hook)(n, f0));
         vs.n = vs.out ? n : -1;
         vi.n = vi.in ? n : -1;
         SSX_HIP(launch_vel(c->fdt, order, true, f0, gd.dims, gd.coef, vsl, vs, vil, vi,
@@ -582,6 +598,12 @@ ssx_status issue_group(ssx_ctx* c, GridDev& gd, bool adj, const Fields& f0, cons
   };
   if (!adj) {
     int n = 0;
+    if (hook) {
+      for (; n < nt; ++n) {
+        SSX_TRY(launch(1, n - 1, n, n, n));
+        SSX_TRY((*hook)(n, buf[cur]));
+      }
+    }
     for (; n + spl <= nt; n += spl) SSX_TRY(launch(spl, n - 1, n, n, n));
     for (; n < nt; ++n) SSX_TRY(launch(1, n - 1, n, n, n));
     if (vs.out) {
@@ -594,6 +616,12 @@ ssx_status issue_group(ssx_ctx* c, GridDev& gd, bool adj, const Fields& f0, cons
     p0.n = pi.in ? nt - 1 : -1;
     SSX_HIP(launch_pres(c->fdt, order, true, buf[0], gd.dims, gd.coef, psl, none, pil, p0, ns, s));
     int n = nt - 1;
+    if (hook) {
+      for (; n >= 0; --n) {
+        SSX_TRY((*hook)(n, buf[cur]));
+        SSX_TRY(launch(1, n, n, n, n - 1));
+      }
+    }
     for (; n - spl + 1 >= 0; n -= spl) SSX_TRY(launch(spl, n, n, n, n - 1));
     for (; n >= 0; --n) SSX_TRY(launch(1, n, n, n, n - 1));
   }
@@ -641,7 +669,8 @@ TraceIO shift_io(TraceIO t, int s0, size_t vsz) {
 // group (each group runs its whole record before the next starts).
 ssx_status issue_propagation(ssx_ctx* c, GridDev& gd, bool adj, const LineDev& vsl, TraceIO vs,
                              const LineDev& vil, TraceIO vi, const LineDev& psl, TraceIO ps,
-                             const LineDev& pil, TraceIO pi, hipStream_t s) {
+                             const LineDev& pil, TraceIO pi, hipStream_t s,
+                             const GroupHook* hook = nullptr) {
   const int ns = c->prob.nshots;
   SSX_HIP(launch_zero(gd.field_block, gd.field_bytes, s));
   if (c->fsz == 2) {
@@ -660,10 +689,13 @@ ssx_status issue_propagation(ssx_ctx* c, GridDev& gd, bool adj, const LineDev& v
   for (int s0 = 0; s0 < ns; s0 += G) {
     const int gs = std::min(G, ns - s0);
     const long long off = (long long)s0 * gd.dims.field_stride;
+    StepHook step_hook;
+    if (hook) step_hook = [&](int n, const Fields& f) { return (*hook)(n, f, s0, gs); };
     SSX_TRY(issue_group(c, gd, adj, shift_fields(gd.fields, off, c->fsz),
                         shift_fields(gd.fields1, off, c->fsz), gs, vsl,
                         shift_io(vs, s0, c->vsz), vil, shift_io(vi, s0, c->vsz), psl,
-                        shift_io(ps, s0, c->vsz), pil, shift_io(pi, s0, c->vsz), s));
+                        shift_io(ps, s0, c->vsz), pil, shift_io(pi, s0, c->vsz), s,
+                        hook ? &step_hook : nullptr));
   }
   return SSX_OK;
 }
@@ -935,6 +967,58 @@ ssx_status do_normal_w(ssx_ctx* c, const double* alpha2_dev, double alpha2_host,
   return SSX_OK;
 }
 
+// g = dJ/dkappa of J = 1/2 ||F h - d||^2 on the physical cells, J per shot
+// (see ssx_grad.hip): a forward sweep storing r^n, the residual, and a
+// transposed sweep accumulating P~^{n+1} r^n, both one step per launch.
+ssx_status do_gradient(ssx_ctx* c, const void* h, const void* d, void* g, double* J_host) {
+  const ssx_problem& p = c->prob;
+  hipStream_t s = c->stream;
+  const long long cells = (long long)p.nz * p.nx;
+  if (!c->ghist) {
+    if (hipMalloc(&c->ghist, (size_t)p.nt * p.nshots * cells * c->fsz) != hipSuccess ||
+        hipMalloc((void**)&c->gacc, (size_t)p.nshots * cells * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      if (c->ghist) (void)hipFree(c->ghist);
+      c->ghist = nullptr;
+      c->gacc = nullptr;
+      return fail(SSX_ERR_OOM, "device allocation of the gradient history failed");
+    }
+  }
+  const long long ns_ = nvec_s(p), nr_ = nvec_r(p);
+  auto hist_at = [&](int n, int s0) {
+    return (char*)c->ghist + ((size_t)n * p.nshots + s0) * cells * c->fsz;
+  };
+  const GroupHook store = [&](int n, const Fields& f, int s0, int gs) -> ssx_status {
+    TraceIO pi = shift_io(io_in(h, ns_, 1.0), s0, c->vsz);
+    pi.n = n;
+    SSX_HIP(launch_grad_store(c->fdt, p.order, f, c->full.dims, p.nz, p.nx, c->h_line, pi,
+                              hist_at(n, s0), gs, s));
+    return SSX_OK;
+  };
+  SSX_TRY(issue_propagation(c, c->full, false, c->r_line, io_out(c->Fp, nr_, c->Z0), c->r_line,
+                            io_none(), c->r_line, io_none(), c->h_line, io_in(h, ns_, 1.0), s,
+                            &store));
+  SSX_HIP(launch_sub(c->vdbl, c->Fp, d, c->e, nr_, p.nshots, s));
+  SSX_HIP(launch_dot1(c->vdbl, c->e, c->e, nr_, p.nshots, c->partial, c->sc + SC_TMP, SC_N, s));
+  SSX_HIP(launch_zero(c->gacc, (size_t)p.nshots * cells * sizeof(double), s));
+  const GroupHook accum = [&](int n, const Fields& f, int s0, int gs) -> ssx_status {
+    SSX_HIP(launch_grad_acc(c->fdt, f, c->full.dims, p.nz, p.nx, hist_at(n, s0),
+                            c->gacc + (size_t)s0 * cells, gs, s));
+    return SSX_OK;
+  };
+  SSX_TRY(issue_propagation(c, c->full, true, c->h_line, io_none(), c->h_line, io_none(),
+                            c->h_line, io_none(), c->r_line, io_in(c->e, nr_, c->Z0), s, &accum));
+  SSX_HIP(launch_grad_final(c->fdt, c->gacc, c->full.coef.ck, c->full.dims, p.nz, p.nx,
+                            p.dt / (p.h * c->Z0), g, p.nshots, s));
+  if (J_host) {
+    std::vector<double> tmp((size_t)p.nshots * SC_N);
+    SSX_HIP(hipMemcpyAsync(tmp.data(), c->sc, tmp.size() * 8, hipMemcpyDeviceToHost, s));
+    SSX_HIP(hipStreamSynchronize(s));
+    for (int sh = 0; sh < p.nshots; ++sh) J_host[sh] = 0.5 * tmp[(size_t)sh * SC_N + SC_TMP];
+  }
+  return SSX_OK;
+}
+
 ssx_status copy_vec(ssx_ctx* c, void* dst, const void* src, size_t bytes) {
   SSX_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream));
   return SSX_OK;
@@ -1122,6 +1206,8 @@ void ssx_destroy(ssx_ctx* c) {
   drop_graphs(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->aux) (void)hipStreamDestroy(c->aux);
+  if (c->ghist) (void)hipFree(c->ghist);
+  if (c->gacc) (void)hipFree(c->gacc);
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   if (c->own) (void)hipFree(c->own);
@@ -1338,6 +1424,14 @@ ssx_status ssx_block(ssx_ctx* c, int32_t src, int32_t rec, int32_t transpose, co
   if (!c->has_v) return fail(SSX_ERR_ARG, "no normal-velocity rows at the source or receiver depth");
   if (src == 1 && rec == 1) return transpose ? do_adj_v(c, x, y, false) : do_fwd_v(c, x, y);
   return do_block(c, src, rec, transpose != 0, x, y);
+}
+
+ssx_status ssx_misfit_gradient(ssx_ctx* c, const void* h, const void* d, void* g,
+                               double* J_host) {
+  if (!c || !h || !d || !g) return fail(SSX_ERR_ARG, "null argument");
+  if (c->fdt != Dt::F64 && c->fdt != Dt::F32)
+    return fail(SSX_ERR_ARG, "the misfit gradient needs F64 or F32 fields");
+  return do_gradient(c, h, d, g, J_host);
 }
 
 ssx_status ssx_lambda(ssx_ctx* c, int32_t side, int32_t transpose, const void* x, void* y) {
