@@ -766,3 +766,46 @@ def test_misfit_gradient_central_differences(order):
     eps = 1e-5 * kap[8, 9]
     fdiff = (J(kap + eps * dk) - J(kap - eps * dk)) / (2 * eps)
     assert abs(fdiff - g[8, 9]) <= 1e-5 * abs(g).max()
+
+
+def test_reduced_objective_gradient_is_partial_gradient():
+    # variable projection: with h*(kappa) the exact minimiser of
+    # 1/2 ||F h - d||^2 + alpha^2/2 ||A h||^2, the reduced objective's
+    # derivative in kappa is the misfit gradient at fixed h = h*
+    # (the penalty does not depend on kappa); checked by central
+    # differences of the reduced objective, each side solved densely
+    prob = tiny_problem(nz=12, nx=16, L=4, nt=16, ns=6, nr=10, xs=(47.0,))
+    kap = tiny_kappa(prob, 61)
+    d = np.random.default_rng(62).standard_normal((prob.nt, prob.nr))
+    Adiag = np.tile(oracle.ops.lateral_distance(prob), prob.nt)
+    n = prob.nt * prob.ns
+
+    def solve(k):
+        m = oracle.Model(prob, k, RHO)
+        F = dense(m.fwd, n, (prob.nt, prob.ns))
+        alpha = 0.2 * np.linalg.norm(F, 2) / Adiag.max()
+        N = F.T @ F + alpha ** 2 * np.diag(Adiag ** 2)
+        hs = np.linalg.solve(N, F.T @ d.ravel())
+        r = F @ hs - d.ravel()
+        return m, hs.reshape(prob.nt, prob.ns), 0.5 * r @ r + 0.5 * alpha ** 2 * np.sum((Adiag * hs) ** 2), alpha
+
+    m, hs, J0, alpha = solve(kap)
+    g, _ = oracle.misfit_gradient(m, hs, d)
+    rng = np.random.default_rng(63)
+    dk = np.zeros_like(kap)
+    dk[1:-1, 1:-1] = rng.standard_normal((prob.nz - 2, prob.nx - 2))
+    dk[np.unravel_index(np.argmax(kap), kap.shape)] = 0.0
+    eps = 1e-5 * kap.mean() / np.abs(dk).max()
+
+    def Jr(k):
+        # alpha held at its value for kappa (it is a fixed weight of the problem)
+        mm = oracle.Model(prob, k, RHO)
+        F = dense(mm.fwd, n, (prob.nt, prob.ns))
+        N = F.T @ F + alpha ** 2 * np.diag(Adiag ** 2)
+        hk = np.linalg.solve(N, F.T @ d.ravel())
+        r = F @ hk - d.ravel()
+        return 0.5 * r @ r + 0.5 * alpha ** 2 * np.sum((Adiag * hk) ** 2)
+
+    fdiff = (Jr(kap + eps * dk) - Jr(kap - eps * dk)) / (2 * eps)
+    an = float(np.sum(g * dk))
+    assert abs(fdiff - an) <= 1e-5 * abs(an), (fdiff, an)
