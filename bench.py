@@ -37,9 +37,15 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2",
-                    choices=["c1", "c2", "c3", "c4", "c4bf", "c5", "xw"],
+                    choices=["c1", "c2", "c3", "c4", "c4bf", "c5", "xw", "vp"],
                     help="c1..c5: the benchmark configurations; xw: the paper's crosswell "
-                         "example, CG against weighted PCG")
+                         "example, CG against weighted PCG; vp: a variable-projection "
+                         "outer loop on the crosswell example")
+    ap.add_argument("--gradient", action="store_true",
+                    help="c1..c4: time the misfit gradient in kappa (forward sweep storing "
+                         "the step history, transposed sweep accumulating it) instead of "
+                         "the solve")
+    ap.add_argument("--outer", type=int, default=4, help="vp: outer iterations")
     ap.add_argument("--solver", default="plain", choices=["plain", "weighted"],
                     help="c1..c4: Algorithm 1 on the Euclidean normal equations (plain) or "
                          "on the weighted ones N_w h = F^T W_d d (weighted)")
@@ -118,6 +124,8 @@ def main():
         return serve_bench(args)
     if args.config == "xw":
         return crosswell_bench(args)
+    if args.config == "vp":
+        return varpro_bench(args)
     cnum = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "c4bf": 4}[args.config]
     wl = inputs.workload(cnum)
     if args.nt:
@@ -174,6 +182,9 @@ def main():
                           "ms_per_propagation": 1e3 * el / (2 * args.prop_only)}), flush=True)
         ctx.close()
         return
+
+    if args.gradient:
+        return gradient_bench(args, wl, ctx, d, fd)
 
     def solve():
         if weighted:
@@ -460,6 +471,143 @@ def crosswell_bench(args):
     }
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def gradient_bench(args, wl, ctx, d, fd):
+    """Timed misfit gradients in kappa (ssx_misfit_gradient) at h = a
+    shifted copy of the true source: two full-grid sweeps of one step per
+    launch, plus per step a store (forward) or an accumulation (transposed)
+    pass over the physical cells.  Bytes per cell-update beyond the step's
+    own: the stored residual (written, then read) and the transposed
+    pressure and FP64 accumulator (read, read and written)."""
+    import numpy as np
+    import torch
+
+    import inputs
+    prob = wl.prob
+    vdt = torch.float64 if fd == "f64" else torch.float32
+    w = inputs.source_wavelet(prob, wl.freq)
+    h = np.roll(np.stack([inputs.spike_gather(prob, w, s) for s in range(prob.nshots)]), 40,
+                axis=2)
+    h = torch.tensor(h, dtype=vdt, device="cuda")
+    g = ctx.empty_model()
+    for _ in range(args.warmup):
+        ctx.misfit_gradient(h, d, g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, J = ctx.misfit_gradient(h, d, g)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    NZ, NX = prob.nz + 2 * prob.npml, prob.nx + 2 * prob.npml
+    cu = 2 * prob.nt * NZ * NX * prob.nshots
+    fsz = 8 if fd == "f64" else 4
+    extra = prob.nt * prob.nz * prob.nx * prob.nshots * (2 * fsz + fsz + 16)
+    out = {
+        "metric": "misfit gradients in kappa/s", "value": round(args.steps / el, 4),
+        "unit": "gradients/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * el / args.steps, 2), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": fd,
+        "data": "synthetic (seeded layered model; d = F of a Ricker point source)",
+        "config": {"workload": f"{wl.name}: {prob.nz}x{prob.nx} @ {prob.h} m, order "
+                               f"{prob.order}, nt {prob.nt}, shots {prob.nshots}, gradient",
+                   "nz": prob.nz, "nx": prob.nx, "nt": prob.nt, "shots": prob.nshots,
+                   "field_dtype": fd},
+        "gcell_updates_per_s": round(cu * args.steps / el / 1e9, 2),
+        "history_bytes": prob.nt * prob.nz * prob.nx * prob.nshots * fsz,
+        "extra_bytes_per_gradient": extra,
+        "misfit": [float(v) for v in J],
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def varpro_bench(args):
+    """A variable-projection outer loop on the crosswell example: data of the
+    point source in the lens model, starting from the homogeneous model.
+    Each outer iteration solves the subproblem (Algorithm 1, --iters or 20
+    iterations, M^-1 = D W^-1 D, alpha_rel = --alpha) for h*(kappa),
+    evaluates the reduced objective 1/2 ||F h* - d||^2 + alpha^2/2 ||A h*||^2
+    and its gradient (the misfit gradient at h*), and takes a steepest-
+    descent step scaled to change kappa by at most 5 % (halved until the
+    reduced objective falls, at most four times).  Reports the objective,
+    the relative model error and the time per outer iteration."""
+    import numpy as np
+    import torch
+
+    import inputs
+    import paper_2203_16573_amd as ssx
+
+    rho = inputs.RHO_WATERLIKE
+    prob = inputs.crosswell_problem()
+    if args.nt:
+        prob = prob.replace(nt=args.nt)
+    K = args.iters or 20
+    fd = args.dtype or "f32"
+    vdt = torch.float64 if fd == "f64" else torch.float32
+    k_true = inputs.crosswell_kappa(lens=True)
+    pctx = ssx.Context(inputs.crosswell_point_problem(prob), k_true, rho, field_dtype=fd)
+    w = inputs.bandpass_wavelet((np.arange(prob.nt) + 0.5) * prob.dt)
+    hpt = torch.tensor((w / prob.h)[None, :, None], dtype=vdt, device="cuda").contiguous()
+    d = pctx.fwd(hpt, pctx.empty_r()).clone()
+    torch.cuda.synchronize()
+    pctx.close()
+    dist = torch.tensor(np.abs(prob.x_src0 + prob.h * np.arange(prob.ns) - prob.xs[0]),
+                        dtype=vdt, device="cuda")
+
+    def reduced(k):
+        ctx = ssx.Context(prob, k, rho, field_dtype=fd)
+        h, _, _, _ = ctx.pcg_solve(d, args.alpha, K, raise_on_breakdown=False)
+        b = ctx.adj(d, ctx.empty_s())
+        alpha = args.alpha * float(torch.linalg.norm(b.double())) / float(
+            torch.linalg.norm(d.double()))
+        e = ctx.fwd(h, ctx.empty_r()) - d
+        J = 0.5 * float(torch.sum(e.double() ** 2)) + 0.5 * alpha ** 2 * float(
+            torch.sum((dist * h).double() ** 2))
+        return ctx, h, J
+
+    k = inputs.crosswell_kappa(lens=False)
+    e0 = float(np.linalg.norm(k - k_true))
+    hist = []
+    t0 = time.perf_counter()
+    ctx, h, J = reduced(k)
+    for it in range(args.outer):
+        g, _ = ctx.misfit_gradient(h, d)
+        gk = g[0].double().cpu().numpy()
+        ctx.close()
+        step = 0.05 * k.max() / max(np.abs(gk).max(), 1e-300)
+        entry = {"outer": it, "reduced_objective": J,
+                 "model_error": float(np.linalg.norm(k - k_true)) / e0}
+        for _ in range(5):
+            kn = k - step * gk
+            cn, hn, Jn = reduced(kn)
+            if Jn < J:
+                break
+            cn.close()
+            step *= 0.5
+        entry["step_halvings"] = _
+        hist.append(entry)
+        if Jn >= J:
+            ctx = None
+            break
+        k, ctx, h, J = kn, cn, hn, Jn
+    el = time.perf_counter() - t0
+    if ctx is not None:
+        hist.append({"outer": len(hist), "reduced_objective": J,
+                     "model_error": float(np.linalg.norm(k - k_true)) / e0})
+        ctx.close()
+    out = {
+        "metric": "variable-projection outer iterations/s (crosswell example)",
+        "value": round(len(hist) / el, 4), "unit": "outer iterations/s", "n_gpus": 1,
+        "steps": args.outer, "warmup": 0, "ms_per_step": round(1e3 * el / max(len(hist), 1), 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": fd,
+        "data": "synthetic (lens model of the paper's shape; bandpass point source)",
+        "config": {"workload": f"crosswell: {prob.nz}x{prob.nx} @ {prob.h} m, order "
+                               f"{prob.order}, nt {prob.nt}, K {K}, alpha_rel {args.alpha}",
+                   "nz": prob.nz, "nx": prob.nx, "nt": prob.nt, "K": K, "field_dtype": fd},
+        "history": hist,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def measured_traffic(config, fd, nshots, tile_z, group, loop, kernel):
