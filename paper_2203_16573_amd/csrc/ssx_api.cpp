@@ -1,9 +1,12 @@
 // C ABI of libssx: validation, model/coefficient setup, propagation drivers,
-// the thin-slab preconditioner and Algorithm 1 (preconditioned CG).
+// the thin-slab preconditioner and Algorithm 1 (preconditioned CG), the
+// weighted normal equations, the other blocks of the modelling operator,
+// Lambda~ and the misfit gradient.
 //
-// Every numerical step runs in the HIP kernels of ssx_kernels.hip; this
-// file only prepares coefficients (once, in FP64 on the host), sequences
-// launches on the context's stream and moves scalars/history to the host.
+// Every numerical step runs in the HIP kernels (ssx_step.hip, ssx_slab.hip,
+// ssx_vec.hip, ssx_grad.hip); this file only prepares coefficients (once, in
+// FP64 on the host), sequences launches on the context's streams and moves
+// scalars/history to the host.
 #include "ssx.h"
 #include "ssx_internal.h"
 

@@ -1,5 +1,6 @@
 // Internal declarations shared by the host API (ssx_api.cpp) and the HIP
-// kernels (ssx_kernels.hip).  Not part of the public ABI.
+// kernels (ssx_step.hip, ssx_slab.hip, ssx_vec.hip, ssx_grad.hip).  Not part
+// of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -93,7 +94,7 @@ struct StepArgs {
   int ngen, nint;
 };
 
-// ---- launchers (ssx_kernels.hip) -----------------------------------------
+// ---- launchers (ssx_step.hip, ssx_slab.hip) ------------------------------
 // One fused time step (velocity then pressure, one launch).  tz: tile height
 // (8, 16 or 32; 32 is not available for FP64 fields).  loop: 0, one tile
 // per workgroup; else one workgroup per general tile and, for the interior
