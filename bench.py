@@ -344,8 +344,10 @@ def crosswell_bench(args):
     left side of the norm1 form), the iterations each needs to reduce it by
     10x, 100x and 1000x, and the data misfit.  It also reports the paper's
     operator checks as relative misfits: the pressure source -2 P_s v_z and
-    the normal load -2 P_s p reproducing the point source's data, re-simulation
-    of the time-reversal
+    the normal load -2 P_s p reproducing the point source's data, Lambda~
+    with the 5-cell datum against the whole path to the receiver surface,
+    the symmetrised Lambda~ of the gather used as a source (lens model),
+    re-simulation of the time-reversal
     inverse 4 V^T d and of the unitary-norm inverse W^-1 F^T W_d d, the
     asymmetry of Lambda~ and the sv relation 1/4 Lambda_r F Lambda_s = V on
     the pressure gather that the point source leaves on z = 3000 m (all in
@@ -437,7 +439,30 @@ def crosswell_bench(args):
     dhn = nrm(d_h)
     mis_hs = nrm(ctx.fwd(-2.0 * vs, ctx.empty_r()) - d_h) / dhn
     mis_fs = nrm(ctx.block(1, 0, False, -2.0 * ps, ctx.empty_r()) - d_h) / dhn
+    # the near datum against the whole path to the receiver surface: Lambda~
+    # with the datum 100 cells from the source line (a slab of the full
+    # source-to-receiver depth) against the 5-cell datum
+    fctx = ssx.Context(prob.replace(slab_dz=-int(round((prob.z_src - prob.z_rec) / prob.h))),
+                       inputs.crosswell_kappa(lens=False), rho, field_dtype=fd)
+    lam_far = fctx.lam(0, False, ps, fctx.empty_s())
+    near_far = nrm(lam - lam_far) / nrm(lam_far)
+    torch.cuda.synchronize()
+    fctx.close()
+    # the symmetrised Lambda~ applied to the point source's pressure gather,
+    # used as a pressure source, against the point source's data, all in the
+    # lens model
+    lctx = ssx.Context(prob, inputs.crosswell_kappa(lens=True), rho, field_dtype=fd)
+    lg = ssx.Context(gprob, inputs.crosswell_kappa(lens=True), rho, field_dtype=fd)
+    ps_l = lg.fwd(hpt, lg.empty_r()).clone()
+    torch.cuda.synchronize()
+    lg.close()
+    hsym = lctx.precond(0.0, ps_l, lctx.empty_s())
+    sym_src = nrm(lctx.fwd(hsym, lctx.empty_r()) - d) / dn
+    torch.cuda.synchronize()
+    lctx.close()
     checks = {"pressure_source_equivalence_misfit": round(mis_hs, 4),
+              "lambda_near_vs_full_path": round(near_far, 4),
+              "symmetrised_lambda_source_misfit": round(sym_src, 4),
               "normal_load_equivalence_misfit": round(mis_fs, 4),
               "time_reversal_resimulation_misfit": round(mis_tr, 4),
               "unitary_inverse_resimulation_misfit": round(mis_u, 4),

@@ -169,3 +169,26 @@ def test_modelling_operator_blocks_parity(fd):
                 assert rel(y[s], m.block(src, rec, x[s])) < TOL[fd], (src, rec)
                 assert rel(g[s], m.block(src, rec, r[s], transpose=True)) < TOL[fd], (src, rec)
     ctx.close()
+
+
+@pytest.mark.parametrize("fd,tol", [("f16", 2e-2), ("bf16", 1e-1)])
+def test_blocks_and_lambda_half_precision_storage_error(fd, tol):
+    # 16-bit wavefield storage with FP32 arithmetic (per-grid field scales):
+    # error against the FP64 oracle, stated and bounded like the other
+    # propagations
+    prob = problem(8)
+    print(f"case blocks/lambda storage dtype={fd}", flush=True)
+    kap = kappa(prob, 7)
+    m = oracle.Model(prob, kap, RHO)
+    ctx = ssx.Context(prob, kap, RHO, field_dtype=fd)
+    rng = np.random.default_rng(15)
+    x = rng.standard_normal((2, prob.nt, prob.ns)) * 1e3   # arbitrary scale
+    errs = []
+    for src, rec in ((1, 1), (0, 1), (1, 0)):
+        y = host(ctx.block(src, rec, False, dev(x, "f32"), ctx.empty_r()))
+        errs += [rel(y[s], m.block(src, rec, x[s])) for s in range(2)]
+    y = host(ctx.lam(0, False, dev(x, "f32"), ctx.empty_s()))
+    errs += [rel(y[s], m.lam(x[s], "s")) for s in range(2)]
+    print(f"{fd} storage: relative L2 errors {errs}")
+    assert max(errs) < tol
+    ctx.close()
