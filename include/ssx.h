@@ -16,7 +16,12 @@
  *   N = F^T F + alpha^2 A^T A (the penalised problem esisp);
  *   and the same in the weighted norms of the Accelerated Iterative
  *   Inversion section: N_w h = F^T W_d d, N_w = F^T W_d F + alpha^2 A^T W_m A
- *   (the normpart system), W_d and W_m thin-slab weights.
+ *   (the normpart system), W_d and W_m thin-slab weights;
+ *   the other blocks of the vector modelling operator (V: normal load to
+ *   normal velocity, eqn vdef), the time-reversal inverse 4 V^T (eqn
+ *   approxinv), Lambda~ and its transpose (eqns lamtilde, lamtransp);
+ *   and the gradient in kappa of the data misfit, by the adjoint state of
+ *   the discrete scheme (the variable-projection outer problem).
  *
  * Discretisation: 2D staggered grid (p on nodes, v_x and v_z on half
  * nodes), order 2 in time and 4 or 8 in space, split-field PML of npml
