@@ -134,3 +134,28 @@ def test_gradient_central_differences_at_production_size():
     an = float(np.sum(g * dk))
     print(f"  <g, dk> {an:.10e}  central difference {fdiff:.10e}")
     assert abs(fdiff - an) <= 1e-5 * abs(an)
+
+
+@pytest.mark.parametrize("fd", ["f64", "f32"])
+def test_gradient_edge_geometry(fd):
+    # no absorbing layer (the stencils reach into the zero ghost cells), odd
+    # sizes, a single shot, one step and a record of several
+    for nt in (1, 37):
+        prob = problem(8, 1, nz=23, nx=131, nt=nt, npml=0, z_src=107.5, x_src0=10.0, ns=117,
+                       z_rec=33.3, x_rec0=0.0, nr=131, slab_dz=-4, xs=(500.0,))
+        print(f"case gradient edge nt={nt} dtype={fd}", flush=True)
+        kap = kappa(prob, 9)
+        m = oracle.Model(prob, kap, RHO)
+        ctx = ssx.Context(prob, kap, RHO, field_dtype=fd)
+        rng = np.random.default_rng(nt)
+        h = rng.standard_normal((1, prob.nt, prob.ns))
+        d = rng.standard_normal((1, prob.nt, prob.nr))
+        g, J = ctx.misfit_gradient(dev(h, fd), dev(d, fd))
+        gr, Jr = oracle.misfit_gradient(m, h[0], d[0])
+        tol = 1e-10 if fd == "f64" else 1e-4
+        if np.linalg.norm(gr) > 0:
+            assert rel(host(g)[0], gr) < tol
+        else:
+            assert np.abs(host(g)[0]).max() == 0.0
+        assert abs(J[0] - Jr) <= tol * Jr
+        ctx.close()
