@@ -281,7 +281,8 @@ ssx_status ssx_block(ssx_ctx* ctx, int32_t src, int32_t rec, int32_t transpose, 
  * fields only (SSX_ERR_ARG otherwise).  The first call allocates the step
  * history, nt * nshots * nz * nx field values plus an FP64 accumulator,
  * held until ssx_destroy (also for contexts made with a workspace);
- * SSX_ERR_OOM if that fails.  Two full simulations, one launch per step. */
+ * SSX_ERR_OOM if that fails.  Two full simulations, one step per launch
+ * (replayed as one captured graph when graphs are on). */
 ssx_status ssx_misfit_gradient(ssx_ctx* ctx, const void* h, const void* d, void* g,
                                double* J_host);
 

@@ -705,19 +705,11 @@ ssx_status issue_propagation(ssx_ctx* c, GridDev& gd, bool adj, const LineDev& v
 
 constexpr size_t GRAPH_CACHE_MAX = 12;
 
-// Runs a propagation: replays a cached graph for (op, pointers) when graphs
-// are enabled (capturing it on first use), else issues the launches.
-ssx_status propagate(ssx_ctx* c, int op, GridDev& gd, bool adj, const LineDev& vsl, TraceIO vs,
-                     const LineDev& vil, TraceIO vi, const LineDev& psl, TraceIO ps,
-                     const LineDev& pil, TraceIO pi) {
-  if (!c->graphs)
-    return issue_propagation(c, gd, adj, vsl, vs, vil, vi, psl, ps, pil, pi, c->run);
-  const void* key[4] = {vs.out, vi.in, ps.out, pi.in};
-  const int tz = (&gd == &c->full) ? c->tile_z_full : c->tile_z_slab;
-  const int spl = (&gd == &c->full) ? c->spl_full : c->spl_slab;
-  const int group = (&gd == &c->full) ? c->group_full : c->group_slab;
-  const int strip = (&gd == &c->full) ? 0 : c->slab_strip;
-  const int loop = (&gd == &c->full) ? c->loop_full : 0;
+// Replays the cached graph of (op, key pointers, launch options), or captures
+// `issue` (given the stream to issue on) into one on first use; runs it on
+// the context's stream.
+ssx_status cached_graph(ssx_ctx* c, int op, const void* const key[4], int tz, int spl, int group,
+                        int strip, int loop, const std::function<ssx_status(hipStream_t)>& issue) {
   for (GraphEntry& e : c->graphs_cache) {
     if (e.op == op && e.ptr[0] == key[0] && e.ptr[1] == key[1] && e.ptr[2] == key[2] &&
         e.ptr[3] == key[3] && e.tile_z == tz && e.fused == (int)c->fused && e.spl == spl &&
@@ -729,7 +721,7 @@ ssx_status propagate(ssx_ctx* c, int op, GridDev& gd, bool adj, const LineDev& v
   }
   if (!c->cap_stream) SSX_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
   SSX_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-  ssx_status st = issue_propagation(c, gd, adj, vsl, vs, vil, vi, psl, ps, pil, pi, c->cap_stream);
+  ssx_status st = issue(c->cap_stream);
   hipGraph_t graph = nullptr;
   hipError_t e1 = hipStreamEndCapture(c->cap_stream, &graph);
   if (st != SSX_OK) {
@@ -765,6 +757,24 @@ ssx_status propagate(ssx_ctx* c, int op, GridDev& gd, bool adj, const LineDev& v
   return SSX_OK;
 }
 
+// Runs a propagation: replays a cached graph for (op, pointers) when graphs
+// are enabled (capturing it on first use), else issues the launches.
+ssx_status propagate(ssx_ctx* c, int op, GridDev& gd, bool adj, const LineDev& vsl, TraceIO vs,
+                     const LineDev& vil, TraceIO vi, const LineDev& psl, TraceIO ps,
+                     const LineDev& pil, TraceIO pi) {
+  if (!c->graphs)
+    return issue_propagation(c, gd, adj, vsl, vs, vil, vi, psl, ps, pil, pi, c->run);
+  const void* key[4] = {vs.out, vi.in, ps.out, pi.in};
+  const bool full = &gd == &c->full;
+  return cached_graph(c, op, key, full ? c->tile_z_full : c->tile_z_slab,
+                      full ? c->spl_full : c->spl_slab, full ? c->group_full : c->group_slab,
+                      full ? 0 : c->slab_strip, full ? c->loop_full : 0,
+                      [&](hipStream_t s) {
+                        return issue_propagation(c, gd, adj, vsl, vs, vil, vi, psl, ps, pil, pi,
+                                                 s);
+                      });
+}
+
 void drop_graphs(ssx_ctx* c) {
   for (GraphEntry& e : c->graphs_cache) (void)hipGraphExecDestroy(e.exec);
   c->graphs_cache.clear();
@@ -775,8 +785,19 @@ enum {
   OP_RSLAB_FWD = 4, OP_RSLAB_ADJ = 5, OP_SLABP_FWD = 6, OP_SLABP_ADJ = 7,
   OP_V_FWD = 8, OP_V_ADJ = 9, OP_LAM_ADJ = 10, OP_LAMT_ADJ = 11, OP_RLAM_ADJ = 12,
   OP_RLAMT_ADJ = 13, OP_TR_INV = 14,
-  OP_B01_FWD = 15, OP_B01_ADJ = 16, OP_B10_FWD = 17, OP_B10_ADJ = 18
+  OP_B01_FWD = 15, OP_B01_ADJ = 16, OP_B10_FWD = 17, OP_B10_ADJ = 18,
+  OP_GRAD = 19
 };
+
+// The library's second stream and its events, created on first use (at
+// the default priority).
+ssx_status ensure_aux(ssx_ctx* c) {
+  if (c->aux) return SSX_OK;
+  SSX_HIP(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+  SSX_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+  SSX_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+  return SSX_OK;
+}
 
 ssx_status do_fwd(ssx_ctx* c, const void* h, void* d) {
   const ssx_problem& p = c->prob;
@@ -941,11 +962,7 @@ ssx_status do_normal_w(ssx_ctx* c, const double* alpha2_dev, double alpha2_host,
   const ssx_problem& pr = c->prob;
   const bool fork = with_m && c->overlap;
   if (fork) {
-    if (!c->aux) {
-      SSX_HIP(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
-      SSX_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-      SSX_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
-    }
+    SSX_TRY(ensure_aux(c));
     SSX_HIP(hipEventRecord(c->ev_fork, c->stream));
     SSX_HIP(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
     ssx_status st = wm_term(c, p, c->aux);
@@ -970,23 +987,15 @@ ssx_status do_normal_w(ssx_ctx* c, const double* alpha2_dev, double alpha2_host,
   return SSX_OK;
 }
 
-// g = dJ/dkappa of J = 1/2 ||F h - d||^2 on the physical cells, J per shot
-// (see ssx_grad.hip): a forward sweep storing r^n, the residual, and a
-// transposed sweep accumulating P~^{n+1} r^n, both one step per launch.
-ssx_status do_gradient(ssx_ctx* c, const void* h, const void* d, void* g, double* J_host) {
+// The device work of one misfit gradient (see ssx_grad.hip) on stream s: a
+// forward sweep storing r^n after every step, the residual, and a
+// transposed sweep accumulating P~^{n+1} r^n before every step, both one
+// step per launch.  (Running the store and accumulation kernels on a second
+// stream beside the next step measured slower: the steps already occupy
+// the device.)
+ssx_status issue_gradient(ssx_ctx* c, const void* h, const void* d, void* g, hipStream_t s) {
   const ssx_problem& p = c->prob;
-  hipStream_t s = c->stream;
   const long long cells = (long long)p.nz * p.nx;
-  if (!c->ghist) {
-    if (hipMalloc(&c->ghist, (size_t)p.nt * p.nshots * cells * c->fsz) != hipSuccess ||
-        hipMalloc((void**)&c->gacc, (size_t)p.nshots * cells * sizeof(double)) != hipSuccess) {
-      (void)hipGetLastError();
-      if (c->ghist) (void)hipFree(c->ghist);
-      c->ghist = nullptr;
-      c->gacc = nullptr;
-      return fail(SSX_ERR_OOM, "device allocation of the gradient history failed");
-    }
-  }
   const long long ns_ = nvec_s(p), nr_ = nvec_r(p);
   auto hist_at = [&](int n, int s0) {
     return (char*)c->ghist + ((size_t)n * p.nshots + s0) * cells * c->fsz;
@@ -1013,10 +1022,37 @@ ssx_status do_gradient(ssx_ctx* c, const void* h, const void* d, void* g, double
                             c->h_line, io_none(), c->r_line, io_in(c->e, nr_, c->Z0), s, &accum));
   SSX_HIP(launch_grad_final(c->fdt, c->gacc, c->full.coef.ck, c->full.dims, p.nz, p.nx,
                             p.dt / (p.h * c->Z0), g, p.nshots, s));
+  return SSX_OK;
+}
+
+// g = dJ/dkappa of J = 1/2 ||F h - d||^2 on the physical cells, J per shot,
+// replayed as one captured graph when graphs are on.
+ssx_status do_gradient(ssx_ctx* c, const void* h, const void* d, void* g, double* J_host) {
+  const ssx_problem& p = c->prob;
+  const long long cells = (long long)p.nz * p.nx;
+  if (!c->ghist) {
+    if (hipMalloc(&c->ghist, (size_t)p.nt * p.nshots * cells * c->fsz) != hipSuccess ||
+        hipMalloc((void**)&c->gacc, (size_t)p.nshots * cells * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      if (c->ghist) (void)hipFree(c->ghist);
+      c->ghist = nullptr;
+      c->gacc = nullptr;
+      return fail(SSX_ERR_OOM, "device allocation of the gradient history failed");
+    }
+  }
+  if (!c->graphs) {
+    SSX_TRY(issue_gradient(c, h, d, g, c->stream));
+  } else {
+    const void* key[4] = {h, d, g, nullptr};
+    SSX_TRY(cached_graph(c, OP_GRAD, key, c->tile_z_full, c->spl_full, c->group_full, 0,
+                         c->loop_full, [&](hipStream_t s) {
+                           return issue_gradient(c, h, d, g, s);
+                         }));
+  }
   if (J_host) {
     std::vector<double> tmp((size_t)p.nshots * SC_N);
-    SSX_HIP(hipMemcpyAsync(tmp.data(), c->sc, tmp.size() * 8, hipMemcpyDeviceToHost, s));
-    SSX_HIP(hipStreamSynchronize(s));
+    SSX_HIP(hipMemcpyAsync(tmp.data(), c->sc, tmp.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    SSX_HIP(hipStreamSynchronize(c->stream));
     for (int sh = 0; sh < p.nshots; ++sh) J_host[sh] = 0.5 * tmp[(size_t)sh * SC_N + SC_TMP];
   }
   return SSX_OK;

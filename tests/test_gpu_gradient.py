@@ -81,9 +81,13 @@ def test_gradient_independent_of_launch_options():
     d = dev(rng.standard_normal((3, prob.nt, prob.nr)), "f32")
     ref, Jref = ctx.misfit_gradient(h, d)
     ref = ref.clone()
-    for opt, val in ((ssx.OPT_TILE_LOOP, 1), (ssx.OPT_TILE_Z, 8), (ssx.OPT_SHOT_GROUP, 2),
+    # a replay of the captured graph, then each option in turn (eager
+    # launches, other step kernels and launch shapes)
+    for opt, val in ((None, None), (ssx.OPT_GRAPHS, 0), (ssx.OPT_GRAPHS, 1), (ssx.OPT_TILE_LOOP, 1),
+                     (ssx.OPT_TILE_Z, 8), (ssx.OPT_SHOT_GROUP, 2),
                      (ssx.OPT_STEPS_PER_LAUNCH, 2), (ssx.OPT_STEP_KERNEL, 0)):
-        ctx.set_option(opt, val)
+        if opt is not None:
+            ctx.set_option(opt, val)
         g, J = ctx.misfit_gradient(h, d)
         torch.cuda.synchronize()
         assert torch.equal(g, ref), (opt, val)
