@@ -438,6 +438,10 @@ def crosswell_bench(args):
     hctx.close()
     dhn = nrm(d_h)
     mis_hs = nrm(ctx.fwd(-2.0 * vs, ctx.empty_r()) - d_h) / dhn
+    # the model-space form of approxinv, 4 V^T F h ~ h, on that equivalent
+    # pressure source
+    h_eq = -2.0 * vs
+    tr_model = nrm(ctx.tr_inverse(ctx.fwd(h_eq, ctx.empty_r()), ctx.empty_s()) - h_eq) / nrm(h_eq)
     mis_fs = nrm(ctx.block(1, 0, False, -2.0 * ps, ctx.empty_r()) - d_h) / dhn
     # the near datum against the whole path to the receiver surface: Lambda~
     # with the datum 100 cells from the source line (a slab of the full
@@ -462,6 +466,7 @@ def crosswell_bench(args):
     lctx.close()
     checks = {"pressure_source_equivalence_misfit": round(mis_hs, 4),
               "lambda_near_vs_full_path": round(near_far, 4),
+              "time_reversal_model_space_misfit": round(tr_model, 4),
               "symmetrised_lambda_source_misfit": round(sym_src, 4),
               "normal_load_equivalence_misfit": round(mis_fs, 4),
               "time_reversal_resimulation_misfit": round(mis_tr, 4),
