@@ -703,7 +703,9 @@ ssx_status issue_propagation(ssx_ctx* c, GridDev& gd, bool adj, const LineDev& v
   return SSX_OK;
 }
 
-constexpr size_t GRAPH_CACHE_MAX = 12;
+// one weighted PCG iteration replays ten distinct propagations; room for them,
+// the Euclidean solve, the other operators and a gradient
+constexpr size_t GRAPH_CACHE_MAX = 24;
 
 // Replays the cached graph of (op, key pointers, launch options), or captures
 // `issue` (given the stream to issue on) into one on first use; runs it on
