@@ -703,7 +703,7 @@ ssx_status issue_propagation(ssx_ctx* c, GridDev& gd, bool adj, const LineDev& v
   return SSX_OK;
 }
 
-// one weighted PCG iteration replays ten distinct propagations; room for them,
+// a weighted PCG solve replays ten distinct propagations; room for them,
 // the Euclidean solve, the other operators and a gradient
 constexpr size_t GRAPH_CACHE_MAX = 24;
 
