@@ -35,4 +35,4 @@ kappa and Krylov-subspace optimality.
 """
 from . import fd, grid, prop, ops, greens  # noqa: F401
 from .ops import (Model, pcg, pcg_solve, precond, penalty, dscale, normal,  # noqa: F401
-                  normal_w, pcg_solve_w, misfit_gradient)
+                  normal_w, pcg_solve_w, misfit_gradient, normal_v, pcg_solve_v)

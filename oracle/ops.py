@@ -402,3 +402,27 @@ def misfit_gradient(model: Model, h, d):
     grad = -(prob.dt / prob.h) * acc[L:L + prob.nz, L:L + prob.nx]
     return grad, 0.5 * float(np.sum(res * res))
 
+
+
+# ----------------------------------------------------------------------------
+# the subproblem with the normal load as the unknown (Operators section: the
+# source vector's second component f_s, observed through the normal
+# velocity, V = Pi_1 S Pi_1^T of the vdef definition)
+
+def normal_v(model: Model, alpha: float, p, shot: int = 0):
+    """N_v p = V^T V p + alpha^2 A^T A p; also returns V p."""
+    Vp = model.fwd_v(p)
+    Ap = penalty(model.prob, p, shot)
+    return model.adj_v(Vp) + alpha * alpha * penalty(model.prob, Ap, shot), Vp
+
+
+def pcg_solve_v(model: Model, d, alpha_rel: float, K: int, shot: int = 0):
+    """min_f ||V f - d||^2 + alpha^2 ||A f||^2 for normal-velocity data d
+    [nt][nr]: b = V^T d, alpha = alpha_rel ||b|| / ||d||, K iterations of
+    Algorithm 1 with M = I (the paper derives no preconditioner for this
+    form)."""
+    b = model.adj_v(d)
+    alpha = alpha_rel * math.sqrt(dot(b, b)) / math.sqrt(dot(d, d))
+    h, hist = pcg(lambda p: normal_v(model, alpha, p, shot), lambda r: r.copy(), b, K,
+                  d_misfit=d)
+    return h, hist, alpha

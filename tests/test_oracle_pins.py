@@ -809,3 +809,24 @@ def test_reduced_objective_gradient_is_partial_gradient():
     fdiff = (Jr(kap + eps * dk) - Jr(kap - eps * dk)) / (2 * eps)
     an = float(np.sum(g * dk))
     assert abs(fdiff - an) <= 1e-5 * abs(an), (fdiff, an)
+
+
+def test_normal_load_subproblem_converges_to_dense_solution():
+    # the normal-load form: N_v = V^T V + alpha^2 A^T A assembled densely
+    # from V is SPD; Algorithm 1 with M = I reaches its Cholesky solution,
+    # and alpha follows the relative rule with b = V^T d
+    prob = tiny_problem(nt=20, ns=8, nr=10, xs=(47.0,))
+    m = oracle.Model(prob, tiny_kappa(prob, 71), RHO)
+    n = prob.nt * prob.ns
+    Vd = dense(m.fwd_v, n, (prob.nt, prob.ns))
+    d = np.random.default_rng(72).standard_normal((prob.nt, prob.nr))
+    b = Vd.T @ d.ravel()
+    alpha = 1e-2 * np.linalg.norm(b) / np.linalg.norm(d)
+    A = np.tile(oracle.ops.lateral_distance(prob), prob.nt)
+    N = Vd.T @ Vd + alpha ** 2 * np.diag(A * A)
+    Lc = np.linalg.cholesky(N)
+    hstar = np.linalg.solve(Lc.T, np.linalg.solve(Lc, b))
+    h, hist, al = oracle.pcg_solve_v(m, d, 1e-2, 400)
+    assert abs(al - alpha) <= 1e-15 * alpha
+    assert np.linalg.norm(h.ravel() - hstar) <= 1e-8 * np.linalg.norm(hstar)
+    assert abs(hist[-1, 3] - np.linalg.norm(m.fwd_v(h) - d)) <= 1e-10 * np.linalg.norm(d)
