@@ -235,6 +235,17 @@ ssx_status ssx_pcg_solve_w(ssx_ctx* ctx, const void* d, double alpha, int32_t ma
                            double rtol, int32_t use_precond, void* h_out,
                            double* hist_host, int32_t* iters_host);
 
+/* The subproblem with the normal load as the unknown (the source vector's
+ * second component, observed as normal velocity on the receiver line):
+ * min_f ||V f - d||^2 + alpha^2 ||A f||^2, Algorithm 1 on N_v f = V^T d,
+ * N_v = V^T V + alpha^2 A^T A, alpha = alpha_rel ||V^T d|| / ||d||, with
+ * M = I (the paper derives no preconditioner for this form).  d:
+ * [nshots][nt][nr] normal-velocity traces; f_out: [nshots][nt][ns]; hist
+ * and return codes as ssx_pcg_solve (column 4: ||V f_k - d||).  Needs the
+ * normal-velocity rows of ssx_fwd_v (SSX_ERR_ARG otherwise). */
+ssx_status ssx_pcg_solve_v(ssx_ctx* ctx, const void* d, double alpha_rel, int32_t maxit,
+                           double rtol, void* f_out, double* hist_host, int32_t* iters_host);
+
 /* ---- V, the time-reversal inverse and Lambda~ (Time Reversal, Unitarity,
  * Computing and Symmetrizing Lambda). */
 

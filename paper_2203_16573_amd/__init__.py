@@ -25,6 +25,7 @@ Function names follow the C ABI (include/ssx.h):
     ctx.lam(side, transpose, x, y)   y = Lambda~ x or its transpose
     ctx.block(src, rec, transpose, x, y)   a block of the modelling operator
     ctx.misfit_gradient(h, d, g) -> J   dJ/dkappa of 1/2 ||F h - d||^2
+    ctx.pcg_solve_v(d, alpha_rel, maxit)   the normal load as the unknown
 
 ``prob`` is any object with the fields of ``ssx_problem`` (nz, nx, h, dt,
 nt, order, npml, pml_R, z_src, x_src0, ns, z_rec, x_rec0, nr, slab_dz and,
@@ -57,7 +58,7 @@ EXPORTS = ("ssx_validate", "ssx_footprint", "ssx_create", "ssx_destroy", "ssx_fw
            "ssx_step_kernel_name", "ssx_cells_per_launch", "ssx_launch_shape",
            "ssx_weight_d", "ssx_weight_m", "ssx_normal_w", "ssx_pcg_solve_w",
            "ssx_fwd_v", "ssx_adj_v", "ssx_tr_inverse", "ssx_lambda", "ssx_block",
-           "ssx_misfit_gradient")
+           "ssx_misfit_gradient", "ssx_pcg_solve_v")
 
 
 class SSXError(RuntimeError):
@@ -122,6 +123,8 @@ def lib():
         L.ssx_lambda.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, vp, vp]
         L.ssx_block.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp]
         L.ssx_misfit_gradient.argtypes = [vp, vp, vp, vp, dp]
+        L.ssx_pcg_solve_v.argtypes = [vp, vp, c_dbl, ctypes.c_int32, c_dbl, vp, dp,
+                                      ctypes.POINTER(ctypes.c_int32)]
         L.ssx_set_option.argtypes = [vp, c_int, c_int]
         L.ssx_last_error.restype = ctypes.c_char_p
         L.ssx_step_kernel_name.argtypes = [vp]
@@ -338,6 +341,20 @@ class Context:
         _check(lib().ssx_block(self._ctx, int(src), int(rec), int(bool(transpose)),
                                self._vec(x, nin, "x"), self._vec(y, nout, "y")))
         return y
+
+    def pcg_solve_v(self, d, alpha_rel, maxit, rtol=0.0, f=None, raise_on_breakdown=True):
+        """The normal load as the unknown: d [nshots][nt][nr] normal-velocity
+        traces.  Returns (f, hist, iterations, status)."""
+        if f is None:
+            f = self.empty_s()
+        hist = np.zeros((self.nshots, maxit + 1, 4))
+        it = ctypes.c_int32(0)
+        st = lib().ssx_pcg_solve_v(self._ctx, self._vec(d, self.n_r, "d"), float(alpha_rel),
+                                   int(maxit), float(rtol), self._vec(f, self.n_s, "f"),
+                                   _dptr(hist), ctypes.byref(it))
+        if st != 0 and (raise_on_breakdown or st not in (5, 6)):
+            _check(st)
+        return f, hist[:, : it.value + 1], it.value, st
 
     def empty_model(self):
         import torch

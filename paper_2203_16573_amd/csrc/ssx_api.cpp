@@ -1312,11 +1312,15 @@ ssx_status ssx_dot(ssx_ctx* c, const void* x, const void* y, int64_t n, double* 
 
 namespace {
 
-// Algorithm 1 for ssx_pcg_solve (weighted = false: N h = F^T d, alpha =
-// a ||F^T d|| / ||d||, alpha_hat = a) and ssx_pcg_solve_w (weighted = true:
-// N_w h = F^T W_d d, alpha = alpha_hat = a).
-ssx_status run_pcg(ssx_ctx* c, bool weighted, const void* d, double a, int32_t maxit, double rtol,
+// Algorithm 1 for ssx_pcg_solve (EUCLID: N h = F^T d, alpha =
+// a ||F^T d|| / ||d||, alpha_hat = a), ssx_pcg_solve_w (WEIGHTED: N_w h =
+// F^T W_d d, alpha = alpha_hat = a) and ssx_pcg_solve_v (VELOCITY: the
+// normal load as the unknown, N_v f = V^T d with V in place of F, alpha as
+// EUCLID, M = I).
+enum class Pcg { EUCLID, WEIGHTED, VELOCITY };
+ssx_status run_pcg(ssx_ctx* c, Pcg mode, const void* d, double a, int32_t maxit, double rtol,
                    int32_t use_precond, void* h_out, double* hist_host, int32_t* iters_host) {
+  const bool weighted = mode == Pcg::WEIGHTED;
   const ssx_problem& p = c->prob;
   hipStream_t s = c->stream;
   const int ns = p.nshots;
@@ -1330,6 +1334,8 @@ ssx_status run_pcg(ssx_ctx* c, bool weighted, const void* d, double a, int32_t m
   if (weighted) {  // r_0 = F^T W_d d
     SSX_TRY(do_wd(c, d, c->rW));
     SSX_TRY(do_adj(c, c->rW, c->r));
+  } else if (mode == Pcg::VELOCITY) {  // r_0 = V^T d
+    SSX_TRY(do_adj_v(c, d, c->r, false));
   } else {  // r_0 = F^T d
     SSX_TRY(do_adj(c, d, c->r));
   }
@@ -1343,6 +1349,13 @@ ssx_status run_pcg(ssx_ctx* c, bool weighted, const void* d, double a, int32_t m
   };
   auto apply_N = [&]() -> ssx_status {
     if (weighted) return do_normal_w(c, sc + SC_ALPHA2, 0.0, a != 0.0, c->p, c->q, c->Fp);
+    if (mode == Pcg::VELOCITY) {  // q = V^T V p + alpha^2 A^T A p
+      SSX_TRY(do_fwd_v(c, c->p, c->Fp));
+      SSX_TRY(do_adj_v(c, c->Fp, c->q, false));
+      SSX_HIP(launch_add_penalty(c->vdbl, c->q, c->p, 2, sc + SC_ALPHA2, SC_N, 0.0, p.nt, p.ns,
+                                 p.nshots, p.x_src0, p.h, c->xs_dev, s));
+      return SSX_OK;
+    }
     return do_normal(c, sc + SC_ALPHA2, 0.0, c->p, c->q, c->Fp);
   };
   SSX_TRY(apply_M(c->r, c->g));
@@ -1406,7 +1419,8 @@ ssx_status ssx_pcg_solve(ssx_ctx* c, const void* d, double alpha_rel, int32_t ma
   if (!c || !d || !h_out) return fail(SSX_ERR_ARG, "null argument");
   if (maxit < 0 || maxit > HIST_CAP) return fail(SSX_ERR_ARG, "maxit out of range");
   if (!std::isfinite(alpha_rel) || alpha_rel < 0) return fail(SSX_ERR_ARG, "alpha_rel must be >= 0");
-  return run_pcg(c, false, d, alpha_rel, maxit, rtol, use_precond, h_out, hist_host, iters_host);
+  return run_pcg(c, Pcg::EUCLID, d, alpha_rel, maxit, rtol, use_precond, h_out, hist_host,
+                 iters_host);
 }
 
 ssx_status ssx_weight_d(ssx_ctx* c, const void* r, void* y) {
@@ -1435,7 +1449,17 @@ ssx_status ssx_pcg_solve_w(ssx_ctx* c, const void* d, double alpha, int32_t maxi
   if (!c->has_rslab) return fail(SSX_ERR_ARG, "context has no receiver-side slab (rslab_dz == 0)");
   if (maxit < 0 || maxit > HIST_CAP) return fail(SSX_ERR_ARG, "maxit out of range");
   if (!std::isfinite(alpha) || alpha < 0) return fail(SSX_ERR_ARG, "alpha must be >= 0");
-  return run_pcg(c, true, d, alpha, maxit, rtol, use_precond, h_out, hist_host, iters_host);
+  return run_pcg(c, Pcg::WEIGHTED, d, alpha, maxit, rtol, use_precond, h_out, hist_host,
+                 iters_host);
+}
+
+ssx_status ssx_pcg_solve_v(ssx_ctx* c, const void* d, double alpha_rel, int32_t maxit,
+                           double rtol, void* f_out, double* hist_host, int32_t* iters_host) {
+  if (!c || !d || !f_out) return fail(SSX_ERR_ARG, "null argument");
+  if (!c->has_v) return fail(SSX_ERR_ARG, "no normal-velocity rows at the source or receiver depth");
+  if (maxit < 0 || maxit > HIST_CAP) return fail(SSX_ERR_ARG, "maxit out of range");
+  if (!std::isfinite(alpha_rel) || alpha_rel < 0) return fail(SSX_ERR_ARG, "alpha_rel must be >= 0");
+  return run_pcg(c, Pcg::VELOCITY, d, alpha_rel, maxit, rtol, 0, f_out, hist_host, iters_host);
 }
 
 ssx_status ssx_fwd_v(ssx_ctx* c, const void* f, void* y) {

@@ -192,3 +192,31 @@ def test_blocks_and_lambda_half_precision_storage_error(fd, tol):
     print(f"{fd} storage: relative L2 errors {errs}")
     assert max(errs) < tol
     ctx.close()
+
+
+@pytest.mark.parametrize("fd", ["f64", "f32"])
+def test_pcg_solve_v_parity(fd):
+    # the normal load as the unknown: Algorithm 1 with M = I on N_v
+    prob = problem(8)
+    print(f"case pcg_v dtype={fd}", flush=True)
+    kap = kappa(prob, 8)
+    m = oracle.Model(prob, kap, RHO)
+    ctx = ssx.Context(prob, kap, RHO, field_dtype=fd)
+    rng = np.random.default_rng(16)
+    d = rng.standard_normal((2, prob.nt, prob.nr))
+    K = 5
+    f, hist, it, st = ctx.pcg_solve_v(dev(d, fd), 1e-3, K)
+    assert it == K and st == 0
+    f = host(f)
+    tol = 1e-10 if fd == "f64" else 1e-4
+    for s in range(2):
+        fr, histr, _ = oracle.pcg_solve_v(m, d[s], 1e-3, K, shot=s)
+        assert rel(f[s], fr) < tol
+        assert np.allclose(hist[s], histr, rtol=10 * tol, atol=0)
+    ctx.close()
+    # refused without normal-velocity rows at the receiver depth
+    prob = problem(8, 1, z_rec=360.0, xs=(500.0,))
+    ctx = ssx.Context(prob, kappa(prob), RHO, field_dtype="f32")
+    with pytest.raises(ssx.SSXError):
+        ctx.pcg_solve_v(ctx.empty_r().zero_(), 1e-3, 2)
+    ctx.close()
