@@ -113,3 +113,12 @@ def test_footprint_counts_the_receiver_side_slab():
     # one more slab of fields and coefficients plus three trace vectors
     assert base < both < 1.5 * base
     ssx.validate(wl.prob.replace(rslab_dz=4), wl.kappa, wl.rho, field_dtype="f64")
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stdout

@@ -134,3 +134,25 @@ def test_rtol_stops_early():
     assert hist[0, it, 0] <= 0.5 * hist[0, 0, 0]
     assert hist[0, it - 1, 0] > 0.5 * hist[0, 0, 0] or it == 1
     ctx.close()
+
+
+def test_graph_cache_eviction_keeps_results():
+    # more distinct propagations than the graph cache holds: evicted graphs
+    # are destroyed and re-captured, every result stays the same
+    prob = inputs.Problem(nz=20, nx=40, h=10.0, dt=1e-3, nt=30, order=4, npml=5, z_src=50.0,
+                          x_src0=0.0, ns=40, z_rec=20.0, x_rec0=0.0, nr=40, slab_dz=3,
+                          xs=(100.0,))
+    print("case graph cache eviction", flush=True)
+    ctx = ssx.Context(prob, kappa(20, 40, 8), RHO, field_dtype="f64")
+    h = torch.tensor(np.random.default_rng(3).standard_normal((1, prob.nt, prob.ns)),
+                     device="cuda")
+    outs = [ctx.empty_r() for _ in range(40)]
+    for o in outs:
+        ctx.fwd(h, o)
+    ref = outs[0].clone()
+    for o in outs[::-1]:
+        ctx.fwd(h, o)
+    torch.cuda.synchronize()
+    for o in outs:
+        assert torch.equal(o, ref)
+    ctx.close()
