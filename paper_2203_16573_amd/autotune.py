@@ -31,7 +31,21 @@ def shape_key(prob, nshots: int, field_dtype: str) -> str:
     NZ, NX = prob.nz + 2 * prob.npml, prob.nx + 2 * prob.npml
     k = prob.order // 2
     nzs = abs(prob.slab_dz) + 1 + 2 * k + 2 * prob.npml
-    return f"{NZ}x{NX}|slab{nzs}|o{prob.order}|{field_dtype}|s{nshots}"
+    key = f"{NZ}x{NX}|slab{nzs}|o{prob.order}|{field_dtype}|s{nshots}"
+    rdz = int(getattr(prob, "rslab_dz", 0))
+    if rdz:  # the receiver-side slab shares the slab options
+        key += f"|rslab{abs(rdz) + 1 + 2 * k + 2 * prob.npml}"
+    return key
+
+
+def tallest_slab(prob) -> int:
+    """Rows of the taller thin slab (one more than the count for a line
+    between rows), which must fit the multi-step slab kernel."""
+    rows = abs(prob.slab_dz) + 1 + prob.order + 2 * prob.npml + 1
+    rdz = int(getattr(prob, "rslab_dz", 0))
+    if rdz:
+        rows = max(rows, abs(rdz) + 1 + prob.order + 2 * prob.npml + 1)
+    return rows
 
 
 def _load(path):
@@ -101,8 +115,7 @@ def tune(prob, kappa, rho, xs=None, field_dtype="f32", nt_tune: int = 60,
     # full-grid candidates: one-step launches also with workgroups looping
     # over the interior tiles
     full_cands = [(spl, tz, 0) for spl, tz in cands] + [(1, tz, 1) for spl, tz in cands if spl == 1]
-    nzs = abs(short.slab_dz) + 1 + short.order + 2 * short.npml + 1
-    if field_dtype != "f64" and nzs <= SLAB_MAXZ:
+    if field_dtype != "f64" and tallest_slab(short) <= SLAB_MAXZ:
         slab_cands += [(4, 8, 64), (4, 8, 128), (8, 8, 128)]
     us = {}
     ctx.set_option(OPT_STEP_KERNEL, 1)

@@ -25,3 +25,4 @@ def test_summary_percentiles():
     assert s["solves"] == 200 and s["requests"] == 100
     assert abs(s["latency_p50_s"] - 50.5) < 1e-9
     assert s["latency_p99_s"] > 99
+
