@@ -64,6 +64,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target length of the oracle's bounded CPU sample")
+    ap.add_argument("--cpu-procs", type=int, default=16,
+                    help="batched configurations: also time the oracle in this many "
+                         "concurrent processes, one shot each (capped by the shots and the "
+                         "host's cores)")
     ap.add_argument("--shots", type=int, default=0,
                     help="override the number of shots (spread across the surface as in "
                          "the batched configuration)")
@@ -91,6 +95,37 @@ def parse():
                     help="with --prop-only: also run 10 plain device copies of this many "
                          "MB (reference for hardware byte counters)")
     return ap.parse_args()
+
+
+def oracle_parallel(cnum, steps, nproc):
+    """Seconds that each of nproc concurrent child processes (fresh
+    interpreters, one thread each, started together) takes for a steps-long
+    oracle forward run of configuration cnum; None if any of them fails."""
+    import subprocess
+    start = time.time() + 8.0
+    code = (
+        "import sys, time, json\n"
+        f"sys.path.insert(0, {ROOT!r})\n"
+        "import numpy as np, inputs, oracle\n"
+        f"wl = inputs.workload({cnum})\n"
+        f"prob = wl.prob.replace(nt={steps}, xs=wl.prob.xs[:1])\n"
+        "m = oracle.Model(prob, wl.kappa, wl.rho)\n"
+        f"hs = np.random.default_rng(0).standard_normal(({steps}, prob.ns))\n"
+        f"time.sleep(max(0.0, {start} - time.time()))\n"
+        "t = time.perf_counter()\n"
+        "m.fwd(hs)\n"
+        "print(json.dumps(time.perf_counter() - t))\n")
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    procs = [subprocess.Popen([sys.executable, "-c", code], stdout=subprocess.PIPE,
+                              stderr=subprocess.DEVNULL, env=env, text=True)
+             for _ in range(nproc)]
+    out = []
+    for pr in procs:
+        o, _ = pr.communicate()
+        if pr.returncode != 0:
+            return None
+        out.append(float(o.strip().splitlines()[-1]))
+    return out
 
 
 def cpu_model():
@@ -278,6 +313,19 @@ def main():
                          f"padded grid ({tc:.1f} s, {cpu_gcell:.4f} Gcell/s, 1 thread), "
                          f"extrapolated linearly to {cu_solve:.3e} cell-updates per solve",
                "cpu": cpu_model()}
+        nproc = min(prob.nshots, args.cpu_procs, os.cpu_count() or 1)
+        if nproc > 1 and not (args.nt or args.shots):
+            par = oracle_parallel(cnum, ns_cpu, nproc)
+            if par:
+                pg = sum(ns_cpu * NZ * NX / t for t in par) / 1e9
+                cpu = {"value": pg * 1e9 / cu_solve, "unit": "solves/s", "cores": nproc,
+                       "kind": "oracle",
+                       "sample": f"FP64 NumPy oracle forward, {ns_cpu} steps of the {NZ}x{NX} "
+                                 f"padded grid in {nproc} concurrent single-threaded "
+                                 f"processes, one shot each ({min(par):.1f}-{max(par):.1f} s, "
+                                 f"{pg:.4f} Gcell/s together), extrapolated linearly to "
+                                 f"{cu_solve:.3e} cell-updates per solve",
+                       "single_core_value": cpu["value"], "cpu": cpu_model()}
 
     ref = None
     if args.ref_f64:
