@@ -46,6 +46,9 @@ def parse():
                          "the step history, transposed sweep accumulating it) instead of "
                          "the solve")
     ap.add_argument("--outer", type=int, default=4, help="vp: outer iterations")
+    ap.add_argument("--compare-cg", action="store_true",
+                    help="c1..c4: after timing, also solve with M = I (plain CG) and report "
+                         "both residual histories, misfits and source errors")
     ap.add_argument("--solver", default="plain", choices=["plain", "weighted"],
                     help="c1..c4: Algorithm 1 on the Euclidean normal equations (plain) or "
                          "on the weighted ones N_w h = F^T W_d d (weighted)")
@@ -327,6 +330,26 @@ def main():
                                  f"{cu_solve:.3e} cell-updates per solve",
                        "single_core_value": cpu["value"], "cpu": cpu_model()}
 
+    cgcmp = None
+    if args.compare_cg and not weighted:
+        def summary(hh, hs_):
+            r = hs_[:, :, 0] / hs_[:, :1, 0]
+            hn = hh.double().cpu().numpy()
+            dn_ = np.linalg.norm(d.double().cpu().numpy().reshape(prob.nshots, -1), axis=1)
+            return {"rel_residual_every_5": [round(float(v), 4) for v in np.median(r, axis=0)[::5]],
+                    "rel_residual_final": round(float(np.median(r[:, -1])), 4),
+                    "misfit_final": round(float(np.median(hs_[:, -1, 3] / dn_)), 4),
+                    "source_error": round(float(np.median(
+                        [np.linalg.norm(hn[s] - htrue[s]) / np.linalg.norm(htrue[s])
+                         for s in range(prob.nshots)])), 4)}
+        pcg_sum = summary(h, hist)
+        hc, histc, _, _ = ctx.pcg_solve(d, wl.alpha_rel, wl.K, use_precond=False,
+                                         raise_on_breakdown=False)
+        cgcmp = {"pcg": pcg_sum, "cg": summary(hc, histc),
+                 "note": "medians over shots; residual = ||r_k|| / ||r_0|| of the Euclidean "
+                         "normal equations, misfit = ||F h_K - d|| / ||d||, source error "
+                         "against the point source that made d"}
+
     ref = None
     if args.ref_f64:
         rctx = ssx.Context(prob, wl.kappa, wl.rho, field_dtype="f64")
@@ -375,6 +398,8 @@ def main():
     }
     if ref is not None:
         out["error_vs_f64_solve"] = ref
+    if cgcmp is not None:
+        out["cg_comparison"] = cgcmp
     print(json.dumps(out), flush=True)
     ctx.close()
 
@@ -390,7 +415,8 @@ def crosswell_bench(args):
     M^-1 = D W^-1 D.  For each alpha in {0, --alpha} the line reports the
     relative normal-residual curves (CG: ||r_k||; PCG: ||M^-1 r_k||, the
     left side of the norm1 form), the iterations each needs to reduce it by
-    10x, 100x and 1000x, and the data misfit.  It also reports the paper's
+    10x, 100x and 1000x, and the data misfit, and beside them the thin-slab
+    preconditioner on the Euclidean normal equations.  It also reports the paper's
     operator checks as relative misfits: the pressure source -2 P_s v_z and
     the normal load -2 P_s p reproducing the point source's data, Lambda~
     with the 5-cell datum against the whole path to the receiver surface,
@@ -439,6 +465,7 @@ def crosswell_bench(args):
     for alpha in sorted({0.0, args.alpha}):
         _, hc, _, stc = ctx.pcg_solve(d, alpha, K, use_precond=False, raise_on_breakdown=False)
         _, hp, _, stp = ctx.pcg_solve_w(d, alpha, K, raise_on_breakdown=False)
+        _, he, _, ste = ctx.pcg_solve(d, alpha, K, raise_on_breakdown=False)
         cg = hc[0, :, 0] / hc[0, 0, 0]
         pcg = hp[0, :, 1] / hp[0, 0, 1]
         entry = {"cg_status": int(stc), "pcg_status": int(stp),
@@ -446,7 +473,13 @@ def crosswell_bench(args):
                  "cg_curve": [round(float(v), 6) for v in cg],
                  "pcg_curve": [round(float(v), 6) for v in pcg],
                  "cg_misfit": round(float(hc[0, -1, 3] / dn), 5),
-                 "pcg_misfit": round(float(hp[0, -1, 3] / dn), 5)}
+                 "pcg_misfit": round(float(hp[0, -1, 3] / dn), 5),
+                 # the thin-slab preconditioner on the Euclidean normal
+                 # equations (ssx_pcg_solve): both of its residual norms
+                 "euclid_pcg": {"status": int(ste),
+                                "r_curve": [round(float(v), 6) for v in he[0, :, 0] / he[0, 0, 0]],
+                                "g_curve": [round(float(v), 6) for v in he[0, :, 1] / he[0, 0, 1]],
+                                "misfit": round(float(he[0, -1, 3] / dn), 5)}}
         for tag, lev in (("10x", 1e-1), ("100x", 1e-2), ("1000x", 1e-3)):
             a, b = reached(cg, lev), reached(pcg, lev)
             entry[f"iters_to_{tag}"] = {"cg": a, "pcg": b,
