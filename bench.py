@@ -625,7 +625,9 @@ def gradient_bench(args, wl, ctx, d, fd):
                    "nz": prob.nz, "nx": prob.nx, "nt": prob.nt, "shots": prob.nshots,
                    "field_dtype": fd},
         "gcell_updates_per_s": round(cu * args.steps / el / 1e9, 2),
-        "history_bytes": prob.nt * prob.nz * prob.nx * prob.nshots * fsz,
+        # rows held in the grid's aligned groups of four columns
+        "history_bytes": prob.nt * prob.nz * prob.nshots * fsz
+        * 4 * ((prob.npml + prob.nx - 1) // 4 - prob.npml // 4 + 1),
         "extra_bytes_per_gradient": extra,
         "misfit": [float(v) for v in J],
     }

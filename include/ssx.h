@@ -290,8 +290,9 @@ ssx_status ssx_block(ssx_ctx* ctx, int32_t src, int32_t rec, int32_t transpose, 
  * held fixed.  J_host: HOST [nshots] or NULL (then the call does not
  * synchronise).  h: [nshots][nt][ns]; d: [nshots][nt][nr].  F64 and F32
  * fields only (SSX_ERR_ARG otherwise).  The first call allocates the step
- * history, nt * nshots * nz * nx field values plus an FP64 accumulator,
- * held until ssx_destroy (also for contexts made with a workspace);
+ * history, nt * nshots * nz * nx' field values plus an FP64 accumulator
+ * of nshots * nz * nx' (nx' = nx rounded out to the grid's aligned groups
+ * of four columns, at most nx + 6), held until ssx_destroy (also for contexts made with a workspace);
  * SSX_ERR_OOM if that fails.  Two full simulations, one step per launch
  * (replayed as one captured graph when graphs are on). */
 ssx_status ssx_misfit_gradient(ssx_ctx* ctx, const void* h, const void* d, void* g,

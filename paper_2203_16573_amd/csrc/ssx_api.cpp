@@ -997,7 +997,7 @@ ssx_status do_normal_w(ssx_ctx* c, const double* alpha2_dev, double alpha2_host,
 // the device.)
 ssx_status issue_gradient(ssx_ctx* c, const void* h, const void* d, void* g, hipStream_t s) {
   const ssx_problem& p = c->prob;
-  const long long cells = (long long)p.nz * p.nx;
+  const long long cells = grad_cells(p.npml, p.nz, p.nx);
   const long long ns_ = nvec_s(p), nr_ = nvec_r(p);
   auto hist_at = [&](int n, int s0) {
     return (char*)c->ghist + ((size_t)n * p.nshots + s0) * cells * c->fsz;
@@ -1031,7 +1031,7 @@ ssx_status issue_gradient(ssx_ctx* c, const void* h, const void* d, void* g, hip
 // replayed as one captured graph when graphs are on.
 ssx_status do_gradient(ssx_ctx* c, const void* h, const void* d, void* g, double* J_host) {
   const ssx_problem& p = c->prob;
-  const long long cells = (long long)p.nz * p.nx;
+  const long long cells = grad_cells(p.npml, p.nz, p.nx);
   if (!c->ghist) {
     if (hipMalloc(&c->ghist, (size_t)p.nt * p.nshots * cells * c->fsz) != hipSuccess ||
         hipMalloc((void**)&c->gacc, (size_t)p.nshots * cells * sizeof(double)) != hipSuccess) {

@@ -13,59 +13,93 @@ namespace ssx {
 
 namespace {
 
-// one thread per physical cell of one shot: r^n = src - (dx + dz) with the
-// staggered stencils and the source injection evaluated as in the step
-// kernels (same weights, same accumulation order)
+// History and accumulator rows hold the physical columns of a row in the
+// grid's aligned groups of four: group gi covers columns 4 (g0 + gi) ..
+// 4 (g0 + gi) + 3 with g0 = L / 4, so that the stencil loads, the history
+// and the accumulator are 16-byte (FP64: 32-byte) vectors.  Entries of
+// columns outside the physical grid hold zero.
+struct GroupRows {
+  int g0, ng;  // first group, groups per row
+  __host__ __device__ GroupRows(int L, int nx) : g0(L / 4), ng((L + nx - 1) / 4 - L / 4 + 1) {}
+  __host__ __device__ int width() const { return 4 * ng; }
+};
+
+// one thread per group of four columns of one physical row and shot:
+// r^n = src - (dx + dz) with the staggered stencils and the source
+// injection evaluated as in the step kernels (same weights, same
+// accumulation order)
 template <int K, typename T>
-__global__ void k_grad_store(Fields f, GridDims g, int nz, int nx, LineDev pil, TraceIO pi,
-                             T* __restrict__ hist, long long shot_cells) {
+__global__ __launch_bounds__(256) void k_grad_store(Fields f, GridDims g, int nz, int nx,
+                                                    LineDev pil, TraceIO pi, T* __restrict__ hist) {
   using C = typename Tr<T>::C;
-  const int shot = blockIdx.y;
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (long long)nz * nx) return;
-  const int iz = int(i / nx), ix = int(i - (long long)iz * nx);
-  const int I = g.L + iz, J = g.L + ix;
+  const GroupRows gr(g.L, nx);
+  const int gi = blockIdx.x * 64 + threadIdx.x, iz = blockIdx.y * 4 + threadIdx.y;
+  const int shot = blockIdx.z;
+  if (gi >= gr.ng || iz >= nz) return;
+  const int I = g.L + iz, J = 4 * (gr.g0 + gi);
   const long long base = shot * g.field_stride + g.origin + (long long)I * g.pitch + J;
   const T* vx = static_cast<const T*>(f.vx) + base;
   const T* vz = static_cast<const T*>(f.vz) + base;
-  C dx = C(0), dz = C(0);
+  C w[12];  // v_x at columns J-4 .. J+7
+  ld4(*reinterpret_cast<C(*)[4]>(w), vx - 4);
+  ld4(*reinterpret_cast<C(*)[4]>(w + 4), vx);
+  ld4(*reinterpret_cast<C(*)[4]>(w + 8), vx + 4);
+  C dx[4] = {C(0), C(0), C(0), C(0)}, dz[4] = {C(0), C(0), C(0), C(0)};
 #pragma unroll
   for (int m = 1; m <= K; ++m) {
-    dx = acc(dx, wst<K, C>(m - 1), ldc<C>(vx + (m - 1)), ldc<C>(vx - m));
-    dz = acc(dz, wst<K, C>(m - 1), ldc<C>(vz + (long long)(m - 1) * g.pitch),
-             ldc<C>(vz - (long long)m * g.pitch));
+    C hi[4], lo[4];
+    ld4(hi, vz + (long long)(m - 1) * g.pitch);
+    ld4(lo, vz - (long long)m * g.pitch);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      dx[e] = acc(dx[e], wst<K, C>(m - 1), w[e + m + 3], w[e + 4 - m]);
+      dz[e] = acc(dz[e], wst<K, C>(m - 1), hi[e], lo[e]);
+    }
   }
-  const C src = line_src<C, typename Tr<T>::V>(pil, pi, I, J, shot);
-  hist[shot * shot_cells + i] = T(src - (dx + dz));
+  C r[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int Je = J + e;
+    const bool phys = Je >= g.L && Je < g.L + nx;
+    const C src = line_src<C, typename Tr<T>::V>(pil, pi, I, Je, shot);
+    r[e] = phys ? src - (dx[e] + dz[e]) : C(0);
+  }
+  st4(hist + ((long long)shot * nz + iz) * gr.width() + 4 * gi, r);
 }
 
-// acc += P~ r^n for every physical cell (FP64 accumulator)
+// acc += P~ r^n over the groups of the physical rows (FP64 accumulator)
 template <typename T>
-__global__ void k_grad_acc(Fields f, GridDims g, int nz, int nx, const T* __restrict__ hist,
-                           long long shot_cells, double* __restrict__ acc) {
-  const int shot = blockIdx.y;
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (long long)nz * nx) return;
-  const int iz = int(i / nx), ix = int(i - (long long)iz * nx);
-  const long long o = shot * g.field_stride + g.origin + (long long)(g.L + iz) * g.pitch + g.L + ix;
-  const double p = double(static_cast<const T*>(f.p)[o]);
-  const double r = double(hist[shot * shot_cells + i]);
-  double* a = acc + shot * shot_cells + i;
-  *a = fma(p, r, *a);
+__global__ __launch_bounds__(256) void k_grad_acc(Fields f, GridDims g, int nz, int nx,
+                                                  const T* __restrict__ hist,
+                                                  double* __restrict__ accum) {
+  const GroupRows gr(g.L, nx);
+  const int gi = blockIdx.x * 64 + threadIdx.x, iz = blockIdx.y * 4 + threadIdx.y;
+  const int shot = blockIdx.z;
+  if (gi >= gr.ng || iz >= nz) return;
+  const int J = 4 * (gr.g0 + gi);
+  const long long o = shot * g.field_stride + g.origin + (long long)(g.L + iz) * g.pitch + J;
+  const long long h = ((long long)shot * nz + iz) * gr.width() + 4 * gi;
+  double p[4], r[4], a[4];
+  ld4(p, static_cast<const T*>(f.p) + o);
+  ld4(r, hist + h);
+  ld4(a, accum + h);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) a[e] = fma(p[e], r[e], a[e]);
+  st4(accum + h, a);
 }
 
 // out = acc * s / ck for every physical cell (ck = dt kappa / (h Z0), so
-// with s = dt / (h Z0) this is acc / kappa)
+// with s = dt / (h Z0) this is acc / kappa); out is [shot][nz][nx]
 template <typename T, typename V>
-__global__ void k_grad_final(const double* __restrict__ acc, const T* __restrict__ ck,
-                             GridDims g, int nz, int nx, double s, long long shot_cells,
-                             V* __restrict__ out) {
-  const int shot = blockIdx.y;
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (long long)nz * nx) return;
-  const int iz = int(i / nx), ix = int(i - (long long)iz * nx);
-  const long long o = g.origin + (long long)(g.L + iz) * g.pitch + g.L + ix;
-  out[shot * shot_cells + i] = V(acc[shot * shot_cells + i] * s / double(ck[o]));
+__global__ void k_grad_final(const double* __restrict__ accum, const T* __restrict__ ck,
+                             GridDims g, int nz, int nx, double s, V* __restrict__ out) {
+  const GroupRows gr(g.L, nx);
+  const int ix = blockIdx.x * blockDim.x + threadIdx.x, iz = blockIdx.y, shot = blockIdx.z;
+  if (ix >= nx) return;
+  const int J = g.L + ix;
+  const long long o = g.origin + (long long)(g.L + iz) * g.pitch + J;
+  const double a = accum[((long long)shot * nz + iz) * gr.width() + (J - 4 * gr.g0)];
+  out[((long long)shot * nz + iz) * nx + ix] = V(a * s / double(ck[o]));
 }
 
 // e = a - b over n elements per shot
@@ -77,31 +111,38 @@ __global__ void k_sub(const V* __restrict__ a, const V* __restrict__ b, V* __res
   if (i < n) e[o] = a[o] - b[o];
 }
 
-dim3 cells_grid(int nz, int nx, int nshots) {
-  return dim3((unsigned)(((long long)nz * nx + 255) / 256), nshots);
+bool dims_ok(int nz, int nx, int nshots) {
+  return nz > 0 && nx > 0 && nshots > 0 && nz <= 4 * 65535 && nshots <= 65535;
+}
+// groups: 64 groups x 4 rows per workgroup
+dim3 group_grid(const GridDims& g, int nz, int nx, int nshots) {
+  const GroupRows gr(g.L, nx);
+  return dim3((unsigned)((gr.ng + 63) / 64), (unsigned)((nz + 3) / 4), (unsigned)nshots);
 }
 
 }  // namespace
 
+long long grad_cells(int L, int nz, int nx) { return (long long)nz * GroupRows(L, nx).width(); }
+
 hipError_t launch_grad_store(Dt dt, int order, const Fields& f, const GridDims& g, int nz, int nx,
                              const LineDev& pil, const TraceIO& pi, void* hist, int nshots,
                              hipStream_t s) {
-  const long long sc = (long long)nz * nx;
-  const dim3 grid = cells_grid(nz, nx, nshots);
+  if (!dims_ok(nz, nx, nshots)) return hipErrorInvalidValue;
+  const dim3 grid = group_grid(g, nz, nx, nshots), block(64, 4);
   if (dt == Dt::F64) {
     if (order == 8)
-      hipLaunchKernelGGL((k_grad_store<4, double>), grid, dim3(256), 0, s, f, g, nz, nx, pil, pi,
-                         static_cast<double*>(hist), sc);
+      hipLaunchKernelGGL((k_grad_store<4, double>), grid, block, 0, s, f, g, nz, nx, pil, pi,
+                         static_cast<double*>(hist));
     else
-      hipLaunchKernelGGL((k_grad_store<2, double>), grid, dim3(256), 0, s, f, g, nz, nx, pil, pi,
-                         static_cast<double*>(hist), sc);
+      hipLaunchKernelGGL((k_grad_store<2, double>), grid, block, 0, s, f, g, nz, nx, pil, pi,
+                         static_cast<double*>(hist));
   } else if (dt == Dt::F32) {
     if (order == 8)
-      hipLaunchKernelGGL((k_grad_store<4, float>), grid, dim3(256), 0, s, f, g, nz, nx, pil, pi,
-                         static_cast<float*>(hist), sc);
+      hipLaunchKernelGGL((k_grad_store<4, float>), grid, block, 0, s, f, g, nz, nx, pil, pi,
+                         static_cast<float*>(hist));
     else
-      hipLaunchKernelGGL((k_grad_store<2, float>), grid, dim3(256), 0, s, f, g, nz, nx, pil, pi,
-                         static_cast<float*>(hist), sc);
+      hipLaunchKernelGGL((k_grad_store<2, float>), grid, block, 0, s, f, g, nz, nx, pil, pi,
+                         static_cast<float*>(hist));
   } else {
     return hipErrorInvalidValue;
   }
@@ -110,14 +151,14 @@ hipError_t launch_grad_store(Dt dt, int order, const Fields& f, const GridDims& 
 
 hipError_t launch_grad_acc(Dt dt, const Fields& f, const GridDims& g, int nz, int nx,
                            const void* hist, double* acc, int nshots, hipStream_t s) {
-  const long long sc = (long long)nz * nx;
-  const dim3 grid = cells_grid(nz, nx, nshots);
+  if (!dims_ok(nz, nx, nshots)) return hipErrorInvalidValue;
+  const dim3 grid = group_grid(g, nz, nx, nshots), block(64, 4);
   if (dt == Dt::F64)
-    hipLaunchKernelGGL(k_grad_acc<double>, grid, dim3(256), 0, s, f, g, nz, nx,
-                       static_cast<const double*>(hist), sc, acc);
+    hipLaunchKernelGGL(k_grad_acc<double>, grid, block, 0, s, f, g, nz, nx,
+                       static_cast<const double*>(hist), acc);
   else if (dt == Dt::F32)
-    hipLaunchKernelGGL(k_grad_acc<float>, grid, dim3(256), 0, s, f, g, nz, nx,
-                       static_cast<const float*>(hist), sc, acc);
+    hipLaunchKernelGGL(k_grad_acc<float>, grid, block, 0, s, f, g, nz, nx,
+                       static_cast<const float*>(hist), acc);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -125,15 +166,15 @@ hipError_t launch_grad_acc(Dt dt, const Fields& f, const GridDims& g, int nz, in
 
 hipError_t launch_grad_final(Dt dt, const double* acc, const void* ck, const GridDims& g, int nz,
                              int nx, double scale, void* out, int nshots, hipStream_t s) {
-  const long long sc = (long long)nz * nx;
-  const dim3 grid = cells_grid(nz, nx, nshots);
+  if (!dims_ok(nz, nx, nshots) || nz > 65535) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((nx + 255) / 256), (unsigned)nz, (unsigned)nshots);
   if (dt == Dt::F64)
     hipLaunchKernelGGL((k_grad_final<double, double>), grid, dim3(256), 0, s, acc,
-                       static_cast<const double*>(ck), g, nz, nx, scale, sc,
+                       static_cast<const double*>(ck), g, nz, nx, scale,
                        static_cast<double*>(out));
   else if (dt == Dt::F32)
     hipLaunchKernelGGL((k_grad_final<float, float>), grid, dim3(256), 0, s, acc,
-                       static_cast<const float*>(ck), g, nz, nx, scale, sc,
+                       static_cast<const float*>(ck), g, nz, nx, scale,
                        static_cast<float*>(out));
   else
     return hipErrorInvalidValue;

@@ -187,17 +187,20 @@ hipError_t launch_pcg_dir(bool vdbl, void* p, const void* g, long long n,
 hipError_t launch_pcg_init(double* sc, double alpha, bool absolute, int nshots, hipStream_t s);
 hipError_t launch_neg_copy(bool vdbl, void* y, const void* x, long long n, hipStream_t s);
 
-// Misfit gradient in kappa (ssx_grad.hip; F64 and F32 fields).  Cells are
-// the physical nz x nx grid of each shot, row-major.
-// hist[shot][cell] = E_h h^n - D^- v^{n+1/2} from the fields f after step n
+// Misfit gradient in kappa (ssx_grad.hip; F64 and F32 fields).  hist and
+// acc hold, per shot, the nz physical rows, each in the grid's aligned
+// groups of four columns that cover the physical ones: grad_cells(L, nz,
+// nx) entries per shot (entries of non-physical columns are zero).
+long long grad_cells(int L, int nz, int nx);
+// hist[shot] = E_h h^n - D^- v^{n+1/2} from the fields f after step n
 // (pi: the pressure-source injection of step n)
 hipError_t launch_grad_store(Dt dt, int order, const Fields& f, const GridDims& g, int nz, int nx,
                              const LineDev& pil, const TraceIO& pi, void* hist, int nshots,
                              hipStream_t s);
-// acc[shot][cell] += P~ hist[shot][cell], P~ the transposed pressure in f
+// acc[shot] += P~ hist[shot], P~ the transposed pressure in f
 hipError_t launch_grad_acc(Dt dt, const Fields& f, const GridDims& g, int nz, int nx,
                            const void* hist, double* acc, int nshots, hipStream_t s);
-// out[shot][cell] = acc * scale / ck(cell)   (out of the vector type)
+// out[shot][iz][ix] = acc * scale / ck   (out of the vector type)
 hipError_t launch_grad_final(Dt dt, const double* acc, const void* ck, const GridDims& g, int nz,
                              int nx, double scale, void* out, int nshots, hipStream_t s);
 // e = a - b, n elements per shot
