@@ -484,10 +484,15 @@ int default_tile_z(const ssx_ctx* c, const GridDev& gd) {
 // A per-step callback of a propagation: called with the step index and the
 // fields of the current group (forward: after step n, holding p^{n+1} and
 // v^{n+1/2}; transposed: before step n, holding the transposed state of
-// level n+1).  Steps then run one per launch.
-using StepHook = std::function<ssx_status(int n, const Fields& f)>;
+// level n+1).  `older` is the other field buffer of the fused kernels,
+// which still holds what the step before read (forward: the state before
+// step n, p^n and v^{n-1/2}, for n >= 1; transposed: level n+2, before
+// every step but the first), else null (the split kernels update in
+// place).  Steps then run one per launch.
+using StepHook = std::function<ssx_status(int n, const Fields& f, const Fields* older)>;
 // the same with the first shot and the shot count of the group
-using GroupHook = std::function<ssx_status(int n, const Fields& f, int s0, int gs)>;
+using GroupHook =
+    std::function<ssx_status(int n, const Fields& f, const Fields* older, int s0, int gs)>;
 
 // One propagation of ns shots (a group of the context's shots) whose
 // fields start at f0 (step n) and f1 (the second buffer).
@@ -507,7 +512,7 @@ ssx_status issue_group(ssx_ctx* c, GridDev& gd, bool adj, const Fields& f0, cons
         pi.n = pi.in ? n : -1;
         SSX_HIP(launch_pres(c->fdt, order, false, f0, gd.dims, gd.coef, psl, ps, pil, pi,
                             ns, s));
-        if (hook) SSX_TRY((*hook)(n, f0));
+        if (hook) SSX_TRY((*hook)(n, f0, nullptr));
       }
       if (vs.out) {
         vs.n = nt - 1;
@@ -519,7 +524,7 @@ ssx_status issue_group(ssx_ctx* c, GridDev& gd, bool adj, const Fields& f0, cons
       SSX_HIP(launch_pres(c->fdt, order, true, f0, gd.dims, gd.coef, psl, none, pil, pi,
                           ns, s));
       for (int n = nt - 1; n >= 0; --n) {
-        if (hook) SSX_TRY((*hook)(n, f0));
+        if (hook) SSX_TRY((*hook)(n, f0, nullptr));
         vs.n = vs.out ? n : -1;
         vi.n = vi.in ? n : -1;
         SSX_HIP(launch_vel(c->fdt, order, true, f0, gd.dims, gd.coef, vsl, vs, vil, vi,
@@ -604,7 +609,7 @@ ssx_status issue_group(ssx_ctx* c, GridDev& gd, bool adj, const Fields& f0, cons
     if (hook) {
       for (; n < nt; ++n) {
         SSX_TRY(launch(1, n - 1, n, n, n));
-        SSX_TRY((*hook)(n, buf[cur]));
+        SSX_TRY((*hook)(n, buf[cur], n >= 1 ? &buf[1 - cur] : nullptr));
       }
     }
     for (; n + spl <= nt; n += spl) SSX_TRY(launch(spl, n - 1, n, n, n));
@@ -621,7 +626,7 @@ ssx_status issue_group(ssx_ctx* c, GridDev& gd, bool adj, const Fields& f0, cons
     int n = nt - 1;
     if (hook) {
       for (; n >= 0; --n) {
-        SSX_TRY((*hook)(n, buf[cur]));
+        SSX_TRY((*hook)(n, buf[cur], n < nt - 1 ? &buf[1 - cur] : nullptr));
         SSX_TRY(launch(1, n, n, n, n - 1));
       }
     }
@@ -693,7 +698,10 @@ ssx_status issue_propagation(ssx_ctx* c, GridDev& gd, bool adj, const LineDev& v
     const int gs = std::min(G, ns - s0);
     const long long off = (long long)s0 * gd.dims.field_stride;
     StepHook step_hook;
-    if (hook) step_hook = [&](int n, const Fields& f) { return (*hook)(n, f, s0, gs); };
+    if (hook)
+      step_hook = [&](int n, const Fields& f, const Fields* older) {
+        return (*hook)(n, f, older, s0, gs);
+      };
     SSX_TRY(issue_group(c, gd, adj, shift_fields(gd.fields, off, c->fsz),
                         shift_fields(gd.fields1, off, c->fsz), gs, vsl,
                         shift_io(vs, s0, c->vsz), vil, shift_io(vi, s0, c->vsz), psl,
@@ -1002,11 +1010,24 @@ ssx_status issue_gradient(ssx_ctx* c, const void* h, const void* d, void* g, hip
   auto hist_at = [&](int n, int s0) {
     return (char*)c->ghist + ((size_t)n * p.nshots + s0) * cells * c->fsz;
   };
-  const GroupHook store = [&](int n, const Fields& f, int s0, int gs) -> ssx_status {
+  // with the fused kernels' second buffer, steps are stored in pairs (n - 1,
+  // n) after step n, from the buffer still holding the state before step n
+  // and the current one; otherwise one step at a time
+  const GroupHook store = [&](int n, const Fields& f, const Fields* older, int s0,
+                              int gs) -> ssx_status {
     TraceIO pi = shift_io(io_in(h, ns_, 1.0), s0, c->vsz);
     pi.n = n;
-    SSX_HIP(launch_grad_store(c->fdt, p.order, f, c->full.dims, p.nz, p.nx, c->h_line, pi,
-                              hist_at(n, s0), gs, s));
+    if (c->fused && n % 2 == 0 && n < p.nt - 1) return SSX_OK;  // paired with step n + 1
+    if (c->fused && n % 2 == 1) {
+      if (!older) return fail(SSX_ERR_ARG, "gradient: no second field buffer");
+      TraceIO pa = pi;
+      pa.n = n - 1;
+      SSX_HIP(launch_grad_store2(c->fdt, p.order, *older, f, c->full.dims, p.nz, p.nx, c->h_line,
+                                 pa, pi, hist_at(n - 1, s0), hist_at(n, s0), gs, s));
+    } else {
+      SSX_HIP(launch_grad_store(c->fdt, p.order, f, c->full.dims, p.nz, p.nx, c->h_line, pi,
+                                hist_at(n, s0), gs, s));
+    }
     return SSX_OK;
   };
   SSX_TRY(issue_propagation(c, c->full, false, c->r_line, io_out(c->Fp, nr_, c->Z0), c->r_line,
@@ -1015,9 +1036,26 @@ ssx_status issue_gradient(ssx_ctx* c, const void* h, const void* d, void* g, hip
   SSX_HIP(launch_sub(c->vdbl, c->Fp, d, c->e, nr_, p.nshots, s));
   SSX_HIP(launch_dot1(c->vdbl, c->e, c->e, nr_, p.nshots, c->partial, c->sc + SC_TMP, SC_N, s));
   SSX_HIP(launch_zero(c->gacc, (size_t)p.nshots * cells * sizeof(double), s));
-  const GroupHook accum = [&](int n, const Fields& f, int s0, int gs) -> ssx_status {
-    SSX_HIP(launch_grad_acc(c->fdt, f, c->full.dims, p.nz, p.nx, hist_at(n, s0),
-                            c->gacc + (size_t)s0 * cells, gs, s));
+  // with the fused kernels' second buffer, steps are accumulated in pairs
+  // (n + 1, n) before step n, from the buffer still holding level n + 2 and
+  // the current one (the same FP64 sums in the same order, half the
+  // accumulator traffic); otherwise one step at a time
+  const GroupHook accum = [&](int n, const Fields& f, const Fields* older, int s0,
+                              int gs) -> ssx_status {
+    double* acc = c->gacc + (size_t)s0 * cells;
+    if (!c->fused) {
+      SSX_HIP(launch_grad_acc(c->fdt, f, c->full.dims, p.nz, p.nx, hist_at(n, s0), acc, gs, s));
+      return SSX_OK;
+    }
+    const int k = p.nt - 1 - n;  // steps taken so far
+    if (k % 2 == 0 && n > 0) return SSX_OK;  // paired with step n - 1
+    if (k % 2 == 1) {
+      if (!older) return fail(SSX_ERR_ARG, "gradient: no second field buffer");
+      SSX_HIP(launch_grad_acc2(c->fdt, *older, f, c->full.dims, p.nz, p.nx, hist_at(n + 1, s0),
+                               hist_at(n, s0), acc, gs, s));
+    } else {
+      SSX_HIP(launch_grad_acc(c->fdt, f, c->full.dims, p.nz, p.nx, hist_at(n, s0), acc, gs, s));
+    }
     return SSX_OK;
   };
   SSX_TRY(issue_propagation(c, c->full, true, c->h_line, io_none(), c->h_line, io_none(),

@@ -24,18 +24,15 @@ struct GroupRows {
   __host__ __device__ int width() const { return 4 * ng; }
 };
 
-// one thread per group of four columns of one physical row and shot:
-// r^n = src - (dx + dz) with the staggered stencils and the source
-// injection evaluated as in the step kernels (same weights, same
-// accumulation order)
+// r^n = src - (dx + dz) on one group of four columns of one physical row
+// and shot, with the staggered stencils and the source injection evaluated
+// as in the step kernels (same weights, same accumulation order)
 template <int K, typename T>
-__global__ __launch_bounds__(256) void k_grad_store(Fields f, GridDims g, int nz, int nx,
-                                                    LineDev pil, TraceIO pi, T* __restrict__ hist) {
+__device__ __forceinline__ void store_group(const Fields& f, const GridDims& g, int nz, int nx,
+                                            const LineDev& pil, const TraceIO& pi, int gi, int iz,
+                                            int shot, T* __restrict__ hist) {
   using C = typename Tr<T>::C;
   const GroupRows gr(g.L, nx);
-  const int gi = blockIdx.x * 64 + threadIdx.x, iz = blockIdx.y * 4 + threadIdx.y;
-  const int shot = blockIdx.z;
-  if (gi >= gr.ng || iz >= nz) return;
   const int I = g.L + iz, J = 4 * (gr.g0 + gi);
   const long long base = shot * g.field_stride + g.origin + (long long)I * g.pitch + J;
   const T* vx = static_cast<const T*>(f.vx) + base;
@@ -67,6 +64,27 @@ __global__ __launch_bounds__(256) void k_grad_store(Fields f, GridDims g, int nz
   st4(hist + ((long long)shot * nz + iz) * gr.width() + 4 * gi, r);
 }
 
+// one thread per group of four columns of one physical row and shot
+template <int K, typename T>
+__global__ __launch_bounds__(256) void k_grad_store(Fields f, GridDims g, int nz, int nx,
+                                                    LineDev pil, TraceIO pi, T* __restrict__ hist) {
+  const int gi = blockIdx.x * 64 + threadIdx.x, iz = blockIdx.y * 4 + threadIdx.y;
+  if (gi >= GroupRows(g.L, nx).ng || iz >= nz) return;
+  store_group<K, T>(f, g, nz, nx, pil, pi, gi, iz, blockIdx.z, hist);
+}
+
+// two steps at once: r of the fields fa (injection pa) into ha and of fb
+// (injection pb) into hb
+template <int K, typename T>
+__global__ __launch_bounds__(256) void k_grad_store2(Fields fa, Fields fb, GridDims g, int nz,
+                                                     int nx, LineDev pil, TraceIO pa, TraceIO pb,
+                                                     T* __restrict__ ha, T* __restrict__ hb) {
+  const int gi = blockIdx.x * 64 + threadIdx.x, iz = blockIdx.y * 4 + threadIdx.y;
+  if (gi >= GroupRows(g.L, nx).ng || iz >= nz) return;
+  store_group<K, T>(fa, g, nz, nx, pil, pa, gi, iz, blockIdx.z, ha);
+  store_group<K, T>(fb, g, nz, nx, pil, pb, gi, iz, blockIdx.z, hb);
+}
+
 // acc += P~ r^n over the groups of the physical rows (FP64 accumulator)
 template <typename T>
 __global__ __launch_bounds__(256) void k_grad_acc(Fields f, GridDims g, int nz, int nx,
@@ -85,6 +103,31 @@ __global__ __launch_bounds__(256) void k_grad_acc(Fields f, GridDims g, int nz, 
   ld4(a, accum + h);
 #pragma unroll
   for (int e = 0; e < 4; ++e) a[e] = fma(p[e], r[e], a[e]);
+  st4(accum + h, a);
+}
+
+// two steps at once: acc += P~_a r_a, then acc += P~_b r_b (the order of two
+// k_grad_acc launches, a first)
+template <typename T>
+__global__ __launch_bounds__(256) void k_grad_acc2(Fields fa, Fields fb, GridDims g, int nz,
+                                                   int nx, const T* __restrict__ ha,
+                                                   const T* __restrict__ hb,
+                                                   double* __restrict__ accum) {
+  const GroupRows gr(g.L, nx);
+  const int gi = blockIdx.x * 64 + threadIdx.x, iz = blockIdx.y * 4 + threadIdx.y;
+  const int shot = blockIdx.z;
+  if (gi >= gr.ng || iz >= nz) return;
+  const int J = 4 * (gr.g0 + gi);
+  const long long o = shot * g.field_stride + g.origin + (long long)(g.L + iz) * g.pitch + J;
+  const long long h = ((long long)shot * nz + iz) * gr.width() + 4 * gi;
+  double pa[4], ra[4], pb[4], rb[4], a[4];
+  ld4(pa, static_cast<const T*>(fa.p) + o);
+  ld4(ra, ha + h);
+  ld4(pb, static_cast<const T*>(fb.p) + o);
+  ld4(rb, hb + h);
+  ld4(a, accum + h);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) a[e] = fma(pb[e], rb[e], fma(pa[e], ra[e], a[e]));
   st4(accum + h, a);
 }
 
@@ -149,6 +192,32 @@ hipError_t launch_grad_store(Dt dt, int order, const Fields& f, const GridDims& 
   return hipGetLastError();
 }
 
+hipError_t launch_grad_store2(Dt dt, int order, const Fields& fa, const Fields& fb,
+                              const GridDims& g, int nz, int nx, const LineDev& pil,
+                              const TraceIO& pa, const TraceIO& pb, void* ha, void* hb, int nshots,
+                              hipStream_t s) {
+  if (!dims_ok(nz, nx, nshots)) return hipErrorInvalidValue;
+  const dim3 grid = group_grid(g, nz, nx, nshots), block(64, 4);
+  if (dt == Dt::F64) {
+    if (order == 8)
+      hipLaunchKernelGGL((k_grad_store2<4, double>), grid, block, 0, s, fa, fb, g, nz, nx, pil, pa,
+                         pb, static_cast<double*>(ha), static_cast<double*>(hb));
+    else
+      hipLaunchKernelGGL((k_grad_store2<2, double>), grid, block, 0, s, fa, fb, g, nz, nx, pil, pa,
+                         pb, static_cast<double*>(ha), static_cast<double*>(hb));
+  } else if (dt == Dt::F32) {
+    if (order == 8)
+      hipLaunchKernelGGL((k_grad_store2<4, float>), grid, block, 0, s, fa, fb, g, nz, nx, pil, pa,
+                         pb, static_cast<float*>(ha), static_cast<float*>(hb));
+    else
+      hipLaunchKernelGGL((k_grad_store2<2, float>), grid, block, 0, s, fa, fb, g, nz, nx, pil, pa,
+                         pb, static_cast<float*>(ha), static_cast<float*>(hb));
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_grad_acc(Dt dt, const Fields& f, const GridDims& g, int nz, int nx,
                            const void* hist, double* acc, int nshots, hipStream_t s) {
   if (!dims_ok(nz, nx, nshots)) return hipErrorInvalidValue;
@@ -159,6 +228,22 @@ hipError_t launch_grad_acc(Dt dt, const Fields& f, const GridDims& g, int nz, in
   else if (dt == Dt::F32)
     hipLaunchKernelGGL(k_grad_acc<float>, grid, block, 0, s, f, g, nz, nx,
                        static_cast<const float*>(hist), acc);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_acc2(Dt dt, const Fields& fa, const Fields& fb, const GridDims& g, int nz,
+                            int nx, const void* ha, const void* hb, double* acc, int nshots,
+                            hipStream_t s) {
+  if (!dims_ok(nz, nx, nshots)) return hipErrorInvalidValue;
+  const dim3 grid = group_grid(g, nz, nx, nshots), block(64, 4);
+  if (dt == Dt::F64)
+    hipLaunchKernelGGL(k_grad_acc2<double>, grid, block, 0, s, fa, fb, g, nz, nx,
+                       static_cast<const double*>(ha), static_cast<const double*>(hb), acc);
+  else if (dt == Dt::F32)
+    hipLaunchKernelGGL(k_grad_acc2<float>, grid, block, 0, s, fa, fb, g, nz, nx,
+                       static_cast<const float*>(ha), static_cast<const float*>(hb), acc);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -197,9 +197,19 @@ long long grad_cells(int L, int nz, int nx);
 hipError_t launch_grad_store(Dt dt, int order, const Fields& f, const GridDims& g, int nz, int nx,
                              const LineDev& pil, const TraceIO& pi, void* hist, int nshots,
                              hipStream_t s);
+// two steps: ha from the fields fa (injection pa), hb from fb (pb)
+hipError_t launch_grad_store2(Dt dt, int order, const Fields& fa, const Fields& fb,
+                              const GridDims& g, int nz, int nx, const LineDev& pil,
+                              const TraceIO& pa, const TraceIO& pb, void* ha, void* hb, int nshots,
+                              hipStream_t s);
 // acc[shot] += P~ hist[shot], P~ the transposed pressure in f
 hipError_t launch_grad_acc(Dt dt, const Fields& f, const GridDims& g, int nz, int nx,
                            const void* hist, double* acc, int nshots, hipStream_t s);
+// two steps: acc[shot] += P~_a ha[shot], then += P~_b hb[shot] (P~_a, P~_b
+// the transposed pressures in fa, fb)
+hipError_t launch_grad_acc2(Dt dt, const Fields& fa, const Fields& fb, const GridDims& g, int nz,
+                            int nx, const void* ha, const void* hb, double* acc, int nshots,
+                            hipStream_t s);
 // out[shot][iz][ix] = acc * scale / ck   (out of the vector type)
 hipError_t launch_grad_final(Dt dt, const double* acc, const void* ck, const GridDims& g, int nz,
                              int nx, double scale, void* out, int nshots, hipStream_t s);
