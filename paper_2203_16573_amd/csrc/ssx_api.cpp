@@ -493,14 +493,22 @@ using StepHook = std::function<ssx_status(int n, const Fields& f, const Fields* 
 // the same with the first shot and the shot count of the group
 using GroupHook =
     std::function<ssx_status(int n, const Fields& f, const Fields* older, int s0, int gs)>;
+// Forward propagations with the fused kernels: where step n stores the
+// residual of its pressure update (the step history of the misfit
+// gradient, GradRows layout, the group's first shot first).  Steps then run
+// one per launch.
+using StepHist = std::function<void*(int n)>;
+using GroupHist = std::function<void*(int n, int s0)>;
 
 // One propagation of ns shots (a group of the context's shots) whose
 // fields start at f0 (step n) and f1 (the second buffer).
 ssx_status issue_group(ssx_ctx* c, GridDev& gd, bool adj, const Fields& f0, const Fields& f1,
                        int ns, const LineDev& vsl, TraceIO vs, const LineDev& vil, TraceIO vi,
                        const LineDev& psl, TraceIO ps, const LineDev& pil, TraceIO pi,
-                       hipStream_t s, const StepHook* hook = nullptr) {
+                       hipStream_t s, const StepHook* hook = nullptr,
+                       const StepHist* hist = nullptr) {
   const int nt = c->prob.nt, order = c->prob.order;
+  if (hist && (!c->fused || adj)) return fail(SSX_ERR_ARG, "step history needs fused forward steps");
   if (!c->fused) {
     if (!adj) {
       for (int n = 0; n < nt; ++n) {
@@ -554,6 +562,7 @@ ssx_status issue_group(ssx_ctx* c, GridDev& gd, bool adj, const Fields& f0, cons
   a.nshots = ns;
   a.nt = nt;
   a.dir = adj ? -1 : 1;
+  a.hist = nullptr;
   // one-step launches on the full grid may loop over tiles (lists built at
   // context creation for tile heights 8, 16, 32)
   const int loop = is_full ? c->loop_full : 0;
@@ -606,10 +615,12 @@ ssx_status issue_group(ssx_ctx* c, GridDev& gd, bool adj, const Fields& f0, cons
   };
   if (!adj) {
     int n = 0;
-    if (hook) {
+    if (hook || hist) {
       for (; n < nt; ++n) {
+        a.hist = hist ? (*hist)(n) : nullptr;
         SSX_TRY(launch(1, n - 1, n, n, n));
-        SSX_TRY((*hook)(n, buf[cur], n >= 1 ? &buf[1 - cur] : nullptr));
+        a.hist = nullptr;
+        if (hook) SSX_TRY((*hook)(n, buf[cur], n >= 1 ? &buf[1 - cur] : nullptr));
       }
     }
     for (; n + spl <= nt; n += spl) SSX_TRY(launch(spl, n - 1, n, n, n));
@@ -678,7 +689,7 @@ TraceIO shift_io(TraceIO t, int s0, size_t vsz) {
 ssx_status issue_propagation(ssx_ctx* c, GridDev& gd, bool adj, const LineDev& vsl, TraceIO vs,
                              const LineDev& vil, TraceIO vi, const LineDev& psl, TraceIO ps,
                              const LineDev& pil, TraceIO pi, hipStream_t s,
-                             const GroupHook* hook = nullptr) {
+                             const GroupHook* hook = nullptr, const GroupHist* hist = nullptr) {
   const int ns = c->prob.nshots;
   SSX_HIP(launch_zero(gd.field_block, gd.field_bytes, s));
   if (c->fsz == 2) {
@@ -702,11 +713,13 @@ ssx_status issue_propagation(ssx_ctx* c, GridDev& gd, bool adj, const LineDev& v
       step_hook = [&](int n, const Fields& f, const Fields* older) {
         return (*hook)(n, f, older, s0, gs);
       };
+    StepHist step_hist;
+    if (hist) step_hist = [&](int n) { return (*hist)(n, s0); };
     SSX_TRY(issue_group(c, gd, adj, shift_fields(gd.fields, off, c->fsz),
                         shift_fields(gd.fields1, off, c->fsz), gs, vsl,
                         shift_io(vs, s0, c->vsz), vil, shift_io(vi, s0, c->vsz), psl,
                         shift_io(ps, s0, c->vsz), pil, shift_io(pi, s0, c->vsz), s,
-                        hook ? &step_hook : nullptr));
+                        hook ? &step_hook : nullptr, hist ? &step_hist : nullptr));
   }
   return SSX_OK;
 }
@@ -998,11 +1011,11 @@ ssx_status do_normal_w(ssx_ctx* c, const double* alpha2_dev, double alpha2_host,
 }
 
 // The device work of one misfit gradient (see ssx_grad.hip) on stream s: a
-// forward sweep storing r^n after every step, the residual, and a
-// transposed sweep accumulating P~^{n+1} r^n before every step, both one
-// step per launch.  (Running the store and accumulation kernels on a second
-// stream beside the next step measured slower: the steps already occupy
-// the device.)
+// forward sweep storing r^n of every step (by the fused step kernel itself,
+// else by a kernel after every step), the residual, and a transposed sweep
+// accumulating P~^{n+1} r^n before the steps, both one step per launch.
+// (Running the side kernels on a second stream beside the next step
+// measured slower: the steps already occupy the device.)
 ssx_status issue_gradient(ssx_ctx* c, const void* h, const void* d, void* g, hipStream_t s) {
   const ssx_problem& p = c->prob;
   const long long cells = grad_cells(p.npml, p.nz, p.nx);
@@ -1010,29 +1023,20 @@ ssx_status issue_gradient(ssx_ctx* c, const void* h, const void* d, void* g, hip
   auto hist_at = [&](int n, int s0) {
     return (char*)c->ghist + ((size_t)n * p.nshots + s0) * cells * c->fsz;
   };
-  // with the fused kernels' second buffer, steps are stored in pairs (n - 1,
-  // n) after step n, from the buffer still holding the state before step n
-  // and the current one; otherwise one step at a time
-  const GroupHook store = [&](int n, const Fields& f, const Fields* older, int s0,
+  // the fused step kernel stores r^n itself; the split kernels leave it to
+  // a kernel of its own after every step
+  const GroupHist hist = [&](int n, int s0) -> void* { return hist_at(n, s0); };
+  const GroupHook store = [&](int n, const Fields& f, const Fields*, int s0,
                               int gs) -> ssx_status {
     TraceIO pi = shift_io(io_in(h, ns_, 1.0), s0, c->vsz);
     pi.n = n;
-    if (c->fused && n % 2 == 0 && n < p.nt - 1) return SSX_OK;  // paired with step n + 1
-    if (c->fused && n % 2 == 1) {
-      if (!older) return fail(SSX_ERR_ARG, "gradient: no second field buffer");
-      TraceIO pa = pi;
-      pa.n = n - 1;
-      SSX_HIP(launch_grad_store2(c->fdt, p.order, *older, f, c->full.dims, p.nz, p.nx, c->h_line,
-                                 pa, pi, hist_at(n - 1, s0), hist_at(n, s0), gs, s));
-    } else {
-      SSX_HIP(launch_grad_store(c->fdt, p.order, f, c->full.dims, p.nz, p.nx, c->h_line, pi,
-                                hist_at(n, s0), gs, s));
-    }
+    SSX_HIP(launch_grad_store(c->fdt, p.order, f, c->full.dims, p.nz, p.nx, c->h_line, pi,
+                              hist_at(n, s0), gs, s));
     return SSX_OK;
   };
   SSX_TRY(issue_propagation(c, c->full, false, c->r_line, io_out(c->Fp, nr_, c->Z0), c->r_line,
                             io_none(), c->r_line, io_none(), c->h_line, io_in(h, ns_, 1.0), s,
-                            &store));
+                            c->fused ? nullptr : &store, c->fused ? &hist : nullptr));
   SSX_HIP(launch_sub(c->vdbl, c->Fp, d, c->e, nr_, p.nshots, s));
   SSX_HIP(launch_dot1(c->vdbl, c->e, c->e, nr_, p.nshots, c->partial, c->sc + SC_TMP, SC_N, s));
   SSX_HIP(launch_zero(c->gacc, (size_t)p.nshots * cells * sizeof(double), s));

@@ -3,8 +3,10 @@
 // ck = dt kappa / (h Z0) and r^n = E_h h^n - D^- v^{n+1/2}, so
 //   dJ/dkappa = (1 / kappa) sum_n P~^{n+1} r^n
 // where P~ = ck dJ/dp^ is the transposed pressure that the adjoint sweep
-// carries.  The forward sweep stores r^n for every physical cell and step;
-// the adjoint sweep accumulates P~^{n+1} r^n in FP64 before its step n.
+// carries.  The forward sweep stores r^n for every physical cell and step
+// (the fused step kernel stores it as it updates the pressure; k_grad_store
+// does it after each step of the split kernels); the adjoint sweep
+// accumulates P~^{n+1} r^n in FP64 before its step n.
 // Only the physical grid is covered: the absorbing layer's coefficients are
 // held fixed, and on the physical grid its split parts are not active.
 #include "ssx_cell.h"
@@ -12,17 +14,6 @@
 namespace ssx {
 
 namespace {
-
-// History and accumulator rows hold the physical columns of a row in the
-// grid's aligned groups of four: group gi covers columns 4 (g0 + gi) ..
-// 4 (g0 + gi) + 3 with g0 = L / 4, so that the stencil loads, the history
-// and the accumulator are 16-byte (FP64: 32-byte) vectors.  Entries of
-// columns outside the physical grid hold zero.
-struct GroupRows {
-  int g0, ng;  // first group, groups per row
-  __host__ __device__ GroupRows(int L, int nx) : g0(L / 4), ng((L + nx - 1) / 4 - L / 4 + 1) {}
-  __host__ __device__ int width() const { return 4 * ng; }
-};
 
 // r^n = src - (dx + dz) on one group of four columns of one physical row
 // and shot, with the staggered stencils and the source injection evaluated
@@ -32,7 +23,7 @@ __device__ __forceinline__ void store_group(const Fields& f, const GridDims& g, 
                                             const LineDev& pil, const TraceIO& pi, int gi, int iz,
                                             int shot, T* __restrict__ hist) {
   using C = typename Tr<T>::C;
-  const GroupRows gr(g.L, nx);
+  const GradRows gr(g.L, nx);
   const int I = g.L + iz, J = 4 * (gr.g0 + gi);
   const long long base = shot * g.field_stride + g.origin + (long long)I * g.pitch + J;
   const T* vx = static_cast<const T*>(f.vx) + base;
@@ -69,20 +60,8 @@ template <int K, typename T>
 __global__ __launch_bounds__(256) void k_grad_store(Fields f, GridDims g, int nz, int nx,
                                                     LineDev pil, TraceIO pi, T* __restrict__ hist) {
   const int gi = blockIdx.x * 64 + threadIdx.x, iz = blockIdx.y * 4 + threadIdx.y;
-  if (gi >= GroupRows(g.L, nx).ng || iz >= nz) return;
+  if (gi >= GradRows(g.L, nx).ng || iz >= nz) return;
   store_group<K, T>(f, g, nz, nx, pil, pi, gi, iz, blockIdx.z, hist);
-}
-
-// two steps at once: r of the fields fa (injection pa) into ha and of fb
-// (injection pb) into hb
-template <int K, typename T>
-__global__ __launch_bounds__(256) void k_grad_store2(Fields fa, Fields fb, GridDims g, int nz,
-                                                     int nx, LineDev pil, TraceIO pa, TraceIO pb,
-                                                     T* __restrict__ ha, T* __restrict__ hb) {
-  const int gi = blockIdx.x * 64 + threadIdx.x, iz = blockIdx.y * 4 + threadIdx.y;
-  if (gi >= GroupRows(g.L, nx).ng || iz >= nz) return;
-  store_group<K, T>(fa, g, nz, nx, pil, pa, gi, iz, blockIdx.z, ha);
-  store_group<K, T>(fb, g, nz, nx, pil, pb, gi, iz, blockIdx.z, hb);
 }
 
 // acc += P~ r^n over the groups of the physical rows (FP64 accumulator)
@@ -90,7 +69,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_grad_acc(Fields f, GridDims g, int nz, int nx,
                                                   const T* __restrict__ hist,
                                                   double* __restrict__ accum) {
-  const GroupRows gr(g.L, nx);
+  const GradRows gr(g.L, nx);
   const int gi = blockIdx.x * 64 + threadIdx.x, iz = blockIdx.y * 4 + threadIdx.y;
   const int shot = blockIdx.z;
   if (gi >= gr.ng || iz >= nz) return;
@@ -113,7 +92,7 @@ __global__ __launch_bounds__(256) void k_grad_acc2(Fields fa, Fields fb, GridDim
                                                    int nx, const T* __restrict__ ha,
                                                    const T* __restrict__ hb,
                                                    double* __restrict__ accum) {
-  const GroupRows gr(g.L, nx);
+  const GradRows gr(g.L, nx);
   const int gi = blockIdx.x * 64 + threadIdx.x, iz = blockIdx.y * 4 + threadIdx.y;
   const int shot = blockIdx.z;
   if (gi >= gr.ng || iz >= nz) return;
@@ -136,7 +115,7 @@ __global__ __launch_bounds__(256) void k_grad_acc2(Fields fa, Fields fb, GridDim
 template <typename T, typename V>
 __global__ void k_grad_final(const double* __restrict__ accum, const T* __restrict__ ck,
                              GridDims g, int nz, int nx, double s, V* __restrict__ out) {
-  const GroupRows gr(g.L, nx);
+  const GradRows gr(g.L, nx);
   const int ix = blockIdx.x * blockDim.x + threadIdx.x, iz = blockIdx.y, shot = blockIdx.z;
   if (ix >= nx) return;
   const int J = g.L + ix;
@@ -159,13 +138,13 @@ bool dims_ok(int nz, int nx, int nshots) {
 }
 // groups: 64 groups x 4 rows per workgroup
 dim3 group_grid(const GridDims& g, int nz, int nx, int nshots) {
-  const GroupRows gr(g.L, nx);
+  const GradRows gr(g.L, nx);
   return dim3((unsigned)((gr.ng + 63) / 64), (unsigned)((nz + 3) / 4), (unsigned)nshots);
 }
 
 }  // namespace
 
-long long grad_cells(int L, int nz, int nx) { return (long long)nz * GroupRows(L, nx).width(); }
+long long grad_cells(int L, int nz, int nx) { return (long long)nz * GradRows(L, nx).width(); }
 
 hipError_t launch_grad_store(Dt dt, int order, const Fields& f, const GridDims& g, int nz, int nx,
                              const LineDev& pil, const TraceIO& pi, void* hist, int nshots,
@@ -186,32 +165,6 @@ hipError_t launch_grad_store(Dt dt, int order, const Fields& f, const GridDims& 
     else
       hipLaunchKernelGGL((k_grad_store<2, float>), grid, block, 0, s, f, g, nz, nx, pil, pi,
                          static_cast<float*>(hist));
-  } else {
-    return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_grad_store2(Dt dt, int order, const Fields& fa, const Fields& fb,
-                              const GridDims& g, int nz, int nx, const LineDev& pil,
-                              const TraceIO& pa, const TraceIO& pb, void* ha, void* hb, int nshots,
-                              hipStream_t s) {
-  if (!dims_ok(nz, nx, nshots)) return hipErrorInvalidValue;
-  const dim3 grid = group_grid(g, nz, nx, nshots), block(64, 4);
-  if (dt == Dt::F64) {
-    if (order == 8)
-      hipLaunchKernelGGL((k_grad_store2<4, double>), grid, block, 0, s, fa, fb, g, nz, nx, pil, pa,
-                         pb, static_cast<double*>(ha), static_cast<double*>(hb));
-    else
-      hipLaunchKernelGGL((k_grad_store2<2, double>), grid, block, 0, s, fa, fb, g, nz, nx, pil, pa,
-                         pb, static_cast<double*>(ha), static_cast<double*>(hb));
-  } else if (dt == Dt::F32) {
-    if (order == 8)
-      hipLaunchKernelGGL((k_grad_store2<4, float>), grid, block, 0, s, fa, fb, g, nz, nx, pil, pa,
-                         pb, static_cast<float*>(ha), static_cast<float*>(hb));
-    else
-      hipLaunchKernelGGL((k_grad_store2<2, float>), grid, block, 0, s, fa, fb, g, nz, nx, pil, pa,
-                         pb, static_cast<float*>(ha), static_cast<float*>(hb));
   } else {
     return hipErrorInvalidValue;
   }

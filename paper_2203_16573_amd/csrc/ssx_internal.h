@@ -92,6 +92,20 @@ struct StepArgs {
   // interior ones (see step_tile_lists)
   const int* tiles;
   int ngen, nint;
+  // forward one-step launches of the fused kernel may also store the
+  // residual of the pressure update of every physical cell (the misfit
+  // gradient's step history, GradRows layout); null otherwise
+  void* hist;
+};
+
+// Rows of the misfit gradient's step history and accumulator: the physical
+// columns of a row in the grid's aligned groups of four, group gi covering
+// columns 4 (g0 + gi) .. 4 (g0 + gi) + 3 with g0 = L / 4 (entries of
+// columns outside the physical grid hold zero).
+struct GradRows {
+  int g0, ng;  // first group, groups per row
+  __host__ __device__ GradRows(int L, int nx) : g0(L / 4), ng((L + nx - 1) / 4 - L / 4 + 1) {}
+  __host__ __device__ int width() const { return 4 * ng; }
 };
 
 // ---- launchers (ssx_step.hip, ssx_slab.hip) ------------------------------
@@ -197,11 +211,6 @@ long long grad_cells(int L, int nz, int nx);
 hipError_t launch_grad_store(Dt dt, int order, const Fields& f, const GridDims& g, int nz, int nx,
                              const LineDev& pil, const TraceIO& pi, void* hist, int nshots,
                              hipStream_t s);
-// two steps: ha from the fields fa (injection pa), hb from fb (pb)
-hipError_t launch_grad_store2(Dt dt, int order, const Fields& fa, const Fields& fb,
-                              const GridDims& g, int nz, int nx, const LineDev& pil,
-                              const TraceIO& pa, const TraceIO& pb, void* ha, void* hb, int nshots,
-                              hipStream_t s);
 // acc[shot] += P~ hist[shot], P~ the transposed pressure in f
 hipError_t launch_grad_acc(Dt dt, const Fields& f, const GridDims& g, int nz, int nx,
                            const void* hist, double* acc, int nshots, hipStream_t s);

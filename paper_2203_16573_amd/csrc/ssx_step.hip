@@ -233,6 +233,16 @@ __device__ __forceinline__ bool interior_tile(const StepArgs& a, int x0, int z0)
          line_clear(a.pil, a.pi, lo, hi);
 }
 
+// The step-history group (GradRows layout) of cells (I, J .. J+3), J a
+// multiple of 4, of one shot: the residual of the pressure update is stored
+// there by forward launches that carry a history pointer.
+template <typename T>
+__device__ __forceinline__ T* hist_group(const StepArgs& a, int shot, int I, int J) {
+  const int L = a.g.L, nz = a.g.NZ - 2 * L, nx = a.g.NX - 2 * L;
+  const GradRows gr(L, nx);
+  return static_cast<T*>(a.hist) + ((long long)shot * nz + (I - L)) * gr.width() + (J - 4 * gr.g0);
+}
+
 // An interior tile's global loads (p^n with its halo, the old velocities,
 // ck), issued into registers.
 template <int K, typename T, int TZ, typename C>
@@ -278,10 +288,11 @@ __device__ __forceinline__ void interior_load(const StepArgs& a, long long base,
 
 // An interior tile's compute phases from its loaded registers: stage p^n,
 // then (after the barrier, where after_stage() may issue the next tile's
-// loads) v^{n+1/2} and p^{n+1}.
-template <int K, bool ADJ, typename T, int TZ, typename C, typename F>
-__device__ __forceinline__ void interior_compute(const StepArgs& a, long long base, int x0, int z0,
-                                                 const InteriorRegs<K, TZ, C>& r,
+// loads) v^{n+1/2} and p^{n+1}.  HIST: also store the residual of the
+// pressure update (interior tiles hold physical cells only and no line).
+template <int K, bool ADJ, typename T, int TZ, typename C, bool HIST, typename F>
+__device__ __forceinline__ void interior_compute(const StepArgs& a, int shot, long long base,
+                                                 int x0, int z0, const InteriorRegs<K, TZ, C>& r,
                                                  C* __restrict__ sP, C* __restrict__ sVX,
                                                  C* __restrict__ sVZ, F&& after_stage) {
   using S = TileShape<K, TZ>;
@@ -385,12 +396,18 @@ __device__ __forceinline__ void interior_compute(const StepArgs& a, long long ba
 #pragma unroll
       for (int e = 0; e < 4; ++e) pn[e] = upd_p<ADJ>(rck[k][e], pc[e], dx[e], dz[e], zero);
       st4(at(pB, rr * P + 4 * g), pn);
+      if constexpr (HIST) {
+        C rs[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) rs[e] = zero - (dx[e] + dz[e]);
+        st4(hist_group<T>(a, shot, z0 + rr, x0 + 4 * g), rs);
+      }
     }
   }
 }
 
 // A general tile (absorbing frame, lines, grid edges), loads included.
-template <int K, bool ADJ, typename T, int TZ, typename C>
+template <int K, bool ADJ, typename T, int TZ, typename C, bool HIST>
 __device__ __forceinline__ void step_general(const StepArgs& a, int shot, int x0, int z0,
                                              C* __restrict__ sP, C* __restrict__ sPX,
                                              C* __restrict__ sVX, C* __restrict__ sVZ,
@@ -743,6 +760,19 @@ __device__ __forceinline__ void step_general(const StepArgs& a, int shot, int x0
                                    sF[FZN + rr], sF[FZN + TZ + rr], &an[e]);
         }
       }
+      if constexpr (HIST) {
+        // physical rows; groups that meet the physical columns (others zero)
+        if (I >= L && I < NZ - L && J + 3 >= L && J < NX - L) {
+          C rs[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int Je = J + e;
+            const C src = lrow ? lrow[4 * g + e] : C(0);
+            rs[e] = (Je >= L && Je < NX - L) ? src - (dx[e] + dz[e]) : C(0);
+          }
+          st4(hist_group<T>(a, shot, I, J), rs);
+        }
+      }
       const unsigned off = rr * P + 4 * g;
       if (!edge_x || J + 3 < NX) {
         st4(at(pB, off), pn);
@@ -779,7 +809,7 @@ __device__ __forceinline__ int xcd_tile(int Lg, int ntiles) {
 //   current tile's compute instead of every workgroup loading, computing and
 //   storing in step.  (General tiles stay outside the loop: inside it, their
 //   long path raises register use past the point of spilling.)
-template <int K, bool ADJ, typename T, int TZ, bool LOOP>
+template <int K, bool ADJ, typename T, int TZ, bool LOOP, bool HIST = false>
 __global__ __launch_bounds__(step_threads(TZ), LOOP ? 4 : 6) void k_step(StepArgs a) {
   using C = typename Tr<T>::C;
   using S = TileShape<K, TZ>;
@@ -809,9 +839,10 @@ __global__ __launch_bounds__(step_threads(TZ), LOOP ? 4 : 6) void k_step(StepArg
     if (interior_tile<K, TZ>(a, x0, z0)) {
       InteriorRegs<K, TZ, C> r;
       interior_load<K, T, TZ, C>(a, base_of(shot), x0, z0, r);
-      interior_compute<K, ADJ, T, TZ, C>(a, base_of(shot), x0, z0, r, sP, sVX, sVZ, [] {});
+      interior_compute<K, ADJ, T, TZ, C, HIST>(a, shot, base_of(shot), x0, z0, r, sP, sVX, sVZ,
+                                               [] {});
     } else {
-      step_general<K, ADJ, T, TZ, C>(a, shot, x0, z0, sP, sPX, sVX, sVZ, sF, sL);
+      step_general<K, ADJ, T, TZ, C, HIST>(a, shot, x0, z0, sP, sPX, sVX, sVZ, sF, sL);
     }
   } else {
     const int ngen_all = a.nshots * a.ngen, nint_all = a.nshots * a.nint;
@@ -821,8 +852,8 @@ __global__ __launch_bounds__(step_threads(TZ), LOOP ? 4 : 6) void k_step(StepArg
       const int e = __builtin_amdgcn_readfirstlane(idx - shot * a.ngen);
       const int tt = ((const __attribute__((address_space(4))) int*)a.tiles)[e];  // scalar load
       const int tzi = tt / a.ntx;
-      step_general<K, ADJ, T, TZ, C>(a, shot, (tt - tzi * a.ntx) * TX, tzi * TZ, sP, sPX, sVX, sVZ,
-                                     sF, sL);
+      step_general<K, ADJ, T, TZ, C, HIST>(a, shot, (tt - tzi * a.ntx) * TX, tzi * TZ, sP, sPX,
+                                           sVX, sVZ, sF, sL);
       return;
     }
     // interior tiles: logical index Li -> (shot, x0, z0); the list entry is
@@ -855,7 +886,8 @@ __global__ __launch_bounds__(step_threads(TZ), LOOP ? 4 : 6) void k_step(StepArg
       const bool more = Ln < nint_all;
       int shotn = 0, x0n = 0, z0n = 0;
       if (more) locate(Ln, shotn, x0n, z0n);
-      interior_compute<K, ADJ, T, TZ, C>(a, base_of(shot), x0, z0, cur, sP, sVX, sVZ, [&] {
+      interior_compute<K, ADJ, T, TZ, C, HIST>(a, shot, base_of(shot), x0, z0, cur, sP, sVX, sVZ,
+                                               [&] {
         if (more) interior_load<K, T, TZ, C>(a, base_of(shotn), x0n, z0n, nxt);
       });
       if (!more) break;
@@ -1237,6 +1269,27 @@ static hipError_t step_t(int tz, int loop, const StepArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(kernel, dim3(nb), dim3(threads), 0, s, a);
     return hipGetLastError();
   };
+  if (a.hist) {
+    // the step history: forward steps with FP32 or FP64 fields only
+    if constexpr (!ADJ && sizeof(T) >= 4) {
+      switch (tz) {
+        case 8:
+          return loop ? go(k_step<K, ADJ, T, 8, true, true>, step_threads(8))
+                      : go(k_step<K, ADJ, T, 8, false, true>, step_threads(8));
+        case 16:
+          return loop ? go(k_step<K, ADJ, T, 16, true, true>, step_threads(16))
+                      : go(k_step<K, ADJ, T, 16, false, true>, step_threads(16));
+        case 32:
+          if constexpr (sizeof(T) < 8) {
+            return loop ? go(k_step<K, ADJ, T, 32, true, true>, step_threads(32))
+                        : go(k_step<K, ADJ, T, 32, false, true>, step_threads(32));
+          }
+          return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+      }
+    }
+    return hipErrorInvalidValue;
+  }
   switch (tz) {
     case 8:
       return loop ? go(k_step<K, ADJ, T, 8, true>, step_threads(8))
