@@ -613,7 +613,11 @@ def gradient_bench(args, wl, ctx, d, fd):
     NZ, NX = prob.nz + 2 * prob.npml, prob.nx + 2 * prob.npml
     cu = 2 * prob.nt * NZ * NX * prob.nshots
     fsz = 8 if fd == "f64" else 4
-    extra = prob.nt * prob.nz * prob.nx * prob.nshots * (2 * fsz + fsz + 16)
+    # algorithmic bytes the gradient adds to the two sweeps, per physical
+    # cell and step: the history written by the forward step (fsz), read
+    # back with the transposed pressure (2 fsz), and the FP64 accumulator
+    # read and written once per step pair (8)
+    extra = prob.nt * prob.nz * prob.nx * prob.nshots * (3 * fsz + 8)
     out = {
         "metric": "misfit gradients in kappa/s", "value": round(args.steps / el, 4),
         "unit": "gradients/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
