@@ -985,14 +985,17 @@ ssx_status do_normal_w(ssx_ctx* c, const double* alpha2_dev, double alpha2_host,
   const ssx_problem& pr = c->prob;
   const bool fork = with_m && c->overlap;
   if (fork) {
+    // forked after F p, so that W_m's slab simulations run beside W_d's
+    // (small grids that leave most of the device idle) rather than beside
+    // the full-grid steps
     SSX_TRY(ensure_aux(c));
+    SSX_TRY(do_fwd(c, p, Fp));
     SSX_HIP(hipEventRecord(c->ev_fork, c->stream));
     SSX_HIP(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
     ssx_status st = wm_term(c, p, c->aux);
     SSX_HIP(hipEventRecord(c->ev_join, c->aux));
     // the context's stream waits for the second one on every path, so that
     // no work reading p or writing the scratch vectors outlives the call
-    if (st == SSX_OK) st = do_fwd(c, p, Fp);
     if (st == SSX_OK) st = do_wd(c, Fp, c->rW);
     if (st == SSX_OK) st = do_adj(c, c->rW, q);
     SSX_HIP(hipStreamWaitEvent(c->stream, c->ev_join, 0));
