@@ -53,8 +53,17 @@ from .prop import adjoint, forward
 class Model:
     """The full-grid and thin-slab discretisations of one problem."""
 
-    def __init__(self, prob, kappa, rho):
+    def __init__(self, prob, kappa, rho, engine: str = "numpy"):
+        """engine: "numpy" (oracle.prop) or "c" (oracle.cengine, the same
+        time stepping as plain C loops, for the full-length runs)."""
         self.prob = prob
+        if engine == "numpy":
+            self._forward, self._adjoint = forward, adjoint
+        elif engine == "c":
+            from . import cengine
+            self._forward, self._adjoint = cengine.forward, cengine.adjoint
+        else:
+            raise ValueError(f"unknown oracle engine {engine!r}")
         self.rho = float(rho)
         kappa = np.asarray(kappa, dtype=np.float64)
         if kappa.shape != (prob.nz, prob.nx):
@@ -113,13 +122,13 @@ class Model:
     # -- F and F^T -----------------------------------------------------------
     def fwd(self, h):
         """d = F h, h [nt][ns] -> d [nt][nr]."""
-        P, _ = forward(self.full, self.prob.nt, h_src=(self.h_line, h),
+        P, _ = self._forward(self.full, self.prob.nt, h_src=(self.h_line, h),
                        rec_p=self.r_line)
         return P
 
     def adj(self, r):
         """g = F^T r, r [nt][nr] -> g [nt][ns]."""
-        hb, _ = adjoint(self.full, self.prob.nt, h_line=self.h_line,
+        hb, _ = self._adjoint(self.full, self.prob.nt, h_line=self.h_line,
                         rec_p=(self.r_line, r))
         return hb
 
@@ -132,14 +141,14 @@ class Model:
         """y = V f (the vdef operator): normal load f [nt][ns] on z_s, normal
         velocity traces [nt][nr] recorded on z_r."""
         fl, rl = self._v_lines()
-        _, V = forward(self.full, self.prob.nt, f_src=(fl, f), rec_v=rl)
+        _, V = self._forward(self.full, self.prob.nt, f_src=(fl, f), rec_v=rl)
         return V
 
     def adj_v(self, r):
         """g = V^T r: r [nt][nr] enters the normal-velocity trace slot on
         z_r; g [nt][ns] is read from the normal-load slot on z_s."""
         fl, rl = self._v_lines()
-        _, fb = adjoint(self.full, self.prob.nt, f_line=fl, rec_v=(rl, r))
+        _, fb = self._adjoint(self.full, self.prob.nt, f_line=fl, rec_v=(rl, r))
         return fb
 
     def block(self, src: int, rec: int, x, transpose: bool = False):
@@ -153,12 +162,12 @@ class Model:
         s_line = self.h_line if src == 0 else g.vz_line(p.z_src, p.x_src0, p.ns)
         r_line = self.r_line if rec == 0 else g.vz_line(p.z_rec, p.x_rec0, p.nr)
         if not transpose:
-            P, V = forward(g, p.nt, h_src=(s_line, x) if src == 0 else None,
+            P, V = self._forward(g, p.nt, h_src=(s_line, x) if src == 0 else None,
                            f_src=(s_line, x) if src == 1 else None,
                            rec_p=r_line if rec == 0 else None,
                            rec_v=r_line if rec == 1 else None)
             return P if rec == 0 else V
-        hb, fb = adjoint(g, p.nt, h_line=s_line if src == 0 else None,
+        hb, fb = self._adjoint(g, p.nt, h_line=s_line if src == 0 else None,
                          f_line=s_line if src == 1 else None,
                          rec_p=(r_line, x) if rec == 0 else None,
                          rec_v=(r_line, x) if rec == 1 else None)
@@ -184,11 +193,11 @@ class Model:
             g, f_line, d_p, d_v = self.rslab()
             dz = self.prob.rslab_dz
         nt = self.prob.nt
-        P, V = forward(g, nt, f_src=(f_line, x), rec_p=d_p, rec_v=d_v)
+        P, V = self._forward(g, nt, f_src=(f_line, x), rec_p=d_p, rec_v=d_v)
         if transpose:
-            _, fb = adjoint(g, nt, f_line=f_line, rec_p=(d_p, V))
+            _, fb = self._adjoint(g, nt, f_line=f_line, rec_p=(d_p, V))
         else:
-            _, fb = adjoint(g, nt, f_line=f_line, rec_v=(d_v, P))
+            _, fb = self._adjoint(g, nt, f_line=f_line, rec_v=(d_v, P))
         return 8.0 * math.copysign(1.0, dz) * fb
 
     # -- thin-slab vector operator X = Pi-projected S on the slab -------------
@@ -196,13 +205,13 @@ class Model:
         """X f = (P, V): normal-load source f on z_s, pressure and normal
         velocity recorded on the datum."""
         g, f_line, d_p, d_v = self.slab()
-        return forward(g, self.prob.nt, f_src=(f_line, f), rec_p=d_p, rec_v=d_v)
+        return self._forward(g, self.prob.nt, f_src=(f_line, f), rec_p=d_p, rec_v=d_v)
 
     def slab_adj(self, a, b):
         """X^T (a, b): a enters the pressure-trace slot, b the v_z slot; the
         result is read from the normal-load source slot."""
         g, f_line, d_p, d_v = self.slab()
-        _, fb = adjoint(g, self.prob.nt, f_line=f_line, rec_p=(d_p, a),
+        _, fb = self._adjoint(g, self.prob.nt, f_line=f_line, rec_p=(d_p, a),
                         rec_v=(d_v, b))
         return fb
 
@@ -223,8 +232,8 @@ class Model:
         cells away), s_r = 4 sign(rslab_dz).  r [nt][nr] -> [nt][nr]."""
         g, f_line, d_p, d_v = self.rslab()
         nt = self.prob.nt
-        P, V = forward(g, nt, f_src=(f_line, r), rec_p=d_p, rec_v=d_v)
-        _, fb = adjoint(g, nt, f_line=f_line, rec_p=(d_p, V), rec_v=(d_v, P))
+        P, V = self._forward(g, nt, f_src=(f_line, r), rec_p=d_p, rec_v=d_v)
+        _, fb = self._adjoint(g, nt, f_line=f_line, rec_p=(d_p, V), rec_v=(d_v, P))
         return 4.0 * math.copysign(1.0, self.prob.rslab_dz) * fb
 
     def wm(self, x):
@@ -237,8 +246,8 @@ class Model:
         self.slab()
         g, _, d_p, d_v, p_line = self._slab
         nt = self.prob.nt
-        P, V = forward(g, nt, h_src=(p_line, x), rec_p=d_p, rec_v=d_v)
-        hb, _ = adjoint(g, nt, h_line=p_line, rec_p=(d_p, V), rec_v=(d_v, P))
+        P, V = self._forward(g, nt, h_src=(p_line, x), rec_p=d_p, rec_v=d_v)
+        hb, _ = self._adjoint(g, nt, h_line=p_line, rec_p=(d_p, V), rec_v=(d_v, P))
         return math.copysign(1.0, self.prob.slab_dz) * hb
 
 
