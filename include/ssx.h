@@ -181,6 +181,22 @@ ssx_status ssx_normal(ssx_ctx* ctx, double alpha, const void* p, void* q, void* 
 ssx_status ssx_dot(ssx_ctx* ctx, const void* x, const void* y, int64_t n,
                    double* out_host);
 
+/* Allocation-free per-shot FP64 inner products, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same kernels and reduction order as
+ * ssx_dot, without a context.  x, y: DEVICE arrays of nshots vectors of n
+ * elements (shots at stride n) of vec_dtype (SSX_F64 or SSX_F32); out_dev:
+ * DEVICE [nshots] doubles receiving <x, y> per shot.  Stream-ordered on
+ * `stream` (hipStream_t, NULL = default stream), no synchronisation.  The
+ * partial sums live in a static device array of the library (one per GPU,
+ * SSX_DOT_STATIC_MAX_SHOTS x 256 doubles, 128 KiB, held until the process
+ * ends); no memory is allocated.  Calls that overlap on one GPU share that
+ * array and race: order them on one stream.  SSX_ERR_ARG for null pointers,
+ * n < 0, nshots outside [1, SSX_DOT_STATIC_MAX_SHOTS] or another dtype. */
+#define SSX_DOT_STATIC_MAX_SHOTS 64
+ssx_status ssx_dot_static(const void* x, const void* y, int64_t n, int32_t nshots,
+                          int32_t vec_dtype, double* out_dev, void* stream);
+
 /* Algorithm 1 (standard PCG, h_0 = 0) on N h = F^T d for every shot:
  * alpha = alpha_rel ||F^T d|| / ||d|| per shot; M^-1 as ssx_precond with
  * alpha_hat = alpha_rel when use_precond != 0, M = I otherwise (plain CG).

@@ -58,7 +58,9 @@ EXPORTS = ("ssx_validate", "ssx_footprint", "ssx_create", "ssx_destroy", "ssx_fw
            "ssx_step_kernel_name", "ssx_cells_per_launch", "ssx_launch_shape",
            "ssx_weight_d", "ssx_weight_m", "ssx_normal_w", "ssx_pcg_solve_w",
            "ssx_fwd_v", "ssx_adj_v", "ssx_tr_inverse", "ssx_lambda", "ssx_block",
-           "ssx_misfit_gradient", "ssx_pcg_solve_v")
+           "ssx_misfit_gradient", "ssx_pcg_solve_v", "ssx_dot_static")
+
+DOT_STATIC_MAX_SHOTS = 64  # SSX_DOT_STATIC_MAX_SHOTS
 
 
 class SSXError(RuntimeError):
@@ -111,6 +113,8 @@ def lib():
         L.ssx_precond.argtypes = [vp, c_dbl, vp, vp]
         L.ssx_normal.argtypes = [vp, c_dbl, vp, vp, vp]
         L.ssx_dot.argtypes = [vp, vp, vp, ctypes.c_int64, dp]
+        L.ssx_dot_static.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                     vp, vp]
         L.ssx_pcg_solve.argtypes = [vp, vp, c_dbl, ctypes.c_int32, c_dbl, ctypes.c_int32,
                                     vp, dp, ctypes.POINTER(ctypes.c_int32)]
         L.ssx_weight_d.argtypes = [vp, vp, vp]
@@ -172,6 +176,32 @@ def footprint(prob, field_dtype: str = "f32", nshots: int | None = None) -> int:
     ns = len(prob.xs) if nshots is None else nshots
     P = make_problem(prob, ns, field_dtype)
     return int(lib().ssx_footprint(ctypes.byref(P)))
+
+
+def dot_static(x, y, nshots: int, out=None, stream=None):
+    """Per-shot FP64 inner products <x, y> of device tensors (nshots vectors
+    each, float64 or float32) through ssx_dot_static, the entry point that
+    allocates no device memory; out: a float64 device tensor [nshots]
+    (allocated here when None).  Stream-ordered, no synchronisation."""
+    import torch
+
+    for t, name in ((x, "x"), (y, "y")):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous device tensor")
+    if x.dtype != y.dtype or x.numel() != y.numel() or x.dtype not in (torch.float64,
+                                                                        torch.float32):
+        raise ValueError("x and y: same float64 / float32 dtype and size")
+    if nshots < 1 or x.numel() % nshots:
+        raise ValueError("nshots must divide the vector length")
+    if out is None:
+        out = torch.empty(nshots, dtype=torch.float64, device=x.device)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    vdt = 0 if x.dtype == torch.float64 else 1
+    _check(lib().ssx_dot_static(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                x.numel() // nshots, int(nshots), vdt,
+                                ctypes.c_void_p(out.data_ptr()),
+                                ctypes.c_void_p(st.cuda_stream)))
+    return out
 
 
 class Context:

@@ -1353,6 +1353,20 @@ ssx_status ssx_dot(ssx_ctx* c, const void* x, const void* y, int64_t n, double* 
   return SSX_OK;
 }
 
+ssx_status ssx_dot_static(const void* x, const void* y, int64_t n, int32_t nshots,
+                          int32_t vec_dtype, double* out_dev, void* stream) {
+  if (!x || !y || !out_dev || n < 0) return fail(SSX_ERR_ARG, "bad argument");
+  if (nshots < 1 || nshots > SSX_DOT_STATIC_MAX_SHOTS)
+    return fail(SSX_ERR_ARG, "ssx_dot_static: nshots must lie in [1, " +
+                                 std::to_string(SSX_DOT_STATIC_MAX_SHOTS) + "]");
+  if (vec_dtype != SSX_F64 && vec_dtype != SSX_F32)
+    return fail(SSX_ERR_ARG, "ssx_dot_static: vec_dtype must be SSX_F64 or SSX_F32");
+  static_assert(SSX_DOT_STATIC_MAX_SHOTS == DOT_SCRATCH_SHOTS, "scratch size");
+  SSX_HIP(launch_dot1_static(vec_dtype == SSX_F64, x, y, n, nshots, out_dev,
+                             static_cast<hipStream_t>(stream)));
+  return SSX_OK;
+}
+
 }  // extern "C"
 
 namespace {

@@ -161,6 +161,11 @@ hipError_t launch_dot3(bool vdbl, const void* x, const void* y, long long n, int
 // out[shot*ostride + 0] = sum x*y only (one product)
 hipError_t launch_dot1(bool vdbl, const void* x, const void* y, long long n, int nshots,
                        double* partial, double* out, int ostride, hipStream_t s);
+// The same with the partial sums in the library's static device array (no
+// allocation, no context): out[shot] for 1 <= nshots <= DOT_SCRATCH_SHOTS.
+constexpr int DOT_SCRATCH_SHOTS = 64;
+hipError_t launch_dot1_static(bool vdbl, const void* x, const void* y, long long n, int nshots,
+                              double* out, hipStream_t s);
 
 // y[shot][t][k] = s * f(k, shot) * x   with f chosen by op:
 //   0: |xk - xs|, 1: |xk - xs|^2, 2: (1 + a^2 |xk-xs|^2)^(-1/2), 3: 1

@@ -4,6 +4,7 @@
 #include "ssx_device.h"
 
 #include <cmath>
+#include <mutex>
 
 namespace ssx {
 
@@ -89,6 +90,47 @@ hipError_t launch_dot3(bool vdbl, const void* x, const void* y, long long n, int
 hipError_t launch_dot1(bool vdbl, const void* x, const void* y, long long n, int nshots,
                        double* partial, double* out, int ostride, hipStream_t s) {
   return dot_t<1>(vdbl, x, y, n, nshots, partial, out, ostride, s);
+}
+
+// ---------------------------------------------------------------------------
+// The allocation-free inner product (ssx_dot_static): its partial sums live
+// in this file-scope device array, one copy per GPU, held until the process
+// ends.  Every partial is written before it is read, so nothing needs
+// clearing between calls; calls that overlap on one GPU share the array and
+// race.
+static __device__ __align__(256) double scratch[DOT_SCRATCH_SHOTS * NBLK_DOT];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};  // device address of `scratch`, per GPU
+}  // namespace
+
+// Device address of `scratch` on the current GPU, looked up once per GPU
+// (the array's name in host code is only a host-side stand-in).
+hipError_t dot_scratch(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    double* p = nullptr;
+    e = hipGetSymbolAddress(reinterpret_cast<void**>(&p), HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+hipError_t launch_dot1_static(bool vdbl, const void* x, const void* y, long long n, int nshots,
+                              double* out, hipStream_t s) {
+  if (nshots < 1 || nshots > DOT_SCRATCH_SHOTS) return hipErrorInvalidValue;
+  double* part = nullptr;
+  hipError_t e = dot_scratch(&part);
+  if (e != hipSuccess) return e;
+  return dot_t<1>(vdbl, x, y, n, nshots, part, out, 1, s);
 }
 
 // ---------------------------------------------------------------------------
