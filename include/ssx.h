@@ -332,11 +332,10 @@ ssx_status ssx_lambda(ssx_ctx* ctx, int32_t side, int32_t transpose, const void*
  *                       and the thin slab: 8, 16 or 32 (32 not for F64
  *                       fields); 0 picks a default from the grid size.
  *   SSX_OPT_TILE_Z_SLAB the same for the thin slab only.
- *   SSX_OPT_STEPS_PER_LAUNCH      time steps fused per launch of the fused
- *                       kernel on the full grid: 1 (default) or 2 (2: F32
- *                       fields only; uses a tile height of 8).
- *   SSX_OPT_STEPS_PER_LAUNCH_SLAB the same for the thin slab, and also 4
- *                       or 8 (not for F64 fields, slabs of at most 56
+ *   SSX_OPT_STEPS_PER_LAUNCH      time steps per launch of the fused
+ *                       kernel on the full grid: 1 (the only value).
+ *   SSX_OPT_STEPS_PER_LAUNCH_SLAB the same for the thin slab: 1 (default),
+ *                       4 or 8 (not for F64 fields, slabs of at most 56
  *                       rows): each workgroup holds the whole slab height
  *                       of a strip of columns in LDS and advances it 4 or
  *                       8 steps, recomputing an x halo of that many

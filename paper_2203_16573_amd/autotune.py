@@ -22,7 +22,7 @@ from . import (OPT_SHOT_GROUP, OPT_SHOT_GROUP_SLAB, OPT_SLAB_STRIP, OPT_STEP_KER
                OPT_TILE_Z_SLAB,
                Context)
 
-DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ssx", "autotune-v5.json")
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ssx", "autotune-v6.json")
 SLAB_MAXZ = 56  # tallest slab the 4/8-step slab kernel holds
 _lock = threading.Lock()
 
@@ -105,9 +105,7 @@ def tune(prob, kappa, rho, xs=None, field_dtype="f32", nt_tune: int = 60,
     # candidates: (steps per launch, tile height)
     if field_dtype == "f64":
         cands = [(1, 8), (1, 16)]
-    elif field_dtype == "f32":
-        cands = [(1, 8), (1, 16), (1, 32), (2, 8)]
-    else:  # two steps per launch are FP32-only
+    else:
         cands = [(1, 8), (1, 16), (1, 32)]
     # slab candidates: the same, plus the multi-step slab kernel
     # (steps, strip width) with the tile height of its one-step remainder

@@ -571,14 +571,13 @@ ssx_status issue_group(ssx_ctx* c, GridDev& gd, bool adj, const Fields& f0, cons
   a.ngen = loop ? gd.ngen[li] : 0;
   a.nint = loop ? gd.nint[li] : 0;
   const int ntz1 = (gd.host.NZ + tz - 1) / tz;
-  const int ntz2 = (gd.host.NZ + STEP2_TZ - 1) / STEP2_TZ;
   // multi-step slab kernel: strip width (ns = 8 needs 128 columns)
   const int wr = (spl == 8 || c->slab_strip == 0) ? 128 : c->slab_strip;
   const int wown = spl >= 4 ? slab_strip_width(order, spl, wr) : 0;
   Fields buf[2] = {f0, f1};
   int cur = 0;
-  // one launch covering `steps` (1 or 2) steps starting at step n with the
-  // given level-0 trace indices
+  // one launch covering `steps` (1, or 4 or 8 on a slab) steps starting at
+  // step n with the given level-0 trace indices
   auto launch = [&](int steps, int ivs, int ivi, int ips, int ipi) -> ssx_status {
     a.in = buf[cur];
     a.out = buf[1 - cur];
@@ -586,14 +585,7 @@ ssx_status issue_group(ssx_ctx* c, GridDev& gd, bool adj, const Fields& f0, cons
     a.vi = vi;
     a.ps = ps;
     a.pi = pi;
-    if (steps == 2) {
-      a.vs.n = ivs;
-      a.vi.n = ivi;
-      a.ps.n = ips;
-      a.pi.n = ipi;
-      a.ntz = ntz2;
-      SSX_HIP(launch_step2(c->fdt, order, adj, a, s));
-    } else if (steps >= 4) {
+    if (steps >= 4) {
       a.vs.n = ivs;
       a.vi.n = ivi;
       a.ps.n = ips;
@@ -1596,11 +1588,7 @@ ssx_status ssx_set_option(ssx_ctx* c, int option, int value) {
       }
       [[fallthrough]];
     case SSX_OPT_STEPS_PER_LAUNCH:
-      if (value != 1 && value != 2) return fail(SSX_ERR_ARG, "steps per launch must be 1 or 2");
-      // two steps per launch: FP32 fields only (the 16-bit instances are
-      // switched off after a device memory fault whose cause is not known)
-      if (value == 2 && c->fdt != Dt::F32)
-        return fail(SSX_ERR_ARG, "two steps per launch are available for F32 fields only");
+      if (value != 1) return fail(SSX_ERR_ARG, "steps per launch on the full grid must be 1");
       if (option == SSX_OPT_STEPS_PER_LAUNCH) c->spl_full = value;
       c->spl_slab = value;
       return SSX_OK;
@@ -1637,10 +1625,7 @@ const char* ssx_step_kernel_name(ssx_ctx* c) {
 
 ssx_status ssx_launch_shape(ssx_ctx* c, int32_t* shape) {
   if (!c || !shape) return fail(SSX_ERR_ARG, "null argument");
-  shape[0] = c->fused ? (c->spl_full == 2 ? STEP2_TZ
-                                           : (c->tile_z_full ? c->tile_z_full
-                                                             : default_tile_z(c, c->full)))
-                      : 0;
+  shape[0] = c->fused ? (c->tile_z_full ? c->tile_z_full : default_tile_z(c, c->full)) : 0;
   shape[1] = c->fused ? c->spl_full : 1;
   shape[2] = shot_group(c, c->full);
   shape[3] = (c->fused && c->spl_full == 1) ? c->loop_full : 0;

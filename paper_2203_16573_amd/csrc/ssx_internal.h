@@ -123,9 +123,6 @@ hipError_t launch_step(Dt dt, int order, bool adj, int tz, int loop, StepArgs a,
 // listed interior tile is interior at every step.
 void step_tile_lists(int order, int tz, const GridDims& g, const LineDev* const* lines,
                      int nlines, std::vector<int>* gen, std::vector<int>* inter);
-// Two fused time steps per launch (tile height 8; not for F64 fields).
-hipError_t launch_step2(Dt dt, int order, bool adj, StepArgs a, hipStream_t s);
-constexpr int STEP2_TZ = 8;
 int step_tile_width();
 // Several time steps per launch on a slab grid of at most SLAB_MAXZ rows
 // (FP32, FP16 or BF16 fields): ns steps (4 or 8) on strips of wr columns

@@ -902,285 +902,7 @@ __global__ __launch_bounds__(step_threads(TZ), LOOP ? 4 : 6) void k_step(StepArg
 }
 
 // ---------------------------------------------------------------------------
-// Two fused time steps per launch (temporal blocking, TZ = 8).
-//
-// Each thread owns fixed 1 x 4 groups of a staged frame (the 64 x 8 tile
-// plus 2R rows and HS columns on each side, R = 2K-1) and keeps p, v_x,
-// v_z, the layer auxiliary and ck of its groups in registers across both
-// levels; LDS only exchanges stencil neighbours.  Level t (t = 0, 1)
-// computes v on the region the next pressure update needs and p on the
-// tile grown by (1 - t) R, so level 1 produces p^{n+2}, v^{n+3/2} on the
-// tile exactly as two single steps would (same expressions, same order).
-// Trace samples and injections of level t use time index n + dir t.
-
-constexpr int r4(int v) { return (v + 3) / 4 * 4; }
-constexpr int cmax(int a, int b) { return a > b ? a : b; }
-
-template <int K, bool ADJ, typename T>
-__global__ __launch_bounds__(256) void k_step2(StepArgs a) {
-  using C = typename Tr<T>::C;
-  using V = typename Tr<T>::V;
-  constexpr int TT = 2, TZ = STEP2_TZ;
-  constexpr int R = 2 * K - 1;
-  constexpr int HR = TT * R;                                 // staged row halo
-  constexpr int HS = r4(cmax(TT * R, r4((TT - 1) * R + K) + K));  // staged column halo
-  constexpr int SR = TZ + 2 * HR, SC = TX + 2 * HS;
-  constexpr int NGR = SC / 4, NG = SR * NGR;
-  constexpr int NQ = (NG + 255) / 256;
-  __shared__ __align__(16) C sP[SR * SC];
-  __shared__ __align__(16) C sVX[SR * SC];
-  __shared__ __align__(16) C sVZ[SR * SC];
-  __shared__ __align__(16) C sPX[ADJ ? SR * SC : 4];
-
-  const int nb = gridDim.x, b = blockIdx.x;
-  const int full = nb >> 3, rem = nb & 7, xcd = b & 7;
-  const int t_ = xcd * full + (xcd < rem ? xcd : rem) + (b >> 3);
-  const int per_shot = a.ntx * a.ntz;
-  const int shot = t_ / per_shot;
-  const int tt = t_ - shot * per_shot;
-  const int tzi = tt / a.ntx, txi = tt - tzi * a.ntx;
-  const int x0 = txi * TX, z0 = tzi * TZ;
-  const int x1 = x0 + TX, z1 = z0 + TZ;
-  const int NX = a.g.NX, NZ = a.g.NZ, P = a.g.pitch, L = a.g.L;
-  const long long base = a.g.origin + (long long)shot * a.g.field_stride;
-  const T* __restrict__ pA = static_cast<const T*>(a.in.p) + base;
-  const T* __restrict__ vxA = static_cast<const T*>(a.in.vx) + base;
-  const T* __restrict__ vzA = static_cast<const T*>(a.in.vz) + base;
-  const T* __restrict__ auA = static_cast<const T*>(a.in.aux) + base;
-  T* __restrict__ pB = static_cast<T*>(a.out.p) + base;
-  T* __restrict__ vxB = static_cast<T*>(a.out.vx) + base;
-  T* __restrict__ vzB = static_cast<T*>(a.out.vz) + base;
-  T* __restrict__ auB = static_cast<T*>(a.out.aux) + base;
-  const C* __restrict__ ckp = static_cast<const C*>(a.c.ck) + a.g.origin;
-  const Pml<C> pm{static_cast<const C*>(a.c.pml), P, NZ};
-  const C cb = C(a.c.cb);
-  const int tid = threadIdx.x;
-  // does the staged frame reach the absorbing layer?
-  const bool near_frame = (z0 - HR < L) || (z1 + HR > NZ - L) || (x0 - HS < L) || (x1 + HS > NX - L);
-
-  // frame coordinates of level regions (t = 0, 1), a_t = (1 - t) R:
-  //  P_t : rows [HR - a_t, HR + TZ + a_t), groups covering columns [HS - a_t, HS + TX + a_t)
-  //  VX_t: P_t rows, groups covering columns [HS - a_t - K, HS + TX + a_t + K - 1)
-  //  VZ_t: rows [HR - a_t - K, HR + TZ + a_t + K - 1), P_t groups
-  auto in_rows = [](int fr, int lo, int hi) { return fr >= lo && fr < hi; };
-  auto in_cols = [](int gc, int lo, int hi) { return 4 * gc + 3 >= lo && 4 * gc < hi; };
-
-  C rp[NQ][4], rvx[NQ][4], rvz[NQ][4], rau[NQ][4], rck[NQ][4];
-#pragma unroll
-  for (int k = 0; k < NQ; ++k) {
-    const int q = tid + 256 * k;
-    const int fr = q / NGR, gc = q - fr * NGR;
-    const int I = z0 - HR + fr, J = x0 - HS + 4 * gc;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) rp[k][e] = rvx[k][e] = rvz[k][e] = rau[k][e] = rck[k][e] = C(0);
-    if (q >= NG || I < 0 || I >= NZ || J >= NX) continue;
-    const long long o = (long long)I * P + J;
-    ld4(rp[k], pA + o);
-    constexpr int a0 = R;
-    const bool rows_p0 = in_rows(fr, HR - a0, HR + TZ + a0);
-    if (rows_p0 && in_cols(gc, HS - a0 - K, HS + TX + a0 + K - 1)) ld4(rvx[k], vxA + o);
-    if (in_rows(fr, HR - a0 - K, HR + TZ + a0 + K - 1) && in_cols(gc, HS - a0, HS + TX + a0))
-      ld4(rvz[k], vzA + o);
-    if (rows_p0 && in_cols(gc, HS - a0, HS + TX + a0)) {
-      ld4(rck[k], ckp + o);
-      if (near_frame) ld4(rau[k], auA + o);
-    } else if (ADJ && near_frame && rows_p0) {
-      ld4(rau[k], auA + o);  // the transposed x-stencil reads aux beyond P_0's columns
-    }
-  }
-
-#pragma unroll
-  for (int lv = 0; lv < TT; ++lv) {
-    const int at = (TT - 1 - lv) * R;
-    // (a) p^{n+lv} (and P~_x) to LDS on the source region of this level
-#pragma unroll
-    for (int k = 0; k < NQ; ++k) {
-      const int q = tid + 256 * k;
-      if (q >= NG) continue;
-      const int fr = q / NGR, gc = q - fr * NGR;
-      const int ap = (TT - lv) * R;  // halo of the p region valid at this level
-      if (lv > 0 && !(in_rows(fr, HR - ap, HR + TZ + ap) && in_cols(gc, HS - ap, HS + TX + ap)))
-        continue;
-      st4(sP + 4 * q, rp[k]);
-      if constexpr (ADJ) {
-        if (near_frame) {
-          C s4[4];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) s4[e] = rp[k][e] + rau[k][e];
-          st4(sPX + 4 * q, s4);
-        }
-      }
-    }
-    __syncthreads();
-
-    // pressure-line sampling of p^{n+lv}
-    {
-      const int idx = a.vs.n + a.dir * lv;
-      if (a.vs.out && idx >= 0 && idx < a.nt && a.vsl.row0 >= z0 && a.vsl.row0 < z1 && tid < TX) {
-        const int J = x0 + tid;
-        if (J >= a.vsl.col0 && J < a.vsl.col0 + a.vsl.ntr && J < NX) {
-          const int r0 = a.vsl.row0 - z0 + HR, r1 = a.vsl.row1 - z0 + HR;
-          const C val = C(a.vsl.w0) * sP[r0 * SC + tid + HS] + C(a.vsl.w1) * sP[r1 * SC + tid + HS];
-          line_out_at<C, V>(a.vsl, a.vs, idx, J, shot, val);
-        }
-      }
-    }
-
-    // (b) v^{n+lv+1/2}
-    const int vidx = a.vi.n + a.dir * lv;
-#pragma unroll
-    for (int k = 0; k < NQ; ++k) {
-      const int q = tid + 256 * k;
-      if (q >= NG) continue;
-      const int fr = q / NGR, gc = q - fr * NGR;
-      const int I = z0 - HR + fr, J = x0 - HS + 4 * gc;
-      const bool rows_p = in_rows(fr, HR - at, HR + TZ + at);
-      if (rows_p && in_cols(gc, HS - at - K, HS + TX + at + K - 1)) {
-        C nv[4] = {C(0), C(0), C(0), C(0)};
-        if (I >= 0 && I < NZ) {
-          const C* row = (ADJ && near_frame) ? (sPX + fr * SC) : (sP + fr * SC);
-          C w[12];
-          ld4(*reinterpret_cast<C(*)[4]>(w), row + 4 * gc - 4);
-          ld4(*reinterpret_cast<C(*)[4]>(w + 4), row + 4 * gc);
-          ld4(*reinterpret_cast<C(*)[4]>(w + 8), row + 4 * gc + 4);
-          C ax[4], bx[4];
-          ld4(ax, pm.xa(2, J));
-          ld4(bx, pm.xa(3, J));
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            if (J + e >= 0 && J + e < NX) {
-              C sx = C(0);
-#pragma unroll
-              for (int m = 1; m <= K; ++m) sx = acc(sx, wst<K, C>(m - 1), w[e + 4 + m], w[e + 5 - m]);
-              nv[e] = rnd<T>(upd_v<ADJ>(ax[e], bx[e], cb, rvx[k][e], sx, C(0)));
-            }
-          }
-        }
-#pragma unroll
-        for (int e = 0; e < 4; ++e) rvx[k][e] = nv[e];
-        st4(sVX + 4 * q, nv);
-      }
-      if (in_rows(fr, HR - at - K, HR + TZ + at + K - 1) && in_cols(gc, HS - at, HS + TX + at)) {
-        C nv[4] = {C(0), C(0), C(0), C(0)};
-        if (I >= 0 && I < NZ) {
-          C sz[4] = {C(0), C(0), C(0), C(0)};
-#pragma unroll
-          for (int m = 1; m <= K; ++m) {
-            C hi[4], lo[4];
-            ld4(hi, sP + (fr + m) * SC + 4 * gc);
-            ld4(lo, sP + (fr + 1 - m) * SC + 4 * gc);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) sz[e] = acc(sz[e], wst<K, C>(m - 1), hi[e], lo[e]);
-          }
-          const C az = pm.azh(I), bz = pm.bzh(I);
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            if (J + e >= 0 && J + e < NX) {
-              const C src = line_src_at<C, V>(a.vil, a.vi, vidx, a.nt, I, J + e, shot);
-              nv[e] = rnd<T>(upd_v<ADJ>(az, bz, cb, rvz[k][e], sz[e], src));
-            }
-          }
-        }
-#pragma unroll
-        for (int e = 0; e < 4; ++e) rvz[k][e] = nv[e];
-        st4(sVZ + 4 * q, nv);
-      }
-    }
-    __syncthreads();
-
-    // v_z-line sampling of v^{n+lv+1/2}
-    {
-      const int idx = a.ps.n + a.dir * lv;
-      if (a.ps.out && idx >= 0 && idx < a.nt && a.psl.row0 >= z0 && a.psl.row0 < z1 && tid < TX) {
-        const int J = x0 + tid;
-        if (J >= a.psl.col0 && J < a.psl.col0 + a.psl.ntr && J < NX) {
-          const int r0 = a.psl.row0 - z0 + HR, r1 = a.psl.row1 - z0 + HR;
-          const C val = C(a.psl.w0) * sVZ[r0 * SC + tid + HS] + C(a.psl.w1) * sVZ[r1 * SC + tid + HS];
-          line_out_at<C, V>(a.psl, a.ps, idx, J, shot, val);
-        }
-      }
-    }
-
-    // (c) p^{n+lv+1} on P_lv
-    const int pidx = a.pi.n + a.dir * lv;
-#pragma unroll
-    for (int k = 0; k < NQ; ++k) {
-      const int q = tid + 256 * k;
-      if (q >= NG) continue;
-      const int fr = q / NGR, gc = q - fr * NGR;
-      if (!(in_rows(fr, HR - at, HR + TZ + at) && in_cols(gc, HS - at, HS + TX + at))) continue;
-      const int I = z0 - HR + fr, J = x0 - HS + 4 * gc;
-      if (I < 0 || I >= NZ) continue;
-      C w[12];
-      ld4(*reinterpret_cast<C(*)[4]>(w), sVX + fr * SC + 4 * gc - 4);
-      ld4(*reinterpret_cast<C(*)[4]>(w + 4), sVX + fr * SC + 4 * gc);
-      ld4(*reinterpret_cast<C(*)[4]>(w + 8), sVX + fr * SC + 4 * gc + 4);
-      C dx[4] = {C(0), C(0), C(0), C(0)}, dz[4] = {C(0), C(0), C(0), C(0)};
-#pragma unroll
-      for (int m = 1; m <= K; ++m) {
-        C hi[4], lo[4];
-        ld4(hi, sVZ + (fr + m - 1) * SC + 4 * gc);
-        ld4(lo, sVZ + (fr - m) * SC + 4 * gc);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          dx[e] = acc(dx[e], wst<K, C>(m - 1), w[e + m + 3], w[e + 4 - m]);
-          dz[e] = acc(dz[e], wst<K, C>(m - 1), hi[e], lo[e]);
-        }
-      }
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int Je = J + e;
-        if (Je < 0 || Je >= NX) {
-          rp[k][e] = C(0);
-          continue;
-        }
-        const C src = line_src_at<C, V>(a.pil, a.pi, pidx, a.nt, I, Je, shot);
-        const bool frame = near_frame && (I < L || I >= NZ - L || Je < L || Je >= NX - L);
-        if (!frame) {
-          rp[k][e] = rnd<T>(upd_p<ADJ>(rck[k][e], rp[k][e], dx[e], dz[e], src));
-        } else {
-          C an;
-          rp[k][e] = rnd<T>(upd_p_frame<ADJ>(rck[k][e], rp[k][e], rau[k][e], dx[e], dz[e], src,
-                                             pm.axn(Je), pm.bxn(Je), pm.azn(I), pm.bzn(I), &an));
-          rau[k][e] = rnd<T>(an);
-        }
-      }
-    }
-  }
-
-  // ---- store the tile: p^{n+2}, v^{n+3/2}, layer auxiliary
-#pragma unroll
-  for (int k = 0; k < NQ; ++k) {
-    const int q = tid + 256 * k;
-    if (q >= NG) continue;
-    const int fr = q / NGR, gc = q - fr * NGR;
-    if (!(in_rows(fr, HR, HR + TZ) && in_cols(gc, HS, HS + TX))) continue;
-    const int I = z0 - HR + fr, J = x0 - HS + 4 * gc;
-    if (I >= NZ || J >= NX) continue;
-    const long long o = (long long)I * P + J;
-    if (J + 3 < NX) {
-      st4(pB + o, rp[k]);
-      st4(vxB + o, rvx[k]);
-      st4(vzB + o, rvz[k]);
-    } else {
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (J + e < NX) {
-          stc(pB + o + e, rp[k][e]);
-          stc(vxB + o + e, rvx[k][e]);
-          stc(vzB + o + e, rvz[k][e]);
-        }
-    }
-    if (near_frame) {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int Je = J + e;
-        if (Je < NX && (I < L || I >= NZ - L || Je < L || Je >= NX - L))
-          stc(auB + o + e, rau[k][e]);
-      }
-    }
-  }
-}
+// line sampling after the last forward step, and a fill kernel
 
 template <typename T>
 __global__ void k_sample_p(Fields f, GridDims g, LineDev sl, TraceIO so) {
@@ -1364,23 +1086,6 @@ void step_tile_lists(int order, int tz, const GridDims& g, const LineDev* const*
 
 hipError_t launch_step(Dt dt, int order, bool adj, int tz, int loop, StepArgs a, hipStream_t s) {
   SSX_DISPATCH(step_t, tz, loop, a, s);
-}
-
-template <int K, bool ADJ, typename T>
-static hipError_t step2_t(const StepArgs& a, hipStream_t s) {
-  if constexpr (!std::is_same<T, float>::value) {
-    // FP32 fields only: the 16-bit instances are not launched (a device
-    // memory fault was seen with them and its cause is not known)
-    return hipErrorInvalidValue;
-  } else {
-    const int nb = a.ntx * a.ntz * a.nshots;
-    hipLaunchKernelGGL((k_step2<K, ADJ, T>), dim3(nb), dim3(256), 0, s, a);
-    return hipGetLastError();
-  }
-}
-
-hipError_t launch_step2(Dt dt, int order, bool adj, StepArgs a, hipStream_t s) {
-  SSX_DISPATCH(step2_t, a, s);
 }
 
 int step_tile_width() { return TX; }

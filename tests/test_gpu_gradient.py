@@ -89,7 +89,7 @@ def test_gradient_independent_of_launch_options():
     for opt, val in ((None, None), (ssx.OPT_GRAPHS, 0), (ssx.OPT_GRAPHS, 1), (ssx.OPT_TILE_LOOP, 1),
                      (ssx.OPT_TILE_Z, 8), (ssx.OPT_TILE_Z, 32), (ssx.OPT_TILE_LOOP, 0),
                      (ssx.OPT_TILE_Z, 16), (ssx.OPT_SHOT_GROUP, 2),
-                     (ssx.OPT_STEPS_PER_LAUNCH, 2), (ssx.OPT_STEP_KERNEL, 0)):
+                     (ssx.OPT_STEP_KERNEL, 0)):
         if opt is not None:
             ctx.set_option(opt, val)
         g, J = ctx.misfit_gradient(h, d)

@@ -58,9 +58,9 @@ def run_all(ctx, prob, fd, seed=0):
 @pytest.mark.parametrize("fd", ["f64", "f32", "f16", "bf16"])
 @pytest.mark.parametrize("order,nt", [(4, 120), (8, 121)])
 def test_fused_equals_split_bitwise(fd, order, nt, geom):
-    # one-step fused kernel at every tile height, and (except FP64) the
-    # two-steps-per-launch kernel, against the split reference; an odd
-    # record length exercises the single-step remainder
+    # one-step fused kernel at every tile height against the split
+    # reference; an odd record length exercises the multi-step slab
+    # kernel's one-step remainder
     prob = problem(order, geom, nt=nt)
     print(f"case fused-vs-split order={order} nt={nt} dtype={fd} geom={geom}", flush=True)
     ctx = ssx.Context(prob, kappa(prob), RHO, field_dtype=fd)
@@ -82,17 +82,9 @@ def test_fused_equals_split_bitwise(fd, order, nt, geom):
             for a, b in zip(split, looped):
                 assert np.array_equal(a, b), (fd, order, tz, "tile loop", loop)
         ctx.set_option(ssx.OPT_TILE_LOOP, 0)
-    if fd == "f32":
-        ctx.set_option(ssx.OPT_TILE_Z, 16)
+    # the full grid takes one step per launch only
+    with pytest.raises(ssx.SSXError):
         ctx.set_option(ssx.OPT_STEPS_PER_LAUNCH, 2)
-        two = run_all(ctx, prob, fd)
-        for i, (a, b) in enumerate(zip(split, two)):
-            assert np.array_equal(a, b), (fd, order, "two steps per launch", i)
-        ctx.set_option(ssx.OPT_STEPS_PER_LAUNCH, 1)
-    else:
-        # two steps per launch are switched off for FP64 and 16-bit fields
-        with pytest.raises(ssx.SSXError):
-            ctx.set_option(ssx.OPT_STEPS_PER_LAUNCH, 2)
     if fd != "f64":
         # slab strips held in LDS over 4 or 8 steps (the odd record leaves a
         # one-step remainder)
