@@ -13,7 +13,11 @@ Extended Surface Sources" (arXiv 2203.16573) that it follows:
              staggered scheme of order 2 in time, 2k in space);
 * ``grid``   padded grid, PML profiles, line sampling (same passage);
 * ``prop``   forward time stepping and its exact transpose (Operators
-             section; Appendix A);
+             section; Appendix A), with constant density or a density
+             array (the operators carry both kappa and rho);
+* ``cengine`` the same time stepping as plain C loops (``cprop.c``,
+             constant density), bitwise equal to ``prop``, for the
+             full-length runs of the large grids;
 * ``ops``    F, F^T, the penalty A, the thin-slab preconditioner, the normal
              operator and Algorithm 1, the weighted normal equations with
              their data- and model-space weights, V, the time-reversal
@@ -31,7 +35,10 @@ energy transmission coefficient that the weighted composition and the
 time-reversal inverse reduce to, and the exact 1D form of the sv relation),
 polynomial exactness of the stencils, dense normal-equation solves, the
 gradient of the weighted objective, central differences of the misfit in
-kappa and Krylov-subspace optimality.
+kappa and Krylov-subspace optimality; with variable density, the dot test,
+energy conservation and the reflection and transmission coefficients of a
+density-only impedance jump at second order.  The C engine is pinned by
+equality with ``prop`` on every operator and by its own dot test.
 """
 from . import fd, grid, prop, ops, greens  # noqa: F401
 from .ops import (Model, pcg, pcg_solve, precond, penalty, dscale, normal,  # noqa: F401

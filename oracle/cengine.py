@@ -80,6 +80,8 @@ class _Ctx:
     """Contiguous FP64 copies of one grid's coefficients, kept alive for a call."""
 
     def __init__(self, g):
+        if getattr(g, "variable_rho", False):
+            raise ValueError("the C engine takes constant density only")
         self.keep = []
         self.c = np.ascontiguousarray(fd.stencil(g.order), dtype=np.float64)
         self.Cb = g.dt / (g.rho * g.h)

@@ -9,6 +9,12 @@ layer parameters):
 
 * the absorbing layer of L cells is added outside the stated physical grid;
   the model is extended into it by copying the nearest physical value;
+* density may vary (the operators of the paper carry both kappa and rho):
+  rho is given at the pressure nodes and each velocity update uses, at its
+  own half node, the mean of the density at its two nodes (the mean density
+  of the cell between them, which the momentum equation integrated over
+  that cell needs when a jump lies between the nodes); a half node beyond
+  the last node takes that node's value;
 * it is a split-field PML with profile sigma(d) = sigma_max (d / (L h))^2,
   d the distance into the layer, sigma_max = 3 c_max ln(1/R) / (2 L h);
 * a field subject to damping sigma advances as
@@ -56,18 +62,36 @@ class Grid:
     """A padded computational grid: physical nz x nx nodes plus L cells of
     absorbing layer on each side."""
 
-    def __init__(self, kappa_phys: np.ndarray, rho: float, h: float, dt: float,
+    def __init__(self, kappa_phys: np.ndarray, rho, h: float, dt: float,
                  npml: int, pml_R: float, order: int):
+        """rho: a constant density or an array [nz][nx] at the physical
+        nodes."""
         kappa_phys = np.asarray(kappa_phys, dtype=np.float64)
         self.nz, self.nx = kappa_phys.shape
-        self.h, self.dt, self.rho = float(h), float(dt), float(rho)
+        self.h, self.dt = float(h), float(dt)
         self.L = int(npml)
         self.order = int(order)
         L = self.L
         self.NZ, self.NX = self.nz + 2 * L, self.nx + 2 * L
         # edge replication of the model into the layer
         self.kappa = np.pad(kappa_phys, L, mode="edge")
-        cmax = float(np.sqrt(kappa_phys.max() / self.rho))
+        if np.ndim(rho) == 0:
+            self.rho = float(rho)
+            self.variable_rho = False
+            cmax = float(np.sqrt(kappa_phys.max() / self.rho))
+        else:
+            rho_phys = np.asarray(rho, dtype=np.float64)
+            if rho_phys.shape != kappa_phys.shape:
+                raise ValueError("rho must be a scalar or an array shaped like kappa")
+            self.variable_rho = True
+            self.rho = r = np.pad(rho_phys, L, mode="edge")
+            # density at (i, j+1/2) and (i+1/2, j): mean of the two nodes;
+            # the velocity updates use its reciprocal (the buoyancy)
+            rnx = np.concatenate([r[:, 1:], r[:, -1:]], axis=1)
+            rnz = np.concatenate([r[1:, :], r[-1:, :]], axis=0)
+            self.bx = 1.0 / (0.5 * (r + rnx))
+            self.bz = 1.0 / (0.5 * (r + rnz))
+            cmax = float(np.sqrt((kappa_phys / rho_phys).max()))
         self.cmax = cmax
         if L > 0:
             smax = 3.0 * cmax * math.log(1.0 / pml_R) / (2.0 * L * h)

@@ -64,7 +64,8 @@ class Model:
             self._forward, self._adjoint = cengine.forward, cengine.adjoint
         else:
             raise ValueError(f"unknown oracle engine {engine!r}")
-        self.rho = float(rho)
+        # constant density, or an array [nz][nx] at the pressure nodes
+        self.rho = float(rho) if np.ndim(rho) == 0 else np.asarray(rho, dtype=np.float64)
         kappa = np.asarray(kappa, dtype=np.float64)
         if kappa.shape != (prob.nz, prob.nx):
             raise ValueError("kappa must be [nz][nx]")
@@ -95,7 +96,8 @@ class Model:
         i_lo = min(i_s, i_s + dz) - k
         i_hi = max(i_s, i_s + dz) + k + (1 if z / prob.h - i_s > 1e-12 else 0)
         rows = np.clip(np.arange(i_lo, i_hi + 1), 0, prob.nz - 1)
-        g = Grid(self.kappa[rows, :], self.rho, prob.h, prob.dt, prob.npml, prob.pml_R,
+        rho = self.rho if np.ndim(self.rho) == 0 else self.rho[rows, :]
+        g = Grid(self.kappa[rows, :], rho, prob.h, prob.dt, prob.npml, prob.pml_R,
                  prob.order)
         zl = z - i_lo * prob.h
         zd = zl + dz * prob.h

@@ -34,14 +34,21 @@ from .grid import Grid, Line
 
 
 def _coefs(g: Grid):
+    """Stencil, velocity coefficients (dt/rho) (1/h) for v_x and v_z (one
+    scalar for constant density; arrays of the buoyancy at each velocity's
+    own half node otherwise), Ck and the layer factors."""
     c = fd.stencil(g.order)
-    Cb = g.dt / (g.rho * g.h)        # (dt/rho) * (1/h)
+    if not getattr(g, "variable_rho", False):
+        Cbx = Cbz = g.dt / (g.rho * g.h)     # (dt/rho) * (1/h)
+    else:
+        Cbx = g.dt * g.bx / g.h               # dt b_x * (1/h)
+        Cbz = g.dt * g.bz / g.h
     Ck = g.dt * g.kappa / g.h        # dt kappa * (1/h)
     ax_n, bx_n = g.ax_n[None, :], g.bx_n[None, :]
     ax_h, bx_h = g.ax_h[None, :], g.bx_h[None, :]
     az_n, bz_n = g.az_n[:, None], g.bz_n[:, None]
     az_h, bz_h = g.az_h[:, None], g.bz_h[:, None]
-    return c, Cb, Ck, (ax_n, bx_n, ax_h, bx_h, az_n, bz_n, az_h, bz_h)
+    return c, (Cbx, Cbz), Ck, (ax_n, bx_n, ax_h, bx_h, az_n, bz_n, az_h, bz_h)
 
 
 def forward(g: Grid, nt: int, h_src=None, f_src=None, rec_p=None, rec_v=None,
@@ -55,24 +62,28 @@ def forward(g: Grid, nt: int, h_src=None, f_src=None, rec_p=None, rec_v=None,
     pressure update multiplies by Ck, D^- v^{n+1/2} - E_h h^n (the layer's
     split parts summed).
     Returns (P [nt][n_p] or None, V [nt][n_v] or None[, energy list])."""
-    c, Cb, Ck, (ax_n, bx_n, ax_h, bx_h, az_n, bz_n, az_h, bz_h) = _coefs(g)
+    c, (Cbx, Cbz), Ck, (ax_n, bx_n, ax_h, bx_h, az_n, bz_n, az_h, bz_h) = _coefs(g)
     shp = (g.NZ, g.NX)
     vx, vz, px, pz = (np.zeros(shp) for _ in range(4))
+    # density at the velocity nodes, for the energy: rho_x = 1/b_x
+    rho_x = 1.0 / g.bx if getattr(g, "variable_rho", False) else g.rho
+    rho_z = 1.0 / g.bz if getattr(g, "variable_rho", False) else g.rho
     P = np.zeros((nt, len(rec_p.cols))) if rec_p is not None else None
     V = np.zeros((nt, len(rec_v.cols))) if rec_v is not None else None
     E = []
     for n in range(nt):
         p = px + pz
         vx_old, vz_old = vx, vz
-        vx = ax_h * vx - bx_h * Cb * fd.dplus(p, c, axis=1)
+        vx = ax_h * vx - bx_h * Cbx * fd.dplus(p, c, axis=1)
         gz = fd.dplus(p, c, axis=0)
         if f_src is not None:
             f_src[0].spread_add(f_src[1][n], gz, -1.0)   # D_z^+ p - E_f f (h folded)
-        vz = az_h * vz - bz_h * Cb * gz
+        vz = az_h * vz - bz_h * Cbz * gz
         if energy:
             # E^{n-1/2}... recorded as 1/2 sum rho v^{n-1/2} v^{n+1/2}
-            # + 1/2 sum p^n p^n / kappa (conserved for sigma = 0)
-            E.append(0.5 * g.rho * np.sum(vx_old * vx + vz_old * vz)
+            # + 1/2 sum p^n p^n / kappa (conserved for sigma = 0), rho at
+            # each velocity's own node
+            E.append(0.5 * np.sum(rho_x * vx_old * vx + rho_z * vz_old * vz)
                      + 0.5 * np.sum(p * p / g.kappa))
         px = ax_n * px - bx_n * Ck * fd.dminus(vx, c, axis=1)
         dz = fd.dminus(vz, c, axis=0)
@@ -100,7 +111,7 @@ def adjoint(g: Grid, nt: int, h_line: Line = None, f_line: Line = None,
     of p_x^{n+1} and p_z^{n+1} (the recording of step n included), before
     the transposed pressure update of step n.
     Returns (hbar [nt][n_h] or None, fbar [nt][n_f] or None)."""
-    c, Cb, Ck, (ax_n, bx_n, ax_h, bx_h, az_n, bz_n, az_h, bz_h) = _coefs(g)
+    c, (Cbx, Cbz), Ck, (ax_n, bx_n, ax_h, bx_h, az_n, bz_n, az_h, bz_h) = _coefs(g)
     shp = (g.NZ, g.NX)
     vxb, vzb, pxb, pzb = (np.zeros(shp) for _ in range(4))
     hb = np.zeros((nt, len(h_line.cols))) if h_line is not None else None
@@ -123,9 +134,9 @@ def adjoint(g: Grid, nt: int, h_line: Line = None, f_line: Line = None,
         pzb = az_n * pzb
         # v_z update: vz' = az_h vz - bz_h Cb D_z^+ p + bz_h Cb E_f f
         if fb is not None:
-            fb[n] = f_line.gather(bz_h * Cb * vzb)
-        t = -(fd.dplus_T(bx_h * Cb * vxb, c, axis=1)
-              + fd.dplus_T(bz_h * Cb * vzb, c, axis=0))
+            fb[n] = f_line.gather(bz_h * Cbz * vzb)
+        t = -(fd.dplus_T(bx_h * Cbx * vxb, c, axis=1)
+              + fd.dplus_T(bz_h * Cbz * vzb, c, axis=0))
         pxb = pxb + t
         pzb = pzb + t
         vxb = ax_h * vxb

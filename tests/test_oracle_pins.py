@@ -830,3 +830,106 @@ def test_normal_load_subproblem_converges_to_dense_solution():
     assert abs(al - alpha) <= 1e-15 * alpha
     assert np.linalg.norm(h.ravel() - hstar) <= 1e-8 * np.linalg.norm(hstar)
     assert abs(hist[-1, 3] - np.linalg.norm(m.fwd_v(h) - d)) <= 1e-10 * np.linalg.norm(d)
+
+
+# ---------------------------------------------------------------------------
+# Variable density (the operators of the Operators section carry kappa and
+# rho): rho at the pressure nodes, buoyancy at the velocity half nodes as the
+# mean of 1/rho at the two nodes.
+
+def _rho_field(prob, seed=3):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(800.0, 2600.0, size=(prob.nz, prob.nx))
+
+
+@pytest.mark.parametrize("order", [4, 8])
+def test_variable_density_dot_products(order):
+    prob = tiny_problem(order=order, nz=14, nx=18, L=4, nt=40)
+    m = oracle.Model(prob, tiny_kappa(prob), _rho_field(prob))
+    rng = np.random.default_rng(order)
+    x = rng.standard_normal((prob.nt, prob.ns))
+    y = rng.standard_normal((prob.nt, prob.nr))
+    Fx, Fty = m.fwd(x), m.adj(y)
+    assert abs(np.sum(Fx * y) - np.sum(x * Fty)) <= 1e-13 * np.linalg.norm(Fx) * np.linalg.norm(y)
+    a = rng.standard_normal((prob.nt, prob.ns))
+    b = rng.standard_normal((prob.nt, prob.ns))
+    P, V = m.slab_fwd(x)
+    lhs = np.sum(P * a) + np.sum(V * b)
+    rhs = np.sum(x * m.slab_adj(a, b))
+    assert abs(lhs - rhs) <= 1e-13 * np.sqrt(np.sum(P * P) + np.sum(V * V)) * np.sqrt(
+        np.sum(a * a) + np.sum(b * b))
+
+
+def test_variable_density_energy_conserved():
+    # no absorbing layer, the source off after its first samples: the
+    # discrete energy with rho at each velocity's own node is constant
+    prob = tiny_problem(order=8, nz=20, nx=24, L=0, nt=160, z_src=95.0, z_rec=150.0,
+                        ns=10, nr=12)
+    rho = _rho_field(prob, 5)
+    g = Grid(tiny_kappa(prob), rho, prob.h, prob.dt, 0, prob.pml_R, prob.order)
+    src = np.zeros((prob.nt, prob.ns))
+    src[:6] = np.random.default_rng(2).standard_normal((6, prob.ns))
+    _, _, E = forward(g, prob.nt, h_src=(g.p_line(prob.z_src, prob.x_src0, prob.ns), src),
+                      energy=True)
+    E = np.array(E[8:])
+    assert np.max(np.abs(E - E[0])) <= 1e-13 * abs(E[0])
+
+
+def test_constant_density_array_equals_scalar():
+    prob = tiny_problem(order=8)
+    kap = tiny_kappa(prob)
+    ms = oracle.Model(prob, kap, RHO)
+    ma = oracle.Model(prob, kap, np.full((prob.nz, prob.nx), RHO))
+    x = np.random.default_rng(4).standard_normal((prob.nt, prob.ns))
+    for a, b in ((ma.fwd(x), ms.fwd(x)), (ma.winv(x), ms.winv(x))):
+        assert np.abs(a - b).max() <= 1e-14 * np.abs(b).max()
+
+
+def _density_jump_error(h, below):
+    # a laterally uniform pressure source at 200 m in c = 2000 m/s, density
+    # 1000 on the nodes above 400 m and 2500 from 400 m down (impedances Z1,
+    # Z2 = 2.5 Z1), so that the continuum interface lies midway between the
+    # last node of one density and the first of the other, z_i = 400 - h/2:
+    # receivers at 100 m see the direct wave (rho1 c / 2) w(t - tau_d) and
+    # its reflection R times it, R = (Z2 - Z1) / (Z2 + Z1); receivers at
+    # 500 m the transmitted wave T (rho1 c / 2) w(t - tau_t), T = 2 Z2 /
+    # (Z1 + Z2) (pressure, normal incidence)
+    c, f, rho1, rho2 = 2000.0, 10.0, 1000.0, 2500.0
+    nz, nx = int(700 / h), int(2000 / h) + 1
+    dt = 0.25 * h / c
+    nt = int(0.42 / dt)
+    z_rec = 500.0 if below else 100.0
+    prob = inputs.Problem(nz=nz, nx=nx, h=h, dt=dt, nt=nt, order=8, npml=20,
+                          z_src=200.0, x_src0=0.0, ns=nx, z_rec=z_rec, x_rec0=0.0, nr=nx,
+                          slab_dz=5, xs=(1000.0,))
+    zi = int(round(400.0 / h))
+    rho = np.full((nz, nx), rho1)
+    rho[zi:, :] = rho2
+    kappa = rho * c * c
+    m = oracle.Model(prob, kappa, rho)
+    w = inputs.ricker((np.arange(nt) + 0.5) * dt, f)
+    d = m.fwd(np.repeat(w[:, None], nx, axis=1))[:, nx // 2]
+    t = (np.arange(nt) + 1) * dt
+    Z1, Z2 = rho1 * c, rho2 * c
+    amp = 0.5 * rho1 * c
+    z_int = (zi - 0.5) * h
+    if below:
+        expect = (2 * Z2 / (Z1 + Z2)) * amp * inputs.ricker(t - (z_rec - 200.0) / c, f)
+    else:
+        R = (Z2 - Z1) / (Z2 + Z1)
+        expect = amp * (inputs.ricker(t - (200.0 - z_rec) / c, f)
+                        + R * inputs.ricker(t - (2 * z_int - 200.0 - z_rec) / c, f))
+    return np.abs(d - expect).max() / np.abs(expect).max()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("below", [False, True])
+def test_plane_wave_density_jump(below):
+    # reflection and transmission at a density-only impedance jump (same
+    # velocity on both sides), at second order as the grid is refined (the
+    # mean of the two node densities at a velocity half node; the mean of
+    # their reciprocals converges at first order only)
+    e10 = _density_jump_error(10.0, below)
+    e5 = _density_jump_error(5.0, below)
+    assert e5 < 5e-3, (e10, e5)
+    assert math.log2(e10 / e5) > 1.6, (e10, e5)
