@@ -128,7 +128,8 @@ ssx_status ssx_validate(const ssx_problem* prob, const double* kappa_host, doubl
 size_t ssx_footprint(const ssx_problem* prob);
 
 /* Create a context.  kappa_host: HOST array [nz][nx] of bulk modulus (Pa),
- * read during the call only; rho: constant density (kg/m^3); xs_host: HOST
+ * read during the call only; rho: constant density (kg/m^3) (see
+ * ssx_create_density for a density array); xs_host: HOST
  * array [nshots] of the physical point of each shot (lateral position, m).
  * stream: hipStream_t for all work of this context (NULL = default stream).
  * workspace: optional DEVICE buffer of at least ssx_footprint(prob) bytes,
@@ -138,6 +139,19 @@ size_t ssx_footprint(const ssx_problem* prob);
 ssx_status ssx_create(const ssx_problem* prob, const double* kappa_host, double rho,
                       const double* xs_host, void* stream, void* workspace,
                       size_t workspace_bytes, ssx_ctx** out);
+
+/* The same for a model with variable density (the operators of the paper
+ * carry both kappa and rho): rho_host, HOST array [nz][nx] of density at
+ * the pressure nodes (kg/m^3), read during the call only.  Each velocity
+ * update uses the mean density of its two nodes (a half node beyond the
+ * last node takes that node's value); the stability bound uses the largest
+ * sqrt(kappa / rho).  Such a context runs the split kernels or the fused
+ * one-step kernel with one tile per workgroup: SSX_OPT_TILE_LOOP and 4 or
+ * 8 slab steps per launch return SSX_ERR_ARG.  SSX_ERR_ARG for a null
+ * rho_host or non-finite or non-positive values. */
+ssx_status ssx_create_density(const ssx_problem* prob, const double* kappa_host,
+                              const double* rho_host, const double* xs_host, void* stream,
+                              void* workspace, size_t workspace_bytes, ssx_ctx** out);
 
 /* Release the context (waits for its stream).  NULL is ignored. */
 void ssx_destroy(ssx_ctx* ctx);

@@ -58,7 +58,7 @@ EXPORTS = ("ssx_validate", "ssx_footprint", "ssx_create", "ssx_destroy", "ssx_fw
            "ssx_step_kernel_name", "ssx_cells_per_launch", "ssx_launch_shape",
            "ssx_weight_d", "ssx_weight_m", "ssx_normal_w", "ssx_pcg_solve_w",
            "ssx_fwd_v", "ssx_adj_v", "ssx_tr_inverse", "ssx_lambda", "ssx_block",
-           "ssx_misfit_gradient", "ssx_pcg_solve_v", "ssx_dot_static")
+           "ssx_misfit_gradient", "ssx_pcg_solve_v", "ssx_dot_static", "ssx_create_density")
 
 DOT_STATIC_MAX_SHOTS = 64  # SSX_DOT_STATIC_MAX_SHOTS
 
@@ -103,6 +103,8 @@ def lib():
         L.ssx_footprint.restype = ctypes.c_size_t
         L.ssx_create.argtypes = [P, dp, c_dbl, dp, vp, vp, ctypes.c_size_t,
                                  ctypes.POINTER(vp)]
+        L.ssx_create_density.argtypes = [P, dp, dp, dp, vp, vp, ctypes.c_size_t,
+                                         ctypes.POINTER(vp)]
         L.ssx_destroy.argtypes = [vp]
         L.ssx_destroy.restype = None
         L.ssx_fwd.argtypes = [vp, vp, vp]
@@ -207,7 +209,7 @@ def dot_static(x, y, nshots: int, out=None, stream=None):
 class Context:
     """An ssx_ctx bound to a torch device stream (the current stream by default)."""
 
-    def __init__(self, prob, kappa, rho: float, xs=None, field_dtype: str = "f32",
+    def __init__(self, prob, kappa, rho, xs=None, field_dtype: str = "f32",
                  stream=None, workspace=None):
         import torch
 
@@ -225,9 +227,19 @@ class Context:
         if workspace is not None:
             ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
         self._workspace = workspace
-        _check(lib().ssx_create(ctypes.byref(self._P), _dptr(k), float(rho), _dptr(xsa),
-                                ctypes.c_void_p(self.stream.cuda_stream), ws_ptr, ws_bytes,
-                                ctypes.byref(ctx)))
+        if np.ndim(rho) == 0:
+            _check(lib().ssx_create(ctypes.byref(self._P), _dptr(k), float(rho), _dptr(xsa),
+                                    ctypes.c_void_p(self.stream.cuda_stream), ws_ptr, ws_bytes,
+                                    ctypes.byref(ctx)))
+        else:
+            # density at every node: [nz][nx]
+            r = np.ascontiguousarray(rho, dtype=np.float64)
+            if r.shape != k.shape:
+                raise ValueError("rho must be a scalar or an array shaped like kappa")
+            _check(lib().ssx_create_density(ctypes.byref(self._P), _dptr(k), _dptr(r),
+                                            _dptr(xsa),
+                                            ctypes.c_void_p(self.stream.cuda_stream), ws_ptr,
+                                            ws_bytes, ctypes.byref(ctx)))
         self._ctx = ctx
 
     # -- helpers --------------------------------------------------------------

@@ -182,6 +182,32 @@ ssx_status check_model(const ssx_problem& p, const double* kappa, double rho, do
   return SSX_OK;
 }
 
+// Variable density: checks rho like kappa and returns the largest velocity
+// sqrt(kappa / rho) and impedance sqrt(kappa rho) of the model.
+ssx_status check_model_density(const ssx_problem& p, const double* kappa, const double* rho,
+                               double* cmax, double* zmax) {
+  double c2 = 0, z2 = 0;
+  const size_t n = (size_t)p.nz * p.nx;
+  for (size_t i = 0; i < n; ++i) {
+    const double k = kappa[i], r = rho[i];
+    if (!std::isfinite(k) || !(k > 0)) return fail(SSX_ERR_ARG, "kappa must be finite and > 0");
+    if (!std::isfinite(r) || !(r > 0)) return fail(SSX_ERR_ARG, "rho must be finite and > 0");
+    c2 = std::max(c2, k / r);
+    z2 = std::max(z2, k * r);
+  }
+  *cmax = std::sqrt(c2);
+  *zmax = std::sqrt(z2);
+  const double bound = 1.0 / (std::sqrt(2.0) * stencil_abs_sum(p.order));
+  const double courant = *cmax * p.dt / p.h;
+  if (courant > bound) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "Courant number %.4f above the stability bound %.4f",
+                  courant, bound);
+    return fail(SSX_ERR_CFL, buf);
+  }
+  return SSX_OK;
+}
+
 // Host-side description of one padded grid and its FP64 coefficients.
 struct GridHost {
   int nz, nx, L, NZ, NX, pitch;
@@ -189,12 +215,15 @@ struct GridHost {
   long long origin;
   std::vector<double> ck;   // laid out like a field (zero ghosts)
   std::vector<double> pml;  // x arrays of length pitch (origin GX), then z arrays
+  // variable density: Z0 dt / (rho h) at the v_x and v_z cells, rho there
+  // the mean of its two nodes; laid out like ck (empty: constant density)
+  std::vector<double> cbx, cbz;
 };
 
 int grid_pitch(int NX) { return ((NX + 2 * GX + 8) + 63) / 64 * 64; }
 
 void build_grid(const ssx_problem& p, const std::vector<double>& kphys, int nz, double Z0,
-                double rho, GridHost* g) {
+                double rho, GridHost* g, const std::vector<double>* rphys = nullptr) {
   const int L = p.npml, nx = p.nx;
   g->nz = nz;
   g->nx = nx;
@@ -218,7 +247,31 @@ void build_grid(const ssx_problem& p, const std::vector<double>& kphys, int nz, 
   }
   // PML: sigma(d) = smax (d / L)^2, d = cells into the layer;
   // a = (1 - sigma dt / 2) / (1 + sigma dt / 2), b = 1 / (1 + sigma dt / 2)
-  const double cmax = std::sqrt(kmax / rho);
+  double cmax = rphys ? 0.0 : std::sqrt(kmax / rho);
+  if (rphys) {
+    // variable density (padded by copying the nearest physical value): the
+    // velocity coefficients at v_x (I, J+1/2) and v_z (I+1/2, J) from the
+    // mean density of their two nodes (the last node's own beyond it)
+    auto rho_at = [&](int I, int J) {
+      const int i = std::min(std::max(I - L, 0), nz - 1);
+      const int j = std::min(std::max(J - L, 0), nx - 1);
+      return (*rphys)[(size_t)i * nx + j];
+    };
+    for (size_t q = 0; q < (size_t)nz * nx; ++q)
+      cmax = std::max(cmax, std::sqrt(kphys[q] / (*rphys)[q]));
+    g->cbx.assign((size_t)g->field_elems, 0.0);
+    g->cbz.assign((size_t)g->field_elems, 0.0);
+    for (int I = 0; I < g->NZ; ++I) {
+      for (int J = 0; J < g->NX; ++J) {
+        const double r0 = rho_at(I, J);
+        const double rx = 0.5 * (r0 + rho_at(I, std::min(J + 1, g->NX - 1)));
+        const double rz = 0.5 * (r0 + rho_at(std::min(I + 1, g->NZ - 1), J));
+        const size_t o = (size_t)(g->origin + (long long)I * g->pitch + J);
+        g->cbx[o] = Z0 * p.dt / (rx * p.h);
+        g->cbz[o] = Z0 * p.dt / (rz * p.h);
+      }
+    }
+  }
   const double smax = L > 0 ? 3.0 * cmax * std::log(1.0 / p.pml_R) / (2.0 * L * p.h) : 0.0;
   auto ab = [&](double pos, int nphys, double* a, double* b) {
     double d = std::max(std::max((double)L - pos, pos - (double)(L + nphys - 1)), 0.0);
@@ -277,6 +330,10 @@ struct GridDev {
   std::vector<int> tiles_host[3];
   int ngen[3] = {0, 0, 0}, nint[3] = {0, 0, 0};
   int* tiles_dev[3] = {nullptr, nullptr, nullptr};
+  // variable density: device copies of the velocity coefficient arrays
+  // (allocated for every context, used when the model has a density array)
+  void* cbx_dev = nullptr;
+  void* cbz_dev = nullptr;
 };
 
 // A captured propagation: keyed by the operation and every trace pointer it
@@ -296,6 +353,7 @@ struct ssx_ctx {
   size_t fsz, csz, vsz;
   hipStream_t stream;
   double rho, Z0;
+  bool vrho = false;  // density given as an array (velocity coefficients per cell)
   GridDev full, slab;
   LineDev h_line, r_line, f_line, dp_line, dv_line;
   // source-side slab: pressure line at z_s (W_m); receiver-side slab (W_d,
@@ -372,6 +430,8 @@ void layout(ssx_ctx* c, const GridHost& fg, const GridHost& sg, const GridHost* 
     gd.amax_part = (float*)a.take((size_t)2 * ns * NBLK_DOT * 4);
     gd.coef.ck = a.take((size_t)gh.field_elems * csz);
     gd.coef.pml = a.take((4 * (size_t)gh.pitch + 4 * (size_t)(gh.NZ + 2 * PZ)) * csz);
+    gd.cbx_dev = a.take((size_t)gh.field_elems * csz);
+    gd.cbz_dev = a.take((size_t)gh.field_elems * csz);
     for (int i = 0; i < 3; ++i) {
       const int tz = 8 << i;
       const size_t n = (size_t)((gh.NX + step_tile_width() - 1) / step_tile_width()) *
@@ -398,20 +458,30 @@ void layout(ssx_ctx* c, const GridHost& fg, const GridHost& sg, const GridHost* 
 
 ssx_status upload(GridDev& gd, bool dbl, hipStream_t s) {
   const GridHost& g = gd.host;
-  if (dbl) {
-    SSX_HIP(hipMemcpyAsync(const_cast<void*>(gd.coef.ck), g.ck.data(), g.ck.size() * 8,
-                           hipMemcpyHostToDevice, s));
-    SSX_HIP(hipMemcpyAsync(const_cast<void*>(gd.coef.pml), g.pml.data(), g.pml.size() * 8,
-                           hipMemcpyHostToDevice, s));
-    SSX_HIP(hipStreamSynchronize(s));
+  // FP64 arrays as they are, else cast once to FP32
+  auto put = [&](const void* dst, const std::vector<double>& src) -> ssx_status {
+    if (dbl) {
+      SSX_HIP(hipMemcpyAsync(const_cast<void*>(dst), src.data(), src.size() * 8,
+                             hipMemcpyHostToDevice, s));
+    } else {
+      std::vector<float> f(src.begin(), src.end());
+      SSX_HIP(hipMemcpyAsync(const_cast<void*>(dst), f.data(), f.size() * 4,
+                             hipMemcpyHostToDevice, s));
+      SSX_HIP(hipStreamSynchronize(s));  // before f goes out of scope
+    }
+    return SSX_OK;
+  };
+  SSX_TRY(put(gd.coef.ck, g.ck));
+  SSX_TRY(put(gd.coef.pml, g.pml));
+  if (!g.cbx.empty()) {
+    SSX_TRY(put(gd.cbx_dev, g.cbx));
+    SSX_TRY(put(gd.cbz_dev, g.cbz));
+    gd.coef.cbx = gd.cbx_dev;
+    gd.coef.cbz = gd.cbz_dev;
   } else {
-    std::vector<float> ck(g.ck.begin(), g.ck.end()), pml(g.pml.begin(), g.pml.end());
-    SSX_HIP(hipMemcpyAsync(const_cast<void*>(gd.coef.ck), ck.data(), ck.size() * 4,
-                           hipMemcpyHostToDevice, s));
-    SSX_HIP(hipMemcpyAsync(const_cast<void*>(gd.coef.pml), pml.data(), pml.size() * 4,
-                           hipMemcpyHostToDevice, s));
-    SSX_HIP(hipStreamSynchronize(s));
+    gd.coef.cbx = gd.coef.cbz = nullptr;
   }
+  SSX_HIP(hipStreamSynchronize(s));
   for (int i = 0; i < 3; ++i) {
     if (gd.tiles_host[i].empty()) continue;
     SSX_HIP(hipMemcpyAsync(gd.tiles_dev[i], gd.tiles_host[i].data(),
@@ -1018,8 +1088,10 @@ ssx_status issue_gradient(ssx_ctx* c, const void* h, const void* d, void* g, hip
   auto hist_at = [&](int n, int s0) {
     return (char*)c->ghist + ((size_t)n * p.nshots + s0) * cells * c->fsz;
   };
-  // the fused step kernel stores r^n itself; the split kernels leave it to
-  // a kernel of its own after every step
+  // the fused step kernel stores r^n itself (constant density); the split
+  // kernels, and the fused ones with a density array, leave it to a kernel
+  // of its own after every step
+  const bool hist_fused = c->fused && !c->vrho;
   const GroupHist hist = [&](int n, int s0) -> void* { return hist_at(n, s0); };
   const GroupHook store = [&](int n, const Fields& f, const Fields*, int s0,
                               int gs) -> ssx_status {
@@ -1031,7 +1103,7 @@ ssx_status issue_gradient(ssx_ctx* c, const void* h, const void* d, void* g, hip
   };
   SSX_TRY(issue_propagation(c, c->full, false, c->r_line, io_out(c->Fp, nr_, c->Z0), c->r_line,
                             io_none(), c->r_line, io_none(), c->h_line, io_in(h, ns_, 1.0), s,
-                            c->fused ? nullptr : &store, c->fused ? &hist : nullptr));
+                            hist_fused ? nullptr : &store, hist_fused ? &hist : nullptr));
   SSX_HIP(launch_sub(c->vdbl, c->Fp, d, c->e, nr_, p.nshots, s));
   SSX_HIP(launch_dot1(c->vdbl, c->e, c->e, nr_, p.nshots, c->partial, c->sc + SC_TMP, SC_N, s));
   SSX_HIP(launch_zero(c->gacc, (size_t)p.nshots * cells * sizeof(double), s));
@@ -1145,15 +1217,20 @@ size_t ssx_footprint(const ssx_problem* prob) {
   return total;
 }
 
-ssx_status ssx_create(const ssx_problem* prob, const double* kappa_host, double rho,
-                      const double* xs_host, void* stream, void* workspace,
-                      size_t workspace_bytes, ssx_ctx** out) {
+// ssx_create (rho_host null: constant density rho) and ssx_create_density
+// (rho_host: density at every node).
+static ssx_status create_impl(const ssx_problem* prob, const double* kappa_host, double rho,
+                              const double* rho_host, const double* xs_host, void* stream,
+                              void* workspace, size_t workspace_bytes, ssx_ctx** out) {
   if (!out) return fail(SSX_ERR_ARG, "out is NULL");
   *out = nullptr;
   SSX_TRY(check_problem(prob));
   if (!kappa_host || !xs_host) return fail(SSX_ERR_ARG, "kappa_host and xs_host are required");
-  double cmax;
-  SSX_TRY(check_model(*prob, kappa_host, rho, &cmax));
+  double cmax, zmax = 0.0;
+  if (rho_host)
+    SSX_TRY(check_model_density(*prob, kappa_host, rho_host, &cmax, &zmax));
+  else
+    SSX_TRY(check_model(*prob, kappa_host, rho, &cmax));
   for (int s = 0; s < prob->nshots; ++s)
     if (!std::isfinite(xs_host[s])) return fail(SSX_ERR_ARG, "xs must be finite");
 
@@ -1167,24 +1244,37 @@ ssx_status ssx_create(const ssx_problem* prob, const double* kappa_host, double 
   c->vsz = dtype_size(p.vec_dtype);
   c->stream = (hipStream_t)stream;
   c->run = c->stream;
-  c->rho = rho;
-  c->Z0 = rho * cmax;
+  c->vrho = rho_host != nullptr;
+  c->rho = c->vrho ? 0.0 : rho;
+  // reference impedance of the stored fields' scaling: rho c_max, or the
+  // largest impedance of a density array
+  c->Z0 = c->vrho ? zmax : rho * cmax;
 
   std::vector<double> kphys(kappa_host, kappa_host + (size_t)p.nz * p.nx);
-  build_grid(p, kphys, p.nz, c->Z0, rho, &c->full.host);
+  std::vector<double> rphys;
+  if (c->vrho) rphys.assign(rho_host, rho_host + (size_t)p.nz * p.nx);
+  // rows i_lo .. i_lo + n - 1 of a model array, clamped to the model
+  auto rows_of = [&](const std::vector<double>& m, int i_lo, int n) {
+    std::vector<double> out((size_t)n * p.nx);
+    for (int r = 0; r < n; ++r) {
+      const int i = std::min(std::max(i_lo + r, 0), p.nz - 1);
+      std::memcpy(&out[(size_t)r * p.nx], &m[(size_t)i * p.nx], p.nx * sizeof(double));
+    }
+    return out;
+  };
+  build_grid(p, kphys, p.nz, c->Z0, rho, &c->full.host, c->vrho ? &rphys : nullptr);
   int i_lo, i_hi;
   double zs;
   slab_rows(p, &i_lo, &i_hi, &zs);
   const int nzs = i_hi - i_lo + 1;
-  std::vector<double> kslab((size_t)nzs * p.nx);
-  for (int r = 0; r < nzs; ++r) {
-    const int i = std::min(std::max(i_lo + r, 0), p.nz - 1);
-    std::memcpy(&kslab[(size_t)r * p.nx], &kphys[(size_t)i * p.nx], p.nx * sizeof(double));
+  {
+    const std::vector<double> kslab = rows_of(kphys, i_lo, nzs);
+    const std::vector<double> rslab = c->vrho ? rows_of(rphys, i_lo, nzs) : std::vector<double>();
+    build_grid(p, kslab, nzs, c->Z0, rho, &c->slab.host, c->vrho ? &rslab : nullptr);
   }
-  build_grid(p, kslab, nzs, c->Z0, rho, &c->slab.host);
   fill_dims(c->full, p.nshots);
   fill_dims(c->slab, p.nshots);
-  c->full.coef.cb = c->Z0 * p.dt / (rho * p.h);
+  c->full.coef.cb = c->vrho ? 0.0 : c->Z0 * p.dt / (rho * p.h);
   c->slab.coef.cb = c->full.coef.cb;
   c->has_rslab = p.rslab_dz != 0;
   int r_lo = 0, r_hi = -1;
@@ -1192,12 +1282,9 @@ ssx_status ssx_create(const ssx_problem* prob, const double* kappa_host, double 
   if (c->has_rslab) {
     rslab_rows(p, &r_lo, &r_hi, &zr);
     const int nzr = r_hi - r_lo + 1;
-    std::vector<double> krs((size_t)nzr * p.nx);
-    for (int r = 0; r < nzr; ++r) {
-      const int i = std::min(std::max(r_lo + r, 0), p.nz - 1);
-      std::memcpy(&krs[(size_t)r * p.nx], &kphys[(size_t)i * p.nx], p.nx * sizeof(double));
-    }
-    build_grid(p, krs, nzr, c->Z0, rho, &c->rslab.host);
+    const std::vector<double> krs = rows_of(kphys, r_lo, nzr);
+    const std::vector<double> rrs = c->vrho ? rows_of(rphys, r_lo, nzr) : std::vector<double>();
+    build_grid(p, krs, nzr, c->Z0, rho, &c->rslab.host, c->vrho ? &rrs : nullptr);
     fill_dims(c->rslab, p.nshots);
     c->rslab.coef.cb = c->full.coef.cb;
   }
@@ -1275,6 +1362,21 @@ ssx_status ssx_create(const ssx_problem* prob, const double* kappa_host, double 
   }
   *out = c;
   return SSX_OK;
+}
+
+ssx_status ssx_create(const ssx_problem* prob, const double* kappa_host, double rho,
+                      const double* xs_host, void* stream, void* workspace,
+                      size_t workspace_bytes, ssx_ctx** out) {
+  return create_impl(prob, kappa_host, rho, nullptr, xs_host, stream, workspace,
+                     workspace_bytes, out);
+}
+
+ssx_status ssx_create_density(const ssx_problem* prob, const double* kappa_host,
+                              const double* rho_host, const double* xs_host, void* stream,
+                              void* workspace, size_t workspace_bytes, ssx_ctx** out) {
+  if (!rho_host) return fail(SSX_ERR_ARG, "rho_host is required");
+  return create_impl(prob, kappa_host, 0.0, rho_host, xs_host, stream, workspace,
+                     workspace_bytes, out);
 }
 
 void ssx_destroy(ssx_ctx* c) {
@@ -1579,6 +1681,8 @@ ssx_status ssx_set_option(ssx_ctx* c, int option, int value) {
       return SSX_OK;
     case SSX_OPT_STEPS_PER_LAUNCH_SLAB:
       if (value == 4 || value == 8) {
+        if (c->vrho)
+          return fail(SSX_ERR_ARG, "4 or 8 slab steps per launch take constant density only");
         if (c->fdt == Dt::F64)
           return fail(SSX_ERR_ARG, "4 or 8 slab steps per launch are not available for F64 fields");
         if (c->slab.host.NZ > SLAB_MAXZ || (c->has_rslab && c->rslab.host.NZ > SLAB_MAXZ))
@@ -1606,6 +1710,8 @@ ssx_status ssx_set_option(ssx_ctx* c, int option, int value) {
     case SSX_OPT_TILE_LOOP:
       if (value != 0 && value != 1 && value < 8)
         return fail(SSX_ERR_ARG, "tile loop must be 0, 1 or at least 8");
+      if (value != 0 && c->vrho)
+        return fail(SSX_ERR_ARG, "the tile loop takes constant density only");
       c->loop_full = value;
       return SSX_OK;
     case SSX_OPT_OVERLAP:

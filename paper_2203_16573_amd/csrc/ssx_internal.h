@@ -64,7 +64,12 @@ struct Coef {
   // long with element J at GX + J; then az_n bz_n az_h bz_h, each NZ + 2 PZ
   // long with element I at PZ + I (1 outside the grid)
   const void* pml;
-  double cb;        // Z0 dt / (rho h)
+  double cb;        // Z0 dt / (rho h) (constant density)
+  // variable density: Z0 dt / (rho_x h) at every v_x cell (i, j+1/2) and
+  // Z0 dt / (rho_z h) at every v_z cell (i+1/2, j), compute type, laid out
+  // like ck; null for constant density (cb is used)
+  const void* cbx;
+  const void* cbz;
 };
 
 // Field pointers of one grid (all shots): main pressure, v_x, v_z and the

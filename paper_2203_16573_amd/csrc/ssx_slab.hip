@@ -505,6 +505,7 @@ int slab_strip_width(int order, int ns, int wr) {
 }
 
 hipError_t launch_slab(Dt dt, int order, bool adj, int ns, int wr, StepArgs a, hipStream_t s) {
+  if (a.c.cbx) return hipErrorInvalidValue;  // constant density only
   const bool o8 = (order == 8);
   switch (dt) {
     case Dt::F64: return hipErrorInvalidValue;

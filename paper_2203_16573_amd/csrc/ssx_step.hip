@@ -56,7 +56,10 @@ __global__ __launch_bounds__(TBX* TBY) void k_vel(Fields f, GridDims g, Coef cf,
   const int P = g.pitch;
   const long long o = (long long)I * P + J;
   const Pml<C> pm{static_cast<const C*>(cf.pml), P, g.NZ};
-  const C cb = C(cf.cb);
+  // velocity coefficient: one value for constant density, else the one of
+  // each velocity's own half node
+  const C cbx = cf.cbx ? static_cast<const C*>(cf.cbx)[g.origin + o] : C(cf.cb);
+  const C cbz = cf.cbz ? static_cast<const C*>(cf.cbz)[g.origin + o] : C(cf.cb);
 
   if (so.n >= 0 && I == sl.row0 && J >= sl.col0 && J < sl.col0 + sl.ntr) {
     const C val = C(sl.w0) * ldc<C>(p + o) + C(sl.w1) * ldc<C>(p + (long long)sl.row1 * P + J);
@@ -78,7 +81,7 @@ __global__ __launch_bounds__(TBX* TBY) void k_vel(Fields f, GridDims g, Coef cf,
       sx = acc(sx, wst<K, C>(m - 1), ldc<C>(p + o + m) + ldc<C>(ax + o + m),
                ldc<C>(p + o + 1 - m) + ldc<C>(ax + o + 1 - m));
   }
-  stc(vx + o, upd_v<ADJ>(pm.axh(J), pm.bxh(J), cb, ldc<C>(vx + o), sx, C(0)));
+  stc(vx + o, upd_v<ADJ>(pm.axh(J), pm.bxh(J), cbx, ldc<C>(vx + o), sx, C(0)));
 
   C sz = C(0);
 #pragma unroll
@@ -86,7 +89,7 @@ __global__ __launch_bounds__(TBX* TBY) void k_vel(Fields f, GridDims g, Coef cf,
     sz = acc(sz, wst<K, C>(m - 1), ldc<C>(p + o + (long long)m * P),
              ldc<C>(p + o + (long long)(1 - m) * P));
   const C src = line_src<C, V>(il, io, I, J, shot);
-  stc(vz + o, upd_v<ADJ>(pm.azh(I), pm.bzh(I), cb, ldc<C>(vz + o), sz, src));
+  stc(vz + o, upd_v<ADJ>(pm.azh(I), pm.bzh(I), cbz, ldc<C>(vz + o), sz, src));
 }
 
 template <int K, bool ADJ, typename T>
@@ -195,10 +198,12 @@ struct TileShape {
 
 // an interior tile's loads, held in registers from their issue to the
 // tile's compute phases
-template <int K, int TZ, typename C>
+template <int K, int TZ, typename C, bool VR = false>
 struct InteriorRegs {
   using S = TileShape<K, TZ>;
   C rp[S::NQP][4], rvx[S::NQX][4], rvz[S::NQZ][4], rck[S::NQT][4];
+  // variable density: the velocity coefficients at the v_x and v_z cells
+  C rbx[VR ? S::NQX : 1][4], rbz[VR ? S::NQZ : 1][4];
 };
 
 // no row of the line is active in rows [lo, hi)
@@ -245,9 +250,9 @@ __device__ __forceinline__ T* hist_group(const StepArgs& a, int shot, int I, int
 
 // An interior tile's global loads (p^n with its halo, the old velocities,
 // ck), issued into registers.
-template <int K, typename T, int TZ, typename C>
+template <int K, typename T, int TZ, typename C, bool VR = false>
 __device__ __forceinline__ void interior_load(const StepArgs& a, long long base, int x0, int z0,
-                                              InteriorRegs<K, TZ, C>& r) {
+                                              InteriorRegs<K, TZ, C, VR>& r) {
   using S = TileShape<K, TZ>;
   constexpr int NT = S::NT, R = S::R, GP = S::GP, HP = S::HP, GVX = S::GVX, HVZ = S::HVZ;
   constexpr int GT = S::GT, NQP = S::NQP, NQX = S::NQX, NQZ = S::NQZ, NQT = S::NQT;
@@ -258,6 +263,12 @@ __device__ __forceinline__ void interior_load(const StepArgs& a, long long base,
   const T* vxA = static_cast<const T*>(a.in.vx) + (o0 - 4);
   const T* vzA = static_cast<const T*>(a.in.vz) + (o0 - (long long)K * P);
   const C* ckA = static_cast<const C*>(a.c.ck) + (a.g.origin + (long long)z0 * P + x0);
+  // (coefficient arrays have no shot stride: element (I, J) at origin + I P + J)
+  const C* bxA = VR ? static_cast<const C*>(a.c.cbx) + (a.g.origin + (long long)z0 * P + x0 - 4)
+                    : nullptr;
+  const C* bzA = VR ? static_cast<const C*>(a.c.cbz) +
+                          (a.g.origin + (long long)(z0 - K) * P + x0)
+                    : nullptr;
 #pragma unroll
   for (int k = 0; k < NQP; ++k) {
     const int q = tid + NT * k;
@@ -272,12 +283,16 @@ __device__ __forceinline__ void interior_load(const StepArgs& a, long long base,
     if (NT * k + NT - 1 < TZ * GVX || q < TZ * GVX) {
       const int rr = q / GVX, g = q - rr * GVX;
       ld4(r.rvx[k], at(vxA, rr * P + 4 * g));
+      if constexpr (VR) ld4(r.rbx[k], at(bxA, rr * P + 4 * g));
     }
   }
 #pragma unroll
   for (int k = 0; k < NQZ; ++k) {
     const int q = tid + NT * k;
-    if (NT * k + NT - 1 < HVZ * GT || q < HVZ * GT) ld4(r.rvz[k], at(vzA, (q >> 4) * P + 4 * (q & 15)));
+    if (NT * k + NT - 1 < HVZ * GT || q < HVZ * GT) {
+      ld4(r.rvz[k], at(vzA, (q >> 4) * P + 4 * (q & 15)));
+      if constexpr (VR) ld4(r.rbz[k], at(bzA, (q >> 4) * P + 4 * (q & 15)));
+    }
   }
 #pragma unroll
   for (int k = 0; k < NQT; ++k) {
@@ -290,9 +305,11 @@ __device__ __forceinline__ void interior_load(const StepArgs& a, long long base,
 // then (after the barrier, where after_stage() may issue the next tile's
 // loads) v^{n+1/2} and p^{n+1}.  HIST: also store the residual of the
 // pressure update (interior tiles hold physical cells only and no line).
-template <int K, bool ADJ, typename T, int TZ, typename C, bool HIST, typename F>
+template <int K, bool ADJ, typename T, int TZ, typename C, bool HIST, typename F,
+          bool VR = false>
 __device__ __forceinline__ void interior_compute(const StepArgs& a, int shot, long long base,
-                                                 int x0, int z0, const InteriorRegs<K, TZ, C>& r,
+                                                 int x0, int z0,
+                                                 const InteriorRegs<K, TZ, C, VR>& r,
                                                  C* __restrict__ sP, C* __restrict__ sVX,
                                                  C* __restrict__ sVZ, F&& after_stage) {
   using S = TileShape<K, TZ>;
@@ -337,7 +354,8 @@ __device__ __forceinline__ void interior_compute(const StepArgs& a, int shot, lo
         C sx = zero;
 #pragma unroll
         for (int m = 1; m <= K; ++m) sx = acc(sx, wst<K, C>(m - 1), w[e + 4 + m], w[e + 5 - m]);
-        val[e] = rnd<T>(upd_v<ADJ>(one, one, cb, rvx[k][e], sx, zero));
+        const C cbe = VR ? r.rbx[k][e] : cb;
+        val[e] = rnd<T>(upd_v<ADJ>(one, one, cbe, rvx[k][e], sx, zero));
       }
       if (g >= 1 && g <= GT) st4(at(vxB, rr * P + 4 * g), val);
       st4(sVX + rr * SPX + 4 * g, val);
@@ -361,7 +379,10 @@ __device__ __forceinline__ void interior_compute(const StepArgs& a, int shot, lo
       }
       C val[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) val[e] = rnd<T>(upd_v<ADJ>(one, one, cb, rvz[k][e], sz[e], zero));
+      for (int e = 0; e < 4; ++e) {
+        const C cbe = VR ? r.rbz[k][e] : cb;
+        val[e] = rnd<T>(upd_v<ADJ>(one, one, cbe, rvz[k][e], sz[e], zero));
+      }
       if (rr >= K && rr < K + TZ) st4(at(vzB, rr * P + 4 * g), val);
       st4(sVZ + rr * SPZ + 4 * g, val);
     }
@@ -407,7 +428,7 @@ __device__ __forceinline__ void interior_compute(const StepArgs& a, int shot, lo
 }
 
 // A general tile (absorbing frame, lines, grid edges), loads included.
-template <int K, bool ADJ, typename T, int TZ, typename C, bool HIST>
+template <int K, bool ADJ, typename T, int TZ, typename C, bool HIST, bool VR = false>
 __device__ __forceinline__ void step_general(const StepArgs& a, int shot, int x0, int z0,
                                              C* __restrict__ sP, C* __restrict__ sPX,
                                              C* __restrict__ sVX, C* __restrict__ sVZ,
@@ -466,25 +487,45 @@ __device__ __forceinline__ void step_general(const StepArgs& a, int shot, int x0
       if (row_in(z0 - R + rr)) ld4(rp[k], at(pA, rr * P + 4 * g));
     }
   }
-  C rvx[NQX][4];
+  // variable density: velocity coefficients at the v_x and v_z cells
+  // (coefficient arrays have no shot stride; zero ghosts outside the grid)
+  const C* bxA = VR ? static_cast<const C*>(a.c.cbx) + (a.g.origin + (long long)z0 * P + x0 - 4)
+                    : nullptr;
+  const C* bzA = VR ? static_cast<const C*>(a.c.cbz) +
+                          (a.g.origin + (long long)(z0 - K) * P + x0)
+                    : nullptr;
+  C rvx[NQX][4], rbx[VR ? NQX : 1][4];
 #pragma unroll
   for (int k = 0; k < NQX; ++k) {
     const int q = tid + NT * k;
 #pragma unroll
     for (int e = 0; e < 4; ++e) rvx[k][e] = C(0);
+    if constexpr (VR) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) rbx[k][e] = C(0);
+    }
     if (NT * k + NT - 1 < TZ * GVX || q < TZ * GVX) {
       const int rr = q / GVX, g = q - rr * GVX;
-      if (row_in(z0 + rr)) ld4(rvx[k], at(vxA, rr * P + 4 * g));
+      if (row_in(z0 + rr)) {
+        ld4(rvx[k], at(vxA, rr * P + 4 * g));
+        if constexpr (VR) ld4(rbx[k], at(bxA, rr * P + 4 * g));
+      }
     }
   }
-  C rvz[NQZ][4];
+  C rvz[NQZ][4], rbz[VR ? NQZ : 1][4];
 #pragma unroll
   for (int k = 0; k < NQZ; ++k) {
     const int q = tid + NT * k;
 #pragma unroll
     for (int e = 0; e < 4; ++e) rvz[k][e] = C(0);
-    if ((NT * k + NT - 1 < HVZ * GT || q < HVZ * GT) && row_in(z0 - K + (q >> 4)))
+    if constexpr (VR) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) rbz[k][e] = C(0);
+    }
+    if ((NT * k + NT - 1 < HVZ * GT || q < HVZ * GT) && row_in(z0 - K + (q >> 4))) {
       ld4(rvz[k], at(vzA, (q >> 4) * P + 4 * (q & 15)));
+      if constexpr (VR) ld4(rbz[k], at(bzA, (q >> 4) * P + 4 * (q & 15)));
+    }
   }
   C rck[NQT][4], rau[NQT][4];
 #pragma unroll
@@ -648,7 +689,8 @@ __device__ __forceinline__ void step_general(const StepArgs& a, int shot, int x0
         C sx = C(0);
 #pragma unroll
         for (int m = 1; m <= K; ++m) sx = acc(sx, wst<K, C>(m - 1), w[e + 4 + m], w[e + 5 - m]);
-        val[e] = rnd<T>(upd_v<ADJ>(ax[e], bx[e], cb, rvx[k][e], sx, C(0)));
+        const C cbe = VR ? rbx[k][e] : cb;
+        val[e] = rnd<T>(upd_v<ADJ>(ax[e], bx[e], cbe, rvx[k][e], sx, C(0)));
         if (edge_x && (J + e < 0 || J + e >= NX)) val[e] = C(0);  // outside the grid
       }
       if (g >= 1 && g <= GT && I < NZ) {
@@ -688,7 +730,8 @@ __device__ __forceinline__ void step_general(const StepArgs& a, int shot, int x0
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const C src = lrow ? lrow[4 * g + e] : C(0);
-        val[e] = rnd<T>(upd_v<ADJ>(az, bz, cb, rvz[k][e], sz[e], src));
+        const C cbe = VR ? rbz[k][e] : cb;
+        val[e] = rnd<T>(upd_v<ADJ>(az, bz, cbe, rvz[k][e], sz[e], src));
         if (!row_ok || (edge_x && J + e >= NX)) val[e] = C(0);  // outside the grid
       }
       if (rr >= K && rr < K + TZ && I < NZ) {
@@ -809,8 +852,9 @@ __device__ __forceinline__ int xcd_tile(int Lg, int ntiles) {
 //   current tile's compute instead of every workgroup loading, computing and
 //   storing in step.  (General tiles stay outside the loop: inside it, their
 //   long path raises register use past the point of spilling.)
-template <int K, bool ADJ, typename T, int TZ, bool LOOP, bool HIST = false>
+template <int K, bool ADJ, typename T, int TZ, bool LOOP, bool HIST = false, bool VR = false>
 __global__ __launch_bounds__(step_threads(TZ), LOOP ? 4 : 6) void k_step(StepArgs a) {
+  static_assert(!(VR && (LOOP || HIST)), "variable density: one tile per workgroup, no history");
   using C = typename Tr<T>::C;
   using S = TileShape<K, TZ>;
   static_assert(2 * K - 1 <= HXS && K <= 4, "halo wider than the staged columns");
@@ -837,12 +881,12 @@ __global__ __launch_bounds__(step_threads(TZ), LOOP ? 4 : 6) void k_step(StepArg
     const int tzi = tt / a.ntx;
     const int x0 = (tt - tzi * a.ntx) * TX, z0 = tzi * TZ;
     if (interior_tile<K, TZ>(a, x0, z0)) {
-      InteriorRegs<K, TZ, C> r;
-      interior_load<K, T, TZ, C>(a, base_of(shot), x0, z0, r);
+      InteriorRegs<K, TZ, C, VR> r;
+      interior_load<K, T, TZ, C, VR>(a, base_of(shot), x0, z0, r);
       interior_compute<K, ADJ, T, TZ, C, HIST>(a, shot, base_of(shot), x0, z0, r, sP, sVX, sVZ,
                                                [] {});
     } else {
-      step_general<K, ADJ, T, TZ, C, HIST>(a, shot, x0, z0, sP, sPX, sVX, sVZ, sF, sL);
+      step_general<K, ADJ, T, TZ, C, HIST, VR>(a, shot, x0, z0, sP, sPX, sVX, sVZ, sF, sL);
     }
   } else {
     const int ngen_all = a.nshots * a.ngen, nint_all = a.nshots * a.nint;
@@ -991,6 +1035,19 @@ static hipError_t step_t(int tz, int loop, const StepArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(kernel, dim3(nb), dim3(threads), 0, s, a);
     return hipGetLastError();
   };
+  if (a.c.cbx) {
+    // variable density: one tile per workgroup, no step history
+    if (loop || a.hist) return hipErrorInvalidValue;
+    switch (tz) {
+      case 8: return go(k_step<K, ADJ, T, 8, false, false, true>, step_threads(8));
+      case 16: return go(k_step<K, ADJ, T, 16, false, false, true>, step_threads(16));
+      case 32:
+        if constexpr (sizeof(T) < 8)
+          return go(k_step<K, ADJ, T, 32, false, false, true>, step_threads(32));
+        return hipErrorInvalidValue;
+      default: return hipErrorInvalidValue;
+    }
+  }
   if (a.hist) {
     // the step history: forward steps with FP32 or FP64 fields only
     if constexpr (!ADJ && sizeof(T) >= 4) {
