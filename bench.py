@@ -57,9 +57,15 @@ def parse():
     ap.add_argument("--iters", type=int, default=0,
                     help="override the PCG iteration count (xw: default 60)")
     ap.add_argument("--autotune", type=int, default=1)
-    ap.add_argument("--requests", type=int, default=12, help="c5: requests served")
-    ap.add_argument("--max-shots", type=int, default=8, help="c5: shots per request cap")
-    ap.add_argument("--max-nt", type=int, default=1500, help="c5: record length cap")
+    ap.add_argument("--requests", type=int, default=24, help="c5: requests served")
+    ap.add_argument("--max-shots", type=int, default=64,
+                    help="c5: shots per request cap (64: the stream's own range)")
+    ap.add_argument("--max-nt", type=int, default=4000,
+                    help="c5: record length cap (4000: the stream's own range)")
+    ap.add_argument("--c5-ref", type=int, default=1,
+                    help="c5: after timing, solve shot 0 of every request again with FP64 "
+                         "fields and vectors and report the served solution's error "
+                         "against it")
     ap.add_argument("--slots", type=int, default=4, help="c5: concurrent requests")
     ap.add_argument("--rate-sweep", action="store_true",
                     help="c5: also serve open-loop streams at 0.5, 1.0 and 1.2x the measured "
@@ -789,13 +795,21 @@ def serve_bench(args):
         reqs.append(serve.Request(i, prob, wl.kappa, wl.rho, d, alpha_rel=wl.alpha_rel, K=wl.K,
                                   field_dtype="f16", arrival=t))
     tuner = None
+    t_tune = time.perf_counter()
     if args.autotune:
         def tuner(ctx, req):
             autotune.apply(ctx, autotune.choose(req.prob, req.kappa, req.rho, field_dtype="f16"))
         for r in reqs:  # tune every shape before timing
             autotune.choose(r.prob, r.kappa, r.rho, field_dtype="f16")
+            print(f"# tuned request {r.rid}: {r.prob.nz}x{r.prob.nx}, {r.nshots} shots, "
+                  f"nt {r.prob.nt}", flush=True)
+    t_tune = time.perf_counter() - t_tune
     budget = int(0.8 * torch.cuda.mem_get_info()[0])
-    srv = serve.Server(budget, slots=args.slots, graphs=bool(args.graphs), tuner=tuner)
+    def progress(res):
+        print(f"# request {res.rid} done: latency {res.t_done - res.t_arrival:.2f} s", flush=True)
+
+    srv = serve.Server(budget, slots=args.slots, graphs=bool(args.graphs), tuner=tuner,
+                       on_done=progress)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     closed = srv.run(reqs, realtime=False)
@@ -811,7 +825,9 @@ def serve_bench(args):
         res = srv.run(reqs, realtime=True)
         return res, serve.summarize(res, time.perf_counter() - t0)
 
+    print(f"# closed loop: {cap}", flush=True)
     opened, lat = open_loop(0.8)
+    print(f"# open loop 0.8x: {lat}", flush=True)
     same = all(torch.equal(a.h, b.h) for a, b in zip(closed, opened))
     sweep = {}
     if args.rate_sweep:
@@ -819,6 +835,27 @@ def serve_bench(args):
             res, summ = open_loop(factor)
             same = same and all(torch.equal(a.h, b.h) for a, b in zip(closed, res))
             sweep[f"open_loop_{factor:g}x"] = summ
+    # accuracy: shot 0 of every request solved again with FP64 fields and
+    # vectors (that path matches the FP64 oracle to 1e-12 per full-length
+    # propagation); the served FP16-storage solution's relative L2 error
+    per_req = []
+    for r, res in zip(reqs, closed):
+        row = {"rid": r.rid, "grid": f"{r.prob.nz}x{r.prob.nx}", "shots": r.nshots,
+               "nt": r.prob.nt, "latency_s": round(res.latency, 3),
+               "admit_wait_s": round(res.t_admit - res.t_arrival, 3)}
+        if args.c5_ref:
+            p1 = r.prob.replace(xs=(r.prob.xs[0],))
+            ref = ssx.Context(p1, r.kappa, r.rho, field_dtype="f64")
+            h64, _, _, _ = ref.pcg_solve(r.d[:1].double().contiguous(), r.alpha_rel, r.K,
+                                         raise_on_breakdown=False)
+            torch.cuda.synchronize()
+            ref.close()
+            h16 = res.h[:1].double()
+            row["h_err_vs_f64"] = float(torch.linalg.norm(h16 - h64) / torch.linalg.norm(h64))
+        per_req.append(row)
+    errs = [q["h_err_vs_f64"] for q in per_req if "h_err_vs_f64" in q]
+    caps = ("none" if args.max_shots >= 64 and args.max_nt >= 4000
+            else f"shots <= {args.max_shots}, nt <= {args.max_nt}")
     out = {
         "metric": "served PCG surface-source solves/s (p50/p99 latency)",
         "value": round(cap["solves_per_s"], 4), "unit": "solves/s", "n_gpus": 1,
@@ -826,13 +863,21 @@ def serve_bench(args):
         "ms_per_step": round(1e3 * wall_closed / len(reqs), 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f16-storage/f32", "data": "synthetic (seeded serving stream)",
-        "config": {"workload": f"c5: first {len(reqs)} requests of the seeded stream, "
-                               f"<= {args.max_shots} shots, nt <= {args.max_nt}, K 20, "
-                               f"{args.slots} slots, graphs {int(bool(args.graphs))}"},
+        "config": {"workload": f"c5: first {len(reqs)} requests of the seeded stream "
+                               f"(grids 201x401 / 401x801 / 801x1601, 1-64 shots, "
+                               f"nt 500-4000), caps: {caps}, K 20, FP16 storage, "
+                               f"{args.slots} slots, graphs {int(bool(args.graphs))}",
+                   "requests": len(reqs), "caps": caps,
+                   "admission_budget_bytes": budget},
         "closed_loop": cap, "open_loop_0p8": lat, **sweep,
         "p50_latency_s": round(lat["latency_p50_s"], 3),
         "p99_latency_s": round(lat["latency_p99_s"], 3),
         "results_identical_closed_vs_open": same,
+        "autotune_s": round(t_tune, 1),
+        "accuracy": {"h_err_vs_f64_solve": {"median": float(np.median(errs)) if errs else None,
+                                            "max": float(np.max(errs)) if errs else None,
+                                            "ref": "shot 0 of each request, FP64 fields"}},
+        "per_request": per_req,
     }
     print(json.dumps(out), flush=True)
 

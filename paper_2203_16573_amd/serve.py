@@ -74,11 +74,12 @@ class Server:
     """Admission by footprint and slots, FIFO order, one stream per request."""
 
     def __init__(self, budget_bytes: int, slots: int = 4, graphs: bool = False,
-                 tuner=None):
+                 tuner=None, on_done=None):
         self.budget = int(budget_bytes)
         self.slots = int(slots)
         self.graphs = bool(graphs)
         self.tuner = tuner            # callable(ctx, req) applying kernel choices, or None
+        self.on_done = on_done        # callable(Result) after each completion, or None
         self._cv = threading.Condition()
         self._free = self.budget
         self._busy = 0
@@ -109,6 +110,8 @@ class Server:
             res = Result(req.rid, h, hist, iters, st, req.arrival, t_admit, t_done)
             with self._cv:
                 self._results.append(res)
+            if self.on_done is not None:
+                self.on_done(res)
         except BaseException as e:  # reported by run()
             with self._cv:
                 self._errors.append(e)
