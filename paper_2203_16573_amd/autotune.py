@@ -17,6 +17,8 @@ import json
 import os
 import threading
 
+import numpy as np
+
 from . import (OPT_SHOT_GROUP, OPT_SHOT_GROUP_SLAB, OPT_SLAB_STRIP, OPT_STEP_KERNEL,
                OPT_STEPS_PER_LAUNCH, OPT_STEPS_PER_LAUNCH_SLAB, OPT_TILE_LOOP, OPT_TILE_Z,
                OPT_TILE_Z_SLAB,
@@ -27,7 +29,7 @@ SLAB_MAXZ = 56  # tallest slab the 4/8-step slab kernel holds
 _lock = threading.Lock()
 
 
-def shape_key(prob, nshots: int, field_dtype: str) -> str:
+def shape_key(prob, nshots: int, field_dtype: str, variable_density: bool = False) -> str:
     NZ, NX = prob.nz + 2 * prob.npml, prob.nx + 2 * prob.npml
     k = prob.order // 2
     nzs = abs(prob.slab_dz) + 1 + 2 * k + 2 * prob.npml
@@ -35,6 +37,8 @@ def shape_key(prob, nshots: int, field_dtype: str) -> str:
     rdz = int(getattr(prob, "rslab_dz", 0))
     if rdz:  # the receiver-side slab shares the slab options
         key += f"|rslab{abs(rdz) + 1 + 2 * k + 2 * prob.npml}"
+    if variable_density:  # other kernel instances, fewer launch forms
+        key += "|vrho"
     return key
 
 
@@ -64,15 +68,17 @@ def _store(path, table):
     os.replace(tmp, path)
 
 
-def _time_ms(fn, reps=3):
+def _time_ms(fn, stream, reps=3):
+    """Milliseconds per call of fn, timed with events on `stream` (the
+    stream the context issues its work on)."""
     import torch
     fn()  # first call captures the graph
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
+    e0.record(stream)
     for _ in range(reps):
         fn()
-    e1.record()
+    e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
 
@@ -111,9 +117,13 @@ def tune(prob, kappa, rho, xs=None, field_dtype="f32", nt_tune: int = 60,
     # (steps, strip width) with the tile height of its one-step remainder
     slab_cands = [(spl, tz, 0) for spl, tz in cands]
     # full-grid candidates: one-step launches also with workgroups looping
-    # over the interior tiles
-    full_cands = [(spl, tz, 0) for spl, tz in cands] + [(1, tz, 1) for spl, tz in cands if spl == 1]
-    if field_dtype != "f64" and tallest_slab(short) <= SLAB_MAXZ:
+    # over the interior tiles (constant density only, as the multi-step slab
+    # kernel)
+    vrho = np.ndim(rho) != 0
+    full_cands = [(spl, tz, 0) for spl, tz in cands]
+    if not vrho:
+        full_cands += [(1, tz, 1) for spl, tz in cands if spl == 1]
+    if field_dtype != "f64" and tallest_slab(short) <= SLAB_MAXZ and not vrho:
         slab_cands += [(4, 8, 64), (4, 8, 128), (8, 8, 128)]
     us = {}
     ctx.set_option(OPT_STEP_KERNEL, 1)
@@ -123,20 +133,20 @@ def tune(prob, kappa, rho, xs=None, field_dtype="f32", nt_tune: int = 60,
         ctx.set_option(OPT_TILE_Z, tz)
         ctx.set_option(OPT_STEPS_PER_LAUNCH, spl)
         ctx.set_option(OPT_TILE_LOOP, loop)
-        us[f"full_s{spl}_tz{tz}_l{loop}"] = 1e3 * _time_ms(full) / (2 * nt)
+        us[f"full_s{spl}_tz{tz}_l{loop}"] = 1e3 * _time_ms(full, ctx.stream) / (2 * nt)
     ctx.set_option(OPT_STEPS_PER_LAUNCH, 1)
     ctx.set_option(OPT_TILE_LOOP, 0)
     for spl, tz, strip in slab_cands:
         ctx.set_option(OPT_TILE_Z_SLAB, tz)
         ctx.set_option(OPT_STEPS_PER_LAUNCH_SLAB, spl)
         ctx.set_option(OPT_SLAB_STRIP, strip)
-        us[f"slab_s{spl}_tz{tz}_w{strip}"] = 1e3 * _time_ms(slab) / (2 * nt)
+        us[f"slab_s{spl}_tz{tz}_w{strip}"] = 1e3 * _time_ms(slab, ctx.stream) / (2 * nt)
     ctx.set_option(OPT_STEPS_PER_LAUNCH_SLAB, 1)
     ctx.set_option(OPT_SLAB_STRIP, 0)
     ctx.set_option(OPT_STEPS_PER_LAUNCH, 1)
     ctx.set_option(OPT_STEP_KERNEL, 0)
-    us["full_split"] = 1e3 * _time_ms(full) / (2 * nt)
-    us["slab_split"] = 1e3 * _time_ms(slab) / (2 * nt)
+    us["full_split"] = 1e3 * _time_ms(full, ctx.stream) / (2 * nt)
+    us["slab_split"] = 1e3 * _time_ms(slab, ctx.stream) / (2 * nt)
     best_full = min(full_cands, key=lambda c: us[f"full_s{c[0]}_tz{c[1]}_l{c[2]}"])
     best_slab = min(slab_cands, key=lambda c: us[f"slab_s{c[0]}_tz{c[1]}_w{c[2]}"])
     fused_total = us[f"full_s{best_full[0]}_tz{best_full[1]}_l{best_full[2]}"] + \
@@ -155,7 +165,7 @@ def tune(prob, kappa, rho, xs=None, field_dtype="f32", nt_tune: int = 60,
         for gsz in _group_candidates(auto_group, ns):
             ctx.set_option(OPT_SHOT_GROUP, gsz)
             ctx.set_option(OPT_SHOT_GROUP_SLAB, 0)
-            us[f"full_group{gsz}"] = 1e3 * _time_ms(full) / (2 * nt)
+            us[f"full_group{gsz}"] = 1e3 * _time_ms(full, ctx.stream) / (2 * nt)
         group = min(_group_candidates(auto_group, ns), key=lambda x: us[f"full_group{x}"])
     ctx.close()
     return {"step_kernel": step_kernel,
@@ -169,7 +179,7 @@ def choose(prob, kappa, rho, xs=None, field_dtype="f32", cache_path: str | None 
            retune: bool = False, **kw) -> dict:
     """Cached :func:`tune` keyed by :func:`shape_key`."""
     xs = tuple(prob.xs) if xs is None else tuple(xs)
-    key = shape_key(prob, len(xs), field_dtype)
+    key = shape_key(prob, len(xs), field_dtype, np.ndim(rho) != 0)
     if cache_path and not retune:
         with _lock:
             hit = _load(cache_path).get(key)
