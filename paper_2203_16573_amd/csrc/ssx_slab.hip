@@ -30,6 +30,14 @@
 namespace ssx {
 
 constexpr int SLAB_THREADS = 1024;
+// LDS row padding (floats) of the x-stencil arrays and, on 64-column strips,
+// of the v_z and ck arrays.  On 64-column strips a wavefront's lanes take
+// consecutive rows, so the row pitch sets which banks a 16-byte access of
+// consecutive lanes hits: 4-column padding (pitch = 4 mod 64 words) measured
+// fastest (c2 slab, four steps per launch: 4.07 us per step against 4.59
+// with 8 columns and 10.3 with none).
+constexpr int SLAB_PADX = 4;
+constexpr int SLAB_PADZ = 4;
 // s_waitcnt operand: vector memory count 0, the other counters unconstrained
 constexpr int VMCNT0 = 0x0F70;
 
@@ -38,7 +46,7 @@ struct SlabShape {
   static constexpr int R = 2 * K - 1;                 // per-step reach in x
   static constexpr int H = (NS * R + 3) / 4 * 4;      // halo columns each side
   static constexpr int W = WR - 2 * H;                // owned columns
-  static constexpr int RP = WR + 8;                   // LDS pitch, x-stencil arrays
+  static constexpr int RP = WR + SLAB_PADX;           // LDS pitch, x-stencil arrays
   static constexpr int ZR = SLAB_MAXZ + 2 * K;        // LDS rows, z-stencil arrays
   static constexpr int G = WR / 4;                    // 4-column groups per row
   // loads, stores: task q = row q / G, group q % G (consecutive lanes on
@@ -48,14 +56,14 @@ struct SlabShape {
   // group w + NWV k, its lanes the rows, so that a whole wavefront skips a
   // group outside the columns the remaining steps still need (the cone
   // that narrows by the step's reach on each side per step).  Otherwise
-  // the load mapping.  CONE pads the v_z and ck rows by 8 columns so that
-  // lanes on consecutive rows hit different LDS banks (there is no room
-  // for that padding in LDS at 128 columns).
+  // the load mapping.  CONE pads the v_z and ck rows as well, so that lanes
+  // on consecutive rows hit different LDS banks (there is no room for that
+  // padding in LDS at 128 columns).
   static constexpr bool CONE = WR == 64;
   static constexpr int NWV = SLAB_THREADS / 64;
   static constexpr int NQS = CONE ? (G + NWV - 1) / NWV : NQ;
-  static constexpr int ZP = CONE ? WR + 8 : WR;   // LDS pitch, v_z
-  static constexpr int CKP = CONE ? WR + 8 : WR;  // LDS pitch, ck
+  static constexpr int ZP = CONE ? WR + SLAB_PADZ : WR;   // LDS pitch, v_z
+  static constexpr int CKP = CONE ? WR + SLAB_PADZ : WR;  // LDS pitch, ck
   // CONE: the values sampled on the two lines at each step are kept in LDS
   // and written after the last step (no global store in flight during the
   // steps, whose waits for trace loads would otherwise also wait for it:
