@@ -56,6 +56,9 @@ def parse():
                     help="weighted solver: penalty weight per metre")
     ap.add_argument("--iters", type=int, default=0,
                     help="override the PCG iteration count (xw: default 60)")
+    ap.add_argument("--rtol", type=float, default=0.0,
+                    help="c1..c4: stop a solve once ||r_k|| <= rtol ||r_0|| (at most the "
+                         "configuration's iteration count; 0: always that count)")
     ap.add_argument("--autotune", type=int, default=1)
     ap.add_argument("--requests", type=int, default=24, help="c5: requests served")
     ap.add_argument("--max-shots", type=int, default=64,
@@ -232,8 +235,9 @@ def main():
 
     def solve():
         if weighted:
-            return ctx.pcg_solve_w(d, args.alpha, wl.K, h=h, raise_on_breakdown=False)
-        return ctx.pcg_solve(d, wl.alpha_rel, wl.K, h=h, raise_on_breakdown=False)
+            return ctx.pcg_solve_w(d, args.alpha, wl.K, rtol=args.rtol, h=h,
+                                   raise_on_breakdown=False)
+        return ctx.pcg_solve(d, wl.alpha_rel, wl.K, rtol=args.rtol, h=h, raise_on_breakdown=False)
 
     for _ in range(args.warmup):
         solve()
@@ -293,10 +297,11 @@ def main():
     # alpha, 2K more on the source-side one
     k = prob.order // 2
     nzs = abs(prob.slab_dz) + 1 + 2 * k + 2 * prob.npml
-    cu_solve = prob.nt * ((2 * wl.K + 1) * NZ * NX + 2 * (wl.K + 1) * nzs * NX)
+    Kr = iters if args.rtol > 0 else wl.K  # iterations the timed solves ran
+    cu_solve = prob.nt * ((2 * Kr + 1) * NZ * NX + 2 * (Kr + 1) * nzs * NX)
     if weighted:
         nzr = abs(prob.rslab_dz) + 1 + 2 * k + 2 * prob.npml
-        cu_solve += prob.nt * NX * (2 * (wl.K + 1) * nzr + (2 * wl.K * nzs if args.alpha else 0))
+        cu_solve += prob.nt * NX * (2 * (Kr + 1) * nzr + (2 * Kr * nzs if args.alpha else 0))
     gcell = cu_solve * prob.nshots / (elapsed / args.steps) / 1e9
 
     cpu = None
@@ -389,7 +394,9 @@ def main():
         "data": "synthetic (seeded layered model; d = F of a Ricker point source)",
         "config": {"workload": f"{wl.name}: {prob.nz}x{prob.nx} @ {prob.h} m, order "
                                f"{prob.order}, nt {prob.nt}, K {wl.K}, shots {prob.nshots}"
-                               + (f", weighted, alpha {args.alpha}/m" if weighted else ""),
+                               + (f", weighted, alpha {args.alpha}/m" if weighted else "")
+                               + (f", stop at ||r_k|| <= {args.rtol:g} ||r_0||"
+                                  if args.rtol > 0 else ""),
                    "nz": prob.nz, "nx": prob.nx, "nt": prob.nt, "K": wl.K,
                    "shots": prob.nshots, "field_dtype": fd},
         "gcell_updates_per_s": round(gcell, 2),
@@ -490,7 +497,75 @@ def crosswell_bench(args):
             a, b = reached(cg, lev), reached(pcg, lev)
             entry[f"iters_to_{tag}"] = {"cg": a, "pcg": b,
                                        "ratio": round(a / b, 2) if a and b else None}
+        # where <g_k, r_k> first changes sign (PCG): from then on beta_k < 0
+        sg = np.sign(hp[0, :, 2])
+        flips = np.nonzero(sg != sg[0])[0]
+        entry["pcg_gr_first_sign_change_at"] = int(flips[0]) if flips.size else None
+        entry["cg_misfit_curve"] = [round(float(v / dn), 5) for v in hc[0, :, 3]]
+        entry["pcg_misfit_curve"] = [round(float(v / dn), 5) for v in hp[0, :, 3]]
         comparison[f"alpha={alpha:g}"] = entry
+
+    # Like for like: both solvers' iterates h_k at checkpoints k, measured in
+    # the same three norms: the Euclidean normal residual ||F^T d - N h|| /
+    # ||F^T d|| (CG's own; N with CG's alpha), the preconditioned weighted
+    # normal residual ||M^-1 (F^T W_d d - N_w h)|| / ||M^-1 F^T W_d d|| (the
+    # norm1 form, PCG's own) and the data misfit ||F h - d|| / ||d||.  Also
+    # the cost of an iteration of each and the time each takes to bring the
+    # data misfit to given levels.
+    Ftd = ctx.adj(d, ctx.empty_s()).clone()
+    FtWd = ctx.adj(ctx.weight_d(d, ctx.empty_r()), ctx.empty_s()).clone()
+    ftd_n = float(torch.linalg.norm(Ftd.double()))
+    checkpoints = [k for k in (0, 2, 5, 10, 20, 30, 45, 60) if k <= K]
+    q, Fh = ctx.empty_s(), ctx.empty_r()
+    like = {}
+    for alpha in sorted({0.0, args.alpha}):
+        a_e = alpha * ftd_n / dn  # the absolute alpha ssx_pcg_solve derives
+        MFtWd_n = float(torch.linalg.norm(ctx.precond(alpha, FtWd, ctx.empty_s()).double()))
+        rows = {"cg": [], "pcg": []}
+        for name in ("cg", "pcg"):
+            for k in checkpoints:
+                if k == 0:
+                    hk = torch.zeros_like(Ftd)
+                elif name == "cg":
+                    hk, _, _, _ = ctx.pcg_solve(d, alpha, k, use_precond=False,
+                                                raise_on_breakdown=False)
+                else:
+                    hk, _, _, _ = ctx.pcg_solve_w(d, alpha, k, raise_on_breakdown=False)
+                hk = hk.clone()
+                e_n = float(torch.linalg.norm((Ftd - ctx.normal(a_e, hk, q)).double())) / ftd_n
+                rw = FtWd - ctx.normal_w(alpha, hk, q)
+                e_w = float(torch.linalg.norm(ctx.precond(alpha, rw.contiguous(),
+                                                          ctx.empty_s()).double())) / MFtWd_n
+                mis = float(torch.linalg.norm((ctx.fwd(hk, Fh) - d).double())) / dn
+                rows[name].append({"k": k, "euclid_normal_res": round(e_n, 6),
+                                   "weighted_normal_res": round(e_w, 6),
+                                   "misfit": round(mis, 5)})
+        # seconds per iteration of each solver (K iterations, after one run)
+        per_it = {}
+        for name in ("cg", "pcg"):
+            run = ((lambda: ctx.pcg_solve(d, alpha, K, use_precond=False,
+                                          raise_on_breakdown=False)) if name == "cg" else
+                   (lambda: ctx.pcg_solve_w(d, alpha, K, raise_on_breakdown=False)))
+            run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            run()
+            torch.cuda.synchronize()
+            per_it[name] = (time.perf_counter() - t0) / K
+        curves = {"cg": np.array(comparison[f"alpha={alpha:g}"]["cg_misfit_curve"]),
+                  "pcg": np.array(comparison[f"alpha={alpha:g}"]["pcg_misfit_curve"])}
+        to_level = {}
+        for lev in (0.5, 0.3, 0.2, 0.15, 0.1):
+            ent = {}
+            for name in ("cg", "pcg"):
+                it = reached(curves[name], lev)
+                ent[name] = None if it is None else {"iters": it,
+                                                     "s": round(it * per_it[name], 4)}
+            to_level[f"misfit<={lev:g}"] = ent
+        like[f"alpha={alpha:g}"] = {"checkpoints": rows,
+                                    "ms_per_iteration": {k: round(1e3 * v, 3)
+                                                         for k, v in per_it.items()},
+                                    "time_to_misfit": to_level}
 
     def nrm(t):
         return float(torch.linalg.norm(t.double()))
@@ -584,6 +659,7 @@ def crosswell_bench(args):
         "ms_per_iteration": round(1e3 * el / (args.steps * K), 3),
         "kernel_choice": None if tuned is None else {k: v for k, v in tuned.items() if k != "us"},
         "cg_vs_pcg": comparison,
+        "cg_vs_pcg_same_norms": like,
         "operator_checks": checks,
     }
     print(json.dumps(out), flush=True)
