@@ -207,7 +207,15 @@ def main():
     ctx.set_graphs(bool(args.graphs))
     wav = inputs.source_wavelet(prob, wl.freq)
     htrue = np.stack([inputs.spike_gather(prob, wav, s) for s in range(prob.nshots)])
-    d = ctx.fwd(torch.tensor(htrue, dtype=vdt, device="cuda"), ctx.empty_r())
+    # the data: F h_true with FP64 fields (input preparation, before any
+    # timing), rounded to the vector type -- the data of the oracle's
+    # full-length solves in tests/golden
+    gen = ssx.Context(prob, wl.kappa, wl.rho, field_dtype="f64")
+    d64 = gen.fwd(torch.tensor(htrue, dtype=torch.float64, device="cuda"), gen.empty_r())
+    torch.cuda.synchronize()
+    gen.close()
+    d = d64.to(vdt).contiguous()
+    del d64
     h = ctx.empty_s()
     torch.cuda.synchronize()
     if args.prop_only:
@@ -411,6 +419,9 @@ def main():
     }
     if ref is not None:
         out["error_vs_f64_solve"] = ref
+    orc = oracle_golden_errors(cnum, wl, prob, h, hist, args, weighted)
+    if orc is not None:
+        out["error_vs_oracle"] = orc
     if cgcmp is not None:
         out["cg_comparison"] = cgcmp
     print(json.dumps(out), flush=True)
@@ -807,6 +818,45 @@ def varpro_bench(args):
         "history": hist,
     }
     print(json.dumps(out), flush=True)
+
+
+def oracle_golden_errors(cnum, wl, prob, h, hist, args, weighted):
+    """Errors of the last timed solve against the FP64 oracle's solve of the
+    same problem, read from the expected values in tests/golden (written by
+    the oracle alone; see tests/golden/make_full_length.py), when the
+    workload is the one they were written for: the kept traces' relative L2
+    error of h_K, the relative error of its norm, and of the residual
+    history (||r_k|| per iteration, and each column as a vector)."""
+    import numpy as np
+    import inputs
+    if weighted or args.rtol > 0 or args.nt or args.shots or args.iters:
+        return None
+    name = {2: "c2_full_length.npz", 4: "c2_full_length.npz", 3: "c3_full_length.npz"}.get(cnum)
+    if name is None:
+        return None
+    path = os.path.join(ROOT, "tests", "golden", name)
+    if not os.path.exists(path):
+        return None
+    z = np.load(path)
+    hh = h.double().cpu().numpy()
+    shots = [0] if cnum in (2, 4) else [int(s) for s in z["shots"]]
+    out = {"reference": f"FP64 oracle, tests/golden/{name}", "shots": {}}
+    for s in shots:
+        key = "h" if cnum in (2, 4) else f"h{s}"
+        hk = "hist" if cnum in (2, 4) else f"hist{s}"
+        cols = z[f"{key}_cols"]
+        ref = z[f"{key}_sample"].astype(np.float64)
+        a = hh[s][:, cols]
+        hr, hg = z[hk], hist[s]
+        rk = np.abs(hg[:, 0] - hr[:, 0]) / hr[:, 0]
+        out["shots"][str(s)] = {
+            "h_rel_l2_kept_traces": float(np.linalg.norm(a - ref) / np.linalg.norm(ref)),
+            "h_norm_rel_err": float(abs(np.linalg.norm(hh[s]) / float(z[f"{key}_norm"]) - 1)),
+            "residual_per_iteration_max_rel_err": float(rk.max()),
+            "residual_per_iteration_rel_err": [round(float(v), 6) for v in rk],
+            "history_columns_rel_l2": [float(np.linalg.norm(hg[:, j] - hr[:, j]) /
+                                             np.linalg.norm(hr[:, j])) for j in range(4)]}
+    return out
 
 
 def measured_traffic(config, fd, nshots, tile_z, group, loop, kernel):

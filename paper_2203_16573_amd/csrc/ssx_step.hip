@@ -40,7 +40,7 @@ constexpr int TBY = 4;
 // split reference kernels: velocity update (+ pressure-line sampling, +
 // v_z injection), then pressure update (+ v_z-line sampling, + pressure
 // injection), one thread per cell, in place.
-template <int K, bool ADJ, typename T>
+template <int K, bool ADJ, typename T, bool VR = false>
 __global__ __launch_bounds__(TBX* TBY) void k_vel(Fields f, GridDims g, Coef cf, LineDev sl,
                                                   TraceIO so, LineDev il, TraceIO io) {
   using C = typename Tr<T>::C;
@@ -56,10 +56,10 @@ __global__ __launch_bounds__(TBX* TBY) void k_vel(Fields f, GridDims g, Coef cf,
   const int P = g.pitch;
   const long long o = (long long)I * P + J;
   const Pml<C> pm{static_cast<const C*>(cf.pml), P, g.NZ};
-  // velocity coefficient: one value for constant density, else the one of
-  // each velocity's own half node
-  const C cbx = cf.cbx ? static_cast<const C*>(cf.cbx)[g.origin + o] : C(cf.cb);
-  const C cbz = cf.cbz ? static_cast<const C*>(cf.cbz)[g.origin + o] : C(cf.cb);
+  // velocity coefficient: one value for constant density, else (VR) the one
+  // of each velocity's own half node
+  const C cbx = VR ? static_cast<const C*>(cf.cbx)[g.origin + o] : C(cf.cb);
+  const C cbz = VR ? static_cast<const C*>(cf.cbz)[g.origin + o] : C(cf.cb);
 
   if (so.n >= 0 && I == sl.row0 && J >= sl.col0 && J < sl.col0 + sl.ntr) {
     const C val = C(sl.w0) * ldc<C>(p + o) + C(sl.w1) * ldc<C>(p + (long long)sl.row1 * P + J);
@@ -977,7 +977,11 @@ static hipError_t vel_t(const Fields& f, const GridDims& g, const Coef& c, const
                         const TraceIO& so, const LineDev& il, const TraceIO& io, int ns,
                         hipStream_t s) {
   dim3 grid((g.NX + TBX - 1) / TBX, (g.NZ + TBY - 1) / TBY, ns);
-  hipLaunchKernelGGL((k_vel<K, ADJ, T>), grid, dim3(TBX, TBY), 0, s, f, g, c, sl, so, il, io);
+  if (c.cbx)
+    hipLaunchKernelGGL((k_vel<K, ADJ, T, true>), grid, dim3(TBX, TBY), 0, s, f, g, c, sl, so, il,
+                       io);
+  else
+    hipLaunchKernelGGL((k_vel<K, ADJ, T>), grid, dim3(TBX, TBY), 0, s, f, g, c, sl, so, il, io);
   return hipGetLastError();
 }
 template <int K, bool ADJ, typename T>
