@@ -414,6 +414,13 @@ def main():
                                                         np.sign(hist[:, :1, 2]), axis=1))),
         "kernel_choice": None if tuned is None else {k: v for k, v in tuned.items() if k != "us"},
         "final_rel_residual": float(np.median(hist[:, -1, 0] / hist[:, 0, 0])),
+        # ||M^-1 r_k|| / ||M^-1 r_0|| (the preconditioned normal residual)
+        "final_rel_precond_residual": float(np.median(hist[:, -1, 1] / hist[:, 0, 1])),
+        "iters_to_drop": {
+            name: {tag: (lambda idx: int(idx[0]) if idx.size else None)(
+                np.nonzero(np.median(hist[:, :, col] / hist[:, :1, col], axis=0) <= lev)[0])
+                   for tag, lev in (("10x", 0.1), ("100x", 0.01))}
+            for name, col in (("residual", 0), ("precond_residual", 1))},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
