@@ -288,7 +288,7 @@ def main():
     # write p, v_x, v_z once
     b_alg = 6 * fsz + csz
     achieved = b_alg * NZ * NX * prob.nshots / (step_ms * 1e-3) / 1e9
-    tz_used, _, _, loop_used = ctx.launch_shape()
+    tz_used, spl_used, _, loop_used = ctx.launch_shape()
     traffic = measured_traffic(args.config, fd, prob.nshots, tz_used, group, loop_used,
                                ctx.step_kernel_name())
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -296,8 +296,10 @@ def main():
                 "traffic": None if traffic is None else traffic["bytes_per_launch"],
                 "traffic_detail": traffic,
                 "kernel": ctx.step_kernel_name(), "tile_z": tz_used, "tile_loop": loop_used,
-                "us_per_launch": round(step_ms * 1e3 / launches, 3),
-                "launches_per_step": launches, "bytes_per_cell": b_alg,
+                "us_per_launch": round(step_ms * 1e3 * spl_used / launches, 3),
+                "steps_per_launch": spl_used,
+                "launches_per_step": launches if spl_used == 1 else round(launches / spl_used, 4),
+                "bytes_per_cell": b_alg,
                 "cells_per_launch": cells}
 
     # cell-updates in one solve: (2K + 1) full propagations, 2 (K + 1) slab;

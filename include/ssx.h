@@ -346,17 +346,23 @@ ssx_status ssx_lambda(ssx_ctx* ctx, int32_t side, int32_t transpose, const void*
  *                       and the thin slab: 8, 16 or 32 (32 not for F64
  *                       fields); 0 picks a default from the grid size.
  *   SSX_OPT_TILE_Z_SLAB the same for the thin slab only.
- *   SSX_OPT_STEPS_PER_LAUNCH      time steps per launch of the fused
- *                       kernel on the full grid: 1 (the only value).
- *   SSX_OPT_STEPS_PER_LAUNCH_SLAB the same for the thin slab: 1 (default),
- *                       4 or 8 (not for F64 fields, slabs of at most 56
- *                       rows): each workgroup holds the whole slab height
- *                       of a strip of columns in LDS and advances it 4 or
- *                       8 steps, recomputing an x halo of that many
- *                       stencil reaches on each side.
- *   SSX_OPT_SLAB_STRIP  strip width in columns of the 4/8-step slab kernel,
- *                       halo included: 64 or 128 (0, the default: 128;
- *                       8 steps always use 128).
+ *   SSX_OPT_STEPS_PER_LAUNCH      time steps per launch on the full
+ *                       grid: 1 (default), the fused one-step kernel; 2, 4
+ *                       or 8, the multi-step kernel: each workgroup holds
+ *                       a region of at most 56 rows and one strip of
+ *                       columns in LDS and advances it that many steps,
+ *                       recomputing a halo of that many stencil reaches
+ *                       on each side; a grid taller than 56 rows is cut
+ *                       into overlapping windows (order 4: 2, 4 or 8
+ *                       steps; order 8: 2 steps, or any of them for a grid
+ *                       of at most 56 rows).  Constant density only; F64
+ *                       fields need 64-column strips.
+ *   SSX_OPT_STEPS_PER_LAUNCH_SLAB the same for the thin slabs.
+ *   SSX_OPT_STRIP       strip width in columns of the multi-step kernel on
+ *                       the full grid, halo included: 64 or 128; 0 (the
+ *                       default): 64 for F64 fields, else 128.  Order 8
+ *                       with 8 steps needs 128.
+ *   SSX_OPT_SLAB_STRIP  the same for the thin slabs.
  *   SSX_OPT_SHOT_GROUP  shots advanced together by one launch on the full
  *                       grid and the thin slab: the shots are split into
  *                       balanced groups of at most this many, and each
@@ -380,7 +386,9 @@ ssx_status ssx_lambda(ssx_ctx* ctx, int32_t side, int32_t transpose, const void*
  *                       F, W_d and F^T, and joins it into the context's
  *                       stream before summing; 0: all on the context's
  *                       stream.
- * Returns SSX_ERR_ARG for an unknown option or value. */
+ * Returns SSX_ERR_ARG for an unknown option or value, or a value that does
+ * not combine with the context's problem or with the other options set
+ * (steps per launch and strip width are checked together). */
 typedef enum {
   SSX_OPT_GRAPHS = 0,
   SSX_OPT_STEP_KERNEL = 1,
@@ -392,7 +400,8 @@ typedef enum {
   SSX_OPT_SHOT_GROUP_SLAB = 7,
   SSX_OPT_SLAB_STRIP = 8,
   SSX_OPT_TILE_LOOP = 9,
-  SSX_OPT_OVERLAP = 10
+  SSX_OPT_OVERLAP = 10,
+  SSX_OPT_STRIP = 11
 } ssx_option;
 ssx_status ssx_set_option(ssx_ctx* ctx, int option, int value);
 

@@ -48,6 +48,7 @@ OPT_STEPS_PER_LAUNCH, OPT_STEPS_PER_LAUNCH_SLAB = 4, 5
 OPT_SHOT_GROUP, OPT_SHOT_GROUP_SLAB, OPT_SLAB_STRIP = 6, 7, 8
 OPT_TILE_LOOP = 9
 OPT_OVERLAP = 10
+OPT_STRIP = 11
 
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_CFL", 3: "ERR_OOM", 4: "ERR_HIP",
           5: "ERR_BREAKDOWN", 6: "ERR_NONFINITE"}

@@ -1,12 +1,13 @@
-"""Execution-shape autotuner for the fused time-step kernel.
+"""Execution-shape autotuner for the time-step kernels.
 
 For a problem shape (padded grid, stencil order, storage type, shots) it
 times, on a short copy of the problem (same grid, same shots, few time
 steps) and under captured graphs as the solver runs them, first the
-candidate (steps per launch, tile height) pairs of the fused step and the
-split two-launch step, then the number of shots advanced per launch, for
-the full grid and the thin slab separately, and applies the fastest choice
-to a context.  Results are cached in a JSON file keyed by shape, never by
+launch forms of each grid -- the fused one-step kernel at each tile height,
+with and without the tile loop, the multi-step kernel at each (steps per
+launch, strip width) it runs on that grid, and the split two-launch step --
+then the number of shots advanced per launch, for the full grid and the
+thin slab separately, and applies the fastest choice to a context.  Results are cached in a JSON file keyed by shape, never by
 the data or the mix of other work, so a given shape always runs the same
 kernels (results do not depend on the choice: every variant evaluates the
 same expressions).
@@ -20,12 +21,31 @@ import threading
 import numpy as np
 
 from . import (OPT_SHOT_GROUP, OPT_SHOT_GROUP_SLAB, OPT_SLAB_STRIP, OPT_STEP_KERNEL,
-               OPT_STEPS_PER_LAUNCH, OPT_STEPS_PER_LAUNCH_SLAB, OPT_TILE_LOOP, OPT_TILE_Z,
-               OPT_TILE_Z_SLAB,
+               OPT_STEPS_PER_LAUNCH, OPT_STEPS_PER_LAUNCH_SLAB, OPT_STRIP, OPT_TILE_LOOP,
+               OPT_TILE_Z, OPT_TILE_Z_SLAB,
                Context)
 
-DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ssx", "autotune-v6.json")
-SLAB_MAXZ = 56  # tallest slab the 4/8-step slab kernel holds
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ssx", "autotune-v7.json")
+SLAB_MAXZ = 56  # rows of one region of the multi-step kernel
+
+
+def multi_shapes(order: int, field_dtype: str, nz_rows: int) -> list:
+    """(steps per launch, strip width) pairs of the multi-step kernel that
+    can run on a grid of nz_rows rows: owned columns left after the halo of
+    ns stencil reaches (rounded up to 4) on each side, 64-column strips for
+    F64 fields, and owned rows left in each window of a taller grid."""
+    out = []
+    for ns in (2, 4, 8):
+        for wr in (64, 128):
+            if field_dtype == "f64" and wr != 64:
+                continue
+            halo = -(-ns * (order - 1) // 4) * 4
+            if wr - 2 * halo <= 0:
+                continue
+            if nz_rows > SLAB_MAXZ and SLAB_MAXZ - 2 * ns * (order - 1) <= 0:
+                continue
+            out.append((ns, wr))
+    return out
 _lock = threading.Lock()
 
 
@@ -113,53 +133,59 @@ def tune(prob, kappa, rho, xs=None, field_dtype="f32", nt_tune: int = 60,
         cands = [(1, 8), (1, 16)]
     else:
         cands = [(1, 8), (1, 16), (1, 32)]
-    # slab candidates: the same, plus the multi-step slab kernel
-    # (steps, strip width) with the tile height of its one-step remainder
-    slab_cands = [(spl, tz, 0) for spl, tz in cands]
-    # full-grid candidates: one-step launches also with workgroups looping
-    # over the interior tiles (constant density only, as the multi-step slab
-    # kernel)
+    # candidates on each grid: (steps per launch, tile height, tile loop,
+    # strip width).  One-step launches at every tile height, on the full
+    # grid also with workgroups looping over the interior tiles; the
+    # multi-step kernel at each (steps, strip width) it runs on that grid,
+    # with tile height 8 for the one-step remainder (constant density only)
     vrho = np.ndim(rho) != 0
-    full_cands = [(spl, tz, 0) for spl, tz in cands]
+    full_cands = [(1, tz, 0, 0) for _, tz in cands]
+    slab_cands = [(1, tz, 0, 0) for _, tz in cands]
     if not vrho:
-        full_cands += [(1, tz, 1) for spl, tz in cands if spl == 1]
-    if field_dtype != "f64" and tallest_slab(short) <= SLAB_MAXZ and not vrho:
-        slab_cands += [(4, 8, 64), (4, 8, 128), (8, 8, 128)]
+        full_cands += [(1, tz, 1, 0) for _, tz in cands]
+        full_cands += [(ns, 8, 0, wr) for ns, wr in multi_shapes(short.order, field_dtype, NZ)]
+        slab_cands += [(ns, 8, 0, wr)
+                       for ns, wr in multi_shapes(short.order, field_dtype, tallest_slab(short))]
+    key_f = lambda c: f"full_s{c[0]}_tz{c[1]}_l{c[2]}_w{c[3]}"  # noqa: E731
+    key_s = lambda c: f"slab_s{c[0]}_tz{c[1]}_w{c[3]}"          # noqa: E731
+
+    def set_full(c):
+        # strip back to its default first: steps and strip are checked together
+        ctx.set_option(OPT_STRIP, 0)
+        ctx.set_option(OPT_TILE_Z, c[1])
+        ctx.set_option(OPT_STEPS_PER_LAUNCH, c[0])
+        ctx.set_option(OPT_STRIP, c[3])
+        ctx.set_option(OPT_TILE_LOOP, c[2])
+
+    def set_slab(c):
+        ctx.set_option(OPT_SLAB_STRIP, 0)
+        ctx.set_option(OPT_TILE_Z_SLAB, c[1])
+        ctx.set_option(OPT_STEPS_PER_LAUNCH_SLAB, c[0])
+        ctx.set_option(OPT_SLAB_STRIP, c[3])
+
     us = {}
     ctx.set_option(OPT_STEP_KERNEL, 1)
     ctx.set_option(OPT_SHOT_GROUP, 0)
     auto_group = max(1, ctx.cells_per_launch() // (NZ * NX))
-    for spl, tz, loop in full_cands:
-        ctx.set_option(OPT_TILE_Z, tz)
-        ctx.set_option(OPT_STEPS_PER_LAUNCH, spl)
-        ctx.set_option(OPT_TILE_LOOP, loop)
-        us[f"full_s{spl}_tz{tz}_l{loop}"] = 1e3 * _time_ms(full, ctx.stream) / (2 * nt)
-    ctx.set_option(OPT_STEPS_PER_LAUNCH, 1)
-    ctx.set_option(OPT_TILE_LOOP, 0)
-    for spl, tz, strip in slab_cands:
-        ctx.set_option(OPT_TILE_Z_SLAB, tz)
-        ctx.set_option(OPT_STEPS_PER_LAUNCH_SLAB, spl)
-        ctx.set_option(OPT_SLAB_STRIP, strip)
-        us[f"slab_s{spl}_tz{tz}_w{strip}"] = 1e3 * _time_ms(slab, ctx.stream) / (2 * nt)
-    ctx.set_option(OPT_STEPS_PER_LAUNCH_SLAB, 1)
-    ctx.set_option(OPT_SLAB_STRIP, 0)
-    ctx.set_option(OPT_STEPS_PER_LAUNCH, 1)
+    for c in full_cands:
+        set_full(c)
+        us[key_f(c)] = 1e3 * _time_ms(full, ctx.stream) / (2 * nt)
+    set_full((1, 8, 0, 0))
+    for c in slab_cands:
+        set_slab(c)
+        us[key_s(c)] = 1e3 * _time_ms(slab, ctx.stream) / (2 * nt)
+    set_slab((1, 8, 0, 0))
     ctx.set_option(OPT_STEP_KERNEL, 0)
     us["full_split"] = 1e3 * _time_ms(full, ctx.stream) / (2 * nt)
     us["slab_split"] = 1e3 * _time_ms(slab, ctx.stream) / (2 * nt)
-    best_full = min(full_cands, key=lambda c: us[f"full_s{c[0]}_tz{c[1]}_l{c[2]}"])
-    best_slab = min(slab_cands, key=lambda c: us[f"slab_s{c[0]}_tz{c[1]}_w{c[2]}"])
-    fused_total = us[f"full_s{best_full[0]}_tz{best_full[1]}_l{best_full[2]}"] + \
-        us[f"slab_s{best_slab[0]}_tz{best_slab[1]}_w{best_slab[2]}"]
+    best_full = min(full_cands, key=lambda c: us[key_f(c)])
+    best_slab = min(slab_cands, key=lambda c: us[key_s(c)])
+    fused_total = us[key_f(best_full)] + us[key_s(best_slab)]
     split_total = us["full_split"] + us["slab_split"]
     step_kernel = 1 if fused_total <= split_total else 0
     ctx.set_option(OPT_STEP_KERNEL, step_kernel)
-    ctx.set_option(OPT_TILE_Z, best_full[1])
-    ctx.set_option(OPT_TILE_Z_SLAB, best_slab[1])
-    ctx.set_option(OPT_STEPS_PER_LAUNCH, best_full[0])
-    ctx.set_option(OPT_TILE_LOOP, best_full[2])
-    ctx.set_option(OPT_STEPS_PER_LAUNCH_SLAB, best_slab[0])
-    ctx.set_option(OPT_SLAB_STRIP, best_slab[2])
+    set_full(best_full)
+    set_slab(best_slab)
     group, group_slab = auto_group, 0
     if ns > 1:
         for gsz in _group_candidates(auto_group, ns):
@@ -170,9 +196,9 @@ def tune(prob, kappa, rho, xs=None, field_dtype="f32", nt_tune: int = 60,
     ctx.close()
     return {"step_kernel": step_kernel,
             "steps_per_launch": best_full[0], "tile_z": best_full[1], "tile_loop": best_full[2],
-            "shot_group": group,
+            "strip": best_full[3], "shot_group": group,
             "steps_per_launch_slab": best_slab[0], "tile_z_slab": best_slab[1],
-            "slab_strip": best_slab[2], "shot_group_slab": group_slab, "us": us}
+            "slab_strip": best_slab[3], "shot_group_slab": group_slab, "us": us}
 
 
 def choose(prob, kappa, rho, xs=None, field_dtype="f32", cache_path: str | None = DEFAULT_CACHE,
@@ -200,9 +226,14 @@ def apply(ctx: Context, choice: dict) -> None:
     ctx.set_option(OPT_STEP_KERNEL, int(choice["step_kernel"]))
     ctx.set_option(OPT_TILE_Z, int(choice["tile_z"]))
     ctx.set_option(OPT_TILE_Z_SLAB, int(choice["tile_z_slab"]))
+    # steps per launch and strip width are checked together: strips back to
+    # their defaults first
+    ctx.set_option(OPT_STRIP, 0)
+    ctx.set_option(OPT_SLAB_STRIP, 0)
     ctx.set_option(OPT_STEPS_PER_LAUNCH, int(choice.get("steps_per_launch", 1)))
     ctx.set_option(OPT_STEPS_PER_LAUNCH_SLAB, int(choice.get("steps_per_launch_slab", 1)))
+    ctx.set_option(OPT_STRIP, int(choice.get("strip", 0)))
+    ctx.set_option(OPT_SLAB_STRIP, int(choice.get("slab_strip", 0)))
     ctx.set_option(OPT_SHOT_GROUP, int(choice.get("shot_group", 0)))
     ctx.set_option(OPT_SHOT_GROUP_SLAB, int(choice.get("shot_group_slab", 0)))
-    ctx.set_option(OPT_SLAB_STRIP, int(choice.get("slab_strip", 0)))
     ctx.set_option(OPT_TILE_LOOP, int(choice.get("tile_loop", 0)))

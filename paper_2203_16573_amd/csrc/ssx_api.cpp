@@ -380,7 +380,8 @@ struct ssx_ctx {
   int tile_z_full = 0, tile_z_slab = 0;  // 0: default
   int spl_full = 1, spl_slab = 1;        // time steps per fused launch
   int group_full = 0, group_slab = 0;    // shots per launch (0: from the cache budget)
-  int slab_strip = 0;                    // strip width of the multi-step slab kernel (0: 128)
+  int slab_strip = 0;                    // strip width of the multi-step kernel, slab (0: default)
+  int strip_full = 0;                    // the same on the full grid
   int loop_full = 0;                     // full-grid one-step kernel: tile loop (0 off)
   hipStream_t cap_stream = nullptr;      // capture stream (graphs are launched on `run`)
   // stream that propagate() issues on: `stream`, or `aux` while the weighted
@@ -532,6 +533,30 @@ TraceIO io_out(void* out, long long stride, double scale) {
 
 int shot_group(const ssx_ctx* c, const GridDev& gd);
 
+// Strip width of the multi-step kernel: the option, else 64 columns for F64
+// fields (LDS) and 128 otherwise.
+int multi_strip(const ssx_ctx* c, bool full, int spl) {
+  (void)spl;
+  const int opt = full ? c->strip_full : c->slab_strip;
+  if (opt) return opt;
+  return c->fdt == Dt::F64 ? 64 : 128;
+}
+
+// Whether spl steps per launch (2, 4 or 8) on strips of wr columns can run on
+// a grid of NZ rows: constant density, a strip with owned columns left, 64
+// columns for F64 fields, and windows with owned rows for a grid taller than
+// SLAB_MAXZ.  Sets the error message and returns false otherwise.
+bool multi_ok(const ssx_ctx* c, int NZ, int spl, int wr) {
+  if (c->vrho) return fail(SSX_ERR_ARG, "several steps per launch take constant density only"), false;
+  if (slab_strip_width(c->prob.order, spl, wr) <= 0)
+    return fail(SSX_ERR_ARG, "no owned columns for these steps per launch and strip width"), false;
+  if (c->fdt == Dt::F64 && wr != 64)
+    return fail(SSX_ERR_ARG, "several steps per launch on F64 fields take 64-column strips"), false;
+  if (slab_windows(c->prob.order, spl, NZ) <= 0)
+    return fail(SSX_ERR_ARG, "the grid is too tall for these steps per launch"), false;
+  return true;
+}
+
 int default_tile_z(const ssx_ctx* c, const GridDev& gd) {
   // enough tiles to fill 256 CUs several times over, else shorter tiles
   const long long tiles32 = (long long)((gd.host.NX + 63) / 64) * ((gd.host.NZ + 31) / 32) *
@@ -641,13 +666,16 @@ ssx_status issue_group(ssx_ctx* c, GridDev& gd, bool adj, const Fields& f0, cons
   a.ngen = loop ? gd.ngen[li] : 0;
   a.nint = loop ? gd.nint[li] : 0;
   const int ntz1 = (gd.host.NZ + tz - 1) / tz;
-  // multi-step slab kernel: strip width (ns = 8 needs 128 columns)
-  const int wr = (spl == 8 || c->slab_strip == 0) ? 128 : c->slab_strip;
-  const int wown = spl >= 4 ? slab_strip_width(order, spl, wr) : 0;
+  // multi-step kernel: strip width, owned columns, windows
+  const int wr = multi_strip(c, is_full, spl);
+  const int wown = spl >= 2 ? slab_strip_width(order, spl, wr) : 0;
+  const int nwin = spl >= 2 ? slab_windows(order, spl, gd.host.NZ) : 0;
+  if (spl >= 2 && (wown <= 0 || nwin <= 0))
+    return fail(SSX_ERR_ARG, "steps per launch not available for this grid");
   Fields buf[2] = {f0, f1};
   int cur = 0;
-  // one launch covering `steps` (1, or 4 or 8 on a slab) steps starting at
-  // step n with the given level-0 trace indices
+  // one launch covering `steps` (1, or the multi-step kernel's 2, 4 or 8)
+  // steps starting at step n with the given level-0 trace indices
   auto launch = [&](int steps, int ivs, int ivi, int ips, int ipi) -> ssx_status {
     a.in = buf[cur];
     a.out = buf[1 - cur];
@@ -655,12 +683,12 @@ ssx_status issue_group(ssx_ctx* c, GridDev& gd, bool adj, const Fields& f0, cons
     a.vi = vi;
     a.ps = ps;
     a.pi = pi;
-    if (steps >= 4) {
+    if (steps >= 2) {
       a.vs.n = ivs;
       a.vi.n = ivi;
       a.ps.n = ips;
       a.pi.n = ipi;
-      a.ntz = 1;
+      a.ntz = nwin;
       a.ntx = (gd.host.NX + wown - 1) / wown;
       SSX_HIP(launch_slab(c->fdt, order, adj, steps, wr, a, s));
       a.ntx = (gd.host.NX + step_tile_width() - 1) / step_tile_width();
@@ -853,7 +881,7 @@ ssx_status propagate(ssx_ctx* c, int op, GridDev& gd, bool adj, const LineDev& v
   const bool full = &gd == &c->full;
   return cached_graph(c, op, key, full ? c->tile_z_full : c->tile_z_slab,
                       full ? c->spl_full : c->spl_slab, full ? c->group_full : c->group_slab,
-                      full ? 0 : c->slab_strip, full ? c->loop_full : 0,
+                      full ? c->strip_full : c->slab_strip, full ? c->loop_full : 0,
                       [&](hipStream_t s) {
                         return issue_propagation(c, gd, adj, vsl, vs, vil, vi, psl, ps, pil, pi,
                                                  s);
@@ -1679,27 +1707,45 @@ ssx_status ssx_set_option(ssx_ctx* c, int option, int value) {
       if (option == SSX_OPT_TILE_Z) c->tile_z_full = value;
       c->tile_z_slab = value;
       return SSX_OK;
-    case SSX_OPT_STEPS_PER_LAUNCH_SLAB:
-      if (value == 4 || value == 8) {
-        if (c->vrho)
-          return fail(SSX_ERR_ARG, "4 or 8 slab steps per launch take constant density only");
-        if (c->fdt == Dt::F64)
-          return fail(SSX_ERR_ARG, "4 or 8 slab steps per launch are not available for F64 fields");
-        if (c->slab.host.NZ > SLAB_MAXZ || (c->has_rslab && c->rslab.host.NZ > SLAB_MAXZ))
-          return fail(SSX_ERR_ARG, "the slab is too tall for 4 or 8 steps per launch");
-        c->spl_slab = value;
-        return SSX_OK;
-      }
-      [[fallthrough]];
     case SSX_OPT_STEPS_PER_LAUNCH:
-      if (value != 1) return fail(SSX_ERR_ARG, "steps per launch on the full grid must be 1");
-      if (option == SSX_OPT_STEPS_PER_LAUNCH) c->spl_full = value;
+      if (value != 1 && value != 2 && value != 4 && value != 8)
+        return fail(SSX_ERR_ARG, "steps per launch must be 1, 2, 4 or 8");
+      if (value > 1 && !multi_ok(c, c->full.host.NZ, value, multi_strip(c, true, value)))
+        return SSX_ERR_ARG;
+      c->spl_full = value;
+      return SSX_OK;
+    case SSX_OPT_STEPS_PER_LAUNCH_SLAB:
+      if (value != 1 && value != 2 && value != 4 && value != 8)
+        return fail(SSX_ERR_ARG, "steps per launch must be 1, 2, 4 or 8");
+      if (value > 1) {
+        const int wr = multi_strip(c, false, value);
+        if (!multi_ok(c, c->slab.host.NZ, value, wr)) return SSX_ERR_ARG;
+        if (c->has_rslab && !multi_ok(c, c->rslab.host.NZ, value, wr)) return SSX_ERR_ARG;
+      }
       c->spl_slab = value;
       return SSX_OK;
     case SSX_OPT_SLAB_STRIP:
+    case SSX_OPT_STRIP:
       if (value != 0 && value != 64 && value != 128)
-        return fail(SSX_ERR_ARG, "slab strip width must be 0, 64 or 128");
-      c->slab_strip = value;
+        return fail(SSX_ERR_ARG, "strip width must be 0, 64 or 128");
+      if (option == SSX_OPT_STRIP) {
+        const int old = c->strip_full;
+        c->strip_full = value;
+        if (c->spl_full > 1 &&
+            !multi_ok(c, c->full.host.NZ, c->spl_full, multi_strip(c, true, c->spl_full))) {
+          c->strip_full = old;
+          return SSX_ERR_ARG;
+        }
+      } else {
+        const int old = c->slab_strip;
+        c->slab_strip = value;
+        const int wr = multi_strip(c, false, c->spl_slab);
+        if (c->spl_slab > 1 && (!multi_ok(c, c->slab.host.NZ, c->spl_slab, wr) ||
+                                (c->has_rslab && !multi_ok(c, c->rslab.host.NZ, c->spl_slab, wr)))) {
+          c->slab_strip = old;
+          return SSX_ERR_ARG;
+        }
+      }
       return SSX_OK;
     case SSX_OPT_SHOT_GROUP:
     case SSX_OPT_SHOT_GROUP_SLAB:
@@ -1726,6 +1772,7 @@ const char* ssx_last_error(void) { return g_err.c_str(); }
 
 const char* ssx_step_kernel_name(ssx_ctx* c) {
   if (c && !c->fused) return "k_vel + k_pres";
+  if (c && c->spl_full > 1) return "k_slab";
   return "k_step";
 }
 

@@ -129,14 +129,20 @@ hipError_t launch_step(Dt dt, int order, bool adj, int tz, int loop, StepArgs a,
 void step_tile_lists(int order, int tz, const GridDims& g, const LineDev* const* lines,
                      int nlines, std::vector<int>* gen, std::vector<int>* inter);
 int step_tile_width();
-// Several time steps per launch on a slab grid of at most SLAB_MAXZ rows
-// (FP32, FP16 or BF16 fields): ns steps (4 or 8) on strips of wr columns
-// (64 or 128; ns = 8 needs 128) held whole in LDS.  a.ntx must be the strip
-// count ceil(NX / slab_strip_width(order, ns, wr)) and a.ntz 1.
+// Several time steps per launch (ssx_slab.hip): ns steps (2, 4 or 8) on
+// strips of wr columns (64 or 128; F64 fields 64 only) and windows of at
+// most SLAB_MAXZ rows held whole in LDS.  a.ntx must be the strip count
+// ceil(NX / slab_strip_width(order, ns, wr)) and a.ntz the window count
+// slab_windows(order, ns, NZ): 1 for a grid of at most SLAB_MAXZ rows, else
+// windows owning slab_window_rows(order, ns) rows each.
 constexpr int SLAB_MAXZ = 56;
 hipError_t launch_slab(Dt dt, int order, bool adj, int ns, int wr, StepArgs a, hipStream_t s);
 // owned columns per strip (0 for an unsupported combination)
 int slab_strip_width(int order, int ns, int wr);
+// owned rows per window of a taller grid (<= 0: no windows for ns steps)
+int slab_window_rows(int order, int ns);
+// windows of a grid of NZ rows (0: too tall for ns steps per launch)
+int slab_windows(int order, int ns, int NZ);
 // All return hipSuccess or the launch error.
 hipError_t launch_vel(Dt dt, int order, bool adj, const Fields& f, const GridDims& g,
                       const Coef& c, const LineDev& samp_line, const TraceIO& samp,

@@ -131,8 +131,9 @@ def test_density_fused_equals_split_bitwise(fd):
         fused = run()
         for a, b in zip(split, fused):
             assert np.array_equal(a, b), (fd, tz)
-    # a density array keeps one tile per workgroup and one slab step per launch
-    for opt, val in ((ssx.OPT_TILE_LOOP, 1), (ssx.OPT_STEPS_PER_LAUNCH_SLAB, 4)):
+    # a density array keeps one tile per workgroup and one step per launch
+    for opt, val in ((ssx.OPT_TILE_LOOP, 1), (ssx.OPT_STEPS_PER_LAUNCH_SLAB, 4),
+                     (ssx.OPT_STEPS_PER_LAUNCH, 2)):
         with pytest.raises(ssx.SSXError):
             ctx.set_option(opt, val)
     ctx.close()

@@ -1,7 +1,9 @@
 """Execution variants of the HIP path must not change results: the fused
-one-launch step equals the split velocity/pressure launches bitwise (FP32 and
-FP64), tile heights agree bitwise, and captured-graph replays equal eager
-launches on every replay."""
+one-step launch equals the split velocity/pressure launches bitwise (every
+field type), tile heights agree bitwise, the multi-step kernel (several
+steps per launch on strips and row windows with recomputed halos) agrees
+bitwise on the full grid and on the slab, and captured-graph replays equal
+eager launches on every replay."""
 import numpy as np
 import pytest
 
@@ -11,6 +13,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 import paper_2203_16573_amd as ssx  # noqa: E402
+from paper_2203_16573_amd.autotune import multi_shapes, tallest_slab  # noqa: E402
 
 RHO = 1000.0
 
@@ -25,6 +28,12 @@ GEOMS = {
     # lines deep inside, part width: interior tiles above, between and below
     "deep": dict(nz=130, nx=300, z_src=603.0, x_src0=450.0, ns=150, z_rec=455.0,
                  x_rec0=1000.0, nr=170),
+    # pressure lines whose two interpolation rows (31/32 and 27/28 of the
+    # padded grid) lie on either side of the boundary between the owned rows
+    # of two windows of the multi-step kernel (32 rows owned per window at
+    # order 4 and 4 steps, 8 at 8 steps; 28 at order 8 and 2 steps)
+    "straddle": dict(nz=100, nx=200, z_src=215.0, x_src0=100.0, ns=120, z_rec=175.0,
+                     x_rec0=0.0, nr=200),
 }
 
 
@@ -38,6 +47,27 @@ def problem(order, geom="small", **kw):
 def kappa(prob, seed=1):
     c = np.random.default_rng(seed).uniform(1800.0, 2400.0, size=(prob.nz, prob.nx))
     return RHO * c * c
+
+
+def check_multistep(ctx, prob, fd, order, ref):
+    """Every (steps per launch, strip width) of the multi-step kernel on the
+    full grid, then on the slab, against ref bitwise."""
+    NZ = prob.nz + 2 * prob.npml
+    for opt_spl, opt_strip, rows, where in (
+            (ssx.OPT_STEPS_PER_LAUNCH, ssx.OPT_STRIP, NZ, "full"),
+            (ssx.OPT_STEPS_PER_LAUNCH_SLAB, ssx.OPT_SLAB_STRIP, tallest_slab(prob), "slab")):
+        shapes = multi_shapes(order, fd, rows)
+        assert shapes, (where, rows)
+        for spl, strip in shapes:
+            print(f"  multi-step {where} spl={spl} strip={strip}", flush=True)
+            ctx.set_option(opt_strip, 0)
+            ctx.set_option(opt_spl, spl)
+            ctx.set_option(opt_strip, strip)
+            got = run_all(ctx, prob, fd)
+            for i, (a, b) in enumerate(zip(ref, got)):
+                assert np.array_equal(a, b), (fd, order, where, spl, strip, i)
+        ctx.set_option(opt_strip, 0)
+        ctx.set_option(opt_spl, 1)
 
 
 def run_all(ctx, prob, fd, seed=0):
@@ -82,22 +112,27 @@ def test_fused_equals_split_bitwise(fd, order, nt, geom):
             for a, b in zip(split, looped):
                 assert np.array_equal(a, b), (fd, order, tz, "tile loop", loop)
         ctx.set_option(ssx.OPT_TILE_LOOP, 0)
-    # the full grid takes one step per launch only
-    with pytest.raises(ssx.SSXError):
-        ctx.set_option(ssx.OPT_STEPS_PER_LAUNCH, 2)
-    if fd != "f64":
-        # slab strips held in LDS over 4 or 8 steps (the odd record leaves a
-        # one-step remainder)
-        for spl, strip in ((4, 64), (4, 128), (8, 128)):
-            ctx.set_option(ssx.OPT_STEPS_PER_LAUNCH_SLAB, spl)
-            ctx.set_option(ssx.OPT_SLAB_STRIP, strip)
-            multi = run_all(ctx, prob, fd)
-            for i, (a, b) in enumerate(zip(split, multi)):
-                assert np.array_equal(a, b), (fd, order, "slab", spl, strip, i)
-        ctx.set_option(ssx.OPT_STEPS_PER_LAUNCH_SLAB, 1)
-    else:
-        with pytest.raises(ssx.SSXError):
-            ctx.set_option(ssx.OPT_STEPS_PER_LAUNCH_SLAB, 4)
+    # regions held in LDS over several steps, on the full grid (row windows
+    # where it is taller than one region) and on the slab; the odd record
+    # leaves a one-step remainder
+    check_multistep(ctx, prob, fd, order, split)
+    ctx.close()
+
+
+@pytest.mark.parametrize("fd", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("order", [4, 8])
+def test_multistep_windows_lines_across_boundaries(fd, order):
+    # lines whose interpolation rows lie in two windows' owned rows: each
+    # window injects what falls in its region, the window owning the first
+    # row samples
+    prob = problem(order, "straddle", nt=123)
+    print(f"case multi-step straddle order={order} dtype={fd}", flush=True)
+    ctx = ssx.Context(prob, kappa(prob, 2), RHO, field_dtype=fd)
+    ctx.set_graphs(False)
+    ctx.set_option(ssx.OPT_STEP_KERNEL, 0)
+    split = run_all(ctx, prob, fd)
+    ctx.set_option(ssx.OPT_STEP_KERNEL, 1)
+    check_multistep(ctx, prob, fd, order, split)
     ctx.close()
 
 
@@ -131,12 +166,27 @@ def test_graph_replays_equal_eager(fd):
 def test_options_rejected():
     prob = problem(8)
     ctx = ssx.Context(prob, kappa(prob), RHO, field_dtype="f64")
+    # (order 8, F64 fields, 57 rows: windows of 2 steps only, 64-column
+    # strips only)
     for opt, val in ((ssx.OPT_TILE_Z, 32), (ssx.OPT_TILE_Z, 12), (ssx.OPT_STEP_KERNEL, 2),
-                     (ssx.OPT_STEPS_PER_LAUNCH, 2), (ssx.OPT_STEPS_PER_LAUNCH, 3),
+                     (ssx.OPT_STEPS_PER_LAUNCH, 3), (ssx.OPT_STEPS_PER_LAUNCH, 4),
+                     (ssx.OPT_STEPS_PER_LAUNCH, 8), (ssx.OPT_STEPS_PER_LAUNCH_SLAB, 8),
                      (ssx.OPT_TILE_LOOP, 2), (ssx.OPT_TILE_LOOP, 7), (ssx.OPT_TILE_LOOP, -1),
-                     (ssx.OPT_SLAB_STRIP, 96), (ssx.OPT_SHOT_GROUP, -1), (99, 1)):
+                     (ssx.OPT_SLAB_STRIP, 96), (ssx.OPT_STRIP, 96), (ssx.OPT_SHOT_GROUP, -1),
+                     (99, 1)):
         with pytest.raises(ssx.SSXError):
             ctx.set_option(opt, val)
+    # steps per launch and strip width are checked together, and a rejected
+    # value leaves the previous one in place
+    ctx.set_option(ssx.OPT_STEPS_PER_LAUNCH, 2)
+    with pytest.raises(ssx.SSXError):
+        ctx.set_option(ssx.OPT_STRIP, 128)
+    assert ctx.launch_shape()[1] == 2
+    ctx.set_option(ssx.OPT_STEPS_PER_LAUNCH, 1)
+    ctx.set_option(ssx.OPT_STRIP, 128)     # allowed while one step per launch
+    with pytest.raises(ssx.SSXError):
+        ctx.set_option(ssx.OPT_STEPS_PER_LAUNCH, 2)
+    ctx.set_option(ssx.OPT_STRIP, 0)
     # the tile-loop setting is reported in the launch shape (a cap of 8 or
     # more is kept as given)
     for val in (0, 1, 8, 100):
@@ -180,7 +230,7 @@ def test_autotune_choice_applies_and_keeps_results():
     print("case autotune wide f32", flush=True)
     kap = kappa(prob)
     choice = autotune.choose(prob, kap, RHO, field_dtype="f32", cache_path=None, nt_tune=20)
-    for key in ("step_kernel", "steps_per_launch", "tile_z", "tile_loop", "shot_group",
+    for key in ("step_kernel", "steps_per_launch", "tile_z", "tile_loop", "strip", "shot_group",
                 "steps_per_launch_slab", "tile_z_slab", "slab_strip", "shot_group_slab"):
         assert key in choice, key
     assert 1 <= choice["shot_group"] <= 3
@@ -189,8 +239,7 @@ def test_autotune_choice_applies_and_keeps_results():
     autotune.apply(ctx, choice)
     tz, spl, grp, loop = ctx.launch_shape()
     if choice["step_kernel"] == 1:
-        assert (tz, spl) == ((8 if choice["steps_per_launch"] == 2 else choice["tile_z"]),
-                             choice["steps_per_launch"])
+        assert (tz, spl) == (choice["tile_z"], choice["steps_per_launch"])
         assert loop == (choice["tile_loop"] if spl == 1 else 0)
     assert grp == choice["shot_group"]
     assert ctx.cells_per_launch() == (prob.nz + 20) * (prob.nx + 20) * grp
