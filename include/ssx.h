@@ -355,13 +355,13 @@ ssx_status ssx_lambda(ssx_ctx* ctx, int32_t side, int32_t transpose, const void*
  *                       on each side; a grid taller than 56 rows is cut
  *                       into overlapping windows (order 4: 2, 4 or 8
  *                       steps; order 8: 2 steps, or any of them for a grid
- *                       of at most 56 rows).  Constant density only; F64
- *                       fields need 64-column strips.
+ *                       of at most 56 rows).  F64 fields and density
+ *                       arrays take 64-column strips.
  *   SSX_OPT_STEPS_PER_LAUNCH_SLAB the same for the thin slabs.
  *   SSX_OPT_STRIP       strip width in columns of the multi-step kernel on
  *                       the full grid, halo included: 64 or 128; 0 (the
- *                       default): 64 for F64 fields, else 128.  Order 8
- *                       with 8 steps needs 128.
+ *                       default): 64 for F64 fields and density arrays,
+ *                       else 128.  Order 8 with 8 steps needs 128.
  *   SSX_OPT_SLAB_STRIP  the same for the thin slabs.
  *   SSX_OPT_SHOT_GROUP  shots advanced together by one launch on the full
  *                       grid and the thin slab: the shots are split into

@@ -29,15 +29,17 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ssx", "autotune
 SLAB_MAXZ = 56  # rows of one region of the multi-step kernel
 
 
-def multi_shapes(order: int, field_dtype: str, nz_rows: int) -> list:
+def multi_shapes(order: int, field_dtype: str, nz_rows: int,
+                 variable_density: bool = False) -> list:
     """(steps per launch, strip width) pairs of the multi-step kernel that
     can run on a grid of nz_rows rows: owned columns left after the halo of
     ns stencil reaches (rounded up to 4) on each side, 64-column strips for
-    F64 fields, and owned rows left in each window of a taller grid."""
+    F64 fields and density arrays, and owned rows left in each window of a
+    taller grid."""
     out = []
     for ns in (2, 4, 8):
         for wr in (64, 128):
-            if field_dtype == "f64" and wr != 64:
+            if (field_dtype == "f64" or variable_density) and wr != 64:
                 continue
             halo = -(-ns * (order - 1) // 4) * 4
             if wr - 2 * halo <= 0:
@@ -137,15 +139,16 @@ def tune(prob, kappa, rho, xs=None, field_dtype="f32", nt_tune: int = 60,
     # strip width).  One-step launches at every tile height, on the full
     # grid also with workgroups looping over the interior tiles; the
     # multi-step kernel at each (steps, strip width) it runs on that grid,
-    # with tile height 8 for the one-step remainder (constant density only)
+    # with tile height 8 for the one-step remainder (the tile loop: constant
+    # density only)
     vrho = np.ndim(rho) != 0
     full_cands = [(1, tz, 0, 0) for _, tz in cands]
     slab_cands = [(1, tz, 0, 0) for _, tz in cands]
     if not vrho:
         full_cands += [(1, tz, 1, 0) for _, tz in cands]
-        full_cands += [(ns, 8, 0, wr) for ns, wr in multi_shapes(short.order, field_dtype, NZ)]
-        slab_cands += [(ns, 8, 0, wr)
-                       for ns, wr in multi_shapes(short.order, field_dtype, tallest_slab(short))]
+    full_cands += [(ns, 8, 0, wr) for ns, wr in multi_shapes(short.order, field_dtype, NZ, vrho)]
+    slab_cands += [(ns, 8, 0, wr)
+                   for ns, wr in multi_shapes(short.order, field_dtype, tallest_slab(short), vrho)]
     key_f = lambda c: f"full_s{c[0]}_tz{c[1]}_l{c[2]}_w{c[3]}"  # noqa: E731
     key_s = lambda c: f"slab_s{c[0]}_tz{c[1]}_w{c[3]}"          # noqa: E731
 

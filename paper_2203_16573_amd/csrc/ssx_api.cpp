@@ -534,20 +534,22 @@ TraceIO io_out(void* out, long long stride, double scale) {
 int shot_group(const ssx_ctx* c, const GridDev& gd);
 
 // Strip width of the multi-step kernel: the option, else 64 columns for F64
-// fields (LDS) and 128 otherwise.
+// fields (LDS) and density arrays, 128 otherwise.
 int multi_strip(const ssx_ctx* c, bool full, int spl) {
   (void)spl;
   const int opt = full ? c->strip_full : c->slab_strip;
   if (opt) return opt;
-  return c->fdt == Dt::F64 ? 64 : 128;
+  return (c->fdt == Dt::F64 || c->vrho) ? 64 : 128;
 }
 
 // Whether spl steps per launch (2, 4 or 8) on strips of wr columns can run on
-// a grid of NZ rows: constant density, a strip with owned columns left, 64
-// columns for F64 fields, and windows with owned rows for a grid taller than
-// SLAB_MAXZ.  Sets the error message and returns false otherwise.
+// a grid of NZ rows: a strip with owned columns left, 64 columns for F64
+// fields and density arrays, and windows with owned rows for a grid taller
+// than SLAB_MAXZ.  Sets the error message and returns false otherwise.
 bool multi_ok(const ssx_ctx* c, int NZ, int spl, int wr) {
-  if (c->vrho) return fail(SSX_ERR_ARG, "several steps per launch take constant density only"), false;
+  if (c->vrho && wr != 64)
+    return fail(SSX_ERR_ARG, "several steps per launch with a density array take 64-column strips"),
+           false;
   if (slab_strip_width(c->prob.order, spl, wr) <= 0)
     return fail(SSX_ERR_ARG, "no owned columns for these steps per launch and strip width"), false;
   if (c->fdt == Dt::F64 && wr != 64)

@@ -130,7 +130,8 @@ void step_tile_lists(int order, int tz, const GridDims& g, const LineDev* const*
                      int nlines, std::vector<int>* gen, std::vector<int>* inter);
 int step_tile_width();
 // Several time steps per launch (ssx_slab.hip): ns steps (2, 4 or 8) on
-// strips of wr columns (64 or 128; F64 fields 64 only) and windows of at
+// strips of wr columns (64 or 128; F64 fields and density arrays, a.c.cbx
+// set, 64 only) and windows of at
 // most SLAB_MAXZ rows held whole in LDS.  a.ntx must be the strip count
 // ceil(NX / slab_strip_width(order, ns, wr)) and a.ntz the window count
 // slab_windows(order, ns, NZ): 1 for a grid of at most SLAB_MAXZ rows, else

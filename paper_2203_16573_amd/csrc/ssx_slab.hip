@@ -97,13 +97,16 @@ int slab_owned_width() {
   return SlabShape<K, NS, WR, 1024>::W;
 }
 
-template <int K, bool ADJ, typename T, int NS, int WR>
+// VR: a density array, the velocity coefficient of every v_x and v_z cell
+// read once per launch into registers (64-column strips only)
+template <int K, bool ADJ, typename T, int NS, int WR, bool VR = false>
 __global__ __launch_bounds__(slab_threads<typename Tr<T>::C>()) void k_slab(StepArgs a) {
   using C = typename Tr<T>::C;
   using V = typename Tr<T>::V;
   constexpr int SLAB_THREADS = slab_threads<C>();
   using S = SlabShape<K, NS, WR, SLAB_THREADS>;
   static_assert(!std::is_same<C, double>::value || S::CONE, "F64 fields: 64-column strips");
+  static_assert(!VR || S::CONE, "variable density: 64-column strips");
   constexpr int H = S::H, W = S::W, RP = S::RP, G = S::G, NQ = S::NQ, NQS = S::NQS;
   constexpr int ZP = S::ZP, R = S::R;
   // region rows are 0 .. SLAB_MAXZ-1 (region row I is grid row zr + I)
@@ -216,19 +219,32 @@ __global__ __launch_bounds__(slab_threads<typename Tr<T>::C>()) void k_slab(Step
       if constexpr (!S::CONE) lck[k] = *reinterpret_cast<const V4<C>*>(ckp + o);
     }
   }
-  // CONE: ck of the cells this thread updates at every step (row tid & 63
-  // of the region, column group (tid >> 6) + NWV k)
-  C ckr[NQS][4];
+  // CONE: ck (VR: and the velocity coefficients) of the cells this thread
+  // updates at every step (row tid & 63 of the region, column group
+  // (tid >> 6) + NWV k)
+  C ckr[NQS][4], cbxr[NQS][4], cbzr[NQS][4];
   if constexpr (S::CONE) {
+    const C* bxp = VR ? static_cast<const C*>(a.c.cbx) + a.g.origin : nullptr;
+    const C* bzp = VR ? static_cast<const C*>(a.c.cbz) + a.g.origin : nullptr;
 #pragma unroll
     for (int k = 0; k < NQS; ++k) {
       const int g = (tid >> 6) + S::NWV * k, I = tid & 63, Ig = zr + I, J = xr + 4 * g;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) ckr[k][e] = C(0);
+      for (int e = 0; e < 4; ++e) ckr[k][e] = cbxr[k][e] = cbzr[k][e] = C(0);
       if (g < G && I < SLAB_MAXZ && Ig >= 0 && Ig < NZ && J < NX) {
-        const V4<C> v = *reinterpret_cast<const V4<C>*>(ckp + (long long)Ig * Pt + J);
+        const long long o = (long long)Ig * Pt + J;
+        const V4<C> v = *reinterpret_cast<const V4<C>*>(ckp + o);
 #pragma unroll
         for (int e = 0; e < 4; ++e) ckr[k][e] = v.e[e];
+        if constexpr (VR) {
+          const V4<C> bx = *reinterpret_cast<const V4<C>*>(bxp + o);
+          const V4<C> bz = *reinterpret_cast<const V4<C>*>(bzp + o);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            cbxr[k][e] = bx.e[e];
+            cbzr[k][e] = bz.e[e];
+          }
+        }
       }
     }
   }
@@ -416,9 +432,14 @@ __global__ __launch_bounds__(slab_threads<typename Tr<T>::C>()) void k_slab(Step
           C sx = C(0);
 #pragma unroll
           for (int m = 1; m <= K; ++m) sx = acc(sx, wst<K, C>(m - 1), w[e + 4 + m], w[e + 5 - m]);
-          nvx[e] = rnd<T>(upd_v<ADJ>(axh[e], bxh[e], cb, ovx[e], sx, C(0)));
+          C cbx = cb, cbz = cb;
+          if constexpr (VR) {
+            cbx = cbxr[k][e];
+            cbz = cbzr[k][e];
+          }
+          nvx[e] = rnd<T>(upd_v<ADJ>(axh[e], bxh[e], cbx, ovx[e], sx, C(0)));
           const C src = src_row ? src_row[c + e] : C(0);
-          nvz[e] = rnd<T>(upd_v<ADJ>(azh, bzh, cb, ovz[e], sz[e], src));
+          nvz[e] = rnd<T>(upd_v<ADJ>(azh, bzh, cbz, ovz[e], sz[e], src));
         }
       }
       st4(svx + X_(I, c), nvx);
@@ -586,7 +607,7 @@ __global__ __launch_bounds__(slab_threads<typename Tr<T>::C>()) void k_slab(Step
 
 // ---------------------------------------------------------------------------
 
-template <int K, bool ADJ, typename T, int NS, int WR>
+template <int K, bool ADJ, typename T, int NS, int WR, bool VR = false>
 static hipError_t slab_go(const StepArgs& a, hipStream_t s) {
   using C = typename Tr<T>::C;
   using S = SlabShape<K, NS, WR, slab_threads<C>()>;
@@ -595,15 +616,24 @@ static hipError_t slab_go(const StepArgs& a, hipStream_t s) {
     return hipErrorInvalidValue;
   if (a.ntz == 1 ? a.g.NZ > SLAB_MAXZ : (S::OZ <= 0 || a.ntz != (a.g.NZ + S::OZ - 1) / S::OZ))
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_slab<K, ADJ, T, NS, WR>), dim3(a.ntx * a.ntz * a.nshots),
+  hipLaunchKernelGGL((k_slab<K, ADJ, T, NS, WR, VR>), dim3(a.ntx * a.ntz * a.nshots),
                      dim3(slab_threads<C>()), 0, s, a);
   return hipGetLastError();
 }
 
 // the (steps, strip width) pairs with owned columns left (order 8: 8 steps
-// need 128 columns); F64 fields 64-column strips only (LDS)
+// need 128 columns); F64 fields and density arrays 64-column strips only
 template <int K, bool ADJ, typename T>
 static hipError_t slab_t(int ns, int wr, const StepArgs& a, hipStream_t s) {
+  if (a.c.cbx) {
+    if (wr != 64) return hipErrorInvalidValue;
+    if (ns == 2) return slab_go<K, ADJ, T, 2, 64, true>(a, s);
+    if (ns == 4) return slab_go<K, ADJ, T, 4, 64, true>(a, s);
+    if constexpr (K == 2) {
+      if (ns == 8) return slab_go<K, ADJ, T, 8, 64, true>(a, s);
+    }
+    return hipErrorInvalidValue;
+  }
   if (ns == 2 && wr == 64) return slab_go<K, ADJ, T, 2, 64>(a, s);
   if (ns == 4 && wr == 64) return slab_go<K, ADJ, T, 4, 64>(a, s);
   if constexpr (K == 2) {
@@ -641,7 +671,6 @@ int slab_windows(int order, int ns, int NZ) {
 }
 
 hipError_t launch_slab(Dt dt, int order, bool adj, int ns, int wr, StepArgs a, hipStream_t s) {
-  if (a.c.cbx) return hipErrorInvalidValue;  // constant density only
   const bool o8 = (order == 8);
   switch (dt) {
     case Dt::F64:

@@ -6,7 +6,8 @@ at the pressure nodes, each velocity update using the mean density of its
 two nodes (the oracle's grid module; its pins fix the reflection and
 transmission of a density-only jump at second order).  Tolerances as the
 constant-density parity tests: FP64 1e-12 per propagation, FP32 1e-5; PCG
-1e-10 (FP64) and 1e-4 (FP32).
+1e-10 (FP64) and 1e-4 (FP32).  The multi-step kernel takes the density array on 64-column
+strips and agrees bitwise with the split kernels.
 """
 import numpy as np
 import pytest
@@ -18,6 +19,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 import paper_2203_16573_amd as ssx  # noqa: E402
+from paper_2203_16573_amd.autotune import multi_shapes, tallest_slab  # noqa: E402
 
 TOL = {"f64": 1e-12, "f32": 1e-5}
 
@@ -105,10 +107,11 @@ def test_density_pcg_parity(fd, tol):
 
 
 @pytest.mark.parametrize("fd", ["f64", "f32", "f16", "bf16"])
-def test_density_fused_equals_split_bitwise(fd):
-    prob = problem(8, nt=121)
+@pytest.mark.parametrize("order", [4, 8])
+def test_density_fused_equals_split_bitwise(fd, order):
+    prob = problem(order, nt=121)
     kappa, rho = model(prob, 4)
-    print(f"case density fused-vs-split {fd}", flush=True)
+    print(f"case density fused-vs-split {fd} order {order}", flush=True)
     ctx = ssx.Context(prob, kappa, rho, field_dtype=fd)
     ctx.set_graphs(False)
     dt = torch.float64 if fd == "f64" else torch.float32
@@ -131,11 +134,29 @@ def test_density_fused_equals_split_bitwise(fd):
         fused = run()
         for a, b in zip(split, fused):
             assert np.array_equal(a, b), (fd, tz)
-    # a density array keeps one tile per workgroup and one step per launch
-    for opt, val in ((ssx.OPT_TILE_LOOP, 1), (ssx.OPT_STEPS_PER_LAUNCH_SLAB, 4),
-                     (ssx.OPT_STEPS_PER_LAUNCH, 2)):
-        with pytest.raises(ssx.SSXError):
-            ctx.set_option(opt, val)
+    # several steps per launch on 64-column strips, on the full grid (row
+    # windows) and on the slab; the odd record leaves a one-step remainder
+    NZ = prob.nz + 2 * prob.npml
+    for opt_spl, opt_strip, rows in (
+            (ssx.OPT_STEPS_PER_LAUNCH, ssx.OPT_STRIP, NZ),
+            (ssx.OPT_STEPS_PER_LAUNCH_SLAB, ssx.OPT_SLAB_STRIP, tallest_slab(prob))):
+        shapes = multi_shapes(order, fd, rows, variable_density=True)
+        assert shapes and all(strip == 64 for _, strip in shapes)
+        for spl, strip in shapes:
+            print(f"  multi-step spl={spl} strip={strip} rows={rows}", flush=True)
+            ctx.set_option(opt_strip, 0)
+            ctx.set_option(opt_spl, spl)
+            ctx.set_option(opt_strip, strip)
+            for a, b in zip(split, run()):
+                assert np.array_equal(a, b), (fd, order, spl, strip, rows)
+        ctx.set_option(opt_strip, 0)
+        ctx.set_option(opt_spl, 1)
+    # a density array: one tile per workgroup, 64-column strips
+    with pytest.raises(ssx.SSXError):
+        ctx.set_option(ssx.OPT_TILE_LOOP, 1)
+    ctx.set_option(ssx.OPT_STEPS_PER_LAUNCH_SLAB, 2)
+    with pytest.raises(ssx.SSXError):
+        ctx.set_option(ssx.OPT_SLAB_STRIP, 128)
     ctx.close()
 
 
