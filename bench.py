@@ -52,6 +52,10 @@ def parse():
     ap.add_argument("--solver", default="plain", choices=["plain", "weighted"],
                     help="c1..c4: Algorithm 1 on the Euclidean normal equations (plain) or "
                          "on the weighted ones N_w h = F^T W_d d (weighted)")
+    ap.add_argument("--density", action="store_true",
+                    help="c1..c4: a density array from the velocity (Gardner's rule, "
+                         "about 1.9-2.6 g/cm^3 on these models) instead of the constant "
+                         "density, velocities unchanged")
     ap.add_argument("--alpha", type=float, default=1e-3,
                     help="weighted solver: penalty weight per metre")
     ap.add_argument("--iters", type=int, default=0,
@@ -175,6 +179,8 @@ def main():
         return varpro_bench(args)
     cnum = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "c4bf": 4}[args.config]
     wl = inputs.workload(cnum)
+    if args.density:
+        wl = inputs.with_gardner_density(wl)
     if args.nt:
         wl.prob = wl.prob.replace(nt=args.nt)
     if args.shots:
@@ -285,12 +291,13 @@ def main():
     fsz = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[fd]
     csz = 8 if fd == "f64" else 4
     # algorithmic bytes per cell-update: read p, v_x, v_z and kappa once,
-    # write p, v_x, v_z once
-    b_alg = 6 * fsz + csz
+    # write p, v_x, v_z once; a density array adds the two velocity
+    # coefficients
+    b_alg = 6 * fsz + csz * (3 if args.density else 1)
     achieved = b_alg * NZ * NX * prob.nshots / (step_ms * 1e-3) / 1e9
     tz_used, spl_used, _, loop_used = ctx.launch_shape()
-    traffic = measured_traffic(args.config, fd, prob.nshots, tz_used, group, loop_used,
-                               ctx.step_kernel_name())
+    traffic = None if args.density else measured_traffic(
+        args.config, fd, prob.nshots, tz_used, group, loop_used, ctx.step_kernel_name())
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else traffic["bytes_per_launch"],
@@ -338,7 +345,7 @@ def main():
                          f"extrapolated linearly to {cu_solve:.3e} cell-updates per solve",
                "cpu": cpu_model()}
         nproc = min(prob.nshots, args.cpu_procs, os.cpu_count() or 1)
-        if nproc > 1 and not (args.nt or args.shots):
+        if nproc > 1 and not (args.nt or args.shots or args.density):
             par = oracle_parallel(cnum, ns_cpu, nproc)
             if par:
                 pg = sum(ns_cpu * NZ * NX / t for t in par) / 1e9
@@ -405,6 +412,7 @@ def main():
         "config": {"workload": f"{wl.name}: {prob.nz}x{prob.nx} @ {prob.h} m, order "
                                f"{prob.order}, nt {prob.nt}, K {wl.K}, shots {prob.nshots}"
                                + (f", weighted, alpha {args.alpha}/m" if weighted else "")
+                               + (", density array (Gardner)" if args.density else "")
                                + (f", stop at ||r_k|| <= {args.rtol:g} ||r_0||"
                                   if args.rtol > 0 else ""),
                    "nz": prob.nz, "nx": prob.nx, "nt": prob.nt, "K": wl.K,
@@ -838,7 +846,7 @@ def oracle_golden_errors(cnum, wl, prob, h, hist, args, weighted):
     history (||r_k|| per iteration, and each column as a vector)."""
     import numpy as np
     import inputs
-    if weighted or args.rtol > 0 or args.nt or args.shots or args.iters:
+    if weighted or args.rtol > 0 or args.nt or args.shots or args.iters or args.density:
         return None
     name = {2: "c2_full_length.npz", 4: "c2_full_length.npz", 3: "c3_full_length.npz"}.get(cnum)
     if name is None:

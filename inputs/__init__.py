@@ -160,6 +160,17 @@ def kappa_from_velocity(vel: np.ndarray, rho: float = RHO_WATERLIKE) -> np.ndarr
     return rho * np.asarray(vel, dtype=np.float64) ** 2
 
 
+def with_gardner_density(wl: "Workload") -> "Workload":
+    """The same workload with a density array instead of the constant
+    density: rho = 310 v^(1/4) kg/m^3 (v in m/s, Gardner's empirical rule for
+    sedimentary rocks) from the workload's velocity, the velocity kept
+    (kappa = rho v^2)."""
+    vel = np.sqrt(np.asarray(wl.kappa, dtype=np.float64) / wl.rho)
+    rho = 310.0 * vel ** 0.25
+    return Workload(wl.name + "+rho", wl.prob, rho * vel ** 2, rho, wl.freq, wl.K,
+                    wl.alpha_rel, wl.dtype, dict(wl.extras))
+
+
 def homogeneous_kappa(nz: int, nx: int, c: float = 2000.0,
                       rho: float = RHO_WATERLIKE) -> np.ndarray:
     return np.full((nz, nx), rho * c * c)
