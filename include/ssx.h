@@ -229,6 +229,38 @@ ssx_status ssx_pcg_solve(ssx_ctx* ctx, const void* d, double alpha_rel, int32_t 
                          double rtol, int32_t use_precond, void* h_out,
                          double* hist_host, int32_t* iters_host);
 
+/* Heterogeneous batch (serving several requests at once): contexts of any
+ * grid sizes, record lengths, shot counts, lines and models -- one stencil
+ * order, one field type, one vector type, one stream -- solved together.
+ * ssx_batch_create takes n >= 1 distinct contexts (the batch keeps the
+ * pointers: destroy the batch before any of them; it owns no device memory
+ * beyond its captured graphs).  SSX_ERR_ARG for a null or repeated context
+ * or contexts that differ in order, types or stream.
+ *
+ * ssx_batch_pcg_solve runs Algorithm 1 for every member as ssx_pcg_solve
+ * does (d[i], h_out[i]: DEVICE, member i's layouts; alpha_rel[i] per member;
+ * hist_host[i]: HOST [nshots_i][maxit+1][4] or NULL, hist_host itself may
+ * be NULL; iters_host: HOST [n] or NULL), with its propagations merged:
+ * the members' solves advance in lockstep, and each propagation stage they
+ * reach together runs as one sequence of launches in which every time
+ * step advances every member's grid (members with shorter records drop out
+ * of the later steps), up to 6 grids per launch of the fused step kernel
+ * (tile height 16, one tile per workgroup, every shot of a member in the
+ * same launch).  Each member's results are bitwise those of its own
+ * ssx_pcg_solve, whatever its launch options (every launch form evaluates
+ * the same expressions).  A member stopping early (rtol, an error) leaves
+ * the lockstep; the others go on.  Synchronises the stream before
+ * returning; returns the first member's error, its message naming the
+ * member.  The members' own stream-ordered work must not run concurrently
+ * with the batch solve. */
+typedef struct ssx_batch ssx_batch;
+ssx_status ssx_batch_create(int32_t n, ssx_ctx* const* ctxs, ssx_batch** out);
+ssx_status ssx_batch_pcg_solve(ssx_batch* batch, const void* const* d, const double* alpha_rel,
+                               int32_t maxit, double rtol, int32_t use_precond,
+                               void* const* h_out, double* const* hist_host,
+                               int32_t* iters_host);
+void ssx_batch_destroy(ssx_batch* batch);
+
 /* ---- weighted normal equations (Accelerated Iterative Inversion, the
  * normpart system S* = S^T W_d, A* = A^T W_m; weights of Computing and
  * Symmetrizing Lambda).  All return SSX_ERR_ARG when the context was

@@ -59,7 +59,8 @@ EXPORTS = ("ssx_validate", "ssx_footprint", "ssx_create", "ssx_destroy", "ssx_fw
            "ssx_step_kernel_name", "ssx_cells_per_launch", "ssx_launch_shape",
            "ssx_weight_d", "ssx_weight_m", "ssx_normal_w", "ssx_pcg_solve_w",
            "ssx_fwd_v", "ssx_adj_v", "ssx_tr_inverse", "ssx_lambda", "ssx_block",
-           "ssx_misfit_gradient", "ssx_pcg_solve_v", "ssx_dot_static", "ssx_create_density")
+           "ssx_misfit_gradient", "ssx_pcg_solve_v", "ssx_dot_static", "ssx_create_density",
+           "ssx_batch_create", "ssx_batch_pcg_solve", "ssx_batch_destroy")
 
 DOT_STATIC_MAX_SHOTS = 64  # SSX_DOT_STATIC_MAX_SHOTS
 
@@ -140,6 +141,12 @@ def lib():
         L.ssx_cells_per_launch.restype = ctypes.c_int64
         L.ssx_launch_shape.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
         L.ssx_launch_shape.restype = ctypes.c_int
+        L.ssx_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp)]
+        L.ssx_batch_pcg_solve.argtypes = [vp, ctypes.POINTER(vp), dp, ctypes.c_int32, c_dbl,
+                                          ctypes.c_int32, ctypes.POINTER(vp),
+                                          ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_int32)]
+        L.ssx_batch_destroy.argtypes = [vp]
+        L.ssx_batch_destroy.restype = None
         _lib = L
     return _lib
 
@@ -442,6 +449,54 @@ class Context:
         if getattr(self, "_ctx", None):
             lib().ssx_destroy(self._ctx)
             self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several contexts (any grids, records, shots and models; one stencil
+    order, field and vector type and stream) solved together with their
+    propagations merged (ssx_batch_*): each member's results are bitwise
+    those of its own solve.  Holds the contexts; close it before them."""
+
+    def __init__(self, contexts):
+        self.contexts = list(contexts)
+        n = len(self.contexts)
+        arr = (ctypes.c_void_p * n)(*[c._ctx for c in self.contexts])
+        out = ctypes.c_void_p()
+        _check(lib().ssx_batch_create(n, arr, ctypes.byref(out)))
+        self._b = out
+
+    def pcg_solve(self, ds, alpha_rel, maxit, rtol=0.0, use_precond=True, hs=None):
+        """Algorithm 1 for every member: ds[i] member i's data; alpha_rel a
+        number or one per member.  Returns (hs, hists, iterations), hists[i]
+        [nshots_i][iterations_i + 1][4]."""
+        cs = self.contexts
+        n = len(cs)
+        if len(ds) != n:
+            raise ValueError(f"expected {n} data arrays, got {len(ds)}")
+        alphas = np.ascontiguousarray(np.broadcast_to(np.asarray(alpha_rel, dtype=np.float64),
+                                                      (n,)))
+        if hs is None:
+            hs = [c.empty_s() for c in cs]
+        hists = [np.zeros((c.nshots, maxit + 1, 4)) for c in cs]
+        vp = ctypes.c_void_p
+        dptrs = (vp * n)(*[c._vec(d, c.n_r, "d") for c, d in zip(cs, ds)])
+        hptrs = (vp * n)(*[c._vec(h, c.n_s, "h") for c, h in zip(cs, hs)])
+        histp = (ctypes.POINTER(ctypes.c_double) * n)(*[_dptr(x) for x in hists])
+        its = (ctypes.c_int32 * n)()
+        _check(lib().ssx_batch_pcg_solve(self._b, dptrs, _dptr(alphas), int(maxit), float(rtol),
+                                         int(bool(use_precond)), hptrs, histp, its))
+        return hs, [x[:, : its[i] + 1] for i, x in enumerate(hists)], list(its)
+
+    def close(self):
+        if getattr(self, "_b", None):
+            lib().ssx_batch_destroy(self._b)
+            self._b = None
 
     def __del__(self):
         try:

@@ -12,10 +12,13 @@
 
 #include <algorithm>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 using namespace ssx;
@@ -399,7 +402,51 @@ struct ssx_ctx {
   unsigned long long use_clock = 0;
 };
 
+// One context's part of a merged propagation of a heterogeneous batch: what
+// propagate() was asked to run.
+struct BatchProp {
+  ssx_ctx* c;
+  GridDev* gd;
+  int op;
+  bool adj;
+  LineDev vsl, vil, psl, pil;
+  TraceIO vs, vi, ps, pi;
+};
+
+struct BatchGraphEntry {
+  std::vector<const void*> key;
+  hipGraphExec_t exec;
+  unsigned long long last_use;
+};
+
+// A heterogeneous batch: contexts solved together, their propagations
+// merged.  During ssx_batch_pcg_solve each context's solve runs on a host
+// thread of its own; every propagation it reaches waits at a barrier until
+// every solve still running has reached its next one, and the last to arrive
+// issues all of them as one merged propagation (one launch per time step
+// for up to BATCH_MAX grids) on the shared stream, where stream order keeps
+// each context's vector work before and after it.
+struct ssx_batch {
+  std::vector<ssx_ctx*> ctx;
+  hipStream_t stream = nullptr;
+  Dt fdt = Dt::F32;
+  int order = 0;
+  hipStream_t cap = nullptr;
+  bool graphs = true;
+  std::vector<BatchGraphEntry> graph_cache;
+  unsigned long long use_clock = 0;
+  std::mutex mu;
+  std::condition_variable cv;
+  int active = 0;                 // solves still running
+  unsigned long long gen = 0;     // merged propagations issued
+  std::vector<BatchProp> pending;
+  ssx_status merged_status = SSX_OK;
+  std::string merged_error;
+};
+
 namespace {
+
+thread_local ssx_batch* tl_batch = nullptr;
 
 long long nvec_s(const ssx_problem& p) { return (long long)p.nt * p.ns; }
 long long nvec_r(const ssx_problem& p) { return (long long)p.nt * p.nr; }
@@ -776,6 +823,27 @@ TraceIO shift_io(TraceIO t, int s0, size_t vsz) {
   return t;
 }
 
+// Start of every propagation: both field buffers zeroed; with 16-bit fields
+// the injected traces normalised per shot by a power of two (the trace slots
+// then carry the per-shot scales).
+ssx_status propagation_start(ssx_ctx* c, GridDev& gd, TraceIO& vs, TraceIO& vi, TraceIO& ps,
+                             TraceIO& pi, hipStream_t s) {
+  SSX_HIP(launch_zero(gd.field_block, gd.field_bytes, s));
+  if (c->fsz == 2) {
+    const void* ia = pi.in ? pi.in : vi.in;
+    const double sa = pi.in ? pi.scale : vi.scale;
+    const void* ib = (pi.in && vi.in) ? vi.in : nullptr;
+    const long long nin = (pi.in ? pi.shot_stride : vi.shot_stride);
+    if (ia) {
+      if (ib && vi.shot_stride != nin) return fail(SSX_ERR_ARG, "mismatched trace inputs");
+      SSX_HIP(launch_field_scale(c->vdbl, ia, sa, ib, vi.scale, nin, c->prob.nshots,
+                                 gd.amax_part, gd.dyn, s));
+      vs.dyn = vi.dyn = ps.dyn = pi.dyn = gd.dyn;
+    }
+  }
+  return SSX_OK;
+}
+
 // One propagation of all shots over nt steps, issued on stream s, group by
 // group (each group runs its whole record before the next starts).
 ssx_status issue_propagation(ssx_ctx* c, GridDev& gd, bool adj, const LineDev& vsl, TraceIO vs,
@@ -783,19 +851,7 @@ ssx_status issue_propagation(ssx_ctx* c, GridDev& gd, bool adj, const LineDev& v
                              const LineDev& pil, TraceIO pi, hipStream_t s,
                              const GroupHook* hook = nullptr, const GroupHist* hist = nullptr) {
   const int ns = c->prob.nshots;
-  SSX_HIP(launch_zero(gd.field_block, gd.field_bytes, s));
-  if (c->fsz == 2) {
-    // 16-bit fields: normalise the injected traces per shot by a power of two
-    const void* ia = pi.in ? pi.in : vi.in;
-    const double sa = pi.in ? pi.scale : vi.scale;
-    const void* ib = (pi.in && vi.in) ? vi.in : nullptr;
-    const long long nin = (pi.in ? pi.shot_stride : vi.shot_stride);
-    if (ia) {
-      if (ib && vi.shot_stride != nin) return fail(SSX_ERR_ARG, "mismatched trace inputs");
-      SSX_HIP(launch_field_scale(c->vdbl, ia, sa, ib, vi.scale, nin, ns, gd.amax_part, gd.dyn, s));
-      vs.dyn = vi.dyn = ps.dyn = pi.dyn = gd.dyn;
-    }
-  }
+  SSX_TRY(propagation_start(c, gd, vs, vi, ps, pi, s));
   const int G = shot_group(c, gd);
   for (int s0 = 0; s0 < ns; s0 += G) {
     const int gs = std::min(G, ns - s0);
@@ -872,11 +928,183 @@ ssx_status cached_graph(ssx_ctx* c, int op, const void* const key[4], int tz, in
   return SSX_OK;
 }
 
+// Step arguments of step t of a batch member's propagation: those of the
+// one-step launch issue_group makes at that step with every shot in one
+// launch, at tile height BATCH_TZ and one tile per workgroup.
+StepArgs batch_step_args(const BatchProp& q, int t) {
+  const ssx_ctx* c = q.c;
+  const GridDev& gd = *q.gd;
+  const int nt = c->prob.nt;
+  StepArgs a{};
+  a.g = gd.dims;
+  a.c = gd.coef;
+  a.vsl = q.vsl;
+  a.vil = q.vil;
+  a.psl = q.psl;
+  a.pil = q.pil;
+  a.ntx = (gd.host.NX + step_tile_width() - 1) / step_tile_width();
+  a.ntz = (gd.host.NZ + BATCH_TZ - 1) / BATCH_TZ;
+  a.nshots = c->prob.nshots;
+  a.nt = nt;
+  a.dir = q.adj ? -1 : 1;
+  a.tiles = nullptr;
+  a.ngen = a.nint = 0;
+  a.hist = nullptr;
+  // the buffers alternate from the first step; forward step n = t samples
+  // level n - 1 and injects at n, transposed step n = nt - 1 - t injects the
+  // pressure source at n - 1
+  a.in = (t & 1) ? gd.fields1 : gd.fields;
+  a.out = (t & 1) ? gd.fields : gd.fields1;
+  const int n = q.adj ? nt - 1 - t : t;
+  const int ivs = q.adj ? n : n - 1, ivi = n, ips = n, ipi = q.adj ? n - 1 : n;
+  auto in_range = [nt](int i) { return i >= 0 && i < nt; };
+  a.vs = q.vs;
+  a.vi = q.vi;
+  a.ps = q.ps;
+  a.pi = q.pi;
+  a.vs.n = (q.vs.out && in_range(ivs)) ? ivs : -1;
+  a.vi.n = (q.vi.in && in_range(ivi)) ? ivi : -1;
+  a.ps.n = (q.ps.out && in_range(ips)) ? ips : -1;
+  a.pi.n = (q.pi.in && in_range(ipi)) ? ipi : -1;
+  return a;
+}
+
+// The propagations of several batch members as one: each member's start
+// (zeroed fields, 16-bit trace scales, the transposed sweep's first pressure
+// update), then for every time step one launch per group of up to BATCH_MAX
+// members of one direction and density form whose record is still running,
+// then each forward member's sampling of its last level.
+ssx_status batch_issue(ssx_batch* b, std::vector<BatchProp> P, hipStream_t s) {
+  int maxnt = 0;
+  for (BatchProp& q : P) {
+    ssx_ctx* c = q.c;
+    GridDev& gd = *q.gd;
+    SSX_TRY(propagation_start(c, gd, q.vs, q.vi, q.ps, q.pi, s));
+    if (q.adj) {
+      TraceIO p0 = q.pi;
+      p0.n = q.pi.in ? c->prob.nt - 1 : -1;
+      SSX_HIP(launch_pres(c->fdt, c->prob.order, true, gd.fields, gd.dims, gd.coef, q.psl,
+                          io_none(), q.pil, p0, c->prob.nshots, s));
+    }
+    maxnt = std::max(maxnt, c->prob.nt);
+  }
+  for (int t = 0; t < maxnt; ++t) {
+    for (int form = 0; form < 4; ++form) {
+      const bool adj = form & 1, vr = (form & 2) != 0;
+      BatchStep bs{};
+      auto flush = [&]() -> ssx_status {
+        if (bs.n) SSX_HIP(launch_step_batch(b->fdt, b->order, adj, vr, bs, s));
+        bs.n = 0;
+        return SSX_OK;
+      };
+      for (const BatchProp& q : P) {
+        if (q.adj != adj || q.c->vrho != vr || t >= q.c->prob.nt) continue;
+        if (bs.n == BATCH_MAX) SSX_TRY(flush());
+        bs.a[bs.n] = batch_step_args(q, t);
+        const StepArgs& a = bs.a[bs.n];
+        bs.pre[bs.n + 1] = bs.pre[bs.n] + (a.ntx * a.ntz * a.nshots + 7) / 8 * 8;
+        ++bs.n;
+      }
+      SSX_TRY(flush());
+    }
+  }
+  for (const BatchProp& q : P) {
+    if (q.adj || !q.vs.out) continue;
+    TraceIO vs = q.vs;
+    vs.n = q.c->prob.nt - 1;
+    const Fields& f = (q.c->prob.nt & 1) ? q.gd->fields1 : q.gd->fields;
+    SSX_HIP(launch_sample_p(q.c->fdt, f, q.gd->dims, q.vsl, vs, q.c->prob.nshots, s));
+  }
+  return SSX_OK;
+}
+
+// Issues the pending propagations as one merged propagation: a cached graph
+// keyed by every member's context, operation and trace pointers, captured on
+// first use, or plain launches.  Called with the batch lock held.
+ssx_status batch_flush(ssx_batch* b) {
+  std::vector<BatchProp> P;
+  P.swap(b->pending);
+  // members in batch order, whatever order their threads arrived in, so
+  // that a stage replays one graph
+  auto rank = [b](const ssx_ctx* c) {
+    return std::find(b->ctx.begin(), b->ctx.end(), c) - b->ctx.begin();
+  };
+  std::sort(P.begin(), P.end(),
+            [&](const BatchProp& x, const BatchProp& y) { return rank(x.c) < rank(y.c); });
+  if (!b->graphs) return batch_issue(b, P, b->stream);
+  std::vector<const void*> key;
+  for (const BatchProp& q : P) {
+    key.push_back(q.c);
+    key.push_back(reinterpret_cast<const void*>((intptr_t)q.op));
+    key.push_back(q.vs.out);
+    key.push_back(q.vi.in);
+    key.push_back(q.ps.out);
+    key.push_back(q.pi.in);
+  }
+  for (BatchGraphEntry& e : b->graph_cache) {
+    if (e.key == key) {
+      e.last_use = ++b->use_clock;
+      SSX_HIP(hipGraphLaunch(e.exec, b->stream));
+      return SSX_OK;
+    }
+  }
+  if (!b->cap) SSX_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+  SSX_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+  const ssx_status st = batch_issue(b, P, b->cap);
+  hipGraph_t graph = nullptr;
+  const hipError_t e1 = hipStreamEndCapture(b->cap, &graph);
+  if (st != SSX_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  SSX_HIP(e1);
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  SSX_HIP(e2);
+  if (b->graph_cache.size() >= GRAPH_CACHE_MAX) {
+    auto lru = std::min_element(b->graph_cache.begin(), b->graph_cache.end(),
+                                [](const BatchGraphEntry& x, const BatchGraphEntry& y) {
+                                  return x.last_use < y.last_use;
+                                });
+    (void)hipGraphExecDestroy(lru->exec);
+    b->graph_cache.erase(lru);
+  }
+  b->graph_cache.push_back({key, exec, ++b->use_clock});
+  SSX_HIP(hipGraphLaunch(exec, b->stream));
+  return SSX_OK;
+}
+
+// Called with the lock held when a member arrives or leaves: once every
+// running solve waits at a propagation, issue them and release the waiters.
+void batch_maybe_flush(ssx_batch* b) {
+  if (b->pending.empty() || (int)b->pending.size() < b->active) return;
+  b->merged_status = batch_flush(b);
+  b->merged_error = b->merged_status == SSX_OK ? std::string() : g_err;
+  ++b->gen;
+  b->cv.notify_all();
+}
+
+// propagate() of a batch member: wait for the merged propagation.
+ssx_status batch_propagate(ssx_batch* b, const BatchProp& q) {
+  std::unique_lock<std::mutex> lk(b->mu);
+  const unsigned long long my_gen = b->gen;
+  b->pending.push_back(q);
+  batch_maybe_flush(b);
+  b->cv.wait(lk, [&] { return b->gen != my_gen; });
+  if (b->merged_status != SSX_OK) g_err = b->merged_error;
+  return b->merged_status;
+}
+
 // Runs a propagation: replays a cached graph for (op, pointers) when graphs
-// are enabled (capturing it on first use), else issues the launches.
+// are enabled (capturing it on first use), else issues the launches.  For a
+// member of a heterogeneous batch being solved, it joins the batch's next
+// merged propagation instead.
 ssx_status propagate(ssx_ctx* c, int op, GridDev& gd, bool adj, const LineDev& vsl, TraceIO vs,
                      const LineDev& vil, TraceIO vi, const LineDev& psl, TraceIO ps,
                      const LineDev& pil, TraceIO pi) {
+  if (tl_batch)
+    return batch_propagate(tl_batch, BatchProp{c, &gd, op, adj, vsl, vil, psl, pil, vs, vi, ps, pi});
   if (!c->graphs)
     return issue_propagation(c, gd, adj, vsl, vs, vil, vi, psl, ps, pil, pi, c->run);
   const void* key[4] = {vs.out, vi.in, ps.out, pi.in};
@@ -1604,6 +1832,83 @@ ssx_status ssx_pcg_solve(ssx_ctx* c, const void* d, double alpha_rel, int32_t ma
   if (!std::isfinite(alpha_rel) || alpha_rel < 0) return fail(SSX_ERR_ARG, "alpha_rel must be >= 0");
   return run_pcg(c, Pcg::EUCLID, d, alpha_rel, maxit, rtol, use_precond, h_out, hist_host,
                  iters_host);
+}
+
+ssx_status ssx_batch_create(int32_t n, ssx_ctx* const* ctxs, ssx_batch** out) {
+  if (!out) return fail(SSX_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (n < 1 || !ctxs) return fail(SSX_ERR_ARG, "a batch needs at least one context");
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i]) return fail(SSX_ERR_ARG, "null context in the batch");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return fail(SSX_ERR_ARG, "a context appears twice in the batch");
+    const ssx_ctx* c = ctxs[i];
+    const ssx_ctx* c0 = ctxs[0];
+    if (c->prob.order != c0->prob.order || c->fdt != c0->fdt || c->vdbl != c0->vdbl)
+      return fail(SSX_ERR_ARG, "batch contexts must share the stencil order, field and vector types");
+    if (c->stream != c0->stream) return fail(SSX_ERR_ARG, "batch contexts must share one stream");
+  }
+  ssx_batch* b = new ssx_batch();
+  b->ctx.assign(ctxs, ctxs + n);
+  b->stream = ctxs[0]->stream;
+  b->fdt = ctxs[0]->fdt;
+  b->order = ctxs[0]->prob.order;
+  b->graphs = ctxs[0]->graphs;
+  *out = b;
+  return SSX_OK;
+}
+
+ssx_status ssx_batch_pcg_solve(ssx_batch* b, const void* const* d, const double* alpha_rel,
+                               int32_t maxit, double rtol, int32_t use_precond,
+                               void* const* h_out, double* const* hist_host, int32_t* iters_host) {
+  if (!b || !d || !alpha_rel || !h_out) return fail(SSX_ERR_ARG, "null argument");
+  if (maxit < 0 || maxit > HIST_CAP) return fail(SSX_ERR_ARG, "maxit out of range");
+  const int n = (int)b->ctx.size();
+  for (int i = 0; i < n; ++i) {
+    if (!d[i] || !h_out[i]) return fail(SSX_ERR_ARG, "null data or output in the batch");
+    if (!std::isfinite(alpha_rel[i]) || alpha_rel[i] < 0)
+      return fail(SSX_ERR_ARG, "alpha_rel must be >= 0");
+  }
+  int dev = 0;
+  SSX_HIP(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> lk(b->mu);
+    b->active = n;
+    b->pending.clear();
+  }
+  std::vector<ssx_status> st(n, SSX_OK);
+  std::vector<std::string> err(n);
+  std::vector<std::thread> th;
+  th.reserve(n);
+  for (int i = 0; i < n; ++i) {
+    th.emplace_back([&, i] {
+      const hipError_t e = hipSetDevice(dev);
+      if (e != hipSuccess) {
+        st[i] = fail(SSX_ERR_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+      } else {
+        tl_batch = b;
+        st[i] = run_pcg(b->ctx[i], Pcg::EUCLID, d[i], alpha_rel[i], maxit, rtol, use_precond,
+                        h_out[i], hist_host ? hist_host[i] : nullptr,
+                        iters_host ? iters_host + i : nullptr);
+        tl_batch = nullptr;
+      }
+      if (st[i] != SSX_OK) err[i] = g_err;
+      std::lock_guard<std::mutex> lk(b->mu);
+      --b->active;
+      batch_maybe_flush(b);
+    });
+  }
+  for (std::thread& t : th) t.join();
+  for (int i = 0; i < n; ++i)
+    if (st[i] != SSX_OK) return fail(st[i], "batch member " + std::to_string(i) + ": " + err[i]);
+  return SSX_OK;
+}
+
+void ssx_batch_destroy(ssx_batch* b) {
+  if (!b) return;
+  for (BatchGraphEntry& e : b->graph_cache) (void)hipGraphExecDestroy(e.exec);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  delete b;
 }
 
 ssx_status ssx_weight_d(ssx_ctx* c, const void* r, void* y) {

@@ -129,6 +129,21 @@ hipError_t launch_step(Dt dt, int order, bool adj, int tz, int loop, StepArgs a,
 void step_tile_lists(int order, int tz, const GridDims& g, const LineDev* const* lines,
                      int nlines, std::vector<int>* gen, std::vector<int>* inter);
 int step_tile_width();
+// Heterogeneous batch: up to BATCH_MAX grids (any sizes and records, one
+// stencil order and field type, all constant density or all density arrays)
+// advanced by one time step in one launch of the fused kernel at tile height
+// BATCH_TZ, one tile per workgroup.  Grid p takes blocks [pre[p], pre[p+1]):
+// its tile count ntx * ntz * nshots rounded up to a multiple of 8; a[p] are
+// its step arguments as for launch_step (no tile lists, no history).
+constexpr int BATCH_MAX = 6;
+constexpr int BATCH_TZ = 16;
+struct BatchStep {
+  int n;
+  int pre[BATCH_MAX + 1];
+  StepArgs a[BATCH_MAX];
+};
+hipError_t launch_step_batch(Dt dt, int order, bool adj, bool vr, const BatchStep& b,
+                             hipStream_t s);
 // Several time steps per launch (ssx_slab.hip): ns steps (2, 4 or 8) on
 // strips of wr columns (64 or 128; F64 fields and density arrays, a.c.cbx
 // set, 64 only) and windows of at

@@ -945,6 +945,44 @@ __global__ __launch_bounds__(step_threads(TZ), LOOP ? 4 : 6) void k_step(StepArg
   }
 }
 
+// Several grids advanced by one time step in one launch (a heterogeneous
+// batch): problem p takes blocks [b.pre[p], b.pre[p+1]) -- its tile count
+// rounded up to a multiple of 8, so that the XCD-aware tile order of the
+// one-grid kernel carries over -- and reads its step arguments from the
+// launch's own argument block.  Each tile runs the one-tile-per-workgroup
+// path of k_step (no history), so every grid's result is bitwise that of
+// its own launch.
+template <int K, bool ADJ, typename T, int TZ, bool VR>
+__global__ __launch_bounds__(step_threads(TZ), 6) void k_step_batch(BatchStep b) {
+  using C = typename Tr<T>::C;
+  using S = TileShape<K, TZ>;
+  __shared__ __align__(16) C sP[S::HP * S::SPP];
+  __shared__ __align__(16) C sPX[ADJ ? TZ * S::SPP : 4];
+  __shared__ __align__(16) C sVX[TZ * S::SPX];
+  __shared__ __align__(16) C sVZ[S::HVZ * S::SPZ];
+  __shared__ __align__(16) C sF[S::NF];
+  __shared__ __align__(16) C sL[4 * TX];
+  int p = 0;
+  for (int i = 1; i < b.n; ++i)
+    if ((int)blockIdx.x >= b.pre[i]) p = i;
+  const StepArgs& a = b.a[p];
+  const int per_shot = a.ntx * a.ntz, ntiles = per_shot * a.nshots;
+  const int t = xcd_tile((int)blockIdx.x - b.pre[p], b.pre[p + 1] - b.pre[p]);
+  if (t >= ntiles) return;  // padding block
+  const int shot = t / per_shot;
+  const int tt = t - shot * per_shot;
+  const int tzi = tt / a.ntx;
+  const int x0 = (tt - tzi * a.ntx) * TX, z0 = tzi * TZ;
+  const long long base = a.g.origin + (long long)shot * a.g.field_stride;
+  if (interior_tile<K, TZ>(a, x0, z0)) {
+    InteriorRegs<K, TZ, C, VR> r;
+    interior_load<K, T, TZ, C, VR>(a, base, x0, z0, r);
+    interior_compute<K, ADJ, T, TZ, C, false>(a, shot, base, x0, z0, r, sP, sVX, sVZ, [] {});
+  } else {
+    step_general<K, ADJ, T, TZ, C, false, VR>(a, shot, x0, z0, sP, sPX, sVX, sVZ, sF, sL);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // line sampling after the last forward step, and a fill kernel
 
@@ -1147,6 +1185,30 @@ void step_tile_lists(int order, int tz, const GridDims& g, const LineDev* const*
 
 hipError_t launch_step(Dt dt, int order, bool adj, int tz, int loop, StepArgs a, hipStream_t s) {
   SSX_DISPATCH(step_t, tz, loop, a, s);
+}
+
+template <int K, bool ADJ, typename T>
+static hipError_t step_batch_t(const BatchStep& b, bool vr, hipStream_t s) {
+  if (b.n < 1 || b.n > BATCH_MAX || b.pre[0] != 0) return hipErrorInvalidValue;
+  for (int i = 0; i < b.n; ++i) {
+    const StepArgs& a = b.a[i];
+    const int need = a.ntx * a.ntz * a.nshots;
+    if ((a.c.cbx != nullptr) != vr || a.tiles || a.hist || b.pre[i + 1] - b.pre[i] < need ||
+        (b.pre[i + 1] - b.pre[i]) % 8 != 0 || a.ntx != (a.g.NX + TX - 1) / TX ||
+        a.ntz != (a.g.NZ + BATCH_TZ - 1) / BATCH_TZ)
+      return hipErrorInvalidValue;
+  }
+  const dim3 grid(b.pre[b.n]), block(step_threads(BATCH_TZ));
+  if (vr)
+    hipLaunchKernelGGL((k_step_batch<K, ADJ, T, BATCH_TZ, true>), grid, block, 0, s, b);
+  else
+    hipLaunchKernelGGL((k_step_batch<K, ADJ, T, BATCH_TZ, false>), grid, block, 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_batch(Dt dt, int order, bool adj, bool vr, const BatchStep& b,
+                             hipStream_t s) {
+  SSX_DISPATCH(step_batch_t, b, vr, s);
 }
 
 int step_tile_width() { return TX; }
