@@ -74,6 +74,9 @@ def parse():
                          "fields and vectors and report the served solution's error "
                          "against it")
     ap.add_argument("--slots", type=int, default=4, help="c5: concurrent requests")
+    ap.add_argument("--batch", type=int, default=1,
+                    help="c5: up to this many queued requests solved as one heterogeneous "
+                         "batch per slot, their propagations merged (1: one request per slot)")
     ap.add_argument("--rate-sweep", action="store_true",
                     help="c5: also serve open-loop streams at 0.5, 1.0 and 1.2x the measured "
                          "capacity (0.8x is always run)")
@@ -952,7 +955,7 @@ def serve_bench(args):
         print(f"# request {res.rid} done: latency {res.t_done - res.t_arrival:.2f} s", flush=True)
 
     srv = serve.Server(budget, slots=args.slots, graphs=bool(args.graphs), tuner=tuner,
-                       on_done=progress)
+                       on_done=progress, batch=args.batch)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     closed = srv.run(reqs, realtime=False)
@@ -1009,8 +1012,9 @@ def serve_bench(args):
         "config": {"workload": f"c5: first {len(reqs)} requests of the seeded stream "
                                f"(grids 201x401 / 401x801 / 801x1601, 1-64 shots, "
                                f"nt 500-4000), caps: {caps}, K 20, FP16 storage, "
-                               f"{args.slots} slots, graphs {int(bool(args.graphs))}",
-                   "requests": len(reqs), "caps": caps,
+                               f"{args.slots} slots, graphs {int(bool(args.graphs))}"
+                               + (f", batches of up to {args.batch}" if args.batch > 1 else ""),
+                   "requests": len(reqs), "caps": caps, "batch": args.batch,
                    "admission_budget_bytes": budget},
         "closed_loop": cap, "open_loop_0p8": lat, **sweep,
         "p50_latency_s": round(lat["latency_p50_s"], 3),

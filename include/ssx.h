@@ -240,7 +240,9 @@ ssx_status ssx_pcg_solve(ssx_ctx* ctx, const void* d, double alpha_rel, int32_t 
  * ssx_batch_pcg_solve runs Algorithm 1 for every member as ssx_pcg_solve
  * does (d[i], h_out[i]: DEVICE, member i's layouts; alpha_rel[i] per member;
  * hist_host[i]: HOST [nshots_i][maxit+1][4] or NULL, hist_host itself may
- * be NULL; iters_host: HOST [n] or NULL), with its propagations merged:
+ * be NULL; iters_host, status_host: HOST [n] or NULL, each member's
+ * iterations and the status its own solve would return), with its
+ * propagations merged:
  * the members' solves advance in lockstep, and each propagation stage they
  * reach together runs as one sequence of launches in which every time
  * step advances every member's grid (members with shorter records drop out
@@ -250,15 +252,15 @@ ssx_status ssx_pcg_solve(ssx_ctx* ctx, const void* d, double alpha_rel, int32_t 
  * ssx_pcg_solve, whatever its launch options (every launch form evaluates
  * the same expressions).  A member stopping early (rtol, an error) leaves
  * the lockstep; the others go on.  Synchronises the stream before
- * returning; returns the first member's error, its message naming the
- * member.  The members' own stream-ordered work must not run concurrently
+ * returning; returns the first member's error (the others' results stay
+ * valid), its message naming the member.  The members' own stream-ordered work must not run concurrently
  * with the batch solve. */
 typedef struct ssx_batch ssx_batch;
 ssx_status ssx_batch_create(int32_t n, ssx_ctx* const* ctxs, ssx_batch** out);
 ssx_status ssx_batch_pcg_solve(ssx_batch* batch, const void* const* d, const double* alpha_rel,
                                int32_t maxit, double rtol, int32_t use_precond,
                                void* const* h_out, double* const* hist_host,
-                               int32_t* iters_host);
+                               int32_t* iters_host, int32_t* status_host);
 void ssx_batch_destroy(ssx_batch* batch);
 
 /* ---- weighted normal equations (Accelerated Iterative Inversion, the

@@ -144,7 +144,8 @@ def lib():
         L.ssx_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp)]
         L.ssx_batch_pcg_solve.argtypes = [vp, ctypes.POINTER(vp), dp, ctypes.c_int32, c_dbl,
                                           ctypes.c_int32, ctypes.POINTER(vp),
-                                          ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_int32)]
+                                          ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_int32)]
         L.ssx_batch_destroy.argtypes = [vp]
         L.ssx_batch_destroy.restype = None
         _lib = L
@@ -471,10 +472,13 @@ class Batch:
         _check(lib().ssx_batch_create(n, arr, ctypes.byref(out)))
         self._b = out
 
-    def pcg_solve(self, ds, alpha_rel, maxit, rtol=0.0, use_precond=True, hs=None):
+    def pcg_solve(self, ds, alpha_rel, maxit, rtol=0.0, use_precond=True, hs=None,
+                  raise_on_breakdown=True):
         """Algorithm 1 for every member: ds[i] member i's data; alpha_rel a
-        number or one per member.  Returns (hs, hists, iterations), hists[i]
-        [nshots_i][iterations_i + 1][4]."""
+        number or one per member.  Returns (hs, hists, iterations, statuses),
+        hists[i] [nshots_i][iterations_i + 1][4]; with raise_on_breakdown
+        False, a member's breakdown (status 5 or 6) is reported in statuses
+        instead of raised."""
         cs = self.contexts
         n = len(cs)
         if len(ds) != n:
@@ -489,9 +493,12 @@ class Batch:
         hptrs = (vp * n)(*[c._vec(h, c.n_s, "h") for c, h in zip(cs, hs)])
         histp = (ctypes.POINTER(ctypes.c_double) * n)(*[_dptr(x) for x in hists])
         its = (ctypes.c_int32 * n)()
-        _check(lib().ssx_batch_pcg_solve(self._b, dptrs, _dptr(alphas), int(maxit), float(rtol),
-                                         int(bool(use_precond)), hptrs, histp, its))
-        return hs, [x[:, : its[i] + 1] for i, x in enumerate(hists)], list(its)
+        sts = (ctypes.c_int32 * n)()
+        st = lib().ssx_batch_pcg_solve(self._b, dptrs, _dptr(alphas), int(maxit), float(rtol),
+                                       int(bool(use_precond)), hptrs, histp, its, sts)
+        if st != 0 and (raise_on_breakdown or any(x not in (0, 5, 6) for x in sts)):
+            _check(st)
+        return hs, [x[:, : its[i] + 1] for i, x in enumerate(hists)], list(its), list(sts)
 
     def close(self):
         if getattr(self, "_b", None):

@@ -1860,7 +1860,8 @@ ssx_status ssx_batch_create(int32_t n, ssx_ctx* const* ctxs, ssx_batch** out) {
 
 ssx_status ssx_batch_pcg_solve(ssx_batch* b, const void* const* d, const double* alpha_rel,
                                int32_t maxit, double rtol, int32_t use_precond,
-                               void* const* h_out, double* const* hist_host, int32_t* iters_host) {
+                               void* const* h_out, double* const* hist_host, int32_t* iters_host,
+                               int32_t* status_host) {
   if (!b || !d || !alpha_rel || !h_out) return fail(SSX_ERR_ARG, "null argument");
   if (maxit < 0 || maxit > HIST_CAP) return fail(SSX_ERR_ARG, "maxit out of range");
   const int n = (int)b->ctx.size();
@@ -1899,6 +1900,8 @@ ssx_status ssx_batch_pcg_solve(ssx_batch* b, const void* const* d, const double*
     });
   }
   for (std::thread& t : th) t.join();
+  if (status_host)
+    for (int i = 0; i < n; ++i) status_host[i] = st[i];
   for (int i = 0; i < n; ++i)
     if (st[i] != SSX_OK) return fail(st[i], "batch member " + std::to_string(i) + ": " + err[i]);
   return SSX_OK;

@@ -7,10 +7,15 @@ memory (by the library's exact footprint) and an execution slot are free;
 each admitted request runs on its own HIP stream with its state resident in
 a workspace taken from the PyTorch caching allocator (the library itself
 allocates nothing), so requests that arrive while others run overlap with
-them on the device.  When a request completes its memory and slot go to the
-next one in the queue.  Results do not depend on what else is running: each
-request's arithmetic is fixed by its shape (kernel choices are keyed by
-shape only).
+them on the device.  With batch > 1, a slot takes the first queued request
+together with up to batch - 1 later queued ones that can share its solve
+(same stencil order, field type, iteration count and preconditioning, all
+within the free memory) and solves them as one heterogeneous batch, their
+propagations merged into one launch per time step (ssx_batch_*).  When a
+request (or batch) completes its memory and slot go to the queue.  Results
+do not depend on what else is running or on batching: each request's
+arithmetic is fixed by its shape (kernel choices are keyed by shape only,
+and a batch member's results are bitwise those of its own solve).
 
 The server records, per request, arrival, admission and completion times
 and reports throughput and latency percentiles.
@@ -25,7 +30,7 @@ from typing import Any
 
 import numpy as np
 
-from . import Context, footprint
+from . import Batch, Context, footprint
 
 
 @dataclasses.dataclass
@@ -70,13 +75,20 @@ def request_bytes(req: Request) -> int:
         req.nshots * req.prob.nt * req.prob.ns * vsz
 
 
+def batch_key(req: Request) -> tuple:
+    """Requests with equal keys can share a batch solve."""
+    return (req.prob.order, req.field_dtype, req.K, bool(req.use_precond))
+
+
 class Server:
-    """Admission by footprint and slots, FIFO order, one stream per request."""
+    """Admission by footprint and slots, FIFO order, one stream per request
+    (or per batch of requests, batch > 1)."""
 
     def __init__(self, budget_bytes: int, slots: int = 4, graphs: bool = False,
-                 tuner=None, on_done=None):
+                 tuner=None, on_done=None, batch: int = 1):
         self.budget = int(budget_bytes)
         self.slots = int(slots)
+        self.batch = max(1, int(batch))
         self.graphs = bool(graphs)
         self.tuner = tuner            # callable(ctx, req) applying kernel choices, or None
         self.on_done = on_done        # callable(Result) after each completion, or None
@@ -86,32 +98,47 @@ class Server:
         self._results: list[Result] = []
         self._errors: list[BaseException] = []
 
-    # -- one request --------------------------------------------------------
-    def _serve(self, req: Request, t0: float, t_admit: float, nbytes: int):
+    # -- one request, or a batch of them ---------------------------------------
+    def _serve(self, group: list, t0: float, t_admit: float, nbytes: int):
         import torch
         try:
             stream = torch.cuda.Stream()
             with torch.cuda.stream(stream):
-                ws = torch.empty(footprint(req.prob, req.field_dtype, req.nshots),
-                                 dtype=torch.uint8, device="cuda")
-                ctx = Context(req.prob, req.kappa, req.rho, field_dtype=req.field_dtype,
-                              stream=stream, workspace=ws)
-                if self.tuner is not None:
-                    self.tuner(ctx, req)
-                ctx.set_graphs(self.graphs)
-                h = ctx.empty_s()
-                h, hist, iters, st = ctx.pcg_solve(req.d, req.alpha_rel, req.K,
-                                                   use_precond=req.use_precond, h=h,
-                                                   raise_on_breakdown=False)
-                ctx.close()
-                del ws
+                wss, ctxs = [], []
+                for req in group:
+                    ws = torch.empty(footprint(req.prob, req.field_dtype, req.nshots),
+                                     dtype=torch.uint8, device="cuda")
+                    ctx = Context(req.prob, req.kappa, req.rho, field_dtype=req.field_dtype,
+                                  stream=stream, workspace=ws)
+                    if self.tuner is not None:
+                        self.tuner(ctx, req)
+                    ctx.set_graphs(self.graphs)
+                    wss.append(ws)
+                    ctxs.append(ctx)
+                if len(group) == 1:
+                    req, ctx = group[0], ctxs[0]
+                    h, hist, iters, st = ctx.pcg_solve(req.d, req.alpha_rel, req.K,
+                                                       use_precond=req.use_precond,
+                                                       h=ctx.empty_s(), raise_on_breakdown=False)
+                    out = [(h, hist, iters, st)]
+                else:
+                    b = Batch(ctxs)
+                    hs, hists, its, sts = b.pcg_solve(
+                        [r.d for r in group], [r.alpha_rel for r in group], group[0].K,
+                        use_precond=group[0].use_precond, raise_on_breakdown=False)
+                    b.close()
+                    out = list(zip(hs, hists, its, sts))
+                for ctx in ctxs:
+                    ctx.close()
+                del wss
             stream.synchronize()
             t_done = time.perf_counter() - t0
-            res = Result(req.rid, h, hist, iters, st, req.arrival, t_admit, t_done)
-            with self._cv:
-                self._results.append(res)
-            if self.on_done is not None:
-                self.on_done(res)
+            for req, (h, hist, iters, st) in zip(group, out):
+                res = Result(req.rid, h, hist, iters, st, req.arrival, t_admit, t_done)
+                with self._cv:
+                    self._results.append(res)
+                if self.on_done is not None:
+                    self.on_done(res)
         except BaseException as e:  # reported by run()
             with self._cv:
                 self._errors.append(e)
@@ -147,12 +174,21 @@ class Server:
                 queue.append(r)
             with self._cv:
                 while queue and self._busy < self.slots and sizes[queue[0].rid] <= self._free:
-                    r = queue.popleft()
-                    nb = sizes[r.rid]
+                    group = [queue.popleft()]
+                    nb = sizes[group[0].rid]
+                    if self.batch > 1:
+                        key = batch_key(group[0])
+                        for r in list(queue):
+                            if len(group) >= self.batch:
+                                break
+                            if batch_key(r) == key and nb + sizes[r.rid] <= self._free:
+                                queue.remove(r)
+                                group.append(r)
+                                nb += sizes[r.rid]
                     self._free -= nb
                     self._busy += 1
                     th = threading.Thread(target=self._serve,
-                                          args=(r, t0, time.perf_counter() - t0, nb),
+                                          args=(group, t0, time.perf_counter() - t0, nb),
                                           daemon=True)
                     th.start()
                     threads.append(th)

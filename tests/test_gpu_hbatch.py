@@ -65,7 +65,8 @@ def test_batch_equals_own_solves_bitwise(fd, order, count):
     alphas = [1e-3 * (1 + i % 3) for i in range(count)]
     K = 5
     b = ssx.Batch(ctxs)
-    hs, hists, its = b.pcg_solve(ds, alphas, K)
+    hs, hists, its, sts = b.pcg_solve(ds, alphas, K)
+    assert sts == [0] * count
     b.close()
     for i, (ctx, d) in enumerate(ms):
         h1, hist1, it1, _ = ctx.pcg_solve(d, alphas[i], K)
@@ -84,7 +85,7 @@ def test_batch_members_stop_at_their_own_iteration():
     ctxs = [c for c, _ in ms]
     ds = [d for _, d in ms]
     b = ssx.Batch(ctxs)
-    hs, hists, its = b.pcg_solve(ds, 0.0, 12, rtol=0.3)
+    hs, hists, its, _ = b.pcg_solve(ds, 0.0, 12, rtol=0.3)
     b.close()
     for i, (ctx, d) in enumerate(ms):
         h1, hist1, it1, _ = ctx.pcg_solve(d, 0.0, 12, rtol=0.3)
@@ -112,7 +113,7 @@ def test_batch_with_tuned_members_and_graph_replays():
         ref.append((arrays(h1), hist1))
     b = ssx.Batch(ctxs)
     for rep in range(2):
-        hs, hists, its = b.pcg_solve(ds, 1e-3, 4)
+        hs, hists, its, _ = b.pcg_solve(ds, 1e-3, 4)
         for i in range(3):
             assert np.array_equal(arrays(hs[i]), ref[i][0]), (rep, i)
             assert np.array_equal(hists[i], ref[i][1]), (rep, i)

@@ -62,6 +62,26 @@ def test_mix_equals_alone(graphs):
         assert np.array_equal(alone.hist, res.hist)
 
 
+@pytest.mark.parametrize("graphs", [False, True])
+def test_batched_serving_equals_alone(graphs):
+    # slots taking up to three queued requests at once as one heterogeneous
+    # batch (propagations merged): every result equals the request served
+    # alone
+    print(f"case serving batched graphs={graphs}", flush=True)
+    reqs = make_requests(n=7)
+    res = serve.Server(budget_bytes=8 << 30, slots=2, graphs=graphs, batch=3).run(
+        reqs, realtime=False)
+    assert [r.rid for r in res] == list(range(len(reqs)))
+    # some requests shared a solve: admitted and completed together
+    spans = [(r.t_admit, r.t_done) for r in res]
+    assert len(set(spans)) < len(spans), spans
+    for req, r in zip(reqs, res):
+        alone = serve.Server(budget_bytes=8 << 30, slots=1).run([req], realtime=False)[0]
+        assert alone.status == r.status and alone.iters == r.iters
+        assert torch.equal(alone.h, r.h), req.rid
+        assert np.array_equal(alone.hist, r.hist)
+
+
 def test_budget_limits_residency():
     # a budget of the largest request's footprint: at every admission the
     # requests then resident (admitted, not yet done) fit the budget, and
