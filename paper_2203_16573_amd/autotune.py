@@ -25,7 +25,7 @@ from . import (OPT_SHOT_GROUP, OPT_SHOT_GROUP_SLAB, OPT_SLAB_STRIP, OPT_STEP_KER
                OPT_TILE_Z, OPT_TILE_Z_SLAB,
                Context)
 
-DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ssx", "autotune-v7.json")
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ssx", "autotune-v8.json")
 SLAB_MAXZ = 56  # rows of one region of the multi-step kernel
 
 
@@ -111,7 +111,7 @@ def _group_candidates(auto: int, nshots: int) -> list:
 
 
 def tune(prob, kappa, rho, xs=None, field_dtype="f32", nt_tune: int = 60,
-         stream=None) -> dict:
+         stream=None, rounds: int = 2) -> dict:
     """Measure the candidates and return {"step_kernel", "steps_per_launch",
     "tile_z", "shot_group", "steps_per_launch_slab", "tile_z_slab",
     "slab_strip", "shot_group_slab", "us": {...}} (per-step times in
@@ -170,17 +170,25 @@ def tune(prob, kappa, rho, xs=None, field_dtype="f32", nt_tune: int = 60,
     ctx.set_option(OPT_STEP_KERNEL, 1)
     ctx.set_option(OPT_SHOT_GROUP, 0)
     auto_group = max(1, ctx.cells_per_launch() // (NZ * NX))
-    for c in full_cands:
-        set_full(c)
-        us[key_f(c)] = 1e3 * _time_ms(full, ctx.stream) / (2 * nt)
-    set_full((1, 8, 0, 0))
-    for c in slab_cands:
-        set_slab(c)
-        us[key_s(c)] = 1e3 * _time_ms(slab, ctx.stream) / (2 * nt)
-    set_slab((1, 8, 0, 0))
-    ctx.set_option(OPT_STEP_KERNEL, 0)
-    us["full_split"] = 1e3 * _time_ms(full, ctx.stream) / (2 * nt)
-    us["slab_split"] = 1e3 * _time_ms(slab, ctx.stream) / (2 * nt)
+    # every candidate is timed in each of `rounds` passes over the list and
+    # keeps its fastest time, so that a slow moment of the device does not
+    # decide between close candidates
+    for _ in range(rounds):
+        ctx.set_option(OPT_STEP_KERNEL, 1)
+        for c in full_cands:
+            set_full(c)
+            t = 1e3 * _time_ms(full, ctx.stream) / (2 * nt)
+            us[key_f(c)] = min(t, us.get(key_f(c), t))
+        set_full((1, 8, 0, 0))
+        for c in slab_cands:
+            set_slab(c)
+            t = 1e3 * _time_ms(slab, ctx.stream) / (2 * nt)
+            us[key_s(c)] = min(t, us.get(key_s(c), t))
+        set_slab((1, 8, 0, 0))
+        ctx.set_option(OPT_STEP_KERNEL, 0)
+        for k, fn in (("full_split", full), ("slab_split", slab)):
+            t = 1e3 * _time_ms(fn, ctx.stream) / (2 * nt)
+            us[k] = min(t, us.get(k, t))
     best_full = min(full_cands, key=lambda c: us[key_f(c)])
     best_slab = min(slab_cands, key=lambda c: us[key_s(c)])
     fused_total = us[key_f(best_full)] + us[key_s(best_slab)]
@@ -191,10 +199,12 @@ def tune(prob, kappa, rho, xs=None, field_dtype="f32", nt_tune: int = 60,
     set_slab(best_slab)
     group, group_slab = auto_group, 0
     if ns > 1:
-        for gsz in _group_candidates(auto_group, ns):
-            ctx.set_option(OPT_SHOT_GROUP, gsz)
-            ctx.set_option(OPT_SHOT_GROUP_SLAB, 0)
-            us[f"full_group{gsz}"] = 1e3 * _time_ms(full, ctx.stream) / (2 * nt)
+        for _ in range(rounds):
+            for gsz in _group_candidates(auto_group, ns):
+                ctx.set_option(OPT_SHOT_GROUP, gsz)
+                ctx.set_option(OPT_SHOT_GROUP_SLAB, 0)
+                t = 1e3 * _time_ms(full, ctx.stream) / (2 * nt)
+                us[f"full_group{gsz}"] = min(t, us.get(f"full_group{gsz}", t))
         group = min(_group_candidates(auto_group, ns), key=lambda x: us[f"full_group{x}"])
     ctx.close()
     return {"step_kernel": step_kernel,
