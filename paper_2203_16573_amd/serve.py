@@ -11,7 +11,11 @@ them on the device.  With batch > 1, a slot takes the first queued request
 together with up to batch - 1 later queued ones that can share its solve
 (same stencil order, field type, iteration count and preconditioning, all
 within the free memory) and solves them as one heterogeneous batch, their
-propagations merged into one launch per time step (ssx_batch_*).  When a
+propagations merged into one launch per time step (ssx_batch_*).  Only
+small requests are batched (at most batch_cells grid cells over all their
+shots: the merged launch pays where single launches are bound by latency),
+and only with records within batch_nt_ratio of each other's length (the
+members run in lockstep, so a short record waits for the longest).  When a
 request (or batch) completes its memory and slot go to the queue.  Results
 do not depend on what else is running or on batching: each request's
 arithmetic is fixed by its shape (kernel choices are keyed by shape only,
@@ -80,15 +84,24 @@ def batch_key(req: Request) -> tuple:
     return (req.prob.order, req.field_dtype, req.K, bool(req.use_precond))
 
 
+def request_cells(req: Request) -> int:
+    """Cells of the padded grid over all the request's shots."""
+    p = req.prob
+    return (p.nz + 2 * p.npml) * (p.nx + 2 * p.npml) * req.nshots
+
+
 class Server:
     """Admission by footprint and slots, FIFO order, one stream per request
     (or per batch of requests, batch > 1)."""
 
     def __init__(self, budget_bytes: int, slots: int = 4, graphs: bool = False,
-                 tuner=None, on_done=None, batch: int = 1):
+                 tuner=None, on_done=None, batch: int = 1, batch_cells: int = 2_000_000,
+                 batch_nt_ratio: float = 1.5):
         self.budget = int(budget_bytes)
         self.slots = int(slots)
         self.batch = max(1, int(batch))
+        self.batch_cells = int(batch_cells)
+        self.batch_nt_ratio = float(batch_nt_ratio)
         self.graphs = bool(graphs)
         self.tuner = tuner            # callable(ctx, req) applying kernel choices, or None
         self.on_done = on_done        # callable(Result) after each completion, or None
@@ -176,12 +189,16 @@ class Server:
                 while queue and self._busy < self.slots and sizes[queue[0].rid] <= self._free:
                     group = [queue.popleft()]
                     nb = sizes[group[0].rid]
-                    if self.batch > 1:
+                    if self.batch > 1 and request_cells(group[0]) <= self.batch_cells:
                         key = batch_key(group[0])
+                        nt0 = group[0].prob.nt
                         for r in list(queue):
                             if len(group) >= self.batch:
                                 break
-                            if batch_key(r) == key and nb + sizes[r.rid] <= self._free:
+                            ratio = max(r.prob.nt, nt0) / min(r.prob.nt, nt0)
+                            if (batch_key(r) == key and request_cells(r) <= self.batch_cells
+                                    and ratio <= self.batch_nt_ratio
+                                    and nb + sizes[r.rid] <= self._free):
                                 queue.remove(r)
                                 group.append(r)
                                 nb += sizes[r.rid]
