@@ -1881,8 +1881,9 @@ ssx_status ssx_batch_pcg_solve(ssx_batch* b, const void* const* d, const double*
   std::vector<std::string> err(n);
   std::vector<std::thread> th;
   th.reserve(n);
+  int started = 0;
   for (int i = 0; i < n; ++i) {
-    th.emplace_back([&, i] {
+    auto member = [&, i] {
       const hipError_t e = hipSetDevice(dev);
       if (e != hipSuccess) {
         st[i] = fail(SSX_ERR_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
@@ -1897,9 +1898,25 @@ ssx_status ssx_batch_pcg_solve(ssx_batch* b, const void* const* d, const double*
       std::lock_guard<std::mutex> lk(b->mu);
       --b->active;
       batch_maybe_flush(b);
-    });
+    };
+    try {
+      th.emplace_back(member);
+      ++started;
+    } catch (...) {
+      break;
+    }
+  }
+  if (started < n) {
+    // a thread could not be started: the members that run go on without
+    // the others (who never arrive at the barrier), and the call fails
+    std::lock_guard<std::mutex> lk(b->mu);
+    b->active -= n - started;
+    batch_maybe_flush(b);
   }
   for (std::thread& t : th) t.join();
+  if (started < n)
+    return fail(SSX_ERR_OOM, "could not start a host thread for batch member " +
+                                 std::to_string(started));
   if (status_host)
     for (int i = 0; i < n; ++i) status_host[i] = st[i];
   for (int i = 0; i < n; ++i)
