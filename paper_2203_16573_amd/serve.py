@@ -90,6 +90,30 @@ def request_cells(req: Request) -> int:
     return (p.nz + 2 * p.npml) * (p.nx + 2 * p.npml) * req.nshots
 
 
+def take_group(queue: deque, sizes: dict, free: int, batch: int, batch_cells: int,
+               batch_nt_ratio: float) -> tuple[list, int]:
+    """Removes from the queue the request at its head, with (batch > 1 and
+    the head small enough) up to batch - 1 later ones that can share its
+    solve: equal batch_key, at most batch_cells cells, records within
+    batch_nt_ratio of the head's, all within `free` bytes.  Returns the group
+    and its bytes.  The head must fit `free`."""
+    group = [queue.popleft()]
+    nb = sizes[group[0].rid]
+    if batch > 1 and request_cells(group[0]) <= batch_cells:
+        key = batch_key(group[0])
+        nt0 = group[0].prob.nt
+        for r in list(queue):
+            if len(group) >= batch:
+                break
+            ratio = max(r.prob.nt, nt0) / min(r.prob.nt, nt0)
+            if (batch_key(r) == key and request_cells(r) <= batch_cells
+                    and ratio <= batch_nt_ratio and nb + sizes[r.rid] <= free):
+                queue.remove(r)
+                group.append(r)
+                nb += sizes[r.rid]
+    return group, nb
+
+
 class Server:
     """Admission by footprint and slots, FIFO order, one stream per request
     (or per batch of requests, batch > 1)."""
@@ -187,21 +211,8 @@ class Server:
                 queue.append(r)
             with self._cv:
                 while queue and self._busy < self.slots and sizes[queue[0].rid] <= self._free:
-                    group = [queue.popleft()]
-                    nb = sizes[group[0].rid]
-                    if self.batch > 1 and request_cells(group[0]) <= self.batch_cells:
-                        key = batch_key(group[0])
-                        nt0 = group[0].prob.nt
-                        for r in list(queue):
-                            if len(group) >= self.batch:
-                                break
-                            ratio = max(r.prob.nt, nt0) / min(r.prob.nt, nt0)
-                            if (batch_key(r) == key and request_cells(r) <= self.batch_cells
-                                    and ratio <= self.batch_nt_ratio
-                                    and nb + sizes[r.rid] <= self._free):
-                                queue.remove(r)
-                                group.append(r)
-                                nb += sizes[r.rid]
+                    group, nb = take_group(queue, sizes, self._free, self.batch,
+                                           self.batch_cells, self.batch_nt_ratio)
                     self._free -= nb
                     self._busy += 1
                     th = threading.Thread(target=self._serve,
