@@ -110,6 +110,15 @@ def parse():
     ap.add_argument("--nt", type=int, default=0,
                     help="override the record length (for short profiling runs; the "
                          "result line then describes that shortened workload)")
+    ap.add_argument("--slab-steps", type=int, default=-1,
+                    help="time steps per launch on the thin slab (after the tuner; -1: "
+                         "as tuned)")
+    ap.add_argument("--slab-strip", type=int, default=-1,
+                    help="strip width of the multi-step kernel on the thin slab (after the "
+                         "tuner; -1: as tuned)")
+    ap.add_argument("--prop-slab", action="store_true",
+                    help="with --prop-only: the pairs are thin-slab propagations (X, then "
+                         "X^T of its datum traces) instead of F^T, F")
     ap.add_argument("--calib-copy", type=float, default=0.0,
                     help="with --prop-only: also run 10 plain device copies of this many "
                          "MB (reference for hardware byte counters)")
@@ -213,6 +222,12 @@ def main():
         ctx.set_option(ssx.OPT_SHOT_GROUP, args.shot_group)
     if args.tile_loop >= 0:
         ctx.set_option(ssx.OPT_TILE_LOOP, args.tile_loop)
+    if args.slab_steps >= 0 or args.slab_strip >= 0:
+        ctx.set_option(ssx.OPT_SLAB_STRIP, 0)
+        if args.slab_steps >= 0:
+            ctx.set_option(ssx.OPT_STEPS_PER_LAUNCH_SLAB, args.slab_steps)
+        if args.slab_strip >= 0:
+            ctx.set_option(ssx.OPT_SLAB_STRIP, args.slab_strip)
     ctx.set_graphs(bool(args.graphs))
     wav = inputs.source_wavelet(prob, wl.freq)
     htrue = np.stack([inputs.spike_gather(prob, wav, s) for s in range(prob.nshots)])
@@ -236,13 +251,22 @@ def main():
                 dst.copy_(src)
             torch.cuda.synchronize()
         g = ctx.empty_s()
+        P, V = ctx.empty_s(), ctx.empty_s()
+        if args.prop_slab:
+            g.normal_()
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.prop_only):
-            ctx.adj(d, g)
-            ctx.fwd(g, d)
+            if args.prop_slab:
+                ctx.slab_fwd(g, P, V)
+                ctx.slab_adj(V, P, g)
+            else:
+                ctx.adj(d, g)
+                ctx.fwd(g, d)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        print(json.dumps({"mode": "prop-only", "config": wl.name, "pairs": args.prop_only,
+        print(json.dumps({"mode": "prop-only" + (" slab" if args.prop_slab else ""),
+                          "config": wl.name, "pairs": args.prop_only,
                           "ms_per_propagation": 1e3 * el / (2 * args.prop_only)}), flush=True)
         ctx.close()
         return
