@@ -92,6 +92,14 @@ __device__ __forceinline__ void cvt4(C (&o)[4], const V4<T>& v) {
   for (int i = 0; i < 4; ++i) o[i] = ldc<C>(&v.e[i]);
 }
 
+// Logical block index of hardware block b of n: workgroups are dealt to the
+// 8 XCDs round-robin, so this gives each XCD a contiguous band of strips,
+// and neighbouring strips, which overlap by their halo columns, share an L2.
+__device__ __forceinline__ int slab_block(int b, int n) {
+  const int per = n >> 3, rem = n & 7, xcd = b & 7;
+  return xcd * per + (xcd < rem ? xcd : rem) + (b >> 3);
+}
+
 template <int K, int NS, int WR>
 int slab_owned_width() {
   return SlabShape<K, NS, WR, 1024>::W;
@@ -136,11 +144,12 @@ __global__ __launch_bounds__(slab_threads<typename Tr<T>::C>()) void k_slab(Step
   auto Z_ = [](int I, int c) { return (I + K) * ZP + c; };
 
   const int NZ = a.g.NZ, NX = a.g.NX, Pt = a.g.pitch, L = a.g.L;
-  // block: shot, then window, then strip
+  // block: shot, then window, then strip (XCD-banded order)
   const int per_shot = a.ntx * a.ntz;
-  const int shot = blockIdx.x / per_shot;
-  const int wz = (blockIdx.x - shot * per_shot) / a.ntx;
-  const int strip = blockIdx.x - shot * per_shot - wz * a.ntx;
+  const int blk = slab_block((int)blockIdx.x, (int)gridDim.x);
+  const int shot = blk / per_shot;
+  const int wz = (blk - shot * per_shot) / a.ntx;
+  const int strip = blk - shot * per_shot - wz * a.ntx;
   const int x0 = strip * W;      // first owned column
   const int xr = x0 - H;         // grid column of region column 0
   // rows: one window holding the whole grid (ntz = 1), or window wz owning
