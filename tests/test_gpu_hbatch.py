@@ -122,6 +122,46 @@ def test_batch_with_tuned_members_and_graph_replays():
         c.close()
 
 
+@pytest.mark.parametrize("fd,order", [("f32", 8), ("f64", 4), ("f16", 4)])
+def test_batch_members_with_multistep_options_bitwise(fd, order):
+    # members whose own options take several steps per launch (on the slab,
+    # the full grid or both; 2, 4 or 8 steps on 64- or 128-column strips;
+    # density arrays; a full grid taller than one window) beside a member
+    # stepping once per launch: in the batch every member steps once per
+    # merged launch, and its result must still equal its own solve's, bit
+    # for bit; the second solve replays the captured merged propagations
+    print(f"case hbatch multistep {fd} order {order}", flush=True)
+    ms = [member(i, order, fd) for i in range(6)]
+    ctxs = [c for c, _ in ms]
+    ds = [d for _, d in ms]
+    # order 8: four steps leave no owned rows in a window, so the full grids
+    # (taller than one window) take two, and their batch steps one per launch
+    full = 4 if order == 4 else 2
+    ctxs[0].set_option(ssx.OPT_STEPS_PER_LAUNCH_SLAB, 4)
+    ctxs[1].set_option(ssx.OPT_STEPS_PER_LAUNCH, full)
+    ctxs[1].set_option(ssx.OPT_STEPS_PER_LAUNCH_SLAB, 4)
+    ctxs[3].set_option(ssx.OPT_STEPS_PER_LAUNCH, full)
+    ctxs[3].set_option(ssx.OPT_STEPS_PER_LAUNCH_SLAB, 2)
+    ctxs[4].set_option(ssx.OPT_STEPS_PER_LAUNCH_SLAB, 8 if order == 4 else 2)
+    ctxs[4].set_option(ssx.OPT_SLAB_STRIP, 64)
+    ctxs[5].set_option(ssx.OPT_STEPS_PER_LAUNCH, 2)
+    alphas = [1e-3 * (1 + i % 2) for i in range(6)]
+    ref = []
+    for i, (ctx, d) in enumerate(ms):
+        h1, hist1, _, _ = ctx.pcg_solve(d, alphas[i], 4)
+        ref.append((arrays(h1), hist1))
+    b = ssx.Batch(ctxs)
+    for rep in range(2):
+        hs, hists, its, sts = b.pcg_solve(ds, alphas, 4)
+        assert sts == [0] * 6
+        for i in range(6):
+            assert np.array_equal(arrays(hs[i]), ref[i][0]), (rep, i)
+            assert np.array_equal(hists[i], ref[i][1]), (rep, i)
+    b.close()
+    for c in ctxs:
+        c.close()
+
+
 def test_batch_rejects_mixed_contexts():
     a, _ = member(0, 8, "f32")
     c4, _ = member(1, 4, "f32")
