@@ -171,6 +171,13 @@ constexpr int LDS_PAD_P = 0, LDS_PAD_X = 0, LDS_PAD_Z = 0;
 // for 64 x 32 (each thread owns the same 1 x 4 cells at every height)
 constexpr int step_threads(int tz) { return tz == 32 ? 512 : 256; }
 
+// waves per SIMD the fused step's register budget is set for: 6 (80 VGPRs)
+// for one tile per workgroup, 4 (128) for the tile loop and for density
+// arrays (velocity coefficients in registers), 2 (256) for FP64 values,
+// which spill at 128
+template <bool LOOP, bool VR, typename C>
+constexpr int step_waves() { return sizeof(C) == 8 ? 2 : ((LOOP || VR) ? 4 : 6); }
+
 // shape of the fused step's TX x TZ tile and of what it stages
 template <int K, int TZ>
 struct TileShape {
@@ -853,7 +860,7 @@ __device__ __forceinline__ int xcd_tile(int Lg, int ntiles) {
 //   storing in step.  (General tiles stay outside the loop: inside it, their
 //   long path raises register use past the point of spilling.)
 template <int K, bool ADJ, typename T, int TZ, bool LOOP, bool HIST = false, bool VR = false>
-__global__ __launch_bounds__(step_threads(TZ), LOOP ? 4 : 6) void k_step(StepArgs a) {
+__global__ __launch_bounds__(step_threads(TZ), (step_waves<LOOP, VR, typename Tr<T>::C>())) void k_step(StepArgs a) {
   static_assert(!(VR && (LOOP || HIST)), "variable density: one tile per workgroup, no history");
   using C = typename Tr<T>::C;
   using S = TileShape<K, TZ>;
@@ -953,7 +960,7 @@ __global__ __launch_bounds__(step_threads(TZ), LOOP ? 4 : 6) void k_step(StepArg
 // path of k_step (no history), so every grid's result is bitwise that of
 // its own launch.
 template <int K, bool ADJ, typename T, int TZ, bool VR>
-__global__ __launch_bounds__(step_threads(TZ), 6) void k_step_batch(BatchStep b) {
+__global__ __launch_bounds__(step_threads(TZ), (step_waves<false, VR, typename Tr<T>::C>())) void k_step_batch(BatchStep b) {
   using C = typename Tr<T>::C;
   using S = TileShape<K, TZ>;
   __shared__ __align__(16) C sP[S::HP * S::SPP];
