@@ -25,7 +25,13 @@ Extended Surface Sources" (arXiv 2203.16573) that it follows:
              (Introduction; Time Reversal; Unitarity;
              Accelerated Iterative Inversion; Computing and Symmetrizing
              Lambda);
-* ``greens`` the closed-form 2D point-source response used as a pin.
+* ``greens`` the closed-form 2D point-source response used as a pin;
+* ``prop3``  the 3D time stepping (planes of sources and receivers,
+             constant density) and its exact transpose (Operators section;
+             the 3D generalisation among the closing remarks), pinned by
+             exact reduction to ``prop`` on y-invariant problems, the dot
+             test, energy conservation and the closed-form 3D point-source
+             response.
 
 Every function is pinned by the CPU tests against facts that do not come
 from this code: the dot-product adjoint test, brute-force dense transposes,
@@ -40,6 +46,6 @@ energy conservation and the reflection and transmission coefficients of a
 density-only impedance jump at second order.  The C engine is pinned by
 equality with ``prop`` on every operator and by its own dot test.
 """
-from . import fd, grid, prop, ops, greens  # noqa: F401
+from . import fd, grid, prop, ops, greens, prop3  # noqa: F401
 from .ops import (Model, pcg, pcg_solve, precond, penalty, dscale, normal,  # noqa: F401
                   normal_w, pcg_solve_w, misfit_gradient, normal_v, pcg_solve_v)
