@@ -456,6 +456,73 @@ int64_t ssx_cells_per_launch(ssx_ctx* ctx);
  * argument. */
 ssx_status ssx_launch_shape(ssx_ctx* ctx, int32_t* shape);
 
+/* ======================================================================
+ * Three dimensions (the 3D form of the Operators section's acoustic
+ * system, the generalisation the closing remarks name): F maps a pressure
+ * source on the plane z = z_src to pressure traces on the plane z = z_rec,
+ * F^T is its exact discrete transpose (eqns sdef and sadj1, Appendix A).
+ * Staggered grid (p on nodes, v_x, v_y, v_z on the half nodes of their
+ * axis), order 2 in time and 4 or 8 in space, the split-field absorbing
+ * layer of npml cells on every side, constant density; sampling and
+ * injection as in 2D (linear interpolation in z, transpose divided by h).
+ * Time alignment as in 2D: source sample n enters p^n -> p^{n+1}, trace
+ * sample n is p^{n+1}.
+ * ==================================================================== */
+typedef struct ssx3_ctx ssx3_ctx;
+
+/*
+ * Physical grid nz x ny x nx (z slowest, x fastest), spacing h in every
+ * direction, node (i, k, j) at depth i h, y = k h, x = j h.  Source plane:
+ * nsx x nsy traces at depth z_src, lateral positions (x_src0 + a h,
+ * y_src0 + b h), trace index b nsx + a; receiver plane likewise.  Lateral
+ * positions must lie on grid nodes; depths may fall between nodes.
+ * field_dtype: SSX_F64 or SSX_F32, also the type of every trace array.
+ */
+typedef struct {
+  int32_t nz, ny, nx;
+  double h, dt;
+  int32_t nt;
+  int32_t order;        /* 4 or 8 */
+  int32_t npml;
+  double pml_R;
+  double z_src, x_src0, y_src0;
+  int32_t nsx, nsy;
+  double z_rec, x_rec0, y_rec0;
+  int32_t nrx, nry;
+  int32_t field_dtype;  /* SSX_F64 or SSX_F32 */
+} ssx3_problem;
+
+/* Host-only check (no device work).  Rejects (ARG): a grid below order + 1
+ * nodes on an axis; order not 4 or 8; negative npml; non-positive h, dt, nt
+ * or trace counts; pml_R outside (0, 1); planes off grid nodes or outside
+ * the physical grid; a padded grid with more than 65535 planes in z; field
+ * types other than F64 and F32; non-finite or non-positive kappa or rho.
+ * CFL: c_max dt / h above 1 / (sqrt(3) sum_m |c_m|).  kappa_host (HOST,
+ * [nz][ny][nx], Pa) may be NULL to check the problem alone. */
+ssx_status ssx3_validate(const ssx3_problem* prob, const double* kappa_host, double rho);
+
+/* Device bytes a 3D context owns (seven fields and the coefficients); 0 if
+ * the problem is invalid. */
+size_t ssx3_footprint(const ssx3_problem* prob);
+
+/* Create a 3D context: kappa_host HOST [nz][ny][nx] bulk modulus (Pa), read
+ * during the call only; rho constant density (kg/m^3); stream the
+ * hipStream_t of all its work (NULL = default stream).  Allocates
+ * ssx3_footprint(prob) bytes of device memory (SSX_ERR_OOM on failure). */
+ssx_status ssx3_create(const ssx3_problem* prob, const double* kappa_host, double rho,
+                       void* stream, ssx3_ctx** out);
+
+/* d = F h.  h: DEVICE [nt][nsy][nsx], d: DEVICE [nt][nry][nrx], both of the
+ * field type; asynchronous on the context's stream; one call at a time per
+ * context (the fields are the context's). */
+ssx_status ssx3_fwd(ssx3_ctx* ctx, const void* h, void* d);
+
+/* g = F^T r.  r: DEVICE [nt][nry][nrx], g: DEVICE [nt][nsy][nsx]. */
+ssx_status ssx3_adj(ssx3_ctx* ctx, const void* r, void* g);
+
+/* Release a 3D context (waits for its stream). */
+void ssx3_destroy(ssx3_ctx* ctx);
+
 #ifdef __cplusplus
 }
 #endif

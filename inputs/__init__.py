@@ -69,6 +69,48 @@ class Problem:
         return dataclasses.replace(self, **kw)
 
 
+@dataclass(frozen=True)
+class Problem3:
+    """Geometry and discretisation of the 3D form: physical grid nz x ny x
+    nx (z slowest, x fastest), spacing h on every axis, node (i, k, j) at
+    depth i h, y = k h, x = j h; an absorbing layer of npml cells on every
+    side.  The source is a plane at depth z_src of nsx x nsy traces at
+    (x_src0 + a h, y_src0 + b h), trace index b nsx + a; the receivers a
+    plane at z_rec likewise."""
+
+    nz: int
+    ny: int
+    nx: int
+    h: float
+    dt: float
+    nt: int
+    order: int = 8
+    npml: int = 10
+    pml_R: float = 1e-3
+    z_src: float = 0.0
+    x_src0: float = 0.0
+    y_src0: float = 0.0
+    nsx: int = 1
+    nsy: int = 1
+    z_rec: float = 0.0
+    x_rec0: float = 0.0
+    y_rec0: float = 0.0
+    nrx: int = 1
+    nry: int = 1
+
+    @property
+    def ns(self) -> int:
+        return self.nsx * self.nsy
+
+    @property
+    def nr(self) -> int:
+        return self.nrx * self.nry
+
+    def replace(self, **kw) -> "Problem3":
+        from dataclasses import replace
+        return replace(self, **kw)
+
+
 @dataclass
 class Workload:
     """A problem plus its model, wavelet and solver settings."""
@@ -153,6 +195,29 @@ def layered_velocity(nz: int, nx: int, h: float, rng: np.random.Generator,
     sm = (sm - sm.mean()) / sm.std()
     sm = np.clip(sm, -3.0, 3.0)
     return vel * (1.0 + pert * sm)
+
+
+def layered_velocity3(nz: int, ny: int, nx: int, h: float, rng: np.random.Generator,
+                      nlayers: int = 8, vmin: float = 1500.0, vmax: float = 4000.0,
+                      amp: float = 20.0) -> np.ndarray:
+    """3D layered model [nz][ny][nx]: ``nlayers - 1`` interfaces at depths
+    drawn uniformly over the grid's depth range (sorted), each bent by a
+    sinusoid in x and one in y of amplitude ``amp`` and random
+    wavelength/phase; layer k has velocity vmin + (vmax - vmin) k /
+    (nlayers - 1)."""
+    nif = nlayers - 1
+    depths = np.sort(rng.uniform(0.1 * (nz - 1) * h, 0.9 * (nz - 1) * h, size=nif))
+    lam = rng.uniform(500.0, 4000.0, size=(nif, 2))
+    phi = rng.uniform(0.0, 2.0 * math.pi, size=(nif, 2))
+    z = np.arange(nz)[:, None, None] * h
+    y = np.arange(ny)[None, :, None] * h
+    x = np.arange(nx)[None, None, :] * h
+    layer = np.zeros((nz, ny, nx), dtype=np.int64)
+    for k in range(nif):
+        zk = (depths[k] + amp * np.sin(2.0 * math.pi * x / lam[k, 0] + phi[k, 0])
+              + amp * np.sin(2.0 * math.pi * y / lam[k, 1] + phi[k, 1]))
+        layer += (z >= zk).astype(np.int64)
+    return vmin + (vmax - vmin) * layer / (nlayers - 1)
 
 
 def kappa_from_velocity(vel: np.ndarray, rho: float = RHO_WATERLIKE) -> np.ndarray:

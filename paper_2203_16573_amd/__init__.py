@@ -60,7 +60,9 @@ EXPORTS = ("ssx_validate", "ssx_footprint", "ssx_create", "ssx_destroy", "ssx_fw
            "ssx_weight_d", "ssx_weight_m", "ssx_normal_w", "ssx_pcg_solve_w",
            "ssx_fwd_v", "ssx_adj_v", "ssx_tr_inverse", "ssx_lambda", "ssx_block",
            "ssx_misfit_gradient", "ssx_pcg_solve_v", "ssx_dot_static", "ssx_create_density",
-           "ssx_batch_create", "ssx_batch_pcg_solve", "ssx_batch_destroy")
+           "ssx_batch_create", "ssx_batch_pcg_solve", "ssx_batch_destroy",
+           "ssx3_validate", "ssx3_footprint", "ssx3_create", "ssx3_fwd", "ssx3_adj",
+           "ssx3_destroy")
 
 DOT_STATIC_MAX_SHOTS = 64  # SSX_DOT_STATIC_MAX_SHOTS
 
@@ -82,6 +84,18 @@ class ssx_problem(ctypes.Structure):
                 ("slab_dz", ctypes.c_int32), ("nshots", ctypes.c_int32),
                 ("field_dtype", ctypes.c_int32), ("vec_dtype", ctypes.c_int32),
                 ("rslab_dz", ctypes.c_int32)]
+
+
+class ssx3_problem(ctypes.Structure):
+    _fields_ = [("nz", ctypes.c_int32), ("ny", ctypes.c_int32), ("nx", ctypes.c_int32),
+                ("h", ctypes.c_double), ("dt", ctypes.c_double),
+                ("nt", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("npml", ctypes.c_int32), ("pml_R", ctypes.c_double),
+                ("z_src", ctypes.c_double), ("x_src0", ctypes.c_double),
+                ("y_src0", ctypes.c_double), ("nsx", ctypes.c_int32), ("nsy", ctypes.c_int32),
+                ("z_rec", ctypes.c_double), ("x_rec0", ctypes.c_double),
+                ("y_rec0", ctypes.c_double), ("nrx", ctypes.c_int32), ("nry", ctypes.c_int32),
+                ("field_dtype", ctypes.c_int32)]
 
 
 _lib = None
@@ -148,6 +162,15 @@ def lib():
                                           ctypes.POINTER(ctypes.c_int32)]
         L.ssx_batch_destroy.argtypes = [vp]
         L.ssx_batch_destroy.restype = None
+        P3 = ctypes.POINTER(ssx3_problem)
+        L.ssx3_validate.argtypes = [P3, dp, c_dbl]
+        L.ssx3_footprint.argtypes = [P3]
+        L.ssx3_footprint.restype = ctypes.c_size_t
+        L.ssx3_create.argtypes = [P3, dp, c_dbl, vp, ctypes.POINTER(vp)]
+        L.ssx3_fwd.argtypes = [vp, vp, vp]
+        L.ssx3_adj.argtypes = [vp, vp, vp]
+        L.ssx3_destroy.argtypes = [vp]
+        L.ssx3_destroy.restype = None
         _lib = L
     return _lib
 
@@ -504,6 +527,96 @@ class Batch:
         if getattr(self, "_b", None):
             lib().ssx_batch_destroy(self._b)
             self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# three dimensions (ssx3_*)
+
+def make_problem3(prob, field_dtype: str = "f32") -> ssx3_problem:
+    if field_dtype not in ("f64", "f32"):
+        raise ValueError("3D fields are f64 or f32")
+    return ssx3_problem(int(prob.nz), int(prob.ny), int(prob.nx), float(prob.h),
+                        float(prob.dt), int(prob.nt), int(prob.order), int(prob.npml),
+                        float(prob.pml_R), float(prob.z_src), float(prob.x_src0),
+                        float(prob.y_src0), int(prob.nsx), int(prob.nsy), float(prob.z_rec),
+                        float(prob.x_rec0), float(prob.y_rec0), int(prob.nrx), int(prob.nry),
+                        DTYPES[field_dtype])
+
+
+def validate3(prob, kappa=None, rho: float = 1000.0, field_dtype: str = "f32") -> None:
+    """Host-only validation of a 3D problem (and model); raises SSXError."""
+    P = make_problem3(prob, field_dtype)
+    k = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64)
+    _check(lib().ssx3_validate(ctypes.byref(P), _dptr(k) if k is not None else None, rho))
+
+
+def footprint3(prob, field_dtype: str = "f32") -> int:
+    P = make_problem3(prob, field_dtype)
+    return int(lib().ssx3_footprint(ctypes.byref(P)))
+
+
+class Context3:
+    """An ssx3_ctx (3D F and F^T) bound to a torch device stream (the current
+    stream by default).  Traces: device tensors [nt][nsy][nsx] (source
+    plane) and [nt][nry][nrx] (receiver plane) of float64 for f64 fields,
+    float32 for f32."""
+
+    def __init__(self, prob, kappa, rho: float, field_dtype: str = "f32", stream=None):
+        import torch
+
+        self.prob = prob
+        self.field_dtype = field_dtype
+        self.dtype = torch.float64 if field_dtype == "f64" else torch.float32
+        self._P = make_problem3(prob, field_dtype)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        k = np.ascontiguousarray(kappa, dtype=np.float64)
+        if k.shape != (prob.nz, prob.ny, prob.nx):
+            raise ValueError("kappa must be [nz][ny][nx]")
+        ctx = ctypes.c_void_p()
+        _check(lib().ssx3_create(ctypes.byref(self._P), _dptr(k), float(rho),
+                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)))
+        self._ctx = ctx
+
+    def _arg(self, t, shape, name):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a device tensor")
+        if t.dtype != self.dtype or not t.is_contiguous() or t.numel() != int(np.prod(shape)):
+            raise ValueError(f"{name}: expected contiguous {self.dtype} of shape {shape}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def empty_src(self):
+        import torch
+        p = self.prob
+        return torch.zeros((p.nt, p.nsy, p.nsx), dtype=self.dtype, device="cuda")
+
+    def empty_rec(self):
+        import torch
+        p = self.prob
+        return torch.zeros((p.nt, p.nry, p.nrx), dtype=self.dtype, device="cuda")
+
+    def fwd(self, h, d):
+        p = self.prob
+        _check(lib().ssx3_fwd(self._ctx, self._arg(h, (p.nt, p.nsy, p.nsx), "h"),
+                              self._arg(d, (p.nt, p.nry, p.nrx), "d")))
+        return d
+
+    def adj(self, r, g):
+        p = self.prob
+        _check(lib().ssx3_adj(self._ctx, self._arg(r, (p.nt, p.nry, p.nrx), "r"),
+                              self._arg(g, (p.nt, p.nsy, p.nsx), "g")))
+        return g
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().ssx3_destroy(self._ctx)
+            self._ctx = None
 
     def __del__(self):
         try:

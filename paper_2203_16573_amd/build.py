@@ -12,7 +12,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libssx.so")
 
-SOURCES = ["ssx_step.hip", "ssx_slab.hip", "ssx_vec.hip", "ssx_grad.hip", "ssx_api.cpp"]
+SOURCES = ["ssx_step.hip", "ssx_slab.hip", "ssx_vec.hip", "ssx_grad.hip", "ssx3.hip",
+           "ssx_api.cpp", "ssx3_api.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC",

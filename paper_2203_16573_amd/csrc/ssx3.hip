@@ -1,0 +1,309 @@
+// Three-dimensional propagation F (source plane -> pressure traces on a
+// receiver plane) and its exact transpose: the 3D form of the acoustic
+// system of the Operators section with the source a density on the plane
+// z = z_s (the closing remarks name 3D as the natural generalisation).
+// Staggered grid: p on nodes, split p_x + p_y + p_z (kept on every cell), and
+// v_x, v_y, v_z on the half nodes of their own axis; order 2 in time, 4 or
+// 8 in space; the split-field absorbing layer of the 2D scheme applied per
+// axis; planes sampled by linear interpolation in z, traces on grid nodes
+// laterally (trace index iy * nx_traces + ix), injection its transpose.
+// Constant density; FP64 or FP32 fields (the compute type is the storage
+// type).
+//
+// Layout: each field is one [NZ][NY][NX] array, x fastest, no ghost cells
+// (values outside the grid are read as zero).  One thread per cell,
+// 64 x 4 (x, y) threads per workgroup, one z plane per grid row.
+//
+// Forward step n: k3_vel (v^{n+1/2} from p^n), k3_pres (p^{n+1} from
+// v^{n+1/2}, the source sample h[n] injected), then the receiver plane
+// sampled (P[n] = R p^{n+1}).  Transposed step n (reverse order): the
+// source-plane gather of the pressure adjoint (hbar[n]), k3_adj_v (the
+// velocity adjoints: the previous step's layer scaling, then the transposed
+// pressure updates), k3_adj_p (the pressure adjoints: layer scaling, the
+// transposed velocity updates, and the recording of step n - 1 added).
+#include "ssx3_internal.h"
+#include "ssx_cell.h"
+
+namespace ssx3 {
+using ssx::acc;
+using ssx::fmac;
+using ssx::wst;
+
+constexpr int BX = 64, BY = 4;
+
+template <typename T>
+struct View {
+  const T* a;
+  int NZ, NY, NX;
+  __device__ __forceinline__ T operator()(int z, int y, int x) const {
+    return (z < 0 || z >= NZ || y < 0 || y >= NY || x < 0 || x >= NX)
+               ? T(0)
+               : a[((long long)z * NY + y) * NX + x];
+  }
+};
+
+// layer factors: per axis (z, y, x) four arrays a_node, b_node, a_half,
+// b_half of the axis length, one after another
+template <typename T>
+struct Fac {
+  const T* f;
+  int NZ, NY, NX;
+  __device__ __forceinline__ const T* ax(int axis) const {
+    return axis == 0 ? f : (axis == 1 ? f + 4 * NZ : f + 4 * NZ + 4 * NY);
+  }
+  __device__ __forceinline__ T an(int axis, int i) const { return ax(axis)[i]; }
+  __device__ __forceinline__ T bn(int axis, int i) const {
+    return ax(axis)[(axis == 0 ? NZ : axis == 1 ? NY : NX) + i];
+  }
+  __device__ __forceinline__ T ah(int axis, int i) const {
+    return ax(axis)[2 * (axis == 0 ? NZ : axis == 1 ? NY : NX) + i];
+  }
+  __device__ __forceinline__ T bh(int axis, int i) const {
+    return ax(axis)[3 * (axis == 0 ? NZ : axis == 1 ? NY : NX) + i];
+  }
+};
+
+// the interpolation weight with which cell (z, y, x) enters plane pl (zero
+// off the plane), and the trace index there
+__device__ __forceinline__ double plane_w(const Plane3& pl, int z, int y, int x, int& tr) {
+  if (y < pl.y0 || y >= pl.y0 + pl.ny || x < pl.x0 || x >= pl.x0 + pl.nx) return 0.0;
+  tr = (y - pl.y0) * pl.nx + (x - pl.x0);
+  double w = 0.0;
+  if (z == pl.r0) w += pl.w0;
+  if (pl.r1 >= 0 && z == pl.r1) w += pl.w1;
+  return w;
+}
+
+template <int K, typename T>
+__global__ __launch_bounds__(BX* BY) void k3_vel(Fields3<T> f, Dims3 d, const T* fac, T cb) {
+  const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y, z = blockIdx.z;
+  if (x >= d.NX || y >= d.NY) return;
+  const long long o = ((long long)z * d.NY + y) * d.NX + x;
+  const View<T> p{f.p, d.NZ, d.NY, d.NX};
+  const Fac<T> F{fac, d.NZ, d.NY, d.NX};
+  T gx = T(0), gy = T(0), gz = T(0);
+#pragma unroll
+  for (int m = 1; m <= K; ++m) {
+    const T c = wst<K, T>(m - 1);
+    gx = acc(gx, c, p(z, y, x + m), p(z, y, x + 1 - m));
+    gy = acc(gy, c, p(z, y + m, x), p(z, y + 1 - m, x));
+    gz = acc(gz, c, p(z + m, y, x), p(z + 1 - m, y, x));
+  }
+  f.vx[o] = fmac(F.ah(2, x), f.vx[o], -(F.bh(2, x) * cb) * gx);
+  f.vy[o] = fmac(F.ah(1, y), f.vy[o], -(F.bh(1, y) * cb) * gy);
+  f.vz[o] = fmac(F.ah(0, z), f.vz[o], -(F.bh(0, z) * cb) * gz);
+}
+
+template <int K, typename T>
+__global__ __launch_bounds__(BX* BY) void k3_pres(Fields3<T> f, Dims3 d, const T* fac,
+                                                  const T* ck, Plane3 src, const T* htr) {
+  const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y, z = blockIdx.z;
+  if (x >= d.NX || y >= d.NY) return;
+  const long long o = ((long long)z * d.NY + y) * d.NX + x;
+  const View<T> vx{f.vx, d.NZ, d.NY, d.NX}, vy{f.vy, d.NZ, d.NY, d.NX},
+      vz{f.vz, d.NZ, d.NY, d.NX};
+  const Fac<T> F{fac, d.NZ, d.NY, d.NX};
+  T dx = T(0), dy = T(0), dz = T(0);
+#pragma unroll
+  for (int m = 1; m <= K; ++m) {
+    const T c = wst<K, T>(m - 1);
+    dx = acc(dx, c, vx(z, y, x + m - 1), vx(z, y, x - m));
+    dy = acc(dy, c, vy(z, y + m - 1, x), vy(z, y - m, x));
+    dz = acc(dz, c, vz(z + m - 1, y, x), vz(z - m, y, x));
+  }
+  if (htr) {
+    int tr = 0;
+    const double w = plane_w(src, z, y, x, tr);
+    if (w != 0.0) dz = dz - T(w) * htr[tr];
+  }
+  const T k = ck[o];
+  const T px = fmac(F.an(2, x), f.px[o], -(F.bn(2, x) * k) * dx);
+  const T py = fmac(F.an(1, y), f.py[o], -(F.bn(1, y) * k) * dy);
+  const T pz = fmac(F.an(0, z), f.pz[o], -(F.bn(0, z) * k) * dz);
+  f.px[o] = px;
+  f.py[o] = py;
+  f.pz[o] = pz;
+  f.p[o] = (px + py) + pz;
+}
+
+// Transposed pressure updates: the velocity adjoints take the layer scaling
+// pending from the previous transposed step (a_half v~), then
+//   v~_a += sum_m c_m (q_a[i+m] - q_a[i+1-m]),  q_a = b_node,a Ck p~_a,
+// the transpose of p_a -= b_node,a Ck D_a^- v_a (D^- = -(D^+)^T).
+template <int K, typename T>
+__global__ __launch_bounds__(BX* BY) void k3_adj_v(Fields3<T> f, Dims3 d, const T* fac,
+                                                   const T* ck) {
+  const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y, z = blockIdx.z;
+  if (x >= d.NX || y >= d.NY) return;
+  const long long o = ((long long)z * d.NY + y) * d.NX + x;
+  const Fac<T> F{fac, d.NZ, d.NY, d.NX};
+  const long long sy = d.NX, sz = (long long)d.NY * d.NX;
+  // q at a neighbouring node of axis a (zero outside the grid)
+  auto q = [&](const T* pa, int axis, int zz, int yy, int xx) -> T {
+    if (zz < 0 || zz >= d.NZ || yy < 0 || yy >= d.NY || xx < 0 || xx >= d.NX) return T(0);
+    const long long j = zz * sz + yy * sy + xx;
+    const int i = axis == 0 ? zz : (axis == 1 ? yy : xx);
+    return (F.bn(axis, i) * ck[j]) * pa[j];
+  };
+  T sx = T(0), sy_ = T(0), sz_ = T(0);
+#pragma unroll
+  for (int m = 1; m <= K; ++m) {
+    const T c = wst<K, T>(m - 1);
+    sx = acc(sx, c, q(f.px, 2, z, y, x + m), q(f.px, 2, z, y, x + 1 - m));
+    sy_ = acc(sy_, c, q(f.py, 1, z, y + m, x), q(f.py, 1, z, y + 1 - m, x));
+    sz_ = acc(sz_, c, q(f.pz, 0, z + m, y, x), q(f.pz, 0, z + 1 - m, y, x));
+  }
+  f.vx[o] = F.ah(2, x) * f.vx[o] + sx;
+  f.vy[o] = F.ah(1, y) * f.vy[o] + sy_;
+  f.vz[o] = F.ah(0, z) * f.vz[o] + sz_;
+}
+
+// Transposed velocity updates: p~_a <- a_node,a p~_a + t, with
+//   t = sum_a sum_m c_m (u_a[i+m-1] - u_a[i-m]),  u_a = b_half,a Cb v~_a
+// (the transpose of v_a -= b_half,a Cb D_a^+ p, p = p_x + p_y + p_z, taken
+// by all three parts), then the recording of step n - 1 (P = R p) added to
+// each part.
+template <int K, typename T>
+__global__ __launch_bounds__(BX* BY) void k3_adj_p(Fields3<T> f, Dims3 d, const T* fac, T cb,
+                                                   Plane3 rec, const T* rtr) {
+  const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y, z = blockIdx.z;
+  if (x >= d.NX || y >= d.NY) return;
+  const long long o = ((long long)z * d.NY + y) * d.NX + x;
+  const Fac<T> F{fac, d.NZ, d.NY, d.NX};
+  const View<T> vx{f.vx, d.NZ, d.NY, d.NX}, vy{f.vy, d.NZ, d.NY, d.NX},
+      vz{f.vz, d.NZ, d.NY, d.NX};
+  auto bx = [&](int i) { return (i < 0 || i >= d.NX) ? T(0) : F.bh(2, i) * cb; };
+  auto by = [&](int i) { return (i < 0 || i >= d.NY) ? T(0) : F.bh(1, i) * cb; };
+  auto bz = [&](int i) { return (i < 0 || i >= d.NZ) ? T(0) : F.bh(0, i) * cb; };
+  T tx = T(0), ty = T(0), tz = T(0);
+#pragma unroll
+  for (int m = 1; m <= K; ++m) {
+    const T c = wst<K, T>(m - 1);
+    tx = acc(tx, c, bx(x + m - 1) * vx(z, y, x + m - 1), bx(x - m) * vx(z, y, x - m));
+    ty = acc(ty, c, by(y + m - 1) * vy(z, y + m - 1, x), by(y - m) * vy(z, y - m, x));
+    tz = acc(tz, c, bz(z + m - 1) * vz(z + m - 1, y, x), bz(z - m) * vz(z - m, y, x));
+  }
+  const T t = (tx + ty) + tz;
+  T r = T(0);
+  if (rtr) {
+    int tr = 0;
+    const double w = plane_w(rec, z, y, x, tr);
+    if (w != 0.0) r = T(w) * rtr[tr];
+  }
+  f.px[o] = fmac(F.an(2, x), f.px[o], t) + r;
+  f.py[o] = fmac(F.an(1, y), f.py[o], t) + r;
+  f.pz[o] = fmac(F.an(0, z), f.pz[o], t) + r;
+}
+
+// the recording's transpose alone (the first transposed step): each part
+// of the pressure adjoint += R^T r
+template <typename T>
+__global__ void k3_spread(Fields3<T> f, Dims3 d, Plane3 pl, const T* tr) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * pl.ny * pl.nx) return;
+  const int row = i / (pl.ny * pl.nx), t = i - row * (pl.ny * pl.nx);
+  if (row == 1 && pl.r1 < 0) return;
+  const int z = row ? pl.r1 : pl.r0, y = pl.y0 + t / pl.nx, x = pl.x0 + t % pl.nx;
+  const T w = T(row ? pl.w1 : pl.w0);
+  const long long o = ((long long)z * d.NY + y) * d.NX + x;
+  const T v = w * tr[t];
+  f.px[o] += v;
+  f.py[o] += v;
+  f.pz[o] += v;
+}
+
+// plane gather: out[t] = sum_rows w s field, s = 1 (MODE 0) or, for the
+// source plane of the transpose, b_node,z Ck (MODE 1)
+template <typename T, int MODE>
+__global__ void k3_gather(const T* field, Dims3 d, Plane3 pl, const T* fac, const T* ck, T* out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= pl.ny * pl.nx) return;
+  const int y = pl.y0 + t / pl.nx, x = pl.x0 + t % pl.nx;
+  const Fac<T> F{fac, d.NZ, d.NY, d.NX};
+  auto val = [&](int z) {
+    const long long o = ((long long)z * d.NY + y) * d.NX + x;
+    return MODE == 0 ? field[o] : (F.bn(0, z) * ck[o]) * field[o];
+  };
+  T s = T(pl.w0) * val(pl.r0);
+  if (pl.r1 >= 0) s = s + T(pl.w1) * val(pl.r1);
+  out[t] = s;
+}
+
+// ---------------------------------------------------------------------------
+
+static dim3 cells(const Dims3& d) { return dim3((d.NX + BX - 1) / BX, (d.NY + BY - 1) / BY, d.NZ); }
+
+template <typename T>
+static hipError_t step_t(int order, bool adj, const Fields3<T>& f, const Dims3& d, const T* fac,
+                         const T* ck, T cb, const Plane3& pl, const T* tr, hipStream_t s) {
+  const dim3 g = cells(d), b(BX, BY);
+  if (d.NZ < 1 || d.NZ > 65535) return hipErrorInvalidValue;
+  if (order == 4) {
+    if (!adj) {
+      hipLaunchKernelGGL((k3_vel<2, T>), g, b, 0, s, f, d, fac, cb);
+      hipLaunchKernelGGL((k3_pres<2, T>), g, b, 0, s, f, d, fac, ck, pl, tr);
+    } else {
+      hipLaunchKernelGGL((k3_adj_v<2, T>), g, b, 0, s, f, d, fac, ck);
+      hipLaunchKernelGGL((k3_adj_p<2, T>), g, b, 0, s, f, d, fac, cb, pl, tr);
+    }
+  } else if (order == 8) {
+    if (!adj) {
+      hipLaunchKernelGGL((k3_vel<4, T>), g, b, 0, s, f, d, fac, cb);
+      hipLaunchKernelGGL((k3_pres<4, T>), g, b, 0, s, f, d, fac, ck, pl, tr);
+    } else {
+      hipLaunchKernelGGL((k3_adj_v<4, T>), g, b, 0, s, f, d, fac, ck);
+      hipLaunchKernelGGL((k3_adj_p<4, T>), g, b, 0, s, f, d, fac, cb, pl, tr);
+    }
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch3_step(bool f64, int order, bool adj, const void* fields, const Dims3& d,
+                        const void* fac, const void* ck, double cb, const Plane3& pl,
+                        const void* tr, hipStream_t s) {
+  if (f64)
+    return step_t<double>(order, adj, fields3<double>(fields, d), d, (const double*)fac,
+                          (const double*)ck, cb, pl, (const double*)tr, s);
+  return step_t<float>(order, adj, fields3<float>(fields, d), d, (const float*)fac,
+                       (const float*)ck, (float)cb, pl, (const float*)tr, s);
+}
+
+hipError_t launch3_spread(bool f64, const void* fields, const Dims3& d, const Plane3& pl,
+                          const void* tr, hipStream_t s) {
+  const int n = 2 * pl.ny * pl.nx;
+  const dim3 g((n + 255) / 256), b(256);
+  if (f64)
+    hipLaunchKernelGGL((k3_spread<double>), g, b, 0, s, fields3<double>(fields, d), d, pl,
+                       (const double*)tr);
+  else
+    hipLaunchKernelGGL((k3_spread<float>), g, b, 0, s, fields3<float>(fields, d), d, pl,
+                       (const float*)tr);
+  return hipGetLastError();
+}
+
+hipError_t launch3_gather(bool f64, bool scaled, const void* field, const Dims3& d,
+                          const Plane3& pl, const void* fac, const void* ck, void* out,
+                          hipStream_t s) {
+  const int n = pl.ny * pl.nx;
+  const dim3 g((n + 255) / 256), b(256);
+  if (f64) {
+    if (scaled)
+      hipLaunchKernelGGL((k3_gather<double, 1>), g, b, 0, s, (const double*)field, d, pl,
+                         (const double*)fac, (const double*)ck, (double*)out);
+    else
+      hipLaunchKernelGGL((k3_gather<double, 0>), g, b, 0, s, (const double*)field, d, pl,
+                         (const double*)fac, (const double*)ck, (double*)out);
+  } else {
+    if (scaled)
+      hipLaunchKernelGGL((k3_gather<float, 1>), g, b, 0, s, (const float*)field, d, pl,
+                         (const float*)fac, (const float*)ck, (float*)out);
+    else
+      hipLaunchKernelGGL((k3_gather<float, 0>), g, b, 0, s, (const float*)field, d, pl,
+                         (const float*)fac, (const float*)ck, (float*)out);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace ssx3

@@ -1,0 +1,50 @@
+// Internal interface between the host side of the 3D entry points
+// (ssx3_api.cpp) and their kernels (ssx3.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ssx3 {
+
+struct Dims3 {
+  int NZ, NY, NX;  // padded grid: physical + 2 npml per axis
+};
+
+// A plane of traces: grid rows r0 (weight w0) and r1 (weight w1; r1 < 0:
+// one row), lateral node ranges [y0, y0 + ny) and [x0, x0 + nx); trace
+// index (y - y0) * nx + (x - x0).
+struct Plane3 {
+  int r0, r1;
+  double w0, w1;
+  int y0, ny, x0, nx;
+};
+
+// The seven [NZ][NY][NX] fields, carved from one buffer in this order.
+template <typename T>
+struct Fields3 {
+  T *vx, *vy, *vz, *px, *py, *pz, *p;
+};
+template <typename T>
+inline Fields3<T> fields3(const void* base, const Dims3& d) {
+  T* b = static_cast<T*>(const_cast<void*>(base));
+  const long long n = (long long)d.NZ * d.NY * d.NX;
+  return {b, b + n, b + 2 * n, b + 3 * n, b + 4 * n, b + 5 * n, b + 6 * n};
+}
+
+// One time step of the fields (forward: v then p with the source plane's
+// samples tr; transposed: the velocity and pressure adjoints with the
+// recording of the next-lower step tr, or none).  fac: the layer factors,
+// per axis z, y, x four arrays a_node, b_node, a_half, b_half; ck = dt kappa
+// / h per cell; cb = dt / (rho h).
+hipError_t launch3_step(bool f64, int order, bool adj, const void* fields, const Dims3& d,
+                        const void* fac, const void* ck, double cb, const Plane3& pl,
+                        const void* tr, hipStream_t s);
+// each pressure part += R^T tr on plane pl
+hipError_t launch3_spread(bool f64, const void* fields, const Dims3& d, const Plane3& pl,
+                          const void* tr, hipStream_t s);
+// out = R field on plane pl; scaled: R (b_node,z ck field)
+hipError_t launch3_gather(bool f64, bool scaled, const void* field, const Dims3& d,
+                          const Plane3& pl, const void* fac, const void* ck, void* out,
+                          hipStream_t s);
+
+}  // namespace ssx3

@@ -315,6 +315,11 @@ struct Layout {
 
 }  // namespace
 
+// the text ssx_last_error returns, for the 3D entry points (ssx3_api.cpp)
+namespace ssx {
+void set_last_error(const std::string& msg) { g_err = msg; }
+}  // namespace ssx
+
 struct GridDev {
   GridHost host;
   GridDims dims;

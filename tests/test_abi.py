@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     txt = open(os.path.join(ROOT, "include", "ssx.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(ssx_[a-z_0-9]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(ssx3?_[a-z_0-9]+)\s*\(", txt)))
 
 
 def test_header_declares_the_binding_exports():
@@ -122,3 +122,62 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stdout
+
+
+# ---------------------------------------------------------------------------
+# the 3D entry points (host-only checks)
+
+def _prob3(**kw):
+    base = dict(nz=20, ny=16, nx=24, h=10.0, dt=1e-3, nt=10, order=8, npml=5,
+                z_src=35.0, x_src0=20.0, y_src0=10.0, nsx=10, nsy=6,
+                z_rec=120.0, x_rec0=0.0, y_rec0=0.0, nrx=24, nry=16)
+    base.update(kw)
+    return inputs.Problem3(**base)
+
+
+def test_validate3_accepts_and_sizes():
+    prob = _prob3()
+    kap = np.full((prob.nz, prob.ny, prob.nx), 1000.0 * 3000.0 ** 2)
+    ssx.validate3(prob, kap, 1000.0, field_dtype="f32")
+    ssx.validate3(prob, kap, 1000.0, field_dtype="f64")
+    n = (prob.nz + 10) * (prob.ny + 10) * (prob.nx + 10)
+    assert ssx.footprint3(prob, "f32") == (8 * n + 4 * (30 + 26 + 34)) * 4
+    assert ssx.footprint3(prob, "f64") == 2 * ssx.footprint3(prob, "f32")
+
+
+@pytest.mark.parametrize("change,status", [
+    (dict(order=6), 1),
+    (dict(nz=8), 1),                    # below order + 1 nodes
+    (dict(npml=-1), 1),
+    (dict(x_src0=15.0), 1),             # off a grid node
+    (dict(nsx=23), 1),                  # past the last column
+    (dict(y_rec0=10.0, nry=16), 1),     # past the last row
+    (dict(z_src=195.0), 1),             # between the last node and beyond
+    (dict(z_rec=-1.0), 1),
+    (dict(nt=0), 1),
+    (dict(pml_R=1.0), 1),
+    (dict(dt=2e-3), 2),                 # c dt / h above 1 / (sqrt 3 sum |c_m|)
+])
+def test_validate3_rejects(change, status):
+    prob = _prob3(**change)
+    kap = np.full((prob.nz, prob.ny, prob.nx), 1000.0 * 3000.0 ** 2)
+    with pytest.raises(ssx.SSXError) as e:
+        ssx.validate3(prob, kap, 1000.0)
+    assert e.value.status == status
+
+
+def test_validate3_rejects_models_and_dtypes():
+    prob = _prob3()
+    kap = np.full((prob.nz, prob.ny, prob.nx), 1000.0 * 3000.0 ** 2)
+    bad = kap.copy()
+    bad[3, 4, 5] = -1.0
+    with pytest.raises(ssx.SSXError):
+        ssx.validate3(prob, bad, 1000.0)
+    with pytest.raises(ssx.SSXError):
+        ssx.validate3(prob, kap, 0.0)
+    P = ssx.make_problem3(prob, "f32")
+    P.field_dtype = 2   # F16: not a 3D field type
+    assert ssx.lib().ssx3_validate(P, None, 1000.0) == 1
+    assert ssx.lib().ssx3_footprint(P) == 0
+    with pytest.raises(ValueError):
+        ssx.make_problem3(prob, "bf16")
