@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2",
-                    choices=["c1", "c2", "c3", "c4", "c4bf", "c5", "xw", "vp"],
+                    choices=["c1", "c2", "c3", "c4", "c4bf", "c5", "xw", "vp", "3d"],
                     help="c1..c5: the benchmark configurations; xw: the paper's crosswell "
                          "example, CG against weighted PCG; vp: a variable-projection "
                          "outer loop on the crosswell example")
@@ -189,6 +189,8 @@ def main():
         return crosswell_bench(args)
     if args.config == "vp":
         return varpro_bench(args)
+    if args.config == "3d":
+        return bench3d(args)
     cnum = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "c4bf": 4}[args.config]
     wl = inputs.workload(cnum)
     if args.density:
@@ -861,6 +863,98 @@ def varpro_bench(args):
                    "nz": prob.nz, "nx": prob.nx, "nt": prob.nt, "K": K, "field_dtype": fd},
         "history": hist,
     }
+    print(json.dumps(out), flush=True)
+
+
+def bench3d(args):
+    """The 3D form (ssx3_*): one step is F then F^T (the propagations of one
+    normal-operator application) on a 201 x 201 x 401 grid (z, y, x) at 10 m
+    with 20 absorbing cells per side (241 x 241 x 441 = 25.6 M cells), order
+    8, nt 1000 (--nt), a seeded 3D layered model (1.5-4 km/s, constant
+    density), the source plane at 1000 m and the receiver plane at 200 m
+    over the whole lateral grid, FP32 fields (--dtype f64 for FP64).  The
+    roofline is that of one time step (k3_vel + k3_pres) timed with events
+    on the context's stream over a forward propagation, against 9 field
+    values per cell-update (read p, v_x, v_y, v_z and ck; write p, v_x, v_y,
+    v_z)."""
+    import numpy as np
+    import torch
+
+    import inputs
+    import paper_2203_16573_amd as ssx
+
+    fd = args.dtype or "f32"
+    rho = 1000.0
+    nz, ny, nx, hh = 201, 201, 401, 10.0
+    prob = inputs.Problem3(nz=nz, ny=ny, nx=nx, h=hh, dt=1e-3, nt=args.nt or 1000, order=8,
+                           npml=20, z_src=1000.0, nsx=nx, nsy=ny, z_rec=200.0, nrx=nx,
+                           nry=ny)
+    vel = inputs.layered_velocity3(nz, ny, nx, hh, np.random.default_rng(inputs.BASE_SEED + 30))
+    kap = rho * vel * vel
+    ctx = ssx.Context3(prob, kap, rho, field_dtype=fd)
+    h = ctx.empty_src()
+    w = inputs.ricker((np.arange(prob.nt) + 0.5) * prob.dt, 15.0)
+    h[:, ny // 2, nx // 2] = torch.tensor(w / hh ** 2, dtype=ctx.dtype, device="cuda")
+    d = ctx.empty_rec()
+    g = ctx.empty_src()
+
+    def step():
+        ctx.fwd(h, d)
+        ctx.adj(d, g)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    # per-step kernel time of the forward sweep, events on the context's stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(ctx.stream)
+    ctx.fwd(h, d)
+    e1.record(ctx.stream)
+    torch.cuda.synchronize()
+    us_step = 1e3 * e0.elapsed_time(e1) / prob.nt
+    NZ, NY, NX = nz + 40, ny + 40, nx + 40
+    cells = NZ * NY * NX
+    esz = 8 if fd == "f64" else 4
+    achieved = 9 * esz * cells / (us_step * 1e-6) / 1e9
+    out = {
+        "metric": "3D F + F^T pairs/s", "value": round(1.0 / el, 4), "unit": "pairs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * el, 2), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": fd,
+        "data": "synthetic (seeded 3D layered model; Ricker point source on the source plane)",
+        "config": {"workload": f"3d: {nz}x{ny}x{nx} @ {hh} m, order 8, nt {prob.nt}, "
+                               f"planes {ny}x{nx}", "nz": nz, "ny": ny, "nx": nx,
+                   "nt": prob.nt, "field_dtype": fd},
+        "gcell_updates_per_s": round(2 * prob.nt * cells / el / 1e9, 2),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0,
+                     "unit": "GB/s", "frac": round(achieved / 8000.0, 4), "traffic": None,
+                     "kernel": "k3_vel + k3_pres", "us_per_step": round(us_step, 3),
+                     "bytes_per_cell": 9 * esz, "cells_per_step": cells},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        # the oracle's 3D forward on the same grid for a few steps,
+        # extrapolated linearly to the step's 2 nt cell-updates
+        from oracle.prop3 import Grid3, forward3
+        gph = Grid3(kap, rho, hh, prob.dt, 20, prob.pml_R, 8)
+        src = gph.p_plane(prob.z_src, 0.0, nx, 0.0, ny)
+        ns_ = 2
+        tc = time.perf_counter()
+        forward3(gph, ns_, h_src=(src, h[:ns_].double().cpu().numpy().reshape(ns_, -1)))
+        tc = time.perf_counter() - tc
+        rate = ns_ * cells / tc
+        out["cpu_baseline"] = {
+            "value": round(rate / (2 * prob.nt * cells), 8), "unit": "pairs/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"FP64 NumPy 3D oracle forward, {ns_} steps of the {NZ}x{NY}x{NX} grid "
+                      f"({tc:.1f} s, {rate / 1e9:.4f} Gcell/s, 1 thread), extrapolated "
+                      f"linearly to {2 * prob.nt * cells:.3e} cell-updates per pair"}
+    ctx.close()
     print(json.dumps(out), flush=True)
 
 

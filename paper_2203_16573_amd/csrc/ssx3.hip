@@ -11,8 +11,11 @@
 // type).
 //
 // Layout: each field is one [NZ][NY][NX] array, x fastest, no ghost cells
-// (values outside the grid are read as zero).  One thread per cell,
-// 64 x 4 (x, y) threads per workgroup, one z plane per grid row.
+// (values outside the grid are read as zero).  One thread per cell, 64 x 4
+// (x, y) threads per workgroup on one z plane; workgroups are dealt to the
+// 8 XCDs round-robin, so the logical tile order gives each XCD a contiguous
+// band of z planes, which it sweeps plane by plane: the z-neighbour planes
+// a stencil reads are then the ones its own L2 has just held.
 //
 // Forward step n: k3_vel (v^{n+1/2} from p^n), k3_pres (p^{n+1} from
 // v^{n+1/2}, the source sample h[n] injected), then the receiver plane
@@ -30,6 +33,20 @@ using ssx::fmac;
 using ssx::wst;
 
 constexpr int BX = 64, BY = 4;
+
+// the cell of this thread: logical tile of hardware block b (XCD bands of
+// consecutive tiles, x tiles fastest, then y tiles, then z planes)
+struct Cell {
+  int x, y, z;
+};
+__device__ __forceinline__ Cell cell_of(const Dims3& d) {
+  const int n = (int)gridDim.x, b = (int)blockIdx.x;
+  const int per = n >> 3, rem = n & 7, xcd = b & 7;
+  const int t = xcd * per + (xcd < rem ? xcd : rem) + (b >> 3);
+  const int tx = (d.NX + BX - 1) / BX, ty = (d.NY + BY - 1) / BY;
+  const int z = t / (tx * ty), r = t - z * (tx * ty), yb = r / tx, xb = r - yb * tx;
+  return {xb * BX + (int)threadIdx.x, yb * BY + (int)threadIdx.y, z};
+}
 
 template <typename T>
 struct View {
@@ -76,7 +93,8 @@ __device__ __forceinline__ double plane_w(const Plane3& pl, int z, int y, int x,
 
 template <int K, typename T>
 __global__ __launch_bounds__(BX* BY) void k3_vel(Fields3<T> f, Dims3 d, const T* fac, T cb) {
-  const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y, z = blockIdx.z;
+  const Cell cc = cell_of(d);
+  const int x = cc.x, y = cc.y, z = cc.z;
   if (x >= d.NX || y >= d.NY) return;
   const long long o = ((long long)z * d.NY + y) * d.NX + x;
   const View<T> p{f.p, d.NZ, d.NY, d.NX};
@@ -97,7 +115,8 @@ __global__ __launch_bounds__(BX* BY) void k3_vel(Fields3<T> f, Dims3 d, const T*
 template <int K, typename T>
 __global__ __launch_bounds__(BX* BY) void k3_pres(Fields3<T> f, Dims3 d, const T* fac,
                                                   const T* ck, Plane3 src, const T* htr) {
-  const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y, z = blockIdx.z;
+  const Cell cc = cell_of(d);
+  const int x = cc.x, y = cc.y, z = cc.z;
   if (x >= d.NX || y >= d.NY) return;
   const long long o = ((long long)z * d.NY + y) * d.NX + x;
   const View<T> vx{f.vx, d.NZ, d.NY, d.NX}, vy{f.vy, d.NZ, d.NY, d.NX},
@@ -133,7 +152,8 @@ __global__ __launch_bounds__(BX* BY) void k3_pres(Fields3<T> f, Dims3 d, const T
 template <int K, typename T>
 __global__ __launch_bounds__(BX* BY) void k3_adj_v(Fields3<T> f, Dims3 d, const T* fac,
                                                    const T* ck) {
-  const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y, z = blockIdx.z;
+  const Cell cc = cell_of(d);
+  const int x = cc.x, y = cc.y, z = cc.z;
   if (x >= d.NX || y >= d.NY) return;
   const long long o = ((long long)z * d.NY + y) * d.NX + x;
   const Fac<T> F{fac, d.NZ, d.NY, d.NX};
@@ -166,7 +186,8 @@ __global__ __launch_bounds__(BX* BY) void k3_adj_v(Fields3<T> f, Dims3 d, const 
 template <int K, typename T>
 __global__ __launch_bounds__(BX* BY) void k3_adj_p(Fields3<T> f, Dims3 d, const T* fac, T cb,
                                                    Plane3 rec, const T* rtr) {
-  const int x = blockIdx.x * BX + threadIdx.x, y = blockIdx.y * BY + threadIdx.y, z = blockIdx.z;
+  const Cell cc = cell_of(d);
+  const int x = cc.x, y = cc.y, z = cc.z;
   if (x >= d.NX || y >= d.NY) return;
   const long long o = ((long long)z * d.NY + y) * d.NX + x;
   const Fac<T> F{fac, d.NZ, d.NY, d.NX};
@@ -231,7 +252,9 @@ __global__ void k3_gather(const T* field, Dims3 d, Plane3 pl, const T* fac, cons
 
 // ---------------------------------------------------------------------------
 
-static dim3 cells(const Dims3& d) { return dim3((d.NX + BX - 1) / BX, (d.NY + BY - 1) / BY, d.NZ); }
+static dim3 cells(const Dims3& d) {
+  return dim3((unsigned)(((d.NX + BX - 1) / BX) * ((d.NY + BY - 1) / BY) * d.NZ));
+}
 
 template <typename T>
 static hipError_t step_t(int order, bool adj, const Fields3<T>& f, const Dims3& d, const T* fac,
