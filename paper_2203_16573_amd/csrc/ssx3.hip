@@ -11,7 +11,10 @@
 // type).
 //
 // Layout: each field is one [NZ][NY][NX] array, x fastest, no ghost cells
-// (values outside the grid are read as zero).  One thread per cell, 64 x 4
+// (values outside the grid are read as zero).  The pressure is split into
+// its three parts in the absorbing frame only: off the frame every layer
+// factor is 1, the forward pressure is updated as one total, and the three
+// parts' adjoints are equal and kept as one value.  One thread per cell, 64 x 4
 // (x, y) threads per workgroup on one z plane; workgroups are dealt to the
 // 8 XCDs round-robin, so the logical tile order gives each XCD a contiguous
 // band of z planes, which it sweeps plane by plane: the z-neighbour planes
@@ -80,6 +83,12 @@ struct Fac {
   }
 };
 
+// off the absorbing frame, where every layer factor is 1 and the pressure
+// is not split
+__device__ __forceinline__ bool inner(const Dims3& d, int z, int y, int x) {
+  return z >= d.L && z < d.NZ - d.L && y >= d.L && y < d.NY - d.L && x >= d.L && x < d.NX - d.L;
+}
+
 // the interpolation weight with which cell (z, y, x) enters plane pl (zero
 // off the plane), and the trace index there
 __device__ __forceinline__ double plane_w(const Plane3& pl, int z, int y, int x, int& tr) {
@@ -136,6 +145,10 @@ __global__ __launch_bounds__(BX* BY) void k3_pres(Fields3<T> f, Dims3 d, const T
     if (w != 0.0) dz = dz - T(w) * htr[tr];
   }
   const T k = ck[o];
+  if (inner(d, z, y, x)) {
+    f.p[o] = fmac(-k, (dx + dy) + dz, f.p[o]);
+    return;
+  }
   const T px = fmac(F.an(2, x), f.px[o], -(F.bn(2, x) * k) * dx);
   const T py = fmac(F.an(1, y), f.py[o], -(F.bn(1, y) * k) * dy);
   const T pz = fmac(F.an(0, z), f.pz[o], -(F.bn(0, z) * k) * dz);
@@ -163,7 +176,7 @@ __global__ __launch_bounds__(BX* BY) void k3_adj_v(Fields3<T> f, Dims3 d, const 
     if (zz < 0 || zz >= d.NZ || yy < 0 || yy >= d.NY || xx < 0 || xx >= d.NX) return T(0);
     const long long j = zz * sz + yy * sy + xx;
     const int i = axis == 0 ? zz : (axis == 1 ? yy : xx);
-    return (F.bn(axis, i) * ck[j]) * pa[j];
+    return (F.bn(axis, i) * ck[j]) * (inner(d, zz, yy, xx) ? f.p[j] : pa[j]);
   };
   T sx = T(0), sy_ = T(0), sz_ = T(0);
 #pragma unroll
@@ -211,6 +224,10 @@ __global__ __launch_bounds__(BX* BY) void k3_adj_p(Fields3<T> f, Dims3 d, const 
     const double w = plane_w(rec, z, y, x, tr);
     if (w != 0.0) r = T(w) * rtr[tr];
   }
+  if (inner(d, z, y, x)) {
+    f.p[o] = (f.p[o] + t) + r;
+    return;
+  }
   f.px[o] = fmac(F.an(2, x), f.px[o], t) + r;
   f.py[o] = fmac(F.an(1, y), f.py[o], t) + r;
   f.pz[o] = fmac(F.an(0, z), f.pz[o], t) + r;
@@ -228,22 +245,28 @@ __global__ void k3_spread(Fields3<T> f, Dims3 d, Plane3 pl, const T* tr) {
   const T w = T(row ? pl.w1 : pl.w0);
   const long long o = ((long long)z * d.NY + y) * d.NX + x;
   const T v = w * tr[t];
+  if (inner(d, z, y, x)) {
+    f.p[o] += v;
+    return;
+  }
   f.px[o] += v;
   f.py[o] += v;
   f.pz[o] += v;
 }
 
-// plane gather: out[t] = sum_rows w s field, s = 1 (MODE 0) or, for the
-// source plane of the transpose, b_node,z Ck (MODE 1)
+// plane gather: out[t] = sum_rows w s v, with v = p, s = 1 (MODE 0) or, for
+// the source plane of the transpose, v = the z part's adjoint, s = b_node,z
+// Ck (MODE 1)
 template <typename T, int MODE>
-__global__ void k3_gather(const T* field, Dims3 d, Plane3 pl, const T* fac, const T* ck, T* out) {
+__global__ void k3_gather(Fields3<T> f, Dims3 d, Plane3 pl, const T* fac, const T* ck, T* out) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= pl.ny * pl.nx) return;
   const int y = pl.y0 + t / pl.nx, x = pl.x0 + t % pl.nx;
   const Fac<T> F{fac, d.NZ, d.NY, d.NX};
   auto val = [&](int z) {
     const long long o = ((long long)z * d.NY + y) * d.NX + x;
-    return MODE == 0 ? field[o] : (F.bn(0, z) * ck[o]) * field[o];
+    if (MODE == 0) return f.p[o];
+    return (F.bn(0, z) * ck[o]) * (inner(d, z, y, x) ? f.p[o] : f.pz[o]);
   };
   T s = T(pl.w0) * val(pl.r0);
   if (pl.r1 >= 0) s = s + T(pl.w1) * val(pl.r1);
@@ -306,25 +329,27 @@ hipError_t launch3_spread(bool f64, const void* fields, const Dims3& d, const Pl
   return hipGetLastError();
 }
 
-hipError_t launch3_gather(bool f64, bool scaled, const void* field, const Dims3& d,
+hipError_t launch3_gather(bool f64, bool scaled, const void* fields, const Dims3& d,
                           const Plane3& pl, const void* fac, const void* ck, void* out,
                           hipStream_t s) {
   const int n = pl.ny * pl.nx;
   const dim3 g((n + 255) / 256), b(256);
   if (f64) {
+    const Fields3<double> f = fields3<double>(fields, d);
     if (scaled)
-      hipLaunchKernelGGL((k3_gather<double, 1>), g, b, 0, s, (const double*)field, d, pl,
-                         (const double*)fac, (const double*)ck, (double*)out);
+      hipLaunchKernelGGL((k3_gather<double, 1>), g, b, 0, s, f, d, pl, (const double*)fac,
+                         (const double*)ck, (double*)out);
     else
-      hipLaunchKernelGGL((k3_gather<double, 0>), g, b, 0, s, (const double*)field, d, pl,
-                         (const double*)fac, (const double*)ck, (double*)out);
+      hipLaunchKernelGGL((k3_gather<double, 0>), g, b, 0, s, f, d, pl, (const double*)fac,
+                         (const double*)ck, (double*)out);
   } else {
+    const Fields3<float> f = fields3<float>(fields, d);
     if (scaled)
-      hipLaunchKernelGGL((k3_gather<float, 1>), g, b, 0, s, (const float*)field, d, pl,
-                         (const float*)fac, (const float*)ck, (float*)out);
+      hipLaunchKernelGGL((k3_gather<float, 1>), g, b, 0, s, f, d, pl, (const float*)fac,
+                         (const float*)ck, (float*)out);
     else
-      hipLaunchKernelGGL((k3_gather<float, 0>), g, b, 0, s, (const float*)field, d, pl,
-                         (const float*)fac, (const float*)ck, (float*)out);
+      hipLaunchKernelGGL((k3_gather<float, 0>), g, b, 0, s, f, d, pl, (const float*)fac,
+                         (const float*)ck, (float*)out);
   }
   return hipGetLastError();
 }

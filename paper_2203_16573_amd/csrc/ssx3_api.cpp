@@ -116,7 +116,7 @@ ssx_status check_model3(const ssx3_problem& p, const double* kappa, double rho, 
 }
 
 Dims3 dims_of(const ssx3_problem& p) {
-  return {p.nz + 2 * p.npml, p.ny + 2 * p.npml, p.nx + 2 * p.npml};
+  return {p.nz + 2 * p.npml, p.ny + 2 * p.npml, p.nx + 2 * p.npml, p.npml};
 }
 
 size_t bytes_of(const ssx3_problem& p) {
@@ -255,11 +255,10 @@ ssx_status ssx3_fwd(ssx3_ctx* c, const void* h, void* d) {
   const long long n = (long long)c->d.NZ * c->d.NY * c->d.NX;
   const long long ns = (long long)p.nsx * p.nsy, nr = (long long)p.nrx * p.nry;
   S3_HIP(hipMemsetAsync(c->fields, 0, 7 * n * c->esz, c->stream));
-  const void* pfield = at(c->fields, 6 * n, c->esz);
   for (int t = 0; t < p.nt; ++t) {
     S3_HIP(ssx3::launch3_step(c->f64, p.order, false, c->fields, c->d, c->fac, c->ck, c->cb,
                               c->src, at(h, t * ns, c->esz), c->stream));
-    S3_HIP(ssx3::launch3_gather(c->f64, false, pfield, c->d, c->rec, c->fac, c->ck,
+    S3_HIP(ssx3::launch3_gather(c->f64, false, c->fields, c->d, c->rec, c->fac, c->ck,
                                 const_cast<char*>(at(d, t * nr, c->esz)), c->stream));
   }
   return SSX_OK;
@@ -271,11 +270,10 @@ ssx_status ssx3_adj(ssx3_ctx* c, const void* r, void* g) {
   const long long n = (long long)c->d.NZ * c->d.NY * c->d.NX;
   const long long ns = (long long)p.nsx * p.nsy, nr = (long long)p.nrx * p.nry;
   S3_HIP(hipMemsetAsync(c->fields, 0, 7 * n * c->esz, c->stream));
-  const void* pz = at(c->fields, 5 * n, c->esz);
   S3_HIP(ssx3::launch3_spread(c->f64, c->fields, c->d, c->rec, at(r, (p.nt - 1) * nr, c->esz),
                               c->stream));
   for (int t = p.nt - 1; t >= 0; --t) {
-    S3_HIP(ssx3::launch3_gather(c->f64, true, pz, c->d, c->src, c->fac, c->ck,
+    S3_HIP(ssx3::launch3_gather(c->f64, true, c->fields, c->d, c->src, c->fac, c->ck,
                                 const_cast<char*>(at(g, t * ns, c->esz)), c->stream));
     S3_HIP(ssx3::launch3_step(c->f64, p.order, true, c->fields, c->d, c->fac, c->ck, c->cb,
                               c->rec, t >= 1 ? at(r, (t - 1) * nr, c->esz) : nullptr,

@@ -8,6 +8,7 @@ namespace ssx3 {
 
 struct Dims3 {
   int NZ, NY, NX;  // padded grid: physical + 2 npml per axis
+  int L;           // absorbing cells per side
 };
 
 // A plane of traces: grid rows r0 (weight w0) and r1 (weight w1; r1 < 0:
@@ -20,6 +21,10 @@ struct Plane3 {
 };
 
 // The seven [NZ][NY][NX] fields, carved from one buffer in this order.
+// The pressure parts px, py, pz are used in the absorbing frame only; p
+// holds the total pressure everywhere (forward) or, in the transposed
+// sweep, the common value of the three parts' adjoints off the frame
+// (equal there: they receive the same updates).
 template <typename T>
 struct Fields3 {
   T *vx, *vy, *vz, *px, *py, *pz, *p;
@@ -42,8 +47,9 @@ hipError_t launch3_step(bool f64, int order, bool adj, const void* fields, const
 // each pressure part += R^T tr on plane pl
 hipError_t launch3_spread(bool f64, const void* fields, const Dims3& d, const Plane3& pl,
                           const void* tr, hipStream_t s);
-// out = R field on plane pl; scaled: R (b_node,z ck field)
-hipError_t launch3_gather(bool f64, bool scaled, const void* field, const Dims3& d,
+// out = R p on plane pl (forward), or, scaled, R (b_node,z ck p~_z) with
+// p~_z the adjoint of the pressure's z part (transposed sweep)
+hipError_t launch3_gather(bool f64, bool scaled, const void* fields, const Dims3& d,
                           const Plane3& pl, const void* fac, const void* ck, void* out,
                           hipStream_t s);
 
