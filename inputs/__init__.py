@@ -76,7 +76,9 @@ class Problem3:
     depth i h, y = k h, x = j h; an absorbing layer of npml cells on every
     side.  The source is a plane at depth z_src of nsx x nsy traces at
     (x_src0 + a h, y_src0 + b h), trace index b nsx + a; the receivers a
-    plane at z_rec likewise."""
+    plane at z_rec likewise.  slab_dz is the signed datum offset (cells) of
+    the thin slab that carries the preconditioner, (x_s, y_s) the physical
+    point from which the penalty measures lateral distance."""
 
     nz: int
     ny: int
@@ -97,6 +99,9 @@ class Problem3:
     y_rec0: float = 0.0
     nrx: int = 1
     nry: int = 1
+    slab_dz: int = 5        # signed thin-slab datum offset (cells) for M^-1
+    x_s: float = 0.0        # the physical point (lateral position) of the
+    y_s: float = 0.0        # subproblem, for the penalty A
 
     @property
     def ns(self) -> int:

@@ -31,7 +31,12 @@ Extended Surface Sources" (arXiv 2203.16573) that it follows:
              the 3D generalisation among the closing remarks), pinned by
              exact reduction to ``prop`` on y-invariant problems, the dot
              test, energy conservation and the closed-form 3D point-source
-             response.
+             response;
+* ``ops3``   the 3D subproblem: F, F^T, the penalty with the lateral
+             distance on the source plane, the thin-slab W^-1 and M^-1,
+             N and Algorithm 1 (``ops.pcg``), pinned by exact reduction of
+             W^-1 to the 2D one on y-invariant input, its symmetry, a dense
+             solve and the Krylov minimisation property of the iterates.
 
 Every function is pinned by the CPU tests against facts that do not come
 from this code: the dot-product adjoint test, brute-force dense transposes,
@@ -46,6 +51,6 @@ energy conservation and the reflection and transmission coefficients of a
 density-only impedance jump at second order.  The C engine is pinned by
 equality with ``prop`` on every operator and by its own dot test.
 """
-from . import fd, grid, prop, ops, greens, prop3  # noqa: F401
+from . import fd, grid, prop, ops, greens, prop3, ops3  # noqa: F401
 from .ops import (Model, pcg, pcg_solve, precond, penalty, dscale, normal,  # noqa: F401
                   normal_w, pcg_solve_w, misfit_gradient, normal_v, pcg_solve_v)

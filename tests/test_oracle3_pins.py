@@ -1,8 +1,10 @@
-"""Pins of the 3D FP64 oracle (``oracle.prop3``) against facts that do not
-come from its own code: the 2D oracle (itself pinned) on a y-invariant
-problem inside the discrete dependency cone, the dot-product test,
-discrete energy conservation in a rigid box and the closed-form 3D
-point-source response."""
+"""Pins of the 3D FP64 oracle (``oracle.prop3``, ``oracle.ops3``) against
+facts that do not come from its own code: the 2D oracle (itself pinned) on
+y-invariant problems inside the discrete dependency cone (propagation and
+the thin-slab W^-1), the dot-product test, discrete energy conservation in
+a rigid box, the closed-form 3D point-source response, the symmetry of
+W^-1, a dense solve, and the Krylov minimisation property of the
+preconditioned iterates."""
 import math
 
 import numpy as np
@@ -134,3 +136,112 @@ def test_point_source_amplitude():
     ref = RHO * np.where(s > 0, inputs.ricker_deriv(s, f), 0.0) / (4 * math.pi * r)
     err = np.abs(P[:, 0] - ref).max() / np.abs(ref).max()
     assert err < 3e-2, err
+
+
+# ---------------------------------------------------------------------------
+# the 3D subproblem operators (oracle.ops3)
+
+import oracle  # noqa: E402
+from oracle.ops3 import (Model3, lateral_distance3, normal3, pcg_solve3,  # noqa: E402
+                         precond3)
+
+
+@pytest.mark.parametrize("order,dz", [(4, 3), (8, -2)])
+def test_y_invariant_thin_slab_reduces_to_2d(order, dz):
+    # the thin-slab W^-1 of a y-invariant model and load: its centre row is
+    # the 2D W^-1 (itself pinned by the plane-wave scale and symmetry)
+    K = order // 2
+    nz, nx, L, nt, h = 16, 18, 4, 10, 10.0
+    ny = 2 * (2 * K * nt + K + 2) + 1
+    kap2 = layered_kappa2(nz, nx, 23)
+    kap3 = np.repeat(kap2[:, None, :], ny, axis=1)
+    ns = 12
+    p2 = inputs.Problem(nz=nz, nx=nx, h=h, dt=1e-3, nt=nt, order=order, npml=L, z_src=65.0,
+                        x_src0=3 * h, ns=ns, z_rec=120.0, x_rec0=h, nr=10, slab_dz=dz,
+                        xs=(80.0,))
+    p3 = inputs.Problem3(nz=nz, ny=ny, nx=nx, h=h, dt=1e-3, nt=nt, order=order, npml=L,
+                         z_src=65.0, x_src0=3 * h, y_src0=0.0, nsx=ns, nsy=ny, z_rec=120.0,
+                         x_rec0=h, nrx=10, nry=1, slab_dz=dz, x_s=80.0)
+    m2 = oracle.Model(p2, kap2, RHO)
+    m3 = Model3(p3, kap3, RHO)
+    g = np.random.default_rng(8).standard_normal((nt, ns))
+    w2 = m2.winv(g)
+    w3 = m3.winv(np.repeat(g[:, None, :], ny, axis=1).reshape(nt, -1))
+    yc = (ny - 1) // 2
+    w3c = w3.reshape(nt, ny, ns)[:, yc, :]
+    assert np.abs(w2).max() > 0
+    assert np.abs(w3c - w2).max() <= 1e-13 * np.abs(w2).max()
+
+
+def _small3(order=4, nt=6, nsx=2, nsy=2, dz=3, L=3):
+    p = inputs.Problem3(nz=10, ny=9, nx=11, h=10.0, dt=1e-3, nt=nt, order=order, npml=L,
+                        z_src=25.0, x_src0=40.0, y_src0=30.0, nsx=nsx, nsy=nsy, z_rec=75.0,
+                        x_rec0=10.0, y_rec0=10.0, nrx=8, nry=6, slab_dz=dz, x_s=45.0,
+                        y_s=35.0)
+    vel = inputs.layered_velocity3(p.nz, p.ny, p.nx, p.h, np.random.default_rng(4))
+    return p, Model3(p, RHO * vel * vel, RHO)
+
+
+def test_thin_slab_operator_symmetric_and_distance():
+    p, m = _small3(order=8, nsx=3, nsy=2, dz=-2)
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((p.nt, p.ns))
+    y = rng.standard_normal((p.nt, p.ns))
+    a, b = np.sum(m.winv(x) * y), np.sum(x * m.winv(y))
+    assert abs(a) > 0 and abs(a - b) <= 1e-12 * abs(a)
+    # distance of trace (a, b) from (x_s, y_s), written out
+    dist = lateral_distance3(p)
+    assert dist[1 * p.nsx + 2] == pytest.approx(math.hypot(40.0 + 20.0 - 45.0,
+                                                           30.0 + 10.0 - 35.0))
+
+
+def _dense(apply, n, shape):
+    cols = []
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = 1.0
+        cols.append(np.asarray(apply(e.reshape(shape))).ravel())
+    return np.array(cols).T
+
+
+def test_pcg_without_preconditioner_reaches_dense_solution():
+    p, m = _small3()
+    rng = np.random.default_rng(6)
+    d = rng.standard_normal((p.nt, p.nr))
+    b = m.adj(d)
+    alpha = 0.3 * math.sqrt(np.sum(b * b)) / math.sqrt(np.sum(d * d))
+    shp = (p.nt, p.ns)
+    N = _dense(lambda x: normal3(m, alpha, x)[0], p.nt * p.ns, shp)
+    assert np.abs(N - N.T).max() <= 1e-12 * np.abs(N).max()
+    hstar = np.linalg.solve(N, b.ravel())
+    h, hist, a = pcg_solve3(m, d, 0.3, 30, use_precond=False)   # 24 unknowns
+    assert a == pytest.approx(alpha)
+    assert np.linalg.norm(h.ravel() - hstar) <= 1e-8 * np.linalg.norm(hstar)
+
+
+def test_preconditioned_iterates_are_krylov_minimisers():
+    # Algorithm 1 with M^-1: iterate k is the N-norm minimiser of the error
+    # over K_k(M^-1 N, M^-1 b) (Galerkin on that span), whatever the sign of
+    # M^-1 on it
+    p, m = _small3(order=8, dz=2)
+    rng = np.random.default_rng(12)
+    d = rng.standard_normal((p.nt, p.nr))
+    b = m.adj(d)
+    alpha = 0.5 * math.sqrt(np.sum(b * b)) / math.sqrt(np.sum(d * d))
+    shp = (p.nt, p.ns)
+    n = p.nt * p.ns
+    N = _dense(lambda x: normal3(m, alpha, x)[0], n, shp)
+    Minv = _dense(lambda x: precond3(m, 0.5, x), n, shp)
+    for k in (1, 2, 3):
+        q = Minv @ b.ravel()
+        Q = [q / np.linalg.norm(q)]
+        for _ in range(k - 1):
+            w = Minv @ (N @ Q[-1])
+            for _ in range(2):
+                for u in Q:
+                    w = w - (u @ w) * u
+            Q.append(w / np.linalg.norm(w))
+        Q = np.array(Q).T
+        ref = Q @ np.linalg.solve(Q.T @ N @ Q, Q.T @ b.ravel())
+        h, _, _ = pcg_solve3(m, d, 0.5, k)
+        assert np.linalg.norm(h.ravel() - ref) <= 1e-9 * np.linalg.norm(ref), k
