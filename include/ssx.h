@@ -460,7 +460,9 @@ ssx_status ssx_launch_shape(ssx_ctx* ctx, int32_t* shape);
  * Three dimensions (the 3D form of the Operators section's acoustic
  * system, the generalisation the closing remarks name): F maps a pressure
  * source on the plane z = z_src to pressure traces on the plane z = z_rec,
- * F^T is its exact discrete transpose (eqns sdef and sadj1, Appendix A).
+ * F^T is its exact discrete transpose (eqns sdef and sadj1, Appendix A);
+ * with the penalty, the thin-slab preconditioner and Algorithm 1 on the
+ * same plane geometry.
  * Staggered grid (p on nodes, v_x, v_y, v_z on the half nodes of their
  * axis), order 2 in time and 4 or 8 in space, the split-field absorbing
  * layer of npml cells on every side, constant density; sampling and
@@ -477,6 +479,10 @@ typedef struct ssx3_ctx ssx3_ctx;
  * y_src0 + b h), trace index b nsx + a; receiver plane likewise.  Lateral
  * positions must lie on grid nodes; depths may fall between nodes.
  * field_dtype: SSX_F64 or SSX_F32, also the type of every trace array.
+ * slab_dz and (x_s, y_s) play the roles of the 2D slab_dz and x_s: the
+ * thin slab of M^-1 around z_src with its datum slab_dz cells away, and
+ * the point from which A measures lateral distance, sqrt((x - x_s)^2 +
+ * (y - y_s)^2).
  */
 typedef struct {
   int32_t nz, ny, nx;
@@ -490,6 +496,8 @@ typedef struct {
   double z_rec, x_rec0, y_rec0;
   int32_t nrx, nry;
   int32_t field_dtype;  /* SSX_F64 or SSX_F32 */
+  int32_t slab_dz;      /* signed thin-slab datum offset (cells), nonzero */
+  double x_s, y_s;      /* the physical point, for the penalty A */
 } ssx3_problem;
 
 /* Host-only check (no device work).  Rejects (ARG): a grid below order + 1
@@ -501,8 +509,9 @@ typedef struct {
  * [nz][ny][nx], Pa) may be NULL to check the problem alone. */
 ssx_status ssx3_validate(const ssx3_problem* prob, const double* kappa_host, double rho);
 
-/* Device bytes a 3D context owns (seven fields and the coefficients); 0 if
- * the problem is invalid. */
+/* Device bytes a 3D context owns (the full grid's and the thin slab's seven
+ * fields and coefficients, ten trace vectors, FP64 scalars); 0 if the
+ * problem is invalid. */
 size_t ssx3_footprint(const ssx3_problem* prob);
 
 /* Create a 3D context: kappa_host HOST [nz][ny][nx] bulk modulus (Pa), read
@@ -519,6 +528,31 @@ ssx_status ssx3_fwd(ssx3_ctx* ctx, const void* h, void* d);
 
 /* g = F^T r.  r: DEVICE [nt][nry][nrx], g: DEVICE [nt][nsy][nsx]. */
 ssx_status ssx3_adj(ssx3_ctx* ctx, const void* r, void* g);
+
+/* y = op(x) on source-plane traces [nt][nsy][nsx], op as ssx_penalty's with
+ * the 3D lateral distance (eqn penop; defprecond for SSX_PEN_DHALF with
+ * a = alpha_hat); x and y may be the same array. */
+ssx_status ssx3_penalty(ssx3_ctx* ctx, int op, double a, const void* x, void* y);
+
+/* g = M^-1 r = D W^-1 D r (eqns defprecond, winvcomp): W^-1 = s X^T J X on
+ * the thin slab, X a normal load on z_src recorded as pressure and normal
+ * velocity on the datum plane, J their exchange, s = 4 sign(slab_dz),
+ * D = (1 + alpha_hat^2 A^T A)^(-1/2).  r, g: DEVICE [nt][nsy][nsx], not
+ * overlapping; alpha_hat >= 0. */
+ssx_status ssx3_precond(ssx3_ctx* ctx, double alpha_hat, const void* r, void* g);
+
+/* Algorithm 1 on N h = F^T d, N = F^T F + alpha^2 A^T A, alpha = alpha_rel
+ * ||F^T d|| / ||d||, M^-1 as ssx3_precond with alpha_hat = alpha_rel
+ * (use_precond != 0) or M = I; h_0 = 0, maxit iterations (0..4096).
+ * d: DEVICE [nt][nry][nrx]; h_out: DEVICE [nt][nsy][nsx]; hist_host: HOST
+ * [maxit + 1][4] (||r_k||, ||g_k||, <g_k, r_k>, ||F h_k - d||) or NULL;
+ * iters_host: HOST or NULL.  FP64 inner products; the call synchronises
+ * the stream once per inner product.  SSX_ERR_BREAKDOWN /
+ * SSX_ERR_NONFINITE if <g, r> or <p, q> becomes zero / non-finite (the
+ * iterate so far is in h_out). */
+ssx_status ssx3_pcg_solve(ssx3_ctx* ctx, const void* d, double alpha_rel, int32_t maxit,
+                          int32_t use_precond, void* h_out, double* hist_host,
+                          int32_t* iters_host);
 
 /* Release a 3D context (waits for its stream). */
 void ssx3_destroy(ssx3_ctx* ctx);

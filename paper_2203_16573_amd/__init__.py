@@ -62,7 +62,7 @@ EXPORTS = ("ssx_validate", "ssx_footprint", "ssx_create", "ssx_destroy", "ssx_fw
            "ssx_misfit_gradient", "ssx_pcg_solve_v", "ssx_dot_static", "ssx_create_density",
            "ssx_batch_create", "ssx_batch_pcg_solve", "ssx_batch_destroy",
            "ssx3_validate", "ssx3_footprint", "ssx3_create", "ssx3_fwd", "ssx3_adj",
-           "ssx3_destroy")
+           "ssx3_penalty", "ssx3_precond", "ssx3_pcg_solve", "ssx3_destroy")
 
 DOT_STATIC_MAX_SHOTS = 64  # SSX_DOT_STATIC_MAX_SHOTS
 
@@ -95,7 +95,8 @@ class ssx3_problem(ctypes.Structure):
                 ("y_src0", ctypes.c_double), ("nsx", ctypes.c_int32), ("nsy", ctypes.c_int32),
                 ("z_rec", ctypes.c_double), ("x_rec0", ctypes.c_double),
                 ("y_rec0", ctypes.c_double), ("nrx", ctypes.c_int32), ("nry", ctypes.c_int32),
-                ("field_dtype", ctypes.c_int32)]
+                ("field_dtype", ctypes.c_int32), ("slab_dz", ctypes.c_int32),
+                ("x_s", ctypes.c_double), ("y_s", ctypes.c_double)]
 
 
 _lib = None
@@ -169,6 +170,10 @@ def lib():
         L.ssx3_create.argtypes = [P3, dp, c_dbl, vp, ctypes.POINTER(vp)]
         L.ssx3_fwd.argtypes = [vp, vp, vp]
         L.ssx3_adj.argtypes = [vp, vp, vp]
+        L.ssx3_penalty.argtypes = [vp, c_int, c_dbl, vp, vp]
+        L.ssx3_precond.argtypes = [vp, c_dbl, vp, vp]
+        L.ssx3_pcg_solve.argtypes = [vp, vp, c_dbl, ctypes.c_int32, ctypes.c_int32, vp, dp,
+                                     ctypes.POINTER(ctypes.c_int32)]
         L.ssx3_destroy.argtypes = [vp]
         L.ssx3_destroy.restype = None
         _lib = L
@@ -546,7 +551,8 @@ def make_problem3(prob, field_dtype: str = "f32") -> ssx3_problem:
                         float(prob.pml_R), float(prob.z_src), float(prob.x_src0),
                         float(prob.y_src0), int(prob.nsx), int(prob.nsy), float(prob.z_rec),
                         float(prob.x_rec0), float(prob.y_rec0), int(prob.nrx), int(prob.nry),
-                        DTYPES[field_dtype])
+                        DTYPES[field_dtype], int(prob.slab_dz), float(prob.x_s),
+                        float(prob.y_s))
 
 
 def validate3(prob, kappa=None, rho: float = 1000.0, field_dtype: str = "f32") -> None:
@@ -612,6 +618,34 @@ class Context3:
         _check(lib().ssx3_adj(self._ctx, self._arg(r, (p.nt, p.nry, p.nrx), "r"),
                               self._arg(g, (p.nt, p.nsy, p.nsx), "g")))
         return g
+
+    def penalty(self, op, a, x, y):
+        p = self.prob
+        shp = (p.nt, p.nsy, p.nsx)
+        _check(lib().ssx3_penalty(self._ctx, int(op), float(a), self._arg(x, shp, "x"),
+                                  self._arg(y, shp, "y")))
+        return y
+
+    def precond(self, alpha_hat, r, g):
+        p = self.prob
+        shp = (p.nt, p.nsy, p.nsx)
+        _check(lib().ssx3_precond(self._ctx, float(alpha_hat), self._arg(r, shp, "r"),
+                                  self._arg(g, shp, "g")))
+        return g
+
+    def pcg_solve(self, d, alpha_rel, maxit, use_precond=True, h=None):
+        """Algorithm 1 on N h = F^T d; returns (h, history [maxit+1][4],
+        iterations)."""
+        p = self.prob
+        if h is None:
+            h = self.empty_src()
+        hist = np.zeros((maxit + 1, 4), dtype=np.float64)
+        it = ctypes.c_int32(0)
+        _check(lib().ssx3_pcg_solve(self._ctx, self._arg(d, (p.nt, p.nry, p.nrx), "d"),
+                                    float(alpha_rel), int(maxit), int(bool(use_precond)),
+                                    self._arg(h, (p.nt, p.nsy, p.nsx), "h"), _dptr(hist),
+                                    ctypes.byref(it)))
+        return h, hist[: it.value + 1], it.value
 
     def close(self):
         if getattr(self, "_ctx", None):

@@ -101,7 +101,8 @@ __device__ __forceinline__ double plane_w(const Plane3& pl, int z, int y, int x,
 }
 
 template <int K, typename T>
-__global__ __launch_bounds__(BX* BY) void k3_vel(Fields3<T> f, Dims3 d, const T* fac, T cb) {
+__global__ __launch_bounds__(BX* BY) void k3_vel(Fields3<T> f, Dims3 d, const T* fac, T cb,
+                                                 Plane3 fpl, const T* ftr) {
   const Cell cc = cell_of(d);
   const int x = cc.x, y = cc.y, z = cc.z;
   if (x >= d.NX || y >= d.NY) return;
@@ -115,6 +116,11 @@ __global__ __launch_bounds__(BX* BY) void k3_vel(Fields3<T> f, Dims3 d, const T*
     gx = acc(gx, c, p(z, y, x + m), p(z, y, x + 1 - m));
     gy = acc(gy, c, p(z, y + m, x), p(z, y + 1 - m, x));
     gz = acc(gz, c, p(z + m, y, x), p(z + 1 - m, y, x));
+  }
+  if (ftr) {  // a normal load on plane fpl (v_z nodes): D_z^+ p - E_f f
+    int tr = 0;
+    const double w = plane_w(fpl, z, y, x, tr);
+    if (w != 0.0) gz = gz - T(w) * ftr[tr];
   }
   f.vx[o] = fmac(F.ah(2, x), f.vx[o], -(F.bh(2, x) * cb) * gx);
   f.vy[o] = fmac(F.ah(1, y), f.vy[o], -(F.bh(1, y) * cb) * gy);
@@ -159,12 +165,13 @@ __global__ __launch_bounds__(BX* BY) void k3_pres(Fields3<T> f, Dims3 d, const T
 }
 
 // Transposed pressure updates: the velocity adjoints take the layer scaling
-// pending from the previous transposed step (a_half v~), then
+// pending from the previous transposed step (a_half v~) and the v_z
+// recording of this step, then
 //   v~_a += sum_m c_m (q_a[i+m] - q_a[i+1-m]),  q_a = b_node,a Ck p~_a,
 // the transpose of p_a -= b_node,a Ck D_a^- v_a (D^- = -(D^+)^T).
 template <int K, typename T>
 __global__ __launch_bounds__(BX* BY) void k3_adj_v(Fields3<T> f, Dims3 d, const T* fac,
-                                                   const T* ck) {
+                                                   const T* ck, Plane3 vpl, const T* vtr) {
   const Cell cc = cell_of(d);
   const int x = cc.x, y = cc.y, z = cc.z;
   if (x >= d.NX || y >= d.NY) return;
@@ -186,9 +193,16 @@ __global__ __launch_bounds__(BX* BY) void k3_adj_v(Fields3<T> f, Dims3 d, const 
     sy_ = acc(sy_, c, q(f.py, 1, z, y + m, x), q(f.py, 1, z, y + 1 - m, x));
     sz_ = acc(sz_, c, q(f.pz, 0, z + m, y, x), q(f.pz, 0, z + 1 - m, y, x));
   }
+  // the v_z recording of this step (V = R v_z) enters after the scaling
+  T rv = T(0);
+  if (vtr) {
+    int tr = 0;
+    const double w = plane_w(vpl, z, y, x, tr);
+    if (w != 0.0) rv = T(w) * vtr[tr];
+  }
   f.vx[o] = F.ah(2, x) * f.vx[o] + sx;
   f.vy[o] = F.ah(1, y) * f.vy[o] + sy_;
-  f.vz[o] = F.ah(0, z) * f.vz[o] + sz_;
+  f.vz[o] = (F.ah(0, z) * f.vz[o] + rv) + sz_;
 }
 
 // Transposed velocity updates: p~_a <- a_node,a p~_a + t, with
@@ -254,11 +268,13 @@ __global__ void k3_spread(Fields3<T> f, Dims3 d, Plane3 pl, const T* tr) {
   f.pz[o] += v;
 }
 
-// plane gather: out[t] = sum_rows w s v, with v = p, s = 1 (MODE 0) or, for
-// the source plane of the transpose, v = the z part's adjoint, s = b_node,z
-// Ck (MODE 1)
+// plane gather: out[t] = sum_rows w s v, with (MODE 0) v = p, s = 1; (1)
+// the pressure-source slot of the transpose, v = the z part's adjoint, s =
+// b_node,z Ck; (2) v = v_z, s = 1; (3) the normal-load slot of the
+// transpose, v = v_z's adjoint, s = b_half,z Cb
 template <typename T, int MODE>
-__global__ void k3_gather(Fields3<T> f, Dims3 d, Plane3 pl, const T* fac, const T* ck, T* out) {
+__global__ void k3_gather(Fields3<T> f, Dims3 d, Plane3 pl, const T* fac, const T* ck, T cb,
+                          T* out) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= pl.ny * pl.nx) return;
   const int y = pl.y0 + t / pl.nx, x = pl.x0 + t % pl.nx;
@@ -266,6 +282,8 @@ __global__ void k3_gather(Fields3<T> f, Dims3 d, Plane3 pl, const T* fac, const 
   auto val = [&](int z) {
     const long long o = ((long long)z * d.NY + y) * d.NX + x;
     if (MODE == 0) return f.p[o];
+    if (MODE == 2) return f.vz[o];
+    if (MODE == 3) return (F.bh(0, z) * cb) * f.vz[o];
     return (F.bn(0, z) * ck[o]) * (inner(d, z, y, x) ? f.p[o] : f.pz[o]);
   };
   T s = T(pl.w0) * val(pl.r0);
@@ -281,23 +299,24 @@ static dim3 cells(const Dims3& d) {
 
 template <typename T>
 static hipError_t step_t(int order, bool adj, const Fields3<T>& f, const Dims3& d, const T* fac,
-                         const T* ck, T cb, const Plane3& pl, const T* tr, hipStream_t s) {
+                         const T* ck, T cb, const Plane3& pl, const T* tr, const Plane3& pl2,
+                         const T* tr2, hipStream_t s) {
   const dim3 g = cells(d), b(BX, BY);
   if (d.NZ < 1 || d.NZ > 65535) return hipErrorInvalidValue;
   if (order == 4) {
     if (!adj) {
-      hipLaunchKernelGGL((k3_vel<2, T>), g, b, 0, s, f, d, fac, cb);
+      hipLaunchKernelGGL((k3_vel<2, T>), g, b, 0, s, f, d, fac, cb, pl2, tr2);
       hipLaunchKernelGGL((k3_pres<2, T>), g, b, 0, s, f, d, fac, ck, pl, tr);
     } else {
-      hipLaunchKernelGGL((k3_adj_v<2, T>), g, b, 0, s, f, d, fac, ck);
+      hipLaunchKernelGGL((k3_adj_v<2, T>), g, b, 0, s, f, d, fac, ck, pl2, tr2);
       hipLaunchKernelGGL((k3_adj_p<2, T>), g, b, 0, s, f, d, fac, cb, pl, tr);
     }
   } else if (order == 8) {
     if (!adj) {
-      hipLaunchKernelGGL((k3_vel<4, T>), g, b, 0, s, f, d, fac, cb);
+      hipLaunchKernelGGL((k3_vel<4, T>), g, b, 0, s, f, d, fac, cb, pl2, tr2);
       hipLaunchKernelGGL((k3_pres<4, T>), g, b, 0, s, f, d, fac, ck, pl, tr);
     } else {
-      hipLaunchKernelGGL((k3_adj_v<4, T>), g, b, 0, s, f, d, fac, ck);
+      hipLaunchKernelGGL((k3_adj_v<4, T>), g, b, 0, s, f, d, fac, ck, pl2, tr2);
       hipLaunchKernelGGL((k3_adj_p<4, T>), g, b, 0, s, f, d, fac, cb, pl, tr);
     }
   } else {
@@ -308,12 +327,14 @@ static hipError_t step_t(int order, bool adj, const Fields3<T>& f, const Dims3& 
 
 hipError_t launch3_step(bool f64, int order, bool adj, const void* fields, const Dims3& d,
                         const void* fac, const void* ck, double cb, const Plane3& pl,
-                        const void* tr, hipStream_t s) {
+                        const void* tr, const Plane3& pl2, const void* tr2, hipStream_t s) {
   if (f64)
     return step_t<double>(order, adj, fields3<double>(fields, d), d, (const double*)fac,
-                          (const double*)ck, cb, pl, (const double*)tr, s);
+                          (const double*)ck, cb, pl, (const double*)tr, pl2,
+                          (const double*)tr2, s);
   return step_t<float>(order, adj, fields3<float>(fields, d), d, (const float*)fac,
-                       (const float*)ck, (float)cb, pl, (const float*)tr, s);
+                       (const float*)ck, (float)cb, pl, (const float*)tr, pl2,
+                       (const float*)tr2, s);
 }
 
 hipError_t launch3_spread(bool f64, const void* fields, const Dims3& d, const Plane3& pl,
@@ -329,28 +350,117 @@ hipError_t launch3_spread(bool f64, const void* fields, const Dims3& d, const Pl
   return hipGetLastError();
 }
 
-hipError_t launch3_gather(bool f64, bool scaled, const void* fields, const Dims3& d,
-                          const Plane3& pl, const void* fac, const void* ck, void* out,
-                          hipStream_t s) {
+template <typename T>
+static void gather_t(int mode, const Fields3<T>& f, const Dims3& d, const Plane3& pl,
+                     const T* fac, const T* ck, T cb, T* out, hipStream_t s) {
   const int n = pl.ny * pl.nx;
   const dim3 g((n + 255) / 256), b(256);
-  if (f64) {
-    const Fields3<double> f = fields3<double>(fields, d);
-    if (scaled)
-      hipLaunchKernelGGL((k3_gather<double, 1>), g, b, 0, s, f, d, pl, (const double*)fac,
-                         (const double*)ck, (double*)out);
-    else
-      hipLaunchKernelGGL((k3_gather<double, 0>), g, b, 0, s, f, d, pl, (const double*)fac,
-                         (const double*)ck, (double*)out);
-  } else {
-    const Fields3<float> f = fields3<float>(fields, d);
-    if (scaled)
-      hipLaunchKernelGGL((k3_gather<float, 1>), g, b, 0, s, f, d, pl, (const float*)fac,
-                         (const float*)ck, (float*)out);
-    else
-      hipLaunchKernelGGL((k3_gather<float, 0>), g, b, 0, s, f, d, pl, (const float*)fac,
-                         (const float*)ck, (float*)out);
+  switch (mode) {
+    case 0: hipLaunchKernelGGL((k3_gather<T, 0>), g, b, 0, s, f, d, pl, fac, ck, cb, out); break;
+    case 1: hipLaunchKernelGGL((k3_gather<T, 1>), g, b, 0, s, f, d, pl, fac, ck, cb, out); break;
+    case 2: hipLaunchKernelGGL((k3_gather<T, 2>), g, b, 0, s, f, d, pl, fac, ck, cb, out); break;
+    default: hipLaunchKernelGGL((k3_gather<T, 3>), g, b, 0, s, f, d, pl, fac, ck, cb, out);
   }
+}
+
+hipError_t launch3_gather(bool f64, int mode, const void* fields, const Dims3& d,
+                          const Plane3& pl, const void* fac, const void* ck, double cb,
+                          void* out, hipStream_t s) {
+  if (mode < 0 || mode > 3) return hipErrorInvalidValue;
+  if (f64)
+    gather_t<double>(mode, fields3<double>(fields, d), d, pl, (const double*)fac,
+                     (const double*)ck, cb, (double*)out, s);
+  else
+    gather_t<float>(mode, fields3<float>(fields, d), d, pl, (const float*)fac,
+                    (const float*)ck, (float)cb, (float*)out, s);
+  return hipGetLastError();
+}
+
+// y[n][t] = sc s_t x[n][t] over nt steps of nt_tr traces: s_t = dist_t (op
+// 0, A), dist_t^2 (1, A^T A) or (1 + a^2 dist_t^2)^(-1/2) (2, D); dist: the
+// lateral distance of each trace from the physical point (FP64)
+template <typename T>
+__global__ void k3_diag(int op, double a, double sc, const double* dist, const T* x, T* y,
+                        long long n, int ntr) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double dd = dist[i % ntr];
+  const double f = op == 0 ? dd : (op == 1 ? dd * dd : 1.0 / sqrt(1.0 + (a * dd) * (a * dd)));
+  y[i] = T(sc * f * (double)x[i]);
+}
+
+// y = x + a z (FP64 a)
+template <typename T>
+__global__ void k3_axpy(T* y, const T* x, double a, const T* z, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  y[i] = T((double)x[i] + a * (double)z[i]);
+}
+
+hipError_t launch3_diag(bool f64, int op, double a, double sc, const double* dist, const void* x,
+                        void* y, long long n, int ntr, hipStream_t s) {
+  const dim3 g((unsigned)((n + 255) / 256)), b(256);
+  if (f64)
+    hipLaunchKernelGGL((k3_diag<double>), g, b, 0, s, op, a, sc, dist, (const double*)x,
+                       (double*)y, n, ntr);
+  else
+    hipLaunchKernelGGL((k3_diag<float>), g, b, 0, s, op, a, sc, dist, (const float*)x,
+                       (float*)y, n, ntr);
+  return hipGetLastError();
+}
+
+hipError_t launch3_axpy(bool f64, void* y, const void* x, double a, const void* z, long long n,
+                        hipStream_t s) {
+  const dim3 g((unsigned)((n + 255) / 256)), b(256);
+  if (f64)
+    hipLaunchKernelGGL((k3_axpy<double>), g, b, 0, s, (double*)y, (const double*)x, a,
+                       (const double*)z, n);
+  else
+    hipLaunchKernelGGL((k3_axpy<float>), g, b, 0, s, (float*)y, (const float*)x, a,
+                       (const float*)z, n);
+  return hipGetLastError();
+}
+
+// <x, y> in FP64: 256 workgroups of 256 threads each sum a fixed strided
+// share and fold it in LDS in a fixed order, then one workgroup folds the
+// 256 partial sums the same way (bitwise deterministic)
+constexpr int DOT_BLOCKS = 256;
+
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[256];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k3_dot_partial(const T* x, const T* y, long long n,
+                                                      double* partial) {
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += 256LL * DOT_BLOCKS)
+    acc += (double)x[i] * (double)y[i];
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k3_dot_final(const double* partial, double* out) {
+  const double s = block_sum(partial[threadIdx.x]);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+hipError_t launch3_dot(bool f64, const void* x, const void* y, long long n, double* partial,
+                       double* out, hipStream_t s) {
+  if (f64)
+    hipLaunchKernelGGL((k3_dot_partial<double>), dim3(DOT_BLOCKS), dim3(256), 0, s,
+                       (const double*)x, (const double*)y, n, partial);
+  else
+    hipLaunchKernelGGL((k3_dot_partial<float>), dim3(DOT_BLOCKS), dim3(256), 0, s,
+                       (const float*)x, (const float*)y, n, partial);
+  hipLaunchKernelGGL(k3_dot_final, dim3(1), dim3(256), 0, s, partial, out);
   return hipGetLastError();
 }
 

@@ -36,21 +36,35 @@ inline Fields3<T> fields3(const void* base, const Dims3& d) {
   return {b, b + n, b + 2 * n, b + 3 * n, b + 4 * n, b + 5 * n, b + 6 * n};
 }
 
-// One time step of the fields (forward: v then p with the source plane's
-// samples tr; transposed: the velocity and pressure adjoints with the
-// recording of the next-lower step tr, or none).  fac: the layer factors,
-// per axis z, y, x four arrays a_node, b_node, a_half, b_half; ck = dt kappa
-// / h per cell; cb = dt / (rho h).
+// One time step of the fields.  Forward: v then p, with the pressure
+// source plane pl and its samples tr, and the normal-load plane pl2 (v_z
+// nodes) and its samples tr2 (either null: none).  Transposed: the velocity
+// and pressure adjoints, with the pressure recording of the next-lower step
+// (pl, tr) and this step's v_z recording (pl2, tr2).  fac: the layer
+// factors, per axis z, y, x four arrays a_node, b_node, a_half, b_half; ck =
+// dt kappa / h per cell; cb = dt / (rho h).
 hipError_t launch3_step(bool f64, int order, bool adj, const void* fields, const Dims3& d,
                         const void* fac, const void* ck, double cb, const Plane3& pl,
-                        const void* tr, hipStream_t s);
+                        const void* tr, const Plane3& pl2, const void* tr2, hipStream_t s);
 // each pressure part += R^T tr on plane pl
 hipError_t launch3_spread(bool f64, const void* fields, const Dims3& d, const Plane3& pl,
                           const void* tr, hipStream_t s);
-// out = R p on plane pl (forward), or, scaled, R (b_node,z ck p~_z) with
-// p~_z the adjoint of the pressure's z part (transposed sweep)
-hipError_t launch3_gather(bool f64, bool scaled, const void* fields, const Dims3& d,
-                          const Plane3& pl, const void* fac, const void* ck, void* out,
-                          hipStream_t s);
+// out = R v on plane pl: mode 0 v = p; 1 (transposed sweep) v = b_node,z ck
+// times the adjoint of the pressure's z part; 2 v = v_z; 3 (transposed
+// sweep) v = b_half,z cb times v_z's adjoint
+hipError_t launch3_gather(bool f64, int mode, const void* fields, const Dims3& d,
+                          const Plane3& pl, const void* fac, const void* ck, double cb,
+                          void* out, hipStream_t s);
+// y = sc s_t x per trace t (n values, ntr traces per step): s_t = dist_t
+// (op 0), dist_t^2 (op 1), (1 + a^2 dist_t^2)^(-1/2) (op 2)
+hipError_t launch3_diag(bool f64, int op, double a, double sc, const double* dist, const void* x,
+                        void* y, long long n, int ntr, hipStream_t s);
+// y = x + a z
+hipError_t launch3_axpy(bool f64, void* y, const void* x, double a, const void* z, long long n,
+                        hipStream_t s);
+
+// out[0] = <x, y> in FP64 over n values (partial: device double[256])
+hipError_t launch3_dot(bool f64, const void* x, const void* y, long long n, double* partial,
+                       double* out, hipStream_t s);
 
 }  // namespace ssx3

@@ -100,3 +100,68 @@ def test_rejects_bad_arguments():
     ctx.close()
     with pytest.raises(ValueError):
         ssx.Context3(prob, kap[:, :, :-1], RHO)
+
+
+# ---------------------------------------------------------------------------
+# the 3D subproblem: penalty, thin-slab M^-1 and Algorithm 1 against the
+# 3D oracle (oracle.ops3)
+
+from oracle.ops3 import (Model3, dscale3, lateral_distance3, pcg_solve3,  # noqa: E402
+                         precond3)
+
+
+def problem_s(order, dz):
+    return problem(order).replace(slab_dz=dz, x_s=345.0, y_s=45.0)
+
+
+@pytest.mark.parametrize("order,dz", [(4, 3), (8, -2)])
+@pytest.mark.parametrize("fd,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_preconditioner_and_penalty_against_oracle(order, dz, fd, tol):
+    print(f"case 3d precond order {order} dz {dz} {fd}", flush=True)
+    prob = problem_s(order, dz)
+    kap = model(prob)
+    m = Model3(prob, kap, RHO)
+    rng = np.random.default_rng(17)
+    r = rng.standard_normal((prob.nt, prob.ns))
+    ref = precond3(m, 2e-3, r)
+    ctx = ssx.Context3(prob, kap, RHO, field_dtype=fd)
+    rt = torch.tensor(r.reshape(prob.nt, prob.nsy, prob.nsx), dtype=ctx.dtype, device="cuda")
+    g = ctx.precond(2e-3, rt, ctx.empty_src())
+    a = ctx.penalty(ssx.PEN_A, 0.0, rt, ctx.empty_src())
+    dh = ctx.penalty(ssx.PEN_DHALF, 2e-3, rt, ctx.empty_src())
+    torch.cuda.synchronize()
+    out = g.double().cpu().numpy().reshape(prob.nt, -1)
+    ctx_a = a.double().cpu().numpy().reshape(prob.nt, -1)
+    ctx_d = dh.double().cpu().numpy().reshape(prob.nt, -1)
+    ctx.close()
+    e = np.abs(out - ref).max() / np.abs(ref).max()
+    print(f"  M^-1 {e:.2e}", flush=True)
+    assert e <= tol
+    dist = lateral_distance3(prob)[None, :]
+    assert np.abs(ctx_a - dist * r).max() <= tol * np.abs(dist * r).max()
+    dref = dscale3(prob, 2e-3)[None, :] * r
+    assert np.abs(ctx_d - dref).max() <= tol * np.abs(dref).max()
+
+
+@pytest.mark.parametrize("fd,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_pcg_solve_against_oracle(fd, tol):
+    print(f"case 3d pcg {fd}", flush=True)
+    prob = problem_s(8, 3)
+    kap = model(prob)
+    m = Model3(prob, kap, RHO)
+    rng = np.random.default_rng(19)
+    d = m.fwd(rng.standard_normal((prob.nt, prob.ns)))
+    K = 4
+    h_ref, hist_ref, _ = pcg_solve3(m, d, 1e-3, K)
+    ctx = ssx.Context3(prob, kap, RHO, field_dtype=fd)
+    dt = torch.tensor(d.reshape(prob.nt, prob.nry, prob.nrx), dtype=ctx.dtype, device="cuda")
+    h, hist, it = ctx.pcg_solve(dt, 1e-3, K)
+    torch.cuda.synchronize()
+    hh = h.double().cpu().numpy().reshape(prob.nt, -1)
+    ctx.close()
+    assert it == K
+    e = np.linalg.norm(hh - h_ref) / np.linalg.norm(h_ref)
+    eh = np.abs(hist - hist_ref).max(axis=0) / np.abs(hist_ref).max(axis=0)
+    print(f"  h {e:.2e}, history {eh}", flush=True)
+    assert e <= tol
+    assert np.all(eh <= tol), eh
