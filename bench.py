@@ -876,7 +876,8 @@ def bench3d(args):
     roofline is that of one time step (k3_vel + k3_pres) timed with events
     on the context's stream over a forward propagation, against 9 field
     values per cell-update (read p, v_x, v_y, v_z and ck; write p, v_x, v_y,
-    v_z)."""
+    v_z).  Also one timed subproblem solve (Algorithm 1 with the thin-slab
+    M^-1, --iters iterations, default 5) on the data of the pairs."""
     import numpy as np
     import torch
 
@@ -888,7 +889,7 @@ def bench3d(args):
     nz, ny, nx, hh = 201, 201, 401, 10.0
     prob = inputs.Problem3(nz=nz, ny=ny, nx=nx, h=hh, dt=1e-3, nt=args.nt or 1000, order=8,
                            npml=20, z_src=1000.0, nsx=nx, nsy=ny, z_rec=200.0, nrx=nx,
-                           nry=ny)
+                           nry=ny, slab_dz=5, x_s=(nx // 2) * hh, y_s=(ny // 2) * hh)
     vel = inputs.layered_velocity3(nz, ny, nx, hh, np.random.default_rng(inputs.BASE_SEED + 30))
     kap = rho * vel * vel
     ctx = ssx.Context3(prob, kap, rho, field_dtype=fd)
@@ -937,6 +938,18 @@ def bench3d(args):
                      "bytes_per_cell": 9 * esz, "cells_per_step": cells},
         "cpu_baseline": None,
     }
+    # one subproblem solve: Algorithm 1 with M^-1 = D W^-1 D on the thin slab
+    # (K = --iters, default 5, alpha_rel 1e-3) on the data of the point source
+    K = args.iters or 5
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hs, hist, it = ctx.pcg_solve(d, 1e-3, K)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    out["pcg_solve"] = {"K": K, "iters": it, "seconds": round(ts, 3),
+                        "solves_per_s": round(1.0 / ts, 4),
+                        "rel_residual": [round(float(x), 5) for x in hist[:, 0] / hist[0, 0]],
+                        "rel_misfit": [round(float(x), 5) for x in hist[:, 3] / hist[0, 3]]}
     if not args.no_cpu_baseline:
         # the oracle's 3D forward on the same grid for a few steps,
         # extrapolated linearly to the step's 2 nt cell-updates
