@@ -509,7 +509,7 @@ typedef struct {
  * [nz][ny][nx], Pa) may be NULL to check the problem alone. */
 ssx_status ssx3_validate(const ssx3_problem* prob, const double* kappa_host, double rho);
 
-/* Device bytes a 3D context owns (the full grid's and the thin slab's seven
+/* Device bytes a 3D context owns (the full grid's and the thin slab's ten
  * fields and coefficients, ten trace vectors, FP64 scalars); 0 if the
  * problem is invalid. */
 size_t ssx3_footprint(const ssx3_problem* prob);

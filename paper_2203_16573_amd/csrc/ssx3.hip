@@ -171,27 +171,23 @@ __global__ __launch_bounds__(BX* BY) void k3_pres(Fields3<T> f, Dims3 d, const T
 // the transpose of p_a -= b_node,a Ck D_a^- v_a (D^- = -(D^+)^T).
 template <int K, typename T>
 __global__ __launch_bounds__(BX* BY) void k3_adj_v(Fields3<T> f, Dims3 d, const T* fac,
-                                                   const T* ck, Plane3 vpl, const T* vtr) {
+                                                   Plane3 vpl, const T* vtr) {
   const Cell cc = cell_of(d);
   const int x = cc.x, y = cc.y, z = cc.z;
   if (x >= d.NX || y >= d.NY) return;
   const long long o = ((long long)z * d.NY + y) * d.NX + x;
   const Fac<T> F{fac, d.NZ, d.NY, d.NX};
-  const long long sy = d.NX, sz = (long long)d.NY * d.NX;
-  // q at a neighbouring node of axis a (zero outside the grid)
-  auto q = [&](const T* pa, int axis, int zz, int yy, int xx) -> T {
-    if (zz < 0 || zz >= d.NZ || yy < 0 || yy >= d.NY || xx < 0 || xx >= d.NX) return T(0);
-    const long long j = zz * sz + yy * sy + xx;
-    const int i = axis == 0 ? zz : (axis == 1 ? yy : xx);
-    return (F.bn(axis, i) * ck[j]) * (inner(d, zz, yy, xx) ? f.p[j] : pa[j]);
-  };
+  // q_a = b_node,a Ck p~_a at the neighbouring nodes, as the kernel that
+  // last updated p~_a stored it (zero outside the grid)
+  const View<T> qx{f.qx, d.NZ, d.NY, d.NX}, qy{f.qy, d.NZ, d.NY, d.NX},
+      qz{f.qz, d.NZ, d.NY, d.NX};
   T sx = T(0), sy_ = T(0), sz_ = T(0);
 #pragma unroll
   for (int m = 1; m <= K; ++m) {
     const T c = wst<K, T>(m - 1);
-    sx = acc(sx, c, q(f.px, 2, z, y, x + m), q(f.px, 2, z, y, x + 1 - m));
-    sy_ = acc(sy_, c, q(f.py, 1, z, y + m, x), q(f.py, 1, z, y + 1 - m, x));
-    sz_ = acc(sz_, c, q(f.pz, 0, z + m, y, x), q(f.pz, 0, z + 1 - m, y, x));
+    sx = acc(sx, c, qx(z, y, x + m), qx(z, y, x + 1 - m));
+    sy_ = acc(sy_, c, qy(z, y + m, x), qy(z, y + 1 - m, x));
+    sz_ = acc(sz_, c, qz(z + m, y, x), qz(z + 1 - m, y, x));
   }
   // the v_z recording of this step (V = R v_z) enters after the scaling
   T rv = T(0);
@@ -205,14 +201,15 @@ __global__ __launch_bounds__(BX* BY) void k3_adj_v(Fields3<T> f, Dims3 d, const 
   f.vz[o] = (F.ah(0, z) * f.vz[o] + rv) + sz_;
 }
 
-// Transposed velocity updates: p~_a <- a_node,a p~_a + t, with
+// Transposed velocity updates (q_a stored with each updated p~_a):
+// p~_a <- a_node,a p~_a + t, with
 //   t = sum_a sum_m c_m (u_a[i+m-1] - u_a[i-m]),  u_a = b_half,a Cb v~_a
 // (the transpose of v_a -= b_half,a Cb D_a^+ p, p = p_x + p_y + p_z, taken
 // by all three parts), then the recording of step n - 1 (P = R p) added to
 // each part.
 template <int K, typename T>
-__global__ __launch_bounds__(BX* BY) void k3_adj_p(Fields3<T> f, Dims3 d, const T* fac, T cb,
-                                                   Plane3 rec, const T* rtr) {
+__global__ __launch_bounds__(BX* BY) void k3_adj_p(Fields3<T> f, Dims3 d, const T* fac,
+                                                   const T* ck, T cb, Plane3 rec, const T* rtr) {
   const Cell cc = cell_of(d);
   const int x = cc.x, y = cc.y, z = cc.z;
   if (x >= d.NX || y >= d.NY) return;
@@ -238,19 +235,31 @@ __global__ __launch_bounds__(BX* BY) void k3_adj_p(Fields3<T> f, Dims3 d, const 
     const double w = plane_w(rec, z, y, x, tr);
     if (w != 0.0) r = T(w) * rtr[tr];
   }
+  const T k = ck[o];
   if (inner(d, z, y, x)) {
-    f.p[o] = (f.p[o] + t) + r;
+    const T pb = (f.p[o] + t) + r;
+    f.p[o] = pb;
+    f.qx[o] = (F.bn(2, x) * k) * pb;
+    f.qy[o] = (F.bn(1, y) * k) * pb;
+    f.qz[o] = (F.bn(0, z) * k) * pb;
     return;
   }
-  f.px[o] = fmac(F.an(2, x), f.px[o], t) + r;
-  f.py[o] = fmac(F.an(1, y), f.py[o], t) + r;
-  f.pz[o] = fmac(F.an(0, z), f.pz[o], t) + r;
+  const T pbx = fmac(F.an(2, x), f.px[o], t) + r;
+  const T pby = fmac(F.an(1, y), f.py[o], t) + r;
+  const T pbz = fmac(F.an(0, z), f.pz[o], t) + r;
+  f.px[o] = pbx;
+  f.py[o] = pby;
+  f.pz[o] = pbz;
+  f.qx[o] = (F.bn(2, x) * k) * pbx;
+  f.qy[o] = (F.bn(1, y) * k) * pby;
+  f.qz[o] = (F.bn(0, z) * k) * pbz;
 }
 
 // the recording's transpose alone (the first transposed step): each part
 // of the pressure adjoint += R^T r
 template <typename T>
-__global__ void k3_spread(Fields3<T> f, Dims3 d, Plane3 pl, const T* tr) {
+__global__ void k3_spread(Fields3<T> f, Dims3 d, Plane3 pl, const T* fac, const T* ck,
+                          const T* tr) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= 2 * pl.ny * pl.nx) return;
   const int row = i / (pl.ny * pl.nx), t = i - row * (pl.ny * pl.nx);
@@ -259,13 +268,22 @@ __global__ void k3_spread(Fields3<T> f, Dims3 d, Plane3 pl, const T* tr) {
   const T w = T(row ? pl.w1 : pl.w0);
   const long long o = ((long long)z * d.NY + y) * d.NX + x;
   const T v = w * tr[t];
+  const Fac<T> F{fac, d.NZ, d.NY, d.NX};
+  const T k = ck[o];
   if (inner(d, z, y, x)) {
-    f.p[o] += v;
+    const T pb = f.p[o] + v;
+    f.p[o] = pb;
+    f.qx[o] = (F.bn(2, x) * k) * pb;
+    f.qy[o] = (F.bn(1, y) * k) * pb;
+    f.qz[o] = (F.bn(0, z) * k) * pb;
     return;
   }
   f.px[o] += v;
   f.py[o] += v;
   f.pz[o] += v;
+  f.qx[o] = (F.bn(2, x) * k) * f.px[o];
+  f.qy[o] = (F.bn(1, y) * k) * f.py[o];
+  f.qz[o] = (F.bn(0, z) * k) * f.pz[o];
 }
 
 // plane gather: out[t] = sum_rows w s v, with (MODE 0) v = p, s = 1; (1)
@@ -284,7 +302,7 @@ __global__ void k3_gather(Fields3<T> f, Dims3 d, Plane3 pl, const T* fac, const 
     if (MODE == 0) return f.p[o];
     if (MODE == 2) return f.vz[o];
     if (MODE == 3) return (F.bh(0, z) * cb) * f.vz[o];
-    return (F.bn(0, z) * ck[o]) * (inner(d, z, y, x) ? f.p[o] : f.pz[o]);
+    return f.qz[o];  // (MODE 1) b_node,z Ck p~_z, as stored
   };
   T s = T(pl.w0) * val(pl.r0);
   if (pl.r1 >= 0) s = s + T(pl.w1) * val(pl.r1);
@@ -308,16 +326,16 @@ static hipError_t step_t(int order, bool adj, const Fields3<T>& f, const Dims3& 
       hipLaunchKernelGGL((k3_vel<2, T>), g, b, 0, s, f, d, fac, cb, pl2, tr2);
       hipLaunchKernelGGL((k3_pres<2, T>), g, b, 0, s, f, d, fac, ck, pl, tr);
     } else {
-      hipLaunchKernelGGL((k3_adj_v<2, T>), g, b, 0, s, f, d, fac, ck, pl2, tr2);
-      hipLaunchKernelGGL((k3_adj_p<2, T>), g, b, 0, s, f, d, fac, cb, pl, tr);
+      hipLaunchKernelGGL((k3_adj_v<2, T>), g, b, 0, s, f, d, fac, pl2, tr2);
+      hipLaunchKernelGGL((k3_adj_p<2, T>), g, b, 0, s, f, d, fac, ck, cb, pl, tr);
     }
   } else if (order == 8) {
     if (!adj) {
       hipLaunchKernelGGL((k3_vel<4, T>), g, b, 0, s, f, d, fac, cb, pl2, tr2);
       hipLaunchKernelGGL((k3_pres<4, T>), g, b, 0, s, f, d, fac, ck, pl, tr);
     } else {
-      hipLaunchKernelGGL((k3_adj_v<4, T>), g, b, 0, s, f, d, fac, ck, pl2, tr2);
-      hipLaunchKernelGGL((k3_adj_p<4, T>), g, b, 0, s, f, d, fac, cb, pl, tr);
+      hipLaunchKernelGGL((k3_adj_v<4, T>), g, b, 0, s, f, d, fac, pl2, tr2);
+      hipLaunchKernelGGL((k3_adj_p<4, T>), g, b, 0, s, f, d, fac, ck, cb, pl, tr);
     }
   } else {
     return hipErrorInvalidValue;
@@ -338,15 +356,15 @@ hipError_t launch3_step(bool f64, int order, bool adj, const void* fields, const
 }
 
 hipError_t launch3_spread(bool f64, const void* fields, const Dims3& d, const Plane3& pl,
-                          const void* tr, hipStream_t s) {
+                          const void* fac, const void* ck, const void* tr, hipStream_t s) {
   const int n = 2 * pl.ny * pl.nx;
   const dim3 g((n + 255) / 256), b(256);
   if (f64)
     hipLaunchKernelGGL((k3_spread<double>), g, b, 0, s, fields3<double>(fields, d), d, pl,
-                       (const double*)tr);
+                       (const double*)fac, (const double*)ck, (const double*)tr);
   else
     hipLaunchKernelGGL((k3_spread<float>), g, b, 0, s, fields3<float>(fields, d), d, pl,
-                       (const float*)tr);
+                       (const float*)fac, (const float*)ck, (const float*)tr);
   return hipGetLastError();
 }
 

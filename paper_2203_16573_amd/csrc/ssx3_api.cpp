@@ -20,7 +20,7 @@ using ssx3::Plane3;
 
 namespace {
 
-// One padded grid on the device: seven fields, ck, layer factors.
+// One padded grid on the device: the fields, ck, layer factors.
 struct Grid3Dev {
   Dims3 d{};
   void* fields = nullptr;
@@ -179,7 +179,7 @@ Dims3 dims_of(const ssx3_problem& p, int nz) {
 }
 
 long long grid_elems(const Dims3& d) {
-  return 8LL * d.NZ * d.NY * d.NX + 4LL * (d.NZ + d.NY + d.NX);
+  return (ssx3::NFIELDS3 + 1LL) * d.NZ * d.NY * d.NX + 4LL * (d.NZ + d.NY + d.NX);
 }
 
 // bytes of every device array of a context
@@ -270,7 +270,7 @@ ssx_status sweep_fwd(ssx3_ctx* c, const Grid3Dev& g, const Plane3& hp, const voi
   const ssx3_problem& p = c->prob;
   const long long nh = (long long)hp.nx * hp.ny, nf = (long long)fp.nx * fp.ny;
   const long long np = (long long)rp.nx * rp.ny, nv = (long long)vp.nx * vp.ny;
-  S3_HIP(hipMemsetAsync(g.fields, 0, 7 * g.cells() * c->esz, c->stream));
+  S3_HIP(hipMemsetAsync(g.fields, 0, ssx3::NFIELDS3 * g.cells() * c->esz, c->stream));
   for (int t = 0; t < p.nt; ++t) {
     S3_HIP(ssx3::launch3_step(c->f64, p.order, false, g.fields, g.d, g.fac, g.ck, c->cb, hp,
                               h ? at(h, t * nh, c->esz) : nullptr, fp,
@@ -295,10 +295,10 @@ ssx_status sweep_adj(ssx3_ctx* c, const Grid3Dev& g, const Plane3& rp, const voi
   const ssx3_problem& p = c->prob;
   const long long nh = (long long)hp.nx * hp.ny, nf = (long long)fp.nx * fp.ny;
   const long long np = (long long)rp.nx * rp.ny, nv = (long long)vp.nx * vp.ny;
-  S3_HIP(hipMemsetAsync(g.fields, 0, 7 * g.cells() * c->esz, c->stream));
+  S3_HIP(hipMemsetAsync(g.fields, 0, ssx3::NFIELDS3 * g.cells() * c->esz, c->stream));
   if (a)
-    S3_HIP(ssx3::launch3_spread(c->f64, g.fields, g.d, rp, at(a, (p.nt - 1) * np, c->esz),
-                                c->stream));
+    S3_HIP(ssx3::launch3_spread(c->f64, g.fields, g.d, rp, g.fac, g.ck,
+                                at(a, (p.nt - 1) * np, c->esz), c->stream));
   for (int t = p.nt - 1; t >= 0; --t) {
     if (H)
       S3_HIP(ssx3::launch3_gather(c->f64, 1, g.fields, g.d, hp, g.fac, g.ck, c->cb,
@@ -384,7 +384,7 @@ ssx_status ssx3_create(const ssx3_problem* prob, const double* kappa_host, doubl
   };
   for (Grid3Dev* g : {&c->full, &c->slab}) {
     const long long n = g->cells();
-    g->fields = carve(7 * n);
+    g->fields = carve(ssx3::NFIELDS3 * n);
     g->ck = carve(n);
     g->fac = carve(4LL * (g->d.NZ + g->d.NY + g->d.NX));
   }

@@ -20,20 +20,25 @@ struct Plane3 {
   int y0, ny, x0, nx;
 };
 
-// The seven [NZ][NY][NX] fields, carved from one buffer in this order.
+// The NFIELDS3 [NZ][NY][NX] fields, carved from one buffer in this order.
 // The pressure parts px, py, pz are used in the absorbing frame only; p
 // holds the total pressure everywhere (forward) or, in the transposed
 // sweep, the common value of the three parts' adjoints off the frame
-// (equal there: they receive the same updates).
+// (equal there: they receive the same updates).  qx, qy, qz (transposed
+// sweep only): b_node,a ck times the adjoint of pressure part a, stored by
+// the kernel that updates it, so that the next transposed pressure update
+// reads one value per stencil neighbour.
+constexpr int NFIELDS3 = 10;
 template <typename T>
 struct Fields3 {
-  T *vx, *vy, *vz, *px, *py, *pz, *p;
+  T *vx, *vy, *vz, *px, *py, *pz, *p, *qx, *qy, *qz;
 };
 template <typename T>
 inline Fields3<T> fields3(const void* base, const Dims3& d) {
   T* b = static_cast<T*>(const_cast<void*>(base));
   const long long n = (long long)d.NZ * d.NY * d.NX;
-  return {b, b + n, b + 2 * n, b + 3 * n, b + 4 * n, b + 5 * n, b + 6 * n};
+  return {b,         b + n,     b + 2 * n, b + 3 * n, b + 4 * n,
+          b + 5 * n, b + 6 * n, b + 7 * n, b + 8 * n, b + 9 * n};
 }
 
 // One time step of the fields.  Forward: v then p, with the pressure
@@ -46,9 +51,9 @@ inline Fields3<T> fields3(const void* base, const Dims3& d) {
 hipError_t launch3_step(bool f64, int order, bool adj, const void* fields, const Dims3& d,
                         const void* fac, const void* ck, double cb, const Plane3& pl,
                         const void* tr, const Plane3& pl2, const void* tr2, hipStream_t s);
-// each pressure part += R^T tr on plane pl
+// each pressure part's adjoint += R^T tr on plane pl (and its q updated)
 hipError_t launch3_spread(bool f64, const void* fields, const Dims3& d, const Plane3& pl,
-                          const void* tr, hipStream_t s);
+                          const void* fac, const void* ck, const void* tr, hipStream_t s);
 // out = R v on plane pl: mode 0 v = p; 1 (transposed sweep) v = b_node,z ck
 // times the adjoint of the pressure's z part; 2 v = v_z; 3 (transposed
 // sweep) v = b_half,z cb times v_z's adjoint
