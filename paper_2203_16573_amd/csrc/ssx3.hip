@@ -166,11 +166,11 @@ __global__ __launch_bounds__(BX* BY) void k3_pres(Fields3<T> f, Dims3 d, const T
 
 // Transposed pressure updates: the velocity adjoints take the layer scaling
 // pending from the previous transposed step (a_half v~) and the v_z
-// recording of this step, then
+// recording of this step (u_a stored with each updated v~_a), then
 //   v~_a += sum_m c_m (q_a[i+m] - q_a[i+1-m]),  q_a = b_node,a Ck p~_a,
 // the transpose of p_a -= b_node,a Ck D_a^- v_a (D^- = -(D^+)^T).
 template <int K, typename T>
-__global__ __launch_bounds__(BX* BY) void k3_adj_v(Fields3<T> f, Dims3 d, const T* fac,
+__global__ __launch_bounds__(BX* BY) void k3_adj_v(Fields3<T> f, Dims3 d, const T* fac, T cb,
                                                    Plane3 vpl, const T* vtr) {
   const Cell cc = cell_of(d);
   const int x = cc.x, y = cc.y, z = cc.z;
@@ -196,9 +196,15 @@ __global__ __launch_bounds__(BX* BY) void k3_adj_v(Fields3<T> f, Dims3 d, const 
     const double w = plane_w(vpl, z, y, x, tr);
     if (w != 0.0) rv = T(w) * vtr[tr];
   }
-  f.vx[o] = F.ah(2, x) * f.vx[o] + sx;
-  f.vy[o] = F.ah(1, y) * f.vy[o] + sy_;
-  f.vz[o] = (F.ah(0, z) * f.vz[o] + rv) + sz_;
+  const T vbx = F.ah(2, x) * f.vx[o] + sx;
+  const T vby = F.ah(1, y) * f.vy[o] + sy_;
+  const T vbz = (F.ah(0, z) * f.vz[o] + rv) + sz_;
+  f.vx[o] = vbx;
+  f.vy[o] = vby;
+  f.vz[o] = vbz;
+  f.ux[o] = (F.bh(2, x) * cb) * vbx;
+  f.uy[o] = (F.bh(1, y) * cb) * vby;
+  f.uz[o] = (F.bh(0, z) * cb) * vbz;
 }
 
 // Transposed velocity updates (q_a stored with each updated p~_a):
@@ -215,18 +221,17 @@ __global__ __launch_bounds__(BX* BY) void k3_adj_p(Fields3<T> f, Dims3 d, const 
   if (x >= d.NX || y >= d.NY) return;
   const long long o = ((long long)z * d.NY + y) * d.NX + x;
   const Fac<T> F{fac, d.NZ, d.NY, d.NX};
-  const View<T> vx{f.vx, d.NZ, d.NY, d.NX}, vy{f.vy, d.NZ, d.NY, d.NX},
-      vz{f.vz, d.NZ, d.NY, d.NX};
-  auto bx = [&](int i) { return (i < 0 || i >= d.NX) ? T(0) : F.bh(2, i) * cb; };
-  auto by = [&](int i) { return (i < 0 || i >= d.NY) ? T(0) : F.bh(1, i) * cb; };
-  auto bz = [&](int i) { return (i < 0 || i >= d.NZ) ? T(0) : F.bh(0, i) * cb; };
+  // u_a = b_half,a Cb v~_a at the neighbouring half nodes, as k3_adj_v
+  // stored it (zero outside the grid)
+  const View<T> ux{f.ux, d.NZ, d.NY, d.NX}, uy{f.uy, d.NZ, d.NY, d.NX},
+      uz{f.uz, d.NZ, d.NY, d.NX};
   T tx = T(0), ty = T(0), tz = T(0);
 #pragma unroll
   for (int m = 1; m <= K; ++m) {
     const T c = wst<K, T>(m - 1);
-    tx = acc(tx, c, bx(x + m - 1) * vx(z, y, x + m - 1), bx(x - m) * vx(z, y, x - m));
-    ty = acc(ty, c, by(y + m - 1) * vy(z, y + m - 1, x), by(y - m) * vy(z, y - m, x));
-    tz = acc(tz, c, bz(z + m - 1) * vz(z + m - 1, y, x), bz(z - m) * vz(z - m, y, x));
+    tx = acc(tx, c, ux(z, y, x + m - 1), ux(z, y, x - m));
+    ty = acc(ty, c, uy(z, y + m - 1, x), uy(z, y - m, x));
+    tz = acc(tz, c, uz(z + m - 1, y, x), uz(z - m, y, x));
   }
   const T t = (tx + ty) + tz;
   T r = T(0);
@@ -296,12 +301,14 @@ __global__ void k3_gather(Fields3<T> f, Dims3 d, Plane3 pl, const T* fac, const 
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= pl.ny * pl.nx) return;
   const int y = pl.y0 + t / pl.nx, x = pl.x0 + t % pl.nx;
-  const Fac<T> F{fac, d.NZ, d.NY, d.NX};
+  (void)fac;  // the scaled values (modes 1, 3) are read as the step kernels
+  (void)ck;   // stored them
+  (void)cb;
   auto val = [&](int z) {
     const long long o = ((long long)z * d.NY + y) * d.NX + x;
     if (MODE == 0) return f.p[o];
     if (MODE == 2) return f.vz[o];
-    if (MODE == 3) return (F.bh(0, z) * cb) * f.vz[o];
+    if (MODE == 3) return f.uz[o];  // b_half,z Cb v~_z, as stored
     return f.qz[o];  // (MODE 1) b_node,z Ck p~_z, as stored
   };
   T s = T(pl.w0) * val(pl.r0);
@@ -326,7 +333,7 @@ static hipError_t step_t(int order, bool adj, const Fields3<T>& f, const Dims3& 
       hipLaunchKernelGGL((k3_vel<2, T>), g, b, 0, s, f, d, fac, cb, pl2, tr2);
       hipLaunchKernelGGL((k3_pres<2, T>), g, b, 0, s, f, d, fac, ck, pl, tr);
     } else {
-      hipLaunchKernelGGL((k3_adj_v<2, T>), g, b, 0, s, f, d, fac, pl2, tr2);
+      hipLaunchKernelGGL((k3_adj_v<2, T>), g, b, 0, s, f, d, fac, cb, pl2, tr2);
       hipLaunchKernelGGL((k3_adj_p<2, T>), g, b, 0, s, f, d, fac, ck, cb, pl, tr);
     }
   } else if (order == 8) {
@@ -334,7 +341,7 @@ static hipError_t step_t(int order, bool adj, const Fields3<T>& f, const Dims3& 
       hipLaunchKernelGGL((k3_vel<4, T>), g, b, 0, s, f, d, fac, cb, pl2, tr2);
       hipLaunchKernelGGL((k3_pres<4, T>), g, b, 0, s, f, d, fac, ck, pl, tr);
     } else {
-      hipLaunchKernelGGL((k3_adj_v<4, T>), g, b, 0, s, f, d, fac, pl2, tr2);
+      hipLaunchKernelGGL((k3_adj_v<4, T>), g, b, 0, s, f, d, fac, cb, pl2, tr2);
       hipLaunchKernelGGL((k3_adj_p<4, T>), g, b, 0, s, f, d, fac, ck, cb, pl, tr);
     }
   } else {

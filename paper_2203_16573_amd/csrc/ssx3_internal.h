@@ -25,20 +25,21 @@ struct Plane3 {
 // holds the total pressure everywhere (forward) or, in the transposed
 // sweep, the common value of the three parts' adjoints off the frame
 // (equal there: they receive the same updates).  qx, qy, qz (transposed
-// sweep only): b_node,a ck times the adjoint of pressure part a, stored by
-// the kernel that updates it, so that the next transposed pressure update
-// reads one value per stencil neighbour.
-constexpr int NFIELDS3 = 10;
+// sweep only): b_node,a ck times the adjoint of pressure part a, and ux,
+// uy, uz: b_half,a cb times the adjoint of v_a, each stored by the kernel
+// that updates that adjoint, so that the next kernel reads one value per
+// stencil neighbour.
+constexpr int NFIELDS3 = 13;
 template <typename T>
 struct Fields3 {
-  T *vx, *vy, *vz, *px, *py, *pz, *p, *qx, *qy, *qz;
+  T *vx, *vy, *vz, *px, *py, *pz, *p, *qx, *qy, *qz, *ux, *uy, *uz;
 };
 template <typename T>
 inline Fields3<T> fields3(const void* base, const Dims3& d) {
   T* b = static_cast<T*>(const_cast<void*>(base));
   const long long n = (long long)d.NZ * d.NY * d.NX;
-  return {b,         b + n,     b + 2 * n, b + 3 * n, b + 4 * n,
-          b + 5 * n, b + 6 * n, b + 7 * n, b + 8 * n, b + 9 * n};
+  return {b,         b + n,     b + 2 * n, b + 3 * n, b + 4 * n,  b + 5 * n, b + 6 * n,
+          b + 7 * n, b + 8 * n, b + 9 * n, b + 10 * n, b + 11 * n, b + 12 * n};
 }
 
 // One time step of the fields.  Forward: v then p, with the pressure
