@@ -14,7 +14,7 @@
 // (values outside the grid are read as zero).  The pressure is split into
 // its three parts in the absorbing frame only: off the frame every layer
 // factor is 1, the forward pressure is updated as one total, and the three
-// parts' adjoints are equal and kept as one value.  One thread per cell, 64 x 4
+// parts' adjoints are equal and kept as one value.  One thread per cell, 64 x 8
 // (x, y) threads per workgroup on one z plane; workgroups are dealt to the
 // 8 XCDs round-robin, so the logical tile order gives each XCD a contiguous
 // band of z planes, which it sweeps plane by plane: the z-neighbour planes
@@ -35,7 +35,7 @@ using ssx::acc;
 using ssx::fmac;
 using ssx::wst;
 
-constexpr int BX = 64, BY = 4;
+constexpr int BX = 64, BY = 8;
 
 // the cell of this thread: logical tile of hardware block b (XCD bands of
 // consecutive tiles, x tiles fastest, then y tiles, then z planes)
