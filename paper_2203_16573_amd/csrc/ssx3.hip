@@ -14,11 +14,12 @@
 // (values outside the grid are read as zero).  The pressure is split into
 // its three parts in the absorbing frame only: off the frame every layer
 // factor is 1, the forward pressure is updated as one total, and the three
-// parts' adjoints are equal and kept as one value.  One thread per cell, 64 x 8
-// (x, y) threads per workgroup on one z plane; workgroups are dealt to the
-// 8 XCDs round-robin, so the logical tile order gives each XCD a contiguous
-// band of z planes, which it sweeps plane by plane: the z-neighbour planes
-// a stencil reads are then the ones its own L2 has just held.
+// parts' adjoints are equal and kept as one value.  One thread per ZW
+// planes of a column (the z-stencil operands of those planes loaded once;
+// one plane in k3_adj_v), 64 x 8 columns per workgroup; workgroups are
+// dealt to the 8 XCDs round-robin, so the logical tile order gives each XCD
+// a contiguous band of z planes, which it sweeps in order: the z-neighbour
+// planes a stencil reads are then the ones its own L2 has just held.
 //
 // Forward step n: k3_vel (v^{n+1/2} from p^n), k3_pres (p^{n+1} from
 // v^{n+1/2}, the source sample h[n] injected), then the receiver plane
@@ -36,19 +37,24 @@ using ssx::fmac;
 using ssx::wst;
 
 constexpr int BX = 64, BY = 8;
+constexpr int ZW = 4;    // z planes per thread: k3_vel, k3_pres, k3_adj_p
+constexpr int ZW_AV = 1;  // k3_adj_v (six stores per plane: one plane each)
 
-// the cell of this thread: logical tile of hardware block b (XCD bands of
-// consecutive tiles, x tiles fastest, then y tiles, then z planes)
+// A thread's column and planes: logical tile of hardware block b (XCD bands
+// of consecutive tiles, x tiles fastest, then y tiles, then chunks of Z z
+// planes)
 struct Cell {
   int x, y, z;
 };
-__device__ __forceinline__ Cell cell_of(const Dims3& d) {
+// the column (x, y) and the first of the thread's Z planes
+template <int Z>
+__device__ __forceinline__ Cell col_of(const Dims3& d) {
   const int n = (int)gridDim.x, b = (int)blockIdx.x;
   const int per = n >> 3, rem = n & 7, xcd = b & 7;
   const int t = xcd * per + (xcd < rem ? xcd : rem) + (b >> 3);
   const int tx = (d.NX + BX - 1) / BX, ty = (d.NY + BY - 1) / BY;
-  const int z = t / (tx * ty), r = t - z * (tx * ty), yb = r / tx, xb = r - yb * tx;
-  return {xb * BX + (int)threadIdx.x, yb * BY + (int)threadIdx.y, z};
+  const int zc = t / (tx * ty), r = t - zc * (tx * ty), yb = r / tx, xb = r - yb * tx;
+  return {xb * BX + (int)threadIdx.x, yb * BY + (int)threadIdx.y, zc * Z};
 }
 
 template <typename T>
@@ -100,68 +106,86 @@ __device__ __forceinline__ double plane_w(const Plane3& pl, int z, int y, int x,
   return w;
 }
 
-template <int K, typename T>
+// Each thread takes Z consecutive planes of its column; the 2K + Z - 1
+// values the z-stencils of those planes read are loaded once, in w.
+template <int K, typename T, int Z>
 __global__ __launch_bounds__(BX* BY) void k3_vel(Fields3<T> f, Dims3 d, const T* fac, T cb,
                                                  Plane3 fpl, const T* ftr) {
-  const Cell cc = cell_of(d);
-  const int x = cc.x, y = cc.y, z = cc.z;
+  const Cell cc = col_of<Z>(d);
+  const int x = cc.x, y = cc.y, z0 = cc.z;
   if (x >= d.NX || y >= d.NY) return;
-  const long long o = ((long long)z * d.NY + y) * d.NX + x;
   const View<T> p{f.p, d.NZ, d.NY, d.NX};
   const Fac<T> F{fac, d.NZ, d.NY, d.NX};
-  T gx = T(0), gy = T(0), gz = T(0);
+  T w[2 * K + Z - 1];  // p at planes z0 + 1 - K ..
 #pragma unroll
-  for (int m = 1; m <= K; ++m) {
-    const T c = wst<K, T>(m - 1);
-    gx = acc(gx, c, p(z, y, x + m), p(z, y, x + 1 - m));
-    gy = acc(gy, c, p(z, y + m, x), p(z, y + 1 - m, x));
-    gz = acc(gz, c, p(z + m, y, x), p(z + 1 - m, y, x));
+  for (int j = 0; j < 2 * K + Z - 1; ++j) w[j] = p(z0 + 1 - K + j, y, x);
+#pragma unroll
+  for (int j = 0; j < Z; ++j) {
+    const int z = z0 + j;
+    if (z >= d.NZ) break;
+    const long long o = ((long long)z * d.NY + y) * d.NX + x;
+    T gx = T(0), gy = T(0), gz = T(0);
+#pragma unroll
+    for (int m = 1; m <= K; ++m) {
+      const T c = wst<K, T>(m - 1);
+      gx = acc(gx, c, p(z, y, x + m), p(z, y, x + 1 - m));
+      gy = acc(gy, c, p(z, y + m, x), p(z, y + 1 - m, x));
+      gz = acc(gz, c, w[j + K - 1 + m], w[j + K - m]);
+    }
+    if (ftr) {  // a normal load on plane fpl (v_z nodes): D_z^+ p - E_f f
+      int tr = 0;
+      const double wt = plane_w(fpl, z, y, x, tr);
+      if (wt != 0.0) gz = gz - T(wt) * ftr[tr];
+    }
+    f.vx[o] = fmac(F.ah(2, x), f.vx[o], -(F.bh(2, x) * cb) * gx);
+    f.vy[o] = fmac(F.ah(1, y), f.vy[o], -(F.bh(1, y) * cb) * gy);
+    f.vz[o] = fmac(F.ah(0, z), f.vz[o], -(F.bh(0, z) * cb) * gz);
   }
-  if (ftr) {  // a normal load on plane fpl (v_z nodes): D_z^+ p - E_f f
-    int tr = 0;
-    const double w = plane_w(fpl, z, y, x, tr);
-    if (w != 0.0) gz = gz - T(w) * ftr[tr];
-  }
-  f.vx[o] = fmac(F.ah(2, x), f.vx[o], -(F.bh(2, x) * cb) * gx);
-  f.vy[o] = fmac(F.ah(1, y), f.vy[o], -(F.bh(1, y) * cb) * gy);
-  f.vz[o] = fmac(F.ah(0, z), f.vz[o], -(F.bh(0, z) * cb) * gz);
 }
 
-template <int K, typename T>
+template <int K, typename T, int Z>
 __global__ __launch_bounds__(BX* BY) void k3_pres(Fields3<T> f, Dims3 d, const T* fac,
                                                   const T* ck, Plane3 src, const T* htr) {
-  const Cell cc = cell_of(d);
-  const int x = cc.x, y = cc.y, z = cc.z;
+  const Cell cc = col_of<Z>(d);
+  const int x = cc.x, y = cc.y, z0 = cc.z;
   if (x >= d.NX || y >= d.NY) return;
-  const long long o = ((long long)z * d.NY + y) * d.NX + x;
   const View<T> vx{f.vx, d.NZ, d.NY, d.NX}, vy{f.vy, d.NZ, d.NY, d.NX},
       vz{f.vz, d.NZ, d.NY, d.NX};
   const Fac<T> F{fac, d.NZ, d.NY, d.NX};
-  T dx = T(0), dy = T(0), dz = T(0);
+  T w[2 * K + Z - 1];  // v_z at planes z0 - K ..
 #pragma unroll
-  for (int m = 1; m <= K; ++m) {
-    const T c = wst<K, T>(m - 1);
-    dx = acc(dx, c, vx(z, y, x + m - 1), vx(z, y, x - m));
-    dy = acc(dy, c, vy(z, y + m - 1, x), vy(z, y - m, x));
-    dz = acc(dz, c, vz(z + m - 1, y, x), vz(z - m, y, x));
+  for (int j = 0; j < 2 * K + Z - 1; ++j) w[j] = vz(z0 - K + j, y, x);
+#pragma unroll
+  for (int j = 0; j < Z; ++j) {
+    const int z = z0 + j;
+    if (z >= d.NZ) break;
+    const long long o = ((long long)z * d.NY + y) * d.NX + x;
+    T dx = T(0), dy = T(0), dz = T(0);
+#pragma unroll
+    for (int m = 1; m <= K; ++m) {
+      const T c = wst<K, T>(m - 1);
+      dx = acc(dx, c, vx(z, y, x + m - 1), vx(z, y, x - m));
+      dy = acc(dy, c, vy(z, y + m - 1, x), vy(z, y - m, x));
+      dz = acc(dz, c, w[j + K + m - 1], w[j + K - m]);
+    }
+    if (htr) {
+      int tr = 0;
+      const double wt = plane_w(src, z, y, x, tr);
+      if (wt != 0.0) dz = dz - T(wt) * htr[tr];
+    }
+    const T k = ck[o];
+    if (inner(d, z, y, x)) {
+      f.p[o] = fmac(-k, (dx + dy) + dz, f.p[o]);
+      continue;
+    }
+    const T px = fmac(F.an(2, x), f.px[o], -(F.bn(2, x) * k) * dx);
+    const T py = fmac(F.an(1, y), f.py[o], -(F.bn(1, y) * k) * dy);
+    const T pz = fmac(F.an(0, z), f.pz[o], -(F.bn(0, z) * k) * dz);
+    f.px[o] = px;
+    f.py[o] = py;
+    f.pz[o] = pz;
+    f.p[o] = (px + py) + pz;
   }
-  if (htr) {
-    int tr = 0;
-    const double w = plane_w(src, z, y, x, tr);
-    if (w != 0.0) dz = dz - T(w) * htr[tr];
-  }
-  const T k = ck[o];
-  if (inner(d, z, y, x)) {
-    f.p[o] = fmac(-k, (dx + dy) + dz, f.p[o]);
-    return;
-  }
-  const T px = fmac(F.an(2, x), f.px[o], -(F.bn(2, x) * k) * dx);
-  const T py = fmac(F.an(1, y), f.py[o], -(F.bn(1, y) * k) * dy);
-  const T pz = fmac(F.an(0, z), f.pz[o], -(F.bn(0, z) * k) * dz);
-  f.px[o] = px;
-  f.py[o] = py;
-  f.pz[o] = pz;
-  f.p[o] = (px + py) + pz;
 }
 
 // Transposed pressure updates: the velocity adjoints take the layer scaling
@@ -169,42 +193,50 @@ __global__ __launch_bounds__(BX* BY) void k3_pres(Fields3<T> f, Dims3 d, const T
 // recording of this step (u_a stored with each updated v~_a), then
 //   v~_a += sum_m c_m (q_a[i+m] - q_a[i+1-m]),  q_a = b_node,a Ck p~_a,
 // the transpose of p_a -= b_node,a Ck D_a^- v_a (D^- = -(D^+)^T).
-template <int K, typename T>
+template <int K, typename T, int Z>
 __global__ __launch_bounds__(BX* BY) void k3_adj_v(Fields3<T> f, Dims3 d, const T* fac, T cb,
                                                    Plane3 vpl, const T* vtr) {
-  const Cell cc = cell_of(d);
-  const int x = cc.x, y = cc.y, z = cc.z;
+  const Cell cc = col_of<Z>(d);
+  const int x = cc.x, y = cc.y, z0 = cc.z;
   if (x >= d.NX || y >= d.NY) return;
-  const long long o = ((long long)z * d.NY + y) * d.NX + x;
   const Fac<T> F{fac, d.NZ, d.NY, d.NX};
   // q_a = b_node,a Ck p~_a at the neighbouring nodes, as the kernel that
   // last updated p~_a stored it (zero outside the grid)
   const View<T> qx{f.qx, d.NZ, d.NY, d.NX}, qy{f.qy, d.NZ, d.NY, d.NX},
       qz{f.qz, d.NZ, d.NY, d.NX};
-  T sx = T(0), sy_ = T(0), sz_ = T(0);
+  T w[2 * K + Z - 1];  // q_z at planes z0 + 1 - K ..
 #pragma unroll
-  for (int m = 1; m <= K; ++m) {
-    const T c = wst<K, T>(m - 1);
-    sx = acc(sx, c, qx(z, y, x + m), qx(z, y, x + 1 - m));
-    sy_ = acc(sy_, c, qy(z, y + m, x), qy(z, y + 1 - m, x));
-    sz_ = acc(sz_, c, qz(z + m, y, x), qz(z + 1 - m, y, x));
+  for (int j = 0; j < 2 * K + Z - 1; ++j) w[j] = qz(z0 + 1 - K + j, y, x);
+#pragma unroll
+  for (int j = 0; j < Z; ++j) {
+    const int z = z0 + j;
+    if (z >= d.NZ) break;
+    const long long o = ((long long)z * d.NY + y) * d.NX + x;
+    T sx = T(0), sy_ = T(0), sz_ = T(0);
+#pragma unroll
+    for (int m = 1; m <= K; ++m) {
+      const T c = wst<K, T>(m - 1);
+      sx = acc(sx, c, qx(z, y, x + m), qx(z, y, x + 1 - m));
+      sy_ = acc(sy_, c, qy(z, y + m, x), qy(z, y + 1 - m, x));
+      sz_ = acc(sz_, c, w[j + K - 1 + m], w[j + K - m]);
+    }
+    // the v_z recording of this step (V = R v_z) enters after the scaling
+    T rv = T(0);
+    if (vtr) {
+      int tr = 0;
+      const double wt = plane_w(vpl, z, y, x, tr);
+      if (wt != 0.0) rv = T(wt) * vtr[tr];
+    }
+    const T vbx = F.ah(2, x) * f.vx[o] + sx;
+    const T vby = F.ah(1, y) * f.vy[o] + sy_;
+    const T vbz = (F.ah(0, z) * f.vz[o] + rv) + sz_;
+    f.vx[o] = vbx;
+    f.vy[o] = vby;
+    f.vz[o] = vbz;
+    f.ux[o] = (F.bh(2, x) * cb) * vbx;
+    f.uy[o] = (F.bh(1, y) * cb) * vby;
+    f.uz[o] = (F.bh(0, z) * cb) * vbz;
   }
-  // the v_z recording of this step (V = R v_z) enters after the scaling
-  T rv = T(0);
-  if (vtr) {
-    int tr = 0;
-    const double w = plane_w(vpl, z, y, x, tr);
-    if (w != 0.0) rv = T(w) * vtr[tr];
-  }
-  const T vbx = F.ah(2, x) * f.vx[o] + sx;
-  const T vby = F.ah(1, y) * f.vy[o] + sy_;
-  const T vbz = (F.ah(0, z) * f.vz[o] + rv) + sz_;
-  f.vx[o] = vbx;
-  f.vy[o] = vby;
-  f.vz[o] = vbz;
-  f.ux[o] = (F.bh(2, x) * cb) * vbx;
-  f.uy[o] = (F.bh(1, y) * cb) * vby;
-  f.uz[o] = (F.bh(0, z) * cb) * vbz;
 }
 
 // Transposed velocity updates (q_a stored with each updated p~_a):
@@ -213,51 +245,60 @@ __global__ __launch_bounds__(BX* BY) void k3_adj_v(Fields3<T> f, Dims3 d, const 
 // (the transpose of v_a -= b_half,a Cb D_a^+ p, p = p_x + p_y + p_z, taken
 // by all three parts), then the recording of step n - 1 (P = R p) added to
 // each part.
-template <int K, typename T>
+template <int K, typename T, int Z>
 __global__ __launch_bounds__(BX* BY) void k3_adj_p(Fields3<T> f, Dims3 d, const T* fac,
                                                    const T* ck, T cb, Plane3 rec, const T* rtr) {
-  const Cell cc = cell_of(d);
-  const int x = cc.x, y = cc.y, z = cc.z;
+  const Cell cc = col_of<Z>(d);
+  const int x = cc.x, y = cc.y, z0 = cc.z;
   if (x >= d.NX || y >= d.NY) return;
-  const long long o = ((long long)z * d.NY + y) * d.NX + x;
+  (void)cb;  // the b_half Cb factors are in u, as k3_adj_v stored it
   const Fac<T> F{fac, d.NZ, d.NY, d.NX};
   // u_a = b_half,a Cb v~_a at the neighbouring half nodes, as k3_adj_v
   // stored it (zero outside the grid)
   const View<T> ux{f.ux, d.NZ, d.NY, d.NX}, uy{f.uy, d.NZ, d.NY, d.NX},
       uz{f.uz, d.NZ, d.NY, d.NX};
-  T tx = T(0), ty = T(0), tz = T(0);
+  T w[2 * K + Z - 1];  // u_z at planes z0 - K ..
 #pragma unroll
-  for (int m = 1; m <= K; ++m) {
-    const T c = wst<K, T>(m - 1);
-    tx = acc(tx, c, ux(z, y, x + m - 1), ux(z, y, x - m));
-    ty = acc(ty, c, uy(z, y + m - 1, x), uy(z, y - m, x));
-    tz = acc(tz, c, uz(z + m - 1, y, x), uz(z - m, y, x));
+  for (int j = 0; j < 2 * K + Z - 1; ++j) w[j] = uz(z0 - K + j, y, x);
+#pragma unroll
+  for (int j = 0; j < Z; ++j) {
+    const int z = z0 + j;
+    if (z >= d.NZ) break;
+    const long long o = ((long long)z * d.NY + y) * d.NX + x;
+    T tx = T(0), ty = T(0), tz = T(0);
+#pragma unroll
+    for (int m = 1; m <= K; ++m) {
+      const T c = wst<K, T>(m - 1);
+      tx = acc(tx, c, ux(z, y, x + m - 1), ux(z, y, x - m));
+      ty = acc(ty, c, uy(z, y + m - 1, x), uy(z, y - m, x));
+      tz = acc(tz, c, w[j + K + m - 1], w[j + K - m]);
+    }
+    const T t = (tx + ty) + tz;
+    T r = T(0);
+    if (rtr) {
+      int tr = 0;
+      const double wt = plane_w(rec, z, y, x, tr);
+      if (wt != 0.0) r = T(wt) * rtr[tr];
+    }
+    const T k = ck[o];
+    if (inner(d, z, y, x)) {
+      const T pb = (f.p[o] + t) + r;
+      f.p[o] = pb;
+      f.qx[o] = (F.bn(2, x) * k) * pb;
+      f.qy[o] = (F.bn(1, y) * k) * pb;
+      f.qz[o] = (F.bn(0, z) * k) * pb;
+      continue;
+    }
+    const T pbx = fmac(F.an(2, x), f.px[o], t) + r;
+    const T pby = fmac(F.an(1, y), f.py[o], t) + r;
+    const T pbz = fmac(F.an(0, z), f.pz[o], t) + r;
+    f.px[o] = pbx;
+    f.py[o] = pby;
+    f.pz[o] = pbz;
+    f.qx[o] = (F.bn(2, x) * k) * pbx;
+    f.qy[o] = (F.bn(1, y) * k) * pby;
+    f.qz[o] = (F.bn(0, z) * k) * pbz;
   }
-  const T t = (tx + ty) + tz;
-  T r = T(0);
-  if (rtr) {
-    int tr = 0;
-    const double w = plane_w(rec, z, y, x, tr);
-    if (w != 0.0) r = T(w) * rtr[tr];
-  }
-  const T k = ck[o];
-  if (inner(d, z, y, x)) {
-    const T pb = (f.p[o] + t) + r;
-    f.p[o] = pb;
-    f.qx[o] = (F.bn(2, x) * k) * pb;
-    f.qy[o] = (F.bn(1, y) * k) * pb;
-    f.qz[o] = (F.bn(0, z) * k) * pb;
-    return;
-  }
-  const T pbx = fmac(F.an(2, x), f.px[o], t) + r;
-  const T pby = fmac(F.an(1, y), f.py[o], t) + r;
-  const T pbz = fmac(F.an(0, z), f.pz[o], t) + r;
-  f.px[o] = pbx;
-  f.py[o] = pby;
-  f.pz[o] = pbz;
-  f.qx[o] = (F.bn(2, x) * k) * pbx;
-  f.qy[o] = (F.bn(1, y) * k) * pby;
-  f.qz[o] = (F.bn(0, z) * k) * pbz;
 }
 
 // the recording's transpose alone (the first transposed step): each part
@@ -318,31 +359,32 @@ __global__ void k3_gather(Fields3<T> f, Dims3 d, Plane3 pl, const T* fac, const 
 
 // ---------------------------------------------------------------------------
 
-static dim3 cells(const Dims3& d) {
-  return dim3((unsigned)(((d.NX + BX - 1) / BX) * ((d.NY + BY - 1) / BY) * d.NZ));
+static dim3 columns(const Dims3& d, int z) {
+  return dim3((unsigned)(((d.NX + BX - 1) / BX) * ((d.NY + BY - 1) / BY) *
+                         ((d.NZ + z - 1) / z)));
 }
 
 template <typename T>
 static hipError_t step_t(int order, bool adj, const Fields3<T>& f, const Dims3& d, const T* fac,
                          const T* ck, T cb, const Plane3& pl, const T* tr, const Plane3& pl2,
                          const T* tr2, hipStream_t s) {
-  const dim3 g = cells(d), b(BX, BY);
+  const dim3 gc = columns(d, ZW), gv = columns(d, ZW_AV), b(BX, BY);
   if (d.NZ < 1 || d.NZ > 65535) return hipErrorInvalidValue;
   if (order == 4) {
     if (!adj) {
-      hipLaunchKernelGGL((k3_vel<2, T>), g, b, 0, s, f, d, fac, cb, pl2, tr2);
-      hipLaunchKernelGGL((k3_pres<2, T>), g, b, 0, s, f, d, fac, ck, pl, tr);
+      hipLaunchKernelGGL((k3_vel<2, T, ZW>), gc, b, 0, s, f, d, fac, cb, pl2, tr2);
+      hipLaunchKernelGGL((k3_pres<2, T, ZW>), gc, b, 0, s, f, d, fac, ck, pl, tr);
     } else {
-      hipLaunchKernelGGL((k3_adj_v<2, T>), g, b, 0, s, f, d, fac, cb, pl2, tr2);
-      hipLaunchKernelGGL((k3_adj_p<2, T>), g, b, 0, s, f, d, fac, ck, cb, pl, tr);
+      hipLaunchKernelGGL((k3_adj_v<2, T, ZW_AV>), gv, b, 0, s, f, d, fac, cb, pl2, tr2);
+      hipLaunchKernelGGL((k3_adj_p<2, T, ZW>), gc, b, 0, s, f, d, fac, ck, cb, pl, tr);
     }
   } else if (order == 8) {
     if (!adj) {
-      hipLaunchKernelGGL((k3_vel<4, T>), g, b, 0, s, f, d, fac, cb, pl2, tr2);
-      hipLaunchKernelGGL((k3_pres<4, T>), g, b, 0, s, f, d, fac, ck, pl, tr);
+      hipLaunchKernelGGL((k3_vel<4, T, ZW>), gc, b, 0, s, f, d, fac, cb, pl2, tr2);
+      hipLaunchKernelGGL((k3_pres<4, T, ZW>), gc, b, 0, s, f, d, fac, ck, pl, tr);
     } else {
-      hipLaunchKernelGGL((k3_adj_v<4, T>), g, b, 0, s, f, d, fac, cb, pl2, tr2);
-      hipLaunchKernelGGL((k3_adj_p<4, T>), g, b, 0, s, f, d, fac, ck, cb, pl, tr);
+      hipLaunchKernelGGL((k3_adj_v<4, T, ZW_AV>), gv, b, 0, s, f, d, fac, cb, pl2, tr2);
+      hipLaunchKernelGGL((k3_adj_p<4, T, ZW>), gc, b, 0, s, f, d, fac, ck, cb, pl, tr);
     }
   } else {
     return hipErrorInvalidValue;
