@@ -170,7 +170,7 @@ def cpu_model():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "bench.py runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import numpy as np
     import torch
